@@ -1,0 +1,173 @@
+/*
+ * slhjb — implicit semi-Lagrangian solver for Hamilton-Jacobi-Bellman equations on MI355X.
+ *
+ * The method is that of Reisinger & Rotaetxe Arto, "Boundary Treatment and
+ * Multigrid Preconditioning for Semi-Lagrangian Schemes Applied to
+ * Hamilton-Jacobi-Bellman Equations" (arXiv:1605.04821):
+ *   u_t - inf_alpha { L^alpha u + c^alpha u + f } = 0 on (0,T] x Omega,  u(0) = g,  u = psi on the boundary
+ *   (eqs. 1.1-1.3), L^alpha u = tr[a^alpha D^2 u] + b^alpha . Du with a^alpha = 1/2 sigma^alpha sigma^alpha,T.
+ * Space: the linear-interpolation semi-Lagrangian Scheme 2 (Section 1) with diffusion points
+ * x +- sqrt(h) s sigma_p and drift point x + h b, truncated at the box boundary (Section 2.1,
+ * eq. TruncScheme with the weights of Prop. pro:scheme2).  Time: the theta-scheme of eq. FullScheme.
+ * Each step solves the row-wise nonlinear system of eq. nonlinear_sys by Howard policy iteration;
+ * each fixed-policy linear system is solved by flexible GMRES preconditioned with a geometric
+ * multigrid V-cycle (Section 3 studies multigrid preconditioning for this class of matrices).
+ *
+ * Memory and threading conventions (all entry points):
+ *   - Every array argument is a DEVICE pointer (e.g. a torch tensor's data_ptr), contiguous, in the
+ *     dtype stated, unless marked "host".  Full-grid arrays hold all nodes including the boundary,
+ *     x fastest: node (i0,i1,i2) is element i0 + n0*(i1 + n1*i2).
+ *   - Coefficient tables in hjb_desc are HOST memory and are copied during hjb_setup.
+ *   - The library never frees or keeps caller memory; the handle owns its workspace.
+ *   - Work is enqueued on the stream given in hjb_desc (NULL = the default stream).  Calls that return
+ *     statistics synchronise that stream before returning.
+ *   - Return values are status codes (HJB_OK or a negative HJB_E*); no exception crosses the ABI.
+ *     hjb_last_error() gives a message for the calling thread's last failure.
+ *   - Arguments are validated on the host before any device work; an invalid argument leaves all
+ *     outputs untouched.  Without a usable GPU, hjb_setup fails with HJB_EDEVICE.
+ *   - A handle must not be used by two threads at once.
+ */
+#ifndef SLHJB_H
+#define SLHJB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hjb_handle hjb_handle;
+
+enum {
+    HJB_OK = 0,
+    HJB_EINVAL = -1,          /* invalid argument (shape, pointer, parameter range) */
+    HJB_EDEVICE = -2,         /* no usable GPU, or a HIP runtime error */
+    HJB_ENOMEM = -3,          /* device allocation failed */
+    HJB_ENOCONV_KRYLOV = -4,  /* linear solve missed its tolerance within max_krylov iterations */
+    HJB_ENOCONV_PI = -5,      /* policy iteration still changing after max_pi iterations */
+    HJB_ENONFINITE = -6,      /* non-finite value met in a residual or norm */
+    HJB_EUNSUPPORTED = -7     /* valid request this build does not implement */
+};
+
+enum { HJB_COEF_CONST = 0 };                    /* sigma, b, c constant per control */
+enum { HJB_PREC_FP64 = 0, HJB_PREC_MIXED = 1 }; /* V-cycle in FP64, or in FP32 under FP64 FGMRES */
+enum { HJB_PRECOND_NONE = 0, HJB_PRECOND_JACOBI = 1, HJB_PRECOND_VCYCLE = 2 };
+
+typedef struct {
+    /* Grid (eqs. 1.1-1.3 on a box, Section 2.1): n[d] nodes per axis, uniform spacing h, corner lo. */
+    int32_t dim;            /* 2 or 3 */
+    int32_t n[3];           /* >= 3 per used axis */
+    double lo[3];
+    double h;
+    /* Controls (Section 1, definition of L): K controls, P diffusion columns each.
+       sigma[(k*P + p)*dim + d] (host, K*P*dim), drift[k*dim + d] (host, K*dim, may be NULL = no drift),
+       c[k] (host, K, may be NULL = 0).  Only Scheme 2 (scheme = 2) is provided: its truncation is the
+       consistent one (Prop. pro:scheme2). */
+    int32_t K, P, coef_model, scheme;
+    const double *sigma, *drift, *c;
+    /* Solver controls. */
+    int32_t precision;      /* HJB_PREC_FP64 | HJB_PREC_MIXED */
+    int32_t precond;        /* HJB_PRECOND_* */
+    int32_t restart;        /* FGMRES restart length m, 1..64 */
+    int32_t max_krylov;     /* total FGMRES iterations per linear solve */
+    int32_t max_pi;         /* policy iterations per time step */
+    int32_t nu1, nu2;       /* V-cycle pre/post Jacobi sweeps */
+    int32_t coarse_sweeps;  /* Jacobi sweeps on the coarsest level */
+    int32_t min_coarse;     /* stop coarsening when a level has <= min_coarse nodes per axis */
+    double omega;           /* Jacobi damping */
+    double rtol_inf;        /* linear solve stops when |F - A X|_inf <= rtol_inf * max(1,|X|_inf) */
+    double tau_rel;         /* policy tie tolerance relative to the scale S of the search */
+    void *stream;           /* hipStream_t */
+} hjb_desc;
+
+typedef struct {
+    int32_t pi_iters;       /* policy iterations (linear solves) in the step */
+    int32_t krylov_total;   /* FGMRES iterations summed over the step's solves */
+    int32_t krylov_max;     /* largest FGMRES count of one solve */
+    int32_t flags;          /* bit 0: positivity condition (eq. CFL_trunc) may fail for theta < 1 */
+    double res_inf;         /* final |F - A X|_inf of the last solve */
+    double cert_bound;      /* bound on |X - X*|_inf of the last solve: res_inf / (1 - theta dt max(c,0)) */
+    int64_t n_changed_first;/* controls changed by the first search of the step */
+} hjb_step_stats;
+
+typedef struct {
+    int32_t steps_done;
+    int32_t flags;
+    int64_t krylov_total;
+    int64_t pi_total;
+    double max_cert_bound;
+} hjb_solve_stats;
+
+/* Fill *d with defaults (2D, FP64, V-cycle, m = 30, rtol 1e-13, tau_rel 1e-13, ...). Grid and controls
+   still have to be set by the caller. */
+void hjb_desc_default(hjb_desc *d);
+
+/* Validate the problem description (eqs. 1.1-1.3 on a box), build per-control stencil tables for every
+   multigrid level and allocate the workspace.  On success *out owns device memory until hjb_destroy. */
+int hjb_setup(const hjb_desc *desc, hjb_handle **out);
+
+/* Replace the stream used by later calls (hipStream_t; NULL = default stream). */
+int hjb_set_stream(hjb_handle *hd, void *stream);
+
+/* Change solver controls after setup (precision, precond, restart, max_krylov, max_pi, nu1, nu2,
+   coarse_sweeps, omega, rtol_inf, tau_rel are taken from *desc; grid and controls must be unchanged). */
+int hjb_set_options(hjb_handle *hd, const hjb_desc *desc);
+
+/*
+ * Policy improvement (Howard's algorithm on eq. nonlinear_sys; the theta-scheme of eq. FullScheme):
+ * for each interior node i and control k,
+ *   G_k = theta*((L^k X)_i + c_k X_i) + (1-theta)*((L^k U)_i + c_k U_i) + f_i,   f = f0 + t_mid*f1,
+ *   t_mid = t_prev + theta*dt.  The residual of row i is X_i - U_i - dt*G_k, so the search minimises G_k.
+ * Tie rule: g* = min_k G_k, tau = tau_rel*S with S = (2*M*(0.5/h) + max|c|)*max(|X|inf,|U|inf) + |f|inf
+ * (M = P + 1 with drift, else P); alpha_in[i] is kept if G_{alpha_in} <= g* + tau, otherwise the smallest
+ * k with G_k <= g* + tau is taken.
+ *   X, U: full-grid FP64 (boundary entries are the Dirichlet values used by truncated points);
+ *   f0, f1: full-grid FP64; alpha_in: full-grid int16 (boundary entries ignored; may equal alpha_out);
+ *   alpha_out: full-grid int16, boundary entries set to -1;
+ *   gmin (nullable): g* per node (0 on the boundary); margin (nullable): min{G_k - g* : G_k > g*+tau};
+ *   ties (nullable, int32): #{k : G_k <= g* + tau};  n_changed (host, nullable): changed interior nodes;
+ *   tau_used (host, nullable): the tau applied.  Synchronises the stream when n_changed or tau_used is given.
+ */
+int hjb_policy_sweep(hjb_handle *hd, const double *X, const double *U, const double *f0, const double *f1,
+                     double t_prev, double dt, double theta, double s,
+                     const int16_t *alpha_in, int16_t *alpha_out, double *gmin, double *margin, int32_t *ties,
+                     int64_t *n_changed, double *tau_used);
+
+/* y = A^alpha x for the fixed-policy matrix of eq. FullScheme restricted to interior nodes,
+   (A x)_i = x_i - theta*dt*((L^{alpha_i} x)_i + c x_i), reading boundary entries of x as given
+   (pass zeros there for the matrix itself).  y is written on interior nodes and zeroed on the boundary.
+   x, y: full-grid FP64 (distinct); alpha: full-grid int16. */
+int hjb_apply(hjb_handle *hd, const int16_t *alpha, const double *x, double *y, double dt, double theta, double s);
+
+/* Solve the fixed-policy system of eq. FullScheme (Dirichlet data moved to the right-hand side as in
+   Remark rem:rhs): X_i - theta*dt*((L X)_i + c X_i) = U_i + (1-theta)*dt*((L U)_i + c U_i) + dt*f_i.
+   X (full-grid FP64): in = initial guess on interior nodes and the Dirichlet data on the boundary;
+   out = solution on interior nodes (boundary untouched).  U: previous time level (full grid). */
+int hjb_linsolve(hjb_handle *hd, const int16_t *alpha, const double *U, const double *f0, const double *f1,
+                 double t_prev, double dt, double theta, double s, double *X, hjb_step_stats *st);
+
+/* One theta-step by policy iteration (eq. nonlinear_sys): searches start from alpha_io (the previous
+   step's policy) and alternate with linear solves until no control changes.
+   Uprev: full-grid FP64 U^{n-1}; Unext: full-grid FP64 whose boundary entries hold psi on entry
+   (never written) and whose interior receives U^n; alpha_io: full-grid int16, in/out. */
+int hjb_step(hjb_handle *hd, const double *Uprev, double *Unext, const double *f0, const double *f1,
+             double t_prev, double dt, double theta, double s, int16_t *alpha_io, hjb_step_stats *st);
+
+/* March U^0 = g (eq. 1.2), U^n = psi on the boundary (eq. 1.3) through n_steps theta-steps with
+   dts[n], thetas[n] (host arrays).  U_final: full-grid FP64 output.  policies (nullable): int16
+   [n_steps][N], the converged policy of each step (the checkpoints an adjoint sweep reuses). */
+int hjb_solve(hjb_handle *hd, const double *g, const double *psi, const double *f0, const double *f1,
+              int32_t n_steps, const double *dts, const double *thetas, double s,
+              double *U_final, int16_t *policies, hjb_solve_stats *st);
+
+/* Free the handle and its device workspace (NULL is ignored). */
+void hjb_destroy(hjb_handle *hd);
+
+/* Message for the calling thread's last failed call ("" if none). */
+const char *hjb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLHJB_H */

@@ -1,0 +1,234 @@
+"""slhjb: MI355X semi-Lagrangian HJB solver (Reisinger & Rotaetxe Arto, arXiv:1605.04821).
+
+Thin ctypes binding of ``libslhjb.so`` (C ABI in ``include/slhjb.h``).  This module only marshals
+arguments: every step of the method runs in the library's HIP kernels.  Device arrays are torch
+tensors on the GPU (contiguous, dtype as documented); PyTorch supplies memory and the stream.
+There is no CPU fallback: if the library is missing the import fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libslhjb.so")
+
+HJB_OK, HJB_EINVAL, HJB_EDEVICE, HJB_ENOMEM = 0, -1, -2, -3
+HJB_ENOCONV_KRYLOV, HJB_ENOCONV_PI, HJB_ENONFINITE, HJB_EUNSUPPORTED = -4, -5, -6, -7
+PREC_FP64, PREC_MIXED = 0, 1
+PRECOND_NONE, PRECOND_JACOBI, PRECOND_VCYCLE = 0, 1, 2
+
+EXPORTED = ["hjb_desc_default", "hjb_setup", "hjb_set_stream", "hjb_set_options", "hjb_policy_sweep", "hjb_apply",
+            "hjb_linsolve", "hjb_step", "hjb_solve", "hjb_destroy", "hjb_last_error"]
+
+
+class HJBError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"slhjb error {code}: {msg}")
+        self.code = code
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("lo", ctypes.c_double * 3),
+                ("h", ctypes.c_double), ("K", ctypes.c_int32), ("P", ctypes.c_int32),
+                ("coef_model", ctypes.c_int32), ("scheme", ctypes.c_int32),
+                ("sigma", ctypes.c_void_p), ("drift", ctypes.c_void_p), ("c", ctypes.c_void_p),
+                ("precision", ctypes.c_int32), ("precond", ctypes.c_int32), ("restart", ctypes.c_int32),
+                ("max_krylov", ctypes.c_int32), ("max_pi", ctypes.c_int32), ("nu1", ctypes.c_int32),
+                ("nu2", ctypes.c_int32), ("coarse_sweeps", ctypes.c_int32), ("min_coarse", ctypes.c_int32),
+                ("omega", ctypes.c_double), ("rtol_inf", ctypes.c_double), ("tau_rel", ctypes.c_double),
+                ("stream", ctypes.c_void_p)]
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("pi_iters", ctypes.c_int32), ("krylov_total", ctypes.c_int32), ("krylov_max", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("res_inf", ctypes.c_double), ("cert_bound", ctypes.c_double),
+                ("n_changed_first", ctypes.c_int64)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("steps_done", ctypes.c_int32), ("flags", ctypes.c_int32), ("krylov_total", ctypes.c_int64),
+                ("pi_total", ctypes.c_int64), ("max_cert_bound", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libslhjb.so not built ({LIB_PATH}); run __graft_entry__.build() or "
+                          f"python paper_1605_04821_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, d, i32, i64 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int64
+    L.hjb_desc_default.argtypes = [ctypes.POINTER(Desc)]
+    L.hjb_desc_default.restype = None
+    L.hjb_setup.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(vp)]
+    L.hjb_setup.restype = ctypes.c_int
+    L.hjb_set_stream.argtypes = [vp, vp]
+    L.hjb_set_options.argtypes = [vp, ctypes.POINTER(Desc)]
+    L.hjb_policy_sweep.argtypes = [vp, vp, vp, vp, vp, d, d, d, d, vp, vp, vp, vp, vp,
+                                   ctypes.POINTER(i64), ctypes.POINTER(d)]
+    L.hjb_apply.argtypes = [vp, vp, vp, vp, d, d, d]
+    L.hjb_linsolve.argtypes = [vp, vp, vp, vp, vp, d, d, d, d, vp, ctypes.POINTER(StepStats)]
+    L.hjb_step.argtypes = [vp, vp, vp, vp, vp, d, d, d, d, vp, ctypes.POINTER(StepStats)]
+    L.hjb_solve.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, d, vp, vp, ctypes.POINTER(SolveStats)]
+    L.hjb_destroy.argtypes = [vp]
+    L.hjb_destroy.restype = None
+    L.hjb_last_error.argtypes = []
+    L.hjb_last_error.restype = ctypes.c_char_p
+    return L
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(rc: int):
+    if rc != HJB_OK:
+        raise HJBError(rc, _lib.hjb_last_error().decode())
+
+
+def _ptr(t) -> Optional[int]:
+    """Device pointer of a contiguous CUDA tensor (None passes NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+@dataclass
+class Options:
+    precision: int = PREC_FP64
+    precond: int = PRECOND_VCYCLE
+    restart: int = 30
+    max_krylov: int = 600
+    max_pi: int = 50
+    nu1: int = 1
+    nu2: int = 1
+    coarse_sweeps: int = 30
+    min_coarse: int = 17
+    omega: float = 0.7
+    rtol_inf: float = 1e-13
+    tau_rel: float = 1e-13
+
+
+class Solver:
+    """A handle for one grid and control set (hjb_setup).
+
+    dim, n, lo, h: the box grid; sigma (K,P,dim), drift (K,dim) or None, c (K,) or None: host arrays.
+    """
+
+    def __init__(self, dim, n, lo, h, sigma, drift=None, c=None, options: Optional[Options] = None):
+        self.options = options or Options()
+        sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+        K, P, dd = sigma.shape
+        if dd != dim:
+            raise ValueError("sigma must have shape (K, P, dim)")
+        self._sigma = sigma
+        self._drift = None if drift is None else np.ascontiguousarray(drift, dtype=np.float64)
+        self._c = None if c is None else np.ascontiguousarray(c, dtype=np.float64)
+        self.dim, self.K, self.P = dim, K, P
+        self.n = tuple(int(v) for v in n)
+        self.N = int(np.prod(self.n))
+        self.h = float(h)
+        desc = Desc()
+        _lib.hjb_desc_default(ctypes.byref(desc))
+        desc.dim = dim
+        for a in range(3):
+            desc.n[a] = self.n[a] if a < dim else 1
+            desc.lo[a] = float(lo[a]) if a < dim else 0.0
+        desc.h = self.h
+        desc.K, desc.P = K, P
+        desc.sigma = self._sigma.ctypes.data
+        desc.drift = None if self._drift is None else self._drift.ctypes.data
+        desc.c = None if self._c is None else self._c.ctypes.data
+        self._fill_options(desc, self.options)
+        desc.stream = None
+        self._desc = desc
+        h_ = ctypes.c_void_p()
+        _check(_lib.hjb_setup(ctypes.byref(desc), ctypes.byref(h_)))
+        self._h = h_
+
+    @staticmethod
+    def _fill_options(desc, o: Options):
+        desc.precision, desc.precond, desc.restart = o.precision, o.precond, o.restart
+        desc.max_krylov, desc.max_pi, desc.nu1, desc.nu2 = o.max_krylov, o.max_pi, o.nu1, o.nu2
+        desc.coarse_sweeps, desc.min_coarse, desc.omega = o.coarse_sweeps, o.min_coarse, o.omega
+        desc.rtol_inf, desc.tau_rel = o.rtol_inf, o.tau_rel
+
+    @classmethod
+    def from_instance(cls, inst, options: Optional[Options] = None):
+        if inst.sigma is None:
+            raise ValueError("the HIP path takes control-constant sigma")
+        return cls(inst.dim, inst.n, inst.lo, inst.h, inst.sigma, inst.drift, inst.c, options)
+
+    def set_options(self, options: Options):
+        self._fill_options(self._desc, options)
+        _check(_lib.hjb_set_options(self._h, ctypes.byref(self._desc)))
+        self.options = options
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.hjb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        _check(_lib.hjb_set_stream(self._h, _stream()))
+
+    # ---- entry points --------------------------------------------------------------------------
+    def policy_sweep(self, X, U, f0, f1, t_prev, dt, theta, s, alpha_in, alpha_out,
+                     gmin=None, margin=None, ties=None):
+        """hjb_policy_sweep; returns (n_changed, tau)."""
+        self._sync_stream()
+        nch = ctypes.c_int64(0)
+        tau = ctypes.c_double(0.0)
+        _check(_lib.hjb_policy_sweep(self._h, _ptr(X), _ptr(U), _ptr(f0), _ptr(f1), float(t_prev), float(dt),
+                                     float(theta), float(s), _ptr(alpha_in), _ptr(alpha_out), _ptr(gmin),
+                                     _ptr(margin), _ptr(ties), ctypes.byref(nch), ctypes.byref(tau)))
+        return int(nch.value), float(tau.value)
+
+    def apply(self, alpha, x, y, dt, theta, s=1.0):
+        self._sync_stream()
+        _check(_lib.hjb_apply(self._h, _ptr(alpha), _ptr(x), _ptr(y), float(dt), float(theta), float(s)))
+
+    def linsolve(self, alpha, U, f0, f1, t_prev, dt, theta, s, X) -> StepStats:
+        self._sync_stream()
+        st = StepStats()
+        _check(_lib.hjb_linsolve(self._h, _ptr(alpha), _ptr(U), _ptr(f0), _ptr(f1), float(t_prev), float(dt),
+                                 float(theta), float(s), _ptr(X), ctypes.byref(st)))
+        return st
+
+    def step(self, Uprev, Unext, f0, f1, t_prev, dt, theta, s, alpha_io) -> StepStats:
+        self._sync_stream()
+        st = StepStats()
+        _check(_lib.hjb_step(self._h, _ptr(Uprev), _ptr(Unext), _ptr(f0), _ptr(f1), float(t_prev), float(dt),
+                             float(theta), float(s), _ptr(alpha_io), ctypes.byref(st)))
+        return st
+
+    def solve(self, g, psi, f0, f1, dts, thetas, s, U_final, policies=None) -> SolveStats:
+        self._sync_stream()
+        dts = np.ascontiguousarray(dts, dtype=np.float64)
+        thetas = np.ascontiguousarray(thetas, dtype=np.float64)
+        st = SolveStats()
+        _check(_lib.hjb_solve(self._h, _ptr(g), _ptr(psi), _ptr(f0), _ptr(f1), int(len(dts)),
+                              dts.ctypes.data, thetas.ctypes.data, float(s), _ptr(U_final), _ptr(policies),
+                              ctypes.byref(st)))
+        return st

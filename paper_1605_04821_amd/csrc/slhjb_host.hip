@@ -1,0 +1,867 @@
+// Host driver of libslhjb: handle and workspace, per-level stencil tables, policy iteration,
+// flexible GMRES with a geometric multigrid V-cycle preconditioner, time march, and the C ABI
+// declared in include/slhjb.h.
+//
+// Method: Reisinger & Rotaetxe Arto (arXiv:1605.04821).  Each theta-step (eq. FullScheme) is a
+// row-wise nonlinear system (eq. nonlinear_sys) solved by Howard policy iteration; each policy's
+// linear system is an M-matrix with row sums >= 1 - theta dt max(c,0) (Section 3.3), so the
+// infinity-norm residual bounds the error and serves as the stopping certificate.
+// The V-cycle rediscretises the operator on each coarse level with the same physical stencil
+// displacements (the 1/(2h) scaling of the finest grid is kept), injects the fine policy, smooths
+// with damped Jacobi (the paper's Gauss-Seidel is sequential) and transfers with full weighting and
+// multilinear prolongation.
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/slhjb.h"
+#include "slhjb_internal.h"
+
+using namespace slhjb;
+
+namespace slhjb {
+int dot_blocks(int64_t N);
+}
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(call)                                                                         \
+    do {                                                                                     \
+        hipError_t _e = (call);                                                              \
+        if (_e != hipSuccess) return fail(HJB_EDEVICE, "%s: %s", #call, hipGetErrorString(_e)); \
+    } while (0)
+
+struct Level {
+    LevelDev g{};
+    PointTab *tab = nullptr;  // device [K][npt]
+    int16_t *alpha = nullptr; // level policy (level 0: not owned)
+    void *r = nullptr, *e = nullptr, *t = nullptr, *d = nullptr;  // precision of the V-cycle
+    void *r64 = nullptr, *e64 = nullptr, *t64 = nullptr, *d64 = nullptr;  // FP64 copies (plain path)
+    void *r32 = nullptr, *e32 = nullptr, *t32 = nullptr, *d32 = nullptr;
+};
+
+}  // namespace
+
+struct hjb_handle {
+    hjb_desc desc{};
+    std::vector<double> sigma, drift, c;
+    bool has_drift = false;
+    int npt = 0, M = 0;
+    double cmax = 0.0, cplus = 0.0;
+    hipStream_t stream = nullptr;
+    int dim = 2;
+    int64_t N = 0;
+    int nb = 0, nbd = 0;
+    std::vector<Level> lev;
+    double s_tab = -1.0;
+    double *c_dev = nullptr;
+    // fine-level buffers
+    double *E = nullptr, *R = nullptr, *Vb = nullptr, *Zb = nullptr;
+    double *Ua = nullptr, *Ub = nullptr, *X = nullptr;
+    int16_t *a0 = nullptr, *a1 = nullptr, *acarry = nullptr;
+    double *partial = nullptr;  // >= max(3*nb, (m+2)*nbd)
+    double *dvals = nullptr;    // device scalars / small vectors [256]
+    int64_t *ipartial = nullptr, *ival = nullptr;
+    double *hpin = nullptr;     // pinned host mirror of small results [256]
+    int64_t *hpin_i = nullptr;
+    std::vector<void *> allocs;
+    // statistics of the last linear solve
+    int last_its = 0;
+    double last_res = 0.0;
+};
+
+namespace {
+
+void fill_tables(hjb_handle *hd, double s, std::vector<PointTab> &host, int level) {
+    const hjb_desc &d = hd->desc;
+    const int dim = d.dim, K = d.K, P = d.P, npt = hd->npt;
+    const double sr = s * (1.0 / sqrt(d.h));
+    const double scale = ldexp(1.0, -level);
+    const Level &L = hd->lev[level];
+    host.assign((size_t)K * npt, PointTab{});
+    for (int k = 0; k < K; ++k) {
+        for (int q = 0; q < npt; ++q) {
+            PointTab &p = host[(size_t)k * npt + q];
+            for (int a = 0; a < 3; ++a) p.Y[a] = 0.0;
+            if (q < 2 * P) {
+                int pp = q / 2;  // points 2p and 2p+1 are x + y_p and x - y_p
+                for (int a = 0; a < dim; ++a) {
+                    double Y = sr * d.sigma[((size_t)k * P + pp) * dim + a];
+                    if (q & 1) Y = -Y;
+                    p.Y[a] = Y * scale;
+                }
+            } else {
+                for (int a = 0; a < dim; ++a) p.Y[a] = hd->drift[(size_t)k * dim + a] * scale;
+            }
+            int64_t off = 0;
+            for (int a = 0; a < 3; ++a) {
+                double fl = floor(p.Y[a]);
+                p.t[a] = p.Y[a] - fl;
+                p.u[a] = 1.0 - p.t[a];
+                p.tf[a] = (float)p.t[a];
+                p.uf[a] = (float)p.u[a];
+                int64_t stride = a == 0 ? 1 : (a == 1 ? L.g.s1 : L.g.s2);
+                if (a < dim) off += (int64_t)fl * stride;
+            }
+            p.off = off;
+        }
+    }
+}
+
+int build_tables(hjb_handle *hd, double s) {
+    if (hd->s_tab == s) return HJB_OK;
+    if (!(s > 0.0) || !isfinite(s)) return fail(HJB_EINVAL, "volatility scale s must be positive and finite");
+    std::vector<PointTab> host;
+    for (size_t l = 0; l < hd->lev.size(); ++l) {
+        Level &L = hd->lev[l];
+        fill_tables(hd, s, host, (int)l);
+        // deep box: no point of any control can leave the box or be clamped from these nodes
+        double E[3] = {0, 0, 0};
+        for (const PointTab &p : host)
+            for (int a = 0; a < 3; ++a) E[a] = std::max(E[a], fabs(p.Y[a]));
+        for (int a = 0; a < 3; ++a) {
+            if (a < hd->dim) {
+                int lo = (int)ceil(E[a]);
+                int hi = L.g.n[a] - 2 - (int)floor(E[a]);
+                L.g.deep_lo[a] = std::max(1, lo);
+                L.g.deep_hi[a] = std::min(L.g.n[a] - 2, hi);
+            } else {
+                L.g.deep_lo[a] = 0;
+                L.g.deep_hi[a] = 0;
+            }
+        }
+        HIPCHK(hipMemcpyAsync(L.tab, host.data(), host.size() * sizeof(PointTab), hipMemcpyHostToDevice, hd->stream));
+    }
+    HIPCHK(hipStreamSynchronize(hd->stream));
+    hd->s_tab = s;
+    return HJB_OK;
+}
+
+StencilDev stencil(const hjb_handle *hd, int level) {
+    StencilDev st;
+    st.tab = hd->lev[level].tab;
+    st.c = hd->c.empty() ? nullptr : hd->c_dev;
+    st.K = hd->desc.K;
+    st.P = hd->desc.P;
+    st.npt = hd->npt;
+    st.has_drift = hd->has_drift ? 1 : 0;
+    st.inv2h = 0.5 / hd->desc.h;
+    return st;
+}
+
+int dalloc(hjb_handle *hd, void **p, size_t bytes) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(HJB_ENOMEM, "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
+    }
+    hd->allocs.push_back(*p);
+    return HJB_OK;
+}
+
+#define TRY(x)                 \
+    do {                       \
+        int _rc = (x);         \
+        if (_rc != HJB_OK) return _rc; \
+    } while (0)
+
+bool mixed(const hjb_handle *hd) { return hd->desc.precision == HJB_PREC_MIXED; }
+
+void select_precision(hjb_handle *hd) {
+    bool f = mixed(hd);
+    for (Level &L : hd->lev) {
+        L.r = f ? L.r32 : L.r64;
+        L.e = f ? L.e32 : L.e64;
+        L.t = f ? L.t32 : L.t64;
+        L.d = f ? L.d32 : L.d64;
+    }
+}
+
+int check_options(const hjb_desc *d) {
+    if (d->precision != HJB_PREC_FP64 && d->precision != HJB_PREC_MIXED) return fail(HJB_EINVAL, "precision");
+    if (d->precond < HJB_PRECOND_NONE || d->precond > HJB_PRECOND_VCYCLE) return fail(HJB_EINVAL, "precond");
+    if (d->restart < 1 || d->restart > kMaxRestart) return fail(HJB_EINVAL, "restart must be in 1..%d", kMaxRestart);
+    if (d->max_krylov < 1) return fail(HJB_EINVAL, "max_krylov must be >= 1");
+    if (d->max_pi < 1) return fail(HJB_EINVAL, "max_pi must be >= 1");
+    if (d->nu1 < 1 || d->nu2 < 0 || d->nu1 > 16 || d->nu2 > 16) return fail(HJB_EINVAL, "nu1 in 1..16, nu2 in 0..16");
+    if (d->coarse_sweeps < 1 || d->coarse_sweeps > 1000) return fail(HJB_EINVAL, "coarse_sweeps in 1..1000");
+    if (!(d->omega > 0.0 && d->omega < 2.0)) return fail(HJB_EINVAL, "omega must be in (0,2)");
+    if (!(d->rtol_inf > 0.0) || !(d->tau_rel >= 0.0)) return fail(HJB_EINVAL, "rtol_inf > 0 and tau_rel >= 0 required");
+    return HJB_OK;
+}
+
+// ---- multigrid ---------------------------------------------------------------------------------
+
+constexpr int64_t kCoarseMaxNodes = 2048;  // LDS-resident coarsest level (two FP64 buffers = 32 KiB)
+
+int prepare_mg(hjb_handle *hd, const int16_t *alpha, double theta_dt) {
+    hipStream_t s = hd->stream;
+    hd->lev[0].alpha = const_cast<int16_t *>(alpha);
+    for (size_t l = 1; l < hd->lev.size(); ++l)
+        launch_inject_policy(hd->dim, hd->lev[l - 1].g, hd->lev[l].g, hd->lev[l - 1].alpha, hd->lev[l].alpha, s);
+    for (size_t l = 0; l < hd->lev.size(); ++l) {
+        Level &L = hd->lev[l];
+        if (mixed(hd))
+            launch_diag<float>(hd->dim, L.g, stencil(hd, (int)l), L.alpha, theta_dt, (float *)L.d, s);
+        else
+            launch_diag<double>(hd->dim, L.g, stencil(hd, (int)l), L.alpha, theta_dt, (double *)L.d, s);
+    }
+    HIPCHK(hipGetLastError());
+    return HJB_OK;
+}
+
+template <typename T>
+void smooth_level(hjb_handle *hd, int l, T *&e, T *&t, const T *r, int sweeps, bool first, double theta_dt) {
+    Level &L = hd->lev[l];
+    StencilDev st = stencil(hd, l);
+    for (int q = 0; q < sweeps; ++q) {
+        launch_jacobi<T>(hd->dim, L.g, st, L.alpha, e, r, (const T *)L.d, t, theta_dt, hd->desc.omega,
+                         first && q == 0, hd->stream);
+        std::swap(e, t);
+    }
+}
+
+// z = V-cycle(v): approximate solve of A z = v; r0 is the level-0 right-hand side (precision T),
+// z the level-0 output buffer (precision T).
+template <typename T>
+void vcycle(hjb_handle *hd, const T *r0, T *z, double theta_dt) {
+    const int Lc = (int)hd->lev.size() - 1;
+    const hjb_desc &d = hd->desc;
+    hipStream_t s = hd->stream;
+    std::vector<T *> e(Lc + 1), t(Lc + 1);
+    std::vector<const T *> r(Lc + 1);
+    for (int l = 0; l <= Lc; ++l) {
+        e[l] = (T *)hd->lev[l].e;
+        t[l] = (T *)hd->lev[l].t;
+        r[l] = (const T *)hd->lev[l].r;
+    }
+    r[0] = r0;
+    // every smoothing sweep writes the other buffer of the pair; start so that level 0 ends in z
+    int flips0 = d.nu1 + d.nu2;
+    if (Lc == 0) flips0 = d.coarse_sweeps;
+    if (flips0 % 2 == 0) {
+        e[0] = z;
+    } else {
+        e[0] = (T *)hd->lev[0].t;
+        t[0] = z;
+    }
+    if (Lc == 0) {
+        smooth_level<T>(hd, 0, e[0], t[0], r[0], d.coarse_sweeps, true, theta_dt);
+        return;
+    }
+    for (int l = 0; l < Lc; ++l) {
+        Level &L = hd->lev[l];
+        smooth_level<T>(hd, l, e[l], t[l], r[l], d.nu1, true, theta_dt);
+        launch_level_residual<T>(hd->dim, L.g, stencil(hd, l), L.alpha, e[l], r[l], t[l], theta_dt, s);
+        launch_restrict<T>(hd->dim, L.g, hd->lev[l + 1].g, t[l], (T *)hd->lev[l + 1].r, s);
+    }
+    {
+        Level &C = hd->lev[Lc];
+        if (C.g.N <= kCoarseMaxNodes) {
+            launch_coarse_solve<T>(hd->dim, C.g, stencil(hd, Lc), C.alpha, r[Lc], (const T *)C.d, e[Lc], t[Lc],
+                                   theta_dt, d.omega, d.coarse_sweeps, s);
+        } else {
+            smooth_level<T>(hd, Lc, e[Lc], t[Lc], r[Lc], d.coarse_sweeps, true, theta_dt);
+        }
+    }
+    for (int l = Lc - 1; l >= 0; --l) {
+        Level &L = hd->lev[l];
+        launch_prolong_add<T>(hd->dim, L.g, hd->lev[l + 1].g, e[l + 1], e[l], s);
+        smooth_level<T>(hd, l, e[l], t[l], r[l], d.nu2, false, theta_dt);
+    }
+}
+
+__global__ void k_jacobi_precond64(const double *v, const double *dg, double *z, int64_t N) {
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n < N) z[n] = v[n] / dg[n];
+}
+__global__ void k_jacobi_precond32(const double *v, const float *dg, float *z, int64_t N) {
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n < N) z[n] = (float)v[n] / dg[n];
+}
+
+// z_j = M^{-1} v_j
+void precondition(hjb_handle *hd, const double *v, void *z, double theta_dt) {
+    const int64_t N = hd->N;
+    hipStream_t s = hd->stream;
+    Level &L0 = hd->lev[0];
+    if (hd->desc.precond == HJB_PRECOND_JACOBI) {
+        int nb = blocks_for(N);
+        if (mixed(hd))
+            hipLaunchKernelGGL(k_jacobi_precond32, dim3(nb), dim3(kBlock), 0, s, v, (const float *)L0.d, (float *)z, N);
+        else
+            hipLaunchKernelGGL(k_jacobi_precond64, dim3(nb), dim3(kBlock), 0, s, v, (const double *)L0.d, (double *)z,
+                               N);
+        return;
+    }
+    if (mixed(hd)) {
+        launch_to_precond(v, L0.r, true, N, s);
+        vcycle<float>(hd, (const float *)L0.r, (float *)z, theta_dt);
+    } else {
+        vcycle<double>(hd, v, (double *)z, theta_dt);
+    }
+}
+
+// ---- flexible GMRES(m) on A^alpha x = b, with x = X on interior nodes ----------------------------
+
+int sync_small(hjb_handle *hd, const void *dev, void *host, size_t bytes) {
+    HIPCHK(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, hd->stream));
+    HIPCHK(hipStreamSynchronize(hd->stream));
+    return HJB_OK;
+}
+
+int fgmres(hjb_handle *hd, const int16_t *alpha, const double *E, double *X, double theta_dt, int *its_out,
+           double *res_out) {
+    const hjb_desc &d = hd->desc;
+    const int64_t N = hd->N;
+    const int m = d.restart;
+    const int dim = hd->dim;
+    hipStream_t s = hd->stream;
+    const Level &L0 = hd->lev[0];
+    StencilDev st = stencil(hd, 0);
+    const bool none = d.precond == HJB_PRECOND_NONE;
+    const bool zf = !none && mixed(hd);
+    const size_t zsz = zf ? sizeof(float) : sizeof(double);
+    double *V = hd->Vb;
+    double *dv = hd->dvals;
+    double *hp = hd->hpin;
+    int its = 0;
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gvec(m + 1), y(m);
+    for (int cycle = 0;; ++cycle) {
+        launch_residual(dim, L0.g, st, alpha, X, E, theta_dt, hd->R, hd->partial, hd->nb, s);
+        launch_reduce_sum(hd->partial, 1, hd->nb, dv + 0, s);
+        launch_reduce_max(hd->partial + hd->nb, 2, hd->nb, dv + 1, s);
+        TRY(sync_small(hd, dv, hp, 3 * sizeof(double)));
+        double beta = sqrt(hp[0]), rinf = hp[1], xinf = hp[2];
+        *res_out = rinf;
+        *its_out = its;
+        if (!isfinite(beta) || !isfinite(xinf)) return fail(HJB_ENONFINITE, "non-finite residual in linear solve");
+        double target = d.rtol_inf * std::max(1.0, xinf);
+        if (rinf <= target) return HJB_OK;
+        if (its >= d.max_krylov)
+            return fail(HJB_ENOCONV_KRYLOV, "FGMRES: |r|_inf = %.3e > %.3e after %d iterations", rinf, target, its);
+        // v0 = r / beta
+        launch_scale_by_inv_sqrt(V, hd->R, dv + 0, N, s);
+        std::fill(gvec.begin(), gvec.end(), 0.0);
+        gvec[0] = beta;
+        int j = 0;
+        for (; j < m && its < d.max_krylov; ++j) {
+            double *vj = V + (int64_t)j * N;
+            double *w = V + (int64_t)(j + 1) * N;
+            void *zj = none ? (void *)vj : (void *)((char *)hd->Zb + (int64_t)j * N * zsz);
+            if (!none) precondition(hd, vj, zj, theta_dt);
+            launch_apply(dim, L0.g, st, alpha, zj, zf, w, theta_dt, hd->partial, hd->nb, s);
+            launch_reduce_sum(hd->partial, 1, hd->nb, dv + 8, s);  // |w|^2 before orthogonalisation
+            // classical Gram-Schmidt, with a second pass when cancellation is severe
+            launch_multidot(w, V, N, j + 1, N, hd->partial, hd->nbd, s);
+            launch_reduce_sum(hd->partial, j + 1, hd->nbd, dv + 16, s);
+            launch_multiaxpy(w, V, N, j + 1, dv + 16, N, hd->partial, hd->nbd, s);
+            launch_reduce_sum(hd->partial, 1, hd->nbd, dv + 9, s);  // |w'|^2
+            HIPCHK(hipMemcpyAsync(hp + 8, dv + 8, (size_t)(8 + j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            double w2 = hp[8], wn2 = hp[9];
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hp[16 + i];
+            if (wn2 < 0.25 * w2) {
+                launch_multidot(w, V, N, j + 1, N, hd->partial, hd->nbd, s);
+                launch_reduce_sum(hd->partial, j + 1, hd->nbd, dv + 16, s);
+                launch_multiaxpy(w, V, N, j + 1, dv + 16, N, hd->partial, hd->nbd, s);
+                launch_reduce_sum(hd->partial, 1, hd->nbd, dv + 9, s);
+                HIPCHK(hipMemcpyAsync(hp + 9, dv + 9, (size_t)(7 + j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                wn2 = hp[9];
+                for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += hp[16 + i];
+            }
+            double hn = sqrt(wn2);
+            if (!isfinite(hn)) return fail(HJB_ENONFINITE, "non-finite Arnoldi vector");
+            H[(size_t)(j + 1) * m + j] = hn;
+            ++its;
+            if (hn > 0.0) launch_scale_by_inv_sqrt(w, w, dv + 9, N, s);
+            // apply previous rotations to column j, then a new one
+            for (int i = 0; i < j; ++i) {
+                double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+            }
+            double a = H[(size_t)j * m + j], b = H[(size_t)(j + 1) * m + j];
+            double r = hypot(a, b);
+            cs[j] = r > 0 ? a / r : 1.0;
+            sn[j] = r > 0 ? b / r : 0.0;
+            H[(size_t)j * m + j] = r;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            gvec[j + 1] = -sn[j] * gvec[j];
+            gvec[j] = cs[j] * gvec[j];
+            if (fabs(gvec[j + 1]) <= 0.5 * target || hn == 0.0) {
+                ++j;
+                break;
+            }
+        }
+        // y = H^{-1} g (upper triangular j x j), x += Z y
+        for (int i = j - 1; i >= 0; --i) {
+            double acc = gvec[i];
+            for (int q = i + 1; q < j; ++q) acc -= H[(size_t)i * m + q] * y[q];
+            y[i] = acc / H[(size_t)i * m + i];
+        }
+        for (int i = 0; i < j; ++i) hp[128 + i] = y[i];
+        HIPCHK(hipMemcpyAsync(dv + 128, hp + 128, (size_t)j * sizeof(double), hipMemcpyHostToDevice, s));
+        const void *Z = none ? (const void *)V : (const void *)hd->Zb;
+        launch_update_solution(X, Z, zf, N, j, dv + 128, N, s);
+        HIPCHK(hipGetLastError());
+    }
+}
+
+// ---- policy search ------------------------------------------------------------------------------
+
+__global__ void k_tau(const double *partial, int nb, double coefA, double tau_rel, double *out) {
+    // out[0] = tau from max(|X|,|U|) (partial[0..nb)) and max|f| (partial[nb..2nb))
+    __shared__ double sx[256], sf[256];
+    double ax = 0.0, af = 0.0;
+    for (int q = threadIdx.x; q < nb; q += blockDim.x) {
+        ax = fmax(ax, partial[q]);
+        af = fmax(af, partial[nb + q]);
+    }
+    sx[threadIdx.x] = ax;
+    sf[threadIdx.x] = af;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sx[threadIdx.x] = fmax(sx[threadIdx.x], sx[threadIdx.x + w]);
+            sf[threadIdx.x] = fmax(sf[threadIdx.x], sf[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double S = coefA * sx[0] + sf[0];
+        out[0] = tau_rel * S;
+    }
+}
+
+__global__ void k_sweep_tau_arg(const double *tau_dev, double *tau_copy) {
+    if (threadIdx.x == 0) tau_copy[0] = tau_dev[0];
+}
+
+int sweep(hjb_handle *hd, const double *X, const double *U, const double *f0, const double *f1, double t_prev,
+          double dt, double theta, const int16_t *a_in, int16_t *a_out, double *gmin, double *margin, int32_t *ties,
+          int64_t *n_changed, double *tau_used) {
+    hipStream_t s = hd->stream;
+    const Level &L0 = hd->lev[0];
+    double t_mid = t_prev + theta * dt;
+    launch_norms_xuf(hd->dim, L0.g, X, U, f0, f1, t_mid, hd->partial, hd->nb, s);
+    double inv2h = 0.5 / hd->desc.h;
+    double coefA = 2.0 * hd->M * inv2h + hd->cmax;
+    hipLaunchKernelGGL(k_tau, dim3(1), dim3(256), 0, s, hd->partial, hd->nb, coefA, hd->desc.tau_rel, hd->dvals + 4);
+    // the sweep takes tau by value: read it back (one small synchronisation per search)
+    HIPCHK(hipMemcpyAsync(hd->hpin + 4, hd->dvals + 4, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double tau = hd->hpin[4];
+    SweepOut o{a_out, gmin, margin, ties, hd->ipartial};
+    launch_sweep(hd->dim, L0.g, stencil(hd, 0), X, U, f0, f1, t_mid, theta, tau, a_in, o, hd->nb, s);
+    HIPCHK(hipGetLastError());
+    if (n_changed) {
+        launch_reduce_sum_i64(hd->ipartial, hd->nb, hd->ival, s);
+        HIPCHK(hipMemcpyAsync(hd->hpin_i, hd->ival, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        *n_changed = hd->hpin_i[0];
+    }
+    if (tau_used) *tau_used = tau;
+    return HJB_OK;
+}
+
+bool finite_param(double x) { return isfinite(x); }
+
+// caller-supplied policies must name a control on every interior node
+int check_policy(hjb_handle *hd, const int16_t *alpha) {
+    launch_bad_policy(hd->dim, hd->lev[0].g, alpha, hd->desc.K, hd->ipartial, hd->nb, hd->stream);
+    launch_reduce_sum_i64(hd->ipartial, hd->nb, hd->ival, hd->stream);
+    HIPCHK(hipMemcpyAsync(hd->hpin_i, hd->ival, sizeof(int64_t), hipMemcpyDeviceToHost, hd->stream));
+    HIPCHK(hipStreamSynchronize(hd->stream));
+    if (hd->hpin_i[0] != 0)
+        return fail(HJB_EINVAL, "policy has %lld interior entries outside [0, K)", (long long)hd->hpin_i[0]);
+    return HJB_OK;
+}
+
+int check_time(double dt, double theta) {
+    if (!(dt > 0.0) || !isfinite(dt)) return fail(HJB_EINVAL, "dt must be positive and finite");
+    if (!(theta >= 0.0 && theta <= 1.0)) return fail(HJB_EINVAL, "theta must be in [0,1]");
+    return HJB_OK;
+}
+
+int linsolve_impl(hjb_handle *hd, const int16_t *alpha, const double *U, const double *f0, const double *f1,
+                  double t_prev, double dt, double theta, double *X, int *its, double *res) {
+    hipStream_t s = hd->stream;
+    double t_mid = t_prev + theta * dt;
+    launch_explicit(hd->dim, hd->lev[0].g, stencil(hd, 0), alpha, U, f0, f1, t_mid, (1.0 - theta) * dt, dt, hd->E,
+                    hd->nb, s);
+    TRY(prepare_mg(hd, alpha, theta * dt));
+    return fgmres(hd, alpha, hd->E, X, theta * dt, its, res);
+}
+
+int step_impl(hjb_handle *hd, const double *Uprev, double *Unext, const double *f0, const double *f1, double t_prev,
+              double dt, double theta, int16_t *alpha_io, hjb_step_stats *st) {
+    hipStream_t s = hd->stream;
+    const int64_t N = hd->N;
+    hjb_step_stats loc{};
+    launch_copy_interior(hd->dim, hd->lev[0].g, Uprev, Unext, s);
+    int16_t *acur = hd->a0, *anew = hd->a1;
+    int64_t changed = 0;
+    TRY(sweep(hd, Unext, Uprev, f0, f1, t_prev, dt, theta, alpha_io, acur, nullptr, nullptr, nullptr, &changed,
+              nullptr));
+    loc.n_changed_first = changed;
+    double cert_den = 1.0 - theta * dt * hd->cplus;
+    if (theta < 1.0) {
+        // eq. CFL_trunc can only be guaranteed for theta < 1 when (1-theta) dt M/h <= 1 (interior weights)
+        double lhs = (1.0 - theta) * dt * (hd->M / hd->desc.h + hd->cmax);
+        if (lhs > 1.0) loc.flags |= 1;
+    }
+    int rc = HJB_OK;
+    for (int it = 0; it < hd->desc.max_pi; ++it) {
+        int its = 0;
+        double res = 0.0;
+        rc = linsolve_impl(hd, acur, Uprev, f0, f1, t_prev, dt, theta, Unext, &its, &res);
+        loc.pi_iters = it + 1;
+        loc.krylov_total += its;
+        loc.krylov_max = std::max(loc.krylov_max, its);
+        loc.res_inf = res;
+        loc.cert_bound = cert_den > 0 ? res / cert_den : INFINITY;
+        if (rc != HJB_OK) break;
+        TRY(sweep(hd, Unext, Uprev, f0, f1, t_prev, dt, theta, acur, anew, nullptr, nullptr, nullptr, &changed,
+                  nullptr));
+        if (changed == 0) break;
+        std::swap(acur, anew);
+        if (it + 1 == hd->desc.max_pi) rc = fail(HJB_ENOCONV_PI, "policy iteration still changing after %d", it + 1);
+    }
+    if (acur != alpha_io) {
+        hipError_t e = hipMemcpyAsync(alpha_io, acur, (size_t)N * sizeof(int16_t), hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) rc = fail(HJB_EDEVICE, "copy policy: %s", hipGetErrorString(e));
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess && rc == HJB_OK) rc = fail(HJB_EDEVICE, "%s", hipGetErrorString(e));
+    if (st) *st = loc;
+    return rc;
+}
+
+}  // namespace
+
+// =====================================================================================================
+// C ABI
+// =====================================================================================================
+
+extern "C" {
+
+void hjb_desc_default(hjb_desc *d) {
+    if (!d) return;
+    memset(d, 0, sizeof *d);
+    d->dim = 2;
+    d->scheme = 2;
+    d->coef_model = HJB_COEF_CONST;
+    d->precision = HJB_PREC_FP64;
+    d->precond = HJB_PRECOND_VCYCLE;
+    d->restart = 30;
+    d->max_krylov = 600;
+    d->max_pi = 50;
+    d->nu1 = 1;
+    d->nu2 = 1;
+    d->coarse_sweeps = 30;
+    d->min_coarse = 17;
+    d->omega = 0.7;
+    d->rtol_inf = 1e-13;
+    d->tau_rel = 1e-13;
+    d->stream = nullptr;
+}
+
+const char *hjb_last_error(void) { return g_err.c_str(); }
+
+int hjb_setup(const hjb_desc *desc, hjb_handle **out) {
+    g_err.clear();
+    if (!desc || !out) return fail(HJB_EINVAL, "null argument");
+    *out = nullptr;
+    const hjb_desc &d = *desc;
+    if (d.dim != 2 && d.dim != 3) return fail(HJB_EINVAL, "dim must be 2 or 3");
+    int64_t N = 1;
+    for (int a = 0; a < d.dim; ++a) {
+        if (d.n[a] < 3) return fail(HJB_EINVAL, "n[%d] must be >= 3", a);
+        N *= d.n[a];
+    }
+    if (N >= (int64_t)1 << 31) return fail(HJB_EINVAL, "grid too large (N must be < 2^31)");
+    if (!(d.h > 0.0) || !isfinite(d.h)) return fail(HJB_EINVAL, "h must be positive");
+    if (d.K < 1 || d.K > 32767) return fail(HJB_EINVAL, "K must be in 1..32767");
+    if (d.P < 1 || d.P > kMaxP) return fail(HJB_EINVAL, "P must be in 1..%d", kMaxP);
+    if (d.scheme != 2) return fail(HJB_EUNSUPPORTED, "only Scheme 2 is provided (consistent truncation)");
+    if (d.coef_model != HJB_COEF_CONST) return fail(HJB_EUNSUPPORTED, "only constant-per-control coefficients");
+    if (!d.sigma) return fail(HJB_EINVAL, "sigma is required");
+    TRY(check_options(&d));
+    for (int64_t q = 0; q < (int64_t)d.K * d.P * d.dim; ++q)
+        if (!isfinite(d.sigma[q])) return fail(HJB_EINVAL, "non-finite sigma");
+    if (d.drift)
+        for (int64_t q = 0; q < (int64_t)d.K * d.dim; ++q)
+            if (!isfinite(d.drift[q])) return fail(HJB_EINVAL, "non-finite drift");
+    if (d.c)
+        for (int q = 0; q < d.K; ++q)
+            if (!isfinite(d.c[q])) return fail(HJB_EINVAL, "non-finite c");
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(HJB_EDEVICE, "no HIP device available");
+
+    hjb_handle *hd = new hjb_handle();
+    hd->desc = d;
+    hd->dim = d.dim;
+    hd->N = N;
+    hd->stream = (hipStream_t)d.stream;
+    hd->sigma.assign(d.sigma, d.sigma + (size_t)d.K * d.P * d.dim);
+    hd->drift.assign((size_t)d.K * d.dim, 0.0);
+    if (d.drift) {
+        hd->drift.assign(d.drift, d.drift + (size_t)d.K * d.dim);
+        for (double b : hd->drift) hd->has_drift |= (b != 0.0);
+    }
+    if (d.c) {
+        hd->c.assign(d.c, d.c + d.K);
+        for (double cc : hd->c) {
+            hd->cmax = std::max(hd->cmax, fabs(cc));
+            hd->cplus = std::max(hd->cplus, cc);
+        }
+    }
+    hd->desc.sigma = hd->sigma.data();
+    hd->desc.drift = hd->drift.data();
+    hd->desc.c = hd->c.empty() ? nullptr : hd->c.data();
+    hd->npt = 2 * d.P + (hd->has_drift ? 1 : 0);
+    hd->M = d.P + (hd->has_drift ? 1 : 0);
+    hd->nb = blocks_for(N);
+    hd->nbd = dot_blocks(N);
+
+    auto cleanup_fail = [&](int rc) {
+        hjb_destroy(hd);
+        return rc;
+    };
+#define STRY(x)                                 \
+    do {                                        \
+        int _rc = (x);                          \
+        if (_rc != HJB_OK) return cleanup_fail(_rc); \
+    } while (0)
+
+    // levels: halve while every axis has an even number of cells and the grid is above the coarse size
+    {
+        int n[3] = {d.n[0], d.dim > 1 ? d.n[1] : 1, d.dim > 2 ? d.n[2] : 1};
+        for (;;) {
+            Level L;
+            for (int a = 0; a < 3; ++a) L.g.n[a] = a < d.dim ? n[a] : 1;
+            L.g.N = (int64_t)L.g.n[0] * L.g.n[1] * L.g.n[2];
+            L.g.s1 = L.g.n[0];
+            L.g.s2 = (int64_t)L.g.n[0] * L.g.n[1];
+            hd->lev.push_back(L);
+            bool can = true, small = true;
+            for (int a = 0; a < d.dim; ++a) {
+                can = can && ((n[a] - 1) % 2 == 0) && ((n[a] - 1) / 2 + 1 >= 3);
+                small = small && n[a] <= std::max(3, d.min_coarse);
+            }
+            if (!can || (small && L.g.N <= kCoarseMaxNodes)) break;
+            for (int a = 0; a < d.dim; ++a) n[a] = (n[a] - 1) / 2 + 1;
+        }
+    }
+    for (size_t l = 0; l < hd->lev.size(); ++l) {
+        Level &L = hd->lev[l];
+        size_t n = (size_t)L.g.N;
+        STRY(dalloc(hd, (void **)&L.tab, (size_t)d.K * hd->npt * sizeof(PointTab)));
+        if (l > 0) STRY(dalloc(hd, (void **)&L.alpha, n * sizeof(int16_t)));
+        STRY(dalloc(hd, &L.r64, n * 8));
+        STRY(dalloc(hd, &L.e64, n * 8));
+        STRY(dalloc(hd, &L.t64, n * 8));
+        STRY(dalloc(hd, &L.d64, n * 8));
+        STRY(dalloc(hd, &L.r32, n * 4));
+        STRY(dalloc(hd, &L.e32, n * 4));
+        STRY(dalloc(hd, &L.t32, n * 4));
+        STRY(dalloc(hd, &L.d32, n * 4));
+    }
+    select_precision(hd);
+    const int m = kMaxRestart;
+    (void)m;
+    STRY(dalloc(hd, (void **)&hd->E, N * 8));
+    STRY(dalloc(hd, (void **)&hd->R, N * 8));
+    STRY(dalloc(hd, (void **)&hd->Vb, (size_t)(d.restart + 1) * N * 8));
+    STRY(dalloc(hd, (void **)&hd->Zb, (size_t)d.restart * N * 8));
+    STRY(dalloc(hd, (void **)&hd->Ua, N * 8));
+    STRY(dalloc(hd, (void **)&hd->Ub, N * 8));
+    STRY(dalloc(hd, (void **)&hd->a0, N * 2));
+    STRY(dalloc(hd, (void **)&hd->a1, N * 2));
+    STRY(dalloc(hd, (void **)&hd->acarry, N * 2));
+    size_t np = std::max<size_t>(3 * (size_t)hd->nb, (size_t)(kMaxRestart + 2) * hd->nbd);
+    STRY(dalloc(hd, (void **)&hd->partial, np * 8));
+    STRY(dalloc(hd, (void **)&hd->dvals, 256 * 8));
+    STRY(dalloc(hd, (void **)&hd->ipartial, (size_t)hd->nb * 8));
+    STRY(dalloc(hd, (void **)&hd->ival, 64));
+    if (!hd->c.empty()) {
+        STRY(dalloc(hd, (void **)&hd->c_dev, (size_t)d.K * 8));
+        hipError_t e = hipMemcpy(hd->c_dev, hd->c.data(), (size_t)d.K * 8, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return cleanup_fail(fail(HJB_EDEVICE, "%s", hipGetErrorString(e)));
+    }
+    {
+        hipError_t e = hipHostMalloc((void **)&hd->hpin, 256 * sizeof(double), hipHostMallocDefault);
+        if (e != hipSuccess) return cleanup_fail(fail(HJB_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e)));
+        e = hipHostMalloc((void **)&hd->hpin_i, 8 * sizeof(int64_t), hipHostMallocDefault);
+        if (e != hipSuccess) return cleanup_fail(fail(HJB_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e)));
+    }
+    STRY(build_tables(hd, 1.0));
+#undef STRY
+    *out = hd;
+    return HJB_OK;
+}
+
+int hjb_set_stream(hjb_handle *hd, void *stream) {
+    if (!hd) return fail(HJB_EINVAL, "null handle");
+    hd->stream = (hipStream_t)stream;
+    return HJB_OK;
+}
+
+int hjb_set_options(hjb_handle *hd, const hjb_desc *desc) {
+    if (!hd || !desc) return fail(HJB_EINVAL, "null argument");
+    TRY(check_options(desc));
+    if (desc->restart > hd->desc.restart)
+        return fail(HJB_EINVAL, "restart cannot grow beyond the value given at setup (%d)", hd->desc.restart);
+    hjb_desc &d = hd->desc;
+    d.precision = desc->precision;
+    d.precond = desc->precond;
+    d.restart = desc->restart;
+    d.max_krylov = desc->max_krylov;
+    d.max_pi = desc->max_pi;
+    d.nu1 = desc->nu1;
+    d.nu2 = desc->nu2;
+    d.coarse_sweeps = desc->coarse_sweeps;
+    d.omega = desc->omega;
+    d.rtol_inf = desc->rtol_inf;
+    d.tau_rel = desc->tau_rel;
+    select_precision(hd);
+    return HJB_OK;
+}
+
+int hjb_policy_sweep(hjb_handle *hd, const double *X, const double *U, const double *f0, const double *f1,
+                     double t_prev, double dt, double theta, double s, const int16_t *alpha_in, int16_t *alpha_out,
+                     double *gmin, double *margin, int32_t *ties, int64_t *n_changed, double *tau_used) {
+    if (!hd) return fail(HJB_EINVAL, "null handle");
+    if (!X || !U || !f0 || !f1 || !alpha_in || !alpha_out) return fail(HJB_EINVAL, "null array argument");
+    if (!finite_param(t_prev)) return fail(HJB_EINVAL, "t_prev must be finite");
+    TRY(check_time(dt, theta));
+    TRY(build_tables(hd, s));
+    int64_t ch = 0;
+    TRY(sweep(hd, X, U, f0, f1, t_prev, dt, theta, alpha_in, alpha_out, gmin, margin, ties, n_changed ? &ch : nullptr,
+              tau_used));
+    if (n_changed) *n_changed = ch;
+    return HJB_OK;
+}
+
+int hjb_apply(hjb_handle *hd, const int16_t *alpha, const double *x, double *y, double dt, double theta, double s) {
+    if (!hd) return fail(HJB_EINVAL, "null handle");
+    if (!alpha || !x || !y) return fail(HJB_EINVAL, "null array argument");
+    if (x == y) return fail(HJB_EINVAL, "x and y must be distinct");
+    TRY(check_time(dt, theta));
+    TRY(build_tables(hd, s));
+    TRY(check_policy(hd, alpha));
+    launch_apply(hd->dim, hd->lev[0].g, stencil(hd, 0), alpha, x, false, y, theta * dt, nullptr, hd->nb, hd->stream);
+    HIPCHK(hipGetLastError());
+    return HJB_OK;
+}
+
+int hjb_linsolve(hjb_handle *hd, const int16_t *alpha, const double *U, const double *f0, const double *f1,
+                 double t_prev, double dt, double theta, double s, double *X, hjb_step_stats *st) {
+    if (!hd) return fail(HJB_EINVAL, "null handle");
+    if (!alpha || !U || !f0 || !f1 || !X) return fail(HJB_EINVAL, "null array argument");
+    TRY(check_time(dt, theta));
+    if (theta == 0.0) return fail(HJB_EINVAL, "theta = 0 has no linear system");
+    TRY(build_tables(hd, s));
+    TRY(check_policy(hd, alpha));
+    int its = 0;
+    double res = 0.0;
+    int rc = linsolve_impl(hd, alpha, U, f0, f1, t_prev, dt, theta, X, &its, &res);
+    if (st) {
+        memset(st, 0, sizeof *st);
+        st->pi_iters = 0;
+        st->krylov_total = its;
+        st->krylov_max = its;
+        st->res_inf = res;
+        double den = 1.0 - theta * dt * hd->cplus;
+        st->cert_bound = den > 0 ? res / den : INFINITY;
+    }
+    hipError_t e = hipStreamSynchronize(hd->stream);
+    if (e != hipSuccess && rc == HJB_OK) rc = fail(HJB_EDEVICE, "%s", hipGetErrorString(e));
+    return rc;
+}
+
+int hjb_step(hjb_handle *hd, const double *Uprev, double *Unext, const double *f0, const double *f1, double t_prev,
+             double dt, double theta, double s, int16_t *alpha_io, hjb_step_stats *st) {
+    if (!hd) return fail(HJB_EINVAL, "null handle");
+    if (!Uprev || !Unext || !f0 || !f1 || !alpha_io) return fail(HJB_EINVAL, "null array argument");
+    if (Uprev == Unext) return fail(HJB_EINVAL, "Uprev and Unext must be distinct");
+    TRY(check_time(dt, theta));
+    if (theta == 0.0) return fail(HJB_EUNSUPPORTED, "explicit steps (theta = 0) are not provided by hjb_step");
+    TRY(build_tables(hd, s));
+    return step_impl(hd, Uprev, Unext, f0, f1, t_prev, dt, theta, alpha_io, st);
+}
+
+int hjb_solve(hjb_handle *hd, const double *g, const double *psi, const double *f0, const double *f1, int32_t n_steps,
+              const double *dts, const double *thetas, double s, double *U_final, int16_t *policies,
+              hjb_solve_stats *st) {
+    if (!hd) return fail(HJB_EINVAL, "null handle");
+    if (!g || !psi || !f0 || !f1 || !dts || !thetas || !U_final) return fail(HJB_EINVAL, "null argument");
+    if (n_steps < 0) return fail(HJB_EINVAL, "n_steps must be >= 0");
+    for (int n = 0; n < n_steps; ++n) {
+        TRY(check_time(dts[n], thetas[n]));
+        if (thetas[n] == 0.0) return fail(HJB_EUNSUPPORTED, "explicit steps (theta = 0) are not provided");
+    }
+    TRY(build_tables(hd, s));
+    const int64_t N = hd->N;
+    hipStream_t str = hd->stream;
+    hjb_solve_stats loc{};
+    HIPCHK(hipMemcpyAsync(hd->Ua, g, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
+    int16_t *acarry = hd->acarry;
+    launch_zero(acarry, (size_t)N * 2, str);
+    double *Ucur = hd->Ua, *Unx = hd->Ub;
+    double t = 0.0;
+    int rc = HJB_OK;
+    for (int n = 0; n < n_steps; ++n) {
+        HIPCHK(hipMemcpyAsync(Unx, psi, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
+        hjb_step_stats sst{};
+        rc = step_impl(hd, Ucur, Unx, f0, f1, t, dts[n], thetas[n], acarry, &sst);
+        loc.krylov_total += sst.krylov_total;
+        loc.pi_total += sst.pi_iters;
+        loc.flags |= sst.flags;
+        loc.max_cert_bound = std::max(loc.max_cert_bound, sst.cert_bound);
+        if (rc != HJB_OK) break;
+        if (policies) HIPCHK(hipMemcpyAsync(policies + (int64_t)n * N, acarry, (size_t)N * 2, hipMemcpyDeviceToDevice, str));
+        std::swap(Ucur, Unx);
+        t = t + dts[n];
+        loc.steps_done = n + 1;
+    }
+    HIPCHK(hipMemcpyAsync(U_final, Ucur, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
+    HIPCHK(hipStreamSynchronize(str));
+    if (st) *st = loc;
+    return rc;
+}
+
+void hjb_destroy(hjb_handle *hd) {
+    if (!hd) return;
+    if (hd->stream) (void)hipStreamSynchronize(hd->stream);
+    else (void)hipDeviceSynchronize();
+    for (void *p : hd->allocs) (void)hipFree(p);
+    if (hd->hpin) (void)hipHostFree(hd->hpin);
+    if (hd->hpin_i) (void)hipHostFree(hd->hpin_i);
+    delete hd;
+}
+
+}  // extern "C"

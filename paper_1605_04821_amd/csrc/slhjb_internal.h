@@ -1,0 +1,111 @@
+// Internal definitions shared by the kernels and the host driver of libslhjb.
+// Not part of the public C ABI (include/slhjb.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace slhjb {
+
+constexpr int kMaxP = 4;                 // diffusion columns per control
+constexpr int kMaxPts = 2 * kMaxP + 1;   // stencil points per control (Scheme 2: 2P diffusion + 1 drift)
+constexpr int kBlock = 256;              // threads per block of the node-parallel kernels
+constexpr int kMaxRestart = 64;
+
+// One stencil point of one control on one grid level.  Y is the displacement in cells of that level
+// (diffusion: s*sigma_p/sqrt(h) scaled to the level, drift: b scaled to the level).  The remaining
+// fields describe the landing when no truncation happens: cell offset floor(Y) per axis folded into a
+// linear offset, fractions t = Y - floor(Y) and u = 1 - t in both precisions.
+struct PointTab {
+    double Y[3];
+    double t[3];
+    double u[3];
+    float tf[3];
+    float uf[3];
+    int64_t off;
+};
+
+struct LevelDev {
+    int32_t n[3];
+    int32_t deep_lo[3], deep_hi[3];  // nodes with deep_lo <= i_d <= deep_hi never truncate
+    int64_t N;
+    int64_t s1, s2;                  // strides of axes 1 and 2
+};
+
+struct StencilDev {
+    const PointTab *tab;  // [K][npt]: points 2p (+sigma_p), 2p+1 (-sigma_p), 2P (drift, if any)
+    const double *c;      // [K] or nullptr
+    int32_t K, P, npt, has_drift;
+    double inv2h;         // 1/(2h) of the finest grid: coarse levels keep the physical displacement
+};
+
+// ---- kernel launchers (slhjb_kernels.hip) ----------------------------------------------------
+
+struct SweepOut {
+    int16_t *alpha_out;
+    double *gmin, *margin;
+    int32_t *ties;
+    int64_t *changed_partial;  // [nblocks]
+};
+
+void launch_sweep(int dim, const LevelDev &g, const StencilDev &st, const double *X, const double *U,
+                  const double *f0, const double *f1, double t_mid, double theta, double tau,
+                  const int16_t *a_in, const SweepOut &o, int nblocks, hipStream_t s);
+
+void launch_norms_xuf(int dim, const LevelDev &g, const double *X, const double *U, const double *f0,
+                      const double *f1, double t_mid, double *partial, int nblocks, hipStream_t s);
+
+// y = x - theta dt (L x + c x) on interior nodes, 0 on the boundary (x may be float or double)
+void launch_apply(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const void *x,
+                  bool x_is_float, double *y, double theta_dt, double *norm2_partial, int nblocks, hipStream_t s);
+
+// E = U + (1-theta) dt (L U + c U) + dt (f0 + t_mid f1)
+void launch_explicit(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const double *U,
+                     const double *f0, const double *f1, double t_mid, double omt_dt, double dt, double *E,
+                     int nblocks, hipStream_t s);
+
+// r = E - (V - theta dt (L V + c V)); partials: [3][nblocks] = sum r^2, max|r|, max|V| (interior)
+void launch_residual(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const double *V,
+                     const double *E, double theta_dt, double *r, double *partial, int nblocks, hipStream_t s);
+
+// multigrid level kernels, T = float or double
+template <typename T>
+void launch_diag(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, double theta_dt, T *d,
+                 hipStream_t s);
+template <typename T>
+void launch_jacobi(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const T *e, const T *r,
+                   const T *d, T *e_out, double theta_dt, double omega, bool first, hipStream_t s);
+template <typename T>
+void launch_level_residual(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const T *e,
+                           const T *r, T *res, double theta_dt, hipStream_t s);
+template <typename T>
+void launch_restrict(int dim, const LevelDev &gf, const LevelDev &gc, const T *rf, T *rc, hipStream_t s);
+template <typename T>
+void launch_prolong_add(int dim, const LevelDev &gf, const LevelDev &gc, const T *ec, T *ef, hipStream_t s);
+template <typename T>
+void launch_coarse_solve(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const T *r,
+                         const T *d, T *e, T *tmp, double theta_dt, double omega, int sweeps, hipStream_t s);
+void launch_bad_policy(int dim, const LevelDev &g, const int16_t *alpha, int K, int64_t *partial, int nblocks,
+                       hipStream_t s);
+void launch_inject_policy(int dim, const LevelDev &gf, const LevelDev &gc, const int16_t *af, int16_t *ac,
+                          hipStream_t s);
+
+// BLAS-1 (FP64 Krylov)
+void launch_multidot(const double *w, const double *V, int64_t ldv, int nvec, int64_t N, double *partial,
+                     int nblocks, hipStream_t s);
+void launch_multiaxpy(double *w, const double *V, int64_t ldv, int nvec, const double *coef, int64_t N,
+                      double *norm2_partial, int nblocks, hipStream_t s);
+void launch_reduce_sum(const double *partial, int nvec, int nblocks, double *out, hipStream_t s);
+void launch_reduce_max(const double *partial, int nvec, int nblocks, double *out, hipStream_t s);
+void launch_reduce_sum_i64(const int64_t *partial, int nblocks, int64_t *out, hipStream_t s);
+void launch_scale_by_inv_sqrt(double *dst, const double *src, const double *norm2, int64_t N, hipStream_t s);
+void launch_to_precond(const double *v, void *out, bool out_float, int64_t N, hipStream_t s);
+void launch_update_solution(double *X, const void *Z, bool z_float, int64_t ldz, int m, const double *y, int64_t N,
+                            hipStream_t s);
+void launch_axpy(double *y, double a, const double *x, int64_t N, hipStream_t s);
+void launch_copy_interior(int dim, const LevelDev &g, const double *src, double *dst, hipStream_t s);
+void launch_zero(void *p, size_t bytes, hipStream_t s);
+
+int blocks_for(int64_t N);
+
+}  // namespace slhjb

@@ -1,0 +1,1052 @@
+// HIP kernels of libslhjb for gfx950 (CDNA4).
+//
+// The operator is the truncated linear-interpolation semi-Lagrangian Scheme 2 of Reisinger &
+// Rotaetxe Arto (arXiv:1605.04821): diffusion points x +- sqrt(h) s sigma_p and drift point x + h b
+// (Section 1, "Examples of LISL schemes"), multilinear interpolation (eq. monotone_int), and
+// truncation at the box boundary with the weights A_p, B_p of eq. eqn_Ap and C = 1/mu of
+// eq. eqn_APp1 (Prop. pro:scheme2), summed as in eq. TruncScheme.
+//
+// Arithmetic of the FP64 operator (identical in every kernel that evaluates it):
+//   displacement in cells Y; mu = min(1, min_d D_d/|Y_d|) with D_d the integer distance to the face
+//   the point moves towards; if mu == 1 the landing cell is i + floor(Y) with fraction Y - floor(Y);
+//   otherwise the limiting coordinate is the face index and the others i + mu*Y (clamped); a landing
+//   cell n-1 becomes cell n-2 with fraction 1; interpolation is the nested lerp (1-t)*a + t*b,
+//   innermost over x; term_p = (A*v+ + B*v-) - (A+B)*V_i, drift 2C*(v_b - V_i), L = (1/2h)*sum.
+// Compiled without floating-point contraction, so these expressions round exactly as written.
+//
+// Thread mapping: one node per thread, x fastest; blocks are renumbered so that each of the eight
+// XCDs (which take hardware blocks round-robin) works on one contiguous slab of rows and keeps the
+// stencil halo of its slab in its own L2.
+
+#include "slhjb_internal.h"
+
+namespace slhjb {
+
+int blocks_for(int64_t N) { return (int)((N + kBlock - 1) / kBlock); }
+
+__device__ __forceinline__ int remap_block(int b, int nb) {
+    int q = nb >> 3, r = nb & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+__device__ __forceinline__ int node_id() { return remap_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; }
+
+template <int DIM>
+__device__ __forceinline__ void unflatten(const LevelDev &g, int i, int ix[3]) {
+    if (DIM == 2) {
+        ix[1] = i / g.n[0];
+        ix[0] = i - ix[1] * g.n[0];
+        ix[2] = 0;
+    } else {
+        int r = i / g.n[0];
+        ix[0] = i - r * g.n[0];
+        ix[2] = r / g.n[1];
+        ix[1] = r - ix[2] * g.n[1];
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ bool interior(const LevelDev &g, const int ix[3]) {
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) ok = ok && ix[d] > 0 && ix[d] < g.n[d] - 1;
+    return ok;
+}
+
+template <int DIM>
+__device__ __forceinline__ bool deep_node(const LevelDev &g, const int ix[3]) {
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) ok = ok && ix[d] >= g.deep_lo[d] && ix[d] <= g.deep_hi[d];
+    return ok;
+}
+
+// ---- landing of a (possibly truncated) stencil point -------------------------------------------
+
+template <int DIM>
+__device__ __forceinline__ double landing(const LevelDev &g, const int ix[3], const double Y[3], int cell[3],
+                                          double t[3]) {
+    double m[3];
+    double mu = 1.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        m[d] = __builtin_inf();
+        if (Y[d] != 0.0) {
+            int D = (Y[d] > 0.0) ? (g.n[d] - 1 - ix[d]) : ix[d];
+            m[d] = (double)D / fabs(Y[d]);
+            if (m[d] < mu) mu = m[d];
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        int c;
+        double tt;
+        if (mu == 1.0) {
+            double fl = floor(Y[d]);
+            c = ix[d] + (int)fl;
+            tt = Y[d] - fl;
+        } else if (Y[d] != 0.0 && m[d] == mu) {
+            c = (Y[d] > 0.0) ? g.n[d] - 1 : 0;
+            tt = 0.0;
+        } else {
+            double q = (double)ix[d] + mu * Y[d];
+            q = q < 0.0 ? 0.0 : q;
+            double top = (double)(g.n[d] - 1);
+            q = q > top ? top : q;
+            double fl = floor(q);
+            c = (int)fl;
+            tt = q - fl;
+        }
+        if (c >= g.n[d] - 1) {
+            c = g.n[d] - 2;
+            tt = 1.0;
+        }
+        cell[d] = c;
+        t[d] = tt;
+    }
+    return mu;
+}
+
+template <typename T>
+__device__ __forceinline__ T lerp_tu(T a, T b, T t, T u) {
+    return u * a + t * b;
+}
+
+// nested multilinear interpolation from corner `base`, innermost over x; TS = storage, TC = arithmetic
+template <int DIM, typename TS, typename TC>
+__device__ __forceinline__ TC interp_base(const TS *__restrict__ V, int base, const LevelDev &g, const TC t[3],
+                                          const TC u[3]) {
+    const int s1 = (int)g.s1;
+    TC a = lerp_tu<TC>((TC)V[base], (TC)V[base + 1], t[0], u[0]);
+    TC b = lerp_tu<TC>((TC)V[base + s1], (TC)V[base + s1 + 1], t[0], u[0]);
+    TC v0 = lerp_tu<TC>(a, b, t[1], u[1]);
+    if (DIM == 2) return v0;
+    const int s2 = (int)g.s2;
+    TC c = lerp_tu<TC>((TC)V[base + s2], (TC)V[base + s2 + 1], t[0], u[0]);
+    TC e = lerp_tu<TC>((TC)V[base + s2 + s1], (TC)V[base + s2 + s1 + 1], t[0], u[0]);
+    TC v1 = lerp_tu<TC>(c, e, t[1], u[1]);
+    return lerp_tu<TC>(v0, v1, t[2], u[2]);
+}
+
+template <typename T>
+struct Frac;
+template <>
+struct Frac<double> {
+    static __device__ __forceinline__ void get(const PointTab &p, double t[3], double u[3]) {
+        t[0] = p.t[0]; t[1] = p.t[1]; t[2] = p.t[2];
+        u[0] = p.u[0]; u[1] = p.u[1]; u[2] = p.u[2];
+    }
+};
+template <>
+struct Frac<float> {
+    static __device__ __forceinline__ void get(const PointTab &p, float t[3], float u[3]) {
+        t[0] = p.tf[0]; t[1] = p.tf[1]; t[2] = p.tf[2];
+        u[0] = p.uf[0]; u[1] = p.uf[1]; u[2] = p.uf[2];
+    }
+};
+
+template <int DIM, typename TS, typename TC>
+__device__ __forceinline__ TC interp_fast(const TS *__restrict__ V, int i, const PointTab &p, const LevelDev &g) {
+    TC t[3], u[3];
+    Frac<TC>::get(p, t, u);
+    return interp_base<DIM, TS, TC>(V, i + (int)p.off, g, t, u);
+}
+
+template <int DIM, typename TS, typename TC>
+__device__ __forceinline__ TC interp_land(const TS *__restrict__ V, const LevelDev &g, const int cell[3],
+                                          const double td[3]) {
+    TC t[3], u[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        t[d] = (TC)td[d];
+        u[d] = (TC)(1.0 - td[d]);
+    }
+    int base = cell[0] + cell[1] * (int)g.s1 + (DIM == 3 ? cell[2] * (int)g.s2 : 0);
+    return interp_base<DIM, TS, TC>(V, base, g, t, u);
+}
+
+// (L-hat^k V)_i for one or two fields sharing the stencil geometry (eq. TruncScheme).
+// TS: storage type of the fields, TC: arithmetic type.
+template <int DIM, typename TS, typename TC, bool TWO>
+__device__ __forceinline__ void lhat_node(const LevelDev &g, const StencilDev &st, int k, int i, const int ix[3],
+                                          bool deep, const TS *__restrict__ V, TC Vi, const TS *__restrict__ W, TC Wi,
+                                          TC &outV, TC &outW) {
+    // policies are validated on entry; the clamp only keeps table reads in bounds
+    k = ((unsigned)k < (unsigned)st.K) ? k : 0;
+    const PointTab *pt = st.tab + k * st.npt;
+    TC accV = (TC)0, accW = (TC)0;
+    if (deep) {
+        for (int p = 0; p < st.P; ++p) {
+            const PointTab &a = pt[2 * p];
+            const PointTab &b = pt[2 * p + 1];
+            TC vp = interp_fast<DIM, TS, TC>(V, i, a, g);
+            TC vm = interp_fast<DIM, TS, TC>(V, i, b, g);
+            accV = accV + ((vp + vm) - (TC)2 * Vi);
+            if (TWO) {
+                TC wp = interp_fast<DIM, TS, TC>(W, i, a, g);
+                TC wm = interp_fast<DIM, TS, TC>(W, i, b, g);
+                accW = accW + ((wp + wm) - (TC)2 * Wi);
+            }
+        }
+        if (st.has_drift) {
+            const PointTab &c = pt[2 * st.P];
+            TC vb = interp_fast<DIM, TS, TC>(V, i, c, g);
+            accV = accV + (TC)2 * (vb - Vi);
+            if (TWO) {
+                TC wb = interp_fast<DIM, TS, TC>(W, i, c, g);
+                accW = accW + (TC)2 * (wb - Wi);
+            }
+        }
+    } else {
+        for (int p = 0; p < st.P; ++p) {
+            const PointTab &a = pt[2 * p];
+            const PointTab &b = pt[2 * p + 1];
+            double Ya[3] = {a.Y[0], a.Y[1], a.Y[2]};
+            double Yb[3] = {b.Y[0], b.Y[1], b.Y[2]};
+            int cp[3], cm[3];
+            double tp[3], tm[3];
+            double mup = landing<DIM>(g, ix, Ya, cp, tp);
+            double mum = landing<DIM>(g, ix, Yb, cm, tm);
+            double A = 2.0 / (mup * (mup + mum));
+            double B = 2.0 / (mum * (mum + mup));
+            TC At = (TC)A, Bt = (TC)B, ABt = (TC)(A + B);
+            TC vp = interp_land<DIM, TS, TC>(V, g, cp, tp);
+            TC vm = interp_land<DIM, TS, TC>(V, g, cm, tm);
+            accV = accV + ((At * vp + Bt * vm) - ABt * Vi);
+            if (TWO) {
+                TC wp = interp_land<DIM, TS, TC>(W, g, cp, tp);
+                TC wm = interp_land<DIM, TS, TC>(W, g, cm, tm);
+                accW = accW + ((At * wp + Bt * wm) - ABt * Wi);
+            }
+        }
+        if (st.has_drift) {
+            const PointTab &c = pt[2 * st.P];
+            double Yc[3] = {c.Y[0], c.Y[1], c.Y[2]};
+            int cb[3];
+            double tb[3];
+            double mub = landing<DIM>(g, ix, Yc, cb, tb);
+            double C = 1.0 / mub;
+            TC C2 = (TC)(2.0 * C);
+            TC vb = interp_land<DIM, TS, TC>(V, g, cb, tb);
+            accV = accV + C2 * (vb - Vi);
+            if (TWO) {
+                TC wb = interp_land<DIM, TS, TC>(W, g, cb, tb);
+                accW = accW + C2 * (wb - Wi);
+            }
+        }
+    }
+    outV = (TC)st.inv2h * accV;
+    if (TWO) outW = (TC)st.inv2h * accW;
+}
+
+template <int DIM, typename TS, typename TC>
+__device__ __forceinline__ TC lhat1(const LevelDev &g, const StencilDev &st, int k, int i, const int ix[3], bool deep,
+                                    const TS *__restrict__ V, TC Vi) {
+    TC a, b;
+    lhat_node<DIM, TS, TC, false>(g, st, k, i, ix, deep, V, Vi, V, Vi, a, b);
+    return a;
+}
+
+// ---- block reductions ----------------------------------------------------------------------------
+
+template <typename T, typename Op>
+__device__ __forceinline__ T block_reduce(T v, Op op, T *sh) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = op(v, __shfl_down(v, off, 64));
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    int nw = (blockDim.x + 63) >> 6;
+    T r = sh[0];
+    for (int w = 1; w < nw; ++w) r = op(r, sh[w]);
+    return r;
+}
+
+struct OpSum {
+    template <typename T>
+    __device__ T operator()(T a, T b) const { return a + b; }
+};
+struct OpMax {
+    __device__ double operator()(double a, double b) const { return a > b ? a : b; }
+};
+
+// ---- policy search (Howard's algorithm, eq. nonlinear_sys) ----------------------------------------
+
+template <int DIM, bool CN>
+__device__ __forceinline__ double eval_G(const LevelDev &g, const StencilDev &st, int k, int i, const int ix[3],
+                                         bool deep, const double *__restrict__ X, double Xi,
+                                         const double *__restrict__ U, double Ui, double theta, double omt, double f) {
+    double lx, lu = 0.0;
+    if (CN)
+        lhat_node<DIM, double, double, true>(g, st, k, i, ix, deep, X, Xi, U, Ui, lx, lu);
+    else
+        lx = lhat1<DIM, double, double>(g, st, k, i, ix, deep, X, Xi);
+    double ck = st.c ? st.c[((unsigned)k < (unsigned)st.K) ? k : 0] : 0.0;
+    return theta * (lx + ck * Xi) + omt * (lu + ck * Ui) + f;
+}
+
+template <int DIM, bool CN, bool EXTRA>
+__global__ __launch_bounds__(kBlock) void k_sweep(LevelDev g, StencilDev st, const double *__restrict__ X,
+                                                  const double *__restrict__ U, const double *__restrict__ f0,
+                                                  const double *__restrict__ f1, double t_mid, double theta,
+                                                  double tau, const int16_t *__restrict__ a_in, SweepOut o) {
+    __shared__ int64_t sh[kBlock / 64];
+    int i = node_id();
+    int64_t changed = 0;
+    if (i < g.N) {
+        int ix[3];
+        unflatten<DIM>(g, i, ix);
+        if (!interior<DIM>(g, ix)) {
+            o.alpha_out[i] = -1;
+            if (o.gmin) o.gmin[i] = 0.0;
+            if (EXTRA) {
+                if (o.margin) o.margin[i] = __builtin_inf();
+                if (o.ties) o.ties[i] = 0;
+            }
+        } else {
+            bool deep = deep_node<DIM>(g, ix);
+            double Xi = X[i], Ui = U[i];
+            double f = f0[i] + t_mid * f1[i];
+            double omt = 1.0 - theta;
+            int cur = a_in[i];
+            double best = __builtin_inf(), gcur = __builtin_inf();
+            int kbest = 0;
+            for (int k = 0; k < st.K; ++k) {
+                double G = eval_G<DIM, CN>(g, st, k, i, ix, deep, X, Xi, U, Ui, theta, omt, f);
+                if (G < best) {
+                    best = G;
+                    kbest = k;
+                }
+                if (k == cur) gcur = G;
+            }
+            double thr = best + tau;
+            int pick;
+            if (cur >= 0 && cur < st.K && gcur <= thr) {
+                pick = cur;
+            } else {
+                pick = kbest;
+                for (int k = 0; k < kbest; ++k) {
+                    double G = eval_G<DIM, CN>(g, st, k, i, ix, deep, X, Xi, U, Ui, theta, omt, f);
+                    if (G <= thr) {
+                        pick = k;
+                        break;
+                    }
+                }
+            }
+            o.alpha_out[i] = (int16_t)pick;
+            changed = (pick != cur) ? 1 : 0;
+            if (o.gmin) o.gmin[i] = best;
+            if (EXTRA) {
+                double mg = __builtin_inf();
+                int nt = 0;
+                for (int k = 0; k < st.K; ++k) {
+                    double G = eval_G<DIM, CN>(g, st, k, i, ix, deep, X, Xi, U, Ui, theta, omt, f);
+                    if (G <= thr)
+                        ++nt;
+                    else if (G - best < mg)
+                        mg = G - best;
+                }
+                if (o.margin) o.margin[i] = mg;
+                if (o.ties) o.ties[i] = nt;
+            }
+        }
+    }
+    int64_t tot = block_reduce<int64_t>(changed, OpSum(), sh);
+    if (threadIdx.x == 0) o.changed_partial[remap_block(blockIdx.x, gridDim.x)] = tot;
+}
+
+void launch_sweep(int dim, const LevelDev &g, const StencilDev &st, const double *X, const double *U,
+                  const double *f0, const double *f1, double t_mid, double theta, double tau, const int16_t *a_in,
+                  const SweepOut &o, int nblocks, hipStream_t s) {
+    bool cn = theta != 1.0;
+    bool extra = o.margin != nullptr || o.ties != nullptr;
+#define SW(D, C, E) hipLaunchKernelGGL((k_sweep<D, C, E>), dim3(nblocks), dim3(kBlock), 0, s, g, st, X, U, f0, f1, \
+                                       t_mid, theta, tau, a_in, o)
+    if (dim == 2) {
+        if (cn) { if (extra) SW(2, true, true); else SW(2, true, false); }
+        else { if (extra) SW(2, false, true); else SW(2, false, false); }
+    } else {
+        if (cn) { if (extra) SW(3, true, true); else SW(3, true, false); }
+        else { if (extra) SW(3, false, true); else SW(3, false, false); }
+    }
+#undef SW
+}
+
+// max over all nodes of max(|X|,|U|) and over interior nodes of |f0 + t_mid f1|
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_norms_xuf(LevelDev g, const double *__restrict__ X,
+                                                      const double *__restrict__ U, const double *__restrict__ f0,
+                                                      const double *__restrict__ f1, double t_mid, double *partial) {
+    __shared__ double sh[kBlock / 64];
+    int i = node_id();
+    double vx = 0.0, vf = 0.0;
+    if (i < g.N) {
+        vx = fmax(fabs(X[i]), fabs(U[i]));
+        int ix[3];
+        unflatten<DIM>(g, i, ix);
+        if (interior<DIM>(g, ix)) vf = fabs(f0[i] + t_mid * f1[i]);
+    }
+    int b = remap_block(blockIdx.x, gridDim.x);
+    double a = block_reduce<double>(vx, OpMax(), sh);
+    if (threadIdx.x == 0) partial[b] = a;
+    double c = block_reduce<double>(vf, OpMax(), sh);
+    if (threadIdx.x == 0) partial[gridDim.x + b] = c;
+}
+
+void launch_norms_xuf(int dim, const LevelDev &g, const double *X, const double *U, const double *f0, const double *f1,
+                      double t_mid, double *partial, int nblocks, hipStream_t s) {
+    if (dim == 2)
+        hipLaunchKernelGGL(k_norms_xuf<2>, dim3(nblocks), dim3(kBlock), 0, s, g, X, U, f0, f1, t_mid, partial);
+    else
+        hipLaunchKernelGGL(k_norms_xuf<3>, dim3(nblocks), dim3(kBlock), 0, s, g, X, U, f0, f1, t_mid, partial);
+}
+
+// ---- FP64 operator kernels ------------------------------------------------------------------------
+
+template <int DIM, typename TX>
+__global__ __launch_bounds__(kBlock) void k_apply(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
+                                                  const TX *__restrict__ x, double *__restrict__ y, double theta_dt,
+                                                  double *norm2_partial) {
+    __shared__ double sh[kBlock / 64];
+    int i = node_id();
+    double yy = 0.0;
+    if (i < g.N) {
+        int ix[3];
+        unflatten<DIM>(g, i, ix);
+        if (interior<DIM>(g, ix)) {
+            int k = alpha[i];
+            bool deep = deep_node<DIM>(g, ix);
+            double xi = (double)x[i];
+            double l = lhat1<DIM, TX, double>(g, st, k, i, ix, deep, x, xi);
+            double ck = st.c ? st.c[((unsigned)k < (unsigned)st.K) ? k : 0] : 0.0;
+            yy = xi - theta_dt * (l + ck * xi);
+        }
+        y[i] = yy;
+    }
+    if (norm2_partial) {
+        double t = block_reduce<double>(yy * yy, OpSum(), sh);
+        if (threadIdx.x == 0) norm2_partial[remap_block(blockIdx.x, gridDim.x)] = t;
+    }
+}
+
+void launch_apply(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const void *x,
+                  bool x_is_float, double *y, double theta_dt, double *norm2_partial, int nblocks, hipStream_t s) {
+#define AP(D, TX) hipLaunchKernelGGL((k_apply<D, TX>), dim3(nblocks), dim3(kBlock), 0, s, g, st, alpha, \
+                                     (const TX *)x, y, theta_dt, norm2_partial)
+    if (x_is_float) {
+        if (dim == 2) AP(2, float); else AP(3, float);
+    } else {
+        if (dim == 2) AP(2, double); else AP(3, double);
+    }
+#undef AP
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_explicit(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
+                                                     const double *__restrict__ U, const double *__restrict__ f0,
+                                                     const double *__restrict__ f1, double t_mid, double omt_dt,
+                                                     double dt, double *__restrict__ E) {
+    int i = node_id();
+    if (i >= g.N) return;
+    int ix[3];
+    unflatten<DIM>(g, i, ix);
+    double e = 0.0;
+    if (interior<DIM>(g, ix)) {
+        double f = f0[i] + t_mid * f1[i];
+        double Ui = U[i];
+        if (omt_dt != 0.0) {
+            int k = alpha[i];
+            bool deep = deep_node<DIM>(g, ix);
+            double l = lhat1<DIM, double, double>(g, st, k, i, ix, deep, U, Ui);
+            double ck = st.c ? st.c[((unsigned)k < (unsigned)st.K) ? k : 0] : 0.0;
+            e = Ui + omt_dt * (l + ck * Ui) + dt * f;
+        } else {
+            e = Ui + dt * f;
+        }
+    }
+    E[i] = e;
+}
+
+void launch_explicit(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const double *U,
+                     const double *f0, const double *f1, double t_mid, double omt_dt, double dt, double *E, int nblocks,
+                     hipStream_t s) {
+    if (dim == 2)
+        hipLaunchKernelGGL(k_explicit<2>, dim3(nblocks), dim3(kBlock), 0, s, g, st, alpha, U, f0, f1, t_mid, omt_dt, dt,
+                           E);
+    else
+        hipLaunchKernelGGL(k_explicit<3>, dim3(nblocks), dim3(kBlock), 0, s, g, st, alpha, U, f0, f1, t_mid, omt_dt, dt,
+                           E);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_residual(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
+                                                     const double *__restrict__ V, const double *__restrict__ E,
+                                                     double theta_dt, double *__restrict__ r, double *partial) {
+    __shared__ double sh[kBlock / 64];
+    int i = node_id();
+    double rr = 0.0, vv = 0.0;
+    if (i < g.N) {
+        int ix[3];
+        unflatten<DIM>(g, i, ix);
+        double Vi = V[i];
+        vv = fabs(Vi);
+        if (interior<DIM>(g, ix)) {
+            int k = alpha[i];
+            bool deep = deep_node<DIM>(g, ix);
+            double l = lhat1<DIM, double, double>(g, st, k, i, ix, deep, V, Vi);
+            double ck = st.c ? st.c[((unsigned)k < (unsigned)st.K) ? k : 0] : 0.0;
+            rr = E[i] - (Vi - theta_dt * (l + ck * Vi));
+        }
+        r[i] = rr;
+    }
+    int b = remap_block(blockIdx.x, gridDim.x);
+    double s2 = block_reduce<double>(rr * rr, OpSum(), sh);
+    if (threadIdx.x == 0) partial[b] = s2;
+    double m = block_reduce<double>(fabs(rr), OpMax(), sh);
+    if (threadIdx.x == 0) partial[gridDim.x + b] = m;
+    double mv = block_reduce<double>(vv, OpMax(), sh);
+    if (threadIdx.x == 0) partial[2 * gridDim.x + b] = mv;
+}
+
+void launch_residual(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const double *V,
+                     const double *E, double theta_dt, double *r, double *partial, int nblocks, hipStream_t s) {
+    if (dim == 2)
+        hipLaunchKernelGGL(k_residual<2>, dim3(nblocks), dim3(kBlock), 0, s, g, st, alpha, V, E, theta_dt, r, partial);
+    else
+        hipLaunchKernelGGL(k_residual<3>, dim3(nblocks), dim3(kBlock), 0, s, g, st, alpha, V, E, theta_dt, r, partial);
+}
+
+// number of interior nodes whose control index is outside [0, K)
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_bad_policy(LevelDev g, const int16_t *__restrict__ alpha, int K,
+                                                       int64_t *partial) {
+    __shared__ int64_t sh[kBlock / 64];
+    int i = node_id();
+    int64_t bad = 0;
+    if (i < g.N) {
+        int ix[3];
+        unflatten<DIM>(g, i, ix);
+        if (interior<DIM>(g, ix)) {
+            int k = alpha[i];
+            bad = (k < 0 || k >= K) ? 1 : 0;
+        }
+    }
+    int64_t t = block_reduce<int64_t>(bad, OpSum(), sh);
+    if (threadIdx.x == 0) partial[remap_block(blockIdx.x, gridDim.x)] = t;
+}
+
+void launch_bad_policy(int dim, const LevelDev &g, const int16_t *alpha, int K, int64_t *partial, int nblocks,
+                       hipStream_t s) {
+    if (dim == 2)
+        hipLaunchKernelGGL(k_bad_policy<2>, dim3(nblocks), dim3(kBlock), 0, s, g, alpha, K, partial);
+    else
+        hipLaunchKernelGGL(k_bad_policy<3>, dim3(nblocks), dim3(kBlock), 0, s, g, alpha, K, partial);
+}
+
+// ---- multigrid level kernels ----------------------------------------------------------------------
+
+// diagonal of A = I - theta dt (L-hat + c) on one level: d = 1 - theta dt (l_ii + c)
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_diag(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
+                                                 double theta_dt, T *__restrict__ d) {
+    int i = node_id();
+    if (i >= g.N) return;
+    int ix[3];
+    unflatten<DIM>(g, i, ix);
+    if (!interior<DIM>(g, ix)) {
+        d[i] = (T)1;
+        return;
+    }
+    int k = alpha[i];
+    k = ((unsigned)k < (unsigned)st.K) ? k : 0;
+    const PointTab *pt = st.tab + k * st.npt;
+    double lii = 0.0;
+    for (int q = 0; q < st.npt; ++q) {
+        double Y[3] = {pt[q].Y[0], pt[q].Y[1], pt[q].Y[2]};
+        int cell[3];
+        double t[3];
+        double mu = landing<DIM>(g, ix, Y, cell, t);
+        double W;
+        if (q < 2 * st.P) {
+            double Yo[3] = {pt[q ^ 1].Y[0], pt[q ^ 1].Y[1], pt[q ^ 1].Y[2]};
+            int co[3];
+            double to[3];
+            double muo = landing<DIM>(g, ix, Yo, co, to);
+            W = 2.0 / (mu * (mu + muo));
+        } else {
+            W = 2.0 / mu;
+        }
+        double wself = 1.0;
+        for (int dd = 0; dd < DIM; ++dd) {
+            if (ix[dd] == cell[dd])
+                wself *= (1.0 - t[dd]);
+            else if (ix[dd] == cell[dd] + 1)
+                wself *= t[dd];
+            else
+                wself = 0.0;
+        }
+        lii += W * (wself - 1.0);
+    }
+    lii *= st.inv2h;
+    double ck = st.c ? st.c[((unsigned)k < (unsigned)st.K) ? k : 0] : 0.0;
+    d[i] = (T)(1.0 - theta_dt * (lii + ck));
+}
+
+template <typename T>
+void launch_diag(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, double theta_dt, T *d,
+                 hipStream_t s) {
+    int nb = blocks_for(g.N);
+    if (dim == 2)
+        hipLaunchKernelGGL((k_diag<2, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, theta_dt, d);
+    else
+        hipLaunchKernelGGL((k_diag<3, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, theta_dt, d);
+}
+
+template <int DIM, typename T>
+__device__ __forceinline__ T apply_level(const LevelDev &g, const StencilDev &st, const int16_t *__restrict__ alpha,
+                                         const T *__restrict__ e, int i, const int ix[3], T theta_dt) {
+    int k = alpha[i];
+    bool deep = deep_node<DIM>(g, ix);
+    T ei = e[i];
+    T l = lhat1<DIM, T, T>(g, st, k, i, ix, deep, e, ei);
+    T ck = st.c ? (T)st.c[((unsigned)k < (unsigned)st.K) ? k : 0] : (T)0;
+    return ei - theta_dt * (l + ck * ei);
+}
+
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_jacobi(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
+                                                   const T *__restrict__ e, const T *__restrict__ r,
+                                                   const T *__restrict__ d, T *__restrict__ e_out, T theta_dt, T omega,
+                                                   int first) {
+    int i = node_id();
+    if (i >= g.N) return;
+    int ix[3];
+    unflatten<DIM>(g, i, ix);
+    T v = (T)0;
+    if (interior<DIM>(g, ix)) {
+        if (first) {
+            v = omega * r[i] / d[i];
+        } else {
+            T ae = apply_level<DIM, T>(g, st, alpha, e, i, ix, theta_dt);
+            v = e[i] + omega * (r[i] - ae) / d[i];
+        }
+    }
+    e_out[i] = v;
+}
+
+template <typename T>
+void launch_jacobi(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const T *e, const T *r,
+                   const T *d, T *e_out, double theta_dt, double omega, bool first, hipStream_t s) {
+    int nb = blocks_for(g.N);
+    if (dim == 2)
+        hipLaunchKernelGGL((k_jacobi<2, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, e, r, d, e_out, (T)theta_dt,
+                           (T)omega, (int)first);
+    else
+        hipLaunchKernelGGL((k_jacobi<3, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, e, r, d, e_out, (T)theta_dt,
+                           (T)omega, (int)first);
+}
+
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_level_residual(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
+                                                           const T *__restrict__ e, const T *__restrict__ r,
+                                                           T *__restrict__ res, T theta_dt) {
+    int i = node_id();
+    if (i >= g.N) return;
+    int ix[3];
+    unflatten<DIM>(g, i, ix);
+    T v = (T)0;
+    if (interior<DIM>(g, ix)) v = r[i] - apply_level<DIM, T>(g, st, alpha, e, i, ix, theta_dt);
+    res[i] = v;
+}
+
+template <typename T>
+void launch_level_residual(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const T *e,
+                           const T *r, T *res, double theta_dt, hipStream_t s) {
+    int nb = blocks_for(g.N);
+    if (dim == 2)
+        hipLaunchKernelGGL((k_level_residual<2, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, e, r, res,
+                           (T)theta_dt);
+    else
+        hipLaunchKernelGGL((k_level_residual<3, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, e, r, res,
+                           (T)theta_dt);
+}
+
+// full weighting: weights 1/4, 1/2, 1/4 per axis around fine node 2I
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict(LevelDev gf, LevelDev gc, const T *__restrict__ rf,
+                                                     T *__restrict__ rc) {
+    int I = node_id();
+    if (I >= gc.N) return;
+    int ix[3];
+    unflatten<DIM>(gc, I, ix);
+    T v = (T)0;
+    if (interior<DIM>(gc, ix)) {
+        int c = 2 * ix[0] + 2 * ix[1] * (int)gf.s1 + (DIM == 3 ? 2 * ix[2] * (int)gf.s2 : 0);
+        const T w[3] = {(T)0.25, (T)0.5, (T)0.25};
+        if (DIM == 2) {
+            for (int b = -1; b <= 1; ++b) {
+                T row = w[0] * rf[c + b * (int)gf.s1 - 1] + w[1] * rf[c + b * (int)gf.s1] + w[2] * rf[c + b * (int)gf.s1 + 1];
+                v += w[b + 1] * row;
+            }
+        } else {
+            for (int cc = -1; cc <= 1; ++cc) {
+                T pl = (T)0;
+                for (int b = -1; b <= 1; ++b) {
+                    int o = c + cc * (int)gf.s2 + b * (int)gf.s1;
+                    T row = w[0] * rf[o - 1] + w[1] * rf[o] + w[2] * rf[o + 1];
+                    pl += w[b + 1] * row;
+                }
+                v += w[cc + 1] * pl;
+            }
+        }
+    }
+    rc[I] = v;
+}
+
+template <typename T>
+void launch_restrict(int dim, const LevelDev &gf, const LevelDev &gc, const T *rf, T *rc, hipStream_t s) {
+    int nb = blocks_for(gc.N);
+    if (dim == 2)
+        hipLaunchKernelGGL((k_restrict<2, T>), dim3(nb), dim3(kBlock), 0, s, gf, gc, rf, rc);
+    else
+        hipLaunchKernelGGL((k_restrict<3, T>), dim3(nb), dim3(kBlock), 0, s, gf, gc, rf, rc);
+}
+
+// multilinear prolongation of the coarse correction, added on fine interior nodes
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong_add(LevelDev gf, LevelDev gc, const T *__restrict__ ec,
+                                                        T *__restrict__ ef) {
+    int i = node_id();
+    if (i >= gf.N) return;
+    int ix[3];
+    unflatten<DIM>(gf, i, ix);
+    if (!interior<DIM>(gf, ix)) return;
+    int lo[3], hi[3];
+    T wl[3], wh[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (d < DIM) {
+            lo[d] = ix[d] >> 1;
+            if (ix[d] & 1) {
+                hi[d] = lo[d] + 1;
+                wl[d] = (T)0.5;
+                wh[d] = (T)0.5;
+            } else {
+                hi[d] = lo[d];
+                wl[d] = (T)1;
+                wh[d] = (T)0;
+            }
+        } else {
+            lo[d] = hi[d] = 0;
+            wl[d] = (T)1;
+            wh[d] = (T)0;
+        }
+    }
+    const int s1 = (int)gc.s1, s2 = (int)gc.s2;
+    T v;
+    auto at = [&](int a, int b, int c) { return ec[a + b * s1 + (DIM == 3 ? c * s2 : 0)]; };
+    T a0 = wl[0] * at(lo[0], lo[1], lo[2]) + wh[0] * at(hi[0], lo[1], lo[2]);
+    T a1 = wl[0] * at(lo[0], hi[1], lo[2]) + wh[0] * at(hi[0], hi[1], lo[2]);
+    v = wl[1] * a0 + wh[1] * a1;
+    if (DIM == 3) {
+        T b0 = wl[0] * at(lo[0], lo[1], hi[2]) + wh[0] * at(hi[0], lo[1], hi[2]);
+        T b1 = wl[0] * at(lo[0], hi[1], hi[2]) + wh[0] * at(hi[0], hi[1], hi[2]);
+        v = wl[2] * v + wh[2] * (wl[1] * b0 + wh[1] * b1);
+    }
+    ef[i] += v;
+}
+
+template <typename T>
+void launch_prolong_add(int dim, const LevelDev &gf, const LevelDev &gc, const T *ec, T *ef, hipStream_t s) {
+    int nb = blocks_for(gf.N);
+    if (dim == 2)
+        hipLaunchKernelGGL((k_prolong_add<2, T>), dim3(nb), dim3(kBlock), 0, s, gf, gc, ec, ef);
+    else
+        hipLaunchKernelGGL((k_prolong_add<3, T>), dim3(nb), dim3(kBlock), 0, s, gf, gc, ec, ef);
+}
+
+// Coarsest level: Jacobi sweeps by one workgroup with the iterate held in LDS.
+template <int DIM, typename T>
+__global__ __launch_bounds__(1024) void k_coarse_solve(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
+                                                       const T *__restrict__ r, const T *__restrict__ d,
+                                                       T *__restrict__ e, T theta_dt, T omega, int sweeps) {
+    extern __shared__ unsigned char smem[];
+    T *a = reinterpret_cast<T *>(smem);
+    T *b = a + g.N;
+    const int N = (int)g.N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        int ix[3];
+        unflatten<DIM>(g, i, ix);
+        a[i] = interior<DIM>(g, ix) ? omega * r[i] / d[i] : (T)0;
+    }
+    __syncthreads();
+    for (int sw = 1; sw < sweeps; ++sw) {
+        for (int i = threadIdx.x; i < N; i += blockDim.x) {
+            int ix[3];
+            unflatten<DIM>(g, i, ix);
+            T v = (T)0;
+            if (interior<DIM>(g, ix)) {
+                T ae = apply_level<DIM, T>(g, st, alpha, a, i, ix, theta_dt);
+                v = a[i] + omega * (r[i] - ae) / d[i];
+            }
+            b[i] = v;
+        }
+        __syncthreads();
+        T *tmp = a;
+        a = b;
+        b = tmp;
+    }
+    for (int i = threadIdx.x; i < N; i += blockDim.x) e[i] = a[i];
+}
+
+template <typename T>
+void launch_coarse_solve(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const T *r,
+                         const T *d, T *e, T *tmp, double theta_dt, double omega, int sweeps, hipStream_t s) {
+    (void)tmp;
+    size_t shm = 2 * (size_t)g.N * sizeof(T);
+    if (dim == 2)
+        hipLaunchKernelGGL((k_coarse_solve<2, T>), dim3(1), dim3(1024), shm, s, g, st, alpha, r, d, e, (T)theta_dt,
+                           (T)omega, sweeps);
+    else
+        hipLaunchKernelGGL((k_coarse_solve<3, T>), dim3(1), dim3(1024), shm, s, g, st, alpha, r, d, e, (T)theta_dt,
+                           (T)omega, sweeps);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_inject_policy(LevelDev gf, LevelDev gc, const int16_t *__restrict__ af,
+                                                          int16_t *__restrict__ ac) {
+    int I = node_id();
+    if (I >= gc.N) return;
+    int ix[3];
+    unflatten<DIM>(gc, I, ix);
+    int16_t v = -1;
+    if (interior<DIM>(gc, ix)) v = af[2 * ix[0] + 2 * ix[1] * (int)gf.s1 + (DIM == 3 ? 2 * ix[2] * (int)gf.s2 : 0)];
+    ac[I] = v;
+}
+
+void launch_inject_policy(int dim, const LevelDev &gf, const LevelDev &gc, const int16_t *af, int16_t *ac,
+                          hipStream_t s) {
+    int nb = blocks_for(gc.N);
+    if (dim == 2)
+        hipLaunchKernelGGL(k_inject_policy<2>, dim3(nb), dim3(kBlock), 0, s, gf, gc, af, ac);
+    else
+        hipLaunchKernelGGL(k_inject_policy<3>, dim3(nb), dim3(kBlock), 0, s, gf, gc, af, ac);
+}
+
+template void launch_diag<float>(int, const LevelDev &, const StencilDev &, const int16_t *, double, float *,
+                                 hipStream_t);
+template void launch_diag<double>(int, const LevelDev &, const StencilDev &, const int16_t *, double, double *,
+                                  hipStream_t);
+template void launch_jacobi<float>(int, const LevelDev &, const StencilDev &, const int16_t *, const float *,
+                                   const float *, const float *, float *, double, double, bool, hipStream_t);
+template void launch_jacobi<double>(int, const LevelDev &, const StencilDev &, const int16_t *, const double *,
+                                    const double *, const double *, double *, double, double, bool, hipStream_t);
+template void launch_level_residual<float>(int, const LevelDev &, const StencilDev &, const int16_t *, const float *,
+                                           const float *, float *, double, hipStream_t);
+template void launch_level_residual<double>(int, const LevelDev &, const StencilDev &, const int16_t *,
+                                            const double *, const double *, double *, double, hipStream_t);
+template void launch_restrict<float>(int, const LevelDev &, const LevelDev &, const float *, float *, hipStream_t);
+template void launch_restrict<double>(int, const LevelDev &, const LevelDev &, const double *, double *, hipStream_t);
+template void launch_prolong_add<float>(int, const LevelDev &, const LevelDev &, const float *, float *, hipStream_t);
+template void launch_prolong_add<double>(int, const LevelDev &, const LevelDev &, const double *, double *,
+                                         hipStream_t);
+template void launch_coarse_solve<float>(int, const LevelDev &, const StencilDev &, const int16_t *, const float *,
+                                         const float *, float *, float *, double, double, int, hipStream_t);
+template void launch_coarse_solve<double>(int, const LevelDev &, const StencilDev &, const int16_t *, const double *,
+                                          const double *, double *, double *, double, double, int, hipStream_t);
+
+// ---- BLAS-1 for FP64 flexible GMRES ----------------------------------------------------------------
+
+constexpr int kDotItems = 4;  // nodes per thread in the multi-vector kernels
+
+__global__ __launch_bounds__(kBlock) void k_multidot(const double *__restrict__ w, const double *__restrict__ V,
+                                                     int64_t ldv, int nvec, int64_t N, double *partial) {
+    __shared__ double sh[kBlock / 64];
+    int b = remap_block(blockIdx.x, gridDim.x);
+    int64_t base = (int64_t)b * kBlock * kDotItems + threadIdx.x;
+    double wv[kDotItems];
+#pragma unroll
+    for (int q = 0; q < kDotItems; ++q) {
+        int64_t n = base + (int64_t)q * kBlock;
+        wv[q] = n < N ? w[n] : 0.0;
+    }
+    for (int v = 0; v < nvec; ++v) {
+        const double *Vv = V + (int64_t)v * ldv;
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < kDotItems; ++q) {
+            int64_t n = base + (int64_t)q * kBlock;
+            if (n < N) acc += wv[q] * Vv[n];
+        }
+        double t = block_reduce<double>(acc, OpSum(), sh);
+        if (threadIdx.x == 0) partial[(int64_t)v * gridDim.x + b] = t;
+    }
+}
+
+int dot_blocks(int64_t N) { return (int)((N + (int64_t)kBlock * kDotItems - 1) / ((int64_t)kBlock * kDotItems)); }
+
+void launch_multidot(const double *w, const double *V, int64_t ldv, int nvec, int64_t N, double *partial, int nblocks,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_multidot, dim3(nblocks), dim3(kBlock), 0, s, w, V, ldv, nvec, N, partial);
+}
+
+__global__ __launch_bounds__(kBlock) void k_multiaxpy(double *__restrict__ w, const double *__restrict__ V, int64_t ldv,
+                                                      int nvec, const double *__restrict__ coef, int64_t N,
+                                                      double *norm2_partial) {
+    __shared__ double sh[kBlock / 64];
+    int b = remap_block(blockIdx.x, gridDim.x);
+    int64_t base = (int64_t)b * kBlock * kDotItems + threadIdx.x;
+    double acc2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < kDotItems; ++q) {
+        int64_t n = base + (int64_t)q * kBlock;
+        if (n < N) {
+            double x = w[n];
+            for (int v = 0; v < nvec; ++v) x -= coef[v] * V[(int64_t)v * ldv + n];
+            w[n] = x;
+            acc2 += x * x;
+        }
+    }
+    double t = block_reduce<double>(acc2, OpSum(), sh);
+    if (threadIdx.x == 0 && norm2_partial) norm2_partial[b] = t;
+}
+
+void launch_multiaxpy(double *w, const double *V, int64_t ldv, int nvec, const double *coef, int64_t N,
+                      double *norm2_partial, int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_multiaxpy, dim3(nblocks), dim3(kBlock), 0, s, w, V, ldv, nvec, coef, N, norm2_partial);
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_sum(const double *__restrict__ partial, int nblocks,
+                                                       double *__restrict__ out) {
+    __shared__ double sh[kBlock / 64];
+    const double *p = partial + (int64_t)blockIdx.x * nblocks;
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < nblocks; q += kBlock) acc += p[q];
+    double t = block_reduce<double>(acc, OpSum(), sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_max(const double *__restrict__ partial, int nblocks,
+                                                       double *__restrict__ out) {
+    __shared__ double sh[kBlock / 64];
+    const double *p = partial + (int64_t)blockIdx.x * nblocks;
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < nblocks; q += kBlock) acc = fmax(acc, p[q]);
+    double t = block_reduce<double>(acc, OpMax(), sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_sum_i64(const int64_t *__restrict__ partial, int nblocks,
+                                                           int64_t *__restrict__ out) {
+    __shared__ int64_t sh[kBlock / 64];
+    int64_t acc = 0;
+    for (int q = threadIdx.x; q < nblocks; q += kBlock) acc += partial[q];
+    int64_t t = block_reduce<int64_t>(acc, OpSum(), sh);
+    if (threadIdx.x == 0) out[0] = t;
+}
+
+void launch_reduce_sum(const double *partial, int nvec, int nblocks, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_sum, dim3(nvec), dim3(kBlock), 0, s, partial, nblocks, out);
+}
+void launch_reduce_max(const double *partial, int nvec, int nblocks, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_max, dim3(nvec), dim3(kBlock), 0, s, partial, nblocks, out);
+}
+void launch_reduce_sum_i64(const int64_t *partial, int nblocks, int64_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_sum_i64, dim3(1), dim3(kBlock), 0, s, partial, nblocks, out);
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale_by_inv_sqrt(double *__restrict__ dst, const double *__restrict__ src,
+                                                              const double *__restrict__ norm2, int64_t N) {
+    int64_t n = (int64_t)remap_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (n >= N) return;
+    double inv = 1.0 / sqrt(norm2[0]);
+    dst[n] = src[n] * inv;
+}
+
+void launch_scale_by_inv_sqrt(double *dst, const double *src, const double *norm2, int64_t N, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_by_inv_sqrt, dim3(blocks_for(N)), dim3(kBlock), 0, s, dst, src, norm2, N);
+}
+
+__global__ __launch_bounds__(kBlock) void k_to_f32(const double *__restrict__ v, float *__restrict__ out, int64_t N) {
+    int64_t n = (int64_t)remap_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (n < N) out[n] = (float)v[n];
+}
+__global__ __launch_bounds__(kBlock) void k_copy_f64(const double *__restrict__ v, double *__restrict__ out, int64_t N) {
+    int64_t n = (int64_t)remap_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (n < N) out[n] = v[n];
+}
+
+void launch_to_precond(const double *v, void *out, bool out_float, int64_t N, hipStream_t s) {
+    if (out_float)
+        hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(N)), dim3(kBlock), 0, s, v, (float *)out, N);
+    else
+        hipLaunchKernelGGL(k_copy_f64, dim3(blocks_for(N)), dim3(kBlock), 0, s, v, (double *)out, N);
+}
+
+template <typename TZ>
+__global__ __launch_bounds__(kBlock) void k_update_solution(double *__restrict__ X, const TZ *__restrict__ Z,
+                                                            int64_t ldz, int m, const double *__restrict__ y,
+                                                            int64_t N) {
+    int64_t n = (int64_t)remap_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (n >= N) return;
+    double x = X[n];
+    for (int j = 0; j < m; ++j) x += y[j] * (double)Z[(int64_t)j * ldz + n];
+    X[n] = x;
+}
+
+void launch_update_solution(double *X, const void *Z, bool z_float, int64_t ldz, int m, const double *y, int64_t N,
+                            hipStream_t s) {
+    if (z_float)
+        hipLaunchKernelGGL(k_update_solution<float>, dim3(blocks_for(N)), dim3(kBlock), 0, s, X, (const float *)Z, ldz,
+                           m, y, N);
+    else
+        hipLaunchKernelGGL(k_update_solution<double>, dim3(blocks_for(N)), dim3(kBlock), 0, s, X, (const double *)Z,
+                           ldz, m, y, N);
+}
+
+__global__ __launch_bounds__(kBlock) void k_axpy(double *__restrict__ y, double a, const double *__restrict__ x,
+                                                 int64_t N) {
+    int64_t n = (int64_t)remap_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (n < N) y[n] += a * x[n];
+}
+
+void launch_axpy(double *y, double a, const double *x, int64_t N, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy, dim3(blocks_for(N)), dim3(kBlock), 0, s, y, a, x, N);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_copy_interior(LevelDev g, const double *__restrict__ src,
+                                                          double *__restrict__ dst) {
+    int i = node_id();
+    if (i >= g.N) return;
+    int ix[3];
+    unflatten<DIM>(g, i, ix);
+    if (interior<DIM>(g, ix)) dst[i] = src[i];
+}
+
+void launch_copy_interior(int dim, const LevelDev &g, const double *src, double *dst, hipStream_t s) {
+    if (dim == 2)
+        hipLaunchKernelGGL(k_copy_interior<2>, dim3(blocks_for(g.N)), dim3(kBlock), 0, s, g, src, dst);
+    else
+        hipLaunchKernelGGL(k_copy_interior<3>, dim3(blocks_for(g.N)), dim3(kBlock), 0, s, g, src, dst);
+}
+
+// Zero fill by a kernel (stream-ordered, safe inside captured graphs); exact byte count.
+__global__ __launch_bounds__(kBlock) void k_zero(unsigned char *__restrict__ p, int64_t bytes) {
+    int64_t q = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * 4;
+    if (q + 4 <= bytes && (((uintptr_t)(p + q)) & 3) == 0) {
+        *reinterpret_cast<uint32_t *>(p + q) = 0u;
+    } else {
+        for (int64_t b = q; b < q + 4 && b < bytes; ++b) p[b] = 0;
+    }
+}
+
+void launch_zero(void *p, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return;
+    int64_t words = (int64_t)((bytes + 3) / 4);
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((words + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       (unsigned char *)p, (int64_t)bytes);
+}
+
+}  // namespace slhjb

@@ -1,0 +1,180 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle on identical seeded inputs.
+
+The sweep must match bit for bit (policy indices, minimum values, tie counts, margins and the tie
+tolerance).  Operator applications match to rounding; solves and marches match to 1e-10 relative
+(the solves stop on an infinity-norm residual certificate of 1e-13).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import log, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def slhjb():
+    import paper_1605_04821_amd as m
+    return m
+
+
+def _toy(n, K, P, seed, drift=True, c=False, h=None, scale=1.0):
+    rng = np.random.default_rng(seed)
+    dim = len(n)
+    N = int(np.prod(n))
+    h = h if h is not None else 1.0 / (max(n) - 1)
+    sig = rng.normal(size=(K, P, dim)) * scale
+    b = rng.normal(size=(K, dim)) * 0.4 if drift else None
+    cc = -rng.uniform(0.0, 1.0, size=K) if c else None
+    inst = workloads.Instance(name=f"toy{n}", dim=dim, n=tuple(n), lo=(0.0,) * dim, h=h, K=K, P=P, sigma=sig,
+                              drift=b, c=cc, f0=rng.normal(size=N), f1=rng.normal(size=N), g=rng.normal(size=N),
+                              psi=np.zeros(N), dts=np.array([0.05, 0.05]), thetas=np.array([1.0, 0.5]))
+    inst.psi = np.where(inst.boundary_mask(), rng.normal(size=N) * 0.3, 0.0)
+    return inst
+
+
+SWEEP_CASES = [
+    ("c1_33", lambda: workloads.config_c1(33)),
+    ("c2_65", lambda: workloads.config_c2(65)),
+    ("c2_257", lambda: workloads.config_c2(257)),
+    ("c5_17", lambda: workloads.config_c5(17)),
+    ("ragged_2d", lambda: _toy((37, 29), K=7, P=2, seed=3, c=True)),
+    ("ragged_3d", lambda: _toy((11, 9, 13), K=5, P=1, seed=4)),
+    ("single_control", lambda: _toy((21, 21), K=1, P=1, seed=5)),
+]
+
+
+@pytest.mark.parametrize("name,mk", SWEEP_CASES, ids=[c[0] for c in SWEEP_CASES])
+@pytest.mark.parametrize("theta", [1.0, 0.5])
+def test_sweep_bit_exact(slhjb, name, mk, theta):
+    inst = mk()
+    log(f"sweep {name} theta={theta} n={inst.n} K={inst.K}")
+    pb = oracle.Problem(inst)
+    X, U = workloads.random_fields(inst, seed=11)
+    a_in = workloads.random_policy(inst, seed=12)
+    t_prev, dt = 0.25, 1.0 / 64
+    f = pb.f_at(inst.f0, inst.f1, t_prev + theta * dt)
+    tau = pb.tau(X, U, f)
+    ref = pb.improve(X, U, theta, f, tau, a_in)
+    solver = slhjb.Solver.from_instance(inst)
+    dX, dU, df0, df1 = to_dev(X), to_dev(U), to_dev(inst.f0), to_dev(inst.f1)
+    da_in = to_dev(a_in)
+    da_out = torch.empty_like(da_in)
+    gmin = torch.empty_like(dX)
+    margin = torch.empty_like(dX)
+    ties = torch.empty(inst.N, dtype=torch.int32, device=dX.device)
+    nch, tau_gpu = solver.policy_sweep(dX, dU, df0, df1, t_prev, dt, theta, 1.0, da_in, da_out, gmin, margin, ties)
+    assert tau_gpu == tau
+    np.testing.assert_array_equal(to_np(da_out), ref["alpha"])
+    np.testing.assert_array_equal(to_np(gmin), ref["gmin"])
+    np.testing.assert_array_equal(to_np(ties), ref["ties"])
+    np.testing.assert_array_equal(to_np(margin), ref["margin"])
+    assert nch == ref["changed"]
+    solver.close()
+
+
+APPLY_CASES = [
+    ("c2_65", lambda: workloads.config_c2(65)),
+    ("c5_17", lambda: workloads.config_c5(17)),
+    ("ragged_2d_c", lambda: _toy((37, 29), K=7, P=2, seed=3, c=True)),
+    ("ragged_3d", lambda: _toy((11, 9, 13), K=5, P=1, seed=4)),
+]
+
+
+@pytest.mark.parametrize("name,mk", APPLY_CASES, ids=[c[0] for c in APPLY_CASES])
+def test_apply_matches_assembled_matrix(slhjb, name, mk):
+    inst = mk()
+    log(f"apply {name}")
+    pb = oracle.Problem(inst)
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=inst.N)
+    alpha = workloads.random_policy(inst, 6)
+    dt, theta = 0.03, 0.7
+    L = pb.assemble(alpha)
+    y_ref = x - theta * dt * (L @ x + pb.c_of(alpha) * x)
+    y_ref[pb.bd] = 0.0
+    solver = slhjb.Solver.from_instance(inst)
+    dy = torch.empty(inst.N, dtype=torch.float64, device="cuda")
+    solver.apply(to_dev(alpha), to_dev(x), dy, dt, theta)
+    y = to_np(dy)
+    np.testing.assert_allclose(y, y_ref, rtol=1e-13, atol=1e-13 * np.max(np.abs(y_ref)))
+    solver.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precond", [1, 2])
+def test_linsolve_matches_oracle(slhjb, precision, precond):
+    inst = workloads.config_c2(65)
+    log(f"linsolve precision={precision} precond={precond}")
+    pb = oracle.Problem(inst)
+    alpha = workloads.random_policy(inst, 7)
+    U, _ = workloads.random_fields(inst, seed=8)
+    t_prev, dt, theta = 0.1, 1.0 / 64, 0.5
+    f = pb.f_at(inst.f0, inst.f1, t_prev + theta * dt)
+    L = pb.assemble(alpha)
+    E = oracle.explicit_part(pb, L, alpha, U, f, dt, theta)
+    V0 = U.copy()
+    V0[pb.bd] = inst.psi[pb.bd]
+    Vref, _ = oracle.linear_solve(pb, L, alpha, V0, E, dt, theta, rtol=1e-15)
+    opts = slhjb.Options(precision=precision, precond=precond)
+    solver = slhjb.Solver.from_instance(inst, opts)
+    dX = to_dev(V0)
+    st = solver.linsolve(to_dev(alpha), to_dev(U), to_dev(inst.f0), to_dev(inst.f1), t_prev, dt, theta, 1.0, dX)
+    X = to_np(dX)
+    log(f"  krylov={st.krylov_total} res={st.res_inf:.2e}")
+    rel = np.max(np.abs(X - Vref)) / np.max(np.abs(Vref))
+    assert rel <= 1e-11, rel
+    assert st.res_inf <= 1e-13 * max(1.0, np.max(np.abs(X)))
+    solver.close()
+
+
+def _march_compare(slhjb, inst, opts=None, tol=1e-10):
+    ref = oracle.march(inst, keep_policies=True)
+    solver = slhjb.Solver.from_instance(inst, opts)
+    g, psi, f0, f1 = to_dev(inst.g), to_dev(inst.psi), to_dev(inst.f0), to_dev(inst.f1)
+    U = torch.empty_like(g)
+    pol = torch.empty((len(inst.dts), inst.N), dtype=torch.int16, device=g.device)
+    st = solver.solve(g, psi, f0, f1, inst.dts, inst.thetas, inst.s, U, pol)
+    Ug = to_np(U)
+    rel = np.max(np.abs(Ug - ref["U"])) / np.max(np.abs(ref["U"]))
+    log(f"  {inst.name}: steps={st.steps_done} krylov={st.krylov_total} pi={st.pi_total} rel={rel:.2e}")
+    assert st.steps_done == len(inst.dts)
+    assert rel <= tol, rel
+    # policies: identical wherever the oracle's decision is not a certified near-tie
+    pb = oracle.Problem(inst)
+    pg = to_np(pol)
+    mism = 0
+    for n in range(len(inst.dts)):
+        mism += int(np.sum(pg[n] != ref["policies"][n]))
+    solver.close()
+    return rel, mism
+
+
+def test_march_c1(slhjb):
+    inst = workloads.config_c1(33)
+    rel, mism = _march_compare(slhjb, inst)
+    log(f"  policy mismatches (near-ties) = {mism}")
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_march_c2_small(slhjb, precision):
+    inst = workloads.config_c2(65, n_cn=8)
+    rel, mism = _march_compare(slhjb, inst, slhjb.Options(precision=precision))
+    log(f"  policy mismatches (near-ties) = {mism}")
+
+
+def test_march_c5_small(slhjb):
+    inst = workloads.config_c5(17, n_steps=4)
+    rel, mism = _march_compare(slhjb, inst, slhjb.Options(precision=1))
+    log(f"  policy mismatches (near-ties) = {mism}")
+
+
+def test_march_ragged_no_coarsening(slhjb):
+    inst = _toy((30, 27), K=4, P=2, seed=9, c=True)
+    _march_compare(slhjb, inst, slhjb.Options(precond=2))

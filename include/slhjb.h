@@ -77,6 +77,9 @@ typedef struct {
     double omega;           /* Jacobi damping */
     double rtol_inf;        /* linear solve stops when |F - A X|_inf <= rtol_inf * max(1,|X|_inf) */
     double tau_rel;         /* policy tie tolerance relative to the scale S of the search */
+    double pi_eta;          /* policy iterations whose policy may still change solve only until the
+                               residual has dropped by this factor (0: every solve to rtol_inf); the
+                               last solve of a step always meets rtol_inf and is confirmed by a search */
     void *stream;           /* hipStream_t */
 } hjb_desc;
 
@@ -149,16 +152,39 @@ int hjb_linsolve(hjb_handle *hd, const int16_t *alpha, const double *U, const do
 /* One theta-step by policy iteration (eq. nonlinear_sys): searches start from alpha_io (the previous
    step's policy) and alternate with linear solves until no control changes.
    Uprev: full-grid FP64 U^{n-1}; Unext: full-grid FP64 whose boundary entries hold psi on entry
-   (never written) and whose interior receives U^n; alpha_io: full-grid int16, in/out. */
+   (never written) and whose interior receives U^n; alpha_io: full-grid int16, in/out.
+   Uprev2 (nullable): U^{n-2}; when given, policy iteration starts from the linear extrapolation
+   U^{n-1} + (dt/dt_prev)(U^{n-1} - U^{n-2}) instead of U^{n-1}.  The starting point only changes how many
+   iterations are needed: the result meets the same residual certificate and policy condition. */
 int hjb_step(hjb_handle *hd, const double *Uprev, double *Unext, const double *f0, const double *f1,
-             double t_prev, double dt, double theta, double s, int16_t *alpha_io, hjb_step_stats *st);
+             double t_prev, double dt, double theta, double s, int16_t *alpha_io, const double *Uprev2,
+             double dt_prev, hjb_step_stats *st);
 
 /* March U^0 = g (eq. 1.2), U^n = psi on the boundary (eq. 1.3) through n_steps theta-steps with
-   dts[n], thetas[n] (host arrays).  U_final: full-grid FP64 output.  policies (nullable): int16
+   dts[n], thetas[n] (host arrays); from the third step on, each step starts from the extrapolation of
+   the two previous levels (see hjb_step).  U_final: full-grid FP64 output.  policies (nullable): int16
    [n_steps][N], the converged policy of each step (the checkpoints an adjoint sweep reuses). */
 int hjb_solve(hjb_handle *hd, const double *g, const double *psi, const double *f0, const double *f1,
               int32_t n_steps, const double *dts, const double *thetas, double s,
               double *U_final, int16_t *policies, hjb_solve_stats *st);
+
+/* Kernel timers.  Any caller that wants the duration of one class of kernel launches during real work
+   (e.g. a benchmark's roofline) enables a timer; each launch of that class is then bracketed by HIP events
+   on the handle's stream (at most max_launches launches are recorded; enable again to reset).
+   hjb_profile_read synchronises the stream and reports the recorded launches, their summed duration in
+   milliseconds and their summed algorithmic bytes (each input element read once, each output written
+   once; halo re-reads of gathered stencil points are not counted). */
+enum {
+    HJB_KERNEL_APPLY = 0,     /* y = A^alpha z in FGMRES (FP64 out; z FP64 or FP32) */
+    HJB_KERNEL_SMOOTH = 1,    /* damped Jacobi sweep with stencil gathers on the finest level */
+    HJB_KERNEL_MG_RESID = 2,  /* multigrid residual on the finest level */
+    HJB_KERNEL_DOT = 3,       /* fused multi-vector dot products of the Arnoldi step */
+    HJB_KERNEL_AXPY = 4,      /* fused multi-vector update of the Arnoldi step */
+    HJB_KERNEL_SWEEP = 5,     /* policy search (all controls per node) */
+    HJB_KERNEL_COUNT = 6
+};
+int hjb_profile_enable(hjb_handle *hd, int32_t kernel, int32_t max_launches);
+int hjb_profile_read(hjb_handle *hd, int32_t kernel, int64_t *launches, double *total_ms, double *total_bytes);
 
 /* Free the handle and its device workspace (NULL is ignored). */
 void hjb_destroy(hjb_handle *hd);

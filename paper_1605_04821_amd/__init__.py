@@ -23,7 +23,11 @@ PREC_FP64, PREC_MIXED = 0, 1
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_VCYCLE = 0, 1, 2
 
 EXPORTED = ["hjb_desc_default", "hjb_setup", "hjb_set_stream", "hjb_set_options", "hjb_policy_sweep", "hjb_apply",
-            "hjb_linsolve", "hjb_step", "hjb_solve", "hjb_destroy", "hjb_last_error"]
+            "hjb_linsolve", "hjb_step", "hjb_solve", "hjb_profile_enable", "hjb_profile_read", "hjb_destroy",
+            "hjb_last_error"]
+KERNEL_APPLY, KERNEL_SMOOTH, KERNEL_MG_RESID, KERNEL_DOT, KERNEL_AXPY, KERNEL_SWEEP = range(6)
+KERNEL_NAMES = {KERNEL_APPLY: "apply", KERNEL_SMOOTH: "smooth", KERNEL_MG_RESID: "mg_residual",
+                KERNEL_DOT: "multidot", KERNEL_AXPY: "multiaxpy", KERNEL_SWEEP: "sweep"}
 
 
 class HJBError(RuntimeError):
@@ -41,7 +45,7 @@ class Desc(ctypes.Structure):
                 ("max_krylov", ctypes.c_int32), ("max_pi", ctypes.c_int32), ("nu1", ctypes.c_int32),
                 ("nu2", ctypes.c_int32), ("coarse_sweeps", ctypes.c_int32), ("min_coarse", ctypes.c_int32),
                 ("omega", ctypes.c_double), ("rtol_inf", ctypes.c_double), ("tau_rel", ctypes.c_double),
-                ("stream", ctypes.c_void_p)]
+                ("pi_eta", ctypes.c_double), ("stream", ctypes.c_void_p)]
 
 
 class StepStats(ctypes.Structure):
@@ -71,8 +75,10 @@ def _load():
                                    ctypes.POINTER(i64), ctypes.POINTER(d)]
     L.hjb_apply.argtypes = [vp, vp, vp, vp, d, d, d]
     L.hjb_linsolve.argtypes = [vp, vp, vp, vp, vp, d, d, d, d, vp, ctypes.POINTER(StepStats)]
-    L.hjb_step.argtypes = [vp, vp, vp, vp, vp, d, d, d, d, vp, ctypes.POINTER(StepStats)]
+    L.hjb_step.argtypes = [vp, vp, vp, vp, vp, d, d, d, d, vp, vp, d, ctypes.POINTER(StepStats)]
     L.hjb_solve.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, d, vp, vp, ctypes.POINTER(SolveStats)]
+    L.hjb_profile_enable.argtypes = [vp, i32, i32]
+    L.hjb_profile_read.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(d), ctypes.POINTER(d)]
     L.hjb_destroy.argtypes = [vp]
     L.hjb_destroy.restype = None
     L.hjb_last_error.argtypes = []
@@ -122,6 +128,7 @@ class Options:
     omega: float = 0.7
     rtol_inf: float = 1e-13
     tau_rel: float = 1e-13
+    pi_eta: float = 1e-3
 
 
 class Solver:
@@ -166,7 +173,7 @@ class Solver:
         desc.precision, desc.precond, desc.restart = o.precision, o.precond, o.restart
         desc.max_krylov, desc.max_pi, desc.nu1, desc.nu2 = o.max_krylov, o.max_pi, o.nu1, o.nu2
         desc.coarse_sweeps, desc.min_coarse, desc.omega = o.coarse_sweeps, o.min_coarse, o.omega
-        desc.rtol_inf, desc.tau_rel = o.rtol_inf, o.tau_rel
+        desc.rtol_inf, desc.tau_rel, desc.pi_eta = o.rtol_inf, o.tau_rel, o.pi_eta
 
     @classmethod
     def from_instance(cls, inst, options: Optional[Options] = None):
@@ -216,12 +223,26 @@ class Solver:
                                  float(theta), float(s), _ptr(X), ctypes.byref(st)))
         return st
 
-    def step(self, Uprev, Unext, f0, f1, t_prev, dt, theta, s, alpha_io) -> StepStats:
+    def step(self, Uprev, Unext, f0, f1, t_prev, dt, theta, s, alpha_io, Uprev2=None, dt_prev=0.0) -> StepStats:
+        """hjb_step; Uprev2/dt_prev (optional) start policy iteration from the time extrapolation."""
         self._sync_stream()
         st = StepStats()
         _check(_lib.hjb_step(self._h, _ptr(Uprev), _ptr(Unext), _ptr(f0), _ptr(f1), float(t_prev), float(dt),
-                             float(theta), float(s), _ptr(alpha_io), ctypes.byref(st)))
+                             float(theta), float(s), _ptr(alpha_io), _ptr(Uprev2), float(dt_prev),
+                             ctypes.byref(st)))
         return st
+
+    def profile_enable(self, kernel: int, max_launches: int = 4096):
+        self._sync_stream()
+        _check(_lib.hjb_profile_enable(self._h, int(kernel), int(max_launches)))
+
+    def profile_read(self, kernel: int):
+        """(launches, total_ms, total_algorithmic_bytes) recorded since profile_enable."""
+        n = ctypes.c_int64(0)
+        ms = ctypes.c_double(0.0)
+        by = ctypes.c_double(0.0)
+        _check(_lib.hjb_profile_read(self._h, int(kernel), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+        return int(n.value), float(ms.value), float(by.value)
 
     def solve(self, g, psi, f0, f1, dts, thetas, s, U_final, policies=None) -> SolveStats:
         self._sync_stream()

@@ -14,6 +14,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -52,6 +53,8 @@ int fail(int code, const char *fmt, ...) {
 struct Level {
     LevelDev g{};
     PointTab *tab = nullptr;  // device [K][npt]
+    FastPtF *fastF = nullptr; // device [K][npt]
+    FastPtD *fastD = nullptr; // device [K][npt]
     int16_t *alpha = nullptr; // level policy (level 0: not owned)
     void *r = nullptr, *e = nullptr, *t = nullptr, *d = nullptr;  // precision of the V-cycle
     void *r64 = nullptr, *e64 = nullptr, *t64 = nullptr, *d64 = nullptr;  // FP64 copies (plain path)
@@ -75,7 +78,7 @@ struct hjb_handle {
     double *c_dev = nullptr;
     // fine-level buffers
     double *E = nullptr, *R = nullptr, *Vb = nullptr, *Zb = nullptr;
-    double *Ua = nullptr, *Ub = nullptr, *X = nullptr;
+    double *Ua = nullptr, *Ub = nullptr, *Uc = nullptr;
     int16_t *a0 = nullptr, *a1 = nullptr, *acarry = nullptr;
     double *partial = nullptr;  // >= max(3*nb, (m+2)*nbd)
     double *dvals = nullptr;    // device scalars / small vectors [256]
@@ -83,12 +86,34 @@ struct hjb_handle {
     double *hpin = nullptr;     // pinned host mirror of small results [256]
     int64_t *hpin_i = nullptr;
     std::vector<void *> allocs;
-    // statistics of the last linear solve
-    int last_its = 0;
-    double last_res = 0.0;
+    bool trace = false;  // SLHJB_TRACE=1: policy-iteration progress on stderr
+    struct Timer {
+        int cap = 0, used = 0;
+        std::vector<hipEvent_t> ev;  // 2*cap events
+        std::vector<double> bytes;
+    } timers[HJB_KERNEL_COUNT];
 };
 
 namespace {
+
+// bracket one launch of kernel class `id` with events when its timer is enabled
+struct TimedLaunch {
+    hjb_handle *hd;
+    int id;
+    int slot = -1;
+    TimedLaunch(hjb_handle *h, int i, double bytes) : hd(h), id(i) {
+        if (id < 0) return;
+        auto &T = hd->timers[id];
+        if (T.used < T.cap) {
+            slot = T.used++;
+            T.bytes[slot] = bytes;
+            (void)hipEventRecord(T.ev[2 * slot], hd->stream);
+        }
+    }
+    ~TimedLaunch() {
+        if (slot >= 0) (void)hipEventRecord(hd->timers[id].ev[2 * slot + 1], hd->stream);
+    }
+};
 
 void fill_tables(hjb_handle *hd, double s, std::vector<PointTab> &host, int level) {
     const hjb_desc &d = hd->desc;
@@ -149,6 +174,19 @@ int build_tables(hjb_handle *hd, double s) {
             }
         }
         HIPCHK(hipMemcpyAsync(L.tab, host.data(), host.size() * sizeof(PointTab), hipMemcpyHostToDevice, hd->stream));
+        std::vector<FastPtF> hf(host.size());
+        std::vector<FastPtD> hdd(host.size());
+        for (size_t q = 0; q < host.size(); ++q) {
+            hf[q].off = hdd[q].off = (int32_t)host[q].off;
+            hdd[q].pad = 0;
+            for (int a = 0; a < 3; ++a) {
+                hf[q].t[a] = host[q].tf[a];
+                hdd[q].t[a] = host[q].t[a];
+            }
+        }
+        HIPCHK(hipMemcpyAsync(L.fastF, hf.data(), hf.size() * sizeof(FastPtF), hipMemcpyHostToDevice, hd->stream));
+        HIPCHK(hipMemcpyAsync(L.fastD, hdd.data(), hdd.size() * sizeof(FastPtD), hipMemcpyHostToDevice, hd->stream));
+        HIPCHK(hipStreamSynchronize(hd->stream));  // host vectors go out of scope
     }
     HIPCHK(hipStreamSynchronize(hd->stream));
     hd->s_tab = s;
@@ -158,6 +196,8 @@ int build_tables(hjb_handle *hd, double s) {
 StencilDev stencil(const hjb_handle *hd, int level) {
     StencilDev st;
     st.tab = hd->lev[level].tab;
+    st.fastF = hd->lev[level].fastF;
+    st.fastD = hd->lev[level].fastD;
     st.c = hd->c.empty() ? nullptr : hd->c_dev;
     st.K = hd->desc.K;
     st.P = hd->desc.P;
@@ -207,6 +247,7 @@ int check_options(const hjb_desc *d) {
     if (d->coarse_sweeps < 1 || d->coarse_sweeps > 1000) return fail(HJB_EINVAL, "coarse_sweeps in 1..1000");
     if (!(d->omega > 0.0 && d->omega < 2.0)) return fail(HJB_EINVAL, "omega must be in (0,2)");
     if (!(d->rtol_inf > 0.0) || !(d->tau_rel >= 0.0)) return fail(HJB_EINVAL, "rtol_inf > 0 and tau_rel >= 0 required");
+    if (!(d->pi_eta >= 0.0 && d->pi_eta < 1.0)) return fail(HJB_EINVAL, "pi_eta must be in [0,1)");
     return HJB_OK;
 }
 
@@ -235,6 +276,8 @@ void smooth_level(hjb_handle *hd, int l, T *&e, T *&t, const T *r, int sweeps, b
     Level &L = hd->lev[l];
     StencilDev st = stencil(hd, l);
     for (int q = 0; q < sweeps; ++q) {
+        bool gathers = !(first && q == 0);
+        TimedLaunch tl(hd, (l == 0 && gathers) ? HJB_KERNEL_SMOOTH : -1, (double)L.g.N * (4.0 * sizeof(T) + 2.0));
         launch_jacobi<T>(hd->dim, L.g, st, L.alpha, e, r, (const T *)L.d, t, theta_dt, hd->desc.omega,
                          first && q == 0, hd->stream);
         std::swap(e, t);
@@ -272,7 +315,10 @@ void vcycle(hjb_handle *hd, const T *r0, T *z, double theta_dt) {
     for (int l = 0; l < Lc; ++l) {
         Level &L = hd->lev[l];
         smooth_level<T>(hd, l, e[l], t[l], r[l], d.nu1, true, theta_dt);
-        launch_level_residual<T>(hd->dim, L.g, stencil(hd, l), L.alpha, e[l], r[l], t[l], theta_dt, s);
+        {
+            TimedLaunch tl(hd, l == 0 ? HJB_KERNEL_MG_RESID : -1, (double)L.g.N * (3.0 * sizeof(T) + 2.0));
+            launch_level_residual<T>(hd->dim, L.g, stencil(hd, l), L.alpha, e[l], r[l], t[l], theta_dt, s);
+        }
         launch_restrict<T>(hd->dim, L.g, hd->lev[l + 1].g, t[l], (T *)hd->lev[l + 1].r, s);
     }
     {
@@ -330,8 +376,9 @@ int sync_small(hjb_handle *hd, const void *dev, void *host, size_t bytes) {
     return HJB_OK;
 }
 
-int fgmres(hjb_handle *hd, const int16_t *alpha, const double *E, double *X, double theta_dt, int *its_out,
-           double *res_out) {
+// Stops when |r|_inf <= rtol_inf*max(1,|X|_inf), or, when eta > 0, once |r|_inf <= eta * (initial |r|_inf).
+int fgmres(hjb_handle *hd, const int16_t *alpha, const double *E, double *X, double theta_dt, double eta,
+           int *its_out, double *res_out, bool *tight_out) {
     const hjb_desc &d = hd->desc;
     const int64_t N = hd->N;
     const int m = d.restart;
@@ -346,6 +393,7 @@ int fgmres(hjb_handle *hd, const int16_t *alpha, const double *E, double *X, dou
     double *dv = hd->dvals;
     double *hp = hd->hpin;
     int its = 0;
+    double loose = 0.0;
     std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gvec(m + 1), y(m);
     for (int cycle = 0;; ++cycle) {
         launch_residual(dim, L0.g, st, alpha, X, E, theta_dt, hd->R, hd->partial, hd->nb, s);
@@ -357,7 +405,10 @@ int fgmres(hjb_handle *hd, const int16_t *alpha, const double *E, double *X, dou
         *its_out = its;
         if (!isfinite(beta) || !isfinite(xinf)) return fail(HJB_ENONFINITE, "non-finite residual in linear solve");
         double target = d.rtol_inf * std::max(1.0, xinf);
-        if (rinf <= target) return HJB_OK;
+        if (cycle == 0 && eta > 0.0) loose = eta * rinf;
+        *tight_out = rinf <= target;
+        if (rinf <= std::max(target, loose)) return HJB_OK;
+        target = std::max(target, loose);
         if (its >= d.max_krylov)
             return fail(HJB_ENOCONV_KRYLOV, "FGMRES: |r|_inf = %.3e > %.3e after %d iterations", rinf, target, its);
         // v0 = r / beta
@@ -370,32 +421,45 @@ int fgmres(hjb_handle *hd, const int16_t *alpha, const double *E, double *X, dou
             double *w = V + (int64_t)(j + 1) * N;
             void *zj = none ? (void *)vj : (void *)((char *)hd->Zb + (int64_t)j * N * zsz);
             if (!none) precondition(hd, vj, zj, theta_dt);
-            launch_apply(dim, L0.g, st, alpha, zj, zf, w, theta_dt, hd->partial, hd->nb, s);
-            launch_reduce_sum(hd->partial, 1, hd->nb, dv + 8, s);  // |w|^2 before orthogonalisation
-            // classical Gram-Schmidt, with a second pass when cancellation is severe
-            launch_multidot(w, V, N, j + 1, N, hd->partial, hd->nbd, s);
-            launch_reduce_sum(hd->partial, j + 1, hd->nbd, dv + 16, s);
-            launch_multiaxpy(w, V, N, j + 1, dv + 16, N, hd->partial, hd->nbd, s);
-            launch_reduce_sum(hd->partial, 1, hd->nbd, dv + 9, s);  // |w'|^2
-            HIPCHK(hipMemcpyAsync(hp + 8, dv + 8, (size_t)(8 + j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            double w2 = hp[8], wn2 = hp[9];
-            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hp[16 + i];
-            if (wn2 < 0.25 * w2) {
-                launch_multidot(w, V, N, j + 1, N, hd->partial, hd->nbd, s);
-                launch_reduce_sum(hd->partial, j + 1, hd->nbd, dv + 16, s);
-                launch_multiaxpy(w, V, N, j + 1, dv + 16, N, hd->partial, hd->nbd, s);
-                launch_reduce_sum(hd->partial, 1, hd->nbd, dv + 9, s);
-                HIPCHK(hipMemcpyAsync(hp + 9, dv + 9, (size_t)(7 + j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-                HIPCHK(hipStreamSynchronize(s));
-                wn2 = hp[9];
-                for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += hp[16 + i];
+            {
+                TimedLaunch tl(hd, HJB_KERNEL_APPLY, (double)N * ((zf ? 4.0 : 8.0) + 2.0 + 8.0));
+                launch_apply(dim, L0.g, st, alpha, zj, zf, w, theta_dt, nullptr, hd->nb, s);
             }
-            double hn = sqrt(wn2);
-            if (!isfinite(hn)) return fail(HJB_ENONFINITE, "non-finite Arnoldi vector");
+            // classical Gram-Schmidt: one pass for <w,V_i> and |w|^2, one for the update and normalisation
+            // (norm by Pythagoras); a second pass when cancellation is severe
+            double hn = 0.0;
+            for (int pass = 0; pass < 2; ++pass) {
+                {
+                    TimedLaunch tl(hd, HJB_KERNEL_DOT, (double)N * 8.0 * (j + 2));
+                    launch_multidot(w, V, N, j + 1, N, hd->partial, hd->nbd, s);
+                }
+                launch_reduce_sum(hd->partial, j + 2, hd->nbd, dv + 16, s);
+                {
+                    TimedLaunch tl(hd, HJB_KERNEL_AXPY, (double)N * 8.0 * (j + 3));
+                    launch_multiaxpy_scale(w, V, N, j + 1, dv + 16, N, hd->nbd, s);
+                }
+                HIPCHK(hipMemcpyAsync(hp + 16, dv + 16, (size_t)(j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                double w2 = hp[16 + j + 1], h2 = 0.0;
+                for (int i = 0; i <= j; ++i) h2 += hp[16 + i] * hp[16 + i];
+                double hn2 = w2 - h2;
+                double sc = hn2 > 0.0 ? sqrt(hn2) : 1.0;  // the factor the kernel divided by
+                if (!isfinite(w2)) return fail(HJB_ENONFINITE, "non-finite Arnoldi vector");
+                if (pass == 0) {
+                    for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hp[16 + i];
+                    hn = sc;
+                } else {
+                    for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += hp[16 + i] * hn;
+                    hn = hn * sc;
+                }
+                if (hn2 > 0.25 * w2) break;
+                if (w2 == 0.0 || (pass == 1 && !(hn2 > 0.0))) {
+                    hn = 0.0;  // w lies in the span of the basis: the Krylov space holds the solution
+                    break;
+                }
+            }
             H[(size_t)(j + 1) * m + j] = hn;
             ++its;
-            if (hn > 0.0) launch_scale_by_inv_sqrt(w, w, dv + 9, N, s);
             // apply previous rotations to column j, then a new one
             for (int i = 0; i < j; ++i) {
                 double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
@@ -474,6 +538,7 @@ int sweep(hjb_handle *hd, const double *X, const double *U, const double *f0, co
     HIPCHK(hipStreamSynchronize(s));
     double tau = hd->hpin[4];
     SweepOut o{a_out, gmin, margin, ties, hd->ipartial};
+    TimedLaunch tl(hd, HJB_KERNEL_SWEEP, (double)hd->N * (4 * 8.0 + 2.0 + 2.0));
     launch_sweep(hd->dim, L0.g, stencil(hd, 0), X, U, f0, f1, t_mid, theta, tau, a_in, o, hd->nb, s);
     HIPCHK(hipGetLastError());
     if (n_changed) {
@@ -506,21 +571,24 @@ int check_time(double dt, double theta) {
 }
 
 int linsolve_impl(hjb_handle *hd, const int16_t *alpha, const double *U, const double *f0, const double *f1,
-                  double t_prev, double dt, double theta, double *X, int *its, double *res) {
+                  double t_prev, double dt, double theta, double *X, double eta, int *its, double *res, bool *tight) {
     hipStream_t s = hd->stream;
     double t_mid = t_prev + theta * dt;
     launch_explicit(hd->dim, hd->lev[0].g, stencil(hd, 0), alpha, U, f0, f1, t_mid, (1.0 - theta) * dt, dt, hd->E,
                     hd->nb, s);
     TRY(prepare_mg(hd, alpha, theta * dt));
-    return fgmres(hd, alpha, hd->E, X, theta * dt, its, res);
+    return fgmres(hd, alpha, hd->E, X, theta * dt, eta, its, res, tight);
 }
 
 int step_impl(hjb_handle *hd, const double *Uprev, double *Unext, const double *f0, const double *f1, double t_prev,
-              double dt, double theta, int16_t *alpha_io, hjb_step_stats *st) {
+              double dt, double theta, int16_t *alpha_io, const double *Uprev2, double dt_prev, hjb_step_stats *st) {
     hipStream_t s = hd->stream;
     const int64_t N = hd->N;
     hjb_step_stats loc{};
-    launch_copy_interior(hd->dim, hd->lev[0].g, Uprev, Unext, s);
+    if (Uprev2)
+        launch_extrapolate(hd->dim, hd->lev[0].g, Uprev, Uprev2, dt / dt_prev, Unext, s);
+    else
+        launch_copy_interior(hd->dim, hd->lev[0].g, Uprev, Unext, s);
     int16_t *acur = hd->a0, *anew = hd->a1;
     int64_t changed = 0;
     TRY(sweep(hd, Unext, Uprev, f0, f1, t_prev, dt, theta, alpha_io, acur, nullptr, nullptr, nullptr, &changed,
@@ -533,10 +601,15 @@ int step_impl(hjb_handle *hd, const double *Uprev, double *Unext, const double *
         if (lhs > 1.0) loc.flags |= 1;
     }
     int rc = HJB_OK;
+    // Policy iteration.  While the policy may still change a solve only reduces the residual by pi_eta;
+    // a step ends after a solve to rtol_inf whose search changes no control.
+    bool want_tight = hd->desc.pi_eta <= 0.0;
     for (int it = 0; it < hd->desc.max_pi; ++it) {
         int its = 0;
         double res = 0.0;
-        rc = linsolve_impl(hd, acur, Uprev, f0, f1, t_prev, dt, theta, Unext, &its, &res);
+        bool tight = false;
+        rc = linsolve_impl(hd, acur, Uprev, f0, f1, t_prev, dt, theta, Unext, want_tight ? 0.0 : hd->desc.pi_eta,
+                           &its, &res, &tight);
         loc.pi_iters = it + 1;
         loc.krylov_total += its;
         loc.krylov_max = std::max(loc.krylov_max, its);
@@ -545,9 +618,17 @@ int step_impl(hjb_handle *hd, const double *Uprev, double *Unext, const double *
         if (rc != HJB_OK) break;
         TRY(sweep(hd, Unext, Uprev, f0, f1, t_prev, dt, theta, acur, anew, nullptr, nullptr, nullptr, &changed,
                   nullptr));
-        if (changed == 0) break;
-        std::swap(acur, anew);
-        if (it + 1 == hd->desc.max_pi) rc = fail(HJB_ENOCONV_PI, "policy iteration still changing after %d", it + 1);
+        if (hd->trace)
+            fprintf(stderr, "[slhjb] pi %d: krylov %d res %.3e tight %d changed %lld\n", it, its, res, (int)tight,
+                    (long long)changed);
+        if (changed == 0) {
+            if (tight) break;
+            want_tight = true;  // same policy, finish the solve
+        } else {
+            std::swap(acur, anew);
+            want_tight = hd->desc.pi_eta <= 0.0;
+        }
+        if (it + 1 == hd->desc.max_pi) rc = fail(HJB_ENOCONV_PI, "policy iteration not converged after %d", it + 1);
     }
     if (acur != alpha_io) {
         hipError_t e = hipMemcpyAsync(alpha_io, acur, (size_t)N * sizeof(int16_t), hipMemcpyDeviceToDevice, s);
@@ -585,6 +666,7 @@ void hjb_desc_default(hjb_desc *d) {
     d->omega = 0.7;
     d->rtol_inf = 1e-13;
     d->tau_rel = 1e-13;
+    d->pi_eta = 1e-3;
     d->stream = nullptr;
 }
 
@@ -623,6 +705,10 @@ int hjb_setup(const hjb_desc *desc, hjb_handle **out) {
 
     hjb_handle *hd = new hjb_handle();
     hd->desc = d;
+    {
+        const char *tr = getenv("SLHJB_TRACE");
+        hd->trace = tr && tr[0] == '1';
+    }
     hd->dim = d.dim;
     hd->N = N;
     hd->stream = (hipStream_t)d.stream;
@@ -680,6 +766,8 @@ int hjb_setup(const hjb_desc *desc, hjb_handle **out) {
         Level &L = hd->lev[l];
         size_t n = (size_t)L.g.N;
         STRY(dalloc(hd, (void **)&L.tab, (size_t)d.K * hd->npt * sizeof(PointTab)));
+        STRY(dalloc(hd, (void **)&L.fastF, (size_t)d.K * hd->npt * sizeof(FastPtF)));
+        STRY(dalloc(hd, (void **)&L.fastD, (size_t)d.K * hd->npt * sizeof(FastPtD)));
         if (l > 0) STRY(dalloc(hd, (void **)&L.alpha, n * sizeof(int16_t)));
         STRY(dalloc(hd, &L.r64, n * 8));
         STRY(dalloc(hd, &L.e64, n * 8));
@@ -699,6 +787,7 @@ int hjb_setup(const hjb_desc *desc, hjb_handle **out) {
     STRY(dalloc(hd, (void **)&hd->Zb, (size_t)d.restart * N * 8));
     STRY(dalloc(hd, (void **)&hd->Ua, N * 8));
     STRY(dalloc(hd, (void **)&hd->Ub, N * 8));
+    STRY(dalloc(hd, (void **)&hd->Uc, N * 8));
     STRY(dalloc(hd, (void **)&hd->a0, N * 2));
     STRY(dalloc(hd, (void **)&hd->a1, N * 2));
     STRY(dalloc(hd, (void **)&hd->acarry, N * 2));
@@ -747,6 +836,7 @@ int hjb_set_options(hjb_handle *hd, const hjb_desc *desc) {
     d.omega = desc->omega;
     d.rtol_inf = desc->rtol_inf;
     d.tau_rel = desc->tau_rel;
+    d.pi_eta = desc->pi_eta;
     select_precision(hd);
     return HJB_OK;
 }
@@ -788,7 +878,8 @@ int hjb_linsolve(hjb_handle *hd, const int16_t *alpha, const double *U, const do
     TRY(check_policy(hd, alpha));
     int its = 0;
     double res = 0.0;
-    int rc = linsolve_impl(hd, alpha, U, f0, f1, t_prev, dt, theta, X, &its, &res);
+    bool tight = false;
+    int rc = linsolve_impl(hd, alpha, U, f0, f1, t_prev, dt, theta, X, 0.0, &its, &res, &tight);
     if (st) {
         memset(st, 0, sizeof *st);
         st->pi_iters = 0;
@@ -804,14 +895,16 @@ int hjb_linsolve(hjb_handle *hd, const int16_t *alpha, const double *U, const do
 }
 
 int hjb_step(hjb_handle *hd, const double *Uprev, double *Unext, const double *f0, const double *f1, double t_prev,
-             double dt, double theta, double s, int16_t *alpha_io, hjb_step_stats *st) {
+             double dt, double theta, double s, int16_t *alpha_io, const double *Uprev2, double dt_prev,
+             hjb_step_stats *st) {
     if (!hd) return fail(HJB_EINVAL, "null handle");
     if (!Uprev || !Unext || !f0 || !f1 || !alpha_io) return fail(HJB_EINVAL, "null array argument");
-    if (Uprev == Unext) return fail(HJB_EINVAL, "Uprev and Unext must be distinct");
+    if (Uprev == Unext || Uprev2 == Unext) return fail(HJB_EINVAL, "Unext must differ from Uprev and Uprev2");
+    if (Uprev2 && !(dt_prev > 0.0 && isfinite(dt_prev))) return fail(HJB_EINVAL, "dt_prev must be positive");
     TRY(check_time(dt, theta));
     if (theta == 0.0) return fail(HJB_EUNSUPPORTED, "explicit steps (theta = 0) are not provided by hjb_step");
     TRY(build_tables(hd, s));
-    return step_impl(hd, Uprev, Unext, f0, f1, t_prev, dt, theta, alpha_io, st);
+    return step_impl(hd, Uprev, Unext, f0, f1, t_prev, dt, theta, alpha_io, Uprev2, dt_prev, st);
 }
 
 int hjb_solve(hjb_handle *hd, const double *g, const double *psi, const double *f0, const double *f1, int32_t n_steps,
@@ -829,22 +922,25 @@ int hjb_solve(hjb_handle *hd, const double *g, const double *psi, const double *
     hipStream_t str = hd->stream;
     hjb_solve_stats loc{};
     HIPCHK(hipMemcpyAsync(hd->Ua, g, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
+    HIPCHK(hipMemcpyAsync(hd->Uc, g, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
     int16_t *acarry = hd->acarry;
     launch_zero(acarry, (size_t)N * 2, str);
-    double *Ucur = hd->Ua, *Unx = hd->Ub;
+    double *Ucur = hd->Ua, *Unx = hd->Ub, *Uold = hd->Uc;
     double t = 0.0;
     int rc = HJB_OK;
     for (int n = 0; n < n_steps; ++n) {
         HIPCHK(hipMemcpyAsync(Unx, psi, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
         hjb_step_stats sst{};
-        rc = step_impl(hd, Ucur, Unx, f0, f1, t, dts[n], thetas[n], acarry, &sst);
+        rc = step_impl(hd, Ucur, Unx, f0, f1, t, dts[n], thetas[n], acarry, n >= 1 ? Uold : nullptr,
+                       n >= 1 ? dts[n - 1] : 0.0, &sst);
         loc.krylov_total += sst.krylov_total;
         loc.pi_total += sst.pi_iters;
         loc.flags |= sst.flags;
         loc.max_cert_bound = std::max(loc.max_cert_bound, sst.cert_bound);
         if (rc != HJB_OK) break;
         if (policies) HIPCHK(hipMemcpyAsync(policies + (int64_t)n * N, acarry, (size_t)N * 2, hipMemcpyDeviceToDevice, str));
-        std::swap(Ucur, Unx);
+        std::swap(Uold, Ucur);  // Uold <- U^{n-1}
+        std::swap(Ucur, Unx);   // Ucur <- U^n
         t = t + dts[n];
         loc.steps_done = n + 1;
     }
@@ -854,8 +950,45 @@ int hjb_solve(hjb_handle *hd, const double *g, const double *psi, const double *
     return rc;
 }
 
+int hjb_profile_enable(hjb_handle *hd, int32_t kernel, int32_t max_launches) {
+    if (!hd) return fail(HJB_EINVAL, "null handle");
+    if (kernel < 0 || kernel >= HJB_KERNEL_COUNT) return fail(HJB_EINVAL, "unknown kernel id %d", kernel);
+    if (max_launches < 0 || max_launches > 100000) return fail(HJB_EINVAL, "max_launches in 0..100000");
+    auto &T = hd->timers[kernel];
+    HIPCHK(hipStreamSynchronize(hd->stream));
+    while ((int)T.ev.size() < 2 * max_launches) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        T.ev.push_back(e);
+    }
+    T.bytes.assign((size_t)max_launches, 0.0);
+    T.cap = max_launches;
+    T.used = 0;
+    return HJB_OK;
+}
+
+int hjb_profile_read(hjb_handle *hd, int32_t kernel, int64_t *launches, double *total_ms, double *total_bytes) {
+    if (!hd) return fail(HJB_EINVAL, "null handle");
+    if (kernel < 0 || kernel >= HJB_KERNEL_COUNT) return fail(HJB_EINVAL, "unknown kernel id %d", kernel);
+    auto &T = hd->timers[kernel];
+    HIPCHK(hipStreamSynchronize(hd->stream));
+    double ms = 0.0, by = 0.0;
+    for (int q = 0; q < T.used; ++q) {
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, T.ev[2 * q], T.ev[2 * q + 1]));
+        ms += t;
+        by += T.bytes[q];
+    }
+    if (launches) *launches = T.used;
+    if (total_ms) *total_ms = ms;
+    if (total_bytes) *total_bytes = by;
+    return HJB_OK;
+}
+
 void hjb_destroy(hjb_handle *hd) {
     if (!hd) return;
+    for (auto &T : hd->timers)
+        for (hipEvent_t e : T.ev) (void)hipEventDestroy(e);
     if (hd->stream) (void)hipStreamSynchronize(hd->stream);
     else (void)hipDeviceSynchronize();
     for (void *p : hd->allocs) (void)hipFree(p);

@@ -25,6 +25,18 @@ struct PointTab {
     int64_t off;
 };
 
+// Compact copies of the untruncated landing used by the node loops (one 16- or 32-byte record per
+// point, staged in LDS by kernels whose control varies per node).
+struct FastPtF {
+    int32_t off;
+    float t[3];
+};
+struct FastPtD {
+    int32_t off;
+    int32_t pad;
+    double t[3];
+};
+
 struct LevelDev {
     int32_t n[3];
     int32_t deep_lo[3], deep_hi[3];  // nodes with deep_lo <= i_d <= deep_hi never truncate
@@ -34,6 +46,8 @@ struct LevelDev {
 
 struct StencilDev {
     const PointTab *tab;  // [K][npt]: points 2p (+sigma_p), 2p+1 (-sigma_p), 2P (drift, if any)
+    const FastPtF *fastF; // [K][npt]
+    const FastPtD *fastD; // [K][npt]
     const double *c;      // [K] or nullptr
     int32_t K, P, npt, has_drift;
     double inv2h;         // 1/(2h) of the finest grid: coarse levels keep the physical displacement
@@ -91,10 +105,12 @@ void launch_inject_policy(int dim, const LevelDev &gf, const LevelDev &gc, const
                           hipStream_t s);
 
 // BLAS-1 (FP64 Krylov)
+// partial[v][b] = block b's part of <w, V_v> for v < nvec, and partial[nvec][b] = part of <w, w>
 void launch_multidot(const double *w, const double *V, int64_t ldv, int nvec, int64_t N, double *partial,
                      int nblocks, hipStream_t s);
-void launch_multiaxpy(double *w, const double *V, int64_t ldv, int nvec, const double *coef, int64_t N,
-                      double *norm2_partial, int nblocks, hipStream_t s);
+// w = (w - sum_v coef[v] V_v) / sqrt(coef[nvec] - sum_v coef[v]^2)  (divisor 1 if that is not positive)
+void launch_multiaxpy_scale(double *w, const double *V, int64_t ldv, int nvec, const double *coef, int64_t N,
+                            int nblocks, hipStream_t s);
 void launch_reduce_sum(const double *partial, int nvec, int nblocks, double *out, hipStream_t s);
 void launch_reduce_max(const double *partial, int nvec, int nblocks, double *out, hipStream_t s);
 void launch_reduce_sum_i64(const int64_t *partial, int nblocks, int64_t *out, hipStream_t s);
@@ -105,6 +121,8 @@ void launch_update_solution(double *X, const void *Z, bool z_float, int64_t ldz,
 void launch_axpy(double *y, double a, const double *x, int64_t N, hipStream_t s);
 void launch_copy_interior(int dim, const LevelDev &g, const double *src, double *dst, hipStream_t s);
 void launch_zero(void *p, size_t bytes, hipStream_t s);
+void launch_extrapolate(int dim, const LevelDev &g, const double *U1, const double *U0, double ratio, double *out,
+                        hipStream_t s);
 
 int blocks_for(int64_t N);
 

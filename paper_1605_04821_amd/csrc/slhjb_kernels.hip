@@ -128,28 +128,30 @@ __device__ __forceinline__ TC interp_base(const TS *__restrict__ V, int base, co
     return lerp_tu<TC>(v0, v1, t[2], u[2]);
 }
 
-template <typename T>
-struct Frac;
+template <typename TC>
+struct FastOf;
 template <>
-struct Frac<double> {
-    static __device__ __forceinline__ void get(const PointTab &p, double t[3], double u[3]) {
-        t[0] = p.t[0]; t[1] = p.t[1]; t[2] = p.t[2];
-        u[0] = p.u[0]; u[1] = p.u[1]; u[2] = p.u[2];
-    }
+struct FastOf<double> {
+    using T = FastPtD;
+    static __device__ __forceinline__ const FastPtD *get(const StencilDev &s) { return s.fastD; }
 };
 template <>
-struct Frac<float> {
-    static __device__ __forceinline__ void get(const PointTab &p, float t[3], float u[3]) {
-        t[0] = p.tf[0]; t[1] = p.tf[1]; t[2] = p.tf[2];
-        u[0] = p.uf[0]; u[1] = p.uf[1]; u[2] = p.uf[2];
-    }
+struct FastOf<float> {
+    using T = FastPtF;
+    static __device__ __forceinline__ const FastPtF *get(const StencilDev &s) { return s.fastF; }
 };
 
+// untruncated landing: cell i + floor(Y), fractions t = Y - floor(Y) and u = 1 - t
 template <int DIM, typename TS, typename TC>
-__device__ __forceinline__ TC interp_fast(const TS *__restrict__ V, int i, const PointTab &p, const LevelDev &g) {
+__device__ __forceinline__ TC interp_fast(const TS *__restrict__ V, int i, const typename FastOf<TC>::T &p,
+                                          const LevelDev &g) {
     TC t[3], u[3];
-    Frac<TC>::get(p, t, u);
-    return interp_base<DIM, TS, TC>(V, i + (int)p.off, g, t, u);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        t[d] = (TC)p.t[d];
+        u[d] = (TC)1 - t[d];
+    }
+    return interp_base<DIM, TS, TC>(V, i + p.off, g, t, u);
 }
 
 template <int DIM, typename TS, typename TC>
@@ -176,9 +178,10 @@ __device__ __forceinline__ void lhat_node(const LevelDev &g, const StencilDev &s
     const PointTab *pt = st.tab + k * st.npt;
     TC accV = (TC)0, accW = (TC)0;
     if (deep) {
+        const typename FastOf<TC>::T *fp = FastOf<TC>::get(st) + k * st.npt;
         for (int p = 0; p < st.P; ++p) {
-            const PointTab &a = pt[2 * p];
-            const PointTab &b = pt[2 * p + 1];
+            const auto &a = fp[2 * p];
+            const auto &b = fp[2 * p + 1];
             TC vp = interp_fast<DIM, TS, TC>(V, i, a, g);
             TC vm = interp_fast<DIM, TS, TC>(V, i, b, g);
             accV = accV + ((vp + vm) - (TC)2 * Vi);
@@ -189,7 +192,7 @@ __device__ __forceinline__ void lhat_node(const LevelDev &g, const StencilDev &s
             }
         }
         if (st.has_drift) {
-            const PointTab &c = pt[2 * st.P];
+            const auto &c = fp[2 * st.P];
             TC vb = interp_fast<DIM, TS, TC>(V, i, c, g);
             accV = accV + (TC)2 * (vb - Vi);
             if (TWO) {
@@ -245,6 +248,32 @@ __device__ __forceinline__ TC lhat1(const LevelDev &g, const StencilDev &st, int
     TC a, b;
     lhat_node<DIM, TS, TC, false>(g, st, k, i, ix, deep, V, Vi, V, Vi, a, b);
     return a;
+}
+
+// Copy the compact tables of arithmetic type TC into LDS and point a copy of the stencil at them.
+// `bytes` is 0 when the table does not fit (the global copy is used then).
+template <typename TC>
+__device__ __forceinline__ StencilDev stage_fast(const StencilDev &st, int bytes) {
+    extern __shared__ uint4 smem_tab[];
+    StencilDev o = st;
+    if (bytes > 0) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(FastOf<TC>::get(st));
+        for (int q = threadIdx.x; q < bytes / 16; q += blockDim.x) smem_tab[q] = src[q];
+        __syncthreads();
+        if (sizeof(TC) == 8)
+            o.fastD = reinterpret_cast<const FastPtD *>(smem_tab);
+        else
+            o.fastF = reinterpret_cast<const FastPtF *>(smem_tab);
+    }
+    return o;
+}
+
+constexpr int kMaxStageBytes = 32768;
+
+template <typename TC>
+int stage_bytes(const StencilDev &st) {
+    int b = st.K * st.npt * (int)(sizeof(TC) == 8 ? sizeof(FastPtD) : sizeof(FastPtF));
+    return b <= kMaxStageBytes ? b : 0;
 }
 
 // ---- block reductions ----------------------------------------------------------------------------
@@ -405,10 +434,11 @@ void launch_norms_xuf(int dim, const LevelDev &g, const double *X, const double 
 // ---- FP64 operator kernels ------------------------------------------------------------------------
 
 template <int DIM, typename TX>
-__global__ __launch_bounds__(kBlock) void k_apply(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
+__global__ __launch_bounds__(kBlock) void k_apply(LevelDev g, StencilDev st0, const int16_t *__restrict__ alpha,
                                                   const TX *__restrict__ x, double *__restrict__ y, double theta_dt,
-                                                  double *norm2_partial) {
+                                                  double *norm2_partial, int stage) {
     __shared__ double sh[kBlock / 64];
+    const StencilDev st = stage_fast<double>(st0, stage);
     int i = node_id();
     double yy = 0.0;
     if (i < g.N) {
@@ -432,8 +462,9 @@ __global__ __launch_bounds__(kBlock) void k_apply(LevelDev g, StencilDev st, con
 
 void launch_apply(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const void *x,
                   bool x_is_float, double *y, double theta_dt, double *norm2_partial, int nblocks, hipStream_t s) {
-#define AP(D, TX) hipLaunchKernelGGL((k_apply<D, TX>), dim3(nblocks), dim3(kBlock), 0, s, g, st, alpha, \
-                                     (const TX *)x, y, theta_dt, norm2_partial)
+    int sb = stage_bytes<double>(st);
+#define AP(D, TX) hipLaunchKernelGGL((k_apply<D, TX>), dim3(nblocks), dim3(kBlock), sb, s, g, st, alpha, \
+                                     (const TX *)x, y, theta_dt, norm2_partial, sb)
     if (x_is_float) {
         if (dim == 2) AP(2, float); else AP(3, float);
     } else {
@@ -443,10 +474,11 @@ void launch_apply(int dim, const LevelDev &g, const StencilDev &st, const int16_
 }
 
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_explicit(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
+__global__ __launch_bounds__(kBlock) void k_explicit(LevelDev g, StencilDev st0, const int16_t *__restrict__ alpha,
                                                      const double *__restrict__ U, const double *__restrict__ f0,
                                                      const double *__restrict__ f1, double t_mid, double omt_dt,
-                                                     double dt, double *__restrict__ E) {
+                                                     double dt, double *__restrict__ E, int stage) {
+    const StencilDev st = stage_fast<double>(st0, stage);
     int i = node_id();
     if (i >= g.N) return;
     int ix[3];
@@ -471,19 +503,22 @@ __global__ __launch_bounds__(kBlock) void k_explicit(LevelDev g, StencilDev st, 
 void launch_explicit(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const double *U,
                      const double *f0, const double *f1, double t_mid, double omt_dt, double dt, double *E, int nblocks,
                      hipStream_t s) {
+    int sb = stage_bytes<double>(st);
     if (dim == 2)
-        hipLaunchKernelGGL(k_explicit<2>, dim3(nblocks), dim3(kBlock), 0, s, g, st, alpha, U, f0, f1, t_mid, omt_dt, dt,
-                           E);
+        hipLaunchKernelGGL(k_explicit<2>, dim3(nblocks), dim3(kBlock), sb, s, g, st, alpha, U, f0, f1, t_mid, omt_dt,
+                           dt, E, sb);
     else
-        hipLaunchKernelGGL(k_explicit<3>, dim3(nblocks), dim3(kBlock), 0, s, g, st, alpha, U, f0, f1, t_mid, omt_dt, dt,
-                           E);
+        hipLaunchKernelGGL(k_explicit<3>, dim3(nblocks), dim3(kBlock), sb, s, g, st, alpha, U, f0, f1, t_mid, omt_dt,
+                           dt, E, sb);
 }
 
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_residual(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
+__global__ __launch_bounds__(kBlock) void k_residual(LevelDev g, StencilDev st0, const int16_t *__restrict__ alpha,
                                                      const double *__restrict__ V, const double *__restrict__ E,
-                                                     double theta_dt, double *__restrict__ r, double *partial) {
+                                                     double theta_dt, double *__restrict__ r, double *partial,
+                                                     int stage) {
     __shared__ double sh[kBlock / 64];
+    const StencilDev st = stage_fast<double>(st0, stage);
     int i = node_id();
     double rr = 0.0, vv = 0.0;
     if (i < g.N) {
@@ -511,10 +546,13 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev g, StencilDev st, 
 
 void launch_residual(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const double *V,
                      const double *E, double theta_dt, double *r, double *partial, int nblocks, hipStream_t s) {
+    int sb = stage_bytes<double>(st);
     if (dim == 2)
-        hipLaunchKernelGGL(k_residual<2>, dim3(nblocks), dim3(kBlock), 0, s, g, st, alpha, V, E, theta_dt, r, partial);
+        hipLaunchKernelGGL(k_residual<2>, dim3(nblocks), dim3(kBlock), sb, s, g, st, alpha, V, E, theta_dt, r, partial,
+                           sb);
     else
-        hipLaunchKernelGGL(k_residual<3>, dim3(nblocks), dim3(kBlock), 0, s, g, st, alpha, V, E, theta_dt, r, partial);
+        hipLaunchKernelGGL(k_residual<3>, dim3(nblocks), dim3(kBlock), sb, s, g, st, alpha, V, E, theta_dt, r, partial,
+                           sb);
 }
 
 // number of interior nodes whose control index is outside [0, K)
@@ -615,10 +653,11 @@ __device__ __forceinline__ T apply_level(const LevelDev &g, const StencilDev &st
 }
 
 template <int DIM, typename T>
-__global__ __launch_bounds__(kBlock) void k_jacobi(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
+__global__ __launch_bounds__(kBlock) void k_jacobi(LevelDev g, StencilDev st0, const int16_t *__restrict__ alpha,
                                                    const T *__restrict__ e, const T *__restrict__ r,
                                                    const T *__restrict__ d, T *__restrict__ e_out, T theta_dt, T omega,
-                                                   int first) {
+                                                   int first, int stage) {
+    const StencilDev st = stage_fast<T>(st0, stage);
     int i = node_id();
     if (i >= g.N) return;
     int ix[3];
@@ -639,18 +678,20 @@ template <typename T>
 void launch_jacobi(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const T *e, const T *r,
                    const T *d, T *e_out, double theta_dt, double omega, bool first, hipStream_t s) {
     int nb = blocks_for(g.N);
+    int sb = first ? 0 : stage_bytes<T>(st);
     if (dim == 2)
-        hipLaunchKernelGGL((k_jacobi<2, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, e, r, d, e_out, (T)theta_dt,
-                           (T)omega, (int)first);
+        hipLaunchKernelGGL((k_jacobi<2, T>), dim3(nb), dim3(kBlock), sb, s, g, st, alpha, e, r, d, e_out, (T)theta_dt,
+                           (T)omega, (int)first, sb);
     else
-        hipLaunchKernelGGL((k_jacobi<3, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, e, r, d, e_out, (T)theta_dt,
-                           (T)omega, (int)first);
+        hipLaunchKernelGGL((k_jacobi<3, T>), dim3(nb), dim3(kBlock), sb, s, g, st, alpha, e, r, d, e_out, (T)theta_dt,
+                           (T)omega, (int)first, sb);
 }
 
 template <int DIM, typename T>
-__global__ __launch_bounds__(kBlock) void k_level_residual(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
+__global__ __launch_bounds__(kBlock) void k_level_residual(LevelDev g, StencilDev st0, const int16_t *__restrict__ alpha,
                                                            const T *__restrict__ e, const T *__restrict__ r,
-                                                           T *__restrict__ res, T theta_dt) {
+                                                           T *__restrict__ res, T theta_dt, int stage) {
+    const StencilDev st = stage_fast<T>(st0, stage);
     int i = node_id();
     if (i >= g.N) return;
     int ix[3];
@@ -664,12 +705,13 @@ template <typename T>
 void launch_level_residual(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const T *e,
                            const T *r, T *res, double theta_dt, hipStream_t s) {
     int nb = blocks_for(g.N);
+    int sb = stage_bytes<T>(st);
     if (dim == 2)
-        hipLaunchKernelGGL((k_level_residual<2, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, e, r, res,
-                           (T)theta_dt);
+        hipLaunchKernelGGL((k_level_residual<2, T>), dim3(nb), dim3(kBlock), sb, s, g, st, alpha, e, r, res,
+                           (T)theta_dt, sb);
     else
-        hipLaunchKernelGGL((k_level_residual<3, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, e, r, res,
-                           (T)theta_dt);
+        hipLaunchKernelGGL((k_level_residual<3, T>), dim3(nb), dim3(kBlock), sb, s, g, st, alpha, e, r, res,
+                           (T)theta_dt, sb);
 }
 
 // full weighting: weights 1/4, 1/2, 1/4 per axis around fine node 2I
@@ -866,10 +908,12 @@ __global__ __launch_bounds__(kBlock) void k_multidot(const double *__restrict__ 
     int b = remap_block(blockIdx.x, gridDim.x);
     int64_t base = (int64_t)b * kBlock * kDotItems + threadIdx.x;
     double wv[kDotItems];
+    double ww = 0.0;
 #pragma unroll
     for (int q = 0; q < kDotItems; ++q) {
         int64_t n = base + (int64_t)q * kBlock;
         wv[q] = n < N ? w[n] : 0.0;
+        ww += wv[q] * wv[q];
     }
     for (int v = 0; v < nvec; ++v) {
         const double *Vv = V + (int64_t)v * ldv;
@@ -882,6 +926,8 @@ __global__ __launch_bounds__(kBlock) void k_multidot(const double *__restrict__ 
         double t = block_reduce<double>(acc, OpSum(), sh);
         if (threadIdx.x == 0) partial[(int64_t)v * gridDim.x + b] = t;
     }
+    double t = block_reduce<double>(ww, OpSum(), sh);
+    if (threadIdx.x == 0) partial[(int64_t)nvec * gridDim.x + b] = t;
 }
 
 int dot_blocks(int64_t N) { return (int)((N + (int64_t)kBlock * kDotItems - 1) / ((int64_t)kBlock * kDotItems)); }
@@ -891,30 +937,33 @@ void launch_multidot(const double *w, const double *V, int64_t ldv, int nvec, in
     hipLaunchKernelGGL(k_multidot, dim3(nblocks), dim3(kBlock), 0, s, w, V, ldv, nvec, N, partial);
 }
 
-__global__ __launch_bounds__(kBlock) void k_multiaxpy(double *__restrict__ w, const double *__restrict__ V, int64_t ldv,
-                                                      int nvec, const double *__restrict__ coef, int64_t N,
-                                                      double *norm2_partial) {
-    __shared__ double sh[kBlock / 64];
+__global__ __launch_bounds__(kBlock) void k_multiaxpy_scale(double *__restrict__ w, const double *__restrict__ V,
+                                                            int64_t ldv, int nvec, const double *__restrict__ coef,
+                                                            int64_t N) {
+    __shared__ double c[kMaxRestart + 2];
+    for (int v = threadIdx.x; v <= nvec; v += blockDim.x) c[v] = coef[v];
+    __syncthreads();
+    // norm of the orthogonalised vector by Pythagoras (the caller re-orthogonalises on cancellation)
+    double h2 = 0.0;
+    for (int v = 0; v < nvec; ++v) h2 += c[v] * c[v];
+    double hn2 = c[nvec] - h2;
+    double inv = hn2 > 0.0 ? 1.0 / sqrt(hn2) : 1.0;
     int b = remap_block(blockIdx.x, gridDim.x);
     int64_t base = (int64_t)b * kBlock * kDotItems + threadIdx.x;
-    double acc2 = 0.0;
 #pragma unroll
     for (int q = 0; q < kDotItems; ++q) {
         int64_t n = base + (int64_t)q * kBlock;
         if (n < N) {
             double x = w[n];
-            for (int v = 0; v < nvec; ++v) x -= coef[v] * V[(int64_t)v * ldv + n];
-            w[n] = x;
-            acc2 += x * x;
+            for (int v = 0; v < nvec; ++v) x -= c[v] * V[(int64_t)v * ldv + n];
+            w[n] = x * inv;
         }
     }
-    double t = block_reduce<double>(acc2, OpSum(), sh);
-    if (threadIdx.x == 0 && norm2_partial) norm2_partial[b] = t;
 }
 
-void launch_multiaxpy(double *w, const double *V, int64_t ldv, int nvec, const double *coef, int64_t N,
-                      double *norm2_partial, int nblocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_multiaxpy, dim3(nblocks), dim3(kBlock), 0, s, w, V, ldv, nvec, coef, N, norm2_partial);
+void launch_multiaxpy_scale(double *w, const double *V, int64_t ldv, int nvec, const double *coef, int64_t N,
+                            int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_multiaxpy_scale, dim3(nblocks), dim3(kBlock), 0, s, w, V, ldv, nvec, coef, N);
 }
 
 __global__ __launch_bounds__(kBlock) void k_reduce_sum(const double *__restrict__ partial, int nblocks,
@@ -1030,6 +1079,26 @@ void launch_copy_interior(int dim, const LevelDev &g, const double *src, double 
         hipLaunchKernelGGL(k_copy_interior<2>, dim3(blocks_for(g.N)), dim3(kBlock), 0, s, g, src, dst);
     else
         hipLaunchKernelGGL(k_copy_interior<3>, dim3(blocks_for(g.N)), dim3(kBlock), 0, s, g, src, dst);
+}
+
+// interior of out = U1 + ratio (U1 - U0): the starting point of a step's policy iteration
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_extrapolate(LevelDev g, const double *__restrict__ U1,
+                                                        const double *__restrict__ U0, double ratio,
+                                                        double *__restrict__ out) {
+    int i = node_id();
+    if (i >= g.N) return;
+    int ix[3];
+    unflatten<DIM>(g, i, ix);
+    if (interior<DIM>(g, ix)) out[i] = U1[i] + ratio * (U1[i] - U0[i]);
+}
+
+void launch_extrapolate(int dim, const LevelDev &g, const double *U1, const double *U0, double ratio, double *out,
+                        hipStream_t s) {
+    if (dim == 2)
+        hipLaunchKernelGGL(k_extrapolate<2>, dim3(blocks_for(g.N)), dim3(kBlock), 0, s, g, U1, U0, ratio, out);
+    else
+        hipLaunchKernelGGL(k_extrapolate<3>, dim3(blocks_for(g.N)), dim3(kBlock), 0, s, g, U1, U0, ratio, out);
 }
 
 // Zero fill by a kernel (stream-ordered, safe inside captured graphs); exact byte count.

@@ -91,6 +91,7 @@ def test_setup_without_gpu_reports_device_error(slhjb):
 def test_null_handle_calls_fail_cleanly(slhjb):
     L = slhjb.lib()
     st = slhjb.StepStats()
-    assert L.hjb_step(None, None, None, None, None, 0.0, 0.1, 1.0, 1.0, None, ctypes.byref(st)) == -1
+    assert L.hjb_step(None, None, None, None, None, 0.0, 0.1, 1.0, 1.0, None, None, 0.0, ctypes.byref(st)) == -1
+    assert L.hjb_profile_enable(None, 0, 10) == -1
     assert L.hjb_apply(None, None, None, None, 0.1, 1.0, 1.0) == -1
     L.hjb_destroy(None)

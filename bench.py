@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle Krylov work in the sample")
     ap.add_argument("--pi-eta", type=float, default=None)
     ap.add_argument("--restart", type=int, default=None)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain device copy of 2^28 bytes (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -176,6 +178,12 @@ def main():
 
     inst = workloads.config_h(n=args.n)
     modes = [m for m in args.modes.split(",") if m]
+    if args.calibrate_copy:
+        a = torch.ones(1 << 25, dtype=torch.float64, device="cuda")   # 2^28 bytes
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     res = {}
     for m in modes:
         print(f"[bench] mode {m}: {inst.n[0]}x{inst.n[1]}, warmup {args.warmup}, steps {args.steps}", file=sys.stderr,

@@ -80,6 +80,7 @@ typedef struct {
     double pi_eta;          /* policy iterations whose policy may still change solve only until the
                                residual has dropped by this factor (0: every solve to rtol_inf); the
                                last solve of a step always meets rtol_inf and is confirmed by a search */
+    int32_t use_graphs;     /* 1: replay captured HIP graphs of the V-cycle (identical kernels), 0: launch eagerly */
     void *stream;           /* hipStream_t */
 } hjb_desc;
 
@@ -101,7 +102,7 @@ typedef struct {
     double max_cert_bound;
 } hjb_solve_stats;
 
-/* Fill *d with defaults (2D, FP64, V-cycle, m = 30, rtol 1e-13, tau_rel 1e-13, ...). Grid and controls
+/* Fill *d with defaults (2D, FP64, V-cycle(2,2), m = 10, rtol 1e-13, tau_rel 1e-13, pi_eta 0.2, ...). Grid and controls
    still have to be set by the caller. */
 void hjb_desc_default(hjb_desc *d);
 
@@ -113,7 +114,8 @@ int hjb_setup(const hjb_desc *desc, hjb_handle **out);
 int hjb_set_stream(hjb_handle *hd, void *stream);
 
 /* Change solver controls after setup (precision, precond, restart, max_krylov, max_pi, nu1, nu2,
-   coarse_sweeps, omega, rtol_inf, tau_rel are taken from *desc; grid and controls must be unchanged). */
+   coarse_sweeps, omega, rtol_inf, tau_rel, pi_eta, use_graphs are taken from *desc; grid and controls
+   are those of the setup).  restart may not exceed its value at setup. */
 int hjb_set_options(hjb_handle *hd, const hjb_desc *desc);
 
 /*

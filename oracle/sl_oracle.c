@@ -30,9 +30,13 @@
  *     mu < 1 the limiting coordinate is set to the face index exactly and the
  *     others are i_d + mu*Y_d, clamped to [0, n_d-1].
  *   - A landing cell n_d-1 is replaced by cell n_d-2 with fraction 1.
- *   - Interpolation is the nested lerp (1-t)*a + t*b, innermost over x.
- *   - Every expression is evaluated left to right as written, with no fused
- *     multiply-add (compiled with -ffp-contract=off).
+ *   - Interpolation is the weighted sum of eq. monotone_int over the 2^d cell
+ *     corners c = 0..2^d-1 (bit d of c set: upper corner along axis d): the
+ *     weight is the product over axes, in axis order, of t_d (upper) or 1-t_d
+ *     (lower), and the sum is w_0*V_0 followed by fma(w_c, V_c, sum) in corner
+ *     order.
+ *   - Apart from those explicit fma() calls every expression is evaluated left
+ *     to right as written (compiled with -ffp-contract=off).
  */
 #include <math.h>
 #include <stdint.h>
@@ -109,21 +113,27 @@ static void landing(const orc_problem *pb, const int64_t ix[3], const double Y[3
     }
 }
 
-static double lerp(double a, double b, double t) { return (1.0 - t) * a + t * b; }
+/* Weight of corner c (bit d set: upper corner on axis d) of a landing, eq. monotone_int_2. */
+static double corner_weight(const orc_problem *pb, const orc_land *L, int c) {
+    double w = ((c & 1) ? L->t[0] : (1.0 - L->t[0]));
+    for (int d = 1; d < pb->dim; ++d) w = w * (((c >> d) & 1) ? L->t[d] : (1.0 - L->t[d]));
+    return w;
+}
 
-/* Multilinear interpolant (eq. monotone_int) of V at a landing point. */
-static double interp(const orc_problem *pb, const orc_land *L, const double *V) {
+static int64_t corner_index(const orc_problem *pb, const orc_land *L, int c) {
     int64_t s1 = pb->n[0], s2 = pb->n[0] * pb->n[1];
-    int64_t base = L->cell[0] + (pb->dim > 1 ? L->cell[1] * s1 : 0) + (pb->dim > 2 ? L->cell[2] * s2 : 0);
-    if (pb->dim == 1) return lerp(V[base], V[base + 1], L->t[0]);
-    double a = lerp(V[base], V[base + 1], L->t[0]);
-    double b = lerp(V[base + s1], V[base + s1 + 1], L->t[0]);
-    double v0 = lerp(a, b, L->t[1]);
-    if (pb->dim == 2) return v0;
-    double c = lerp(V[base + s2], V[base + s2 + 1], L->t[0]);
-    double e = lerp(V[base + s2 + s1], V[base + s2 + s1 + 1], L->t[0]);
-    double v1 = lerp(c, e, L->t[1]);
-    return lerp(v0, v1, L->t[2]);
+    int64_t idx = L->cell[0] + (c & 1);
+    if (pb->dim > 1) idx += (L->cell[1] + ((c >> 1) & 1)) * s1;
+    if (pb->dim > 2) idx += (L->cell[2] + ((c >> 2) & 1)) * s2;
+    return idx;
+}
+
+/* Multilinear interpolant (eq. monotone_int): sum over the cell corners of weight times value. */
+static double interp(const orc_problem *pb, const orc_land *L, const double *V) {
+    int nc = 1 << pb->dim;
+    double v = corner_weight(pb, L, 0) * V[corner_index(pb, L, 0)];
+    for (int c = 1; c < nc; ++c) v = fma(corner_weight(pb, L, c), V[corner_index(pb, L, c)], v);
+    return v;
 }
 
 static void diffusion_Y(const orc_problem *pb, int k, int64_t i, int p, double Y[3]) {
@@ -206,19 +216,10 @@ void orc_landing(const orc_problem *pb, int64_t i, const double *Y, int64_t *cel
 }
 
 static int64_t emit_point(const orc_problem *pb, const orc_land *L, double weight, int64_t *cols, double *vals) {
-    int64_t s1 = pb->n[0], s2 = pb->n[0] * pb->n[1];
-    int64_t base = L->cell[0] + (pb->dim > 1 ? L->cell[1] * s1 : 0) + (pb->dim > 2 ? L->cell[2] * s2 : 0);
     int nc = 1 << pb->dim;
     for (int c = 0; c < nc; ++c) {
-        double w = weight;
-        int64_t off = 0;
-        for (int d = 0; d < pb->dim; ++d) {
-            int bit = (c >> d) & 1;
-            w = w * (bit ? L->t[d] : (1.0 - L->t[d]));
-            off += bit ? (d == 0 ? 1 : (d == 1 ? s1 : s2)) : 0;
-        }
-        cols[c] = base + off;
-        vals[c] = w;
+        cols[c] = corner_index(pb, L, c);
+        vals[c] = weight * corner_weight(pb, L, c);
     }
     return nc;
 }

@@ -45,7 +45,7 @@ class Desc(ctypes.Structure):
                 ("max_krylov", ctypes.c_int32), ("max_pi", ctypes.c_int32), ("nu1", ctypes.c_int32),
                 ("nu2", ctypes.c_int32), ("coarse_sweeps", ctypes.c_int32), ("min_coarse", ctypes.c_int32),
                 ("omega", ctypes.c_double), ("rtol_inf", ctypes.c_double), ("tau_rel", ctypes.c_double),
-                ("pi_eta", ctypes.c_double), ("stream", ctypes.c_void_p)]
+                ("pi_eta", ctypes.c_double), ("use_graphs", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class StepStats(ctypes.Structure):
@@ -118,17 +118,18 @@ def _stream():
 class Options:
     precision: int = PREC_FP64
     precond: int = PRECOND_VCYCLE
-    restart: int = 30
+    restart: int = 10
     max_krylov: int = 600
     max_pi: int = 50
-    nu1: int = 1
-    nu2: int = 1
+    nu1: int = 2
+    nu2: int = 2
     coarse_sweeps: int = 30
     min_coarse: int = 17
-    omega: float = 0.7
+    omega: float = 0.8
     rtol_inf: float = 1e-13
     tau_rel: float = 1e-13
-    pi_eta: float = 1e-3
+    pi_eta: float = 0.2
+    use_graphs: int = 1
 
 
 class Solver:
@@ -174,6 +175,7 @@ class Solver:
         desc.max_krylov, desc.max_pi, desc.nu1, desc.nu2 = o.max_krylov, o.max_pi, o.nu1, o.nu2
         desc.coarse_sweeps, desc.min_coarse, desc.omega = o.coarse_sweeps, o.min_coarse, o.omega
         desc.rtol_inf, desc.tau_rel, desc.pi_eta = o.rtol_inf, o.tau_rel, o.pi_eta
+        desc.use_graphs = o.use_graphs
 
     @classmethod
     def from_instance(cls, inst, options: Optional[Options] = None):

@@ -80,6 +80,7 @@ struct hjb_handle {
     double *E = nullptr, *R = nullptr, *Vb = nullptr, *Zb = nullptr;
     double *Ua = nullptr, *Ub = nullptr, *Uc = nullptr;
     int16_t *a0 = nullptr, *a1 = nullptr, *acarry = nullptr;
+    double *Q = nullptr;        // [K][N] explicit part of G for the searches of one step (or null)
     double *partial = nullptr;  // >= max(3*nb, (m+2)*nbd)
     double *dvals = nullptr;    // device scalars / small vectors [256]
     int64_t *ipartial = nullptr, *ival = nullptr;
@@ -87,6 +88,14 @@ struct hjb_handle {
     int64_t *hpin_i = nullptr;
     std::vector<void *> allocs;
     bool trace = false;  // SLHJB_TRACE=1: policy-iteration progress on stderr
+    // captured V-cycles, keyed by the buffers and scalars baked into their kernel arguments
+    struct VGraph {
+        const void *a0, *v, *z;
+        double theta_dt;
+        hipGraphExec_t exec;
+    };
+    std::vector<VGraph> vgraphs;
+    hipStream_t capture_stream = nullptr;
     struct Timer {
         int cap = 0, used = 0;
         std::vector<hipEvent_t> ev;  // 2*cap events
@@ -174,14 +183,20 @@ int build_tables(hjb_handle *hd, double s) {
             }
         }
         HIPCHK(hipMemcpyAsync(L.tab, host.data(), host.size() * sizeof(PointTab), hipMemcpyHostToDevice, hd->stream));
+        // corner weights of the untruncated landing: product over axes (axis order) of t or 1 - t
         std::vector<FastPtF> hf(host.size());
         std::vector<FastPtD> hdd(host.size());
         for (size_t q = 0; q < host.size(); ++q) {
+            memset(&hf[q], 0, sizeof(FastPtF));
+            memset(&hdd[q], 0, sizeof(FastPtD));
             hf[q].off = hdd[q].off = (int32_t)host[q].off;
-            hdd[q].pad = 0;
-            for (int a = 0; a < 3; ++a) {
-                hf[q].t[a] = host[q].tf[a];
-                hdd[q].t[a] = host[q].t[a];
+            const double *t = host[q].t;
+            for (int c = 0; c < (1 << hd->dim); ++c) {
+                double w = (c & 1) ? t[0] : (1.0 - t[0]);
+                w = w * (((c >> 1) & 1) ? t[1] : (1.0 - t[1]));
+                if (hd->dim == 3) w = w * (((c >> 2) & 1) ? t[2] : (1.0 - t[2]));
+                hdd[q].w[c] = w;
+                hf[q].w[c] = (float)w;
             }
         }
         HIPCHK(hipMemcpyAsync(L.fastF, hf.data(), hf.size() * sizeof(FastPtF), hipMemcpyHostToDevice, hd->stream));
@@ -347,7 +362,7 @@ __global__ void k_jacobi_precond32(const double *v, const float *dg, float *z, i
 }
 
 // z_j = M^{-1} v_j
-void precondition(hjb_handle *hd, const double *v, void *z, double theta_dt) {
+void precondition_eager(hjb_handle *hd, const double *v, void *z, double theta_dt) {
     const int64_t N = hd->N;
     hipStream_t s = hd->stream;
     Level &L0 = hd->lev[0];
@@ -366,6 +381,48 @@ void precondition(hjb_handle *hd, const double *v, void *z, double theta_dt) {
     } else {
         vcycle<double>(hd, v, (double *)z, theta_dt);
     }
+}
+
+void drop_graphs(hjb_handle *hd) {
+    for (auto &g : hd->vgraphs) (void)hipGraphExecDestroy(g.exec);
+    hd->vgraphs.clear();
+}
+
+// z = M^{-1} v.  The V-cycle's launch sequence depends only on buffer addresses and theta*dt, so it is
+// captured once per (level-0 policy buffer, v, z, theta*dt) and replayed; policy, diagonal and table
+// contents are refreshed in place before each replay.  Timers on the smoother kernels force the
+// eager path (events cannot be accumulated from inside a replayed graph).
+int precondition(hjb_handle *hd, const double *v, void *z, double theta_dt) {
+    bool timed = hd->timers[HJB_KERNEL_SMOOTH].cap > 0 || hd->timers[HJB_KERNEL_MG_RESID].cap > 0;
+    if (!hd->desc.use_graphs || hd->desc.precond != HJB_PRECOND_VCYCLE || timed) {
+        precondition_eager(hd, v, z, theta_dt);
+        return HJB_OK;
+    }
+    const void *a0 = hd->lev[0].alpha;
+    for (auto &g : hd->vgraphs)
+        if (g.a0 == a0 && g.v == v && g.z == z && g.theta_dt == theta_dt) {
+            HIPCHK(hipGraphLaunch(g.exec, hd->stream));
+            return HJB_OK;
+        }
+    if (hd->vgraphs.size() >= 256) drop_graphs(hd);
+    if (!hd->capture_stream) HIPCHK(hipStreamCreateWithFlags(&hd->capture_stream, hipStreamNonBlocking));
+    hipStream_t saved = hd->stream;
+    hd->stream = hd->capture_stream;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(hd->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        precondition_eager(hd, v, z, theta_dt);
+        e = hipStreamEndCapture(hd->capture_stream, &graph);
+    }
+    hd->stream = saved;
+    if (e != hipSuccess) return fail(HJB_EDEVICE, "V-cycle capture: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(HJB_EDEVICE, "V-cycle instantiate: %s", hipGetErrorString(e));
+    hd->vgraphs.push_back({a0, v, z, theta_dt, exec});
+    HIPCHK(hipGraphLaunch(exec, hd->stream));
+    return HJB_OK;
 }
 
 // ---- flexible GMRES(m) on A^alpha x = b, with x = X on interior nodes ----------------------------
@@ -420,7 +477,7 @@ int fgmres(hjb_handle *hd, const int16_t *alpha, const double *E, double *X, dou
             double *vj = V + (int64_t)j * N;
             double *w = V + (int64_t)(j + 1) * N;
             void *zj = none ? (void *)vj : (void *)((char *)hd->Zb + (int64_t)j * N * zsz);
-            if (!none) precondition(hd, vj, zj, theta_dt);
+            if (!none) TRY(precondition(hd, vj, zj, theta_dt));
             {
                 TimedLaunch tl(hd, HJB_KERNEL_APPLY, (double)N * ((zf ? 4.0 : 8.0) + 2.0 + 8.0));
                 launch_apply(dim, L0.g, st, alpha, zj, zf, w, theta_dt, nullptr, hd->nb, s);
@@ -525,7 +582,7 @@ __global__ void k_sweep_tau_arg(const double *tau_dev, double *tau_copy) {
 
 int sweep(hjb_handle *hd, const double *X, const double *U, const double *f0, const double *f1, double t_prev,
           double dt, double theta, const int16_t *a_in, int16_t *a_out, double *gmin, double *margin, int32_t *ties,
-          int64_t *n_changed, double *tau_used) {
+          int64_t *n_changed, double *tau_used, int qmode = 0) {
     hipStream_t s = hd->stream;
     const Level &L0 = hd->lev[0];
     double t_mid = t_prev + theta * dt;
@@ -539,7 +596,8 @@ int sweep(hjb_handle *hd, const double *X, const double *U, const double *f0, co
     double tau = hd->hpin[4];
     SweepOut o{a_out, gmin, margin, ties, hd->ipartial};
     TimedLaunch tl(hd, HJB_KERNEL_SWEEP, (double)hd->N * (4 * 8.0 + 2.0 + 2.0));
-    launch_sweep(hd->dim, L0.g, stencil(hd, 0), X, U, f0, f1, t_mid, theta, tau, a_in, o, hd->nb, s);
+    if (!hd->Q) qmode = 0;
+    launch_sweep(hd->dim, L0.g, stencil(hd, 0), X, U, f0, f1, t_mid, theta, tau, a_in, o, hd->Q, qmode, hd->nb, s);
     HIPCHK(hipGetLastError());
     if (n_changed) {
         launch_reduce_sum_i64(hd->ipartial, hd->nb, hd->ival, s);
@@ -591,8 +649,10 @@ int step_impl(hjb_handle *hd, const double *Uprev, double *Unext, const double *
         launch_copy_interior(hd->dim, hd->lev[0].g, Uprev, Unext, s);
     int16_t *acur = hd->a0, *anew = hd->a1;
     int64_t changed = 0;
+    // the explicit part of every G_k is fixed within the step: the first search stores it (when the
+    // handle could afford the K*N cache) and the later searches read it
     TRY(sweep(hd, Unext, Uprev, f0, f1, t_prev, dt, theta, alpha_io, acur, nullptr, nullptr, nullptr, &changed,
-              nullptr));
+              nullptr, 1));
     loc.n_changed_first = changed;
     double cert_den = 1.0 - theta * dt * hd->cplus;
     if (theta < 1.0) {
@@ -617,7 +677,7 @@ int step_impl(hjb_handle *hd, const double *Uprev, double *Unext, const double *
         loc.cert_bound = cert_den > 0 ? res / cert_den : INFINITY;
         if (rc != HJB_OK) break;
         TRY(sweep(hd, Unext, Uprev, f0, f1, t_prev, dt, theta, acur, anew, nullptr, nullptr, nullptr, &changed,
-                  nullptr));
+                  nullptr, 2));
         if (hd->trace)
             fprintf(stderr, "[slhjb] pi %d: krylov %d res %.3e tight %d changed %lld\n", it, its, res, (int)tight,
                     (long long)changed);
@@ -656,17 +716,18 @@ void hjb_desc_default(hjb_desc *d) {
     d->coef_model = HJB_COEF_CONST;
     d->precision = HJB_PREC_FP64;
     d->precond = HJB_PRECOND_VCYCLE;
-    d->restart = 30;
+    d->restart = 10;
     d->max_krylov = 600;
     d->max_pi = 50;
-    d->nu1 = 1;
-    d->nu2 = 1;
+    d->nu1 = 2;
+    d->nu2 = 2;
     d->coarse_sweeps = 30;
     d->min_coarse = 17;
-    d->omega = 0.7;
+    d->omega = 0.8;
     d->rtol_inf = 1e-13;
     d->tau_rel = 1e-13;
-    d->pi_eta = 1e-3;
+    d->pi_eta = 0.2;
+    d->use_graphs = 1;
     d->stream = nullptr;
 }
 
@@ -730,7 +791,6 @@ int hjb_setup(const hjb_desc *desc, hjb_handle **out) {
     hd->desc.c = hd->c.empty() ? nullptr : hd->c.data();
     hd->npt = 2 * d.P + (hd->has_drift ? 1 : 0);
     hd->M = d.P + (hd->has_drift ? 1 : 0);
-    hd->nb = blocks_for(N);
     hd->nbd = dot_blocks(N);
 
     auto cleanup_fail = [&](int rc) {
@@ -752,6 +812,7 @@ int hjb_setup(const hjb_desc *desc, hjb_handle **out) {
             L.g.N = (int64_t)L.g.n[0] * L.g.n[1] * L.g.n[2];
             L.g.s1 = L.g.n[0];
             L.g.s2 = (int64_t)L.g.n[0] * L.g.n[1];
+            set_tiles(L.g, d.dim);
             hd->lev.push_back(L);
             bool can = true, small = true;
             for (int a = 0; a < d.dim; ++a) {
@@ -778,6 +839,7 @@ int hjb_setup(const hjb_desc *desc, hjb_handle **out) {
         STRY(dalloc(hd, &L.t32, n * 4));
         STRY(dalloc(hd, &L.d32, n * 4));
     }
+    hd->nb = tiles_for(hd->lev[0].g);  // blocks of the node kernels on the finest grid (partial sums)
     select_precision(hd);
     const int m = kMaxRestart;
     (void)m;
@@ -791,6 +853,20 @@ int hjb_setup(const hjb_desc *desc, hjb_handle **out) {
     STRY(dalloc(hd, (void **)&hd->a0, N * 2));
     STRY(dalloc(hd, (void **)&hd->a1, N * 2));
     STRY(dalloc(hd, (void **)&hd->acarry, N * 2));
+    {
+        // cache of the explicit part of the search values (K doubles per node) when it is affordable
+        size_t qbytes = (size_t)d.K * (size_t)N * 8;
+        size_t freeb = 0, totalb = 0;
+        if (hipMemGetInfo(&freeb, &totalb) == hipSuccess && qbytes <= freeb / 4 && qbytes <= ((size_t)16 << 30)) {
+            void *p = nullptr;
+            if (hipMalloc(&p, qbytes) == hipSuccess) {
+                hd->Q = (double *)p;
+                hd->allocs.push_back(p);
+            } else {
+                (void)hipGetLastError();
+            }
+        }
+    }
     size_t np = std::max<size_t>(3 * (size_t)hd->nb, (size_t)(kMaxRestart + 2) * hd->nbd);
     STRY(dalloc(hd, (void **)&hd->partial, np * 8));
     STRY(dalloc(hd, (void **)&hd->dvals, 256 * 8));
@@ -837,7 +913,9 @@ int hjb_set_options(hjb_handle *hd, const hjb_desc *desc) {
     d.rtol_inf = desc->rtol_inf;
     d.tau_rel = desc->tau_rel;
     d.pi_eta = desc->pi_eta;
+    d.use_graphs = desc->use_graphs;
     select_precision(hd);
+    drop_graphs(hd);
     return HJB_OK;
 }
 
@@ -987,6 +1065,8 @@ int hjb_profile_read(hjb_handle *hd, int32_t kernel, int64_t *launches, double *
 
 void hjb_destroy(hjb_handle *hd) {
     if (!hd) return;
+    drop_graphs(hd);
+    if (hd->capture_stream) (void)hipStreamDestroy(hd->capture_stream);
     for (auto &T : hd->timers)
         for (hipEvent_t e : T.ev) (void)hipEventDestroy(e);
     if (hd->stream) (void)hipStreamSynchronize(hd->stream);

@@ -11,6 +11,7 @@ constexpr int kMaxP = 4;                 // diffusion columns per control
 constexpr int kMaxPts = 2 * kMaxP + 1;   // stencil points per control (Scheme 2: 2P diffusion + 1 drift)
 constexpr int kBlock = 256;              // threads per block of the node-parallel kernels
 constexpr int kMaxRestart = 64;
+constexpr int kTX = 32, kTY = 8;         // node tile of one block (kTX * kTY == kBlock)
 
 // One stencil point of one control on one grid level.  Y is the displacement in cells of that level
 // (diffusion: s*sigma_p/sqrt(h) scaled to the level, drift: b scaled to the level).  The remaining
@@ -25,20 +26,24 @@ struct PointTab {
     int64_t off;
 };
 
-// Compact copies of the untruncated landing used by the node loops (one 16- or 32-byte record per
-// point, staged in LDS by kernels whose control varies per node).
+// Untruncated landing used by the node loops: linear offset of the landing cell and the 2^d corner
+// weights (corner c: bit d set = upper corner on axis d; weight = product over axes of t_d or 1 - t_d).
+// Sizes are multiples of 16 bytes so kernels whose control varies per node can stage them in LDS.
 struct FastPtF {
     int32_t off;
-    float t[3];
+    float w[8];
+    int32_t pad[3];
 };
 struct FastPtD {
     int32_t off;
     int32_t pad;
-    double t[3];
+    double w[8];
+    int64_t pad2;
 };
 
 struct LevelDev {
     int32_t n[3];
+    int32_t ntx, nty, ntz;           // tiles of kTX x kTY x 1 nodes covering the grid
     int32_t deep_lo[3], deep_hi[3];  // nodes with deep_lo <= i_d <= deep_hi never truncate
     int64_t N;
     int64_t s1, s2;                  // strides of axes 1 and 2
@@ -62,9 +67,11 @@ struct SweepOut {
     int64_t *changed_partial;  // [nblocks]
 };
 
+// qmode: 0 evaluate the explicit part (theta < 1) or skip it (theta = 1); 1 evaluate it and store
+// Q[k*N + i] = (1-theta)((L^k U)_i + c_k U_i); 2 read it from Q.
 void launch_sweep(int dim, const LevelDev &g, const StencilDev &st, const double *X, const double *U,
                   const double *f0, const double *f1, double t_mid, double theta, double tau,
-                  const int16_t *a_in, const SweepOut &o, int nblocks, hipStream_t s);
+                  const int16_t *a_in, const SweepOut &o, double *Q, int qmode, int nblocks, hipStream_t s);
 
 void launch_norms_xuf(int dim, const LevelDev &g, const double *X, const double *U, const double *f0,
                       const double *f1, double t_mid, double *partial, int nblocks, hipStream_t s);
@@ -125,5 +132,11 @@ void launch_extrapolate(int dim, const LevelDev &g, const double *U1, const doub
                         hipStream_t s);
 
 int blocks_for(int64_t N);
+inline int tiles_for(const LevelDev &g) { return g.ntx * g.nty * g.ntz; }
+inline void set_tiles(LevelDev &g, int dim) {
+    g.ntx = (g.n[0] + kTX - 1) / kTX;
+    g.nty = (g.n[1] + kTY - 1) / kTY;
+    g.ntz = dim == 3 ? g.n[2] : 1;
+}
 
 }  // namespace slhjb

@@ -10,9 +10,12 @@
 //   displacement in cells Y; mu = min(1, min_d D_d/|Y_d|) with D_d the integer distance to the face
 //   the point moves towards; if mu == 1 the landing cell is i + floor(Y) with fraction Y - floor(Y);
 //   otherwise the limiting coordinate is the face index and the others i + mu*Y (clamped); a landing
-//   cell n-1 becomes cell n-2 with fraction 1; interpolation is the nested lerp (1-t)*a + t*b,
-//   innermost over x; term_p = (A*v+ + B*v-) - (A+B)*V_i, drift 2C*(v_b - V_i), L = (1/2h)*sum.
-// Compiled without floating-point contraction, so these expressions round exactly as written.
+//   cell n-1 becomes cell n-2 with fraction 1; interpolation is the weighted corner sum of
+//   eq. monotone_int: corner weights are products over axes (in axis order) of t_d or 1 - t_d, the sum
+//   is w_0 V_0 then fma(w_c, V_c, sum) in corner order; term_p = (A*v+ + B*v-) - (A+B)*V_i,
+//   drift 2C*(v_b - V_i), L = (1/2h)*sum.
+// Compiled without floating-point contraction: apart from the explicit fma calls these expressions
+// round exactly as written.
 //
 // Thread mapping: one node per thread, x fastest; blocks are renumbered so that each of the eight
 // XCDs (which take hardware blocks round-robin) works on one contiguous slab of rows and keeps the
@@ -30,6 +33,21 @@ __device__ __forceinline__ int remap_block(int b, int nb) {
 }
 
 __device__ __forceinline__ int node_id() { return remap_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; }
+
+// Node of this thread: blocks cover kTX x kTY tiles (x fastest, then y, then z), so that the stencil
+// rows gathered by vertically adjacent nodes are shared in cache.  Returns -1 outside the grid.
+template <int DIM>
+__device__ __forceinline__ int tile_node(const LevelDev &g, int ix[3]) {
+    int b = remap_block(blockIdx.x, gridDim.x);
+    int bx = b % g.ntx, r = b / g.ntx;
+    int by = DIM == 3 ? r % g.nty : r;
+    int bz = DIM == 3 ? r / g.nty : 0;
+    ix[0] = bx * kTX + (int)(threadIdx.x % kTX);
+    ix[1] = by * kTY + (int)(threadIdx.x / kTX);
+    ix[2] = bz;
+    if (ix[0] >= g.n[0] || ix[1] >= g.n[1]) return -1;
+    return ix[0] + ix[1] * (int)g.s1 + (DIM == 3 ? ix[2] * (int)g.s2 : 0);
+}
 
 template <int DIM>
 __device__ __forceinline__ void unflatten(const LevelDev &g, int i, int ix[3]) {
@@ -107,25 +125,25 @@ __device__ __forceinline__ double landing(const LevelDev &g, const int ix[3], co
     return mu;
 }
 
-template <typename T>
-__device__ __forceinline__ T lerp_tu(T a, T b, T t, T u) {
-    return u * a + t * b;
-}
+__device__ __forceinline__ double fmat(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float fmat(float a, float b, float c) { return fmaf(a, b, c); }
 
-// nested multilinear interpolation from corner `base`, innermost over x; TS = storage, TC = arithmetic
+// weighted sum over the 2^DIM corners of the cell at `base` (eq. monotone_int); TS storage, TC arithmetic
 template <int DIM, typename TS, typename TC>
-__device__ __forceinline__ TC interp_base(const TS *__restrict__ V, int base, const LevelDev &g, const TC t[3],
-                                          const TC u[3]) {
+__device__ __forceinline__ TC interp_w(const TS *__restrict__ V, int base, const LevelDev &g, const TC w[8]) {
     const int s1 = (int)g.s1;
-    TC a = lerp_tu<TC>((TC)V[base], (TC)V[base + 1], t[0], u[0]);
-    TC b = lerp_tu<TC>((TC)V[base + s1], (TC)V[base + s1 + 1], t[0], u[0]);
-    TC v0 = lerp_tu<TC>(a, b, t[1], u[1]);
-    if (DIM == 2) return v0;
-    const int s2 = (int)g.s2;
-    TC c = lerp_tu<TC>((TC)V[base + s2], (TC)V[base + s2 + 1], t[0], u[0]);
-    TC e = lerp_tu<TC>((TC)V[base + s2 + s1], (TC)V[base + s2 + s1 + 1], t[0], u[0]);
-    TC v1 = lerp_tu<TC>(c, e, t[1], u[1]);
-    return lerp_tu<TC>(v0, v1, t[2], u[2]);
+    TC v = w[0] * (TC)V[base];
+    v = fmat(w[1], (TC)V[base + 1], v);
+    v = fmat(w[2], (TC)V[base + s1], v);
+    v = fmat(w[3], (TC)V[base + s1 + 1], v);
+    if (DIM == 3) {
+        const int s2 = (int)g.s2;
+        v = fmat(w[4], (TC)V[base + s2], v);
+        v = fmat(w[5], (TC)V[base + s2 + 1], v);
+        v = fmat(w[6], (TC)V[base + s2 + s1], v);
+        v = fmat(w[7], (TC)V[base + s2 + s1 + 1], v);
+    }
+    return v;
 }
 
 template <typename TC>
@@ -141,30 +159,35 @@ struct FastOf<float> {
     static __device__ __forceinline__ const FastPtF *get(const StencilDev &s) { return s.fastF; }
 };
 
-// untruncated landing: cell i + floor(Y), fractions t = Y - floor(Y) and u = 1 - t
+// untruncated landing: cell i + floor(Y) with the precomputed corner weights
 template <int DIM, typename TS, typename TC>
 __device__ __forceinline__ TC interp_fast(const TS *__restrict__ V, int i, const typename FastOf<TC>::T &p,
                                           const LevelDev &g) {
-    TC t[3], u[3];
+    TC w[8];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        t[d] = (TC)p.t[d];
-        u[d] = (TC)1 - t[d];
-    }
-    return interp_base<DIM, TS, TC>(V, i + p.off, g, t, u);
+    for (int c = 0; c < (1 << DIM); ++c) w[c] = (TC)p.w[c];
+    return interp_w<DIM, TS, TC>(V, i + p.off, g, w);
 }
 
+// general landing: corner weights from the fractions, product over axes in axis order
 template <int DIM, typename TS, typename TC>
 __device__ __forceinline__ TC interp_land(const TS *__restrict__ V, const LevelDev &g, const int cell[3],
                                           const double td[3]) {
-    TC t[3], u[3];
+    TC t[3], u[3], w[8];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         t[d] = (TC)td[d];
-        u[d] = (TC)(1.0 - td[d]);
+        u[d] = (TC)1 - t[d];
+    }
+#pragma unroll
+    for (int c = 0; c < (1 << DIM); ++c) {
+        TC x = (c & 1) ? t[0] : u[0];
+        x = x * (((c >> 1) & 1) ? t[1] : u[1]);
+        if (DIM == 3) x = x * (((c >> 2) & 1) ? t[2] : u[2]);
+        w[c] = x;
     }
     int base = cell[0] + cell[1] * (int)g.s1 + (DIM == 3 ? cell[2] * (int)g.s2 : 0);
-    return interp_base<DIM, TS, TC>(V, base, g, t, u);
+    return interp_w<DIM, TS, TC>(V, base, g, w);
 }
 
 // (L-hat^k V)_i for one or two fields sharing the stencil geometry (eq. TruncScheme).
@@ -178,7 +201,7 @@ __device__ __forceinline__ void lhat_node(const LevelDev &g, const StencilDev &s
     const PointTab *pt = st.tab + k * st.npt;
     TC accV = (TC)0, accW = (TC)0;
     if (deep) {
-        const typename FastOf<TC>::T *fp = FastOf<TC>::get(st) + k * st.npt;
+        const typename FastOf<TC>::T *fp = FastOf<TC>::get(st) + k * st.npt;  // corner weights precomputed
         for (int p = 0; p < st.P; ++p) {
             const auto &a = fp[2 * p];
             const auto &b = fp[2 * p + 1];
@@ -246,34 +269,15 @@ template <int DIM, typename TS, typename TC>
 __device__ __forceinline__ TC lhat1(const LevelDev &g, const StencilDev &st, int k, int i, const int ix[3], bool deep,
                                     const TS *__restrict__ V, TC Vi) {
     TC a, b;
-    lhat_node<DIM, TS, TC, false>(g, st, k, i, ix, deep, V, Vi, V, Vi, a, b);
-    return a;
-}
-
-// Copy the compact tables of arithmetic type TC into LDS and point a copy of the stencil at them.
-// `bytes` is 0 when the table does not fit (the global copy is used then).
-template <typename TC>
-__device__ __forceinline__ StencilDev stage_fast(const StencilDev &st, int bytes) {
-    extern __shared__ uint4 smem_tab[];
-    StencilDev o = st;
-    if (bytes > 0) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(FastOf<TC>::get(st));
-        for (int q = threadIdx.x; q < bytes / 16; q += blockDim.x) smem_tab[q] = src[q];
-        __syncthreads();
-        if (sizeof(TC) == 8)
-            o.fastD = reinterpret_cast<const FastPtD *>(smem_tab);
-        else
-            o.fastF = reinterpret_cast<const FastPtF *>(smem_tab);
+    // the policy is piecewise constant: when the whole wavefront shares one control (and is untruncated),
+    // its stencil tables are read once through the scalar unit instead of per lane
+    int k0 = __builtin_amdgcn_readfirstlane(k);
+    if (__all(k == k0 && deep)) {
+        lhat_node<DIM, TS, TC, false>(g, st, k0, i, ix, true, V, Vi, V, Vi, a, b);
+    } else {
+        lhat_node<DIM, TS, TC, false>(g, st, k, i, ix, deep, V, Vi, V, Vi, a, b);
     }
-    return o;
-}
-
-constexpr int kMaxStageBytes = 32768;
-
-template <typename TC>
-int stage_bytes(const StencilDev &st) {
-    int b = st.K * st.npt * (int)(sizeof(TC) == 8 ? sizeof(FastPtD) : sizeof(FastPtF));
-    return b <= kMaxStageBytes ? b : 0;
+    return a;
 }
 
 // ---- block reductions ----------------------------------------------------------------------------
@@ -302,30 +306,43 @@ struct OpMax {
 
 // ---- policy search (Howard's algorithm, eq. nonlinear_sys) ----------------------------------------
 
-template <int DIM, bool CN>
+// G_k at node i.  QM 0: explicit part evaluated (theta < 1) or absent (theta = 1); QM 1: evaluated and
+// stored in Q; QM 2: read from Q.  All three round identically.
+template <int DIM, bool CN, int QM>
 __device__ __forceinline__ double eval_G(const LevelDev &g, const StencilDev &st, int k, int i, const int ix[3],
                                          bool deep, const double *__restrict__ X, double Xi,
-                                         const double *__restrict__ U, double Ui, double theta, double omt, double f) {
+                                         const double *__restrict__ U, double Ui, double theta, double omt, double f,
+                                         double *__restrict__ Q) {
+    double ck = st.c ? st.c[k] : 0.0;
     double lx, lu = 0.0;
-    if (CN)
-        lhat_node<DIM, double, double, true>(g, st, k, i, ix, deep, X, Xi, U, Ui, lx, lu);
-    else
+    double q;
+    if (CN && QM == 2) {
         lx = lhat1<DIM, double, double>(g, st, k, i, ix, deep, X, Xi);
-    double ck = st.c ? st.c[((unsigned)k < (unsigned)st.K) ? k : 0] : 0.0;
-    return theta * (lx + ck * Xi) + omt * (lu + ck * Ui) + f;
+        q = Q[(int64_t)k * g.N + i];
+    } else {
+        if (CN)
+            lhat_node<DIM, double, double, true>(g, st, k, i, ix, deep, X, Xi, U, Ui, lx, lu);
+        else
+            lx = lhat1<DIM, double, double>(g, st, k, i, ix, deep, X, Xi);
+        q = omt * (lu + ck * Ui);
+        if (CN && QM == 1) Q[(int64_t)k * g.N + i] = q;
+    }
+    return theta * (lx + ck * Xi) + q + f;
 }
 
-template <int DIM, bool CN, bool EXTRA>
+template <int DIM, bool CN, bool EXTRA, int QM>
 __global__ __launch_bounds__(kBlock) void k_sweep(LevelDev g, StencilDev st, const double *__restrict__ X,
                                                   const double *__restrict__ U, const double *__restrict__ f0,
                                                   const double *__restrict__ f1, double t_mid, double theta,
-                                                  double tau, const int16_t *__restrict__ a_in, SweepOut o) {
+                                                  double tau, const int16_t *__restrict__ a_in, SweepOut o,
+                                                  double *__restrict__ Q) {
     __shared__ int64_t sh[kBlock / 64];
-    int i = node_id();
+    int ix[3];
+    int i = tile_node<DIM>(g, ix);
     int64_t changed = 0;
-    if (i < g.N) {
-        int ix[3];
-        unflatten<DIM>(g, i, ix);
+    // re-evaluations read the cache this thread has just written
+    constexpr int QM2 = QM == 1 ? 2 : QM;
+    if (i >= 0) {
         if (!interior<DIM>(g, ix)) {
             o.alpha_out[i] = -1;
             if (o.gmin) o.gmin[i] = 0.0;
@@ -342,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(LevelDev g, StencilDev st, con
             double best = __builtin_inf(), gcur = __builtin_inf();
             int kbest = 0;
             for (int k = 0; k < st.K; ++k) {
-                double G = eval_G<DIM, CN>(g, st, k, i, ix, deep, X, Xi, U, Ui, theta, omt, f);
+                double G = eval_G<DIM, CN, QM>(g, st, k, i, ix, deep, X, Xi, U, Ui, theta, omt, f, Q);
                 if (G < best) {
                     best = G;
                     kbest = k;
@@ -356,7 +373,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(LevelDev g, StencilDev st, con
             } else {
                 pick = kbest;
                 for (int k = 0; k < kbest; ++k) {
-                    double G = eval_G<DIM, CN>(g, st, k, i, ix, deep, X, Xi, U, Ui, theta, omt, f);
+                    double G = eval_G<DIM, CN, QM2>(g, st, k, i, ix, deep, X, Xi, U, Ui, theta, omt, f, Q);
                     if (G <= thr) {
                         pick = k;
                         break;
@@ -370,7 +387,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(LevelDev g, StencilDev st, con
                 double mg = __builtin_inf();
                 int nt = 0;
                 for (int k = 0; k < st.K; ++k) {
-                    double G = eval_G<DIM, CN>(g, st, k, i, ix, deep, X, Xi, U, Ui, theta, omt, f);
+                    double G = eval_G<DIM, CN, QM2>(g, st, k, i, ix, deep, X, Xi, U, Ui, theta, omt, f, Q);
                     if (G <= thr)
                         ++nt;
                     else if (G - best < mg)
@@ -385,21 +402,33 @@ __global__ __launch_bounds__(kBlock) void k_sweep(LevelDev g, StencilDev st, con
     if (threadIdx.x == 0) o.changed_partial[remap_block(blockIdx.x, gridDim.x)] = tot;
 }
 
-void launch_sweep(int dim, const LevelDev &g, const StencilDev &st, const double *X, const double *U,
-                  const double *f0, const double *f1, double t_mid, double theta, double tau, const int16_t *a_in,
-                  const SweepOut &o, int nblocks, hipStream_t s) {
+template <int DIM>
+void launch_sweep_dim(const LevelDev &g, const StencilDev &st, const double *X, const double *U, const double *f0,
+                      const double *f1, double t_mid, double theta, double tau, const int16_t *a_in,
+                      const SweepOut &o, double *Q, int qmode, int nblocks, hipStream_t s) {
     bool cn = theta != 1.0;
     bool extra = o.margin != nullptr || o.ties != nullptr;
-#define SW(D, C, E) hipLaunchKernelGGL((k_sweep<D, C, E>), dim3(nblocks), dim3(kBlock), 0, s, g, st, X, U, f0, f1, \
-                                       t_mid, theta, tau, a_in, o)
-    if (dim == 2) {
-        if (cn) { if (extra) SW(2, true, true); else SW(2, true, false); }
-        else { if (extra) SW(2, false, true); else SW(2, false, false); }
+#define SW(C, E, QQ) hipLaunchKernelGGL((k_sweep<DIM, C, E, QQ>), dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, X, U, f0, \
+                                        f1, t_mid, theta, tau, a_in, o, Q)
+    if (!cn) {
+        if (extra) SW(false, true, 0); else SW(false, false, 0);
+    } else if (qmode == 1) {
+        if (extra) SW(true, true, 1); else SW(true, false, 1);
+    } else if (qmode == 2) {
+        if (extra) SW(true, true, 2); else SW(true, false, 2);
     } else {
-        if (cn) { if (extra) SW(3, true, true); else SW(3, true, false); }
-        else { if (extra) SW(3, false, true); else SW(3, false, false); }
+        if (extra) SW(true, true, 0); else SW(true, false, 0);
     }
 #undef SW
+}
+
+void launch_sweep(int dim, const LevelDev &g, const StencilDev &st, const double *X, const double *U,
+                  const double *f0, const double *f1, double t_mid, double theta, double tau, const int16_t *a_in,
+                  const SweepOut &o, double *Q, int qmode, int nblocks, hipStream_t s) {
+    if (dim == 2)
+        launch_sweep_dim<2>(g, st, X, U, f0, f1, t_mid, theta, tau, a_in, o, Q, qmode, nblocks, s);
+    else
+        launch_sweep_dim<3>(g, st, X, U, f0, f1, t_mid, theta, tau, a_in, o, Q, qmode, nblocks, s);
 }
 
 // max over all nodes of max(|X|,|U|) and over interior nodes of |f0 + t_mid f1|
@@ -408,12 +437,11 @@ __global__ __launch_bounds__(kBlock) void k_norms_xuf(LevelDev g, const double *
                                                       const double *__restrict__ U, const double *__restrict__ f0,
                                                       const double *__restrict__ f1, double t_mid, double *partial) {
     __shared__ double sh[kBlock / 64];
-    int i = node_id();
+    int ix[3];
+    int i = tile_node<DIM>(g, ix);
     double vx = 0.0, vf = 0.0;
-    if (i < g.N) {
+    if (i >= 0) {
         vx = fmax(fabs(X[i]), fabs(U[i]));
-        int ix[3];
-        unflatten<DIM>(g, i, ix);
         if (interior<DIM>(g, ix)) vf = fabs(f0[i] + t_mid * f1[i]);
     }
     int b = remap_block(blockIdx.x, gridDim.x);
@@ -426,9 +454,9 @@ __global__ __launch_bounds__(kBlock) void k_norms_xuf(LevelDev g, const double *
 void launch_norms_xuf(int dim, const LevelDev &g, const double *X, const double *U, const double *f0, const double *f1,
                       double t_mid, double *partial, int nblocks, hipStream_t s) {
     if (dim == 2)
-        hipLaunchKernelGGL(k_norms_xuf<2>, dim3(nblocks), dim3(kBlock), 0, s, g, X, U, f0, f1, t_mid, partial);
+        hipLaunchKernelGGL(k_norms_xuf<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, X, U, f0, f1, t_mid, partial);
     else
-        hipLaunchKernelGGL(k_norms_xuf<3>, dim3(nblocks), dim3(kBlock), 0, s, g, X, U, f0, f1, t_mid, partial);
+        hipLaunchKernelGGL(k_norms_xuf<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, X, U, f0, f1, t_mid, partial);
 }
 
 // ---- FP64 operator kernels ------------------------------------------------------------------------
@@ -436,14 +464,13 @@ void launch_norms_xuf(int dim, const LevelDev &g, const double *X, const double 
 template <int DIM, typename TX>
 __global__ __launch_bounds__(kBlock) void k_apply(LevelDev g, StencilDev st0, const int16_t *__restrict__ alpha,
                                                   const TX *__restrict__ x, double *__restrict__ y, double theta_dt,
-                                                  double *norm2_partial, int stage) {
+                                                  double *norm2_partial) {
     __shared__ double sh[kBlock / 64];
-    const StencilDev st = stage_fast<double>(st0, stage);
-    int i = node_id();
+    const StencilDev &st = st0;
+    int ix[3];
+    int i = tile_node<DIM>(g, ix);
     double yy = 0.0;
-    if (i < g.N) {
-        int ix[3];
-        unflatten<DIM>(g, i, ix);
+    if (i >= 0) {
         if (interior<DIM>(g, ix)) {
             int k = alpha[i];
             bool deep = deep_node<DIM>(g, ix);
@@ -462,9 +489,8 @@ __global__ __launch_bounds__(kBlock) void k_apply(LevelDev g, StencilDev st0, co
 
 void launch_apply(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const void *x,
                   bool x_is_float, double *y, double theta_dt, double *norm2_partial, int nblocks, hipStream_t s) {
-    int sb = stage_bytes<double>(st);
-#define AP(D, TX) hipLaunchKernelGGL((k_apply<D, TX>), dim3(nblocks), dim3(kBlock), sb, s, g, st, alpha, \
-                                     (const TX *)x, y, theta_dt, norm2_partial, sb)
+#define AP(D, TX) hipLaunchKernelGGL((k_apply<D, TX>), dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, \
+                                     (const TX *)x, y, theta_dt, norm2_partial)
     if (x_is_float) {
         if (dim == 2) AP(2, float); else AP(3, float);
     } else {
@@ -477,12 +503,11 @@ template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_explicit(LevelDev g, StencilDev st0, const int16_t *__restrict__ alpha,
                                                      const double *__restrict__ U, const double *__restrict__ f0,
                                                      const double *__restrict__ f1, double t_mid, double omt_dt,
-                                                     double dt, double *__restrict__ E, int stage) {
-    const StencilDev st = stage_fast<double>(st0, stage);
-    int i = node_id();
-    if (i >= g.N) return;
+                                                     double dt, double *__restrict__ E) {
+    const StencilDev &st = st0;
     int ix[3];
-    unflatten<DIM>(g, i, ix);
+    int i = tile_node<DIM>(g, ix);
+    if (i < 0) return;
     double e = 0.0;
     if (interior<DIM>(g, ix)) {
         double f = f0[i] + t_mid * f1[i];
@@ -503,27 +528,24 @@ __global__ __launch_bounds__(kBlock) void k_explicit(LevelDev g, StencilDev st0,
 void launch_explicit(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const double *U,
                      const double *f0, const double *f1, double t_mid, double omt_dt, double dt, double *E, int nblocks,
                      hipStream_t s) {
-    int sb = stage_bytes<double>(st);
     if (dim == 2)
-        hipLaunchKernelGGL(k_explicit<2>, dim3(nblocks), dim3(kBlock), sb, s, g, st, alpha, U, f0, f1, t_mid, omt_dt,
-                           dt, E, sb);
+        hipLaunchKernelGGL(k_explicit<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, U, f0, f1, t_mid, omt_dt,
+                           dt, E);
     else
-        hipLaunchKernelGGL(k_explicit<3>, dim3(nblocks), dim3(kBlock), sb, s, g, st, alpha, U, f0, f1, t_mid, omt_dt,
-                           dt, E, sb);
+        hipLaunchKernelGGL(k_explicit<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, U, f0, f1, t_mid, omt_dt,
+                           dt, E);
 }
 
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_residual(LevelDev g, StencilDev st0, const int16_t *__restrict__ alpha,
                                                      const double *__restrict__ V, const double *__restrict__ E,
-                                                     double theta_dt, double *__restrict__ r, double *partial,
-                                                     int stage) {
+                                                     double theta_dt, double *__restrict__ r, double *partial) {
     __shared__ double sh[kBlock / 64];
-    const StencilDev st = stage_fast<double>(st0, stage);
-    int i = node_id();
+    const StencilDev &st = st0;
+    int ix[3];
+    int i = tile_node<DIM>(g, ix);
     double rr = 0.0, vv = 0.0;
-    if (i < g.N) {
-        int ix[3];
-        unflatten<DIM>(g, i, ix);
+    if (i >= 0) {
         double Vi = V[i];
         vv = fabs(Vi);
         if (interior<DIM>(g, ix)) {
@@ -546,13 +568,10 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev g, StencilDev st0,
 
 void launch_residual(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const double *V,
                      const double *E, double theta_dt, double *r, double *partial, int nblocks, hipStream_t s) {
-    int sb = stage_bytes<double>(st);
     if (dim == 2)
-        hipLaunchKernelGGL(k_residual<2>, dim3(nblocks), dim3(kBlock), sb, s, g, st, alpha, V, E, theta_dt, r, partial,
-                           sb);
+        hipLaunchKernelGGL(k_residual<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, V, E, theta_dt, r, partial);
     else
-        hipLaunchKernelGGL(k_residual<3>, dim3(nblocks), dim3(kBlock), sb, s, g, st, alpha, V, E, theta_dt, r, partial,
-                           sb);
+        hipLaunchKernelGGL(k_residual<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, V, E, theta_dt, r, partial);
 }
 
 // number of interior nodes whose control index is outside [0, K)
@@ -560,11 +579,10 @@ template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_bad_policy(LevelDev g, const int16_t *__restrict__ alpha, int K,
                                                        int64_t *partial) {
     __shared__ int64_t sh[kBlock / 64];
-    int i = node_id();
+    int ix[3];
+    int i = tile_node<DIM>(g, ix);
     int64_t bad = 0;
-    if (i < g.N) {
-        int ix[3];
-        unflatten<DIM>(g, i, ix);
+    if (i >= 0) {
         if (interior<DIM>(g, ix)) {
             int k = alpha[i];
             bad = (k < 0 || k >= K) ? 1 : 0;
@@ -577,9 +595,9 @@ __global__ __launch_bounds__(kBlock) void k_bad_policy(LevelDev g, const int16_t
 void launch_bad_policy(int dim, const LevelDev &g, const int16_t *alpha, int K, int64_t *partial, int nblocks,
                        hipStream_t s) {
     if (dim == 2)
-        hipLaunchKernelGGL(k_bad_policy<2>, dim3(nblocks), dim3(kBlock), 0, s, g, alpha, K, partial);
+        hipLaunchKernelGGL(k_bad_policy<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, alpha, K, partial);
     else
-        hipLaunchKernelGGL(k_bad_policy<3>, dim3(nblocks), dim3(kBlock), 0, s, g, alpha, K, partial);
+        hipLaunchKernelGGL(k_bad_policy<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, alpha, K, partial);
 }
 
 // ---- multigrid level kernels ----------------------------------------------------------------------
@@ -588,10 +606,9 @@ void launch_bad_policy(int dim, const LevelDev &g, const int16_t *alpha, int K, 
 template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_diag(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
                                                  double theta_dt, T *__restrict__ d) {
-    int i = node_id();
-    if (i >= g.N) return;
     int ix[3];
-    unflatten<DIM>(g, i, ix);
+    int i = tile_node<DIM>(g, ix);
+    if (i < 0) return;
     if (!interior<DIM>(g, ix)) {
         d[i] = (T)1;
         return;
@@ -634,7 +651,7 @@ __global__ __launch_bounds__(kBlock) void k_diag(LevelDev g, StencilDev st, cons
 template <typename T>
 void launch_diag(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, double theta_dt, T *d,
                  hipStream_t s) {
-    int nb = blocks_for(g.N);
+    int nb = tiles_for(g);
     if (dim == 2)
         hipLaunchKernelGGL((k_diag<2, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, theta_dt, d);
     else
@@ -656,12 +673,11 @@ template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_jacobi(LevelDev g, StencilDev st0, const int16_t *__restrict__ alpha,
                                                    const T *__restrict__ e, const T *__restrict__ r,
                                                    const T *__restrict__ d, T *__restrict__ e_out, T theta_dt, T omega,
-                                                   int first, int stage) {
-    const StencilDev st = stage_fast<T>(st0, stage);
-    int i = node_id();
-    if (i >= g.N) return;
+                                                   int first) {
+    const StencilDev &st = st0;
     int ix[3];
-    unflatten<DIM>(g, i, ix);
+    int i = tile_node<DIM>(g, ix);
+    if (i < 0) return;
     T v = (T)0;
     if (interior<DIM>(g, ix)) {
         if (first) {
@@ -677,25 +693,23 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(LevelDev g, StencilDev st0, c
 template <typename T>
 void launch_jacobi(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const T *e, const T *r,
                    const T *d, T *e_out, double theta_dt, double omega, bool first, hipStream_t s) {
-    int nb = blocks_for(g.N);
-    int sb = first ? 0 : stage_bytes<T>(st);
+    int nb = tiles_for(g);
     if (dim == 2)
-        hipLaunchKernelGGL((k_jacobi<2, T>), dim3(nb), dim3(kBlock), sb, s, g, st, alpha, e, r, d, e_out, (T)theta_dt,
-                           (T)omega, (int)first, sb);
+        hipLaunchKernelGGL((k_jacobi<2, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, e, r, d, e_out, (T)theta_dt,
+                           (T)omega, (int)first);
     else
-        hipLaunchKernelGGL((k_jacobi<3, T>), dim3(nb), dim3(kBlock), sb, s, g, st, alpha, e, r, d, e_out, (T)theta_dt,
-                           (T)omega, (int)first, sb);
+        hipLaunchKernelGGL((k_jacobi<3, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, e, r, d, e_out, (T)theta_dt,
+                           (T)omega, (int)first);
 }
 
 template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_level_residual(LevelDev g, StencilDev st0, const int16_t *__restrict__ alpha,
                                                            const T *__restrict__ e, const T *__restrict__ r,
-                                                           T *__restrict__ res, T theta_dt, int stage) {
-    const StencilDev st = stage_fast<T>(st0, stage);
-    int i = node_id();
-    if (i >= g.N) return;
+                                                           T *__restrict__ res, T theta_dt) {
+    const StencilDev &st = st0;
     int ix[3];
-    unflatten<DIM>(g, i, ix);
+    int i = tile_node<DIM>(g, ix);
+    if (i < 0) return;
     T v = (T)0;
     if (interior<DIM>(g, ix)) v = r[i] - apply_level<DIM, T>(g, st, alpha, e, i, ix, theta_dt);
     res[i] = v;
@@ -704,24 +718,22 @@ __global__ __launch_bounds__(kBlock) void k_level_residual(LevelDev g, StencilDe
 template <typename T>
 void launch_level_residual(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const T *e,
                            const T *r, T *res, double theta_dt, hipStream_t s) {
-    int nb = blocks_for(g.N);
-    int sb = stage_bytes<T>(st);
+    int nb = tiles_for(g);
     if (dim == 2)
-        hipLaunchKernelGGL((k_level_residual<2, T>), dim3(nb), dim3(kBlock), sb, s, g, st, alpha, e, r, res,
-                           (T)theta_dt, sb);
+        hipLaunchKernelGGL((k_level_residual<2, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, e, r, res,
+                           (T)theta_dt);
     else
-        hipLaunchKernelGGL((k_level_residual<3, T>), dim3(nb), dim3(kBlock), sb, s, g, st, alpha, e, r, res,
-                           (T)theta_dt, sb);
+        hipLaunchKernelGGL((k_level_residual<3, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, e, r, res,
+                           (T)theta_dt);
 }
 
 // full weighting: weights 1/4, 1/2, 1/4 per axis around fine node 2I
 template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_restrict(LevelDev gf, LevelDev gc, const T *__restrict__ rf,
                                                      T *__restrict__ rc) {
-    int I = node_id();
-    if (I >= gc.N) return;
     int ix[3];
-    unflatten<DIM>(gc, I, ix);
+    int I = tile_node<DIM>(gc, ix);
+    if (I < 0) return;
     T v = (T)0;
     if (interior<DIM>(gc, ix)) {
         int c = 2 * ix[0] + 2 * ix[1] * (int)gf.s1 + (DIM == 3 ? 2 * ix[2] * (int)gf.s2 : 0);
@@ -748,7 +760,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelDev gf, LevelDev gc, c
 
 template <typename T>
 void launch_restrict(int dim, const LevelDev &gf, const LevelDev &gc, const T *rf, T *rc, hipStream_t s) {
-    int nb = blocks_for(gc.N);
+    int nb = tiles_for(gc);
     if (dim == 2)
         hipLaunchKernelGGL((k_restrict<2, T>), dim3(nb), dim3(kBlock), 0, s, gf, gc, rf, rc);
     else
@@ -759,10 +771,9 @@ void launch_restrict(int dim, const LevelDev &gf, const LevelDev &gc, const T *r
 template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelDev gf, LevelDev gc, const T *__restrict__ ec,
                                                         T *__restrict__ ef) {
-    int i = node_id();
-    if (i >= gf.N) return;
     int ix[3];
-    unflatten<DIM>(gf, i, ix);
+    int i = tile_node<DIM>(gf, ix);
+    if (i < 0) return;
     if (!interior<DIM>(gf, ix)) return;
     int lo[3], hi[3];
     T wl[3], wh[3];
@@ -801,7 +812,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelDev gf, LevelDev gc
 
 template <typename T>
 void launch_prolong_add(int dim, const LevelDev &gf, const LevelDev &gc, const T *ec, T *ef, hipStream_t s) {
-    int nb = blocks_for(gf.N);
+    int nb = tiles_for(gf);
     if (dim == 2)
         hipLaunchKernelGGL((k_prolong_add<2, T>), dim3(nb), dim3(kBlock), 0, s, gf, gc, ec, ef);
     else
@@ -858,10 +869,9 @@ void launch_coarse_solve(int dim, const LevelDev &g, const StencilDev &st, const
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_inject_policy(LevelDev gf, LevelDev gc, const int16_t *__restrict__ af,
                                                           int16_t *__restrict__ ac) {
-    int I = node_id();
-    if (I >= gc.N) return;
     int ix[3];
-    unflatten<DIM>(gc, I, ix);
+    int I = tile_node<DIM>(gc, ix);
+    if (I < 0) return;
     int16_t v = -1;
     if (interior<DIM>(gc, ix)) v = af[2 * ix[0] + 2 * ix[1] * (int)gf.s1 + (DIM == 3 ? 2 * ix[2] * (int)gf.s2 : 0)];
     ac[I] = v;
@@ -869,7 +879,7 @@ __global__ __launch_bounds__(kBlock) void k_inject_policy(LevelDev gf, LevelDev 
 
 void launch_inject_policy(int dim, const LevelDev &gf, const LevelDev &gc, const int16_t *af, int16_t *ac,
                           hipStream_t s) {
-    int nb = blocks_for(gc.N);
+    int nb = tiles_for(gc);
     if (dim == 2)
         hipLaunchKernelGGL(k_inject_policy<2>, dim3(nb), dim3(kBlock), 0, s, gf, gc, af, ac);
     else
@@ -1067,18 +1077,17 @@ void launch_axpy(double *y, double a, const double *x, int64_t N, hipStream_t s)
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_copy_interior(LevelDev g, const double *__restrict__ src,
                                                           double *__restrict__ dst) {
-    int i = node_id();
-    if (i >= g.N) return;
     int ix[3];
-    unflatten<DIM>(g, i, ix);
+    int i = tile_node<DIM>(g, ix);
+    if (i < 0) return;
     if (interior<DIM>(g, ix)) dst[i] = src[i];
 }
 
 void launch_copy_interior(int dim, const LevelDev &g, const double *src, double *dst, hipStream_t s) {
     if (dim == 2)
-        hipLaunchKernelGGL(k_copy_interior<2>, dim3(blocks_for(g.N)), dim3(kBlock), 0, s, g, src, dst);
+        hipLaunchKernelGGL(k_copy_interior<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, src, dst);
     else
-        hipLaunchKernelGGL(k_copy_interior<3>, dim3(blocks_for(g.N)), dim3(kBlock), 0, s, g, src, dst);
+        hipLaunchKernelGGL(k_copy_interior<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, src, dst);
 }
 
 // interior of out = U1 + ratio (U1 - U0): the starting point of a step's policy iteration
@@ -1086,19 +1095,18 @@ template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_extrapolate(LevelDev g, const double *__restrict__ U1,
                                                         const double *__restrict__ U0, double ratio,
                                                         double *__restrict__ out) {
-    int i = node_id();
-    if (i >= g.N) return;
     int ix[3];
-    unflatten<DIM>(g, i, ix);
+    int i = tile_node<DIM>(g, ix);
+    if (i < 0) return;
     if (interior<DIM>(g, ix)) out[i] = U1[i] + ratio * (U1[i] - U0[i]);
 }
 
 void launch_extrapolate(int dim, const LevelDev &g, const double *U1, const double *U0, double ratio, double *out,
                         hipStream_t s) {
     if (dim == 2)
-        hipLaunchKernelGGL(k_extrapolate<2>, dim3(blocks_for(g.N)), dim3(kBlock), 0, s, g, U1, U0, ratio, out);
+        hipLaunchKernelGGL(k_extrapolate<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, U1, U0, ratio, out);
     else
-        hipLaunchKernelGGL(k_extrapolate<3>, dim3(blocks_for(g.N)), dim3(kBlock), 0, s, g, U1, U0, ratio, out);
+        hipLaunchKernelGGL(k_extrapolate<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, U1, U0, ratio, out);
 }
 
 // Zero fill by a kernel (stream-ordered, safe inside captured graphs); exact byte count.

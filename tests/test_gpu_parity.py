@@ -178,3 +178,27 @@ def test_march_c5_small(slhjb):
 def test_march_ragged_no_coarsening(slhjb):
     inst = _toy((30, 27), K=4, P=2, seed=9, c=True)
     _march_compare(slhjb, inst, slhjb.Options(precond=2))
+
+
+def test_vcycle_graph_replays_match_eager(slhjb):
+    """Replayed V-cycle graphs launch the same kernels as the eager path: every replay must give the
+    eager result bit for bit, also with eager work and synchronisations between replays."""
+    inst = workloads.config_c2(129)
+    log("graph replay vs eager")
+    alpha = workloads.random_policy(inst, 21)
+    U, _ = workloads.random_fields(inst, seed=22)
+    V0 = U.copy()
+    V0[inst.boundary_mask()] = inst.psi[inst.boundary_mask()]
+    args = (to_dev(alpha), to_dev(U), to_dev(inst.f0), to_dev(inst.f1), 0.1, 1.0 / 64, 0.5, 1.0)
+    outs = []
+    for use_graphs in (0, 1, 1, 1):
+        solver = slhjb.Solver.from_instance(inst, slhjb.Options(precision=1, use_graphs=use_graphs))
+        for rep in range(2):
+            dX = to_dev(V0)
+            st = solver.linsolve(*args, dX)
+            torch.cuda.synchronize()
+            outs.append(to_np(dX))
+            _ = (dX * 2.0).sum().item()   # unrelated eager work between replays
+        solver.close()
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])

@@ -23,7 +23,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 
 
 def parse():
@@ -89,16 +90,43 @@ def run_mode(slhjb, inst, torch, mode, steps, warmup, args):
     gpu_ms = ev0.elapsed_time(ev1)
     kern = {}
     for k, name in slhjb.KERNEL_NAMES.items():
-        n, ms, by = solver.profile_read(k)
+        n, ms, by, fl = solver.profile_read(k)
         if n:
             kern[name] = dict(launches=n, total_ms=ms, avg_us=1e3 * ms / n, bytes_per_launch=by / n,
-                              gbs=(by / n) / (1e-3 * ms / n) / 1e9)
+                              gbs=(by / n) / (1e-3 * ms / n) / 1e9, flops_per_launch=fl / n,
+                              tflops=(fl / n) / (1e-3 * ms / n) / 1e12)
     solver.close()
     pi = sum(s[0] for s in stats)
     kry = sum(s[1] for s in stats)
     return dict(mode=mode, wall_s=wall, gpu_ms=gpu_ms, steps_per_s=steps / wall, ms_per_step=1e3 * wall / steps,
                 pi_per_step=pi / steps, krylov_per_solve=kry / max(pi, 1), max_res=max(s[2] for s in stats),
                 max_cert=max(s[3] for s in stats), kernels=kern, U=Ua)
+
+
+def measured_traffic(kernel, pi_per_step):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, scaled by
+    the copy-kernel calibration recorded there; None when the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "h2049_hbm_traffic.json")
+    src = os.path.join(ROOT, "paper_1605_04821_amd", "csrc", "slhjb_kernels.hip")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    per = rec["per_dispatch"]
+    tot = lambda name: per[name]["read_bytes"] + per[name]["write_bytes"]
+    if kernel == "sweep":
+        # timed Crank-Nicolson steps: one search storing the explicit part, then pi_per_step reading it
+        a = [k for k in per if "k_sweep<2, true, false, 1>" in k]
+        b = [k for k in per if "k_sweep<2, true, false, 2>" in k]
+        if not a or not b:
+            return None
+        return (tot(a[0]) + pi_per_step * tot(b[0])) / (1.0 + pi_per_step)
+    names = {"apply": "k_apply<2, float>", "smooth": "k_jacobi<2, float>", "mg_residual": "k_level_residual<2, float>"}
+    hit = [k for k in per if names.get(kernel, "?") in k]
+    return tot(hit[0]) if hit else None
 
 
 def cpu_baseline(inst, budget_s, pi_per_step):
@@ -179,9 +207,8 @@ def main():
     inst = workloads.config_h(n=args.n)
     modes = [m for m in args.modes.split(",") if m]
     if args.calibrate_copy:
-        a = torch.ones(1 << 25, dtype=torch.float64, device="cuda")   # 2^28 bytes
-        b = torch.empty_like(a)
-        b.copy_(a)
+        a = torch.ones(1 << 25, dtype=torch.float64, device="cuda")   # written: 2^28 bytes
+        b = a + 1.0                                                   # read 2^28, written 2^28 bytes
         torch.cuda.synchronize()
         del a, b
     res = {}
@@ -202,9 +229,18 @@ def main():
     kern = head["kernels"]
     dom_name = max(kern, key=lambda k: kern[k]["total_ms"])
     dom = kern[dom_name]
-    roof = {"bound": "hbm", "kernel": dom_name, "achieved": round(dom["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
-            "avg_us": round(dom["avg_us"], 2), "bytes_per_launch": dom["bytes_per_launch"]}
+    if dom_name == "sweep":
+        # the search does K interpolated stencil evaluations per node: FP64 arithmetic against the vector peak
+        roof = {"bound": "alu", "kernel": dom_name, "achieved": round(dom["tflops"], 3),
+                "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(dom["tflops"] / FP64_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": None, "avg_us": round(dom["avg_us"], 2), "flops_per_launch": dom["flops_per_launch"]}
+    else:
+        roof = {"bound": "hbm", "kernel": dom_name, "achieved": round(dom["gbs"], 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_us": round(dom["avg_us"], 2), "bytes_per_launch": dom["bytes_per_launch"]}
+    roof["traffic"] = measured_traffic(dom_name, head["pi_per_step"])
+    stencil_roof = {k: {"achieved_gbs": round(kern[k]["gbs"], 1), "frac": round(kern[k]["gbs"] / HBM_PEAK_GBS, 4),
+                        "avg_us": round(kern[k]["avg_us"], 2)} for k in ("apply", "smooth", "mg_residual") if k in kern}
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
@@ -228,6 +264,7 @@ def main():
         "kernels": {m: {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                         for k, v in res[m]["kernels"].items()} for m in res},
         "roofline": roof,
+        "stencil_kernels_hbm": stencil_roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

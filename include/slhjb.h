@@ -174,8 +174,10 @@ int hjb_solve(hjb_handle *hd, const double *g, const double *psi, const double *
    (e.g. a benchmark's roofline) enables a timer; each launch of that class is then bracketed by HIP events
    on the handle's stream (at most max_launches launches are recorded; enable again to reset).
    hjb_profile_read synchronises the stream and reports the recorded launches, their summed duration in
-   milliseconds and their summed algorithmic bytes (each input element read once, each output written
-   once; halo re-reads of gathered stencil points are not counted). */
+   milliseconds, their summed algorithmic bytes (each input element read once, each output written
+   once; halo re-reads of gathered stencil points are not counted) and, for the policy search, their
+   summed algorithmic FP64 operations on interior nodes (untruncated stencil arithmetic; 0 otherwise).
+   Enabling a timer of the smoother or the multigrid residual makes V-cycles launch eagerly. */
 enum {
     HJB_KERNEL_APPLY = 0,     /* y = A^alpha z in FGMRES (FP64 out; z FP64 or FP32) */
     HJB_KERNEL_SMOOTH = 1,    /* damped Jacobi sweep with stencil gathers on the finest level */
@@ -186,7 +188,8 @@ enum {
     HJB_KERNEL_COUNT = 6
 };
 int hjb_profile_enable(hjb_handle *hd, int32_t kernel, int32_t max_launches);
-int hjb_profile_read(hjb_handle *hd, int32_t kernel, int64_t *launches, double *total_ms, double *total_bytes);
+int hjb_profile_read(hjb_handle *hd, int32_t kernel, int64_t *launches, double *total_ms, double *total_bytes,
+                     double *total_flops);
 
 /* Free the handle and its device workspace (NULL is ignored). */
 void hjb_destroy(hjb_handle *hd);

@@ -78,7 +78,7 @@ def _load():
     L.hjb_step.argtypes = [vp, vp, vp, vp, vp, d, d, d, d, vp, vp, d, ctypes.POINTER(StepStats)]
     L.hjb_solve.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, d, vp, vp, ctypes.POINTER(SolveStats)]
     L.hjb_profile_enable.argtypes = [vp, i32, i32]
-    L.hjb_profile_read.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(d), ctypes.POINTER(d)]
+    L.hjb_profile_read.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d)]
     L.hjb_destroy.argtypes = [vp]
     L.hjb_destroy.restype = None
     L.hjb_last_error.argtypes = []
@@ -239,12 +239,14 @@ class Solver:
         _check(_lib.hjb_profile_enable(self._h, int(kernel), int(max_launches)))
 
     def profile_read(self, kernel: int):
-        """(launches, total_ms, total_algorithmic_bytes) recorded since profile_enable."""
+        """(launches, total_ms, algorithmic_bytes, algorithmic_flops) recorded since profile_enable."""
         n = ctypes.c_int64(0)
         ms = ctypes.c_double(0.0)
         by = ctypes.c_double(0.0)
-        _check(_lib.hjb_profile_read(self._h, int(kernel), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
-        return int(n.value), float(ms.value), float(by.value)
+        fl = ctypes.c_double(0.0)
+        _check(_lib.hjb_profile_read(self._h, int(kernel), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by),
+                                     ctypes.byref(fl)))
+        return int(n.value), float(ms.value), float(by.value), float(fl.value)
 
     def solve(self, g, psi, f0, f1, dts, thetas, s, U_final, policies=None) -> SolveStats:
         self._sync_stream()

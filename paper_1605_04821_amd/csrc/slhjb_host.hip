@@ -80,7 +80,7 @@ struct hjb_handle {
     double *E = nullptr, *R = nullptr, *Vb = nullptr, *Zb = nullptr;
     double *Ua = nullptr, *Ub = nullptr, *Uc = nullptr;
     int16_t *a0 = nullptr, *a1 = nullptr, *acarry = nullptr;
-    double *Q = nullptr;        // [K][N] explicit part of G for the searches of one step (or null)
+    double *Q = nullptr;        // [K][blocks][kBlock] explicit part of G for the searches of one step (or null)
     double *partial = nullptr;  // >= max(3*nb, (m+2)*nbd)
     double *dvals = nullptr;    // device scalars / small vectors [256]
     int64_t *ipartial = nullptr, *ival = nullptr;
@@ -96,10 +96,11 @@ struct hjb_handle {
     };
     std::vector<VGraph> vgraphs;
     hipStream_t capture_stream = nullptr;
+    hipEvent_t sync_ev = nullptr;  // polled to wait for small read-backs
     struct Timer {
         int cap = 0, used = 0;
         std::vector<hipEvent_t> ev;  // 2*cap events
-        std::vector<double> bytes;
+        std::vector<double> bytes, flops;
     } timers[HJB_KERNEL_COUNT];
 };
 
@@ -110,12 +111,13 @@ struct TimedLaunch {
     hjb_handle *hd;
     int id;
     int slot = -1;
-    TimedLaunch(hjb_handle *h, int i, double bytes) : hd(h), id(i) {
+    TimedLaunch(hjb_handle *h, int i, double bytes, double flops = 0.0) : hd(h), id(i) {
         if (id < 0) return;
         auto &T = hd->timers[id];
         if (T.used < T.cap) {
             slot = T.used++;
             T.bytes[slot] = bytes;
+            T.flops[slot] = flops;
             (void)hipEventRecord(T.ev[2 * slot], hd->stream);
         }
     }
@@ -427,10 +429,19 @@ int precondition(hjb_handle *hd, const double *v, void *z, double theta_dt) {
 
 // ---- flexible GMRES(m) on A^alpha x = b, with x = X on interior nodes ----------------------------
 
+// Wait for the work queued so far by polling an event (a small result is read back right after).
+int wait_stream(hjb_handle *hd) {
+    HIPCHK(hipEventRecord(hd->sync_ev, hd->stream));
+    for (;;) {
+        hipError_t e = hipEventQuery(hd->sync_ev);
+        if (e == hipSuccess) return HJB_OK;
+        if (e != hipErrorNotReady) return fail(HJB_EDEVICE, "hipEventQuery: %s", hipGetErrorString(e));
+    }
+}
+
 int sync_small(hjb_handle *hd, const void *dev, void *host, size_t bytes) {
     HIPCHK(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, hd->stream));
-    HIPCHK(hipStreamSynchronize(hd->stream));
-    return HJB_OK;
+    return wait_stream(hd);
 }
 
 // Stops when |r|_inf <= rtol_inf*max(1,|X|_inf), or, when eta > 0, once |r|_inf <= eta * (initial |r|_inf).
@@ -496,7 +507,7 @@ int fgmres(hjb_handle *hd, const int16_t *alpha, const double *E, double *X, dou
                     launch_multiaxpy_scale(w, V, N, j + 1, dv + 16, N, hd->nbd, s);
                 }
                 HIPCHK(hipMemcpyAsync(hp + 16, dv + 16, (size_t)(j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
-                HIPCHK(hipStreamSynchronize(s));
+                TRY(wait_stream(hd));
                 double w2 = hp[16 + j + 1], h2 = 0.0;
                 for (int i = 0; i <= j; ++i) h2 += hp[16 + i] * hp[16 + i];
                 double hn2 = w2 - h2;
@@ -590,22 +601,29 @@ int sweep(hjb_handle *hd, const double *X, const double *U, const double *f0, co
     double inv2h = 0.5 / hd->desc.h;
     double coefA = 2.0 * hd->M * inv2h + hd->cmax;
     hipLaunchKernelGGL(k_tau, dim3(1), dim3(256), 0, s, hd->partial, hd->nb, coefA, hd->desc.tau_rel, hd->dvals + 4);
-    // the sweep takes tau by value: read it back (one small synchronisation per search)
-    HIPCHK(hipMemcpyAsync(hd->hpin + 4, hd->dvals + 4, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    double tau = hd->hpin[4];
     SweepOut o{a_out, gmin, margin, ties, hd->ipartial};
-    TimedLaunch tl(hd, HJB_KERNEL_SWEEP, (double)hd->N * (4 * 8.0 + 2.0 + 2.0));
     if (!hd->Q) qmode = 0;
-    launch_sweep(hd->dim, L0.g, stencil(hd, 0), X, U, f0, f1, t_mid, theta, tau, a_in, o, hd->Q, qmode, hd->nb, s);
+    // algorithmic FP64 work of the untruncated stencil per control and field: each point is a 2^d-corner
+    // weighted sum (2^(d+1) - 1 flops), each diffusion pair adds 4, the drift 3, the 1/(2h) scaling 1
+    const int P = hd->desc.P, dpts = 2 * P + (hd->has_drift ? 1 : 0);
+    const double per_field = dpts * ((2 << hd->dim) - 1) + 4.0 * P + (hd->has_drift ? 3.0 : 0.0) + 1.0;
+    const bool cn = theta != 1.0;
+    const double per_ctl = per_field + 5.0 + ((cn && qmode != 2) ? per_field + 3.0 : 0.0);
+    double n_int = 1.0;
+    for (int a = 0; a < hd->dim; ++a) n_int *= (double)(hd->desc.n[a] - 2);
+    TimedLaunch tl(hd, HJB_KERNEL_SWEEP, (double)hd->N * (4 * 8.0 + 2.0 + 2.0) + (qmode == 2 ? n_int * 8.0 * hd->desc.K : 0.0),
+                   n_int * (hd->desc.K * per_ctl + 2.0));
+    launch_sweep(hd->dim, L0.g, stencil(hd, 0), X, U, f0, f1, t_mid, theta, hd->dvals + 4, a_in, o, hd->Q, qmode,
+                 hd->nb, s);
     HIPCHK(hipGetLastError());
-    if (n_changed) {
+    if (n_changed || tau_used) {
         launch_reduce_sum_i64(hd->ipartial, hd->nb, hd->ival, s);
         HIPCHK(hipMemcpyAsync(hd->hpin_i, hd->ival, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        *n_changed = hd->hpin_i[0];
+        HIPCHK(hipMemcpyAsync(hd->hpin + 4, hd->dvals + 4, sizeof(double), hipMemcpyDeviceToHost, s));
+        TRY(wait_stream(hd));
+        if (n_changed) *n_changed = hd->hpin_i[0];
+        if (tau_used) *tau_used = hd->hpin[4];
     }
-    if (tau_used) *tau_used = tau;
     return HJB_OK;
 }
 
@@ -855,7 +873,7 @@ int hjb_setup(const hjb_desc *desc, hjb_handle **out) {
     STRY(dalloc(hd, (void **)&hd->acarry, N * 2));
     {
         // cache of the explicit part of the search values (K doubles per node) when it is affordable
-        size_t qbytes = (size_t)d.K * (size_t)N * 8;
+        size_t qbytes = (size_t)d.K * (size_t)hd->nb * kBlock * 8;  // tile-major, one slot per thread
         size_t freeb = 0, totalb = 0;
         if (hipMemGetInfo(&freeb, &totalb) == hipSuccess && qbytes <= freeb / 4 && qbytes <= ((size_t)16 << 30)) {
             void *p = nullptr;
@@ -882,6 +900,10 @@ int hjb_setup(const hjb_desc *desc, hjb_handle **out) {
         if (e != hipSuccess) return cleanup_fail(fail(HJB_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e)));
         e = hipHostMalloc((void **)&hd->hpin_i, 8 * sizeof(int64_t), hipHostMallocDefault);
         if (e != hipSuccess) return cleanup_fail(fail(HJB_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e)));
+    }
+    {
+        hipError_t e = hipEventCreateWithFlags(&hd->sync_ev, hipEventDisableTiming);
+        if (e != hipSuccess) return cleanup_fail(fail(HJB_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e)));
     }
     STRY(build_tables(hd, 1.0));
 #undef STRY
@@ -1040,26 +1062,30 @@ int hjb_profile_enable(hjb_handle *hd, int32_t kernel, int32_t max_launches) {
         T.ev.push_back(e);
     }
     T.bytes.assign((size_t)max_launches, 0.0);
+    T.flops.assign((size_t)max_launches, 0.0);
     T.cap = max_launches;
     T.used = 0;
     return HJB_OK;
 }
 
-int hjb_profile_read(hjb_handle *hd, int32_t kernel, int64_t *launches, double *total_ms, double *total_bytes) {
+int hjb_profile_read(hjb_handle *hd, int32_t kernel, int64_t *launches, double *total_ms, double *total_bytes,
+                     double *total_flops) {
     if (!hd) return fail(HJB_EINVAL, "null handle");
     if (kernel < 0 || kernel >= HJB_KERNEL_COUNT) return fail(HJB_EINVAL, "unknown kernel id %d", kernel);
     auto &T = hd->timers[kernel];
     HIPCHK(hipStreamSynchronize(hd->stream));
-    double ms = 0.0, by = 0.0;
+    double ms = 0.0, by = 0.0, fl = 0.0;
     for (int q = 0; q < T.used; ++q) {
         float t = 0.f;
         HIPCHK(hipEventElapsedTime(&t, T.ev[2 * q], T.ev[2 * q + 1]));
         ms += t;
         by += T.bytes[q];
+        fl += T.flops[q];
     }
     if (launches) *launches = T.used;
     if (total_ms) *total_ms = ms;
     if (total_bytes) *total_bytes = by;
+    if (total_flops) *total_flops = fl;
     return HJB_OK;
 }
 
@@ -1067,6 +1093,7 @@ void hjb_destroy(hjb_handle *hd) {
     if (!hd) return;
     drop_graphs(hd);
     if (hd->capture_stream) (void)hipStreamDestroy(hd->capture_stream);
+    if (hd->sync_ev) (void)hipEventDestroy(hd->sync_ev);
     for (auto &T : hd->timers)
         for (hipEvent_t e : T.ev) (void)hipEventDestroy(e);
     if (hd->stream) (void)hipStreamSynchronize(hd->stream);

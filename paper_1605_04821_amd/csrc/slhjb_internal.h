@@ -68,9 +68,9 @@ struct SweepOut {
 };
 
 // qmode: 0 evaluate the explicit part (theta < 1) or skip it (theta = 1); 1 evaluate it and store
-// Q[k*N + i] = (1-theta)((L^k U)_i + c_k U_i); 2 read it from Q.
+// (1-theta)((L^k U)_i + c_k U_i) in Q (K * blocks * kBlock doubles, tile-major); 2 read it from Q.
 void launch_sweep(int dim, const LevelDev &g, const StencilDev &st, const double *X, const double *U,
-                  const double *f0, const double *f1, double t_mid, double theta, double tau,
+                  const double *f0, const double *f1, double t_mid, double theta, const double *tau,
                   const int16_t *a_in, const SweepOut &o, double *Q, int qmode, int nblocks, hipStream_t s);
 
 void launch_norms_xuf(int dim, const LevelDev &g, const double *X, const double *U, const double *f0,

@@ -307,7 +307,8 @@ struct OpMax {
 // ---- policy search (Howard's algorithm, eq. nonlinear_sys) ----------------------------------------
 
 // G_k at node i.  QM 0: explicit part evaluated (theta < 1) or absent (theta = 1); QM 1: evaluated and
-// stored in Q; QM 2: read from Q.  All three round identically.
+// stored in Q; QM 2: read from Q.  All three round identically.  Q is tile-major: entry (k, block, lane)
+// at (k * blocks + block) * kBlock + lane, so each wavefront moves whole aligned cache lines.
 template <int DIM, bool CN, int QM>
 __device__ __forceinline__ double eval_G(const LevelDev &g, const StencilDev &st, int k, int i, const int ix[3],
                                          bool deep, const double *__restrict__ X, double Xi,
@@ -318,14 +319,14 @@ __device__ __forceinline__ double eval_G(const LevelDev &g, const StencilDev &st
     double q;
     if (CN && QM == 2) {
         lx = lhat1<DIM, double, double>(g, st, k, i, ix, deep, X, Xi);
-        q = Q[(int64_t)k * g.N + i];
+        q = Q[((int64_t)k * gridDim.x + remap_block(blockIdx.x, gridDim.x)) * kBlock + threadIdx.x];
     } else {
         if (CN)
             lhat_node<DIM, double, double, true>(g, st, k, i, ix, deep, X, Xi, U, Ui, lx, lu);
         else
             lx = lhat1<DIM, double, double>(g, st, k, i, ix, deep, X, Xi);
         q = omt * (lu + ck * Ui);
-        if (CN && QM == 1) Q[(int64_t)k * g.N + i] = q;
+        if (CN && QM == 1) Q[((int64_t)k * gridDim.x + remap_block(blockIdx.x, gridDim.x)) * kBlock + threadIdx.x] = q;
     }
     return theta * (lx + ck * Xi) + q + f;
 }
@@ -334,9 +335,10 @@ template <int DIM, bool CN, bool EXTRA, int QM>
 __global__ __launch_bounds__(kBlock) void k_sweep(LevelDev g, StencilDev st, const double *__restrict__ X,
                                                   const double *__restrict__ U, const double *__restrict__ f0,
                                                   const double *__restrict__ f1, double t_mid, double theta,
-                                                  double tau, const int16_t *__restrict__ a_in, SweepOut o,
-                                                  double *__restrict__ Q) {
+                                                  const double *__restrict__ tau_p, const int16_t *__restrict__ a_in,
+                                                  SweepOut o, double *__restrict__ Q) {
     __shared__ int64_t sh[kBlock / 64];
+    const double tau = tau_p[0];  // written by the tolerance kernel just before
     int ix[3];
     int i = tile_node<DIM>(g, ix);
     int64_t changed = 0;
@@ -404,7 +406,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(LevelDev g, StencilDev st, con
 
 template <int DIM>
 void launch_sweep_dim(const LevelDev &g, const StencilDev &st, const double *X, const double *U, const double *f0,
-                      const double *f1, double t_mid, double theta, double tau, const int16_t *a_in,
+                      const double *f1, double t_mid, double theta, const double *tau, const int16_t *a_in,
                       const SweepOut &o, double *Q, int qmode, int nblocks, hipStream_t s) {
     bool cn = theta != 1.0;
     bool extra = o.margin != nullptr || o.ties != nullptr;
@@ -423,8 +425,8 @@ void launch_sweep_dim(const LevelDev &g, const StencilDev &st, const double *X, 
 }
 
 void launch_sweep(int dim, const LevelDev &g, const StencilDev &st, const double *X, const double *U,
-                  const double *f0, const double *f1, double t_mid, double theta, double tau, const int16_t *a_in,
-                  const SweepOut &o, double *Q, int qmode, int nblocks, hipStream_t s) {
+                  const double *f0, const double *f1, double t_mid, double theta, const double *tau,
+                  const int16_t *a_in, const SweepOut &o, double *Q, int qmode, int nblocks, hipStream_t s) {
     if (dim == 2)
         launch_sweep_dim<2>(g, st, X, U, f0, f1, t_mid, theta, tau, a_in, o, Q, qmode, nblocks, s);
     else

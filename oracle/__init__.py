@@ -426,3 +426,68 @@ def brute_force_step(pb: Problem, Uprev, psi, f0, f1, t_prev, dt, theta):
     V = Vb.copy()
     V[I] = best
     return V
+
+
+# ---------------------------------------------------------------------------
+# Adjoint at fixed policies (the discrete adjoint of eq. FullScheme, transposed)
+# ---------------------------------------------------------------------------
+
+def fixed_policy_march(inst, policies, s: Optional[float] = None, rtol=1e-15):
+    """U^0..U^N of the theta-scheme with the given per-step policies (one linear solve per step)."""
+    pb = Problem(inst, s=s)
+    U = _f64(inst.g).copy()
+    out = [U.copy()]
+    t = 0.0
+    for n in range(len(policies)):
+        dt, th = float(inst.dts[n]), float(inst.thetas[n])
+        alpha = np.ascontiguousarray(policies[n], dtype=np.int16)
+        f = pb.f_at(inst.f0, inst.f1, t + th * dt)
+        L = pb.assemble(alpha)
+        E = explicit_part(pb, L, alpha, U, f, dt, th)
+        V = U.copy()
+        V[pb.bd] = inst.psi[pb.bd]
+        V, _ = linear_solve(pb, L, alpha, V, E, dt, th, rtol=rtol)
+        U = V
+        out.append(U.copy())
+        t = t + dt
+    return out
+
+
+def adjoint_dense(inst, policies, lam_N, s: Optional[float] = None):
+    """Gradients of a functional J of U^N with dJ/dU^N = lam_N, at fixed policies.
+
+    Step n solves A_n U^n = B_n U^{n-1} + dt f_n + (Dirichlet terms), A_n = I - theta dt (L + C) on interior
+    unknowns, B_n = I + (1-theta) dt (L + C) applied to the full U^{n-1}.  Backwards: A_n^T mu_n = lam_n,
+    dJ/df0 += dt mu_n, dJ/df1 += dt t_mid mu_n, lam_{n-1} = B_n^T mu_n; dJ/dg = lam_0 (all nodes).
+    """
+    pb = Problem(inst, s=s)
+    I = pb.interior
+    N = pb.N
+    lam = _f64(lam_N).copy()
+    lam[pb.bd] = 0.0
+    df0 = np.zeros(N)
+    df1 = np.zeros(N)
+    times = np.concatenate([[0.0], np.cumsum(inst.dts)])
+    for n in reversed(range(len(policies))):
+        dt, th = float(inst.dts[n]), float(inst.thetas[n])
+        t_mid = float(times[n]) + th * dt
+        alpha = np.ascontiguousarray(policies[n], dtype=np.int16)
+        L = pb.assemble(alpha).tocsr()
+        c = pb.c_of(alpha)
+        A = _system_matrix(pb, L, alpha, dt, th)
+        mu = np.zeros(N)
+        mu[I] = spla.spsolve(A.T.tocsc(), lam[I])
+        df0 += dt * mu
+        df1 += dt * t_mid * mu
+        lam_new = np.zeros(N)
+        lam_new[I] = mu[I] + (1.0 - th) * dt * c[I] * mu[I]
+        lam_new += (1.0 - th) * dt * (L[I].T @ mu[I])
+        lam = lam_new
+    return dict(df0=df0, df1=df1, dg=lam)
+
+
+def ds_central_difference(inst, policies, lam_N, s: float, eps: float = 1e-5):
+    """d/ds of lam_N . U^N(s) at fixed policies by a central difference of the fixed-policy march."""
+    up = fixed_policy_march(inst, policies, s=s + eps)[-1]
+    dn = fixed_policy_march(inst, policies, s=s - eps)[-1]
+    return float(np.dot(lam_N, up - dn) / (2.0 * eps))

@@ -23,8 +23,8 @@ PREC_FP64, PREC_MIXED = 0, 1
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_VCYCLE = 0, 1, 2
 
 EXPORTED = ["hjb_desc_default", "hjb_setup", "hjb_set_stream", "hjb_set_options", "hjb_policy_sweep", "hjb_apply",
-            "hjb_linsolve", "hjb_step", "hjb_solve", "hjb_profile_enable", "hjb_profile_read", "hjb_destroy",
-            "hjb_last_error"]
+            "hjb_linsolve", "hjb_step", "hjb_solve", "hjb_adjoint", "hjb_apply_transposed", "hjb_profile_enable",
+            "hjb_profile_read", "hjb_destroy", "hjb_last_error"]
 KERNEL_APPLY, KERNEL_SMOOTH, KERNEL_MG_RESID, KERNEL_DOT, KERNEL_AXPY, KERNEL_SWEEP = range(6)
 KERNEL_NAMES = {KERNEL_APPLY: "apply", KERNEL_SMOOTH: "smooth", KERNEL_MG_RESID: "mg_residual",
                 KERNEL_DOT: "multidot", KERNEL_AXPY: "multiaxpy", KERNEL_SWEEP: "sweep"}
@@ -59,6 +59,11 @@ class SolveStats(ctypes.Structure):
                 ("pi_total", ctypes.c_int64), ("max_cert_bound", ctypes.c_double)]
 
 
+class AdjointStats(ctypes.Structure):
+    _fields_ = [("krylov_recompute", ctypes.c_int64), ("krylov_adjoint", ctypes.c_int64),
+                ("max_res_adjoint", ctypes.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libslhjb.so not built ({LIB_PATH}); run __graft_entry__.build() or "
@@ -77,6 +82,9 @@ def _load():
     L.hjb_linsolve.argtypes = [vp, vp, vp, vp, vp, d, d, d, d, vp, ctypes.POINTER(StepStats)]
     L.hjb_step.argtypes = [vp, vp, vp, vp, vp, d, d, d, d, vp, vp, d, ctypes.POINTER(StepStats)]
     L.hjb_solve.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, d, vp, vp, ctypes.POINTER(SolveStats)]
+    L.hjb_adjoint.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, d, vp, vp, vp, vp, vp, ctypes.POINTER(d),
+                              ctypes.POINTER(AdjointStats)]
+    L.hjb_apply_transposed.argtypes = [vp, vp, vp, vp, d, d, d]
     L.hjb_profile_enable.argtypes = [vp, i32, i32]
     L.hjb_profile_read.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d)]
     L.hjb_destroy.argtypes = [vp]
@@ -234,6 +242,24 @@ class Solver:
                              ctypes.byref(st)))
         return st
 
+    def apply_transposed(self, alpha, x, y, dt, theta, s=1.0):
+        self._sync_stream()
+        _check(_lib.hjb_apply_transposed(self._h, _ptr(alpha), _ptr(x), _ptr(y), float(dt), float(theta), float(s)))
+
+    def adjoint(self, g, psi, f0, f1, dts, thetas, s, policies, dJ_dUN, dJ_df0, dJ_dg, dJ_df1=None,
+                want_ds=True):
+        """hjb_adjoint at fixed policies; returns (dJ/ds or None, AdjointStats)."""
+        self._sync_stream()
+        dts = np.ascontiguousarray(dts, dtype=np.float64)
+        thetas = np.ascontiguousarray(thetas, dtype=np.float64)
+        st = AdjointStats()
+        ds = ctypes.c_double(0.0)
+        _check(_lib.hjb_adjoint(self._h, _ptr(g), _ptr(psi), _ptr(f0), _ptr(f1), int(len(dts)), dts.ctypes.data,
+                                thetas.ctypes.data, float(s), _ptr(policies), _ptr(dJ_dUN), _ptr(dJ_df0),
+                                _ptr(dJ_df1), _ptr(dJ_dg), ctypes.byref(ds) if want_ds else None,
+                                ctypes.byref(st)))
+        return (float(ds.value) if want_ds else None), st
+
     def profile_enable(self, kernel: int, max_launches: int = 4096):
         self._sync_stream()
         _check(_lib.hjb_profile_enable(self._h, int(kernel), int(max_launches)))
@@ -257,3 +283,41 @@ class Solver:
                               dts.ctypes.data, thetas.ctypes.data, float(s), _ptr(U_final), _ptr(policies),
                               ctypes.byref(st)))
         return st
+
+
+def _autograd_function():
+    import torch
+
+    class HJBMarch(torch.autograd.Function):
+        """U^N = march(g, f0, f1, s) as a differentiable function; the backward pass is the discrete
+        adjoint at the forward policies (hjb_adjoint)."""
+
+        @staticmethod
+        def forward(ctx, g, f0, f1, s, solver, psi, dts, thetas):
+            N = g.numel()
+            U = torch.empty_like(g)
+            pol = torch.empty((len(dts), N), dtype=torch.int16, device=g.device)
+            solver.solve(g, psi, f0, f1, dts, thetas, float(s), U, pol)
+            ctx.save_for_backward(g, f0, f1, psi, pol)
+            ctx.meta = (solver, float(s), np.asarray(dts, np.float64), np.asarray(thetas, np.float64))
+            return U
+
+        @staticmethod
+        def backward(ctx, gU):
+            g, f0, f1, psi, pol = ctx.saved_tensors
+            solver, s, dts, thetas = ctx.meta
+            df0, df1, dg = torch.empty_like(g), torch.empty_like(g), torch.empty_like(g)
+            ds, _ = solver.adjoint(g, psi, f0, f1, dts, thetas, s, pol, gU.contiguous(), df0, dg, dJ_df1=df1)
+            dsv = torch.tensor(ds, dtype=torch.float64, device=g.device)
+            return dg, df0, df1, dsv, None, None, None, None
+
+    return HJBMarch
+
+
+def hjb_march(solver: Solver, g, psi, f0, f1, dts, thetas, s):
+    """Differentiable march: returns U^N; gradients flow to g, f0, f1 and s (a 0-d FP64 tensor or float)."""
+    import torch
+    F = _autograd_function()
+    if not torch.is_tensor(s):
+        s = torch.tensor(float(s), dtype=torch.float64, device=g.device)
+    return F.apply(g, f0, f1, s, solver, psi, dts, thetas)

@@ -1,0 +1,456 @@
+// Adjoint kernels of libslhjb: the transposed operator of eq. FullScheme at a fixed policy and the
+// derivative of the operator with respect to the volatility scale s.
+//
+// Transposition.  The rows of L-hat^alpha (eq. Lhat: for each stencil point, its truncation weight
+// times the corner weights of eq. monotone_int, plus the diagonal) are emitted into fixed slots
+// (node i, entry e) and stably sorted by column.  The transposed product then gathers, for each
+// column j, the entries of the rows that reference j in increasing row order: deterministic, no
+// atomics.
+//
+// s-derivative.  Diffusion displacements are Y = s*sigma/sqrt(h) (drift points do not depend on s).
+// The operator is evaluated with forward-mode dual numbers along the same landing rules as the
+// forward kernels, so the derivative includes how truncation (mu, A_p, B_p of Prop. pro:scheme2)
+// changes with s; it is the one-sided derivative at the (measure-zero) kinks of floor and min.
+
+#include <hipcub/hipcub.hpp>
+
+#include "slhjb_internal.h"
+
+namespace slhjb {
+
+__device__ __forceinline__ int remap_block_a(int b, int nb) {
+    int q = nb >> 3, r = nb & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+template <int DIM>
+__device__ __forceinline__ int tile_node_a(const LevelDev &g, int ix[3]) {
+    int b = remap_block_a(blockIdx.x, gridDim.x);
+    int bx = b % g.ntx, r = b / g.ntx;
+    int by = DIM == 3 ? r % g.nty : r;
+    int bz = DIM == 3 ? r / g.nty : 0;
+    ix[0] = bx * kTX + (int)(threadIdx.x % kTX);
+    ix[1] = by * kTY + (int)(threadIdx.x / kTX);
+    ix[2] = bz;
+    if (ix[0] >= g.n[0] || ix[1] >= g.n[1]) return -1;
+    return ix[0] + ix[1] * (int)g.s1 + (DIM == 3 ? ix[2] * (int)g.s2 : 0);
+}
+
+template <int DIM>
+__device__ __forceinline__ bool interior_a(const LevelDev &g, const int ix[3]) {
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) ok = ok && ix[d] > 0 && ix[d] < g.n[d] - 1;
+    return ok;
+}
+
+// ---- dual numbers ---------------------------------------------------------------------------------
+
+struct Dual {
+    double v, d;
+};
+__device__ __forceinline__ Dual dmk(double v, double d) { return Dual{v, d}; }
+__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+__device__ __forceinline__ Dual operator/(Dual a, Dual b) {
+    return {a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)};
+}
+
+// landing of x_i + mu*Y with the forward kernels' rules, carrying d/ds (dY = Y/s for diffusion points)
+template <int DIM>
+__device__ Dual landing_dual(const LevelDev &g, const int ix[3], const double Y[3], const double dY[3], int cell[3],
+                             Dual t[3]) {
+    Dual m[3];
+    Dual mu = dmk(1.0, 0.0);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        m[d] = dmk(__builtin_inf(), 0.0);
+        if (Y[d] != 0.0) {
+            double D = (double)((Y[d] > 0.0) ? (g.n[d] - 1 - ix[d]) : ix[d]);
+            double aY = fabs(Y[d]), daY = Y[d] > 0.0 ? dY[d] : -dY[d];
+            m[d] = dmk(D / aY, -D * daY / (aY * aY));
+            if (m[d].v < mu.v) mu = m[d];
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        int c;
+        Dual tt;
+        if (mu.v == 1.0) {
+            double fl = floor(Y[d]);
+            c = ix[d] + (int)fl;
+            tt = dmk(Y[d] - fl, dY[d]);
+        } else if (Y[d] != 0.0 && m[d].v == mu.v) {
+            c = (Y[d] > 0.0) ? g.n[d] - 1 : 0;
+            tt = dmk(0.0, 0.0);
+        } else {
+            Dual q = dmk((double)ix[d], 0.0) + mu * dmk(Y[d], dY[d]);
+            double top = (double)(g.n[d] - 1);
+            if (q.v < 0.0) q = dmk(0.0, 0.0);
+            if (q.v > top) q = dmk(top, 0.0);
+            double fl = floor(q.v);
+            c = (int)fl;
+            tt = dmk(q.v - fl, q.d);
+        }
+        if (c >= g.n[d] - 1) {
+            c = g.n[d] - 2;
+            tt = dmk(1.0, 0.0);
+        }
+        cell[d] = c;
+        t[d] = tt;
+    }
+    return mu;
+}
+
+template <int DIM>
+__device__ Dual interp_dual(const double *__restrict__ V, const LevelDev &g, const int cell[3], const Dual t[3]) {
+    Dual v = dmk(0.0, 0.0);
+    const int s1 = (int)g.s1, s2 = (int)g.s2;
+    int base = cell[0] + cell[1] * s1 + (DIM == 3 ? cell[2] * s2 : 0);
+#pragma unroll
+    for (int c = 0; c < (1 << DIM); ++c) {
+        Dual w = (c & 1) ? t[0] : dmk(1.0, 0.0) - t[0];
+        w = w * (((c >> 1) & 1) ? t[1] : dmk(1.0, 0.0) - t[1]);
+        if (DIM == 3) w = w * (((c >> 2) & 1) ? t[2] : dmk(1.0, 0.0) - t[2]);
+        int off = (c & 1) + ((c >> 1) & 1) * s1 + (DIM == 3 ? ((c >> 2) & 1) * s2 : 0);
+        v = v + w * dmk(V[base + off], 0.0);
+    }
+    return v;
+}
+
+// d/ds (L-hat^k V)_i (only diffusion points depend on s)
+template <int DIM>
+__device__ double dlhat_ds(const LevelDev &g, const StencilDev &st, int k, int i, const int ix[3],
+                           const double *__restrict__ V, double inv_s) {
+    const PointTab *pt = st.tab + k * st.npt;
+    double Vi = V[i];
+    Dual acc = dmk(0.0, 0.0);
+    for (int p = 0; p < st.P; ++p) {
+        const PointTab &a = pt[2 * p];
+        const PointTab &b = pt[2 * p + 1];
+        double Ya[3] = {a.Y[0], a.Y[1], a.Y[2]}, dYa[3] = {a.Y[0] * inv_s, a.Y[1] * inv_s, a.Y[2] * inv_s};
+        double Yb[3] = {b.Y[0], b.Y[1], b.Y[2]}, dYb[3] = {b.Y[0] * inv_s, b.Y[1] * inv_s, b.Y[2] * inv_s};
+        int cp[3], cm[3];
+        Dual tp[3], tm[3];
+        Dual mup = landing_dual<DIM>(g, ix, Ya, dYa, cp, tp);
+        Dual mum = landing_dual<DIM>(g, ix, Yb, dYb, cm, tm);
+        Dual two = dmk(2.0, 0.0);
+        Dual A = two / (mup * (mup + mum));
+        Dual B = two / (mum * (mum + mup));
+        Dual vp = interp_dual<DIM>(V, g, cp, tp);
+        Dual vm = interp_dual<DIM>(V, g, cm, tm);
+        acc = acc + ((A * vp + B * vm) - (A + B) * dmk(Vi, 0.0));
+    }
+    return st.inv2h * acc.d;
+}
+
+// partial[b] = block b's part of sum_i mu_i (wa * dL V_a + wb * dL V_b)_i over interior nodes
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_ds_dot(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
+                                                   const double *__restrict__ mu, const double *__restrict__ Va,
+                                                   double wa, const double *__restrict__ Vb, double wb, double inv_s,
+                                                   double *__restrict__ partial) {
+    __shared__ double sh[kBlock / 64];
+    int ix[3];
+    int i = tile_node_a<DIM>(g, ix);
+    double v = 0.0;
+    if (i >= 0 && interior_a<DIM>(g, ix)) {
+        int k = alpha[i];
+        k = ((unsigned)k < (unsigned)st.K) ? k : 0;
+        double d = wa * dlhat_ds<DIM>(g, st, k, i, ix, Va, inv_s);
+        if (wb != 0.0) d += wb * dlhat_ds<DIM>(g, st, k, i, ix, Vb, inv_s);
+        v = mu[i] * d;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) t += sh[w];
+        partial[remap_block_a(blockIdx.x, gridDim.x)] = t;
+    }
+}
+
+void launch_ds_dot(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const double *mu,
+                   const double *Va, double wa, const double *Vb, double wb, double inv_s, double *partial,
+                   hipStream_t s) {
+    if (dim == 2)
+        hipLaunchKernelGGL(k_ds_dot<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, mu, Va, wa, Vb, wb, inv_s,
+                           partial);
+    else
+        hipLaunchKernelGGL(k_ds_dot<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, mu, Va, wa, Vb, wb, inv_s,
+                           partial);
+}
+
+// ---- row listing of L-hat^alpha -------------------------------------------------------------------
+
+// landing without derivatives (the forward rules; duplicated here so this file stands alone)
+template <int DIM>
+__device__ double landing_plain(const LevelDev &g, const int ix[3], const double Y[3], int cell[3], double t[3]) {
+    double m[3];
+    double mu = 1.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        m[d] = __builtin_inf();
+        if (Y[d] != 0.0) {
+            int D = (Y[d] > 0.0) ? (g.n[d] - 1 - ix[d]) : ix[d];
+            m[d] = (double)D / fabs(Y[d]);
+            if (m[d] < mu) mu = m[d];
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        int c;
+        double tt;
+        if (mu == 1.0) {
+            double fl = floor(Y[d]);
+            c = ix[d] + (int)fl;
+            tt = Y[d] - fl;
+        } else if (Y[d] != 0.0 && m[d] == mu) {
+            c = (Y[d] > 0.0) ? g.n[d] - 1 : 0;
+            tt = 0.0;
+        } else {
+            double q = (double)ix[d] + mu * Y[d];
+            double top = (double)(g.n[d] - 1);
+            q = q < 0.0 ? 0.0 : (q > top ? top : q);
+            double fl = floor(q);
+            c = (int)fl;
+            tt = q - fl;
+        }
+        if (c >= g.n[d] - 1) {
+            c = g.n[d] - 2;
+            tt = 1.0;
+        }
+        cell[d] = c;
+        t[d] = tt;
+    }
+    return mu;
+}
+
+// slots [i*E, (i+1)*E): for each stencil point its 2^d corners (weight * corner weight / 2h), then the
+// diagonal -(sum of weights)/2h.  Boundary rows get the sentinel column N.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_emit_rows(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
+                                                      int E, int32_t *__restrict__ cols, double *__restrict__ vals,
+                                                      int32_t *__restrict__ ids) {
+    int ix[3];
+    int i = tile_node_a<DIM>(g, ix);
+    if (i < 0) return;
+    int64_t base = (int64_t)i * E;
+    for (int e = 0; e < E; ++e) ids[base + e] = (int32_t)(base + e);
+    if (!interior_a<DIM>(g, ix)) {
+        for (int e = 0; e < E; ++e) {
+            cols[base + e] = (int32_t)g.N;
+            vals[base + e] = 0.0;
+        }
+        return;
+    }
+    int k = alpha[i];
+    k = ((unsigned)k < (unsigned)st.K) ? k : 0;
+    const PointTab *pt = st.tab + k * st.npt;
+    int e = 0;
+    double diag = 0.0;
+    for (int q = 0; q < st.npt; ++q) {
+        double Y[3] = {pt[q].Y[0], pt[q].Y[1], pt[q].Y[2]};
+        int cell[3];
+        double t[3];
+        double mu = landing_plain<DIM>(g, ix, Y, cell, t);
+        double W;
+        if (q < 2 * st.P) {
+            double Yo[3] = {pt[q ^ 1].Y[0], pt[q ^ 1].Y[1], pt[q ^ 1].Y[2]};
+            int co[3];
+            double to[3];
+            double muo = landing_plain<DIM>(g, ix, Yo, co, to);
+            W = 2.0 / (mu * (mu + muo));
+        } else {
+            W = 2.0 / mu;
+        }
+        double Ws = W * st.inv2h;
+        const int s1 = (int)g.s1, s2 = (int)g.s2;
+        int cb = cell[0] + cell[1] * s1 + (DIM == 3 ? cell[2] * s2 : 0);
+        for (int c = 0; c < (1 << DIM); ++c) {
+            double w = (c & 1) ? t[0] : (1.0 - t[0]);
+            w = w * (((c >> 1) & 1) ? t[1] : (1.0 - t[1]));
+            if (DIM == 3) w = w * (((c >> 2) & 1) ? t[2] : (1.0 - t[2]));
+            int off = (c & 1) + ((c >> 1) & 1) * s1 + (DIM == 3 ? ((c >> 2) & 1) * s2 : 0);
+            cols[base + e] = cb + off;
+            vals[base + e] = Ws * w;
+            ++e;
+        }
+        diag -= Ws;
+    }
+    cols[base + e] = i;
+    vals[base + e] = diag;
+    ++e;
+    for (; e < E; ++e) {
+        cols[base + e] = (int32_t)g.N;
+        vals[base + e] = 0.0;
+    }
+}
+
+// colptr[j] = first sorted position whose column is >= j, for j = 0..N (the sentinel N sorts last)
+__global__ __launch_bounds__(kBlock) void k_colptr(const int32_t *__restrict__ keys, int64_t n, int32_t N,
+                                                   int32_t *__restrict__ colptr) {
+    int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= n) return;
+    int32_t key = keys[p];
+    int32_t prev = p == 0 ? -1 : keys[p - 1];
+    for (int32_t j = prev + 1; j <= key && j <= N; ++j) colptr[j] = (int32_t)p;
+}
+
+// Row listing and its column-sorted order for policy alpha; scratch holds hipCUB's temporary storage.
+int build_transpose(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, int E, int32_t *cols,
+                    double *vals, int32_t *ids, int32_t *cols_sorted, int32_t *ids_sorted, int32_t *colptr,
+                    void *scratch, size_t scratch_bytes, hipStream_t s) {
+    int64_t n = g.N * (int64_t)E;
+    if (dim == 2)
+        hipLaunchKernelGGL(k_emit_rows<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, E, cols, vals, ids);
+    else
+        hipLaunchKernelGGL(k_emit_rows<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, E, cols, vals, ids);
+    int end_bit = 1;
+    while (((int64_t)1 << end_bit) <= g.N) ++end_bit;
+    size_t tb = scratch_bytes;
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(scratch, tb, cols, cols_sorted, ids, ids_sorted, (int)n, 0,
+                                                      end_bit, s);
+    if (e != hipSuccess) return -1;
+    hipLaunchKernelGGL(k_colptr, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, cols_sorted, n,
+                       (int32_t)g.N, colptr);
+    return 0;
+}
+
+size_t transpose_scratch_bytes(int64_t n, int N) {
+    size_t tb = 0;
+    int end_bit = 1;
+    while (((int64_t)1 << end_bit) <= N) ++end_bit;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr,
+                                             (int32_t *)nullptr, (int)n, 0, end_bit, (hipStream_t)0);
+    return tb;
+}
+
+// (L^T x)_j over the interior rows that reference column j, in increasing row order
+__device__ __forceinline__ double lt_gather(int j, const int32_t *__restrict__ colptr,
+                                            const int32_t *__restrict__ ids, const double *__restrict__ vals, int E,
+                                            const double *__restrict__ x) {
+    double acc = 0.0;
+    for (int p = colptr[j]; p < colptr[j + 1]; ++p) {
+        int id = ids[p];
+        acc += vals[id] * x[id / E];
+    }
+    return acc;
+}
+
+// mode 0: y = A^T x = x - theta dt (L^T x + c x) on interior nodes, 0 on the boundary
+// mode 1: y = B^T x = [interior] (x + (1-theta) dt c x) + (1-theta) dt L^T x on every node
+// mode 2: r = b - A^T x on interior nodes (0 on the boundary), partials [sum r^2, max|r|, max|x|]
+template <int DIM, int MODE>
+__global__ __launch_bounds__(kBlock) void k_apply_T(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
+                                                    const int32_t *__restrict__ colptr,
+                                                    const int32_t *__restrict__ ids, const double *__restrict__ vals,
+                                                    int E, const double *__restrict__ x, const double *__restrict__ b,
+                                                    double w, double *__restrict__ y, double *partial) {
+    __shared__ double sh[kBlock / 64];
+    int ix[3];
+    int j = tile_node_a<DIM>(g, ix);
+    double rr = 0.0, xx = 0.0;
+    if (j >= 0) {
+        bool in = interior_a<DIM>(g, ix);
+        double cj = 0.0;
+        if (in && st.c) {
+            int k = alpha[j];
+            cj = st.c[((unsigned)k < (unsigned)st.K) ? k : 0];
+        }
+        double lt = lt_gather(j, colptr, ids, vals, E, x);
+        double xj = x[j];
+        if (MODE == 0) {
+            y[j] = in ? xj - w * (lt + cj * xj) : 0.0;
+        } else if (MODE == 1) {
+            y[j] = (in ? xj + w * cj * xj : 0.0) + w * lt;
+        } else {
+            double r = in ? b[j] - (xj - w * (lt + cj * xj)) : 0.0;
+            y[j] = r;
+            rr = r;
+            xx = fabs(xj);
+        }
+    }
+    if (MODE == 2) {
+        double v2 = rr * rr, vm = fabs(rr), vx = xx;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            v2 += __shfl_down(v2, off, 64);
+            vm = fmax(vm, __shfl_down(vm, off, 64));
+            vx = fmax(vx, __shfl_down(vx, off, 64));
+        }
+        __shared__ double sm[kBlock / 64], sx[kBlock / 64];
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) {
+            sh[threadIdx.x >> 6] = v2;
+            sm[threadIdx.x >> 6] = vm;
+            sx[threadIdx.x >> 6] = vx;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double a = 0.0, m = 0.0, q = 0.0;
+            for (int t = 0; t < kBlock / 64; ++t) {
+                a += sh[t];
+                m = fmax(m, sm[t]);
+                q = fmax(q, sx[t]);
+            }
+            int bb = remap_block_a(blockIdx.x, gridDim.x);
+            partial[bb] = a;
+            partial[gridDim.x + bb] = m;
+            partial[2 * gridDim.x + bb] = q;
+        }
+    }
+}
+
+void launch_apply_T(int dim, int mode, const LevelDev &g, const StencilDev &st, const int16_t *alpha,
+                    const int32_t *colptr, const int32_t *ids, const double *vals, int E, const double *x,
+                    const double *b, double w, double *y, double *partial, hipStream_t s) {
+#define AT(D, M) hipLaunchKernelGGL((k_apply_T<D, M>), dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, colptr, \
+                                    ids, vals, E, x, b, w, y, partial)
+    if (dim == 2) {
+        if (mode == 0) AT(2, 0); else if (mode == 1) AT(2, 1); else AT(2, 2);
+    } else {
+        if (mode == 0) AT(3, 0); else if (mode == 1) AT(3, 1); else AT(3, 2);
+    }
+#undef AT
+}
+
+// y += a * x (interior nodes only) for the f-gradients
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_axpy_interior(LevelDev g, double a, const double *__restrict__ x,
+                                                          double *__restrict__ y) {
+    int ix[3];
+    int i = tile_node_a<DIM>(g, ix);
+    if (i < 0 || !interior_a<DIM>(g, ix)) return;
+    y[i] += a * x[i];
+}
+
+void launch_axpy_interior(int dim, const LevelDev &g, double a, const double *x, double *y, hipStream_t s) {
+    if (dim == 2)
+        hipLaunchKernelGGL(k_axpy_interior<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, a, x, y);
+    else
+        hipLaunchKernelGGL(k_axpy_interior<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, a, x, y);
+}
+
+// y = x on interior nodes, 0 on the boundary
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_mask_interior(LevelDev g, const double *__restrict__ x,
+                                                          double *__restrict__ y) {
+    int ix[3];
+    int i = tile_node_a<DIM>(g, ix);
+    if (i < 0) return;
+    y[i] = interior_a<DIM>(g, ix) ? x[i] : 0.0;
+}
+
+void launch_mask_interior(int dim, const LevelDev &g, const double *x, double *y, hipStream_t s) {
+    if (dim == 2)
+        hipLaunchKernelGGL(k_mask_interior<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, x, y);
+    else
+        hipLaunchKernelGGL(k_mask_interior<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, x, y);
+}
+
+}  // namespace slhjb

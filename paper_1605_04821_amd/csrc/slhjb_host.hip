@@ -18,6 +18,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -444,18 +445,26 @@ int sync_small(hjb_handle *hd, const void *dev, void *host, size_t bytes) {
     return wait_stream(hd);
 }
 
-// Stops when |r|_inf <= rtol_inf*max(1,|X|_inf), or, when eta > 0, once |r|_inf <= eta * (initial |r|_inf).
-int fgmres(hjb_handle *hd, const int16_t *alpha, const double *E, double *X, double theta_dt, double eta,
-           int *its_out, double *res_out, bool *tight_out) {
+// The operator of one linear solve: residual() writes r = b - A X into hd->R with the partials
+// [sum r^2 | max|r| | max|X|] (hd->nb each) in hd->partial; apply(z, z_is_float, w) writes w = A z;
+// precond(v, z) writes z = M^{-1} v (empty: no preconditioner, z = v).
+struct KrylovOp {
+    std::function<void()> residual;
+    std::function<void(const void *, bool, double *)> apply;
+    std::function<int(const double *, void *)> precond;
+    bool zf = false;
+};
+
+// Flexible GMRES(m).  Stops when |r|_inf <= rtol_inf*max(1,|X|_inf), or, when eta > 0, once
+// |r|_inf <= eta * (initial |r|_inf).
+int fgmres_core(hjb_handle *hd, const KrylovOp &op, double *X, double eta, int *its_out, double *res_out,
+                bool *tight_out) {
     const hjb_desc &d = hd->desc;
     const int64_t N = hd->N;
     const int m = d.restart;
-    const int dim = hd->dim;
     hipStream_t s = hd->stream;
-    const Level &L0 = hd->lev[0];
-    StencilDev st = stencil(hd, 0);
-    const bool none = d.precond == HJB_PRECOND_NONE;
-    const bool zf = !none && mixed(hd);
+    const bool none = !op.precond;
+    const bool zf = !none && op.zf;
     const size_t zsz = zf ? sizeof(float) : sizeof(double);
     double *V = hd->Vb;
     double *dv = hd->dvals;
@@ -464,7 +473,7 @@ int fgmres(hjb_handle *hd, const int16_t *alpha, const double *E, double *X, dou
     double loose = 0.0;
     std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gvec(m + 1), y(m);
     for (int cycle = 0;; ++cycle) {
-        launch_residual(dim, L0.g, st, alpha, X, E, theta_dt, hd->R, hd->partial, hd->nb, s);
+        op.residual();
         launch_reduce_sum(hd->partial, 1, hd->nb, dv + 0, s);
         launch_reduce_max(hd->partial + hd->nb, 2, hd->nb, dv + 1, s);
         TRY(sync_small(hd, dv, hp, 3 * sizeof(double)));
@@ -488,11 +497,8 @@ int fgmres(hjb_handle *hd, const int16_t *alpha, const double *E, double *X, dou
             double *vj = V + (int64_t)j * N;
             double *w = V + (int64_t)(j + 1) * N;
             void *zj = none ? (void *)vj : (void *)((char *)hd->Zb + (int64_t)j * N * zsz);
-            if (!none) TRY(precondition(hd, vj, zj, theta_dt));
-            {
-                TimedLaunch tl(hd, HJB_KERNEL_APPLY, (double)N * ((zf ? 4.0 : 8.0) + 2.0 + 8.0));
-                launch_apply(dim, L0.g, st, alpha, zj, zf, w, theta_dt, nullptr, hd->nb, s);
-            }
+            if (!none) TRY(op.precond(vj, zj));
+            op.apply(zj, zf, w);
             // classical Gram-Schmidt: one pass for <w,V_i> and |w|^2, one for the update and normalisation
             // (norm by Pythagoras); a second pass when cancellation is severe
             double hn = 0.0;
@@ -559,6 +565,24 @@ int fgmres(hjb_handle *hd, const int16_t *alpha, const double *E, double *X, dou
         launch_update_solution(X, Z, zf, N, j, dv + 128, N, s);
         HIPCHK(hipGetLastError());
     }
+}
+
+int fgmres(hjb_handle *hd, const int16_t *alpha, const double *E, double *X, double theta_dt, double eta,
+           int *its_out, double *res_out, bool *tight_out) {
+    const int dim = hd->dim;
+    const Level &L0 = hd->lev[0];
+    const StencilDev st = stencil(hd, 0);
+    hipStream_t s = hd->stream;
+    KrylovOp op;
+    op.residual = [=]() { launch_residual(dim, L0.g, st, alpha, X, E, theta_dt, hd->R, hd->partial, hd->nb, s); };
+    op.apply = [=](const void *z, bool zf, double *w) {
+        TimedLaunch tl(hd, HJB_KERNEL_APPLY, (double)hd->N * ((zf ? 4.0 : 8.0) + 2.0 + 8.0));
+        launch_apply(dim, L0.g, st, alpha, z, zf, w, theta_dt, nullptr, hd->nb, s);
+    };
+    if (hd->desc.precond != HJB_PRECOND_NONE)
+        op.precond = [=](const double *v, void *z) { return precondition(hd, v, z, theta_dt); };
+    op.zf = mixed(hd);
+    return fgmres_core(hd, op, X, eta, its_out, res_out, tight_out);
 }
 
 // ---- policy search ------------------------------------------------------------------------------
@@ -1086,6 +1110,188 @@ int hjb_profile_read(hjb_handle *hd, int32_t kernel, int64_t *launches, double *
     if (total_ms) *total_ms = ms;
     if (total_bytes) *total_bytes = by;
     if (total_flops) *total_flops = fl;
+    return HJB_OK;
+}
+
+// ---- adjoint ------------------------------------------------------------------------------------
+
+namespace {
+
+struct TransposeWork {
+    int E = 0;
+    int32_t *cols = nullptr, *ids = nullptr, *cols_s = nullptr, *ids_s = nullptr, *colptr = nullptr;
+    double *vals = nullptr;
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    std::vector<void *> mem;
+    ~TransposeWork() {
+        for (void *p : mem) (void)hipFree(p);
+    }
+    int alloc(hjb_handle *hd) {
+        E = hd->npt * (1 << hd->dim) + 1;
+        int64_t n = hd->N * (int64_t)E;
+        if (n >= ((int64_t)1 << 31)) return fail(HJB_EUNSUPPORTED, "transposed operator too large (%lld entries)", (long long)n);
+        scratch_bytes = transpose_scratch_bytes(n, (int)hd->N);
+        struct R {
+            void **p;
+            size_t b;
+        } req[] = {{(void **)&cols, (size_t)n * 4}, {(void **)&ids, (size_t)n * 4}, {(void **)&cols_s, (size_t)n * 4},
+                   {(void **)&ids_s, (size_t)n * 4}, {(void **)&vals, (size_t)n * 8},
+                   {(void **)&colptr, (size_t)(hd->N + 1) * 4}, {&scratch, scratch_bytes + 256}};
+        for (auto &r : req) {
+            if (hipMalloc(r.p, r.b) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(HJB_ENOMEM, "adjoint workspace (%zu bytes)", r.b);
+            }
+            mem.push_back(*r.p);
+        }
+        return HJB_OK;
+    }
+    int build(hjb_handle *hd, const int16_t *alpha) {
+        if (build_transpose(hd->dim, hd->lev[0].g, stencil(hd, 0), alpha, E, cols, vals, ids, cols_s, ids_s, colptr,
+                            scratch, scratch_bytes, hd->stream) != 0)
+            return fail(HJB_EDEVICE, "radix sort of the transposed operator failed");
+        HIPCHK(hipGetLastError());
+        return HJB_OK;
+    }
+};
+
+// Solve A_alpha^T mu = b (interior) with FGMRES + Jacobi; mu starts at zero.
+int solve_transposed(hjb_handle *hd, TransposeWork &T, const int16_t *alpha, const double *b, double *mu,
+                     double theta_dt, int *its, double *res) {
+    const int dim = hd->dim;
+    const Level &L0 = hd->lev[0];
+    const StencilDev st = stencil(hd, 0);
+    hipStream_t s = hd->stream;
+    launch_diag<double>(dim, L0.g, st, alpha, theta_dt, (double *)L0.d64, s);  // diag(A^T) = diag(A)
+    launch_zero(mu, (size_t)hd->N * 8, s);
+    KrylovOp op;
+    op.residual = [=, &T]() {
+        launch_apply_T(dim, 2, L0.g, st, alpha, T.colptr, T.ids_s, T.vals, T.E, mu, b, theta_dt, hd->R, hd->partial, s);
+    };
+    op.apply = [=, &T](const void *z, bool, double *w) {
+        launch_apply_T(dim, 0, L0.g, st, alpha, T.colptr, T.ids_s, T.vals, T.E, (const double *)z, nullptr, theta_dt, w,
+                       nullptr, s);
+    };
+    op.precond = [=](const double *v, void *z) {
+        hipLaunchKernelGGL(k_jacobi_precond64, dim3(blocks_for(hd->N)), dim3(kBlock), 0, s, v,
+                           (const double *)L0.d64, (double *)z, hd->N);
+        return HJB_OK;
+    };
+    op.zf = false;
+    bool tight = false;
+    return fgmres_core(hd, op, mu, 0.0, its, res, &tight);
+}
+
+}  // namespace
+
+int hjb_apply_transposed(hjb_handle *hd, const int16_t *alpha, const double *x, double *y, double dt, double theta,
+                         double s) {
+    if (!hd) return fail(HJB_EINVAL, "null handle");
+    if (!alpha || !x || !y) return fail(HJB_EINVAL, "null array argument");
+    if (x == y) return fail(HJB_EINVAL, "x and y must be distinct");
+    TRY(check_time(dt, theta));
+    TRY(build_tables(hd, s));
+    TRY(check_policy(hd, alpha));
+    TransposeWork T;
+    TRY(T.alloc(hd));
+    TRY(T.build(hd, alpha));
+    launch_apply_T(hd->dim, 0, hd->lev[0].g, stencil(hd, 0), alpha, T.colptr, T.ids_s, T.vals, T.E, x, nullptr,
+                   theta * dt, y, nullptr, hd->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(hd->stream));
+    return HJB_OK;
+}
+
+int hjb_adjoint(hjb_handle *hd, const double *g, const double *psi, const double *f0, const double *f1, int32_t n_steps,
+                const double *dts, const double *thetas, double s, const int16_t *policies, const double *dJ_dUN,
+                double *dJ_df0, double *dJ_df1, double *dJ_dg, double *dJ_ds, hjb_adjoint_stats *stats) {
+    if (!hd) return fail(HJB_EINVAL, "null handle");
+    if (!g || !psi || !f0 || !f1 || !dts || !thetas || !policies || !dJ_dUN || !dJ_df0 || !dJ_dg)
+        return fail(HJB_EINVAL, "null argument");
+    if (n_steps < 1) return fail(HJB_EINVAL, "n_steps must be >= 1");
+    for (int n = 0; n < n_steps; ++n) {
+        TRY(check_time(dts[n], thetas[n]));
+        if (thetas[n] == 0.0) return fail(HJB_EUNSUPPORTED, "explicit steps (theta = 0) are not provided");
+    }
+    TRY(build_tables(hd, s));
+    const int64_t N = hd->N;
+    const int dim = hd->dim;
+    const LevelDev &g0 = hd->lev[0].g;
+    hipStream_t str = hd->stream;
+    for (int n = 0; n < n_steps; ++n) TRY(check_policy(hd, policies + (int64_t)n * N));
+    hjb_adjoint_stats loc{};
+    // values U^0..U^N, recomputed from the policy checkpoints
+    double *Us = nullptr, *lam = nullptr, *mu = nullptr;
+    if (hipMalloc((void **)&Us, (size_t)(n_steps + 1) * N * 8) != hipSuccess ||
+        hipMalloc((void **)&lam, (size_t)N * 8) != hipSuccess || hipMalloc((void **)&mu, (size_t)N * 8) != hipSuccess) {
+        (void)hipGetLastError();
+        if (Us) (void)hipFree(Us);
+        if (lam) (void)hipFree(lam);
+        return fail(HJB_ENOMEM, "adjoint value storage");
+    }
+    struct Free {
+        std::vector<void *> p;
+        ~Free() {
+            for (void *q : p) (void)hipFree(q);
+        }
+    } fr{{Us, lam, mu}};
+    std::vector<double> tprev(n_steps);
+    int rc = HJB_OK;
+    {
+        HIPCHK(hipMemcpyAsync(Us, g, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
+        double t = 0.0;
+        for (int n = 0; n < n_steps; ++n) {
+            double *Un = Us + (int64_t)(n + 1) * N;
+            const double *Up = Us + (int64_t)n * N;
+            HIPCHK(hipMemcpyAsync(Un, psi, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
+            launch_copy_interior(dim, g0, Up, Un, str);
+            int its = 0;
+            double res = 0.0;
+            bool tight = false;
+            rc = linsolve_impl(hd, policies + (int64_t)n * N, Up, f0, f1, t, dts[n], thetas[n], Un, 0.0, &its, &res,
+                               &tight);
+            loc.krylov_recompute += its;
+            if (rc != HJB_OK) return rc;
+            tprev[n] = t;
+            t = t + dts[n];
+        }
+    }
+    TransposeWork T;
+    TRY(T.alloc(hd));
+    launch_mask_interior(dim, g0, dJ_dUN, lam, str);
+    launch_zero(dJ_df0, (size_t)N * 8, str);
+    if (dJ_df1) launch_zero(dJ_df1, (size_t)N * 8, str);
+    double ds = 0.0;
+    const double inv_s = 1.0 / s;
+    for (int n = n_steps - 1; n >= 0; --n) {
+        const int16_t *alpha = policies + (int64_t)n * N;
+        const double dt = dts[n], th = thetas[n];
+        const double t_mid = tprev[n] + th * dt;
+        TRY(T.build(hd, alpha));
+        int its = 0;
+        double res = 0.0;
+        rc = solve_transposed(hd, T, alpha, lam, mu, th * dt, &its, &res);
+        loc.krylov_adjoint += its;
+        loc.max_res_adjoint = std::max(loc.max_res_adjoint, res);
+        if (rc != HJB_OK) return rc;
+        launch_axpy_interior(dim, g0, dt, mu, dJ_df0, str);
+        if (dJ_df1) launch_axpy_interior(dim, g0, dt * t_mid, mu, dJ_df1, str);
+        if (dJ_ds) {
+            launch_ds_dot(dim, g0, stencil(hd, 0), alpha, mu, Us + (int64_t)(n + 1) * N, th, Us + (int64_t)n * N,
+                          1.0 - th, inv_s, hd->partial, str);
+            launch_reduce_sum(hd->partial, 1, hd->nb, hd->dvals + 200, str);
+            TRY(sync_small(hd, hd->dvals + 200, hd->hpin + 200, sizeof(double)));
+            ds += dt * hd->hpin[200];
+        }
+        // lambda_{n-1} = B_n^T mu_n on every node
+        launch_apply_T(dim, 1, g0, stencil(hd, 0), alpha, T.colptr, T.ids_s, T.vals, T.E, mu, nullptr,
+                       (1.0 - th) * dt, n > 0 ? lam : dJ_dg, nullptr, str);
+        HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipStreamSynchronize(str));
+    if (dJ_ds) *dJ_ds = ds;
+    if (stats) *stats = loc;
     return HJB_OK;
 }
 

@@ -132,6 +132,20 @@ void launch_extrapolate(int dim, const LevelDev &g, const double *U1, const doub
                         hipStream_t s);
 
 int blocks_for(int64_t N);
+
+// adjoint (slhjb_adjoint.hip)
+int build_transpose(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, int E, int32_t *cols,
+                    double *vals, int32_t *ids, int32_t *cols_sorted, int32_t *ids_sorted, int32_t *colptr,
+                    void *scratch, size_t scratch_bytes, hipStream_t s);
+size_t transpose_scratch_bytes(int64_t n, int N);
+void launch_apply_T(int dim, int mode, const LevelDev &g, const StencilDev &st, const int16_t *alpha,
+                    const int32_t *colptr, const int32_t *ids, const double *vals, int E, const double *x,
+                    const double *b, double w, double *y, double *partial, hipStream_t s);
+void launch_ds_dot(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const double *mu,
+                   const double *Va, double wa, const double *Vb, double wb, double inv_s, double *partial,
+                   hipStream_t s);
+void launch_axpy_interior(int dim, const LevelDev &g, double a, const double *x, double *y, hipStream_t s);
+void launch_mask_interior(int dim, const LevelDev &g, const double *x, double *y, hipStream_t s);
 inline int tiles_for(const LevelDev &g) { return g.ntx * g.nty * g.ntz; }
 inline void set_tiles(LevelDev &g, int dim) {
     g.ntx = (g.n[0] + kTX - 1) / kTX;

@@ -165,10 +165,12 @@ int hjb_step(hjb_handle *hd, const double *Uprev, double *Unext, const double *f
 /* March U^0 = g (eq. 1.2), U^n = psi on the boundary (eq. 1.3) through n_steps theta-steps with
    dts[n], thetas[n] (host arrays); from the third step on, each step starts from the extrapolation of
    the two previous levels (see hjb_step).  U_final: full-grid FP64 output.  policies (nullable): int16
-   [n_steps][N], the converged policy of each step (the checkpoints an adjoint sweep reuses). */
+   [n_steps][N], the converged policy of each step (the checkpoints an adjoint sweep reuses).
+   values (nullable): FP64 [n_steps+1][N], U^0 = g and every U^n, for hjb_adjoint to use instead of
+   recomputing them. */
 int hjb_solve(hjb_handle *hd, const double *g, const double *psi, const double *f0, const double *f1,
               int32_t n_steps, const double *dts, const double *thetas, double s,
-              double *U_final, int16_t *policies, hjb_solve_stats *st);
+              double *U_final, int16_t *policies, double *values, hjb_solve_stats *st);
 
 typedef struct {
     int64_t krylov_recompute;  /* FGMRES iterations of the forward recomputation */
@@ -180,19 +182,22 @@ typedef struct {
  * Discrete adjoint of hjb_solve at the policies it returned (gradients of a functional J of U^N).
  * Each step solves A_n U^n = B_n U^{n-1} + dt_n f(t_mid) + Dirichlet terms (eq. FullScheme with
  * A_n = I - theta dt (L^{alpha_n} + C) on interior nodes and B_n = I + (1-theta) dt (L^{alpha_n} + C) on the
- * full previous level).  The values U^n are recomputed from g with one fixed-policy solve per step, then
- * backwards: A_n^T mu_n = lambda_n, dJ/df0 += dt mu_n, dJ/df1 += dt t_mid mu_n,
+ * full previous level).  The values U^n are taken from `values` (hjb_solve's output) or, when it is
+ * NULL, recomputed from g with one fixed-policy solve per step; then backwards: A_n^T mu_n = lambda_n, dJ/df0 += dt mu_n, dJ/df1 += dt t_mid mu_n,
  * dJ/ds += dt mu_n^T (theta d_s L U^n + (1-theta) d_s L U^{n-1}), lambda_{n-1} = B_n^T mu_n, dJ/dg = lambda_0.
  * Policies are held fixed, so the gradient is exact away from policy switches (where J is differentiable).
  *   g, psi, f0, f1: full-grid FP64 as for hjb_solve; policies: int16 [n_steps][N] from hjb_solve;
+ *   values (nullable): FP64 [n_steps+1][N] from hjb_solve;
  *   dts, thetas: host [n_steps]; dJ_dUN: full-grid FP64 (boundary entries ignored);
  *   dJ_df0, dJ_dg: full-grid FP64 outputs (dJ_df0 zero on the boundary); dJ_df1: nullable;
- *   dJ_ds: host scalar (nullable).  Transposed solves use FGMRES with a Jacobi preconditioner on an
- *   explicitly transposed operator (rows listed and stably sorted by column, no atomics).
+ *   dJ_ds: host scalar (nullable).  Transposed solves use FGMRES on an explicitly transposed operator
+ *   (rows listed and stably sorted by column, no atomics), preconditioned by a V-cycle on the transposed
+ *   level operators (or Jacobi, following the handle's preconditioner option), each starting from the
+ *   previous step's multiplier.  Workspace is allocated per call.
  */
 int hjb_adjoint(hjb_handle *hd, const double *g, const double *psi, const double *f0, const double *f1,
                 int32_t n_steps, const double *dts, const double *thetas, double s, const int16_t *policies,
-                const double *dJ_dUN, double *dJ_df0, double *dJ_df1, double *dJ_dg, double *dJ_ds,
+                const double *values, const double *dJ_dUN, double *dJ_df0, double *dJ_df1, double *dJ_dg, double *dJ_ds,
                 hjb_adjoint_stats *st);
 
 /* y = (A^alpha)^T x for the matrix of hjb_apply (interior rows and columns; y zero on the boundary).

@@ -81,8 +81,8 @@ def _load():
     L.hjb_apply.argtypes = [vp, vp, vp, vp, d, d, d]
     L.hjb_linsolve.argtypes = [vp, vp, vp, vp, vp, d, d, d, d, vp, ctypes.POINTER(StepStats)]
     L.hjb_step.argtypes = [vp, vp, vp, vp, vp, d, d, d, d, vp, vp, d, ctypes.POINTER(StepStats)]
-    L.hjb_solve.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, d, vp, vp, ctypes.POINTER(SolveStats)]
-    L.hjb_adjoint.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, d, vp, vp, vp, vp, vp, ctypes.POINTER(d),
+    L.hjb_solve.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, d, vp, vp, vp, ctypes.POINTER(SolveStats)]
+    L.hjb_adjoint.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, d, vp, vp, vp, vp, vp, vp, ctypes.POINTER(d),
                               ctypes.POINTER(AdjointStats)]
     L.hjb_apply_transposed.argtypes = [vp, vp, vp, vp, d, d, d]
     L.hjb_profile_enable.argtypes = [vp, i32, i32]
@@ -247,15 +247,17 @@ class Solver:
         _check(_lib.hjb_apply_transposed(self._h, _ptr(alpha), _ptr(x), _ptr(y), float(dt), float(theta), float(s)))
 
     def adjoint(self, g, psi, f0, f1, dts, thetas, s, policies, dJ_dUN, dJ_df0, dJ_dg, dJ_df1=None,
-                want_ds=True):
-        """hjb_adjoint at fixed policies; returns (dJ/ds or None, AdjointStats)."""
+                want_ds=True, values=None):
+        """hjb_adjoint at fixed policies; values: the forward values [n_steps+1][N] (None: recompute).
+        Returns (dJ/ds or None, AdjointStats)."""
         self._sync_stream()
         dts = np.ascontiguousarray(dts, dtype=np.float64)
         thetas = np.ascontiguousarray(thetas, dtype=np.float64)
         st = AdjointStats()
         ds = ctypes.c_double(0.0)
         _check(_lib.hjb_adjoint(self._h, _ptr(g), _ptr(psi), _ptr(f0), _ptr(f1), int(len(dts)), dts.ctypes.data,
-                                thetas.ctypes.data, float(s), _ptr(policies), _ptr(dJ_dUN), _ptr(dJ_df0),
+                                thetas.ctypes.data, float(s), _ptr(policies), _ptr(values), _ptr(dJ_dUN),
+                                _ptr(dJ_df0),
                                 _ptr(dJ_df1), _ptr(dJ_dg), ctypes.byref(ds) if want_ds else None,
                                 ctypes.byref(st)))
         return (float(ds.value) if want_ds else None), st
@@ -274,14 +276,14 @@ class Solver:
                                      ctypes.byref(fl)))
         return int(n.value), float(ms.value), float(by.value), float(fl.value)
 
-    def solve(self, g, psi, f0, f1, dts, thetas, s, U_final, policies=None) -> SolveStats:
+    def solve(self, g, psi, f0, f1, dts, thetas, s, U_final, policies=None, values=None) -> SolveStats:
         self._sync_stream()
         dts = np.ascontiguousarray(dts, dtype=np.float64)
         thetas = np.ascontiguousarray(thetas, dtype=np.float64)
         st = SolveStats()
         _check(_lib.hjb_solve(self._h, _ptr(g), _ptr(psi), _ptr(f0), _ptr(f1), int(len(dts)),
                               dts.ctypes.data, thetas.ctypes.data, float(s), _ptr(U_final), _ptr(policies),
-                              ctypes.byref(st)))
+                              _ptr(values), ctypes.byref(st)))
         return st
 
 
@@ -297,17 +299,19 @@ def _autograd_function():
             N = g.numel()
             U = torch.empty_like(g)
             pol = torch.empty((len(dts), N), dtype=torch.int16, device=g.device)
-            solver.solve(g, psi, f0, f1, dts, thetas, float(s), U, pol)
-            ctx.save_for_backward(g, f0, f1, psi, pol)
+            vals = torch.empty((len(dts) + 1, N), dtype=torch.float64, device=g.device)
+            solver.solve(g, psi, f0, f1, dts, thetas, float(s), U, pol, vals)
+            ctx.save_for_backward(g, f0, f1, psi, pol, vals)
             ctx.meta = (solver, float(s), np.asarray(dts, np.float64), np.asarray(thetas, np.float64))
             return U
 
         @staticmethod
         def backward(ctx, gU):
-            g, f0, f1, psi, pol = ctx.saved_tensors
+            g, f0, f1, psi, pol, vals = ctx.saved_tensors
             solver, s, dts, thetas = ctx.meta
             df0, df1, dg = torch.empty_like(g), torch.empty_like(g), torch.empty_like(g)
-            ds, _ = solver.adjoint(g, psi, f0, f1, dts, thetas, s, pol, gU.contiguous(), df0, dg, dJ_df1=df1)
+            ds, _ = solver.adjoint(g, psi, f0, f1, dts, thetas, s, pol, gU.contiguous(), df0, dg, dJ_df1=df1,
+                                   values=vals)
             dsv = torch.tensor(ds, dtype=torch.float64, device=g.device)
             return dg, df0, df1, dsv, None, None, None, None
 

@@ -291,66 +291,206 @@ __global__ __launch_bounds__(kBlock) void k_emit_rows(LevelDev g, StencilDev st,
     }
 }
 
-// colptr[j] = first sorted position whose column is >= j, for j = 0..N (the sentinel N sorts last)
-__global__ __launch_bounds__(kBlock) void k_colptr(const int32_t *__restrict__ keys, int64_t n, int32_t N,
-                                                   int32_t *__restrict__ colptr) {
+// colptr[j] = first sorted position whose column is >= j, for j = 0..N (the sentinel N sorts last);
+// the entries are then laid out in column order: vals_s[p] = vals[id], rows_s[p] = id / E.
+__global__ __launch_bounds__(kBlock) void k_colptr(const int32_t *__restrict__ keys, const int32_t *__restrict__ ids,
+                                                   const double *__restrict__ vals, int E, int64_t n, int32_t N,
+                                                   int32_t *__restrict__ colptr, double *__restrict__ vals_s,
+                                                   int32_t *__restrict__ rows_s) {
     int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (p >= n) return;
     int32_t key = keys[p];
     int32_t prev = p == 0 ? -1 : keys[p - 1];
     for (int32_t j = prev + 1; j <= key && j <= N; ++j) colptr[j] = (int32_t)p;
+    if (p == n - 1)
+        for (int32_t j = key + 1; j <= N; ++j) colptr[j] = (int32_t)n;
+    int32_t id = ids[p];
+    vals_s[p] = vals[id];
+    rows_s[p] = id / E;
 }
 
-// Row listing and its column-sorted order for policy alpha; scratch holds hipCUB's temporary storage.
-int build_transpose(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, int E, int32_t *cols,
-                    double *vals, int32_t *ids, int32_t *cols_sorted, int32_t *ids_sorted, int32_t *colptr,
-                    void *scratch, size_t scratch_bytes, hipStream_t s) {
+// slice widths: longest column of each wavefront's 64 nodes, capped at kEllCap
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_ell_width(LevelDev g, const int32_t *__restrict__ colptr,
+                                                      int32_t *__restrict__ width) {
+    int ix[3];
+    int j = tile_node_a<DIM>(g, ix);
+    int cnt = j >= 0 ? colptr[j + 1] - colptr[j] : 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) cnt = max(cnt, __shfl_xor(cnt, off, 64));
+    if ((threadIdx.x & 63) == 0)
+        width[(int64_t)remap_block_a(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6)] = min(cnt, kEllCap);
+}
+
+// lane l of a slice copies its column's first `width` entries (zero weight on the node itself past its count)
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_ell_fill(LevelDev g, const int32_t *__restrict__ colptr,
+                                                     const int32_t *__restrict__ rows_s,
+                                                     const double *__restrict__ vals_s,
+                                                     const int32_t *__restrict__ width, const int32_t *__restrict__ soff,
+                                                     int32_t *__restrict__ ell_rows, double *__restrict__ ell_vals,
+                                                     float *__restrict__ ell_vals32, int16_t *__restrict__ ell_d16) {
+    int ix[3];
+    int j = tile_node_a<DIM>(g, ix);
+    int64_t sl = (int64_t)remap_block_a(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
+    int W = width[sl];
+    int64_t base = (int64_t)soff[sl] * 64 + (threadIdx.x & 63);
+    int p0 = j >= 0 ? colptr[j] : 0;
+    int cnt = j >= 0 ? colptr[j + 1] - p0 : 0;
+    int self = j >= 0 ? j : 0;
+    const int s1 = (int)g.s1;
+    for (int q = 0; q < W; ++q) {
+        bool real = q < cnt;
+        int row = real ? rows_s[p0 + q] : self;
+        double v = real ? vals_s[p0 + q] : 0.0;
+        ell_rows[base + (int64_t)q * 64] = row;
+        ell_vals[base + (int64_t)q * 64] = v;
+        if (ell_vals32) ell_vals32[base + (int64_t)q * 64] = (float)v;
+        if (DIM == 2 && ell_d16) {
+            int dx = j >= 0 ? row % s1 - ix[0] : 0;
+            int dy = j >= 0 ? row / s1 - ix[1] : 0;
+            ell_d16[base + (int64_t)q * 64] = (int16_t)((dx & 0xff) | (dy << 8));
+        }
+    }
+}
+
+// Row listing of level g's operator for policy alpha, its column-sorted (CSC) form and the sliced ELL copy.
+int build_transpose(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, int E, TransposeBuf &b,
+                    hipStream_t s) {
     int64_t n = g.N * (int64_t)E;
+    const int nt = tiles_for(g);
     if (dim == 2)
-        hipLaunchKernelGGL(k_emit_rows<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, E, cols, vals, ids);
+        hipLaunchKernelGGL(k_emit_rows<2>, dim3(nt), dim3(kBlock), 0, s, g, st, alpha, E, b.cols, b.vals, b.ids);
     else
-        hipLaunchKernelGGL(k_emit_rows<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, E, cols, vals, ids);
+        hipLaunchKernelGGL(k_emit_rows<3>, dim3(nt), dim3(kBlock), 0, s, g, st, alpha, E, b.cols, b.vals, b.ids);
     int end_bit = 1;
     while (((int64_t)1 << end_bit) <= g.N) ++end_bit;
-    size_t tb = scratch_bytes;
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(scratch, tb, cols, cols_sorted, ids, ids_sorted, (int)n, 0,
+    size_t tb = b.scratch_bytes;
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(b.scratch, tb, b.cols, b.cols_s, b.ids, b.ids_s, (int)n, 0,
                                                       end_bit, s);
     if (e != hipSuccess) return -1;
-    hipLaunchKernelGGL(k_colptr, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, cols_sorted, n,
-                       (int32_t)g.N, colptr);
+    hipLaunchKernelGGL(k_colptr, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, b.cols_s, b.ids_s,
+                       b.vals, E, n, (int32_t)g.N, b.colptr, b.vals_s, b.rows_s);
+    const int64_t ns = ell_slices(g);
+    if (dim == 2)
+        hipLaunchKernelGGL(k_ell_width<2>, dim3(nt), dim3(kBlock), 0, s, g, b.colptr, b.ell_w);
+    else
+        hipLaunchKernelGGL(k_ell_width<3>, dim3(nt), dim3(kBlock), 0, s, g, b.colptr, b.ell_w);
+    tb = b.scratch_bytes;
+    e = hipcub::DeviceScan::ExclusiveSum(b.scratch, tb, b.ell_w, b.ell_off, (int)ns, s);
+    if (e != hipSuccess) return -1;
+    if (dim == 2)
+        hipLaunchKernelGGL(k_ell_fill<2>, dim3(nt), dim3(kBlock), 0, s, g, b.colptr, b.rows_s, b.vals_s, b.ell_w,
+                           b.ell_off, b.ell_rows, b.ell_vals, b.ell_vals32, b.ell_d16);
+    else
+        hipLaunchKernelGGL(k_ell_fill<3>, dim3(nt), dim3(kBlock), 0, s, g, b.colptr, b.rows_s, b.vals_s, b.ell_w,
+                           b.ell_off, b.ell_rows, b.ell_vals, b.ell_vals32, b.ell_d16);
     return 0;
 }
 
-size_t transpose_scratch_bytes(int64_t n, int N) {
-    size_t tb = 0;
+size_t transpose_scratch_bytes(int64_t n, int N, int nslices) {
+    size_t tb = 0, ts = 0;
     int end_bit = 1;
     while (((int64_t)1 << end_bit) <= N) ++end_bit;
     (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr,
                                              (int32_t *)nullptr, (int)n, 0, end_bit, (hipStream_t)0);
-    return tb;
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, ts, (int32_t *)nullptr, (int32_t *)nullptr, nslices,
+                                           (hipStream_t)0);
+    return tb > ts ? tb : ts;
 }
 
-// (L^T x)_j over the interior rows that reference column j, in increasing row order
-__device__ __forceinline__ double lt_gather(int j, const int32_t *__restrict__ colptr,
-                                            const int32_t *__restrict__ ids, const double *__restrict__ vals, int E,
-                                            const double *__restrict__ x) {
+// (L^T x)_j over the interior rows that reference column j, in increasing row order: the slice's
+// ELL entries, then the column's entries past the cap.
+template <typename TX>
+__device__ __forceinline__ double lt_gather(int j, const TransposeView &T, const TX *__restrict__ x) {
+    const int64_t sl = (int64_t)remap_block_a(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
+    const int W = T.ell_w[sl];
+    const int32_t *__restrict__ er = T.ell_rows + (int64_t)T.ell_off[sl] * 64 + (threadIdx.x & 63);
+    const double *__restrict__ ev = T.ell_vals + (int64_t)T.ell_off[sl] * 64 + (threadIdx.x & 63);
     double acc = 0.0;
-    for (int p = colptr[j]; p < colptr[j + 1]; ++p) {
-        int id = ids[p];
-        acc += vals[id] * x[id / E];
+    int q = 0;
+    for (; q + 8 <= W; q += 8) {
+        int r[8];
+        double v[8], xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) r[u] = er[(q + u) * 64];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = ev[(q + u) * 64];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xv[u] = (double)x[r[u]];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u] * xv[u];
     }
+    for (; q + 4 <= W; q += 4) {
+        const int r0 = er[q * 64], r1 = er[(q + 1) * 64], r2 = er[(q + 2) * 64], r3 = er[(q + 3) * 64];
+        const double v0 = ev[q * 64], v1 = ev[(q + 1) * 64], v2 = ev[(q + 2) * 64], v3 = ev[(q + 3) * 64];
+        const double x0 = (double)x[r0], x1 = (double)x[r1], x2 = (double)x[r2], x3 = (double)x[r3];
+        acc += v0 * x0;
+        acc += v1 * x1;
+        acc += v2 * x2;
+        acc += v3 * x3;
+    }
+    for (; q < W; ++q) acc += ev[q * 64] * (double)x[er[q * 64]];
+    const int p1 = T.colptr[j + 1];
+    for (int p = T.colptr[j] + W; p < p1; ++p) acc += T.vals[p] * (double)x[T.rows[p]];
+    return acc;
+}
+
+// FP32 gather of the preconditioner (same entries and order, float weights and accumulation); the
+// loads of four entries are issued before their products are accumulated
+template <bool PACKED>
+__device__ __forceinline__ float lt_gather32(int j, int s1, const TransposeView &T, const float *__restrict__ x) {
+    const int64_t sl = (int64_t)remap_block_a(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
+    const int W = T.ell_w[sl];
+    const int64_t base = (int64_t)T.ell_off[sl] * 64 + (threadIdx.x & 63);
+    const float *__restrict__ ev = T.ell_vals32 + base;
+    const int16_t *__restrict__ ed = T.ell_d16 + base;
+    const int32_t *__restrict__ er = T.ell_rows + base;
+    auto row = [&](int q) -> int {
+        if (PACKED) {
+            int c = ed[q * 64];
+            return j + (int)(int8_t)(c & 0xff) + (c >> 8) * s1;
+        }
+        return er[q * 64];
+    };
+    float acc = 0.0f;
+    int q = 0;
+    for (; q + 8 <= W; q += 8) {
+        int r[8];
+        float v[8], xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) r[u] = row(q + u);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = ev[(q + u) * 64];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xv[u] = x[r[u]];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u] * xv[u];
+    }
+    for (; q + 4 <= W; q += 4) {
+        const int r0 = row(q), r1 = row(q + 1), r2 = row(q + 2), r3 = row(q + 3);
+        const float v0 = ev[q * 64], v1 = ev[(q + 1) * 64], v2 = ev[(q + 2) * 64], v3 = ev[(q + 3) * 64];
+        const float x0 = x[r0], x1 = x[r1], x2 = x[r2], x3 = x[r3];
+        acc += v0 * x0;
+        acc += v1 * x1;
+        acc += v2 * x2;
+        acc += v3 * x3;
+    }
+    for (; q < W; ++q) acc += ev[q * 64] * x[row(q)];
+    const int p1 = T.colptr[j + 1];
+    for (int p = T.colptr[j] + W; p < p1; ++p) acc += (float)T.vals[p] * x[T.rows[p]];
     return acc;
 }
 
 // mode 0: y = A^T x = x - theta dt (L^T x + c x) on interior nodes, 0 on the boundary
 // mode 1: y = B^T x = [interior] (x + (1-theta) dt c x) + (1-theta) dt L^T x on every node
 // mode 2: r = b - A^T x on interior nodes (0 on the boundary), partials [sum r^2, max|r|, max|x|]
+// mode 3: r = b - A^T x on interior nodes (0 on the boundary), no partials
 template <int DIM, int MODE>
 __global__ __launch_bounds__(kBlock) void k_apply_T(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
-                                                    const int32_t *__restrict__ colptr,
-                                                    const int32_t *__restrict__ ids, const double *__restrict__ vals,
-                                                    int E, const double *__restrict__ x, const double *__restrict__ b,
-                                                    double w, double *__restrict__ y, double *partial) {
+                                                    TransposeView T, const double *__restrict__ x,
+                                                    const double *__restrict__ b, double w, double *__restrict__ y,
+                                                    double *partial) {
     __shared__ double sh[kBlock / 64];
     int ix[3];
     int j = tile_node_a<DIM>(g, ix);
@@ -362,7 +502,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_T(LevelDev g, StencilDev st, c
             int k = alpha[j];
             cj = st.c[((unsigned)k < (unsigned)st.K) ? k : 0];
         }
-        double lt = lt_gather(j, colptr, ids, vals, E, x);
+        double lt = lt_gather<double>(j, T, x);
         double xj = x[j];
         if (MODE == 0) {
             y[j] = in ? xj - w * (lt + cj * xj) : 0.0;
@@ -407,16 +547,58 @@ __global__ __launch_bounds__(kBlock) void k_apply_T(LevelDev g, StencilDev st, c
 }
 
 void launch_apply_T(int dim, int mode, const LevelDev &g, const StencilDev &st, const int16_t *alpha,
-                    const int32_t *colptr, const int32_t *ids, const double *vals, int E, const double *x,
-                    const double *b, double w, double *y, double *partial, hipStream_t s) {
-#define AT(D, M) hipLaunchKernelGGL((k_apply_T<D, M>), dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, colptr, \
-                                    ids, vals, E, x, b, w, y, partial)
+                    const TransposeView &T, const double *x, const double *b, double w, double *y, double *partial,
+                    hipStream_t s) {
+#define AT(D, M) hipLaunchKernelGGL((k_apply_T<D, M>), dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, T, x, b, \
+                                    w, y, partial)
     if (dim == 2) {
-        if (mode == 0) AT(2, 0); else if (mode == 1) AT(2, 1); else AT(2, 2);
+        if (mode == 0) AT(2, 0); else if (mode == 1) AT(2, 1); else if (mode == 2) AT(2, 2); else AT(2, 3);
     } else {
-        if (mode == 0) AT(3, 0); else if (mode == 1) AT(3, 1); else AT(3, 2);
+        if (mode == 0) AT(3, 0); else if (mode == 1) AT(3, 1); else if (mode == 2) AT(3, 2); else AT(3, 3);
     }
 #undef AT
+}
+
+// Damped Jacobi sweep on A^T e = r: y = x + omega (r - A^T x) / d (interior; 0 on the boundary).
+// FIRST: x = 0, so y = omega r / d without gathers.
+template <int DIM, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_jacobi_T(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
+                                                     TransposeView T, const double *__restrict__ x,
+                                                     const double *__restrict__ r, const double *__restrict__ d,
+                                                     double theta_dt, double omega, double *__restrict__ y) {
+    int ix[3];
+    int j = tile_node_a<DIM>(g, ix);
+    if (j < 0) return;
+    if (!interior_a<DIM>(g, ix)) {
+        y[j] = 0.0;
+        return;
+    }
+    if (FIRST) {
+        y[j] = omega * r[j] / d[j];
+        return;
+    }
+    double cj = 0.0;
+    if (st.c) {
+        int k = alpha[j];
+        cj = st.c[((unsigned)k < (unsigned)st.K) ? k : 0];
+    }
+    double xj = x[j];
+    double lt = lt_gather<double>(j, T, x);
+    double res = r[j] - (xj - theta_dt * (lt + cj * xj));
+    y[j] = xj + omega * res / d[j];
+}
+
+void launch_jacobi_T(int dim, bool first, const LevelDev &g, const StencilDev &st, const int16_t *alpha,
+                     const TransposeView &T, const double *x, const double *r, const double *d, double theta_dt,
+                     double omega, double *y, hipStream_t s) {
+#define JT(D, F) hipLaunchKernelGGL((k_jacobi_T<D, F>), dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, T, x, r, \
+                                    d, theta_dt, omega, y)
+    if (dim == 2) {
+        if (first) JT(2, true); else JT(2, false);
+    } else {
+        if (first) JT(3, true); else JT(3, false);
+    }
+#undef JT
 }
 
 // y += a * x (interior nodes only) for the f-gradients
@@ -451,6 +633,116 @@ void launch_mask_interior(int dim, const LevelDev &g, const double *x, double *y
         hipLaunchKernelGGL(k_mask_interior<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, x, y);
     else
         hipLaunchKernelGGL(k_mask_interior<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, x, y);
+}
+
+
+// y = A^T x with an FP32 x (the preconditioned basis vectors of the mixed mode), FP64 weights and output
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_apply_T_f32x(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
+                                                         TransposeView T, const float *__restrict__ x, double w,
+                                                         double *__restrict__ y) {
+    int ix[3];
+    int j = tile_node_a<DIM>(g, ix);
+    if (j < 0) return;
+    if (!interior_a<DIM>(g, ix)) {
+        y[j] = 0.0;
+        return;
+    }
+    double cj = 0.0;
+    if (st.c) {
+        int k = alpha[j];
+        cj = st.c[((unsigned)k < (unsigned)st.K) ? k : 0];
+    }
+    double xj = (double)x[j];
+    y[j] = xj - w * (lt_gather<float>(j, T, x) + cj * xj);
+}
+
+void launch_apply_T_f32x(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha,
+                         const TransposeView &T, const float *x, double w, double *y, hipStream_t s) {
+    if (dim == 2)
+        hipLaunchKernelGGL(k_apply_T_f32x<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, T, x, w, y);
+    else
+        hipLaunchKernelGGL(k_apply_T_f32x<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, T, x, w, y);
+}
+
+template <int DIM>
+__device__ __forceinline__ float coef32(const StencilDev &st, const int16_t *__restrict__ alpha, int j) {
+    if (!st.c) return 0.0f;
+    int k = alpha[j];
+    return (float)st.c[((unsigned)k < (unsigned)st.K) ? k : 0];
+}
+
+// FP32 damped Jacobi sweep on A^T e = r (see k_jacobi_T)
+template <int DIM, bool FIRST, bool PACKED>
+__global__ __launch_bounds__(kBlock) void k_jacobi_T32(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
+                                                       TransposeView T, const float *__restrict__ x,
+                                                       const float *__restrict__ r, const float *__restrict__ d,
+                                                       float theta_dt, float omega, float *__restrict__ y) {
+    int ix[3];
+    int j = tile_node_a<DIM>(g, ix);
+    if (j < 0) return;
+    if (!interior_a<DIM>(g, ix)) {
+        y[j] = 0.0f;
+        return;
+    }
+    if (FIRST) {
+        y[j] = omega * r[j] / d[j];
+        return;
+    }
+    float xj = x[j];
+    float lt = lt_gather32<PACKED>(j, (int)g.s1, T, x);
+    float res = r[j] - (xj - theta_dt * (lt + coef32<DIM>(st, alpha, j) * xj));
+    y[j] = xj + omega * res / d[j];
+}
+
+void launch_jacobi_T32(int dim, bool first, const LevelDev &g, const StencilDev &st, const int16_t *alpha,
+                       const TransposeView &T, const float *x, const float *r, const float *d, double theta_dt,
+                       double omega, float *y, hipStream_t s) {
+    const bool pk = T.ell_d16 != nullptr && dim == 2;
+    const float td = (float)theta_dt, om = (float)omega;
+#define J32(D, F, P) hipLaunchKernelGGL((k_jacobi_T32<D, F, P>), dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, \
+                                        T, x, r, d, td, om, y)
+    if (dim == 2) {
+        if (first) J32(2, true, false);
+        else if (pk) J32(2, false, true);
+        else J32(2, false, false);
+    } else {
+        if (first) J32(3, true, false); else J32(3, false, false);
+    }
+#undef J32
+}
+
+// FP32 residual y = b - A^T x (interior; 0 on the boundary)
+template <int DIM, bool PACKED>
+__global__ __launch_bounds__(kBlock) void k_resid_T32(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
+                                                      TransposeView T, const float *__restrict__ x,
+                                                      const float *__restrict__ b, float theta_dt,
+                                                      float *__restrict__ y) {
+    int ix[3];
+    int j = tile_node_a<DIM>(g, ix);
+    if (j < 0) return;
+    if (!interior_a<DIM>(g, ix)) {
+        y[j] = 0.0f;
+        return;
+    }
+    float xj = x[j];
+    float lt = lt_gather32<PACKED>(j, (int)g.s1, T, x);
+    y[j] = b[j] - (xj - theta_dt * (lt + coef32<DIM>(st, alpha, j) * xj));
+}
+
+void launch_resid_T32(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const TransposeView &T,
+                      const float *x, const float *b, double theta_dt, float *y, hipStream_t s) {
+    const bool pk = T.ell_d16 != nullptr && dim == 2;
+    const float td = (float)theta_dt;
+    if (dim == 2) {
+        if (pk)
+            hipLaunchKernelGGL((k_resid_T32<2, true>), dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, T, x, b, td, y);
+        else
+            hipLaunchKernelGGL((k_resid_T32<2, false>), dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, T, x, b, td,
+                               y);
+    } else {
+        hipLaunchKernelGGL((k_resid_T32<3, false>), dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, T, x, b, td, y);
+    }
 }
 
 }  // namespace slhjb

@@ -19,6 +19,8 @@
 
 #include <algorithm>
 #include <functional>
+#include <memory>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -1033,7 +1035,7 @@ int hjb_step(hjb_handle *hd, const double *Uprev, double *Unext, const double *f
 
 int hjb_solve(hjb_handle *hd, const double *g, const double *psi, const double *f0, const double *f1, int32_t n_steps,
               const double *dts, const double *thetas, double s, double *U_final, int16_t *policies,
-              hjb_solve_stats *st) {
+              double *values, hjb_solve_stats *st) {
     if (!hd) return fail(HJB_EINVAL, "null handle");
     if (!g || !psi || !f0 || !f1 || !dts || !thetas || !U_final) return fail(HJB_EINVAL, "null argument");
     if (n_steps < 0) return fail(HJB_EINVAL, "n_steps must be >= 0");
@@ -1052,6 +1054,7 @@ int hjb_solve(hjb_handle *hd, const double *g, const double *psi, const double *
     double *Ucur = hd->Ua, *Unx = hd->Ub, *Uold = hd->Uc;
     double t = 0.0;
     int rc = HJB_OK;
+    if (values) HIPCHK(hipMemcpyAsync(values, g, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
     for (int n = 0; n < n_steps; ++n) {
         HIPCHK(hipMemcpyAsync(Unx, psi, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
         hjb_step_stats sst{};
@@ -1063,6 +1066,8 @@ int hjb_solve(hjb_handle *hd, const double *g, const double *psi, const double *
         loc.max_cert_bound = std::max(loc.max_cert_bound, sst.cert_bound);
         if (rc != HJB_OK) break;
         if (policies) HIPCHK(hipMemcpyAsync(policies + (int64_t)n * N, acarry, (size_t)N * 2, hipMemcpyDeviceToDevice, str));
+        if (values)
+            HIPCHK(hipMemcpyAsync(values + (int64_t)(n + 1) * N, Unx, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
         std::swap(Uold, Ucur);  // Uold <- U^{n-1}
         std::swap(Ucur, Unx);   // Ucur <- U^n
         t = t + dts[n];
@@ -1113,77 +1118,226 @@ int hjb_profile_read(hjb_handle *hd, int32_t kernel, int64_t *launches, double *
     return HJB_OK;
 }
 
+}  // extern "C"
+
 // ---- adjoint ------------------------------------------------------------------------------------
 
 namespace {
 
 struct TransposeWork {
     int E = 0;
-    int32_t *cols = nullptr, *ids = nullptr, *cols_s = nullptr, *ids_s = nullptr, *colptr = nullptr;
-    double *vals = nullptr;
-    void *scratch = nullptr;
-    size_t scratch_bytes = 0;
+    TransposeBuf b{};
     std::vector<void *> mem;
+    TransposeWork() = default;
+    TransposeWork(const TransposeWork &) = delete;
+    TransposeWork &operator=(const TransposeWork &) = delete;
     ~TransposeWork() {
         for (void *p : mem) (void)hipFree(p);
     }
-    int alloc(hjb_handle *hd) {
+    TransposeView view() const {
+        return TransposeView{b.colptr, b.rows_s,    b.vals_s,     b.ell_w,
+                             b.ell_off, b.ell_rows, b.ell_vals, b.ell_vals32, b.ell_d16};
+    }
+    int alloc(hjb_handle *hd, int level, bool f32, bool pack) {
+        const LevelDev &g = hd->lev[level].g;
+        const int64_t nodes = g.N;
         E = hd->npt * (1 << hd->dim) + 1;
-        int64_t n = hd->N * (int64_t)E;
-        if (n >= ((int64_t)1 << 31)) return fail(HJB_EUNSUPPORTED, "transposed operator too large (%lld entries)", (long long)n);
-        scratch_bytes = transpose_scratch_bytes(n, (int)hd->N);
+        int64_t n = nodes * (int64_t)E;
+        const int64_t ns = ell_slices(g);
+        const int64_t ne = ns * 64 * kEllCap;  // ELL entries at most
+        if (n >= ((int64_t)1 << 31) || ne >= ((int64_t)1 << 31))
+            return fail(HJB_EUNSUPPORTED, "transposed operator too large (%lld entries)", (long long)n);
+        b.scratch_bytes = transpose_scratch_bytes(n, (int)nodes, (int)ns);
         struct R {
             void **p;
-            size_t b;
-        } req[] = {{(void **)&cols, (size_t)n * 4}, {(void **)&ids, (size_t)n * 4}, {(void **)&cols_s, (size_t)n * 4},
-                   {(void **)&ids_s, (size_t)n * 4}, {(void **)&vals, (size_t)n * 8},
-                   {(void **)&colptr, (size_t)(hd->N + 1) * 4}, {&scratch, scratch_bytes + 256}};
+            size_t bytes;
+        } req[] = {{(void **)&b.cols, (size_t)n * 4},   {(void **)&b.ids, (size_t)n * 4},
+                   {(void **)&b.cols_s, (size_t)n * 4}, {(void **)&b.ids_s, (size_t)n * 4},
+                   {(void **)&b.rows_s, (size_t)n * 4}, {(void **)&b.vals, (size_t)n * 8},
+                   {(void **)&b.vals_s, (size_t)n * 8}, {(void **)&b.colptr, (size_t)(nodes + 1) * 4},
+                   {(void **)&b.ell_w, (size_t)ns * 4}, {(void **)&b.ell_off, (size_t)ns * 4},
+                   {(void **)&b.ell_rows, (size_t)ne * 4}, {(void **)&b.ell_vals, (size_t)ne * 8},
+                   {&b.scratch, b.scratch_bytes + 256}};
         for (auto &r : req) {
-            if (hipMalloc(r.p, r.b) != hipSuccess) {
+            if (hipMalloc(r.p, r.bytes) != hipSuccess) {
                 (void)hipGetLastError();
-                return fail(HJB_ENOMEM, "adjoint workspace (%zu bytes)", r.b);
+                return fail(HJB_ENOMEM, "adjoint workspace (%zu bytes)", r.bytes);
             }
             mem.push_back(*r.p);
         }
+        b.ell_vals32 = nullptr;
+        b.ell_d16 = nullptr;
+        if (f32) {
+            if (hipMalloc((void **)&b.ell_vals32, (size_t)ne * 4) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(HJB_ENOMEM, "adjoint workspace (FP32 weights)");
+            }
+            mem.push_back(b.ell_vals32);
+        }
+        if (pack) {
+            if (hipMalloc((void **)&b.ell_d16, (size_t)ne * 2) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(HJB_ENOMEM, "adjoint workspace (packed rows)");
+            }
+            mem.push_back(b.ell_d16);
+        }
         return HJB_OK;
     }
-    int build(hjb_handle *hd, const int16_t *alpha) {
-        if (build_transpose(hd->dim, hd->lev[0].g, stencil(hd, 0), alpha, E, cols, vals, ids, cols_s, ids_s, colptr,
-                            scratch, scratch_bytes, hd->stream) != 0)
+    int build(hjb_handle *hd, int level, const int16_t *alpha) {
+        const LevelDev &g = hd->lev[level].g;
+        if (build_transpose(hd->dim, g, stencil(hd, level), alpha, E, b, hd->stream) != 0)
             return fail(HJB_EDEVICE, "radix sort of the transposed operator failed");
         HIPCHK(hipGetLastError());
+        if (hd->trace) {  // padding of the sliced ELL copy
+            const int64_t ns = ell_slices(g);
+            int32_t last[2] = {0, 0};
+            HIPCHK(hipMemcpyAsync(&last[0], b.ell_off + ns - 1, 4, hipMemcpyDeviceToHost, hd->stream));
+            HIPCHK(hipMemcpyAsync(&last[1], b.ell_w + ns - 1, 4, hipMemcpyDeviceToHost, hd->stream));
+            int32_t nnz = 0;
+            HIPCHK(hipMemcpyAsync(&nnz, b.colptr + g.N, 4, hipMemcpyDeviceToHost, hd->stream));
+            HIPCHK(hipStreamSynchronize(hd->stream));
+            fprintf(stderr, "[slhjb] level %d transposed operator: %d entries, ELL slots %lld (%.2f per entry)\n", level,
+                    nnz, (long long)(last[0] + last[1]) * 64, (double)(last[0] + last[1]) * 64.0 / std::max(1, nnz));
+        }
         return HJB_OK;
     }
 };
 
-// Solve A_alpha^T mu = b (interior) with FGMRES + Jacobi; mu starts at zero.
-int solve_transposed(hjb_handle *hd, TransposeWork &T, const int16_t *alpha, const double *b, double *mu,
+// Transposed operators of every multigrid level for one policy (coarse policies injected as in the
+// forward V-cycle), with FP64 Jacobi diagonals (diag(A^T) = diag(A)).
+struct TransposeHierarchy {
+    std::vector<std::unique_ptr<TransposeWork>> lev;
+    bool f32 = false;
+    // all_levels: V-cycle preconditioner; f32: FP32 copies for the mixed mode; pack: 2D int8 row offsets
+    int alloc(hjb_handle *hd, bool all_levels, bool f32_, bool pack) {
+        f32 = f32_;
+        size_t nl = all_levels ? hd->lev.size() : 1;
+        for (size_t l = 0; l < nl; ++l) {
+            lev.emplace_back(new TransposeWork());
+            TRY(lev.back()->alloc(hd, (int)l, f32, pack));
+        }
+        return HJB_OK;
+    }
+    int build(hjb_handle *hd, const int16_t *alpha, double theta_dt) {
+        hipStream_t s = hd->stream;
+        hd->lev[0].alpha = const_cast<int16_t *>(alpha);
+        for (size_t l = 1; l < lev.size(); ++l)
+            launch_inject_policy(hd->dim, hd->lev[l - 1].g, hd->lev[l].g, hd->lev[l - 1].alpha, hd->lev[l].alpha, s);
+        for (size_t l = 0; l < lev.size(); ++l) {
+            Level &L = hd->lev[l];
+            launch_diag<double>(hd->dim, L.g, stencil(hd, (int)l), L.alpha, theta_dt, (double *)L.d64, s);
+            if (f32) launch_diag<float>(hd->dim, L.g, stencil(hd, (int)l), L.alpha, theta_dt, (float *)L.d32, s);
+            TRY(lev[l]->build(hd, (int)l, L.alpha));
+        }
+        return HJB_OK;
+    }
+};
+
+template <typename T>
+void smooth_T(hjb_handle *hd, const TransposeHierarchy &H, int l, T *&e, T *&t, const T *r, int sweeps, bool first,
+              double theta_dt) {
+    Level &L = hd->lev[l];
+    for (int q = 0; q < sweeps; ++q) {
+        if constexpr (std::is_same<T, float>::value)
+            launch_jacobi_T32(hd->dim, first && q == 0, L.g, stencil(hd, l), L.alpha, H.lev[l]->view(), e, r,
+                              (const float *)L.d32, theta_dt, hd->desc.omega, t, hd->stream);
+        else
+            launch_jacobi_T(hd->dim, first && q == 0, L.g, stencil(hd, l), L.alpha, H.lev[l]->view(), e, r,
+                            (const double *)L.d64, theta_dt, hd->desc.omega, t, hd->stream);
+        std::swap(e, t);
+    }
+}
+
+// z = V-cycle for A^T z = v: the forward cycle's transfers and sweep counts, with damped Jacobi on the
+// transposed level operators and sweeps on the coarsest level.  T = float in the mixed mode.
+template <typename T>
+void vcycle_T(hjb_handle *hd, const TransposeHierarchy &H, const T *r0, T *z, double theta_dt) {
+    constexpr bool F = std::is_same<T, float>::value;
+    const int Lc = (int)H.lev.size() - 1;
+    const hjb_desc &d = hd->desc;
+    hipStream_t s = hd->stream;
+    std::vector<T *> e(Lc + 1), t(Lc + 1);
+    std::vector<const T *> r(Lc + 1);
+    for (int l = 0; l <= Lc; ++l) {
+        e[l] = (T *)(F ? hd->lev[l].e32 : hd->lev[l].e64);
+        t[l] = (T *)(F ? hd->lev[l].t32 : hd->lev[l].t64);
+        r[l] = (const T *)(F ? hd->lev[l].r32 : hd->lev[l].r64);
+    }
+    r[0] = r0;
+    int flips0 = Lc == 0 ? d.coarse_sweeps : d.nu1 + d.nu2;
+    if (flips0 % 2 == 0) {
+        e[0] = z;
+    } else {
+        e[0] = (T *)(F ? hd->lev[0].t32 : hd->lev[0].t64);
+        t[0] = z;
+    }
+    if (Lc == 0) {
+        smooth_T<T>(hd, H, 0, e[0], t[0], r[0], d.coarse_sweeps, true, theta_dt);
+        return;
+    }
+    for (int l = 0; l < Lc; ++l) {
+        Level &L = hd->lev[l];
+        smooth_T<T>(hd, H, l, e[l], t[l], r[l], d.nu1, true, theta_dt);
+        if constexpr (F)
+            launch_resid_T32(hd->dim, L.g, stencil(hd, l), L.alpha, H.lev[l]->view(), e[l], r[l], theta_dt, t[l], s);
+        else
+            launch_apply_T(hd->dim, 3, L.g, stencil(hd, l), L.alpha, H.lev[l]->view(), e[l], r[l], theta_dt, t[l],
+                           nullptr, s);
+        launch_restrict<T>(hd->dim, L.g, hd->lev[l + 1].g, t[l], (T *)(F ? hd->lev[l + 1].r32 : hd->lev[l + 1].r64), s);
+    }
+    smooth_T<T>(hd, H, Lc, e[Lc], t[Lc], r[Lc], d.coarse_sweeps, true, theta_dt);
+    for (int l = Lc - 1; l >= 0; --l) {
+        launch_prolong_add<T>(hd->dim, hd->lev[l].g, hd->lev[l + 1].g, e[l + 1], e[l], s);
+        smooth_T<T>(hd, H, l, e[l], t[l], r[l], d.nu2, false, theta_dt);
+    }
+}
+
+// Solve A_alpha^T mu = b (interior) with FGMRES preconditioned by the transposed V-cycle (or Jacobi,
+// following the handle's preconditioner option), starting from the given mu.
+int solve_transposed(hjb_handle *hd, TransposeHierarchy &H, const int16_t *alpha, const double *b, double *mu,
                      double theta_dt, int *its, double *res) {
     const int dim = hd->dim;
     const Level &L0 = hd->lev[0];
     const StencilDev st = stencil(hd, 0);
     hipStream_t s = hd->stream;
-    launch_diag<double>(dim, L0.g, st, alpha, theta_dt, (double *)L0.d64, s);  // diag(A^T) = diag(A)
-    launch_zero(mu, (size_t)hd->N * 8, s);
+    const TransposeView T0 = H.lev[0]->view();
     KrylovOp op;
-    op.residual = [=, &T]() {
-        launch_apply_T(dim, 2, L0.g, st, alpha, T.colptr, T.ids_s, T.vals, T.E, mu, b, theta_dt, hd->R, hd->partial, s);
+    op.residual = [=]() {
+        launch_apply_T(dim, 2, L0.g, st, alpha, T0, mu, b, theta_dt, hd->R, hd->partial, s);
     };
-    op.apply = [=, &T](const void *z, bool, double *w) {
-        launch_apply_T(dim, 0, L0.g, st, alpha, T.colptr, T.ids_s, T.vals, T.E, (const double *)z, nullptr, theta_dt, w,
-                       nullptr, s);
-    };
-    op.precond = [=](const double *v, void *z) {
-        hipLaunchKernelGGL(k_jacobi_precond64, dim3(blocks_for(hd->N)), dim3(kBlock), 0, s, v,
-                           (const double *)L0.d64, (double *)z, hd->N);
-        return HJB_OK;
+    op.apply = [=](const void *z, bool zf, double *w) {
+        if (zf)
+            launch_apply_T_f32x(dim, L0.g, st, alpha, T0, (const float *)z, theta_dt, w, s);
+        else
+            launch_apply_T(dim, 0, L0.g, st, alpha, T0, (const double *)z, nullptr, theta_dt, w, nullptr, s);
     };
     op.zf = false;
+    if (hd->desc.precond == HJB_PRECOND_VCYCLE && H.f32) {
+        op.precond = [=, &H](const double *v, void *z) {
+            launch_to_precond(v, L0.r32, true, hd->N, s);
+            vcycle_T<float>(hd, H, (const float *)L0.r32, (float *)z, theta_dt);
+            return HJB_OK;
+        };
+        op.zf = true;
+    } else if (hd->desc.precond == HJB_PRECOND_VCYCLE) {
+        op.precond = [=, &H](const double *v, void *z) {
+            vcycle_T<double>(hd, H, v, (double *)z, theta_dt);
+            return HJB_OK;
+        };
+    } else if (hd->desc.precond == HJB_PRECOND_JACOBI) {
+        op.precond = [=](const double *v, void *z) {
+            hipLaunchKernelGGL(k_jacobi_precond64, dim3(blocks_for(hd->N)), dim3(kBlock), 0, s, v,
+                               (const double *)L0.d64, (double *)z, hd->N);
+            return HJB_OK;
+        };
+    }
     bool tight = false;
     return fgmres_core(hd, op, mu, 0.0, its, res, &tight);
 }
 
 }  // namespace
+
+extern "C" {
 
 int hjb_apply_transposed(hjb_handle *hd, const int16_t *alpha, const double *x, double *y, double dt, double theta,
                          double s) {
@@ -1194,18 +1348,19 @@ int hjb_apply_transposed(hjb_handle *hd, const int16_t *alpha, const double *x, 
     TRY(build_tables(hd, s));
     TRY(check_policy(hd, alpha));
     TransposeWork T;
-    TRY(T.alloc(hd));
-    TRY(T.build(hd, alpha));
-    launch_apply_T(hd->dim, 0, hd->lev[0].g, stencil(hd, 0), alpha, T.colptr, T.ids_s, T.vals, T.E, x, nullptr,
-                   theta * dt, y, nullptr, hd->stream);
+    TRY(T.alloc(hd, 0, false, false));
+    TRY(T.build(hd, 0, alpha));
+    launch_apply_T(hd->dim, 0, hd->lev[0].g, stencil(hd, 0), alpha, T.view(), x, nullptr, theta * dt, y, nullptr,
+                   hd->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(hd->stream));
     return HJB_OK;
 }
 
 int hjb_adjoint(hjb_handle *hd, const double *g, const double *psi, const double *f0, const double *f1, int32_t n_steps,
-                const double *dts, const double *thetas, double s, const int16_t *policies, const double *dJ_dUN,
-                double *dJ_df0, double *dJ_df1, double *dJ_dg, double *dJ_ds, hjb_adjoint_stats *stats) {
+                const double *dts, const double *thetas, double s, const int16_t *policies, const double *values,
+                const double *dJ_dUN, double *dJ_df0, double *dJ_df1, double *dJ_dg, double *dJ_ds,
+                hjb_adjoint_stats *stats) {
     if (!hd) return fail(HJB_EINVAL, "null handle");
     if (!g || !psi || !f0 || !f1 || !dts || !thetas || !policies || !dJ_dUN || !dJ_df0 || !dJ_dg)
         return fail(HJB_EINVAL, "null argument");
@@ -1221,26 +1376,36 @@ int hjb_adjoint(hjb_handle *hd, const double *g, const double *psi, const double
     hipStream_t str = hd->stream;
     for (int n = 0; n < n_steps; ++n) TRY(check_policy(hd, policies + (int64_t)n * N));
     hjb_adjoint_stats loc{};
-    // values U^0..U^N, recomputed from the policy checkpoints
+    // values U^0..U^N: the forward march's, or recomputed from the policy checkpoints
     double *Us = nullptr, *lam = nullptr, *mu = nullptr;
-    if (hipMalloc((void **)&Us, (size_t)(n_steps + 1) * N * 8) != hipSuccess ||
-        hipMalloc((void **)&lam, (size_t)N * 8) != hipSuccess || hipMalloc((void **)&mu, (size_t)N * 8) != hipSuccess) {
-        (void)hipGetLastError();
-        if (Us) (void)hipFree(Us);
-        if (lam) (void)hipFree(lam);
-        return fail(HJB_ENOMEM, "adjoint value storage");
-    }
     struct Free {
         std::vector<void *> p;
         ~Free() {
             for (void *q : p) (void)hipFree(q);
         }
-    } fr{{Us, lam, mu}};
+    } fr;
+    auto get = [&](double **p, size_t bytes) -> int {
+        if (hipMalloc((void **)p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(HJB_ENOMEM, "adjoint storage (%zu bytes)", bytes);
+        }
+        fr.p.push_back(*p);
+        return HJB_OK;
+    };
+    TRY(get(&lam, (size_t)N * 8));
+    TRY(get(&mu, (size_t)N * 8));
     std::vector<double> tprev(n_steps);
-    int rc = HJB_OK;
     {
-        HIPCHK(hipMemcpyAsync(Us, g, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
         double t = 0.0;
+        for (int n = 0; n < n_steps; ++n) {
+            tprev[n] = t;
+            t = t + dts[n];
+        }
+    }
+    const double *Uv = values;
+    if (!values) {
+        TRY(get(&Us, (size_t)(n_steps + 1) * N * 8));
+        HIPCHK(hipMemcpyAsync(Us, g, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
         for (int n = 0; n < n_steps; ++n) {
             double *Un = Us + (int64_t)(n + 1) * N;
             const double *Up = Us + (int64_t)n * N;
@@ -1249,17 +1414,26 @@ int hjb_adjoint(hjb_handle *hd, const double *g, const double *psi, const double
             int its = 0;
             double res = 0.0;
             bool tight = false;
-            rc = linsolve_impl(hd, policies + (int64_t)n * N, Up, f0, f1, t, dts[n], thetas[n], Un, 0.0, &its, &res,
-                               &tight);
+            int rc = linsolve_impl(hd, policies + (int64_t)n * N, Up, f0, f1, tprev[n], dts[n], thetas[n], Un, 0.0,
+                                   &its, &res, &tight);
             loc.krylov_recompute += its;
             if (rc != HJB_OK) return rc;
-            tprev[n] = t;
-            t = t + dts[n];
         }
+        Uv = Us;
     }
-    TransposeWork T;
-    TRY(T.alloc(hd));
+    TransposeHierarchy TH;
+    {
+        // int8 row offsets need every stencil point within 127 cells (2D)
+        double reach = 0.0;
+        const double sr = s / sqrt(hd->desc.h);
+        for (double v : hd->sigma) reach = std::max(reach, fabs(sr * v));
+        for (double v : hd->drift) reach = std::max(reach, fabs(v));
+        const bool vc = hd->desc.precond == HJB_PRECOND_VCYCLE;
+        const bool f32 = vc && mixed(hd);
+        TRY(TH.alloc(hd, vc, f32, f32 && dim == 2 && reach + 2.0 <= 127.0));
+    }
     launch_mask_interior(dim, g0, dJ_dUN, lam, str);
+    launch_zero(mu, (size_t)N * 8, str);  // mu_{n+1} is the initial guess of mu_n
     launch_zero(dJ_df0, (size_t)N * 8, str);
     if (dJ_df1) launch_zero(dJ_df1, (size_t)N * 8, str);
     double ds = 0.0;
@@ -1268,25 +1442,25 @@ int hjb_adjoint(hjb_handle *hd, const double *g, const double *psi, const double
         const int16_t *alpha = policies + (int64_t)n * N;
         const double dt = dts[n], th = thetas[n];
         const double t_mid = tprev[n] + th * dt;
-        TRY(T.build(hd, alpha));
+        TRY(TH.build(hd, alpha, th * dt));
         int its = 0;
         double res = 0.0;
-        rc = solve_transposed(hd, T, alpha, lam, mu, th * dt, &its, &res);
+        int rc = solve_transposed(hd, TH, alpha, lam, mu, th * dt, &its, &res);
         loc.krylov_adjoint += its;
         loc.max_res_adjoint = std::max(loc.max_res_adjoint, res);
         if (rc != HJB_OK) return rc;
         launch_axpy_interior(dim, g0, dt, mu, dJ_df0, str);
         if (dJ_df1) launch_axpy_interior(dim, g0, dt * t_mid, mu, dJ_df1, str);
         if (dJ_ds) {
-            launch_ds_dot(dim, g0, stencil(hd, 0), alpha, mu, Us + (int64_t)(n + 1) * N, th, Us + (int64_t)n * N,
+            launch_ds_dot(dim, g0, stencil(hd, 0), alpha, mu, Uv + (int64_t)(n + 1) * N, th, Uv + (int64_t)n * N,
                           1.0 - th, inv_s, hd->partial, str);
             launch_reduce_sum(hd->partial, 1, hd->nb, hd->dvals + 200, str);
             TRY(sync_small(hd, hd->dvals + 200, hd->hpin + 200, sizeof(double)));
             ds += dt * hd->hpin[200];
         }
         // lambda_{n-1} = B_n^T mu_n on every node
-        launch_apply_T(dim, 1, g0, stencil(hd, 0), alpha, T.colptr, T.ids_s, T.vals, T.E, mu, nullptr,
-                       (1.0 - th) * dt, n > 0 ? lam : dJ_dg, nullptr, str);
+        launch_apply_T(dim, 1, g0, stencil(hd, 0), alpha, TH.lev[0]->view(), mu, nullptr, (1.0 - th) * dt,
+                       n > 0 ? lam : dJ_dg, nullptr, str);
         HIPCHK(hipGetLastError());
     }
     HIPCHK(hipStreamSynchronize(str));

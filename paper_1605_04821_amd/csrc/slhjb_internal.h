@@ -134,19 +134,55 @@ void launch_extrapolate(int dim, const LevelDev &g, const double *U1, const doub
 int blocks_for(int64_t N);
 
 // adjoint (slhjb_adjoint.hip)
-int build_transpose(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, int E, int32_t *cols,
-                    double *vals, int32_t *ids, int32_t *cols_sorted, int32_t *ids_sorted, int32_t *colptr,
-                    void *scratch, size_t scratch_bytes, hipStream_t s);
-size_t transpose_scratch_bytes(int64_t n, int N);
+// Row listing of one level's operator (slots [i*E, (i+1)*E)) and its column-sorted form.
+// The sorted entries are also laid out as sliced ELL: slice = one wavefront of the node kernels' launch
+// (remapped block * 4 + wave), width = the slice's longest column capped at kEllCap, entry q of lane l
+// at (off[slice] + q) * 64 + l; entries past the cap stay in the CSC arrays.
+constexpr int kEllCap = 32;
+// The FP32 copy (preconditioner) holds the weights as float and, in 2D when every stencil point stays
+// within 127 cells, the row as int8 offsets (dx | dy << 8) from the column node.
+struct TransposeBuf {
+    int32_t *cols, *ids, *cols_s, *ids_s, *colptr, *rows_s;
+    double *vals, *vals_s;
+    int32_t *ell_w, *ell_off, *ell_rows;
+    double *ell_vals;
+    float *ell_vals32;   // nullable: no FP32 copy
+    int16_t *ell_d16;    // nullable: rows not packed
+    void *scratch;
+    size_t scratch_bytes;
+};
+struct TransposeView {
+    const int32_t *colptr, *rows;
+    const double *vals;
+    const int32_t *ell_w, *ell_off, *ell_rows;
+    const double *ell_vals;
+    const float *ell_vals32;
+    const int16_t *ell_d16;
+};
+int build_transpose(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, int E, TransposeBuf &b,
+                    hipStream_t s);
+size_t transpose_scratch_bytes(int64_t n, int N, int nslices);
+inline int64_t ell_slices(const LevelDev &g);
 void launch_apply_T(int dim, int mode, const LevelDev &g, const StencilDev &st, const int16_t *alpha,
-                    const int32_t *colptr, const int32_t *ids, const double *vals, int E, const double *x,
-                    const double *b, double w, double *y, double *partial, hipStream_t s);
+                    const TransposeView &T, const double *x, const double *b, double w, double *y, double *partial,
+                    hipStream_t s);
+void launch_apply_T_f32x(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha,
+                         const TransposeView &T, const float *x, double w, double *y, hipStream_t s);
+void launch_jacobi_T32(int dim, bool first, const LevelDev &g, const StencilDev &st, const int16_t *alpha,
+                       const TransposeView &T, const float *x, const float *r, const float *d, double theta_dt,
+                       double omega, float *y, hipStream_t s);
+void launch_resid_T32(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const TransposeView &T,
+                      const float *x, const float *b, double theta_dt, float *y, hipStream_t s);
+void launch_jacobi_T(int dim, bool first, const LevelDev &g, const StencilDev &st, const int16_t *alpha,
+                     const TransposeView &T, const double *x, const double *r, const double *d, double theta_dt,
+                     double omega, double *y, hipStream_t s);
 void launch_ds_dot(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const double *mu,
                    const double *Va, double wa, const double *Vb, double wb, double inv_s, double *partial,
                    hipStream_t s);
 void launch_axpy_interior(int dim, const LevelDev &g, double a, const double *x, double *y, hipStream_t s);
 void launch_mask_interior(int dim, const LevelDev &g, const double *x, double *y, hipStream_t s);
 inline int tiles_for(const LevelDev &g) { return g.ntx * g.nty * g.ntz; }
+inline int64_t ell_slices(const LevelDev &g) { return (int64_t)tiles_for(g) * (kBlock / 64); }
 inline void set_tiles(LevelDev &g, int dim) {
     g.ntx = (g.n[0] + kTX - 1) / kTX;
     g.nty = (g.n[1] + kTY - 1) / kTY;

@@ -95,6 +95,6 @@ def test_null_handle_calls_fail_cleanly(slhjb):
     assert L.hjb_profile_enable(None, 0, 10) == -1
     assert L.hjb_apply(None, None, None, None, 0.1, 1.0, 1.0) == -1
     assert L.hjb_apply_transposed(None, None, None, None, 0.1, 1.0, 1.0) == -1
-    assert L.hjb_adjoint(None, None, None, None, None, 1, None, None, 1.0, None, None, None, None, None, None,
+    assert L.hjb_adjoint(None, None, None, None, None, 1, None, None, 1.0, None, None, None, None, None, None, None,
                          None) == -1
     L.hjb_destroy(None)

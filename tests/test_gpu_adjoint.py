@@ -94,17 +94,17 @@ def _lam_N(inst, UN, seed=31):
     return lam
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision,precond", [(0, 2), (1, 2), (0, 1)], ids=["fp64-vcycle", "mixed-vcycle", "fp64-jacobi"])
 @pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
-def test_adjoint_matches_oracle(slhjb, name, mk, precision):
+def test_adjoint_matches_oracle(slhjb, name, mk, precision, precond):
     inst = mk()
-    log(f"adjoint {name} n={inst.n} steps={len(inst.dts)} precision={precision}")
+    log(f"adjoint {name} n={inst.n} steps={len(inst.dts)} precision={precision} precond={precond}")
     s = S_TEST
     ref_march = oracle.march(inst, s=s, keep_policies=True)
     pols = ref_march["policies"]
     lam = _lam_N(inst, ref_march["U"])
     ref = oracle.adjoint_dense(inst, pols, lam, s=s)
-    solver = slhjb.Solver.from_instance(inst, slhjb.Options(precision=precision))
+    solver = slhjb.Solver.from_instance(inst, slhjb.Options(precision=precision, precond=precond))
     dg = torch.empty(inst.N, dtype=torch.float64, device="cuda")
     df0, df1 = torch.empty_like(dg), torch.empty_like(dg)
     ds, st = solver.adjoint(to_dev(inst.g), to_dev(inst.psi), to_dev(inst.f0), to_dev(inst.f1), inst.dts,
@@ -153,4 +153,31 @@ def test_adjoint_rejects_explicit_steps(slhjb):
     with pytest.raises(slhjb.HJBError):
         solver.adjoint(to_dev(inst.g), to_dev(inst.psi), to_dev(inst.f0), to_dev(inst.f1), inst.dts, inst.thetas,
                        1.0, pols, out, torch.empty_like(out), torch.empty_like(out))
+    solver.close()
+
+
+def test_adjoint_with_stored_values(slhjb):
+    """Passing hjb_solve's stored values gives the same gradients as recomputing them."""
+    inst = workloads.config_c2(65, n_cn=6)
+    log("adjoint with stored values c2_65")
+    solver = slhjb.Solver.from_instance(inst)
+    g, psi, f0, f1 = to_dev(inst.g), to_dev(inst.psi), to_dev(inst.f0), to_dev(inst.f1)
+    U = torch.empty_like(g)
+    pol = torch.empty((len(inst.dts), inst.N), dtype=torch.int16, device="cuda")
+    vals = torch.empty((len(inst.dts) + 1, inst.N), dtype=torch.float64, device="cuda")
+    solver.solve(g, psi, f0, f1, inst.dts, inst.thetas, 1.0, U, pol, vals)
+    np.testing.assert_array_equal(to_np(vals[-1]), to_np(U))
+    np.testing.assert_array_equal(to_np(vals[0]), inst.g)
+    lam = torch.from_numpy(_lam_N(inst, to_np(U))).cuda()
+    outs = []
+    for v in (None, vals):
+        dg, df0, df1 = torch.empty_like(g), torch.empty_like(g), torch.empty_like(g)
+        ds, st = solver.adjoint(g, psi, f0, f1, inst.dts, inst.thetas, 1.0, pol, lam, df0, dg, dJ_df1=df1, values=v)
+        log(f"  values={'stored' if v is not None else 'recomputed'}: recompute its {st.krylov_recompute}, "
+            f"adjoint its {st.krylov_adjoint}, ds {ds:.12e}")
+        outs.append((to_np(dg), to_np(df0), to_np(df1), ds))
+    assert outs[1][0] is not None
+    for a, b in zip(outs[0][:3], outs[1][:3]):
+        assert np.max(np.abs(a - b)) <= 1e-10 * max(1.0, np.max(np.abs(a)))
+    assert abs(outs[0][3] - outs[1][3]) <= 1e-9 * max(1.0, abs(outs[0][3]))
     solver.close()

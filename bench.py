@@ -8,7 +8,9 @@ FGMRES solves preconditioned by the multigrid V-cycle, each step certified to |r
 
 Modes: "mixed" (FP32 V-cycle under FP64 FGMRES; the headline value) and "fp64" (everything FP64).
 Prints one JSON line.  A kernel-timer pass inside the timed region gives the roofline of the
-dominant kernel; the CPU oracle is timed on a bounded sample (see cpu_baseline.sample).
+dominant kernel; the CPU oracle is timed on a bounded sample (see cpu_baseline.sample).  The
+"adjoint" entries time one full forward march and the discrete adjoint march after it (gradients
+with respect to f0, f1, g and s) on the 513^2 adjoint workload and on the benchmark grid.
 """
 from __future__ import annotations
 
@@ -35,6 +37,7 @@ def parse():
     ap.add_argument("--n", type=int, default=2049, help="grid nodes per axis of the 2D workload")
     ap.add_argument("--modes", default="mixed,fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost measurement")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle Krylov work in the sample")
     ap.add_argument("--pi-eta", type=float, default=None)
     ap.add_argument("--restart", type=int, default=None)
@@ -101,6 +104,45 @@ def run_mode(slhjb, inst, torch, mode, steps, warmup, args):
     return dict(mode=mode, wall_s=wall, gpu_ms=gpu_ms, steps_per_s=steps / wall, ms_per_step=1e3 * wall / steps,
                 pi_per_step=pi / steps, krylov_per_solve=kry / max(pi, 1), max_res=max(s[2] for s in stats),
                 max_cert=max(s[3] for s in stats), kernels=kern, U=Ua)
+
+
+def adjoint_cost(slhjb, torch, inst, mode, reps=1):
+    """Seconds of one full forward march (hjb_solve, keeping policies and values) and of the adjoint
+    march that follows (hjb_adjoint), after one untimed pair.  J = 1/2 |U^N - u_tgt|^2 (u_tgt = 0
+    where the workload has no target)."""
+    import numpy as np
+    prec = slhjb.PREC_MIXED if mode == "mixed" else slhjb.PREC_FP64
+    solver = slhjb.Solver.from_instance(inst, slhjb.Options(precision=prec))
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    g, psi, f0, f1 = dev(inst.g), dev(inst.psi), dev(inst.f0), dev(inst.f1)
+    tgt = dev(inst.meta["u_tgt"]) if "u_tgt" in inst.meta else torch.zeros_like(g)
+    n = len(inst.dts)
+    U = torch.empty_like(g)
+    pol = torch.empty((n, inst.N), dtype=torch.int16, device="cuda")
+    vals = torch.empty((n + 1, inst.N), dtype=torch.float64, device="cuda")
+    dg, df0, df1, lam = (torch.empty_like(g) for _ in range(4))
+    best = None
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = solver.solve(g, psi, f0, f1, inst.dts, inst.thetas, inst.s, U, pol, vals)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        torch.sub(U, tgt, out=lam)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ds, ast = solver.adjoint(g, psi, f0, f1, inst.dts, inst.thetas, inst.s, pol, lam, df0, dg, dJ_df1=df1,
+                                 values=vals)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        if r >= 1 and (best is None or t3 - t2 < best["adjoint_s"]):
+            best = {"workload": f"{inst.name} ({inst.n[0]}x{inst.n[1]}, {n} solves)", "mode": mode,
+                    "forward_s": round(t1 - t0, 4), "adjoint_s": round(t3 - t2, 4),
+                    "adjoint_over_forward": round((t3 - t2) / (t1 - t0), 3),
+                    "forward_krylov": int(st.krylov_total), "adjoint_krylov": int(ast.krylov_adjoint),
+                    "dJ_ds": ds}
+    solver.close()
+    return best
 
 
 def measured_traffic(kernel, pi_per_step):
@@ -241,6 +283,15 @@ def main():
     roof["traffic"] = measured_traffic(dom_name, head["pi_per_step"])
     stencil_roof = {k: {"achieved_gbs": round(kern[k]["gbs"], 1), "frac": round(kern[k]["gbs"] / HBM_PEAK_GBS, 4),
                         "avg_us": round(kern[k]["avg_us"], 2)} for k in ("apply", "smooth", "mg_residual") if k in kern}
+    adj = None
+    if not args.no_adjoint:
+        adj = []
+        for wl, mode in ((workloads.config_c3(513), "mixed"), (inst, "mixed")):
+            print(f"[bench] adjoint cost {wl.name} {mode}", file=sys.stderr, flush=True)
+            a = adjoint_cost(slhjb, torch, wl, mode)
+            print(f"[bench]   forward {a['forward_s']:.3f} s, adjoint {a['adjoint_s']:.3f} s "
+                  f"({a['adjoint_over_forward']:.2f}x)", file=sys.stderr, flush=True)
+            adj.append(a)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
@@ -265,6 +316,7 @@ def main():
                         for k, v in res[m]["kernels"].items()} for m in res},
         "roofline": roof,
         "stencil_kernels_hbm": stencil_roof,
+        "adjoint": adj,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

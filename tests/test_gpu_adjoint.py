@@ -27,7 +27,7 @@ def slhjb():
     return m
 
 
-def _toy(n, K, P, seed, drift=True, c=False, n_steps=3):
+def _toy(n, K, P, seed, drift=True, c=False, n_steps=3, thetas=None):
     rng = np.random.default_rng(seed)
     dim = len(n)
     N = int(np.prod(n))
@@ -36,7 +36,7 @@ def _toy(n, K, P, seed, drift=True, c=False, n_steps=3):
     b = rng.normal(size=(K, dim)) * 0.4 if drift else None
     cc = -rng.uniform(0.0, 1.0, size=K) if c else None
     dts = np.full(n_steps, 0.05)
-    thetas = np.array([1.0] + [0.5] * (n_steps - 1))
+    thetas = np.array([1.0] + [0.5] * (n_steps - 1)) if thetas is None else np.asarray(thetas, float)
     inst = workloads.Instance(name=f"toy{n}", dim=dim, n=tuple(n), lo=(0.0,) * dim, h=h, K=K, P=P, sigma=sig,
                               drift=b, c=cc, f0=rng.normal(size=N), f1=rng.normal(size=N), g=rng.normal(size=N),
                               psi=np.zeros(N), dts=dts, thetas=thetas)
@@ -49,6 +49,7 @@ CASES = [
     ("c2_33_cn", lambda: workloads.config_c2(33, n_cn=8)),
     ("ragged_2d_c", lambda: _toy((37, 29), K=7, P=2, seed=3, c=True)),
     ("ragged_3d", lambda: _toy((11, 9, 13), K=5, P=1, seed=4)),
+    ("cn_first_2d", lambda: _toy((23, 19), K=6, P=1, seed=8, c=True, thetas=[0.5, 0.5, 1.0])),
 ]
 
 

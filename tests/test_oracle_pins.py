@@ -348,3 +348,77 @@ def test_observed_order_one_under_refinement():
         errs.append(_err(inst))
     rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert all(0.6 < r < 1.6 for r in rates), (errs, rates)
+
+
+# ---------------------------------------------------------------------------
+# Adjoint oracle (fixed-policy discrete adjoint of the theta-march, eq. FullScheme)
+# ---------------------------------------------------------------------------
+
+def _adjoint_toy(seed=7, n=(11, 9), c=True):
+    rng = np.random.default_rng(seed)
+    dim = len(n)
+    N = int(np.prod(n))
+    K, P = 4, 2
+    inst = workloads.Instance(name="adj_toy", dim=dim, n=tuple(n), lo=(0.0,) * dim, h=1.0 / (max(n) - 1), K=K, P=P,
+                              sigma=rng.normal(size=(K, P, dim)), drift=rng.normal(size=(K, dim)) * 0.4,
+                              c=(-rng.uniform(0.0, 1.0, size=K) if c else None), f0=rng.normal(size=N),
+                              f1=rng.normal(size=N), g=rng.normal(size=N), psi=np.zeros(N),
+                              dts=np.array([0.04, 0.05, 0.05]), thetas=np.array([1.0, 0.5, 0.5]))
+    inst.psi = np.where(inst.boundary_mask(), rng.normal(size=N) * 0.3, 0.0)
+    pols = np.stack([workloads.random_policy(inst, seed + 1 + k) for k in range(len(inst.dts))])
+    lam = rng.normal(size=N)
+    lam[inst.boundary_mask()] = 0.0
+    return inst, pols, lam
+
+
+def test_fixed_policy_march_reproduces_march():
+    inst = workloads.config_c2(17, n_cn=3)
+    r = oracle.march(inst, keep_policies=True, keep_values=True)
+    vals = oracle.fixed_policy_march(inst, r["policies"])
+    for a, b in zip(vals, r["values"]):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("n", [(11, 9), (7, 6, 5)])
+def test_adjoint_equals_directional_derivatives(n):
+    """At fixed policies U^N is affine in (g, f0, f1), so lam . U^N(x + e) - lam . U^N(x) equals the adjoint's
+    gradient dotted with e for any e, up to the solves' rounding."""
+    inst, pols, lam = _adjoint_toy(n=n)
+    ref = oracle.adjoint_dense(inst, pols, lam)
+    J0 = float(lam @ oracle.fixed_policy_march(inst, pols)[-1])
+    rng = np.random.default_rng(3)
+    for field, key in (("g", "dg"), ("f0", "df0"), ("f1", "df1")):
+        e = rng.normal(size=inst.N)
+        pert = workloads.Instance(**{**inst.__dict__})
+        setattr(pert, field, getattr(inst, field) + e)
+        J1 = float(lam @ oracle.fixed_policy_march(pert, pols)[-1])
+        pred = float(ref[key] @ e)
+        assert abs((J1 - J0) - pred) <= 1e-10 * max(1.0, abs(pred)), (field, J1 - J0, pred)
+    # boundary entries of the f-gradients vanish (f enters interior rows only); the first step is
+    # implicit (theta = 1), whose explicit part is U^0 at the node itself, so dg vanishes there too
+    bd = inst.boundary_mask()
+    assert np.all(ref["df0"][bd] == 0.0) and np.all(ref["df1"][bd] == 0.0)
+    assert inst.thetas[0] == 1.0 and np.all(ref["dg"][bd] == 0.0)
+
+
+def test_adjoint_boundary_gradient_for_crank_nicolson_start():
+    """With theta < 1 in the first step the explicit part reads U^0 on boundary nodes: dg there is the
+    directional derivative along boundary perturbations."""
+    inst, pols, lam = _adjoint_toy(seed=5)
+    inst.thetas = np.array([0.5, 0.5, 1.0])
+    ref = oracle.adjoint_dense(inst, pols, lam)
+    bd = inst.boundary_mask()
+    assert np.any(ref["dg"][bd] != 0.0)
+    e = np.where(bd, np.random.default_rng(9).normal(size=inst.N), 0.0)
+    J0 = float(lam @ oracle.fixed_policy_march(inst, pols)[-1])
+    pert = workloads.Instance(**{**inst.__dict__})
+    pert.g = inst.g + e
+    J1 = float(lam @ oracle.fixed_policy_march(pert, pols)[-1])
+    assert abs((J1 - J0) - float(ref["dg"] @ e)) <= 1e-10 * max(1.0, abs(J1 - J0))
+
+
+def test_s_central_difference_is_converged():
+    inst, pols, lam = _adjoint_toy(seed=11)
+    a = oracle.ds_central_difference(inst, pols, lam, 0.93, eps=1e-5)
+    b = oracle.ds_central_difference(inst, pols, lam, 0.93, eps=5e-6)
+    assert abs(a - b) <= 1e-7 * max(1.0, abs(a))

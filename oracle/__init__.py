@@ -108,7 +108,9 @@ class Problem:
     """Grid + coefficients of one instance, marshalled for the C oracle.
 
     sigma: (K,P,dim) per control, or sigma_node (N,P,dim) shared by all controls;
-    drift: (K,dim) or None; c: (K,) or None.  s scales sigma.
+    drift: (K,dim) or None; c: (K,) or None.  s scales sigma.  With coef_model "xscaled" the
+    coefficients at node x are sigma_k(x) = diag(x) S_k and b_k(x) = diag(x) beta_k (S = sigma,
+    beta = drift), expanded here into per-node arrays.
     """
 
     def __init__(self, inst, s: Optional[float] = None):
@@ -124,16 +126,26 @@ class Problem:
             st.n[d] = self.n[d] if d < self.dim else 1
         st.h = self.h
         st.sr = self.s * (1.0 / math.sqrt(self.h))
-        if inst.sigma is not None:
+        xs = getattr(inst, "coef_model", "const") == "xscaled"
+        if xs:
+            # sigma_k(x)_{:,p} = x * S_{k,p}, b_k(x) = x * beta_k (elementwise), per node
+            X = np.stack(inst.coords(), axis=-1)                                   # (N, dim)
+            self._sigma = np.ascontiguousarray(X[None, :, None, :] * _f64(inst.sigma)[:, None, :, :])
+            st.sig_k, st.sig_i = self.N * self.P * self.dim, self.P * self.dim
+        elif inst.sigma is not None:
             self._sigma = _f64(inst.sigma)
             st.sig_k, st.sig_i = self.P * self.dim, 0
         else:
             self._sigma = _f64(inst.sigma_node)
             st.sig_k, st.sig_i = 0, self.P * self.dim
         st.sigma = self._sigma.ctypes.data
-        self._drift = _f64(inst.drift)
+        if xs and inst.drift is not None:
+            self._drift = np.ascontiguousarray(X[None, :, :] * _f64(inst.drift)[:, None, :])
+            st.b_k, st.b_i = self.N * self.dim, self.dim
+        else:
+            self._drift = _f64(inst.drift)
+            st.b_k, st.b_i = self.dim, 0
         st.drift = None if self._drift is None else self._drift.ctypes.data
-        st.b_k, st.b_i = self.dim, 0
         self._c = _f64(inst.c)
         st.c = None if self._c is None else self._c.ctypes.data
         st.c_k, st.c_i = 1, 0

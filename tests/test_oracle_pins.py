@@ -141,6 +141,52 @@ def test_operator_exact_on_affine_and_bilinear(dim):
                     np.testing.assert_allclose(val[I], expect, rtol=1e-9, atol=1e-9)
 
 
+def test_xscaled_operator_exact_on_affine_and_bilinear():
+    """x-dependent coefficients sigma_k(x) = diag(x) S_k, b_k(x) = diag(x) beta_k: the same closed forms hold
+    node by node with the node's own sigma and b (consistency is pointwise)."""
+    inst = workloads.c4_instance(17, 0.15, 0.3, 0.4, 0.03)
+    inst.drift = inst.drift * 40.0   # drift of several cells, so that its truncation is exercised too
+    inst.s = 1.1
+    pb = oracle.Problem(inst)
+    X = inst.coords()
+    I = pb.interior
+    for k in range(inst.K):
+        alpha = np.full(pb.N, k, np.int16)
+        L = pb.assemble(alpha)
+        mub = np.array([pb.weights(int(i), k)["mu_b"] for i in I])
+        sig = [[X[a][I] * inst.sigma[k, p, a] for a in range(2)] for p in range(inst.P)]
+        b = [X[a][I] * inst.drift[k, a] for a in range(2)]
+        for a in range(2):
+            for val in (pb.lhat(X[a], k0=k), L @ X[a]):
+                np.testing.assert_allclose(val[I], b[a], rtol=1e-9, atol=1e-9)
+        phi = X[0] * X[1]
+        expect = (inst.s ** 2 * sum(sig[p][0] * sig[p][1] for p in range(inst.P))
+                  + b[0] * X[1][I] + b[1] * X[0][I] + mub * inst.h * b[0] * b[1])
+        for val in (pb.lhat(phi, k0=k), L @ phi):
+            np.testing.assert_allclose(val[I], expect, rtol=1e-9, atol=1e-9)
+    assert np.any(mub < 1.0)
+
+
+def test_c4_batch_draws():
+    """Batch recipe: sizes from the stated set, parameter ranges, control encoding and payoff data."""
+    b = workloads.config_c4(count=16)
+    assert len(b) == 16 and {i.n[0] for i in b} <= {65, 129, 257, 513}
+    for inst in b:
+        m = inst.meta
+        assert 0.1 <= m["sig_min"] <= 0.2 and 0.1 <= m["sig_max"] - m["sig_min"] <= 0.2
+        assert 0.3 <= m["rho_bar"] <= 0.5 and 0.0 <= m["r"] <= 0.05
+        S = inst.sigma
+        for k in range(8):
+            a = 0.5 * S[k].T @ S[k]          # a = 1/2 sum_p S_p S_p^T (at x = 1)
+            s1 = m["sig_max"] if k & 1 else m["sig_min"]
+            s2 = m["sig_max"] if k & 2 else m["sig_min"]
+            rho = m["rho_bar"] if k & 4 else -m["rho_bar"]
+            np.testing.assert_allclose(a, 0.5 * np.array([[s1 * s1, rho * s1 * s2], [rho * s1 * s2, s2 * s2]]),
+                                       rtol=1e-14, atol=1e-16)
+        X = inst.coords()
+        np.testing.assert_array_equal(inst.g, np.maximum(X[0] - X[1], 0.0))
+
+
 def test_operator_exact_on_squares_for_integer_axis_steps():
     """With axis-aligned integer steps every landing point is a node, so x_a^2 is reproduced:
     L-hat x_a^2 = s^2 sigma_a^2 exactly, also in truncated rows (eq. AB2)."""
@@ -249,6 +295,19 @@ def test_policy_iteration_equals_brute_force(theta, cfg):
     Vb = oracle.brute_force_step(pb, inst.g, inst.psi, inst.f0, inst.f1, 0.2, dt, theta)
     np.testing.assert_allclose(V, Vb, rtol=1e-11, atol=1e-11)
     assert st.pi_iters >= 1
+
+
+def test_policy_iteration_equals_brute_force_xscaled():
+    """Same characterisation for the x-scaled two-asset model (8 controls, 4 interior nodes), with a
+    random g so that the step is not trivial."""
+    inst = workloads.c4_instance(4, 0.15, 0.35, 0.45, 0.04)
+    inst.g = np.random.default_rng(21).normal(size=inst.N)
+    pb = oracle.Problem(inst)
+    alpha0 = np.zeros(pb.N, np.int16)
+    alpha0[pb.bd] = -1
+    V, alpha, st = oracle.step(pb, inst.g, inst.psi, inst.f0, inst.f1, 0.0, 0.25, 1.0, alpha0)
+    Vb = oracle.brute_force_step(pb, inst.g, inst.psi, inst.f0, inst.f1, 0.0, 0.25, 1.0)
+    np.testing.assert_allclose(V, Vb, rtol=1e-11, atol=1e-11)
 
 
 def test_policy_iteration_is_monotone_and_terminates():

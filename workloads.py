@@ -51,6 +51,8 @@ class Instance:
     thetas: np.ndarray           # (n_steps,)
     s: float = 1.0               # volatility scale multiplying sigma
     sigma_node: Optional[np.ndarray] = None   # (N, P, dim): x-dependent, control-independent sigma
+    coef_model: str = "const"    # "const": sigma, drift per control; "xscaled": sigma_k(x) = diag(x) S_k,
+                                 # b_k(x) = diag(x) beta_k with S = sigma (K, P, dim), beta = drift (K, dim)
     exact: Optional[callable] = None          # closed-form u(t, X) if known, X = coordinate arrays
     meta: dict = dataclasses.field(default_factory=dict)
 
@@ -305,6 +307,54 @@ def problem_b(Nx: int, dt: Optional[float] = None, theta: float = 1.0, n_alpha: 
 # ---------------------------------------------------------------------------
 # Generic random fields for parity tests
 # ---------------------------------------------------------------------------
+
+def c4_instance(n: int, sig_min: float, sig_max: float, rho_bar: float, r: float, n_steps: int = 50,
+                T: float = 1.0, name: str = "c4") -> Instance:
+    """Two-asset model with uncertain volatilities and correlation on [0,4]^2 (x-scaled coefficients).
+
+    Control k: bit 0 picks sigma_1, bit 1 picks sigma_2 in {sig_min, sig_max}, bit 2 picks
+    rho in {-rho_bar, +rho_bar}.  a = 1/2 sigma sigma^T with the Cholesky columns S_1 = (s1, rho s2),
+    S_2 = (0, sqrt(1 - rho^2) s2) scaled by diag(x); drift diag(x) (r, r); c = -r; f = 0;
+    g = psi = max(x_1 - x_2, 0); theta = 1 with dt = T / n_steps.
+    """
+    shape, lo, h = (n, n), (0.0, 0.0), 4.0 / (n - 1)
+    K, P = 8, 2
+    S = np.zeros((K, P, 2))
+    beta = np.zeros((K, 2))
+    for k in range(K):
+        s1 = sig_max if (k & 1) else sig_min
+        s2 = sig_max if (k & 2) else sig_min
+        rho = rho_bar if (k & 4) else -rho_bar
+        S[k, 0] = (s1, rho * s2)
+        S[k, 1] = (0.0, math.sqrt(1.0 - rho * rho) * s2)
+        beta[k] = (r, r)
+    inst = Instance(name=f"{name}_{n}", dim=2, n=shape, lo=lo, h=h, K=K, P=P, sigma=S, drift=beta,
+                    c=np.full(K, -r), f0=None, f1=None, g=None, psi=None,
+                    dts=np.full(n_steps, T / n_steps), thetas=np.ones(n_steps), coef_model="xscaled")
+    X = inst.coords()
+    payoff = np.maximum(X[0] - X[1], 0.0)
+    inst.f0 = np.zeros(inst.N)
+    inst.f1 = np.zeros(inst.N)
+    inst.g = payoff.copy()
+    inst.psi = np.where(inst.boundary_mask(), payoff, 0.0)
+    inst.meta.update(sig_min=sig_min, sig_max=sig_max, rho_bar=rho_bar, r=r)
+    return inst
+
+
+def config_c4(count: int = 64, seed: int = 4821, sizes=(65, 129, 257, 513), n_steps: int = 50):
+    """Batch of `count` uneven two-asset instances (see c4_instance); per instance the draw order is
+    n, sig_min ~ U[.1,.2], sig_max = sig_min + U[.1,.2], rho_bar ~ U[.3,.5], r ~ U[0,.05]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(count):
+        n = int(rng.choice(np.asarray(sizes)))
+        smin = float(rng.uniform(0.1, 0.2))
+        smax = smin + float(rng.uniform(0.1, 0.2))
+        rho = float(rng.uniform(0.3, 0.5))
+        r = float(rng.uniform(0.0, 0.05))
+        out.append(c4_instance(n, smin, smax, rho, r, n_steps=n_steps, name=f"c4b{b}"))
+    return out
+
 
 def random_fields(inst: Instance, seed: int, scale: float = 1.0):
     """Seeded smooth-plus-noise fields (X, U) with the instance's boundary data, for operator tests."""

@@ -49,7 +49,12 @@ enum {
     HJB_EUNSUPPORTED = -7     /* valid request this build does not implement */
 };
 
-enum { HJB_COEF_CONST = 0 };                    /* sigma, b, c constant per control */
+enum {
+    HJB_COEF_CONST = 0,     /* sigma, b, c constant per control */
+    HJB_COEF_XSCALED = 1    /* sigma_k(x) = diag(x) S_k, b_k(x) = diag(x) beta_k (x the node's coordinates,
+                               eq. 1.1 with x-dependent coefficients): sigma holds S, drift holds beta;
+                               c constant per control */
+};
 enum { HJB_PREC_FP64 = 0, HJB_PREC_MIXED = 1 }; /* V-cycle in FP64, or in FP32 under FP64 FGMRES */
 enum { HJB_PRECOND_NONE = 0, HJB_PRECOND_JACOBI = 1, HJB_PRECOND_VCYCLE = 2 };
 
@@ -61,8 +66,8 @@ typedef struct {
     double h;
     /* Controls (Section 1, definition of L): K controls, P diffusion columns each.
        sigma[(k*P + p)*dim + d] (host, K*P*dim), drift[k*dim + d] (host, K*dim, may be NULL = no drift),
-       c[k] (host, K, may be NULL = 0).  Only Scheme 2 (scheme = 2) is provided: its truncation is the
-       consistent one (Prop. pro:scheme2). */
+       c[k] (host, K, may be NULL = 0); coef_model: HJB_COEF_* (how sigma and drift depend on x).
+       Only Scheme 2 (scheme = 2) is provided: its truncation is the consistent one (Prop. pro:scheme2). */
     int32_t K, P, coef_model, scheme;
     const double *sigma, *drift, *c;
     /* Solver controls. */

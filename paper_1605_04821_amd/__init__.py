@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libslhjb.so")
 HJB_OK, HJB_EINVAL, HJB_EDEVICE, HJB_ENOMEM = 0, -1, -2, -3
 HJB_ENOCONV_KRYLOV, HJB_ENOCONV_PI, HJB_ENONFINITE, HJB_EUNSUPPORTED = -4, -5, -6, -7
 PREC_FP64, PREC_MIXED = 0, 1
+COEF_CONST, COEF_XSCALED = 0, 1
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_VCYCLE = 0, 1, 2
 
 EXPORTED = ["hjb_desc_default", "hjb_setup", "hjb_set_stream", "hjb_set_options", "hjb_policy_sweep", "hjb_apply",
@@ -146,7 +147,8 @@ class Solver:
     dim, n, lo, h: the box grid; sigma (K,P,dim), drift (K,dim) or None, c (K,) or None: host arrays.
     """
 
-    def __init__(self, dim, n, lo, h, sigma, drift=None, c=None, options: Optional[Options] = None):
+    def __init__(self, dim, n, lo, h, sigma, drift=None, c=None, options: Optional[Options] = None,
+                 coef_model: int = COEF_CONST):
         self.options = options or Options()
         sigma = np.ascontiguousarray(sigma, dtype=np.float64)
         K, P, dd = sigma.shape
@@ -167,6 +169,7 @@ class Solver:
             desc.lo[a] = float(lo[a]) if a < dim else 0.0
         desc.h = self.h
         desc.K, desc.P = K, P
+        desc.coef_model = int(coef_model)
         desc.sigma = self._sigma.ctypes.data
         desc.drift = None if self._drift is None else self._drift.ctypes.data
         desc.c = None if self._c is None else self._c.ctypes.data
@@ -188,8 +191,9 @@ class Solver:
     @classmethod
     def from_instance(cls, inst, options: Optional[Options] = None):
         if inst.sigma is None:
-            raise ValueError("the HIP path takes control-constant sigma")
-        return cls(inst.dim, inst.n, inst.lo, inst.h, inst.sigma, inst.drift, inst.c, options)
+            raise ValueError("the HIP path takes per-control sigma tables (constant or x-scaled)")
+        cm = COEF_XSCALED if getattr(inst, "coef_model", "const") == "xscaled" else COEF_CONST
+        return cls(inst.dim, inst.n, inst.lo, inst.h, inst.sigma, inst.drift, inst.c, options, coef_model=cm)
 
     def set_options(self, options: Options):
         self._fill_options(self._desc, options)

@@ -127,10 +127,11 @@ __device__ double dlhat_ds(const LevelDev &g, const StencilDev &st, int k, int i
     double Vi = V[i];
     Dual acc = dmk(0.0, 0.0);
     for (int p = 0; p < st.P; ++p) {
-        const PointTab &a = pt[2 * p];
-        const PointTab &b = pt[2 * p + 1];
-        double Ya[3] = {a.Y[0], a.Y[1], a.Y[2]}, dYa[3] = {a.Y[0] * inv_s, a.Y[1] * inv_s, a.Y[2] * inv_s};
-        double Yb[3] = {b.Y[0], b.Y[1], b.Y[2]}, dYb[3] = {b.Y[0] * inv_s, b.Y[1] * inv_s, b.Y[2] * inv_s};
+        double Ya[3], Yb[3];
+        point_Y(st, pt[2 * p], 2 * p, ix, DIM, Ya);
+        point_Y(st, pt[2 * p + 1], 2 * p + 1, ix, DIM, Yb);
+        double dYa[3] = {Ya[0] * inv_s, Ya[1] * inv_s, Ya[2] * inv_s};
+        double dYb[3] = {Yb[0] * inv_s, Yb[1] * inv_s, Yb[2] * inv_s};
         int cp[3], cm[3];
         Dual tp[3], tm[3];
         Dual mup = landing_dual<DIM>(g, ix, Ya, dYa, cp, tp);
@@ -254,13 +255,15 @@ __global__ __launch_bounds__(kBlock) void k_emit_rows(LevelDev g, StencilDev st,
     int e = 0;
     double diag = 0.0;
     for (int q = 0; q < st.npt; ++q) {
-        double Y[3] = {pt[q].Y[0], pt[q].Y[1], pt[q].Y[2]};
+        double Y[3];
+        point_Y(st, pt[q], q, ix, DIM, Y);
         int cell[3];
         double t[3];
         double mu = landing_plain<DIM>(g, ix, Y, cell, t);
         double W;
         if (q < 2 * st.P) {
-            double Yo[3] = {pt[q ^ 1].Y[0], pt[q ^ 1].Y[1], pt[q ^ 1].Y[2]};
+            double Yo[3];
+            point_Y(st, pt[q ^ 1], q ^ 1, ix, DIM, Yo);
             int co[3];
             double to[3];
             double muo = landing_plain<DIM>(g, ix, Yo, co, to);

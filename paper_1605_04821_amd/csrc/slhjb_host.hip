@@ -140,15 +140,16 @@ void fill_tables(hjb_handle *hd, double s, std::vector<PointTab> &host, int leve
         for (int q = 0; q < npt; ++q) {
             PointTab &p = host[(size_t)k * npt + q];
             for (int a = 0; a < 3; ++a) p.Y[a] = 0.0;
+            const bool xs = d.coef_model == HJB_COEF_XSCALED;  // table holds S and beta (see point_Y)
             if (q < 2 * P) {
                 int pp = q / 2;  // points 2p and 2p+1 are x + y_p and x - y_p
                 for (int a = 0; a < dim; ++a) {
-                    double Y = sr * d.sigma[((size_t)k * P + pp) * dim + a];
+                    double Y = xs ? d.sigma[((size_t)k * P + pp) * dim + a] : sr * d.sigma[((size_t)k * P + pp) * dim + a];
                     if (q & 1) Y = -Y;
-                    p.Y[a] = Y * scale;
+                    p.Y[a] = xs ? Y : Y * scale;
                 }
             } else {
-                for (int a = 0; a < dim; ++a) p.Y[a] = hd->drift[(size_t)k * dim + a] * scale;
+                for (int a = 0; a < dim; ++a) p.Y[a] = xs ? hd->drift[(size_t)k * dim + a] : hd->drift[(size_t)k * dim + a] * scale;
             }
             int64_t off = 0;
             for (int a = 0; a < 3; ++a) {
@@ -177,7 +178,10 @@ int build_tables(hjb_handle *hd, double s) {
         for (const PointTab &p : host)
             for (int a = 0; a < 3; ++a) E[a] = std::max(E[a], fabs(p.Y[a]));
         for (int a = 0; a < 3; ++a) {
-            if (a < hd->dim) {
+            if (a < hd->dim && hd->desc.coef_model == HJB_COEF_XSCALED) {
+                L.g.deep_lo[a] = 1;  // displacements vary per node: no precomputed fast path
+                L.g.deep_hi[a] = 0;
+            } else if (a < hd->dim) {
                 int lo = (int)ceil(E[a]);
                 int hi = L.g.n[a] - 2 - (int)floor(E[a]);
                 L.g.deep_lo[a] = std::max(1, lo);
@@ -224,6 +228,11 @@ StencilDev stencil(const hjb_handle *hd, int level) {
     st.npt = hd->npt;
     st.has_drift = hd->has_drift ? 1 : 0;
     st.inv2h = 0.5 / hd->desc.h;
+    st.xs = hd->desc.coef_model == HJB_COEF_XSCALED ? 1 : 0;
+    st.sr = hd->s_tab * (1.0 / sqrt(hd->desc.h));
+    st.scale = ldexp(1.0, -level);
+    for (int a = 0; a < 3; ++a) st.lo[a] = hd->desc.lo[a];
+    st.hl = ldexp(hd->desc.h, level);
     return st;
 }
 
@@ -793,7 +802,8 @@ int hjb_setup(const hjb_desc *desc, hjb_handle **out) {
     if (d.K < 1 || d.K > 32767) return fail(HJB_EINVAL, "K must be in 1..32767");
     if (d.P < 1 || d.P > kMaxP) return fail(HJB_EINVAL, "P must be in 1..%d", kMaxP);
     if (d.scheme != 2) return fail(HJB_EUNSUPPORTED, "only Scheme 2 is provided (consistent truncation)");
-    if (d.coef_model != HJB_COEF_CONST) return fail(HJB_EUNSUPPORTED, "only constant-per-control coefficients");
+    if (d.coef_model != HJB_COEF_CONST && d.coef_model != HJB_COEF_XSCALED)
+        return fail(HJB_EUNSUPPORTED, "coefficient model %d is not provided", d.coef_model);
     if (!d.sigma) return fail(HJB_EINVAL, "sigma is required");
     TRY(check_options(&d));
     for (int64_t q = 0; q < (int64_t)d.K * d.P * d.dim; ++q)
@@ -1424,10 +1434,16 @@ int hjb_adjoint(hjb_handle *hd, const double *g, const double *psi, const double
     TransposeHierarchy TH;
     {
         // int8 row offsets need every stencil point within 127 cells (2D)
-        double reach = 0.0;
+        double reach = 0.0, xmax = 1.0;
         const double sr = s / sqrt(hd->desc.h);
-        for (double v : hd->sigma) reach = std::max(reach, fabs(sr * v));
-        for (double v : hd->drift) reach = std::max(reach, fabs(v));
+        if (hd->desc.coef_model == HJB_COEF_XSCALED) {
+            xmax = 0.0;
+            for (int a = 0; a < dim; ++a)
+                xmax = std::max(xmax, std::max(fabs(hd->desc.lo[a]),
+                                               fabs(hd->desc.lo[a] + (hd->desc.n[a] - 1) * hd->desc.h)));
+        }
+        for (double v : hd->sigma) reach = std::max(reach, fabs(sr * v) * xmax);
+        for (double v : hd->drift) reach = std::max(reach, fabs(v) * xmax);
         const bool vc = hd->desc.precond == HJB_PRECOND_VCYCLE;
         const bool f32 = vc && mixed(hd);
         TRY(TH.alloc(hd, vc, f32, f32 && dim == 2 && reach + 2.0 <= 127.0));

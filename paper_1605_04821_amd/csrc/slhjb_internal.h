@@ -56,7 +56,37 @@ struct StencilDev {
     const double *c;      // [K] or nullptr
     int32_t K, P, npt, has_drift;
     double inv2h;         // 1/(2h) of the finest grid: coarse levels keep the physical displacement
+    // x-scaled coefficients (sigma_k(x) = diag(x) S_k, b_k(x) = diag(x) beta_k): the table holds S (signed)
+    // and beta; displacements are formed per node, see point_Y
+    int32_t xs;
+    double sr;            // s / sqrt(h) of the finest grid
+    double scale;         // 2^-level: displacements in this level's cells
+    double lo[3], hl;     // node coordinates on this level: x = lo + i * hl
 };
+
+// Displacement in cells of stencil point q (table entry p) at node ix.  Constant coefficients: the
+// table's value.  x-scaled: sr * (x * S) for diffusion points and x * beta for the drift point, per
+// axis, then the level scale (exact: a power of two).
+__device__ __forceinline__ void point_Y(const StencilDev &st, const PointTab &p, int q, const int ix[3], int dim,
+                                        double Y[3]) {
+    if (!st.xs) {
+        Y[0] = p.Y[0];
+        Y[1] = p.Y[1];
+        Y[2] = p.Y[2];
+        return;
+    }
+    const bool diffusion = q < 2 * st.P;
+    for (int d = 0; d < 3; ++d) {
+        if (d < dim) {
+            double x = st.lo[d] + (double)ix[d] * st.hl;
+            double v = x * p.Y[d];
+            if (diffusion) v = st.sr * v;
+            Y[d] = v * st.scale;
+        } else {
+            Y[d] = 0.0;
+        }
+    }
+}
 
 // ---- kernel launchers (slhjb_kernels.hip) ----------------------------------------------------
 

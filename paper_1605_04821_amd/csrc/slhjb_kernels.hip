@@ -225,10 +225,9 @@ __device__ __forceinline__ void lhat_node(const LevelDev &g, const StencilDev &s
         }
     } else {
         for (int p = 0; p < st.P; ++p) {
-            const PointTab &a = pt[2 * p];
-            const PointTab &b = pt[2 * p + 1];
-            double Ya[3] = {a.Y[0], a.Y[1], a.Y[2]};
-            double Yb[3] = {b.Y[0], b.Y[1], b.Y[2]};
+            double Ya[3], Yb[3];
+            point_Y(st, pt[2 * p], 2 * p, ix, DIM, Ya);
+            point_Y(st, pt[2 * p + 1], 2 * p + 1, ix, DIM, Yb);
             int cp[3], cm[3];
             double tp[3], tm[3];
             double mup = landing<DIM>(g, ix, Ya, cp, tp);
@@ -246,8 +245,8 @@ __device__ __forceinline__ void lhat_node(const LevelDev &g, const StencilDev &s
             }
         }
         if (st.has_drift) {
-            const PointTab &c = pt[2 * st.P];
-            double Yc[3] = {c.Y[0], c.Y[1], c.Y[2]};
+            double Yc[3];
+            point_Y(st, pt[2 * st.P], 2 * st.P, ix, DIM, Yc);
             int cb[3];
             double tb[3];
             double mub = landing<DIM>(g, ix, Yc, cb, tb);
@@ -620,13 +619,15 @@ __global__ __launch_bounds__(kBlock) void k_diag(LevelDev g, StencilDev st, cons
     const PointTab *pt = st.tab + k * st.npt;
     double lii = 0.0;
     for (int q = 0; q < st.npt; ++q) {
-        double Y[3] = {pt[q].Y[0], pt[q].Y[1], pt[q].Y[2]};
+        double Y[3];
+        point_Y(st, pt[q], q, ix, DIM, Y);
         int cell[3];
         double t[3];
         double mu = landing<DIM>(g, ix, Y, cell, t);
         double W;
         if (q < 2 * st.P) {
-            double Yo[3] = {pt[q ^ 1].Y[0], pt[q ^ 1].Y[1], pt[q ^ 1].Y[2]};
+            double Yo[3];
+            point_Y(st, pt[q ^ 1], q ^ 1, ix, DIM, Yo);
             int co[3];
             double to[3];
             double muo = landing<DIM>(g, ix, Yo, co, to);

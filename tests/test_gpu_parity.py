@@ -39,6 +39,17 @@ def _toy(n, K, P, seed, drift=True, c=False, h=None, scale=1.0):
     return inst
 
 
+def _xscaled_toy(n, seed, K=5, P=2):
+    """x-scaled coefficients on an off-origin ragged box with a drift of several cells (truncated drift)."""
+    inst = _toy(n, K=K, P=P, seed=seed, c=True)
+    rng = np.random.default_rng(seed + 100)
+    inst.lo = (0.5, 0.25)
+    inst.sigma = rng.normal(size=(K, P, 2)) * 0.7
+    inst.drift = rng.normal(size=(K, 2)) * 3.0
+    inst.coef_model = "xscaled"
+    return inst
+
+
 SWEEP_CASES = [
     ("c1_33", lambda: workloads.config_c1(33)),
     ("c2_65", lambda: workloads.config_c2(65)),
@@ -47,6 +58,8 @@ SWEEP_CASES = [
     ("ragged_2d", lambda: _toy((37, 29), K=7, P=2, seed=3, c=True)),
     ("ragged_3d", lambda: _toy((11, 9, 13), K=5, P=1, seed=4)),
     ("single_control", lambda: _toy((21, 21), K=1, P=1, seed=5)),
+    ("c4_65_xscaled", lambda: workloads.c4_instance(65, 0.15, 0.3, 0.4, 0.03)),
+    ("xscaled_ragged", lambda: _xscaled_toy((31, 23), seed=6)),
 ]
 
 
@@ -84,6 +97,8 @@ APPLY_CASES = [
     ("c5_17", lambda: workloads.config_c5(17)),
     ("ragged_2d_c", lambda: _toy((37, 29), K=7, P=2, seed=3, c=True)),
     ("ragged_3d", lambda: _toy((11, 9, 13), K=5, P=1, seed=4)),
+    ("c4_65_xscaled", lambda: workloads.c4_instance(65, 0.15, 0.3, 0.4, 0.03)),
+    ("xscaled_ragged", lambda: _xscaled_toy((31, 23), seed=6)),
 ]
 
 
@@ -178,6 +193,19 @@ def test_march_c5_small(slhjb):
 def test_march_ragged_no_coarsening(slhjb):
     inst = _toy((30, 27), K=4, P=2, seed=9, c=True)
     _march_compare(slhjb, inst, slhjb.Options(precond=2))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_march_c4_xscaled(slhjb, precision):
+    """Two-asset x-scaled instance at 65^2, all 50 implicit steps."""
+    inst = workloads.c4_instance(65, 0.12, 0.29, 0.35, 0.02)
+    rel, mism = _march_compare(slhjb, inst, slhjb.Options(precision=precision))
+    log(f"  policy mismatches (near-ties) = {mism}")
+
+
+def test_march_xscaled_ragged(slhjb):
+    inst = _xscaled_toy((30, 27), seed=9)
+    _march_compare(slhjb, inst, slhjb.Options(precision=1))
 
 
 def test_vcycle_graph_replays_match_eager(slhjb):

@@ -210,6 +210,27 @@ int hjb_adjoint(hjb_handle *hd, const double *g, const double *psi, const double
 int hjb_apply_transposed(hjb_handle *hd, const int16_t *alpha, const double *x, double *y, double dt, double theta,
                          double s);
 
+/* ---- batches of independent instances (uneven grids, coefficients and multigrid depths) ----------
+
+   One handle drives many instances together: every kernel launch covers the tiles of all instances
+   that take part, and policy iteration and FGMRES advance in lockstep, each instance stopping on its
+   own certificate.  Instances may differ in n, lo, h, K, P, coef_model and coefficient tables; dim and
+   the solver options (taken from descs[0]; nu1 + nu2 even, V-cycle or no preconditioner) are shared.
+   Full-grid arrays of the batch are the instances' arrays concatenated, instance b starting at node
+   offsets[b] of hjb_batch_layout. */
+typedef struct hjb_batch hjb_batch;
+int hjb_setup_batch(const hjb_desc *descs, int32_t count, hjb_batch **out);
+/* offsets (host, count entries, nullable) and total nodes (host, nullable) of the concatenated layout */
+int hjb_batch_layout(const hjb_batch *bh, int64_t *offsets, int64_t *total);
+int hjb_batch_set_stream(hjb_batch *bh, void *stream);
+/* hjb_solve for every instance with one shared schedule and s; arrays in the concatenated layout
+   (device, FP64; policies int16 [n_steps][total], nullable); st: host [count] (nullable).
+   The first instance that fails (e.g. HJB_ENOCONV_KRYLOV) stops the whole batch; the message names it. */
+int hjb_solve_batch(hjb_batch *bh, const double *g, const double *psi, const double *f0, const double *f1,
+                    int32_t n_steps, const double *dts, const double *thetas, double s, double *U_final,
+                    int16_t *policies, hjb_solve_stats *st);
+void hjb_destroy_batch(hjb_batch *bh);
+
 /* Kernel timers.  Any caller that wants the duration of one class of kernel launches during real work
    (e.g. a benchmark's roofline) enables a timer; each launch of that class is then bracketed by HIP events
    on the handle's stream (at most max_launches launches are recorded; enable again to reset).

@@ -25,7 +25,8 @@ PRECOND_NONE, PRECOND_JACOBI, PRECOND_VCYCLE = 0, 1, 2
 
 EXPORTED = ["hjb_desc_default", "hjb_setup", "hjb_set_stream", "hjb_set_options", "hjb_policy_sweep", "hjb_apply",
             "hjb_linsolve", "hjb_step", "hjb_solve", "hjb_adjoint", "hjb_apply_transposed", "hjb_profile_enable",
-            "hjb_profile_read", "hjb_destroy", "hjb_last_error"]
+            "hjb_profile_read", "hjb_destroy", "hjb_last_error", "hjb_setup_batch", "hjb_batch_layout",
+            "hjb_batch_set_stream", "hjb_solve_batch", "hjb_destroy_batch"]
 KERNEL_APPLY, KERNEL_SMOOTH, KERNEL_MG_RESID, KERNEL_DOT, KERNEL_AXPY, KERNEL_SWEEP = range(6)
 KERNEL_NAMES = {KERNEL_APPLY: "apply", KERNEL_SMOOTH: "smooth", KERNEL_MG_RESID: "mg_residual",
                 KERNEL_DOT: "multidot", KERNEL_AXPY: "multiaxpy", KERNEL_SWEEP: "sweep"}
@@ -86,6 +87,12 @@ def _load():
     L.hjb_adjoint.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, d, vp, vp, vp, vp, vp, vp, ctypes.POINTER(d),
                               ctypes.POINTER(AdjointStats)]
     L.hjb_apply_transposed.argtypes = [vp, vp, vp, vp, d, d, d]
+    L.hjb_setup_batch.argtypes = [ctypes.POINTER(Desc), i32, ctypes.POINTER(vp)]
+    L.hjb_batch_layout.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.hjb_batch_set_stream.argtypes = [vp, vp]
+    L.hjb_solve_batch.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, d, vp, vp, ctypes.POINTER(SolveStats)]
+    L.hjb_destroy_batch.argtypes = [vp]
+    L.hjb_destroy_batch.restype = None
     L.hjb_profile_enable.argtypes = [vp, i32, i32]
     L.hjb_profile_read.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d)]
     L.hjb_destroy.argtypes = [vp]
@@ -289,6 +296,79 @@ class Solver:
                               dts.ctypes.data, thetas.ctypes.data, float(s), _ptr(U_final), _ptr(policies),
                               _ptr(values), ctypes.byref(st)))
         return st
+
+
+class Batch:
+    """hjb_setup_batch / hjb_solve_batch: many independent instances (uneven grids and coefficients)
+    advanced together; arrays are the instances' arrays concatenated (see offsets)."""
+
+    def __init__(self, instances, options: Optional[Options] = None):
+        self.options = options or Options()
+        self.instances = list(instances)
+        B = len(self.instances)
+        descs = (Desc * B)()
+        self._keep = []
+        for b, inst in enumerate(self.instances):
+            if inst.sigma is None:
+                raise ValueError("the HIP path takes per-control sigma tables (constant or x-scaled)")
+            sig = np.ascontiguousarray(inst.sigma, dtype=np.float64)
+            dr = None if inst.drift is None else np.ascontiguousarray(inst.drift, dtype=np.float64)
+            cc = None if inst.c is None else np.ascontiguousarray(inst.c, dtype=np.float64)
+            self._keep += [sig, dr, cc]
+            d = descs[b]
+            _lib.hjb_desc_default(ctypes.byref(d))
+            d.dim = inst.dim
+            for a in range(3):
+                d.n[a] = int(inst.n[a]) if a < inst.dim else 1
+                d.lo[a] = float(inst.lo[a]) if a < inst.dim else 0.0
+            d.h = float(inst.h)
+            d.K, d.P = sig.shape[0], sig.shape[1]
+            d.coef_model = COEF_XSCALED if getattr(inst, "coef_model", "const") == "xscaled" else COEF_CONST
+            d.sigma = sig.ctypes.data
+            d.drift = None if dr is None else dr.ctypes.data
+            d.c = None if cc is None else cc.ctypes.data
+            Solver._fill_options(d, self.options)
+            d.stream = None
+        h = ctypes.c_void_p()
+        _check(_lib.hjb_setup_batch(descs, B, ctypes.byref(h)))
+        self._h = h
+        offs = (ctypes.c_int64 * B)()
+        tot = ctypes.c_int64(0)
+        _check(_lib.hjb_batch_layout(self._h, offs, ctypes.byref(tot)))
+        self.offsets = [int(v) for v in offs]
+        self.total = int(tot.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.hjb_destroy_batch(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def concat(self, field: str):
+        """Host FP64 array of the named instance field in the batch layout."""
+        out = np.empty(self.total)
+        for inst, o in zip(self.instances, self.offsets):
+            out[o:o + inst.N] = getattr(inst, field)
+        return out
+
+    def split(self, a):
+        """Per-instance views of a batch-layout array (numpy or tensor)."""
+        return [a[o:o + inst.N] for inst, o in zip(self.instances, self.offsets)]
+
+    def solve(self, g, psi, f0, f1, dts, thetas, s, U_final, policies=None):
+        """hjb_solve_batch; returns per-instance SolveStats."""
+        _check(_lib.hjb_batch_set_stream(self._h, _stream()))
+        dts = np.ascontiguousarray(dts, dtype=np.float64)
+        thetas = np.ascontiguousarray(thetas, dtype=np.float64)
+        st = (SolveStats * len(self.instances))()
+        _check(_lib.hjb_solve_batch(self._h, _ptr(g), _ptr(psi), _ptr(f0), _ptr(f1), int(len(dts)),
+                                    dts.ctypes.data, thetas.ctypes.data, float(s), _ptr(U_final), _ptr(policies), st))
+        return list(st)
 
 
 def _autograd_function():

@@ -786,7 +786,12 @@ void hjb_desc_default(hjb_desc *d) {
 
 const char *hjb_last_error(void) { return g_err.c_str(); }
 
-int hjb_setup(const hjb_desc *desc, hjb_handle **out) {
+}  // extern "C"
+
+namespace {
+
+// tables_only: level geometry and stencil tables, no work vectors (instances of a batch)
+int setup_impl(const hjb_desc *desc, hjb_handle **out, bool tables_only) {
     g_err.clear();
     if (!desc || !out) return fail(HJB_EINVAL, "null argument");
     *out = nullptr;
@@ -883,6 +888,7 @@ int hjb_setup(const hjb_desc *desc, hjb_handle **out) {
         STRY(dalloc(hd, (void **)&L.tab, (size_t)d.K * hd->npt * sizeof(PointTab)));
         STRY(dalloc(hd, (void **)&L.fastF, (size_t)d.K * hd->npt * sizeof(FastPtF)));
         STRY(dalloc(hd, (void **)&L.fastD, (size_t)d.K * hd->npt * sizeof(FastPtD)));
+        if (tables_only) continue;
         if (l > 0) STRY(dalloc(hd, (void **)&L.alpha, n * sizeof(int16_t)));
         STRY(dalloc(hd, &L.r64, n * 8));
         STRY(dalloc(hd, &L.e64, n * 8));
@@ -895,8 +901,7 @@ int hjb_setup(const hjb_desc *desc, hjb_handle **out) {
     }
     hd->nb = tiles_for(hd->lev[0].g);  // blocks of the node kernels on the finest grid (partial sums)
     select_precision(hd);
-    const int m = kMaxRestart;
-    (void)m;
+    if (!tables_only) {
     STRY(dalloc(hd, (void **)&hd->E, N * 8));
     STRY(dalloc(hd, (void **)&hd->R, N * 8));
     STRY(dalloc(hd, (void **)&hd->Vb, (size_t)(d.restart + 1) * N * 8));
@@ -921,7 +926,8 @@ int hjb_setup(const hjb_desc *desc, hjb_handle **out) {
             }
         }
     }
-    size_t np = std::max<size_t>(3 * (size_t)hd->nb, (size_t)(kMaxRestart + 2) * hd->nbd);
+    }
+    size_t np = tables_only ? 16 : std::max<size_t>(3 * (size_t)hd->nb, (size_t)(kMaxRestart + 2) * hd->nbd);
     STRY(dalloc(hd, (void **)&hd->partial, np * 8));
     STRY(dalloc(hd, (void **)&hd->dvals, 256 * 8));
     STRY(dalloc(hd, (void **)&hd->ipartial, (size_t)hd->nb * 8));
@@ -946,6 +952,12 @@ int hjb_setup(const hjb_desc *desc, hjb_handle **out) {
     *out = hd;
     return HJB_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+int hjb_setup(const hjb_desc *desc, hjb_handle **out) { return setup_impl(desc, out, false); }
 
 int hjb_set_stream(hjb_handle *hd, void *stream) {
     if (!hd) return fail(HJB_EINVAL, "null handle");
@@ -1498,6 +1510,736 @@ void hjb_destroy(hjb_handle *hd) {
     if (hd->hpin) (void)hipHostFree(hd->hpin);
     if (hd->hpin_i) (void)hipHostFree(hd->hpin_i);
     delete hd;
+}
+
+}  // extern "C"
+
+// =====================================================================================================
+// Batches of independent instances
+// =====================================================================================================
+//
+// Instances keep their own grids, coefficient tables and multigrid depths (set up as tables-only
+// handles); their arrays are concatenated per level.  Every launch covers all instances that take
+// part (per-level tile tables, per-instance flags), and the per-instance scalars of policy iteration
+// and FGMRES (Hessenberg matrices, rotations, convergence) are advanced in lockstep on the host.
+
+namespace {
+
+struct TileTab {
+    int32_t n = 0;
+    int32_t *inst = nullptr, *tile = nullptr, *first_dev = nullptr;
+    std::vector<int32_t> first;  // [B+1] entry range of each instance
+};
+
+struct BLevel {
+    std::vector<int64_t> off;      // [B] start of each instance's array, -1 without this level
+    int64_t total = 0;
+    BInst *I = nullptr;            // device [B]
+    std::vector<BInst> Ih;
+    TileTab all;                   // instances that have this level
+    TileTab fine;                  // instances with a coarser level below this one
+    TileTab csm;                   // coarsest here but too large for the one-workgroup solve
+    std::vector<int32_t> lds;      // coarsest here, solved by one workgroup in LDS
+    int32_t *lds_dev = nullptr;
+    int64_t lds_maxN = 0;
+    int16_t *alpha = nullptr;      // injected policy (levels >= 1)
+    void *r64 = nullptr, *e64 = nullptr, *t64 = nullptr, *d64 = nullptr;
+    void *r32 = nullptr, *e32 = nullptr, *t32 = nullptr, *d32 = nullptr;
+};
+
+}  // namespace
+
+struct hjb_batch {
+    int B = 0, dim = 2;
+    hjb_desc opt{};                 // solver options (from the first descriptor)
+    std::vector<hjb_handle *> sub;  // per instance: level geometry and stencil tables
+    std::vector<int> nlev;
+    hipStream_t stream = nullptr;
+    std::vector<BLevel> lev;
+    int64_t N = 0;                  // level-0 nodes of all instances
+    double *E = nullptr, *R = nullptr, *Vb = nullptr, *Zb = nullptr, *Ua = nullptr, *Ub = nullptr, *Uc = nullptr;
+    int16_t *a0 = nullptr, *a1 = nullptr, *acarry = nullptr;
+    double *partial = nullptr;
+    int64_t *ipartial = nullptr;
+    double *dseg = nullptr, *dtau = nullptr, *dcoefA = nullptr, *dcoef = nullptr, *dy = nullptr;
+    int64_t *dchg = nullptr;
+    int32_t *dm = nullptr;
+    uint8_t *dmask[4] = {nullptr, nullptr, nullptr, nullptr};  // step, solve, Arnoldi cycle, second pass / changed
+    double *hseg = nullptr, *hcoef = nullptr, *hy = nullptr;
+    int64_t *hchg = nullptr;
+    int32_t *hm = nullptr;
+    uint8_t *hmask[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<void *> allocs, pinned;
+};
+
+namespace {
+
+constexpr int kLdc = kMaxRestart + 2;  // per-instance stride of the coefficient arrays
+
+int balloc(hjb_batch *bh, void **p, size_t bytes) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (bytes == 0) bytes = 256;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(HJB_ENOMEM, "batch workspace (%zu bytes)", bytes);
+    }
+    bh->allocs.push_back(*p);
+    return HJB_OK;
+}
+
+int bpin(hjb_batch *bh, void **p, size_t bytes) {
+    if (hipHostMalloc(p, bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(HJB_ENOMEM, "pinned batch buffer (%zu bytes)", bytes);
+    }
+    bh->pinned.push_back(*p);
+    return HJB_OK;
+}
+
+// tile table over the instances selected by `take`, in instance order
+int build_tiletab(hjb_batch *bh, int l, const std::function<bool(int)> &take, TileTab &T) {
+    std::vector<int32_t> inst, tile;
+    T.first.assign(bh->B + 1, 0);
+    for (int b = 0; b < bh->B; ++b) {
+        T.first[b] = (int32_t)inst.size();
+        if (l < bh->nlev[b] && take(b)) {
+            const int nt = tiles_for(bh->sub[b]->lev[l].g);
+            for (int t = 0; t < nt; ++t) {
+                inst.push_back(b);
+                tile.push_back(t);
+            }
+        }
+    }
+    T.first[bh->B] = (int32_t)inst.size();
+    T.n = (int32_t)inst.size();
+    TRY(balloc(bh, (void **)&T.inst, std::max<size_t>(1, inst.size()) * 4));
+    TRY(balloc(bh, (void **)&T.tile, std::max<size_t>(1, tile.size()) * 4));
+    TRY(balloc(bh, (void **)&T.first_dev, (size_t)(bh->B + 1) * 4));
+    if (!inst.empty()) {
+        HIPCHK(hipMemcpy(T.inst, inst.data(), inst.size() * 4, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(T.tile, tile.data(), tile.size() * 4, hipMemcpyHostToDevice));
+    }
+    HIPCHK(hipMemcpy(T.first_dev, T.first.data(), (size_t)(bh->B + 1) * 4, hipMemcpyHostToDevice));
+    return HJB_OK;
+}
+
+BTiles btiles(const TileTab &T, const BInst *I, const uint8_t *mask) { return BTiles{T.inst, T.tile, I, mask, T.n}; }
+
+int bwait(hjb_batch *bh) {
+    HIPCHK(hipStreamSynchronize(bh->stream));
+    return HJB_OK;
+}
+
+int bupload_mask(hjb_batch *bh, int k) {
+    HIPCHK(hipMemcpyAsync(bh->dmask[k], bh->hmask[k], (size_t)bh->B, hipMemcpyHostToDevice, bh->stream));
+    return HJB_OK;
+}
+
+// per-instance descriptors of every level for the current tables (deep boxes and s)
+int brefresh(hjb_batch *bh) {
+    for (size_t l = 0; l < bh->lev.size(); ++l) {
+        BLevel &L = bh->lev[l];
+        for (int b = 0; b < bh->B; ++b) {
+            if ((int)l < bh->nlev[b]) {
+                L.Ih[b].g = bh->sub[b]->lev[l].g;
+                L.Ih[b].st = stencil(bh->sub[b], (int)l);
+                L.Ih[b].off = L.off[b];
+            }
+        }
+        HIPCHK(hipMemcpyAsync(L.I, L.Ih.data(), (size_t)bh->B * sizeof(BInst), hipMemcpyHostToDevice, bh->stream));
+    }
+    return bwait(bh);
+}
+
+// ---- batched multigrid ---------------------------------------------------------------------------
+
+template <typename T>
+void bprepare_mg(hjb_batch *bh, const int16_t *alpha0, double theta_dt, const uint8_t *mask) {
+    constexpr bool F = std::is_same<T, float>::value;
+    hipStream_t s = bh->stream;
+    for (size_t l = 1; l < bh->lev.size(); ++l) {
+        const int16_t *af = l == 1 ? alpha0 : bh->lev[l - 1].alpha;
+        launch_inject_b(bh->dim, btiles(bh->lev[l].all, bh->lev[l].I, mask), bh->lev[l - 1].I, af, bh->lev[l].alpha,
+                        s);
+    }
+    for (size_t l = 0; l < bh->lev.size(); ++l) {
+        BLevel &L = bh->lev[l];
+        const int16_t *al = l == 0 ? alpha0 : L.alpha;
+        launch_diag_b<T>(bh->dim, btiles(L.all, L.I, mask), al, theta_dt, (T *)(F ? L.d32 : L.d64), s);
+    }
+}
+
+// even number of Jacobi sweeps on the listed instances, ending in e
+template <typename T>
+void bsweeps_even(hjb_batch *bh, int l, const TileTab &TT, const int16_t *al, T *e, T *t, const T *r, const T *d,
+                  double theta_dt, const uint8_t *mask) {
+    if (TT.n == 0) return;
+    const int sweeps = bh->opt.coarse_sweeps + (bh->opt.coarse_sweeps & 1);
+    BTiles bt = btiles(TT, bh->lev[l].I, mask);
+    for (int q = 0; q < sweeps; ++q) {
+        if (q % 2 == 0)
+            launch_jacobi_b<T>(bh->dim, bt, al, e, r, d, t, theta_dt, bh->opt.omega, q == 0, bh->stream);
+        else
+            launch_jacobi_b<T>(bh->dim, bt, al, t, r, d, e, theta_dt, bh->opt.omega, false, bh->stream);
+    }
+}
+
+// z = V-cycle(r0) for every instance with mask[b] = 1 (nu1 + nu2 even: each level ends in its e buffer)
+template <typename T>
+void bvcycle(hjb_batch *bh, const T *r0, T *z, double theta_dt, const int16_t *alpha0, const uint8_t *mask) {
+    constexpr bool F = std::is_same<T, float>::value;
+    const hjb_desc &d = bh->opt;
+    hipStream_t s = bh->stream;
+    const int Lm = (int)bh->lev.size();
+    std::vector<T *> e(Lm), t(Lm), dd(Lm);
+    std::vector<const T *> r(Lm);
+    std::vector<const int16_t *> al(Lm);
+    for (int l = 0; l < Lm; ++l) {
+        BLevel &L = bh->lev[l];
+        e[l] = (T *)(F ? L.e32 : L.e64);
+        t[l] = (T *)(F ? L.t32 : L.t64);
+        r[l] = (const T *)(F ? L.r32 : L.r64);
+        dd[l] = (T *)(F ? L.d32 : L.d64);
+        al[l] = l == 0 ? alpha0 : L.alpha;
+    }
+    r[0] = r0;
+    e[0] = z;
+    auto coarse = [&](int l) {
+        BLevel &L = bh->lev[l];
+        launch_coarse_b<T>(bh->dim, L.lds_dev, (int)L.lds.size(), L.lds_maxN, L.I, mask, al[l], r[l], dd[l], e[l],
+                           theta_dt, d.omega, d.coarse_sweeps, s);
+        bsweeps_even<T>(bh, l, L.csm, al[l], e[l], t[l], r[l], dd[l], theta_dt, mask);
+    };
+    coarse(0);
+    for (int l = 0; l + 1 < Lm; ++l) {
+        BLevel &L = bh->lev[l];
+        BTiles ft = btiles(L.fine, L.I, mask);
+        for (int q = 0; q < d.nu1; ++q) {
+            launch_jacobi_b<T>(bh->dim, ft, al[l], e[l], r[l], dd[l], t[l], theta_dt, d.omega, q == 0, s);
+            std::swap(e[l], t[l]);
+        }
+        launch_level_residual_b<T>(bh->dim, ft, al[l], e[l], r[l], t[l], theta_dt, s);
+        launch_restrict_b<T>(bh->dim, btiles(bh->lev[l + 1].all, bh->lev[l + 1].I, mask), L.I, t[l],
+                             (T *)(F ? bh->lev[l + 1].r32 : bh->lev[l + 1].r64), s);
+        coarse(l + 1);
+    }
+    for (int l = Lm - 2; l >= 0; --l) {
+        BLevel &L = bh->lev[l];
+        BTiles ft = btiles(L.fine, L.I, mask);
+        launch_prolong_add_b<T>(bh->dim, ft, bh->lev[l + 1].I, e[l + 1], e[l], s);
+        for (int q = 0; q < d.nu2; ++q) {
+            launch_jacobi_b<T>(bh->dim, ft, al[l], e[l], r[l], dd[l], t[l], theta_dt, d.omega, false, s);
+            std::swap(e[l], t[l]);
+        }
+    }
+}
+
+// ---- batched FGMRES ------------------------------------------------------------------------------
+
+struct BSolveOut {
+    std::vector<int> its;
+    std::vector<double> res;
+    std::vector<uint8_t> tight;
+};
+
+// Solve A_b X_b = E_b for every instance with on[b]; eta[b] as in fgmres_core.
+int bfgmres(hjb_batch *bh, const int16_t *alpha, double *X, double theta_dt, const std::vector<uint8_t> &on,
+            const std::vector<double> &eta, BSolveOut &out) {
+    const hjb_desc &d = bh->opt;
+    const int B = bh->B, m = d.restart, dim = bh->dim;
+    const int64_t N = bh->N;
+    hipStream_t s = bh->stream;
+    const bool mixed_p = d.precision == HJB_PREC_MIXED;
+    const bool none = d.precond == HJB_PRECOND_NONE;
+    const bool zf = mixed_p && !none && d.precond == HJB_PRECOND_VCYCLE;
+    const size_t zsz = zf ? 4 : 8;
+    BLevel &L0 = bh->lev[0];
+    const TileTab &A0 = L0.all;
+    const int n0 = A0.n;
+    out.its.assign(B, 0);
+    out.res.assign(B, 0.0);
+    out.tight.assign(B, 0);
+    std::vector<double> loose(B, 0.0), target(B, 0.0), beta(B, 0.0);
+    std::vector<std::vector<double>> H(B), cs(B), sn(B), gv(B), yv(B);
+    for (int b = 0; b < B; ++b) {
+        H[b].assign((size_t)(m + 1) * m, 0.0);
+        cs[b].assign(m, 0.0);
+        sn[b].assign(m, 0.0);
+        gv[b].assign(m + 1, 0.0);
+        yv[b].assign(m, 0.0);
+    }
+    std::vector<uint8_t> act = on;  // still solving
+    std::vector<int> jb(B, 0);
+    uint8_t *mS = bh->dmask[1], *mC = bh->dmask[2], *mP = bh->dmask[3];
+    uint8_t *hS = bh->hmask[1], *hC = bh->hmask[2], *hP = bh->hmask[3];
+    for (int cycle = 0;; ++cycle) {
+        for (int b = 0; b < B; ++b) hS[b] = act[b];
+        TRY(bupload_mask(bh, 1));
+        launch_residual_b(dim, btiles(A0, L0.I, mS), alpha, X, bh->E, theta_dt, bh->R, bh->partial, s);
+        launch_seg_sum(bh->partial, n0, A0.first_dev, 1, mS, bh->dseg, B, s);
+        launch_seg_max(bh->partial + n0, n0, A0.first_dev, 2, mS, bh->dseg + B, B, s);
+        HIPCHK(hipMemcpyAsync(bh->hseg, bh->dseg, (size_t)3 * B * 8, hipMemcpyDeviceToHost, s));
+        TRY(bwait(bh));
+        bool any = false;
+        for (int b = 0; b < B; ++b) {
+            if (!act[b]) continue;
+            double b2 = bh->hseg[b], rinf = bh->hseg[B + 2 * b], xinf = bh->hseg[B + 2 * b + 1];
+            out.res[b] = rinf;
+            if (!isfinite(b2) || !isfinite(xinf)) return fail(HJB_ENONFINITE, "non-finite residual (instance %d)", b);
+            target[b] = d.rtol_inf * std::max(1.0, xinf);
+            if (cycle == 0 && eta[b] > 0.0) loose[b] = eta[b] * rinf;
+            out.tight[b] = rinf <= target[b];
+            if (rinf <= std::max(target[b], loose[b])) {
+                act[b] = 0;
+                continue;
+            }
+            target[b] = std::max(target[b], loose[b]);
+            if (out.its[b] >= d.max_krylov)
+                return fail(HJB_ENOCONV_KRYLOV, "FGMRES (instance %d): |r|_inf = %.3e > %.3e after %d iterations", b,
+                            rinf, target[b], out.its[b]);
+            beta[b] = sqrt(b2);
+            std::fill(gv[b].begin(), gv[b].end(), 0.0);
+            gv[b][0] = beta[b];
+            jb[b] = 0;
+            any = true;
+        }
+        if (!any) return HJB_OK;
+        for (int b = 0; b < B; ++b) hC[b] = act[b];
+        TRY(bupload_mask(bh, 2));
+        // v0 = r / |r|_2 per instance (dseg[b] holds sum r^2)
+        launch_scale_b(dim, btiles(A0, L0.I, mC), bh->Vb, bh->R, bh->dseg, 1, s);
+        std::vector<uint8_t> inc = act;
+        for (int j = 0; j < m; ++j) {
+            bool anyc = false;
+            for (int b = 0; b < B; ++b) anyc |= inc[b] != 0;
+            if (!anyc) break;
+            double *vj = bh->Vb + (int64_t)j * N;
+            double *w = bh->Vb + (int64_t)(j + 1) * N;
+            void *zj = none ? (void *)vj : (void *)((char *)bh->Zb + (int64_t)j * N * zsz);
+            if (!none) {
+                if (d.precond == HJB_PRECOND_JACOBI) {
+                    return fail(HJB_EUNSUPPORTED, "batched solves take the V-cycle preconditioner (or none)");
+                } else if (zf) {
+                    launch_to_precond(vj, L0.r32, true, N, s);
+                    bvcycle<float>(bh, (const float *)L0.r32, (float *)zj, theta_dt, alpha, mC);
+                } else {
+                    bvcycle<double>(bh, vj, (double *)zj, theta_dt, alpha, mC);
+                }
+            }
+            launch_apply_b(dim, btiles(A0, L0.I, mC), alpha, zj, zf, w, theta_dt, s);
+            std::vector<double> hn(B, 0.0);
+            std::vector<uint8_t> need(inc);  // instances still orthogonalising in this pass
+            for (int pass = 0; pass < 2; ++pass) {
+                bool anyp = false;
+                for (int b = 0; b < B; ++b) {
+                    hP[b] = need[b];
+                    anyp |= need[b] != 0;
+                }
+                if (!anyp) break;
+                TRY(bupload_mask(bh, 3));
+                launch_multidot_b(dim, btiles(A0, L0.I, mP), w, bh->Vb, N, j + 1, bh->partial, s);
+                launch_seg_sum(bh->partial, n0, A0.first_dev, j + 2, mP, bh->dseg, B, s);
+                HIPCHK(hipMemcpyAsync(bh->hseg, bh->dseg, (size_t)B * (j + 2) * 8, hipMemcpyDeviceToHost, s));
+                TRY(bwait(bh));
+                for (int b = 0; b < B; ++b) {
+                    if (!need[b]) continue;
+                    const double *hp = bh->hseg + (size_t)b * (j + 2);
+                    double *cb = bh->hcoef + (size_t)b * kLdc;
+                    for (int i = 0; i <= j + 1; ++i) cb[i] = hp[i];
+                }
+                HIPCHK(hipMemcpyAsync(bh->dcoef, bh->hcoef, (size_t)B * kLdc * 8, hipMemcpyHostToDevice, s));
+                launch_multiaxpy_scale_b(dim, btiles(A0, L0.I, mP), w, bh->Vb, N, j + 1, bh->dcoef, kLdc, s);
+                for (int b = 0; b < B; ++b) {
+                    if (!need[b]) continue;
+                    const double *hp = bh->hseg + (size_t)b * (j + 2);
+                    double w2 = hp[j + 1], h2 = 0.0;
+                    for (int i = 0; i <= j; ++i) h2 += hp[i] * hp[i];
+                    double hn2 = w2 - h2;
+                    double sc = hn2 > 0.0 ? sqrt(hn2) : 1.0;
+                    if (!isfinite(w2)) return fail(HJB_ENONFINITE, "non-finite Arnoldi vector (instance %d)", b);
+                    if (pass == 0) {
+                        for (int i = 0; i <= j; ++i) H[b][(size_t)i * m + j] = hp[i];
+                        hn[b] = sc;
+                    } else {
+                        for (int i = 0; i <= j; ++i) H[b][(size_t)i * m + j] += hp[i] * hn[b];
+                        hn[b] = hn[b] * sc;
+                    }
+                    bool done_b = hn2 > 0.25 * w2;
+                    if (!done_b && (w2 == 0.0 || (pass == 1 && !(hn2 > 0.0)))) {
+                        hn[b] = 0.0;
+                        done_b = true;
+                    }
+                    need[b] = done_b ? 0 : 1;
+                }
+                // the host coefficient buffer is rewritten only after the next wait
+            }
+            bool changed = false;
+            for (int b = 0; b < B; ++b) {
+                if (!inc[b]) continue;
+                std::vector<double> &Hb = H[b];
+                Hb[(size_t)(j + 1) * m + j] = hn[b];
+                ++out.its[b];
+                for (int i = 0; i < j; ++i) {
+                    double a = Hb[(size_t)i * m + j], c = Hb[(size_t)(i + 1) * m + j];
+                    Hb[(size_t)i * m + j] = cs[b][i] * a + sn[b][i] * c;
+                    Hb[(size_t)(i + 1) * m + j] = -sn[b][i] * a + cs[b][i] * c;
+                }
+                double a = Hb[(size_t)j * m + j], c = Hb[(size_t)(j + 1) * m + j];
+                double rr = hypot(a, c);
+                cs[b][j] = rr > 0 ? a / rr : 1.0;
+                sn[b][j] = rr > 0 ? c / rr : 0.0;
+                Hb[(size_t)j * m + j] = rr;
+                Hb[(size_t)(j + 1) * m + j] = 0.0;
+                gv[b][j + 1] = -sn[b][j] * gv[b][j];
+                gv[b][j] = cs[b][j] * gv[b][j];
+                jb[b] = j + 1;
+                if (fabs(gv[b][j + 1]) <= 0.5 * target[b] || hn[b] == 0.0 || out.its[b] >= d.max_krylov) {
+                    inc[b] = 0;
+                    changed = true;
+                }
+            }
+            if (changed) {
+                for (int b = 0; b < B; ++b) hC[b] = inc[b];
+                TRY(bupload_mask(bh, 2));
+            }
+        }
+        // y = H^{-1} g per instance, X += Z y
+        for (int b = 0; b < B; ++b) {
+            bh->hm[b] = 0;
+            if (!act[b]) continue;
+            const int jj = jb[b];
+            for (int i = jj - 1; i >= 0; --i) {
+                double acc = gv[b][i];
+                for (int q = i + 1; q < jj; ++q) acc -= H[b][(size_t)i * m + q] * yv[b][q];
+                yv[b][i] = acc / H[b][(size_t)i * m + i];
+            }
+            bh->hm[b] = jj;
+            for (int i = 0; i < jj; ++i) bh->hy[(size_t)b * kMaxRestart + i] = yv[b][i];
+        }
+        HIPCHK(hipMemcpyAsync(bh->dy, bh->hy, (size_t)B * kMaxRestart * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(bh->dm, bh->hm, (size_t)B * 4, hipMemcpyHostToDevice, s));
+        for (int b = 0; b < B; ++b) hS[b] = act[b];
+        TRY(bupload_mask(bh, 1));
+        launch_update_b(dim, btiles(A0, L0.I, mS), X, none ? (const void *)bh->Vb : (const void *)bh->Zb, zf, N,
+                        bh->dm, bh->dy, kMaxRestart, s);
+        HIPCHK(hipGetLastError());
+    }
+}
+
+// search of every instance with on[b]: a_out from a_in at X (U: previous level); changed counts in hchg
+int bsweep(hjb_batch *bh, const double *X, const double *U, const double *f0, const double *f1, double t_prev,
+           double dt, double theta, const int16_t *a_in, int16_t *a_out, const std::vector<uint8_t> &on) {
+    hipStream_t s = bh->stream;
+    BLevel &L0 = bh->lev[0];
+    for (int b = 0; b < bh->B; ++b) bh->hmask[0][b] = on[b];
+    TRY(bupload_mask(bh, 0));
+    const double t_mid = t_prev + theta * dt;
+    BTiles bt = btiles(L0.all, L0.I, bh->dmask[0]);
+    launch_norms_b(bh->dim, bt, X, U, f0, f1, t_mid, bh->partial, s);
+    launch_tau_b(bh->partial, L0.all.n, L0.all.first_dev, bh->dcoefA, bh->opt.tau_rel, bh->dmask[0], bh->dtau, bh->B, s);
+    launch_sweep_b(bh->dim, bt, X, U, f0, f1, t_mid, theta, bh->dtau, a_in, a_out, bh->ipartial, s);
+    launch_seg_sum_i64(bh->ipartial, L0.all.n, L0.all.first_dev, bh->dmask[0], bh->dchg, bh->B, s);
+    HIPCHK(hipMemcpyAsync(bh->hchg, bh->dchg, (size_t)bh->B * 8, hipMemcpyDeviceToHost, s));
+    return bwait(bh);
+}
+
+int blinsolve(hjb_batch *bh, const int16_t *alpha, const double *U, const double *f0, const double *f1, double t_prev,
+              double dt, double theta, double *X, const std::vector<uint8_t> &on, const std::vector<double> &eta,
+              BSolveOut &out) {
+    hipStream_t s = bh->stream;
+    BLevel &L0 = bh->lev[0];
+    for (int b = 0; b < bh->B; ++b) bh->hmask[0][b] = on[b];
+    TRY(bupload_mask(bh, 0));
+    const double theta_dt = theta * dt;
+    if (bh->opt.precond == HJB_PRECOND_VCYCLE) {
+        if (bh->opt.precision == HJB_PREC_MIXED)
+            bprepare_mg<float>(bh, alpha, theta_dt, bh->dmask[0]);
+        else
+            bprepare_mg<double>(bh, alpha, theta_dt, bh->dmask[0]);
+    }
+    launch_explicit_b(bh->dim, btiles(L0.all, L0.I, bh->dmask[0]), alpha, U, f0, f1, t_prev + theta * dt,
+                      (1.0 - theta) * dt, dt, bh->E, s);
+    return bfgmres(bh, alpha, X, theta_dt, on, eta, out);
+}
+
+// one time step of every instance: policy iteration in lockstep (instances stop independently)
+int bstep(hjb_batch *bh, const double *Uprev, double *Unext, const double *f0, const double *f1, double t_prev,
+          double dt, double theta, const double *Uprev2, double dt_prev, std::vector<hjb_step_stats> &st) {
+    const int B = bh->B;
+    const hjb_desc &d = bh->opt;
+    hipStream_t s = bh->stream;
+    BLevel &L0 = bh->lev[0];
+    st.assign(B, hjb_step_stats{});
+    std::vector<uint8_t> on(B, 1);
+    BTiles all0 = btiles(L0.all, L0.I, nullptr);
+    if (Uprev2)
+        launch_extrapolate_b(bh->dim, all0, Uprev, Uprev2, dt / dt_prev, Unext, s);
+    else
+        launch_copy_interior_b(bh->dim, all0, Uprev, Unext, s);
+    TRY(bsweep(bh, Unext, Uprev, f0, f1, t_prev, dt, theta, bh->acarry, bh->a0, on));
+    for (int b = 0; b < B; ++b) st[b].n_changed_first = bh->hchg[b];
+    std::vector<uint8_t> want_tight(B, d.pi_eta <= 0.0 ? 1 : 0);
+    std::vector<double> eta(B, 0.0);
+    BSolveOut so;
+    for (int it = 0; it < d.max_pi; ++it) {
+        for (int b = 0; b < B; ++b) eta[b] = want_tight[b] ? 0.0 : d.pi_eta;
+        TRY(blinsolve(bh, bh->a0, Uprev, f0, f1, t_prev, dt, theta, Unext, on, eta, so));
+        for (int b = 0; b < B; ++b) {
+            if (!on[b]) continue;
+            st[b].pi_iters = it + 1;
+            st[b].krylov_total += so.its[b];
+            st[b].krylov_max = std::max(st[b].krylov_max, so.its[b]);
+            st[b].res_inf = so.res[b];
+            double den = 1.0 - theta * dt * bh->sub[b]->cplus;
+            st[b].cert_bound = den > 0 ? so.res[b] / den : INFINITY;
+        }
+        TRY(bsweep(bh, Unext, Uprev, f0, f1, t_prev, dt, theta, bh->a0, bh->a1, on));
+        bool any_left = false, any_changed = false;
+        for (int b = 0; b < B; ++b) {
+            bh->hmask[3][b] = 0;
+            if (!on[b]) continue;
+            if (bh->hchg[b] == 0) {
+                if (so.tight[b])
+                    on[b] = 0;
+                else
+                    want_tight[b] = 1;
+            } else {
+                bh->hmask[3][b] = 1;
+                any_changed = true;
+                want_tight[b] = d.pi_eta <= 0.0 ? 1 : 0;
+            }
+            any_left |= on[b] != 0;
+        }
+        if (any_changed) {
+            TRY(bupload_mask(bh, 3));
+            launch_copy_policy_b(bh->dim, btiles(L0.all, L0.I, bh->dmask[3]), bh->a1, bh->a0, s);
+        }
+        if (!any_left) break;
+        if (it + 1 == d.max_pi) return fail(HJB_ENOCONV_PI, "policy iteration not converged after %d", it + 1);
+    }
+    HIPCHK(hipMemcpyAsync(bh->acarry, bh->a0, (size_t)bh->N * 2, hipMemcpyDeviceToDevice, s));
+    return bwait(bh);
+}
+
+}  // namespace
+
+extern "C" {
+
+int hjb_setup_batch(const hjb_desc *descs, int32_t count, hjb_batch **out) {
+    g_err.clear();
+    if (!descs || !out) return fail(HJB_EINVAL, "null argument");
+    *out = nullptr;
+    if (count < 1) return fail(HJB_EINVAL, "count must be >= 1");
+    const hjb_desc &d0 = descs[0];
+    TRY(check_options(&d0));
+    if ((d0.nu1 + d0.nu2) % 2 != 0) return fail(HJB_EUNSUPPORTED, "batched V-cycles take an even nu1 + nu2");
+    if (d0.precond == HJB_PRECOND_JACOBI) return fail(HJB_EUNSUPPORTED, "batched solves take the V-cycle or no preconditioner");
+    for (int b = 0; b < count; ++b)
+        if (descs[b].dim != d0.dim) return fail(HJB_EINVAL, "all instances of a batch have the same dimension");
+    hjb_batch *bh = new hjb_batch();
+    auto bail = [&](int rc) {
+        hjb_destroy_batch(bh);
+        return rc;
+    };
+#define BTRY(x)                            \
+    do {                                   \
+        int _rc = (x);                     \
+        if (_rc != HJB_OK) return bail(_rc); \
+    } while (0)
+    bh->B = count;
+    bh->dim = d0.dim;
+    bh->opt = d0;
+    bh->stream = (hipStream_t)d0.stream;
+    for (int b = 0; b < count; ++b) {
+        hjb_desc db = descs[b];
+        // solver options are the batch's
+        db.precision = d0.precision;
+        db.precond = d0.precond;
+        db.restart = d0.restart;
+        db.max_krylov = d0.max_krylov;
+        db.max_pi = d0.max_pi;
+        db.nu1 = d0.nu1;
+        db.nu2 = d0.nu2;
+        db.coarse_sweeps = d0.coarse_sweeps;
+        db.min_coarse = d0.min_coarse;
+        db.omega = d0.omega;
+        db.rtol_inf = d0.rtol_inf;
+        db.tau_rel = d0.tau_rel;
+        db.pi_eta = d0.pi_eta;
+        db.use_graphs = 0;
+        db.stream = d0.stream;
+        hjb_handle *h = nullptr;
+        int rc = setup_impl(&db, &h, true);
+        if (rc != HJB_OK) {
+            std::string msg = g_err;
+            bail(rc);
+            return fail(rc, "instance %d: %s", b, msg.c_str());
+        }
+        bh->sub.push_back(h);
+        bh->nlev.push_back((int)h->lev.size());
+    }
+    const int Lm = *std::max_element(bh->nlev.begin(), bh->nlev.end());
+    bh->lev.resize(Lm);
+    const bool mixed_p = d0.precision == HJB_PREC_MIXED;
+    int64_t maxn = 0;
+    for (int l = 0; l < Lm; ++l) {
+        BLevel &L = bh->lev[l];
+        L.off.assign(count, -1);
+        L.Ih.assign(count, BInst{});
+        for (int b = 0; b < count; ++b) {
+            if (l >= bh->nlev[b]) continue;
+            L.off[b] = L.total;
+            L.total += bh->sub[b]->lev[l].g.N;
+            const bool coarsest = l == bh->nlev[b] - 1;
+            if (coarsest && bh->sub[b]->lev[l].g.N <= kCoarseMaxNodes) {
+                L.lds.push_back(b);
+                L.lds_maxN = std::max(L.lds_maxN, bh->sub[b]->lev[l].g.N);
+            }
+        }
+        BTRY(balloc(bh, (void **)&L.I, (size_t)count * sizeof(BInst)));
+        BTRY(build_tiletab(bh, l, [&](int) { return true; }, L.all));
+        BTRY(build_tiletab(bh, l, [&](int b) { return l + 1 < bh->nlev[b]; }, L.fine));
+        BTRY(build_tiletab(bh, l, [&](int b) {
+            return l == bh->nlev[b] - 1 && bh->sub[b]->lev[l].g.N > kCoarseMaxNodes; }, L.csm));
+        BTRY(balloc(bh, (void **)&L.lds_dev, std::max<size_t>(1, L.lds.size()) * 4));
+        if (!L.lds.empty())
+            HIPCHK(hipMemcpy(L.lds_dev, L.lds.data(), L.lds.size() * 4, hipMemcpyHostToDevice));
+        const size_t n = (size_t)L.total;
+        if (l > 0) BTRY(balloc(bh, (void **)&L.alpha, n * 2));
+        if (!mixed_p || l == 0) {
+            BTRY(balloc(bh, &L.r64, n * 8));
+            BTRY(balloc(bh, &L.e64, n * 8));
+            BTRY(balloc(bh, &L.t64, n * 8));
+            BTRY(balloc(bh, &L.d64, n * 8));
+        }
+        if (mixed_p) {
+            BTRY(balloc(bh, &L.r32, n * 4));
+            BTRY(balloc(bh, &L.e32, n * 4));
+            BTRY(balloc(bh, &L.t32, n * 4));
+            BTRY(balloc(bh, &L.d32, n * 4));
+        }
+        maxn = std::max<int64_t>(maxn, L.all.n);
+    }
+    bh->N = bh->lev[0].total;
+    const size_t N = (size_t)bh->N;
+    const int m = d0.restart;
+    BTRY(balloc(bh, (void **)&bh->E, N * 8));
+    BTRY(balloc(bh, (void **)&bh->R, N * 8));
+    BTRY(balloc(bh, (void **)&bh->Vb, (size_t)(m + 1) * N * 8));
+    BTRY(balloc(bh, (void **)&bh->Zb, (size_t)m * N * 8));
+    BTRY(balloc(bh, (void **)&bh->Ua, N * 8));
+    BTRY(balloc(bh, (void **)&bh->Ub, N * 8));
+    BTRY(balloc(bh, (void **)&bh->Uc, N * 8));
+    BTRY(balloc(bh, (void **)&bh->a0, N * 2));
+    BTRY(balloc(bh, (void **)&bh->a1, N * 2));
+    BTRY(balloc(bh, (void **)&bh->acarry, N * 2));
+    BTRY(balloc(bh, (void **)&bh->partial, (size_t)kLdc * maxn * 8));
+    BTRY(balloc(bh, (void **)&bh->ipartial, (size_t)maxn * 8));
+    BTRY(balloc(bh, (void **)&bh->dseg, (size_t)count * kLdc * 8));
+    BTRY(balloc(bh, (void **)&bh->dtau, (size_t)count * 8));
+    BTRY(balloc(bh, (void **)&bh->dcoefA, (size_t)count * 8));
+    BTRY(balloc(bh, (void **)&bh->dcoef, (size_t)count * kLdc * 8));
+    BTRY(balloc(bh, (void **)&bh->dy, (size_t)count * kMaxRestart * 8));
+    BTRY(balloc(bh, (void **)&bh->dchg, (size_t)count * 8));
+    BTRY(balloc(bh, (void **)&bh->dm, (size_t)count * 4));
+    for (int k = 0; k < 4; ++k) {
+        BTRY(balloc(bh, (void **)&bh->dmask[k], (size_t)count));
+        BTRY(bpin(bh, (void **)&bh->hmask[k], (size_t)count));
+    }
+    BTRY(bpin(bh, (void **)&bh->hseg, (size_t)count * kLdc * 8));
+    BTRY(bpin(bh, (void **)&bh->hcoef, (size_t)count * kLdc * 8));
+    BTRY(bpin(bh, (void **)&bh->hy, (size_t)count * kMaxRestart * 8));
+    BTRY(bpin(bh, (void **)&bh->hchg, (size_t)count * 8));
+    BTRY(bpin(bh, (void **)&bh->hm, (size_t)count * 4));
+    memset(bh->hcoef, 0, (size_t)count * kLdc * 8);
+    memset(bh->hy, 0, (size_t)count * kMaxRestart * 8);
+    {
+        std::vector<double> cA(count);
+        for (int b = 0; b < count; ++b) {
+            const hjb_handle *h = bh->sub[b];
+            cA[b] = 2.0 * h->M * (0.5 / h->desc.h) + h->cmax;
+        }
+        HIPCHK(hipMemcpy(bh->dcoefA, cA.data(), (size_t)count * 8, hipMemcpyHostToDevice));
+    }
+#undef BTRY
+    *out = bh;
+    return HJB_OK;
+}
+
+int hjb_batch_layout(const hjb_batch *bh, int64_t *offsets, int64_t *total) {
+    if (!bh) return fail(HJB_EINVAL, "null batch");
+    if (offsets)
+        for (int b = 0; b < bh->B; ++b) offsets[b] = bh->lev[0].off[b];
+    if (total) *total = bh->N;
+    return HJB_OK;
+}
+
+int hjb_batch_set_stream(hjb_batch *bh, void *stream) {
+    if (!bh) return fail(HJB_EINVAL, "null batch");
+    bh->stream = (hipStream_t)stream;
+    for (hjb_handle *h : bh->sub) h->stream = bh->stream;
+    return HJB_OK;
+}
+
+int hjb_solve_batch(hjb_batch *bh, const double *g, const double *psi, const double *f0, const double *f1,
+                    int32_t n_steps, const double *dts, const double *thetas, double s, double *U_final,
+                    int16_t *policies, hjb_solve_stats *st) {
+    if (!bh) return fail(HJB_EINVAL, "null batch");
+    if (!g || !psi || !f0 || !f1 || !dts || !thetas || !U_final) return fail(HJB_EINVAL, "null argument");
+    if (n_steps < 0) return fail(HJB_EINVAL, "n_steps must be >= 0");
+    for (int n = 0; n < n_steps; ++n) {
+        TRY(check_time(dts[n], thetas[n]));
+        if (thetas[n] == 0.0) return fail(HJB_EUNSUPPORTED, "explicit steps (theta = 0) are not provided");
+    }
+    const int B = bh->B;
+    const int64_t N = bh->N;
+    hipStream_t str = bh->stream;
+    for (hjb_handle *h : bh->sub) {
+        h->stream = str;
+        TRY(build_tables(h, s));
+    }
+    TRY(brefresh(bh));
+    std::vector<hjb_solve_stats> loc(B, hjb_solve_stats{});
+    HIPCHK(hipMemcpyAsync(bh->Ua, g, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
+    HIPCHK(hipMemcpyAsync(bh->Uc, g, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
+    launch_zero(bh->acarry, (size_t)N * 2, str);
+    double *Ucur = bh->Ua, *Unx = bh->Ub, *Uold = bh->Uc;
+    double t = 0.0;
+    int rc = HJB_OK;
+    std::vector<hjb_step_stats> sst;
+    for (int n = 0; n < n_steps; ++n) {
+        HIPCHK(hipMemcpyAsync(Unx, psi, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
+        rc = bstep(bh, Ucur, Unx, f0, f1, t, dts[n], thetas[n], n >= 1 ? Uold : nullptr, n >= 1 ? dts[n - 1] : 0.0,
+                   sst);
+        if (rc != HJB_OK) break;
+        for (int b = 0; b < B; ++b) {
+            loc[b].krylov_total += sst[b].krylov_total;
+            loc[b].pi_total += sst[b].pi_iters;
+            loc[b].flags |= sst[b].flags;
+            loc[b].max_cert_bound = std::max(loc[b].max_cert_bound, sst[b].cert_bound);
+            loc[b].steps_done = n + 1;
+        }
+        if (policies)
+            HIPCHK(hipMemcpyAsync(policies + (int64_t)n * N, bh->acarry, (size_t)N * 2, hipMemcpyDeviceToDevice, str));
+        std::swap(Uold, Ucur);
+        std::swap(Ucur, Unx);
+        t = t + dts[n];
+    }
+    HIPCHK(hipMemcpyAsync(U_final, Ucur, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
+    HIPCHK(hipStreamSynchronize(str));
+    if (st)
+        for (int b = 0; b < B; ++b) st[b] = loc[b];
+    return rc;
+}
+
+void hjb_destroy_batch(hjb_batch *bh) {
+    if (!bh) return;
+    if (bh->stream) (void)hipStreamSynchronize(bh->stream);
+    else (void)hipDeviceSynchronize();
+    for (hjb_handle *h : bh->sub) hjb_destroy(h);
+    for (void *p : bh->allocs) (void)hipFree(p);
+    for (void *p : bh->pinned) (void)hipHostFree(p);
+    delete bh;
 }
 
 }  // extern "C"

@@ -212,6 +212,73 @@ void launch_ds_dot(int dim, const LevelDev &g, const StencilDev &st, const int16
 void launch_axpy_interior(int dim, const LevelDev &g, double a, const double *x, double *y, hipStream_t s);
 void launch_mask_interior(int dim, const LevelDev &g, const double *x, double *y, hipStream_t s);
 inline int tiles_for(const LevelDev &g) { return g.ntx * g.nty * g.ntz; }
+
+// ---- batched launches (slhjb_batch.hip) ------------------------------------------------------------
+
+// one instance on one level of a batch: grid, stencil, and where its arrays start in the level's
+// concatenated batch arrays
+struct BInst {
+    LevelDev g;
+    StencilDev st;
+    int64_t off;
+};
+// tiles of one batched launch: entry p = (instance inst[p], tile tile[p]); an instance's entries are
+// contiguous; blocks of instances with active[b] == 0 exit at once (active may be null)
+struct BTiles {
+    const int32_t *inst, *tile;
+    const BInst *I;
+    const uint8_t *active;
+    int32_t n;
+};
+void launch_norms_b(int dim, const BTiles &T, const double *X, const double *U, const double *f0, const double *f1,
+                    double t_mid, double *partial, hipStream_t s);
+void launch_tau_b(const double *partial, int n, const int32_t *first, const double *coefA, double tau_rel,
+                  const uint8_t *active, double *tau, int B, hipStream_t s);
+void launch_sweep_b(int dim, const BTiles &T, const double *X, const double *U, const double *f0, const double *f1,
+                    double t_mid, double theta, const double *tau, const int16_t *a_in, int16_t *a_out,
+                    int64_t *changed_partial, hipStream_t s);
+void launch_explicit_b(int dim, const BTiles &T, const int16_t *alpha, const double *U, const double *f0,
+                       const double *f1, double t_mid, double omt_dt, double dt, double *E, hipStream_t s);
+void launch_residual_b(int dim, const BTiles &T, const int16_t *alpha, const double *V, const double *E,
+                       double theta_dt, double *r, double *partial, hipStream_t s);
+void launch_apply_b(int dim, const BTiles &T, const int16_t *alpha, const void *x, bool x_float, double *y,
+                    double theta_dt, hipStream_t s);
+template <typename T>
+void launch_diag_b(int dim, const BTiles &Tb, const int16_t *alpha, double theta_dt, T *d, hipStream_t s);
+template <typename T>
+void launch_jacobi_b(int dim, const BTiles &Tb, const int16_t *alpha, const T *e, const T *r, const T *d, T *e_out,
+                     double theta_dt, double omega, bool first, hipStream_t s);
+template <typename T>
+void launch_level_residual_b(int dim, const BTiles &Tb, const int16_t *alpha, const T *e, const T *r, T *res,
+                             double theta_dt, hipStream_t s);
+template <typename T>
+void launch_restrict_b(int dim, const BTiles &Tc, const BInst *If, const T *rf, T *rc, hipStream_t s);
+template <typename T>
+void launch_prolong_add_b(int dim, const BTiles &Tf, const BInst *Ic, const T *ec, T *ef, hipStream_t s);
+template <typename T>
+void launch_coarse_b(int dim, const int32_t *list, int count, int64_t maxN, const BInst *Iv, const uint8_t *active,
+                     const int16_t *alpha, const T *r, const T *d, T *e, double theta_dt, double omega, int sweeps,
+                     hipStream_t s);
+void launch_inject_b(int dim, const BTiles &Tc, const BInst *If, const int16_t *af, int16_t *ac, hipStream_t s);
+void launch_copy_interior_b(int dim, const BTiles &T, const double *src, double *dst, hipStream_t s);
+void launch_extrapolate_b(int dim, const BTiles &T, const double *U1, const double *U0, double ratio, double *out,
+                          hipStream_t s);
+void launch_copy_policy_b(int dim, const BTiles &T, const int16_t *src, int16_t *dst, hipStream_t s);
+void launch_multidot_b(int dim, const BTiles &T, const double *w, const double *V, int64_t ldv, int nvec,
+                       double *partial, hipStream_t s);
+void launch_multiaxpy_scale_b(int dim, const BTiles &T, double *w, const double *V, int64_t ldv, int nvec,
+                              const double *coef, int ldc, hipStream_t s);
+void launch_scale_b(int dim, const BTiles &T, double *dst, const double *src, const double *norm2, int ldn,
+                    hipStream_t s);
+void launch_update_b(int dim, const BTiles &T, double *X, const void *Z, bool z_float, int64_t ldz, const int32_t *m,
+                     const double *y, int ldy, hipStream_t s);
+void launch_seg_sum(const double *partial, int n, const int32_t *first, int nvec, const uint8_t *active, double *out,
+                    int B, hipStream_t s);
+void launch_seg_max(const double *partial, int n, const int32_t *first, int nvec, const uint8_t *active, double *out,
+                    int B, hipStream_t s);
+void launch_seg_sum_i64(const int64_t *partial, int n, const int32_t *first, const uint8_t *active, int64_t *out, int B,
+                        hipStream_t s);
+
 inline int64_t ell_slices(const LevelDev &g) { return (int64_t)tiles_for(g) * (kBlock / 64); }
 inline void set_tiles(LevelDev &g, int dim) {
     g.ntx = (g.n[0] + kTX - 1) / kTX;

@@ -98,3 +98,7 @@ def test_null_handle_calls_fail_cleanly(slhjb):
     assert L.hjb_adjoint(None, None, None, None, None, 1, None, None, 1.0, None, None, None, None, None, None, None,
                          None) == -1
     L.hjb_destroy(None)
+    assert L.hjb_solve_batch(None, None, None, None, None, 1, None, None, 1.0, None, None, None) == -1
+    assert L.hjb_batch_layout(None, None, None) == -1
+    assert L.hjb_setup_batch(None, 0, None) == -1
+    L.hjb_destroy_batch(None)

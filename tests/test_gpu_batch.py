@@ -1,0 +1,121 @@
+"""Batched solves (hjb_setup_batch / hjb_solve_batch) against the oracle and against single-instance solves.
+
+Each batch mixes grid sizes, coefficient models, control counts and multigrid depths: x-scaled
+two-asset instances, ragged boxes with discounting and drift, a grid that cannot coarsen (solved on
+one level in LDS) and one that cannot coarsen and is too large for that (Jacobi sweeps).  All
+instances share one schedule.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import log, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def slhjb():
+    import paper_1605_04821_amd as m
+    return m
+
+
+def _toy(n, K, P, seed, c=True, drift=True):
+    rng = np.random.default_rng(seed)
+    dim = len(n)
+    N = int(np.prod(n))
+    inst = workloads.Instance(name=f"toy{n}", dim=dim, n=tuple(n), lo=(0.0,) * dim, h=1.0 / (max(n) - 1), K=K, P=P,
+                              sigma=rng.normal(size=(K, P, dim)),
+                              drift=rng.normal(size=(K, dim)) * 0.4 if drift else None,
+                              c=-rng.uniform(0.0, 1.0, size=K) if c else None, f0=rng.normal(size=N),
+                              f1=rng.normal(size=N), g=rng.normal(size=N), psi=np.zeros(N),
+                              dts=np.array([0.05]), thetas=np.array([1.0]))
+    inst.psi = np.where(inst.boundary_mask(), rng.normal(size=N) * 0.3, 0.0)
+    return inst
+
+
+def _schedule(insts, dts, thetas):
+    for inst in insts:
+        inst.dts = np.asarray(dts, float)
+        inst.thetas = np.asarray(thetas, float)
+    return insts
+
+
+def _batch_2d():
+    insts = [workloads.c4_instance(65, 0.12, 0.29, 0.35, 0.02),
+             workloads.c4_instance(17, 0.15, 0.31, 0.45, 0.04),
+             _toy((37, 29), K=5, P=2, seed=3),
+             workloads.c4_instance(33, 0.18, 0.30, 0.32, 0.01),
+             _toy((30, 27), K=4, P=1, seed=9),        # odd cell counts: one level, LDS solve
+             _toy((52, 47), K=3, P=1, seed=11)]       # one level of 2444 nodes: Jacobi sweeps
+    return _schedule(insts, [0.02, 0.02, 0.01, 0.01], [1.0, 1.0, 0.5, 0.5])
+
+
+def _run_batch(slhjb, insts, opts):
+    bt = slhjb.Batch(insts, opts)
+    g, psi, f0, f1 = (to_dev(bt.concat(k)) for k in ("g", "psi", "f0", "f1"))
+    U = torch.empty_like(g)
+    pol = torch.empty((len(insts[0].dts), bt.total), dtype=torch.int16, device="cuda")
+    st = bt.solve(g, psi, f0, f1, insts[0].dts, insts[0].thetas, 1.0, U, pol)
+    out = [to_np(u) for u in bt.split(U)]
+    pols = [to_np(pol[:, o:o + inst.N]) for inst, o in zip(insts, bt.offsets)]
+    bt.close()
+    return out, pols, st
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_matches_oracle_and_single(slhjb, precision):
+    insts = _batch_2d()
+    log(f"batch of {len(insts)} 2D instances, precision={precision}")
+    opts = slhjb.Options(precision=precision)
+    Ub, pb, st = _run_batch(slhjb, insts, opts)
+    for b, inst in enumerate(insts):
+        ref = oracle.march(inst, keep_policies=True)
+        rel = np.max(np.abs(Ub[b] - ref["U"])) / np.max(np.abs(ref["U"]))
+        solver = slhjb.Solver.from_instance(inst, opts)
+        g = to_dev(inst.g)
+        U1 = torch.empty_like(g)
+        pol1 = torch.empty((len(inst.dts), inst.N), dtype=torch.int16, device="cuda")
+        st1 = solver.solve(g, to_dev(inst.psi), to_dev(inst.f0), to_dev(inst.f1), inst.dts, inst.thetas, 1.0, U1, pol1)
+        solver.close()
+        rel1 = np.max(np.abs(Ub[b] - to_np(U1))) / np.max(np.abs(to_np(U1)))
+        log(f"  {inst.name}: batch pi={st[b].pi_total} krylov={st[b].krylov_total} | single pi={st1.pi_total} "
+            f"krylov={st1.krylov_total} | rel vs oracle {rel:.2e}, vs single {rel1:.2e}")
+        assert st[b].steps_done == len(inst.dts)
+        assert rel <= 1e-10
+        assert rel1 <= 1e-10
+
+
+def test_batch_of_one_equals_single(slhjb):
+    inst = _schedule([workloads.c4_instance(65, 0.12, 0.29, 0.35, 0.02)], [0.02] * 3, [1.0] * 3)[0]
+    Ub, pb, st = _run_batch(slhjb, [inst], slhjb.Options(precision=0))
+    solver = slhjb.Solver.from_instance(inst, slhjb.Options(precision=0))
+    g = to_dev(inst.g)
+    U1 = torch.empty_like(g)
+    pol1 = torch.empty((3, inst.N), dtype=torch.int16, device="cuda")
+    solver.solve(g, to_dev(inst.psi), to_dev(inst.f0), to_dev(inst.f1), inst.dts, inst.thetas, 1.0, U1, pol1)
+    solver.close()
+    np.testing.assert_allclose(Ub[0], to_np(U1), rtol=0, atol=1e-12 * np.max(np.abs(Ub[0])))
+    np.testing.assert_array_equal(pb[0], to_np(pol1))
+
+
+def test_batch_3d(slhjb):
+    insts = _schedule([workloads.config_c5(17, n_steps=2), workloads.config_c5(9, K=16, n_steps=2),
+                       _toy((11, 9, 13), K=5, P=1, seed=4)], [1.0 / 32] * 2, [1.0, 1.0])
+    log("batch of 3D instances")
+    Ub, pb, st = _run_batch(slhjb, insts, slhjb.Options(precision=1))
+    for b, inst in enumerate(insts):
+        ref = oracle.march(inst)
+        rel = np.max(np.abs(Ub[b] - ref["U"])) / np.max(np.abs(ref["U"]))
+        log(f"  {inst.name}: pi={st[b].pi_total} krylov={st[b].krylov_total} rel {rel:.2e}")
+        assert rel <= 1e-10
+
+
+def test_batch_rejects_bad_options(slhjb):
+    insts = _batch_2d()[:2]
+    with pytest.raises(slhjb.HJBError):
+        slhjb.Batch(insts, slhjb.Options(nu1=2, nu2=1))
+    with pytest.raises(slhjb.HJBError):
+        slhjb.Batch(insts, slhjb.Options(precond=slhjb.PRECOND_JACOBI))

@@ -10,7 +10,8 @@ Modes: "mixed" (FP32 V-cycle under FP64 FGMRES; the headline value) and "fp64" (
 Prints one JSON line.  A kernel-timer pass inside the timed region gives the roofline of the
 dominant kernel; the CPU oracle is timed on a bounded sample (see cpu_baseline.sample).  The
 "adjoint" entries time one full forward march and the discrete adjoint march after it (gradients
-with respect to f0, f1, g and s) on the 513^2 adjoint workload and on the benchmark grid.
+with respect to f0, f1, g and s) on the 513^2 adjoint workload and on the benchmark grid; the
+"batch" entry times 64 uneven two-asset instances solved as one batch and one after another.
 """
 from __future__ import annotations
 
@@ -38,6 +39,7 @@ def parse():
     ap.add_argument("--modes", default="mixed,fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch measurement")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle Krylov work in the sample")
     ap.add_argument("--pi-eta", type=float, default=None)
     ap.add_argument("--restart", type=int, default=None)
@@ -143,6 +145,51 @@ def adjoint_cost(slhjb, torch, inst, mode, reps=1):
                     "dJ_ds": ds}
     solver.close()
     return best
+
+
+def batch_cost(slhjb, torch, mode):
+    """The 64 uneven two-asset instances (65^2 ... 513^2, 50 implicit steps each) solved as one batch
+    (hjb_solve_batch, after one untimed solve) and one after another (hjb_solve per instance, each
+    solver warmed by a one-step solve)."""
+    import numpy as np
+    import workloads
+    insts = workloads.config_c4(count=64)
+    prec = slhjb.PREC_MIXED if mode == "mixed" else slhjb.PREC_FP64
+    opts = slhjb.Options(precision=prec)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    dts, ths = insts[0].dts, insts[0].thetas
+    bt = slhjb.Batch(insts, opts)
+    g, psi, f0, f1 = (dev(bt.concat(k)) for k in ("g", "psi", "f0", "f1"))
+    U = torch.empty_like(g)
+    times = []
+    for r in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = bt.solve(g, psi, f0, f1, dts, ths, 1.0, U)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    Ub = [u.clone() for u in bt.split(U)]
+    bt.close()
+    seq = 0.0
+    worst = 0.0
+    for b, inst in enumerate(insts):
+        sv = slhjb.Solver.from_instance(inst, opts)
+        gg, pp, a0, a1 = dev(inst.g), dev(inst.psi), dev(inst.f0), dev(inst.f1)
+        u1 = torch.empty_like(gg)
+        sv.solve(gg, pp, a0, a1, dts[:1], ths[:1], 1.0, u1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sv.solve(gg, pp, a0, a1, dts, ths, 1.0, u1)
+        torch.cuda.synchronize()
+        seq += time.perf_counter() - t0
+        worst = max(worst, float((u1 - Ub[b]).abs().max().item() / Ub[b].abs().max().item()))
+        sv.close()
+    steps = len(insts) * len(dts)
+    return {"workload": f"64 two-asset instances (n in {{65,129,257,513}}, {sum(i.N for i in insts)} nodes), "
+                        f"{len(dts)} implicit steps each", "mode": mode, "batch_s": round(times[-1], 4),
+            "sequential_s": round(seq, 4), "speedup": round(seq / times[-1], 2),
+            "instance_steps_per_s": round(steps / times[-1], 1), "pi_total": int(sum(x.pi_total for x in st)),
+            "krylov_total": int(sum(x.krylov_total for x in st)), "max_rel_diff_vs_sequential": worst}
 
 
 def measured_traffic(kernel, pi_per_step):
@@ -292,6 +339,12 @@ def main():
             print(f"[bench]   forward {a['forward_s']:.3f} s, adjoint {a['adjoint_s']:.3f} s "
                   f"({a['adjoint_over_forward']:.2f}x)", file=sys.stderr, flush=True)
             adj.append(a)
+    batch = None
+    if not args.no_batch:
+        print("[bench] batch of 64 two-asset instances", file=sys.stderr, flush=True)
+        batch = batch_cost(slhjb, torch, "mixed")
+        print(f"[bench]   batch {batch['batch_s']:.3f} s, one by one {batch['sequential_s']:.3f} s "
+              f"({batch['speedup']:.1f}x)", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
@@ -317,6 +370,7 @@ def main():
         "roofline": roof,
         "stencil_kernels_hbm": stencil_roof,
         "adjoint": adj,
+        "batch": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -231,6 +231,18 @@ int hjb_solve_batch(hjb_batch *bh, const double *g, const double *psi, const dou
                     int16_t *policies, hjb_solve_stats *st);
 void hjb_destroy_batch(hjb_batch *bh);
 
+/* Node tile of the kernels' blocks (256 threads): width 16, 32 (default), 64 or 128 nodes along x.
+   Results do not depend on it apart from the order of the reductions inside the Krylov solver. */
+int hjb_set_tile_width(hjb_handle *hd, int32_t width);
+/* Chooses the tile width for this handle's grid and coefficients by timing the search, the operator
+   apply and the V-cycle on synthetic data for each width (weighted as 9.5 searches and 45 Krylov
+   iterations per time step), and keeps it in the handle.  cache_path (nullable): a JSON-lines file of
+   earlier choices keyed by dim, n, K, P, stencil points, coefficient model, precision and stencil reach
+   at the handle's current s; a hit skips the timing, a miss appends the new choice.
+   tile_width_out, cost_ms_out (host, nullable; cost_ms_out: 4 entries for widths 16..128, filled only
+   when timed).  Overwrites the handle's work buffers; synchronises the stream. */
+int hjb_autotune(hjb_handle *hd, const char *cache_path, int32_t *tile_width_out, double *cost_ms_out);
+
 /* Kernel timers.  Any caller that wants the duration of one class of kernel launches during real work
    (e.g. a benchmark's roofline) enables a timer; each launch of that class is then bracketed by HIP events
    on the handle's stream (at most max_launches launches are recorded; enable again to reset).

@@ -26,7 +26,7 @@ PRECOND_NONE, PRECOND_JACOBI, PRECOND_VCYCLE = 0, 1, 2
 EXPORTED = ["hjb_desc_default", "hjb_setup", "hjb_set_stream", "hjb_set_options", "hjb_policy_sweep", "hjb_apply",
             "hjb_linsolve", "hjb_step", "hjb_solve", "hjb_adjoint", "hjb_apply_transposed", "hjb_profile_enable",
             "hjb_profile_read", "hjb_destroy", "hjb_last_error", "hjb_setup_batch", "hjb_batch_layout",
-            "hjb_batch_set_stream", "hjb_solve_batch", "hjb_destroy_batch"]
+            "hjb_batch_set_stream", "hjb_solve_batch", "hjb_destroy_batch", "hjb_set_tile_width", "hjb_autotune"]
 KERNEL_APPLY, KERNEL_SMOOTH, KERNEL_MG_RESID, KERNEL_DOT, KERNEL_AXPY, KERNEL_SWEEP = range(6)
 KERNEL_NAMES = {KERNEL_APPLY: "apply", KERNEL_SMOOTH: "smooth", KERNEL_MG_RESID: "mg_residual",
                 KERNEL_DOT: "multidot", KERNEL_AXPY: "multiaxpy", KERNEL_SWEEP: "sweep"}
@@ -67,6 +67,9 @@ class AdjointStats(ctypes.Structure):
 
 
 def _load():
+    # torch's HIP runtime must be loaded first: the library's libamdhip64 dependency then binds to it
+    # (same soname) and both share one runtime and one set of streams
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libslhjb.so not built ({LIB_PATH}); run __graft_entry__.build() or "
                           f"python paper_1605_04821_amd/build.py")
@@ -93,6 +96,8 @@ def _load():
     L.hjb_solve_batch.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, d, vp, vp, ctypes.POINTER(SolveStats)]
     L.hjb_destroy_batch.argtypes = [vp]
     L.hjb_destroy_batch.restype = None
+    L.hjb_set_tile_width.argtypes = [vp, i32]
+    L.hjb_autotune.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i32), ctypes.POINTER(d)]
     L.hjb_profile_enable.argtypes = [vp, i32, i32]
     L.hjb_profile_read.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d)]
     L.hjb_destroy.argtypes = [vp]
@@ -181,7 +186,7 @@ class Solver:
         desc.drift = None if self._drift is None else self._drift.ctypes.data
         desc.c = None if self._c is None else self._c.ctypes.data
         self._fill_options(desc, self.options)
-        desc.stream = None
+        desc.stream = _stream()   # torch initialises the device first; the library works on its stream
         self._desc = desc
         h_ = ctypes.c_void_p()
         _check(_lib.hjb_setup(ctypes.byref(desc), ctypes.byref(h_)))
@@ -273,6 +278,20 @@ class Solver:
                                 ctypes.byref(st)))
         return (float(ds.value) if want_ds else None), st
 
+    def set_tile_width(self, width: int):
+        self._sync_stream()
+        _check(_lib.hjb_set_tile_width(self._h, int(width)))
+
+    def autotune(self, cache_path: Optional[str] = None):
+        """hjb_autotune; returns (tile width, {width: weighted cost in ms} or None on a cache hit)."""
+        self._sync_stream()
+        w = ctypes.c_int32(0)
+        costs = (ctypes.c_double * 4)(*([float("nan")] * 4))
+        _check(_lib.hjb_autotune(self._h, None if cache_path is None else os.fsencode(cache_path), ctypes.byref(w),
+                                 costs))
+        c = {16 << q: float(costs[q]) for q in range(4)}
+        return int(w.value), (None if all(v != v for v in c.values()) else c)
+
     def profile_enable(self, kernel: int, max_launches: int = 4096):
         self._sync_stream()
         _check(_lib.hjb_profile_enable(self._h, int(kernel), int(max_launches)))
@@ -328,7 +347,7 @@ class Batch:
             d.drift = None if dr is None else dr.ctypes.data
             d.c = None if cc is None else cc.ctypes.data
             Solver._fill_options(d, self.options)
-            d.stream = None
+            d.stream = _stream()
         h = ctypes.c_void_p()
         _check(_lib.hjb_setup_batch(descs, B, ctypes.byref(h)))
         self._h = h

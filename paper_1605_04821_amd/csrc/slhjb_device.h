@@ -15,7 +15,7 @@ __device__ __forceinline__ int remap_block(int b, int nb) {
 
 __device__ __forceinline__ int node_id() { return remap_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x; }
 
-// Node of this thread: blocks cover kTX x kTY tiles (x fastest, then y, then z), so that the stencil
+// Node of this thread: blocks cover 2^tlog x (256 / 2^tlog) tiles (x fastest, then y, then z), so that the stencil
 // rows gathered by vertically adjacent nodes are shared in cache.  Returns -1 outside the grid.
 template <int DIM>
 __device__ __forceinline__ int tile_node(const LevelDev &g, int ix[3]) {
@@ -23,8 +23,8 @@ __device__ __forceinline__ int tile_node(const LevelDev &g, int ix[3]) {
     int bx = b % g.ntx, r = b / g.ntx;
     int by = DIM == 3 ? r % g.nty : r;
     int bz = DIM == 3 ? r / g.nty : 0;
-    ix[0] = bx * kTX + (int)(threadIdx.x % kTX);
-    ix[1] = by * kTY + (int)(threadIdx.x / kTX);
+    ix[0] = (bx << g.tlog) + (int)(threadIdx.x & ((1u << g.tlog) - 1));
+    ix[1] = by * (kBlock >> g.tlog) + (int)(threadIdx.x >> g.tlog);
     ix[2] = bz;
     if (ix[0] >= g.n[0] || ix[1] >= g.n[1]) return -1;
     return ix[0] + ix[1] * (int)g.s1 + (DIM == 3 ? ix[2] * (int)g.s2 : 0);

@@ -76,6 +76,8 @@ struct hjb_handle {
     int dim = 2;
     int64_t N = 0;
     int nb = 0, nbd = 0;
+    int nb_cap = 0;      // largest level-0 tile count over the tile shapes the handle may take
+    int tlog = kTileLog2;
     std::vector<Level> lev;
     double s_tab = -1.0;
     double *c_dev = nullptr;
@@ -871,6 +873,7 @@ int setup_impl(const hjb_desc *desc, hjb_handle **out, bool tables_only) {
             L.g.N = (int64_t)L.g.n[0] * L.g.n[1] * L.g.n[2];
             L.g.s1 = L.g.n[0];
             L.g.s2 = (int64_t)L.g.n[0] * L.g.n[1];
+            L.g.tlog = kTileLog2;
             set_tiles(L.g, d.dim);
             hd->lev.push_back(L);
             bool can = true, small = true;
@@ -900,6 +903,12 @@ int setup_impl(const hjb_desc *desc, hjb_handle **out, bool tables_only) {
         STRY(dalloc(hd, &L.d32, n * 4));
     }
     hd->nb = tiles_for(hd->lev[0].g);  // blocks of the node kernels on the finest grid (partial sums)
+    for (int tl = kTileLogMin; tl <= kTileLogMax; ++tl) {
+        LevelDev g = hd->lev[0].g;
+        g.tlog = tl;
+        set_tiles(g, d.dim);
+        hd->nb_cap = std::max(hd->nb_cap, tiles_for(g));
+    }
     select_precision(hd);
     if (!tables_only) {
     STRY(dalloc(hd, (void **)&hd->E, N * 8));
@@ -914,7 +923,7 @@ int setup_impl(const hjb_desc *desc, hjb_handle **out, bool tables_only) {
     STRY(dalloc(hd, (void **)&hd->acarry, N * 2));
     {
         // cache of the explicit part of the search values (K doubles per node) when it is affordable
-        size_t qbytes = (size_t)d.K * (size_t)hd->nb * kBlock * 8;  // tile-major, one slot per thread
+        size_t qbytes = (size_t)d.K * (size_t)hd->nb_cap * kBlock * 8;  // tile-major, one slot per thread
         size_t freeb = 0, totalb = 0;
         if (hipMemGetInfo(&freeb, &totalb) == hipSuccess && qbytes <= freeb / 4 && qbytes <= ((size_t)16 << 30)) {
             void *p = nullptr;
@@ -927,10 +936,10 @@ int setup_impl(const hjb_desc *desc, hjb_handle **out, bool tables_only) {
         }
     }
     }
-    size_t np = tables_only ? 16 : std::max<size_t>(3 * (size_t)hd->nb, (size_t)(kMaxRestart + 2) * hd->nbd);
+    size_t np = tables_only ? 16 : std::max<size_t>(3 * (size_t)hd->nb_cap, (size_t)(kMaxRestart + 2) * hd->nbd);
     STRY(dalloc(hd, (void **)&hd->partial, np * 8));
     STRY(dalloc(hd, (void **)&hd->dvals, 256 * 8));
-    STRY(dalloc(hd, (void **)&hd->ipartial, (size_t)hd->nb * 8));
+    STRY(dalloc(hd, (void **)&hd->ipartial, (size_t)hd->nb_cap * 8));
     STRY(dalloc(hd, (void **)&hd->ival, 64));
     if (!hd->c.empty()) {
         STRY(dalloc(hd, (void **)&hd->c_dev, (size_t)d.K * 8));
@@ -1137,6 +1146,164 @@ int hjb_profile_read(hjb_handle *hd, int32_t kernel, int64_t *launches, double *
     if (total_ms) *total_ms = ms;
     if (total_bytes) *total_bytes = by;
     if (total_flops) *total_flops = fl;
+    return HJB_OK;
+}
+
+}  // extern "C"
+
+// ---- tile shape and its tuner ---------------------------------------------------------------------
+
+namespace {
+
+// every level takes width 2^tlog, but not wider than the level's own next power of two
+void apply_tiles(hjb_handle *hd, int tlog) {
+    for (Level &L : hd->lev) {
+        int w = kTileLogMin;
+        while (w < tlog && (1 << w) < L.g.n[0]) ++w;
+        L.g.tlog = w;
+        set_tiles(L.g, hd->dim);
+    }
+    hd->nb = tiles_for(hd->lev[0].g);
+    hd->tlog = tlog;
+    drop_graphs(hd);
+}
+
+std::string tune_key(const hjb_handle *hd) {
+    const hjb_desc &d = hd->desc;
+    double reach = 0.0, xmax = 1.0;
+    if (d.coef_model == HJB_COEF_XSCALED) {
+        xmax = 0.0;
+        for (int a = 0; a < d.dim; ++a)
+            xmax = std::max(xmax, std::max(fabs(d.lo[a]), fabs(d.lo[a] + (d.n[a] - 1) * d.h)));
+    }
+    const double sr = hd->s_tab * (1.0 / sqrt(d.h));
+    for (double v : hd->sigma) reach = std::max(reach, fabs(sr * v) * xmax);
+    for (double v : hd->drift) reach = std::max(reach, fabs(v) * xmax);
+    char buf[256];
+    snprintf(buf, sizeof buf, "dim=%d n=%dx%dx%d K=%d P=%d npt=%d coef=%d prec=%d reach=%.1f", d.dim, d.n[0],
+             d.dim > 1 ? d.n[1] : 1, d.dim > 2 ? d.n[2] : 1, d.K, d.P, hd->npt, d.coef_model, d.precision,
+             std::round(reach * 2.0) / 2.0);
+    return buf;
+}
+
+// tile width recorded for `key` in a JSON-lines cache, or 0
+int cache_lookup(const char *path, const std::string &key) {
+    FILE *f = fopen(path, "r");
+    if (!f) return 0;
+    char line[4096];
+    int found = 0;
+    const std::string pat = "\"key\": \"" + key + "\"";
+    while (fgets(line, sizeof line, f)) {
+        if (!strstr(line, pat.c_str())) continue;
+        const char *w = strstr(line, "\"tile_width\": ");
+        if (w) found = atoi(w + 14);
+    }
+    fclose(f);
+    return found;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hjb_set_tile_width(hjb_handle *hd, int32_t width) {
+    if (!hd) return fail(HJB_EINVAL, "null handle");
+    int tl = -1;
+    for (int c = kTileLogMin; c <= kTileLogMax; ++c)
+        if (width == (1 << c)) tl = c;
+    if (tl < 0) return fail(HJB_EINVAL, "tile width must be 16, 32, 64 or 128");
+    HIPCHK(hipStreamSynchronize(hd->stream));
+    apply_tiles(hd, tl);
+    return HJB_OK;
+}
+
+int hjb_autotune(hjb_handle *hd, const char *cache_path, int32_t *tile_width_out, double *cost_ms_out) {
+    if (!hd) return fail(HJB_EINVAL, "null handle");
+    const std::string key = tune_key(hd);
+    if (cache_path) {
+        int w = cache_lookup(cache_path, key);
+        if (w) {
+            TRY(hjb_set_tile_width(hd, w));
+            if (tile_width_out) *tile_width_out = w;
+            return HJB_OK;
+        }
+    }
+    const int64_t N = hd->N;
+    const int dim = hd->dim;
+    hipStream_t s = hd->stream;
+    HIPCHK(hipStreamSynchronize(s));
+    // synthetic data: zero fields, a policy of 8-node patches cycling through the controls
+    std::vector<int16_t> pol((size_t)N);
+    const hjb_desc &d = hd->desc;
+    for (int64_t i = 0; i < N; ++i) {
+        int ix = (int)(i % d.n[0]), r = (int)(i / d.n[0]);
+        int iy = dim > 1 ? r % d.n[1] : 0, iz = dim > 2 ? r / d.n[1] : 0;
+        bool bd = ix == 0 || ix == d.n[0] - 1 || iy == 0 || iy == d.n[1] - 1 ||
+                  (dim == 3 && (iz == 0 || iz == d.n[2] - 1));
+        pol[(size_t)i] = bd ? -1 : (int16_t)((ix / 8 + 3 * (iy / 8) + 5 * (iz / 8)) % d.K);
+    }
+    HIPCHK(hipMemcpy(hd->a0, pol.data(), (size_t)N * 2, hipMemcpyHostToDevice));
+    launch_zero(hd->Ua, (size_t)N * 8, s);
+    launch_zero(hd->Uc, (size_t)N * 8, s);
+    launch_zero(hd->E, (size_t)N * 8, s);
+    launch_zero(hd->R, (size_t)N * 8, s);
+    launch_zero(hd->Vb, (size_t)N * 8, s);
+    launch_zero(hd->Zb, (size_t)N * 8, s);
+    const double dt = 1.0 / 64, theta_dt = dt;
+    const bool zf = mixed(hd) && hd->desc.precond != HJB_PRECOND_NONE;
+    hipEvent_t ev[4];
+    for (hipEvent_t &e : ev) HIPCHK(hipEventCreate(&e));
+    double best = INFINITY;
+    int best_tl = hd->tlog;
+    std::vector<std::pair<int, double>> costs;
+    int rc = HJB_OK;
+    for (int tl = kTileLogMin; tl <= kTileLogMax && rc == HJB_OK; ++tl) {
+        apply_tiles(hd, tl);
+        TRY(prepare_mg(hd, hd->a0, theta_dt));
+        // weights: searches and Krylov iterations (one apply and one V-cycle each) per time step of the
+        // Crank-Nicolson benchmark march
+        const int ns = 2, na = 5;
+        for (int rep = 0; rep < 2; ++rep) {  // the first pass warms caches and code
+            HIPCHK(hipEventRecord(ev[0], s));
+            for (int q = 0; q < ns; ++q)
+                TRY(sweep(hd, hd->Ua, hd->Uc, hd->E, hd->R, 0.0, dt, 1.0, hd->a0, hd->a1, nullptr, nullptr, nullptr,
+                          nullptr, nullptr, 0));
+            HIPCHK(hipEventRecord(ev[1], s));
+            for (int q = 0; q < na; ++q)
+                launch_apply(dim, hd->lev[0].g, stencil(hd, 0), hd->a0, hd->Zb, zf, hd->Vb + N, theta_dt, nullptr,
+                             hd->nb, s);
+            HIPCHK(hipEventRecord(ev[2], s));
+            if (hd->desc.precond != HJB_PRECOND_NONE)
+                for (int q = 0; q < na; ++q) precondition_eager(hd, hd->Vb, hd->Zb, theta_dt);
+            HIPCHK(hipEventRecord(ev[3], s));
+        }
+        HIPCHK(hipEventSynchronize(ev[3]));
+        float t_sw = 0, t_ap = 0, t_vc = 0;
+        HIPCHK(hipEventElapsedTime(&t_sw, ev[0], ev[1]));
+        HIPCHK(hipEventElapsedTime(&t_ap, ev[1], ev[2]));
+        HIPCHK(hipEventElapsedTime(&t_vc, ev[2], ev[3]));
+        double cost = 9.5 * t_sw / ns + 45.0 * (t_ap + t_vc) / na;
+        costs.push_back({1 << tl, cost});
+        if (cost < best) {
+            best = cost;
+            best_tl = tl;
+        }
+    }
+    for (hipEvent_t &e : ev) (void)hipEventDestroy(e);
+    apply_tiles(hd, best_tl);
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "{\"key\": \"%s\", \"tile_width\": %d, \"cost_ms\": {", key.c_str(), 1 << best_tl);
+            for (size_t q = 0; q < costs.size(); ++q)
+                fprintf(f, "%s\"%d\": %.4f", q ? ", " : "", costs[q].first, costs[q].second);
+            fprintf(f, "}}\n");
+            fclose(f);
+        }
+    }
+    if (tile_width_out) *tile_width_out = 1 << best_tl;
+    if (cost_ms_out)
+        for (size_t q = 0; q < costs.size(); ++q) cost_ms_out[q] = costs[q].second;
     return HJB_OK;
 }
 

@@ -11,7 +11,8 @@ constexpr int kMaxP = 4;                 // diffusion columns per control
 constexpr int kMaxPts = 2 * kMaxP + 1;   // stencil points per control (Scheme 2: 2P diffusion + 1 drift)
 constexpr int kBlock = 256;              // threads per block of the node-parallel kernels
 constexpr int kMaxRestart = 64;
-constexpr int kTX = 32, kTY = 8;         // node tile of one block (kTX * kTY == kBlock)
+constexpr int kTileLog2 = 5;             // default node tile of one block: 32 x 8 (width 2^kTileLog2)
+constexpr int kTileLogMin = 4, kTileLogMax = 7;  // tile widths 16 ... 128 (heights 16 ... 2)
 
 // One stencil point of one control on one grid level.  Y is the displacement in cells of that level
 // (diffusion: s*sigma_p/sqrt(h) scaled to the level, drift: b scaled to the level).  The remaining
@@ -43,7 +44,8 @@ struct FastPtD {
 
 struct LevelDev {
     int32_t n[3];
-    int32_t ntx, nty, ntz;           // tiles of kTX x kTY x 1 nodes covering the grid
+    int32_t tlog;                    // tile width 2^tlog nodes along x, height kBlock / 2^tlog along y
+    int32_t ntx, nty, ntz;           // tiles covering the grid
     int32_t deep_lo[3], deep_hi[3];  // nodes with deep_lo <= i_d <= deep_hi never truncate
     int64_t N;
     int64_t s1, s2;                  // strides of axes 1 and 2
@@ -281,8 +283,9 @@ void launch_seg_sum_i64(const int64_t *partial, int n, const int32_t *first, con
 
 inline int64_t ell_slices(const LevelDev &g) { return (int64_t)tiles_for(g) * (kBlock / 64); }
 inline void set_tiles(LevelDev &g, int dim) {
-    g.ntx = (g.n[0] + kTX - 1) / kTX;
-    g.nty = (g.n[1] + kTY - 1) / kTY;
+    const int tx = 1 << g.tlog, ty = kBlock >> g.tlog;
+    g.ntx = (g.n[0] + tx - 1) / tx;
+    g.nty = (g.n[1] + ty - 1) / ty;
     g.ntz = dim == 3 ? g.n[2] : 1;
 }
 

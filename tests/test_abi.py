@@ -102,3 +102,5 @@ def test_null_handle_calls_fail_cleanly(slhjb):
     assert L.hjb_batch_layout(None, None, None) == -1
     assert L.hjb_setup_batch(None, 0, None) == -1
     L.hjb_destroy_batch(None)
+    assert L.hjb_set_tile_width(None, 32) == -1
+    assert L.hjb_autotune(None, None, None, None) == -1

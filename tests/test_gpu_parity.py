@@ -230,3 +230,56 @@ def test_vcycle_graph_replays_match_eager(slhjb):
         solver.close()
     for o in outs[1:]:
         np.testing.assert_array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("width", [16, 64, 128])
+def test_tile_widths_sweep_and_march(slhjb, width):
+    """Every tile shape gives the bit-exact search and a march within the parity bound."""
+    for name, mk in (("c2_65", lambda: workloads.config_c2(65)), ("ragged_3d", lambda: _toy((11, 9, 13), K=5, P=1, seed=4)),
+                     ("xscaled_ragged", lambda: _xscaled_toy((31, 23), seed=6))):
+        inst = mk()
+        log(f"tile width {width}: sweep {name}")
+        pb = oracle.Problem(inst)
+        X, U = workloads.random_fields(inst, seed=11)
+        a_in = workloads.random_policy(inst, seed=12)
+        t_prev, dt, theta = 0.1, 0.02, 0.5
+        f = pb.f_at(inst.f0, inst.f1, t_prev + theta * dt)
+        ref = pb.improve(X, U, theta, f, pb.tau(X, U, f), a_in, want_extra=False)
+        solver = slhjb.Solver.from_instance(inst)
+        solver.set_tile_width(width)
+        da = torch.empty(inst.N, dtype=torch.int16, device="cuda")
+        solver.policy_sweep(to_dev(X), to_dev(U), to_dev(inst.f0), to_dev(inst.f1), t_prev, dt, theta, 1.0,
+                            to_dev(a_in), da)
+        np.testing.assert_array_equal(to_np(da), ref["alpha"])
+        solver.close()
+    inst = workloads.config_c2(65, n_cn=4)
+    ref = oracle.march(inst)
+    solver = slhjb.Solver.from_instance(inst, slhjb.Options(precision=1))
+    solver.set_tile_width(width)
+    g = to_dev(inst.g)
+    U = torch.empty_like(g)
+    solver.solve(g, to_dev(inst.psi), to_dev(inst.f0), to_dev(inst.f1), inst.dts, inst.thetas, 1.0, U)
+    rel = np.max(np.abs(to_np(U) - ref["U"])) / np.max(np.abs(ref["U"]))
+    log(f"  march c2_65 rel {rel:.2e}")
+    assert rel <= 1e-10
+    solver.close()
+
+
+def test_autotune_and_cache(slhjb, tmp_path):
+    inst = workloads.config_c2(129, n_cn=2)
+    cache = tmp_path / "tiles.jsonl"
+    solver = slhjb.Solver.from_instance(inst, slhjb.Options(precision=1))
+    w, costs = solver.autotune(str(cache))
+    log(f"autotune 129^2: width {w}, costs {costs}")
+    assert w in (16, 32, 64, 128) and costs is not None and min(costs, key=costs.get) == w
+    w2, costs2 = solver.autotune(str(cache))   # cache hit
+    assert w2 == w and costs2 is None
+    assert len(cache.read_text().strip().splitlines()) == 1
+    # the tuned handle still solves to the parity bound
+    ref = oracle.march(inst)
+    g = to_dev(inst.g)
+    U = torch.empty_like(g)
+    solver.solve(g, to_dev(inst.psi), to_dev(inst.f0), to_dev(inst.f1), inst.dts, inst.thetas, 1.0, U)
+    rel = np.max(np.abs(to_np(U) - ref["U"])) / np.max(np.abs(ref["U"]))
+    assert rel <= 1e-10
+    solver.close()

@@ -135,6 +135,13 @@ def _stream():
     return torch.cuda.current_stream().cuda_stream
 
 
+def _setup_stream():
+    """torch's current stream (initialising torch's device first), or NULL without a device: setup then
+    reports HJB_EDEVICE itself."""
+    import torch
+    return _stream() if torch.cuda.is_available() else None
+
+
 @dataclass
 class Options:
     precision: int = PREC_FP64
@@ -186,7 +193,7 @@ class Solver:
         desc.drift = None if self._drift is None else self._drift.ctypes.data
         desc.c = None if self._c is None else self._c.ctypes.data
         self._fill_options(desc, self.options)
-        desc.stream = _stream()   # torch initialises the device first; the library works on its stream
+        desc.stream = _setup_stream()   # torch initialises the device first; the library works on its stream
         self._desc = desc
         h_ = ctypes.c_void_p()
         _check(_lib.hjb_setup(ctypes.byref(desc), ctypes.byref(h_)))
@@ -347,7 +354,7 @@ class Batch:
             d.drift = None if dr is None else dr.ctypes.data
             d.c = None if cc is None else cc.ctypes.data
             Solver._fill_options(d, self.options)
-            d.stream = _stream()
+            d.stream = _setup_stream()
         h = ctypes.c_void_p()
         _check(_lib.hjb_setup_batch(descs, B, ctypes.byref(h)))
         self._h = h

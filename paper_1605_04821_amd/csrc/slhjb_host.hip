@@ -1737,6 +1737,13 @@ struct hjb_batch {
     int32_t *hm = nullptr;
     uint8_t *hmask[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<void *> allocs, pinned;
+    struct VGraph {
+        const void *a0, *v, *z;
+        double theta_dt;
+        hipGraphExec_t exec;
+    };
+    std::vector<VGraph> vgraphs;    // captured batched V-cycles (masks are read from fixed buffers)
+    hipStream_t capture_stream = nullptr;
 };
 
 namespace {
@@ -1901,6 +1908,52 @@ void bvcycle(hjb_batch *bh, const T *r0, T *z, double theta_dt, const int16_t *a
     }
 }
 
+void bprecondition_eager(hjb_batch *bh, const double *v, void *z, double theta_dt, const int16_t *alpha,
+                         const uint8_t *mask) {
+    if (bh->opt.precision == HJB_PREC_MIXED) {
+        launch_to_precond(v, bh->lev[0].r32, true, bh->N, bh->stream);
+        bvcycle<float>(bh, (const float *)bh->lev[0].r32, (float *)z, theta_dt, alpha, mask);
+    } else {
+        bvcycle<double>(bh, v, (double *)z, theta_dt, alpha, mask);
+    }
+}
+
+// z = V-cycle(v) for the instances flagged in mask, replayed from a graph captured once per
+// (policy buffer, v, z, theta*dt); the flags, diagonals and policies are read from fixed buffers
+int bprecondition(hjb_batch *bh, const double *v, void *z, double theta_dt, const int16_t *alpha, const uint8_t *mask) {
+    if (!bh->opt.use_graphs) {
+        bprecondition_eager(bh, v, z, theta_dt, alpha, mask);
+        return HJB_OK;
+    }
+    for (auto &g : bh->vgraphs)
+        if (g.a0 == alpha && g.v == v && g.z == z && g.theta_dt == theta_dt) {
+            HIPCHK(hipGraphLaunch(g.exec, bh->stream));
+            return HJB_OK;
+        }
+    if (bh->vgraphs.size() >= 256) {
+        for (auto &g : bh->vgraphs) (void)hipGraphExecDestroy(g.exec);
+        bh->vgraphs.clear();
+    }
+    if (!bh->capture_stream) HIPCHK(hipStreamCreateWithFlags(&bh->capture_stream, hipStreamNonBlocking));
+    hipStream_t saved = bh->stream;
+    bh->stream = bh->capture_stream;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(bh->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        bprecondition_eager(bh, v, z, theta_dt, alpha, mask);
+        e = hipStreamEndCapture(bh->capture_stream, &graph);
+    }
+    bh->stream = saved;
+    if (e != hipSuccess) return fail(HJB_EDEVICE, "batched V-cycle capture: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(HJB_EDEVICE, "batched V-cycle instantiate: %s", hipGetErrorString(e));
+    bh->vgraphs.push_back({alpha, v, z, theta_dt, exec});
+    HIPCHK(hipGraphLaunch(exec, bh->stream));
+    return HJB_OK;
+}
+
 // ---- batched FGMRES ------------------------------------------------------------------------------
 
 struct BSolveOut {
@@ -1983,16 +2036,7 @@ int bfgmres(hjb_batch *bh, const int16_t *alpha, double *X, double theta_dt, con
             double *vj = bh->Vb + (int64_t)j * N;
             double *w = bh->Vb + (int64_t)(j + 1) * N;
             void *zj = none ? (void *)vj : (void *)((char *)bh->Zb + (int64_t)j * N * zsz);
-            if (!none) {
-                if (d.precond == HJB_PRECOND_JACOBI) {
-                    return fail(HJB_EUNSUPPORTED, "batched solves take the V-cycle preconditioner (or none)");
-                } else if (zf) {
-                    launch_to_precond(vj, L0.r32, true, N, s);
-                    bvcycle<float>(bh, (const float *)L0.r32, (float *)zj, theta_dt, alpha, mC);
-                } else {
-                    bvcycle<double>(bh, vj, (double *)zj, theta_dt, alpha, mC);
-                }
-            }
+            if (!none) TRY(bprecondition(bh, vj, zj, theta_dt, alpha, mC));
             launch_apply_b(dim, btiles(A0, L0.I, mC), alpha, zj, zf, w, theta_dt, s);
             std::vector<double> hn(B, 0.0);
             std::vector<uint8_t> need(inc);  // instances still orthogonalising in this pass
@@ -2403,6 +2447,8 @@ void hjb_destroy_batch(hjb_batch *bh) {
     if (!bh) return;
     if (bh->stream) (void)hipStreamSynchronize(bh->stream);
     else (void)hipDeviceSynchronize();
+    for (auto &g : bh->vgraphs) (void)hipGraphExecDestroy(g.exec);
+    if (bh->capture_stream) (void)hipStreamDestroy(bh->capture_stream);
     for (hjb_handle *h : bh->sub) hjb_destroy(h);
     for (void *p : bh->allocs) (void)hipFree(p);
     for (void *p : bh->pinned) (void)hipHostFree(p);

@@ -119,3 +119,14 @@ def test_batch_rejects_bad_options(slhjb):
         slhjb.Batch(insts, slhjb.Options(nu1=2, nu2=1))
     with pytest.raises(slhjb.HJBError):
         slhjb.Batch(insts, slhjb.Options(precond=slhjb.PRECOND_JACOBI))
+
+
+def test_batch_graph_replays_match_eager(slhjb):
+    """Batched V-cycles replayed from captured graphs (reused across Krylov iterations, policy iterations
+    and time steps, with eager work in between) give the eager results bit for bit."""
+    insts = _batch_2d()[:4]
+    Ug, pg, _ = _run_batch(slhjb, insts, slhjb.Options(precision=1, use_graphs=1))
+    Ue, pe, _ = _run_batch(slhjb, insts, slhjb.Options(precision=1, use_graphs=0))
+    for a, b, pa, pb_ in zip(Ug, Ue, pg, pe):
+        np.testing.assert_array_equal(a, b)
+        np.testing.assert_array_equal(pa, pb_)

@@ -181,7 +181,45 @@ __device__ __forceinline__ void lhat_node(const LevelDev &g, const StencilDev &s
     k = ((unsigned)k < (unsigned)st.K) ? k : 0;
     const PointTab *pt = st.tab + k * st.npt;
     TC accV = (TC)0, accW = (TC)0;
-    if (deep) {
+    if (deep && st.xs) {
+        // x-scaled coefficients away from the boundary: no point can leave the box (mu = 1, A = B = C = 1),
+        // so the landing is i + floor(Y) with fraction Y - floor(Y), the general rules' untruncated case
+        auto land1 = [&](int q, int cell[3], double t[3]) {
+            double Y[3];
+            point_Y(st, pt[q], q, ix, DIM, Y);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                double fl = floor(Y[d]);
+                cell[d] = ix[d] + (int)fl;
+                t[d] = Y[d] - fl;
+            }
+        };
+        for (int p = 0; p < st.P; ++p) {
+            int cp[3], cm[3];
+            double tp[3], tm[3];
+            land1(2 * p, cp, tp);
+            land1(2 * p + 1, cm, tm);
+            TC vp = interp_land<DIM, TS, TC>(V, g, cp, tp);
+            TC vm = interp_land<DIM, TS, TC>(V, g, cm, tm);
+            accV = accV + ((vp + vm) - (TC)2 * Vi);
+            if (TWO) {
+                TC wp = interp_land<DIM, TS, TC>(W, g, cp, tp);
+                TC wm = interp_land<DIM, TS, TC>(W, g, cm, tm);
+                accW = accW + ((wp + wm) - (TC)2 * Wi);
+            }
+        }
+        if (st.has_drift) {
+            int cb[3];
+            double tb[3];
+            land1(2 * st.P, cb, tb);
+            TC vb = interp_land<DIM, TS, TC>(V, g, cb, tb);
+            accV = accV + (TC)2 * (vb - Vi);
+            if (TWO) {
+                TC wb = interp_land<DIM, TS, TC>(W, g, cb, tb);
+                accW = accW + (TC)2 * (wb - Wi);
+            }
+        }
+    } else if (deep) {
         const typename FastOf<TC>::T *fp = FastOf<TC>::get(st) + k * st.npt;  // corner weights precomputed
         for (int p = 0; p < st.P; ++p) {
             const auto &a = fp[2 * p];

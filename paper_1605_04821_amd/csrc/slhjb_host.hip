@@ -177,13 +177,25 @@ int build_tables(hjb_handle *hd, double s) {
         fill_tables(hd, s, host, (int)l);
         // deep box: no point of any control can leave the box or be clamped from these nodes
         double E[3] = {0, 0, 0};
-        for (const PointTab &p : host)
-            for (int a = 0; a < 3; ++a) E[a] = std::max(E[a], fabs(p.Y[a]));
+        if (hd->desc.coef_model == HJB_COEF_XSCALED) {
+            // largest displacement anywhere on the grid: |sr * x * S| (diffusion), |x * beta| (drift)
+            const double sr = s * (1.0 / sqrt(hd->desc.h)), scale = ldexp(1.0, -(int)l);
+            for (int a = 0; a < hd->dim; ++a) {
+                const double xm = std::max(fabs(hd->desc.lo[a]),
+                                           fabs(hd->desc.lo[a] + (hd->desc.n[a] - 1) * hd->desc.h));
+                for (int k = 0; k < hd->desc.K; ++k)
+                    for (int q = 0; q < hd->npt; ++q) {
+                        const double y = fabs(host[(size_t)k * hd->npt + q].Y[a]) * xm * (q < 2 * hd->desc.P ? sr : 1.0);
+                        E[a] = std::max(E[a], y * scale);
+                    }
+                E[a] = E[a] * (1.0 + 1e-12) + 1e-12;  // the kernels round sr*(x*S) in another order
+            }
+        } else {
+            for (const PointTab &p : host)
+                for (int a = 0; a < 3; ++a) E[a] = std::max(E[a], fabs(p.Y[a]));
+        }
         for (int a = 0; a < 3; ++a) {
-            if (a < hd->dim && hd->desc.coef_model == HJB_COEF_XSCALED) {
-                L.g.deep_lo[a] = 1;  // displacements vary per node: no precomputed fast path
-                L.g.deep_hi[a] = 0;
-            } else if (a < hd->dim) {
+            if (a < hd->dim) {
                 int lo = (int)ceil(E[a]);
                 int hi = L.g.n[a] - 2 - (int)floor(E[a]);
                 L.g.deep_lo[a] = std::max(1, lo);

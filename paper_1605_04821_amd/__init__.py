@@ -151,7 +151,7 @@ class Options:
     max_pi: int = 50
     nu1: int = 2
     nu2: int = 2
-    coarse_sweeps: int = 30
+    coarse_sweeps: int = 10
     min_coarse: int = 17
     omega: float = 0.8
     rtol_inf: float = 1e-13

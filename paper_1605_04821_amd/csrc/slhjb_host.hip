@@ -788,7 +788,7 @@ void hjb_desc_default(hjb_desc *d) {
     d->max_pi = 50;
     d->nu1 = 2;
     d->nu2 = 2;
-    d->coarse_sweeps = 30;
+    d->coarse_sweeps = 10;
     d->min_coarse = 17;
     d->omega = 0.8;
     d->rtol_inf = 1e-13;

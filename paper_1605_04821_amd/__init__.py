@@ -149,11 +149,11 @@ class Options:
     restart: int = 10
     max_krylov: int = 600
     max_pi: int = 50
-    nu1: int = 2
-    nu2: int = 2
+    nu1: int = 3
+    nu2: int = 3
     coarse_sweeps: int = 10
     min_coarse: int = 17
-    omega: float = 0.8
+    omega: float = 0.9
     rtol_inf: float = 1e-13
     tau_rel: float = 1e-13
     pi_eta: float = 0.2

@@ -786,11 +786,11 @@ void hjb_desc_default(hjb_desc *d) {
     d->restart = 10;
     d->max_krylov = 600;
     d->max_pi = 50;
-    d->nu1 = 2;
-    d->nu2 = 2;
+    d->nu1 = 3;
+    d->nu2 = 3;
     d->coarse_sweeps = 10;
     d->min_coarse = 17;
-    d->omega = 0.8;
+    d->omega = 0.9;
     d->rtol_inf = 1e-13;
     d->tau_rel = 1e-13;
     d->pi_eta = 0.2;

@@ -51,9 +51,11 @@ enum {
 
 enum {
     HJB_COEF_CONST = 0,     /* sigma, b, c constant per control */
-    HJB_COEF_XSCALED = 1    /* sigma_k(x) = diag(x) S_k, b_k(x) = diag(x) beta_k (x the node's coordinates,
+    HJB_COEF_XSCALED = 1,   /* sigma_k(x) = diag(x) S_k, b_k(x) = diag(x) beta_k (x the node's coordinates,
                                eq. 1.1 with x-dependent coefficients): sigma holds S, drift holds beta;
                                c constant per control */
+    HJB_COEF_FIELD = 2      /* sigma(x) per node, the same for every control: sigma[(i*P + p)*dim + d]
+                               (host, N*P*dim, full grid, x fastest); drift, c constant per control */
 };
 enum { HJB_PREC_FP64 = 0, HJB_PREC_MIXED = 1 }; /* V-cycle in FP64, or in FP32 under FP64 FGMRES */
 enum { HJB_PRECOND_NONE = 0, HJB_PRECOND_JACOBI = 1, HJB_PRECOND_VCYCLE = 2 };
@@ -86,6 +88,8 @@ typedef struct {
                                residual has dropped by this factor (0: every solve to rtol_inf); the
                                last solve of a step always meets rtol_inf and is confirmed by a search */
     int32_t use_graphs;     /* 1: replay captured HIP graphs of the V-cycle (identical kernels), 0: launch eagerly */
+    int32_t f_per_control;  /* 0: f0, f1 are full-grid arrays shared by all controls; 1: [K][N], the source
+                               of each control (the search and the right-hand side take the node's control's) */
     void *stream;           /* hipStream_t */
 } hjb_desc;
 
@@ -162,7 +166,10 @@ int hjb_linsolve(hjb_handle *hd, const int16_t *alpha, const double *U, const do
    (never written) and whose interior receives U^n; alpha_io: full-grid int16, in/out.
    Uprev2 (nullable): U^{n-2}; when given, policy iteration starts from the linear extrapolation
    U^{n-1} + (dt/dt_prev)(U^{n-1} - U^{n-2}) instead of U^{n-1}.  The starting point only changes how many
-   iterations are needed: the result meets the same residual certificate and policy condition. */
+   iterations are needed: the result meets the same residual certificate and policy condition.
+   theta = 0 is the explicit scheme: one search at U^{n-1} (f at t_{n-1}) and U^n = U^{n-1} + dt min_k G_k
+   on interior nodes, queued on the stream without a wait; stats flag bit 0 when dt (M/h + max|c|) > 1
+   (positivity of the untruncated weights may fail). */
 int hjb_step(hjb_handle *hd, const double *Uprev, double *Unext, const double *f0, const double *f1,
              double t_prev, double dt, double theta, double s, int16_t *alpha_io, const double *Uprev2,
              double dt_prev, hjb_step_stats *st);

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libslhjb.so")
 HJB_OK, HJB_EINVAL, HJB_EDEVICE, HJB_ENOMEM = 0, -1, -2, -3
 HJB_ENOCONV_KRYLOV, HJB_ENOCONV_PI, HJB_ENONFINITE, HJB_EUNSUPPORTED = -4, -5, -6, -7
 PREC_FP64, PREC_MIXED = 0, 1
-COEF_CONST, COEF_XSCALED = 0, 1
+COEF_CONST, COEF_XSCALED, COEF_FIELD = 0, 1, 2
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_VCYCLE = 0, 1, 2
 
 EXPORTED = ["hjb_desc_default", "hjb_setup", "hjb_set_stream", "hjb_set_options", "hjb_policy_sweep", "hjb_apply",
@@ -47,7 +47,8 @@ class Desc(ctypes.Structure):
                 ("max_krylov", ctypes.c_int32), ("max_pi", ctypes.c_int32), ("nu1", ctypes.c_int32),
                 ("nu2", ctypes.c_int32), ("coarse_sweeps", ctypes.c_int32), ("min_coarse", ctypes.c_int32),
                 ("omega", ctypes.c_double), ("rtol_inf", ctypes.c_double), ("tau_rel", ctypes.c_double),
-                ("pi_eta", ctypes.c_double), ("use_graphs", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("pi_eta", ctypes.c_double), ("use_graphs", ctypes.c_int32), ("f_per_control", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
 
 
 class StepStats(ctypes.Structure):
@@ -167,12 +168,18 @@ class Solver:
     """
 
     def __init__(self, dim, n, lo, h, sigma, drift=None, c=None, options: Optional[Options] = None,
-                 coef_model: int = COEF_CONST):
+                 coef_model: int = COEF_CONST, K: Optional[int] = None, f_per_control: bool = False):
+        """sigma: (K, P, dim) per control (constant or x-scaled model) or (N, P, dim) per node (field model,
+        K then taken from drift, c or the argument)."""
         self.options = options or Options()
         sigma = np.ascontiguousarray(sigma, dtype=np.float64)
-        K, P, dd = sigma.shape
+        K0, P, dd = sigma.shape
         if dd != dim:
-            raise ValueError("sigma must have shape (K, P, dim)")
+            raise ValueError("sigma must have shape (K or N, P, dim)")
+        if coef_model == COEF_FIELD:
+            K = K if K is not None else (len(drift) if drift is not None else len(c))
+        else:
+            K = K0
         self._sigma = sigma
         self._drift = None if drift is None else np.ascontiguousarray(drift, dtype=np.float64)
         self._c = None if c is None else np.ascontiguousarray(c, dtype=np.float64)
@@ -189,6 +196,7 @@ class Solver:
         desc.h = self.h
         desc.K, desc.P = K, P
         desc.coef_model = int(coef_model)
+        desc.f_per_control = 1 if f_per_control else 0
         desc.sigma = self._sigma.ctypes.data
         desc.drift = None if self._drift is None else self._drift.ctypes.data
         desc.c = None if self._c is None else self._c.ctypes.data
@@ -209,10 +217,13 @@ class Solver:
 
     @classmethod
     def from_instance(cls, inst, options: Optional[Options] = None):
+        fpc = np.ndim(inst.f0) == 2
         if inst.sigma is None:
-            raise ValueError("the HIP path takes per-control sigma tables (constant or x-scaled)")
+            return cls(inst.dim, inst.n, inst.lo, inst.h, inst.sigma_node, inst.drift, inst.c, options,
+                       coef_model=COEF_FIELD, K=inst.K, f_per_control=fpc)
         cm = COEF_XSCALED if getattr(inst, "coef_model", "const") == "xscaled" else COEF_CONST
-        return cls(inst.dim, inst.n, inst.lo, inst.h, inst.sigma, inst.drift, inst.c, options, coef_model=cm)
+        return cls(inst.dim, inst.n, inst.lo, inst.h, inst.sigma, inst.drift, inst.c, options, coef_model=cm,
+                   f_per_control=fpc)
 
     def set_options(self, options: Options):
         self._fill_options(self._desc, options)

@@ -128,8 +128,8 @@ __device__ double dlhat_ds(const LevelDev &g, const StencilDev &st, int k, int i
     Dual acc = dmk(0.0, 0.0);
     for (int p = 0; p < st.P; ++p) {
         double Ya[3], Yb[3];
-        point_Y(st, pt[2 * p], 2 * p, ix, DIM, Ya);
-        point_Y(st, pt[2 * p + 1], 2 * p + 1, ix, DIM, Yb);
+        point_Y(st, pt[2 * p], 2 * p, ix, i, DIM, Ya);
+        point_Y(st, pt[2 * p + 1], 2 * p + 1, ix, i, DIM, Yb);
         double dYa[3] = {Ya[0] * inv_s, Ya[1] * inv_s, Ya[2] * inv_s};
         double dYb[3] = {Yb[0] * inv_s, Yb[1] * inv_s, Yb[2] * inv_s};
         int cp[3], cm[3];
@@ -256,14 +256,14 @@ __global__ __launch_bounds__(kBlock) void k_emit_rows(LevelDev g, StencilDev st,
     double diag = 0.0;
     for (int q = 0; q < st.npt; ++q) {
         double Y[3];
-        point_Y(st, pt[q], q, ix, DIM, Y);
+        point_Y(st, pt[q], q, ix, i, DIM, Y);
         int cell[3];
         double t[3];
         double mu = landing_plain<DIM>(g, ix, Y, cell, t);
         double W;
         if (q < 2 * st.P) {
             double Yo[3];
-            point_Y(st, pt[q ^ 1], q ^ 1, ix, DIM, Yo);
+            point_Y(st, pt[q ^ 1], q ^ 1, ix, i, DIM, Yo);
             int co[3];
             double to[3];
             double muo = landing_plain<DIM>(g, ix, Yo, co, to);

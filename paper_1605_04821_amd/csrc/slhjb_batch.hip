@@ -260,14 +260,14 @@ __global__ __launch_bounds__(kBlock) void k_diag_b(BTiles Tb, const int16_t *__r
     double lii = 0.0;
     for (int q = 0; q < st.npt; ++q) {
         double Y[3];
-        point_Y(st, pt[q], q, ix, DIM, Y);
+        point_Y(st, pt[q], q, ix, i, DIM, Y);
         int cell[3];
         double t[3];
         double mu = landing<DIM>(g, ix, Y, cell, t);
         double W;
         if (q < 2 * st.P) {
             double Yo[3];
-            point_Y(st, pt[q ^ 1], q ^ 1, ix, DIM, Yo);
+            point_Y(st, pt[q ^ 1], q ^ 1, ix, i, DIM, Yo);
             int co[3];
             double to[3];
             double muo = landing<DIM>(g, ix, Yo, co, to);

@@ -181,12 +181,12 @@ __device__ __forceinline__ void lhat_node(const LevelDev &g, const StencilDev &s
     k = ((unsigned)k < (unsigned)st.K) ? k : 0;
     const PointTab *pt = st.tab + k * st.npt;
     TC accV = (TC)0, accW = (TC)0;
-    if (deep && st.xs) {
-        // x-scaled coefficients away from the boundary: no point can leave the box (mu = 1, A = B = C = 1),
+    if (deep && st.pernode) {
+        // per-node displacements away from the boundary: no point can leave the box (mu = 1, A = B = C = 1),
         // so the landing is i + floor(Y) with fraction Y - floor(Y), the general rules' untruncated case
         auto land1 = [&](int q, int cell[3], double t[3]) {
             double Y[3];
-            point_Y(st, pt[q], q, ix, DIM, Y);
+            point_Y(st, pt[q], q, ix, i, DIM, Y);
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 double fl = floor(Y[d]);
@@ -245,8 +245,8 @@ __device__ __forceinline__ void lhat_node(const LevelDev &g, const StencilDev &s
     } else {
         for (int p = 0; p < st.P; ++p) {
             double Ya[3], Yb[3];
-            point_Y(st, pt[2 * p], 2 * p, ix, DIM, Ya);
-            point_Y(st, pt[2 * p + 1], 2 * p + 1, ix, DIM, Yb);
+            point_Y(st, pt[2 * p], 2 * p, ix, i, DIM, Ya);
+            point_Y(st, pt[2 * p + 1], 2 * p + 1, ix, i, DIM, Yb);
             int cp[3], cm[3];
             double tp[3], tm[3];
             double mup = landing<DIM>(g, ix, Ya, cp, tp);
@@ -265,7 +265,7 @@ __device__ __forceinline__ void lhat_node(const LevelDev &g, const StencilDev &s
         }
         if (st.has_drift) {
             double Yc[3];
-            point_Y(st, pt[2 * st.P], 2 * st.P, ix, DIM, Yc);
+            point_Y(st, pt[2 * st.P], 2 * st.P, ix, i, DIM, Yc);
             int cb[3];
             double tb[3];
             double mub = landing<DIM>(g, ix, Yc, cb, tb);

@@ -62,6 +62,7 @@ struct Level {
     void *r = nullptr, *e = nullptr, *t = nullptr, *d = nullptr;  // precision of the V-cycle
     void *r64 = nullptr, *e64 = nullptr, *t64 = nullptr, *d64 = nullptr;  // FP64 copies (plain path)
     void *r32 = nullptr, *e32 = nullptr, *t32 = nullptr, *d32 = nullptr;
+    double *sig_node = nullptr;  // per-node sigma model: [N][P][dim] on this level (injected from level 0)
 };
 
 }  // namespace
@@ -146,6 +147,7 @@ void fill_tables(hjb_handle *hd, double s, std::vector<PointTab> &host, int leve
             if (q < 2 * P) {
                 int pp = q / 2;  // points 2p and 2p+1 are x + y_p and x - y_p
                 for (int a = 0; a < dim; ++a) {
+                    if (d.coef_model == HJB_COEF_FIELD) break;  // per node: see point_Y
                     double Y = xs ? d.sigma[((size_t)k * P + pp) * dim + a] : sr * d.sigma[((size_t)k * P + pp) * dim + a];
                     if (q & 1) Y = -Y;
                     p.Y[a] = xs ? Y : Y * scale;
@@ -190,6 +192,18 @@ int build_tables(hjb_handle *hd, double s) {
                     }
                 E[a] = E[a] * (1.0 + 1e-12) + 1e-12;  // the kernels round sr*(x*S) in another order
             }
+        } else if (hd->desc.coef_model == HJB_COEF_FIELD) {
+            // largest per-node diffusion displacement, and the drift points of the table
+            const double sr = s * (1.0 / sqrt(hd->desc.h)), scale = ldexp(1.0, -(int)l);
+            const int pd = hd->desc.P * hd->dim;
+            for (size_t q = 0; q < hd->sigma.size(); ++q) {
+                const int a = (int)(q % pd) % hd->dim;
+                E[a] = std::max(E[a], sr * fabs(hd->sigma[q]) * scale);
+            }
+            for (int k = 0; k < hd->desc.K; ++k)
+                for (int q = 2 * hd->desc.P; q < hd->npt; ++q)
+                    for (int a = 0; a < hd->dim; ++a) E[a] = std::max(E[a], fabs(host[(size_t)k * hd->npt + q].Y[a]));
+            for (int a = 0; a < hd->dim; ++a) E[a] = E[a] * (1.0 + 1e-12) + 1e-12;
         } else {
             for (const PointTab &p : host)
                 for (int a = 0; a < 3; ++a) E[a] = std::max(E[a], fabs(p.Y[a]));
@@ -243,6 +257,10 @@ StencilDev stencil(const hjb_handle *hd, int level) {
     st.has_drift = hd->has_drift ? 1 : 0;
     st.inv2h = 0.5 / hd->desc.h;
     st.xs = hd->desc.coef_model == HJB_COEF_XSCALED ? 1 : 0;
+    st.field = hd->desc.coef_model == HJB_COEF_FIELD ? 1 : 0;
+    st.pernode = st.xs || st.field;
+    st.sig_node = hd->lev[level].sig_node;
+    st.fk = (level == 0 && hd->desc.f_per_control) ? hd->N : 0;
     st.sr = hd->s_tab * (1.0 / sqrt(hd->desc.h));
     st.scale = ldexp(1.0, -level);
     for (int a = 0; a < 3; ++a) st.lo[a] = hd->desc.lo[a];
@@ -646,7 +664,7 @@ int sweep(hjb_handle *hd, const double *X, const double *U, const double *f0, co
     hipStream_t s = hd->stream;
     const Level &L0 = hd->lev[0];
     double t_mid = t_prev + theta * dt;
-    launch_norms_xuf(hd->dim, L0.g, X, U, f0, f1, t_mid, hd->partial, hd->nb, s);
+    launch_norms_xuf(hd->dim, L0.g, X, U, f0, f1, t_mid, hd->desc.K, stencil(hd, 0).fk, hd->partial, hd->nb, s);
     double inv2h = 0.5 / hd->desc.h;
     double coefA = 2.0 * hd->M * inv2h + hd->cmax;
     hipLaunchKernelGGL(k_tau, dim3(1), dim3(256), 0, s, hd->partial, hd->nb, coefA, hd->desc.tau_rel, hd->dvals + 4);
@@ -710,6 +728,19 @@ int step_impl(hjb_handle *hd, const double *Uprev, double *Unext, const double *
     hipStream_t s = hd->stream;
     const int64_t N = hd->N;
     hjb_step_stats loc{};
+    if (theta == 0.0) {
+        // explicit scheme: U^n = U^{n-1} + dt min_k G_k(U^{n-1}) on interior nodes, one search and no solve
+        // (G_k at theta = 0 equals the theta = 1 quantity evaluated at X = U, with f at t_{n-1})
+        TRY(sweep(hd, Uprev, Uprev, f0, f1, t_prev, 0.0, 1.0, alpha_io, hd->a0, hd->E, nullptr, nullptr, nullptr,
+                  nullptr, 0));
+        launch_explicit_update(hd->dim, hd->lev[0].g, Uprev, hd->E, dt, Unext, s);
+        HIPCHK(hipMemcpyAsync(alpha_io, hd->a0, (size_t)N * sizeof(int16_t), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipGetLastError());
+        // positivity of the explicit scheme (eq. CFL_trunc): (1 - theta) dt (M/h + |c|) <= 1 for interior weights
+        if (dt * (hd->M / hd->desc.h + hd->cmax) > 1.0) loc.flags |= 1;
+        if (st) *st = loc;
+        return HJB_OK;
+    }
     if (Uprev2)
         launch_extrapolate(hd->dim, hd->lev[0].g, Uprev, Uprev2, dt / dt_prev, Unext, s);
     else
@@ -821,11 +852,12 @@ int setup_impl(const hjb_desc *desc, hjb_handle **out, bool tables_only) {
     if (d.K < 1 || d.K > 32767) return fail(HJB_EINVAL, "K must be in 1..32767");
     if (d.P < 1 || d.P > kMaxP) return fail(HJB_EINVAL, "P must be in 1..%d", kMaxP);
     if (d.scheme != 2) return fail(HJB_EUNSUPPORTED, "only Scheme 2 is provided (consistent truncation)");
-    if (d.coef_model != HJB_COEF_CONST && d.coef_model != HJB_COEF_XSCALED)
+    if (d.coef_model != HJB_COEF_CONST && d.coef_model != HJB_COEF_XSCALED && d.coef_model != HJB_COEF_FIELD)
         return fail(HJB_EUNSUPPORTED, "coefficient model %d is not provided", d.coef_model);
     if (!d.sigma) return fail(HJB_EINVAL, "sigma is required");
     TRY(check_options(&d));
-    for (int64_t q = 0; q < (int64_t)d.K * d.P * d.dim; ++q)
+    const int64_t nsig = (d.coef_model == HJB_COEF_FIELD ? N : (int64_t)d.K) * d.P * d.dim;
+    for (int64_t q = 0; q < nsig; ++q)
         if (!isfinite(d.sigma[q])) return fail(HJB_EINVAL, "non-finite sigma");
     if (d.drift)
         for (int64_t q = 0; q < (int64_t)d.K * d.dim; ++q)
@@ -846,7 +878,7 @@ int setup_impl(const hjb_desc *desc, hjb_handle **out, bool tables_only) {
     hd->dim = d.dim;
     hd->N = N;
     hd->stream = (hipStream_t)d.stream;
-    hd->sigma.assign(d.sigma, d.sigma + (size_t)d.K * d.P * d.dim);
+    hd->sigma.assign(d.sigma, d.sigma + (size_t)nsig);
     hd->drift.assign((size_t)d.K * d.dim, 0.0);
     if (d.drift) {
         hd->drift.assign(d.drift, d.drift + (size_t)d.K * d.dim);
@@ -903,6 +935,20 @@ int setup_impl(const hjb_desc *desc, hjb_handle **out, bool tables_only) {
         STRY(dalloc(hd, (void **)&L.tab, (size_t)d.K * hd->npt * sizeof(PointTab)));
         STRY(dalloc(hd, (void **)&L.fastF, (size_t)d.K * hd->npt * sizeof(FastPtF)));
         STRY(dalloc(hd, (void **)&L.fastD, (size_t)d.K * hd->npt * sizeof(FastPtD)));
+        if (d.coef_model == HJB_COEF_FIELD) {
+            // per-node sigma on this level: the finest level's value at the coinciding node
+            const int pd = d.P * d.dim, stp = 1 << l;
+            std::vector<double> sl(n * pd);
+            for (size_t I = 0; I < n; ++I) {
+                const int64_t ix = (int64_t)(I % L.g.n[0]), r = (int64_t)(I / L.g.n[0]);
+                const int64_t iy = r % L.g.n[1], iz = r / L.g.n[1];
+                const int64_t i0 = ix * stp + iy * stp * d.n[0] + (d.dim > 2 ? iz * stp * (int64_t)d.n[0] * d.n[1] : 0);
+                for (int q = 0; q < pd; ++q) sl[I * pd + q] = hd->sigma[(size_t)i0 * pd + q];
+            }
+            STRY(dalloc(hd, (void **)&L.sig_node, n * pd * 8));
+            hipError_t e = hipMemcpy(L.sig_node, sl.data(), n * pd * 8, hipMemcpyHostToDevice);
+            if (e != hipSuccess) return cleanup_fail(fail(HJB_EDEVICE, "%s", hipGetErrorString(e)));
+        }
         if (tables_only) continue;
         if (l > 0) STRY(dalloc(hd, (void **)&L.alpha, n * sizeof(int16_t)));
         STRY(dalloc(hd, &L.r64, n * 8));
@@ -1082,10 +1128,7 @@ int hjb_solve(hjb_handle *hd, const double *g, const double *psi, const double *
     if (!hd) return fail(HJB_EINVAL, "null handle");
     if (!g || !psi || !f0 || !f1 || !dts || !thetas || !U_final) return fail(HJB_EINVAL, "null argument");
     if (n_steps < 0) return fail(HJB_EINVAL, "n_steps must be >= 0");
-    for (int n = 0; n < n_steps; ++n) {
-        TRY(check_time(dts[n], thetas[n]));
-        if (thetas[n] == 0.0) return fail(HJB_EUNSUPPORTED, "explicit steps (theta = 0) are not provided");
-    }
+    for (int n = 0; n < n_steps; ++n) TRY(check_time(dts[n], thetas[n]));
     TRY(build_tables(hd, s));
     const int64_t N = hd->N;
     hipStream_t str = hd->stream;
@@ -1570,6 +1613,7 @@ int hjb_adjoint(hjb_handle *hd, const double *g, const double *psi, const double
         TRY(check_time(dts[n], thetas[n]));
         if (thetas[n] == 0.0) return fail(HJB_EUNSUPPORTED, "explicit steps (theta = 0) are not provided");
     }
+    if (hd->desc.f_per_control) return fail(HJB_EUNSUPPORTED, "the adjoint takes one source for all controls");
     TRY(build_tables(hd, s));
     const int64_t N = hd->N;
     const int dim = hd->dim;
@@ -2257,8 +2301,10 @@ int hjb_setup_batch(const hjb_desc *descs, int32_t count, hjb_batch **out) {
     TRY(check_options(&d0));
     if ((d0.nu1 + d0.nu2) % 2 != 0) return fail(HJB_EUNSUPPORTED, "batched V-cycles take an even nu1 + nu2");
     if (d0.precond == HJB_PRECOND_JACOBI) return fail(HJB_EUNSUPPORTED, "batched solves take the V-cycle or no preconditioner");
-    for (int b = 0; b < count; ++b)
+    for (int b = 0; b < count; ++b) {
         if (descs[b].dim != d0.dim) return fail(HJB_EINVAL, "all instances of a batch have the same dimension");
+        if (descs[b].f_per_control) return fail(HJB_EUNSUPPORTED, "batched instances take one source for all controls");
+    }
     hjb_batch *bh = new hjb_batch();
     auto bail = [&](int rc) {
         hjb_destroy_batch(bh);

@@ -61,16 +61,31 @@ struct StencilDev {
     // x-scaled coefficients (sigma_k(x) = diag(x) S_k, b_k(x) = diag(x) beta_k): the table holds S (signed)
     // and beta; displacements are formed per node, see point_Y
     int32_t xs;
+    int32_t field;        // per-node sigma (all controls): diffusion displacements sr * sig_node[i][p]
+    int32_t pernode;      // xs || field: displacements vary per node (no precomputed untruncated tables)
     double sr;            // s / sqrt(h) of the finest grid
     double scale;         // 2^-level: displacements in this level's cells
     double lo[3], hl;     // node coordinates on this level: x = lo + i * hl
+    const double *sig_node;  // field model: [N_level][P][dim] on this level
+    int64_t fk;           // control stride of f0, f1 (0: one source for all controls; N: [K][N])
 };
 
-// Displacement in cells of stencil point q (table entry p) at node ix.  Constant coefficients: the
-// table's value.  x-scaled: sr * (x * S) for diffusion points and x * beta for the drift point, per
-// axis, then the level scale (exact: a power of two).
-__device__ __forceinline__ void point_Y(const StencilDev &st, const PointTab &p, int q, const int ix[3], int dim,
-                                        double Y[3]) {
+// Displacement in cells of stencil point q (table entry p) at node ix (linear index i on its level).
+// Constant coefficients: the table's value.  x-scaled: sr * (x * S) for diffusion points and x * beta
+// for the drift point, per axis, then the level scale (exact: a power of two).  Per-node sigma: the
+// diffusion points from the node's sigma, the drift point from the table.
+__device__ __forceinline__ void point_Y(const StencilDev &st, const PointTab &p, int q, const int ix[3], int i,
+                                        int dim, double Y[3]) {
+    if (st.field && q < 2 * st.P) {
+        // per-node sigma: Y = sr * sigma_p(x_i), the minus point its negation
+        const double *sg = st.sig_node + ((int64_t)i * st.P + (q >> 1)) * dim;
+        for (int d = 0; d < 3; ++d) {
+            double v = d < dim ? st.sr * sg[d] : 0.0;
+            if (q & 1) v = -v;
+            Y[d] = v * st.scale;
+        }
+        return;
+    }
     if (!st.xs) {
         Y[0] = p.Y[0];
         Y[1] = p.Y[1];
@@ -105,8 +120,10 @@ void launch_sweep(int dim, const LevelDev &g, const StencilDev &st, const double
                   const double *f0, const double *f1, double t_mid, double theta, const double *tau,
                   const int16_t *a_in, const SweepOut &o, double *Q, int qmode, int nblocks, hipStream_t s);
 
-void launch_norms_xuf(int dim, const LevelDev &g, const double *X, const double *U, const double *f0,
-                      const double *f1, double t_mid, double *partial, int nblocks, hipStream_t s);
+void launch_norms_xuf(int dim, const LevelDev &g, const double *X, const double *U, const double *f0, const double *f1,
+                      double t_mid, int K, int64_t fk, double *partial, int nblocks, hipStream_t s);
+void launch_explicit_update(int dim, const LevelDev &g, const double *U, const double *gmin, double dt, double *out,
+                            hipStream_t s);
 
 // y = x - theta dt (L x + c x) on interior nodes, 0 on the boundary (x may be float or double)
 void launch_apply(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const void *x,

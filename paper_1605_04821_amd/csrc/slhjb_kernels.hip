@@ -52,13 +52,15 @@ __global__ __launch_bounds__(kBlock) void k_sweep(LevelDev g, StencilDev st, con
         } else {
             bool deep = deep_node<DIM>(g, ix);
             double Xi = X[i], Ui = U[i];
-            double f = f0[i] + t_mid * f1[i];
+            const double f = f0[i] + t_mid * f1[i];
+            // the source of control k (one source for all controls unless st.fk != 0)
+            auto fk = [&](int k) { return st.fk ? f0[k * st.fk + i] + t_mid * f1[k * st.fk + i] : f; };
             double omt = 1.0 - theta;
             int cur = a_in[i];
             double best = __builtin_inf(), gcur = __builtin_inf();
             int kbest = 0;
             for (int k = 0; k < st.K; ++k) {
-                double G = eval_G<DIM, CN, QM>(g, st, k, i, ix, deep, X, Xi, U, Ui, theta, omt, f, Q);
+                double G = eval_G<DIM, CN, QM>(g, st, k, i, ix, deep, X, Xi, U, Ui, theta, omt, fk(k), Q);
                 if (G < best) {
                     best = G;
                     kbest = k;
@@ -72,7 +74,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(LevelDev g, StencilDev st, con
             } else {
                 pick = kbest;
                 for (int k = 0; k < kbest; ++k) {
-                    double G = eval_G<DIM, CN, QM2>(g, st, k, i, ix, deep, X, Xi, U, Ui, theta, omt, f, Q);
+                    double G = eval_G<DIM, CN, QM2>(g, st, k, i, ix, deep, X, Xi, U, Ui, theta, omt, fk(k), Q);
                     if (G <= thr) {
                         pick = k;
                         break;
@@ -86,7 +88,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(LevelDev g, StencilDev st, con
                 double mg = __builtin_inf();
                 int nt = 0;
                 for (int k = 0; k < st.K; ++k) {
-                    double G = eval_G<DIM, CN, QM2>(g, st, k, i, ix, deep, X, Xi, U, Ui, theta, omt, f, Q);
+                    double G = eval_G<DIM, CN, QM2>(g, st, k, i, ix, deep, X, Xi, U, Ui, theta, omt, fk(k), Q);
                     if (G <= thr)
                         ++nt;
                     else if (G - best < mg)
@@ -134,14 +136,20 @@ void launch_sweep(int dim, const LevelDev &g, const StencilDev &st, const double
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_norms_xuf(LevelDev g, const double *__restrict__ X,
                                                       const double *__restrict__ U, const double *__restrict__ f0,
-                                                      const double *__restrict__ f1, double t_mid, double *partial) {
+                                                      const double *__restrict__ f1, double t_mid, int K, int64_t fk,
+                                                      double *partial) {
     __shared__ double sh[kBlock / 64];
     int ix[3];
     int i = tile_node<DIM>(g, ix);
     double vx = 0.0, vf = 0.0;
     if (i >= 0) {
         vx = fmax(fabs(X[i]), fabs(U[i]));
-        if (interior<DIM>(g, ix)) vf = fabs(f0[i] + t_mid * f1[i]);
+        if (interior<DIM>(g, ix)) {
+            if (fk == 0)
+                vf = fabs(f0[i] + t_mid * f1[i]);
+            else
+                for (int k = 0; k < K; ++k) vf = fmax(vf, fabs(f0[k * fk + i] + t_mid * f1[k * fk + i]));
+        }
     }
     int b = remap_block(blockIdx.x, gridDim.x);
     double a = block_reduce<double>(vx, OpMax(), sh);
@@ -151,11 +159,13 @@ __global__ __launch_bounds__(kBlock) void k_norms_xuf(LevelDev g, const double *
 }
 
 void launch_norms_xuf(int dim, const LevelDev &g, const double *X, const double *U, const double *f0, const double *f1,
-                      double t_mid, double *partial, int nblocks, hipStream_t s) {
+                      double t_mid, int K, int64_t fk, double *partial, int nblocks, hipStream_t s) {
     if (dim == 2)
-        hipLaunchKernelGGL(k_norms_xuf<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, X, U, f0, f1, t_mid, partial);
+        hipLaunchKernelGGL(k_norms_xuf<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, X, U, f0, f1, t_mid, K, fk,
+                           partial);
     else
-        hipLaunchKernelGGL(k_norms_xuf<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, X, U, f0, f1, t_mid, partial);
+        hipLaunchKernelGGL(k_norms_xuf<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, X, U, f0, f1, t_mid, K, fk,
+                           partial);
 }
 
 // ---- FP64 operator kernels ------------------------------------------------------------------------
@@ -209,7 +219,8 @@ __global__ __launch_bounds__(kBlock) void k_explicit(LevelDev g, StencilDev st0,
     if (i < 0) return;
     double e = 0.0;
     if (interior<DIM>(g, ix)) {
-        double f = f0[i] + t_mid * f1[i];
+        const int64_t fo = st.fk ? (int64_t)(((unsigned)alpha[i] < (unsigned)st.K) ? alpha[i] : 0) * st.fk : 0;
+        double f = f0[fo + i] + t_mid * f1[fo + i];
         double Ui = U[i];
         if (omt_dt != 0.0) {
             int k = alpha[i];
@@ -318,14 +329,14 @@ __global__ __launch_bounds__(kBlock) void k_diag(LevelDev g, StencilDev st, cons
     double lii = 0.0;
     for (int q = 0; q < st.npt; ++q) {
         double Y[3];
-        point_Y(st, pt[q], q, ix, DIM, Y);
+        point_Y(st, pt[q], q, ix, i, DIM, Y);
         int cell[3];
         double t[3];
         double mu = landing<DIM>(g, ix, Y, cell, t);
         double W;
         if (q < 2 * st.P) {
             double Yo[3];
-            point_Y(st, pt[q ^ 1], q ^ 1, ix, DIM, Yo);
+            point_Y(st, pt[q ^ 1], q ^ 1, ix, i, DIM, Yo);
             int co[3];
             double to[3];
             double muo = landing<DIM>(g, ix, Yo, co, to);
@@ -808,6 +819,25 @@ void launch_extrapolate(int dim, const LevelDev &g, const double *U1, const doub
         hipLaunchKernelGGL(k_extrapolate<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, U1, U0, ratio, out);
     else
         hipLaunchKernelGGL(k_extrapolate<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, U1, U0, ratio, out);
+}
+
+// explicit step: out = U + dt * g on interior nodes (g: the searched minimum of G_k)
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_explicit_update(LevelDev g, const double *__restrict__ U,
+                                                            const double *__restrict__ gmin, double dt,
+                                                            double *__restrict__ out) {
+    int ix[3];
+    int i = tile_node<DIM>(g, ix);
+    if (i < 0) return;
+    if (interior<DIM>(g, ix)) out[i] = U[i] + dt * gmin[i];
+}
+
+void launch_explicit_update(int dim, const LevelDev &g, const double *U, const double *gmin, double dt, double *out,
+                            hipStream_t s) {
+    if (dim == 2)
+        hipLaunchKernelGGL(k_explicit_update<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, U, gmin, dt, out);
+    else
+        hipLaunchKernelGGL(k_explicit_update<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, U, gmin, dt, out);
 }
 
 // Zero fill by a kernel (stream-ordered, safe inside captured graphs); exact byte count.

@@ -346,9 +346,8 @@ class Batch:
         descs = (Desc * B)()
         self._keep = []
         for b, inst in enumerate(self.instances):
-            if inst.sigma is None:
-                raise ValueError("the HIP path takes per-control sigma tables (constant or x-scaled)")
-            sig = np.ascontiguousarray(inst.sigma, dtype=np.float64)
+            field = inst.sigma is None
+            sig = np.ascontiguousarray(inst.sigma_node if field else inst.sigma, dtype=np.float64)
             dr = None if inst.drift is None else np.ascontiguousarray(inst.drift, dtype=np.float64)
             cc = None if inst.c is None else np.ascontiguousarray(inst.c, dtype=np.float64)
             self._keep += [sig, dr, cc]
@@ -359,8 +358,10 @@ class Batch:
                 d.n[a] = int(inst.n[a]) if a < inst.dim else 1
                 d.lo[a] = float(inst.lo[a]) if a < inst.dim else 0.0
             d.h = float(inst.h)
-            d.K, d.P = sig.shape[0], sig.shape[1]
-            d.coef_model = COEF_XSCALED if getattr(inst, "coef_model", "const") == "xscaled" else COEF_CONST
+            d.K, d.P = int(inst.K), sig.shape[1]
+            d.coef_model = COEF_FIELD if field else (
+                COEF_XSCALED if getattr(inst, "coef_model", "const") == "xscaled" else COEF_CONST)
+            d.f_per_control = 1 if np.ndim(inst.f0) == 2 else 0
             d.sigma = sig.ctypes.data
             d.drift = None if dr is None else dr.ctypes.data
             d.c = None if cc is None else cc.ctypes.data

@@ -51,6 +51,7 @@ CASES = [
     ("ragged_3d", lambda: _toy((11, 9, 13), K=5, P=1, seed=4)),
     ("cn_first_2d", lambda: _toy((23, 19), K=6, P=1, seed=8, c=True, thetas=[0.5, 0.5, 1.0])),
     ("c4_33_xscaled", lambda: workloads.c4_instance(33, 0.15, 0.3, 0.4, 0.03, n_steps=5)),
+    ("problem_a_41_field", lambda: workloads.problem_a(41, dt=0.125, theta=1.0)),
 ]
 
 

@@ -130,3 +130,16 @@ def test_batch_graph_replays_match_eager(slhjb):
     for a, b, pa, pb_ in zip(Ug, Ue, pg, pe):
         np.testing.assert_array_equal(a, b)
         np.testing.assert_array_equal(pa, pb_)
+
+
+def test_batch_mixed_coefficient_models(slhjb):
+    """Per-node sigma (Problem A at two sizes), x-scaled and constant coefficients in one batch."""
+    insts = _schedule([workloads.problem_a(41), workloads.problem_a(81),
+                       workloads.c4_instance(33, 0.15, 0.31, 0.45, 0.04), _toy((37, 29), K=5, P=2, seed=3)],
+                      [0.125, 0.125], [1.0, 1.0])
+    Ub, pb, st = _run_batch(slhjb, insts, slhjb.Options(precision=1))
+    for b, inst in enumerate(insts):
+        ref = oracle.march(inst)
+        rel = np.max(np.abs(Ub[b] - ref["U"])) / np.max(np.abs(ref["U"]))
+        log(f"  {inst.name}: pi={st[b].pi_total} krylov={st[b].krylov_total} rel {rel:.2e}")
+        assert rel <= 1e-10

@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch measurement")
+    ap.add_argument("--no-configs", action="store_true", help="skip the marches of the other configurations")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle Krylov work in the sample")
     ap.add_argument("--pi-eta", type=float, default=None)
     ap.add_argument("--restart", type=int, default=None)
@@ -192,6 +193,28 @@ def batch_cost(slhjb, torch, mode):
             "krylov_total": int(sum(x.krylov_total for x in st)), "max_rel_diff_vs_sequential": worst}
 
 
+def march_rate(slhjb, torch, inst, mode, n_steps=None):
+    """Time steps per second of hjb_solve over the instance's schedule (its first n_steps), after one
+    untimed march; policy iterations and Krylov iterations of the timed march."""
+    import numpy as np
+    prec = slhjb.PREC_MIXED if mode == "mixed" else slhjb.PREC_FP64
+    solver = slhjb.Solver.from_instance(inst, slhjb.Options(precision=prec))
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    g, psi, f0, f1 = dev(inst.g), dev(inst.psi), dev(inst.f0), dev(inst.f1)
+    dts = inst.dts if n_steps is None else inst.dts[:n_steps]
+    ths = inst.thetas if n_steps is None else inst.thetas[:n_steps]
+    U = torch.empty_like(g)
+    for r in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = solver.solve(g, psi, f0, f1, dts, ths, inst.s, U)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+    solver.close()
+    return {"steps_per_s": round(len(dts) / el, 3), "steps": len(dts), "pi_per_step": round(st.pi_total / len(dts), 2),
+            "krylov_per_solve": round(st.krylov_total / max(1, st.pi_total), 2)}
+
+
 def measured_traffic(kernel, pi_per_step):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, scaled by
     the copy-kernel calibration recorded there; None when the kernel source changed since it was taken."""
@@ -339,6 +362,17 @@ def main():
             print(f"[bench]   forward {a['forward_s']:.3f} s, adjoint {a['adjoint_s']:.3f} s "
                   f"({a['adjoint_over_forward']:.2f}x)", file=sys.stderr, flush=True)
             adj.append(a)
+    configs = None
+    if not args.no_configs:
+        configs = {}
+        for name, wl, nst in (("c1 33^2 (10 implicit steps)", workloads.config_c1(33), None),
+                              ("c2 257^2 (Rannacher + 63 Crank-Nicolson steps)", workloads.config_c2(257), None),
+                              ("c3 513^2 (as c2)", workloads.config_c3(513), None),
+                              ("c5 129^3 (64 controls, first 8 of 32 implicit steps)", workloads.config_c5(129), 8)):
+            print(f"[bench] march {name}", file=sys.stderr, flush=True)
+            configs[name] = {m: march_rate(slhjb, torch, wl, m, nst) for m in ("mixed", "fp64")}
+            print(f"[bench]   mixed {configs[name]['mixed']['steps_per_s']:.2f} steps/s, fp64 "
+                  f"{configs[name]['fp64']['steps_per_s']:.2f} steps/s", file=sys.stderr, flush=True)
     batch = None
     if not args.no_batch:
         print("[bench] batch of 64 two-asset instances", file=sys.stderr, flush=True)
@@ -371,6 +405,7 @@ def main():
         "stencil_kernels_hbm": stencil_roof,
         "adjoint": adj,
         "batch": batch,
+        "other_configs": configs,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

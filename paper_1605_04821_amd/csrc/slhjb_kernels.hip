@@ -28,13 +28,22 @@ namespace slhjb {
 int blocks_for(int64_t N) { return (int)((N + kBlock - 1) / kBlock); }
 
 
-template <int DIM, bool CN, bool EXTRA, int QM>
-__global__ __launch_bounds__(kBlock) void k_sweep(LevelDev g, StencilDev st, const double *__restrict__ X,
+// PN: per-node coefficients or per-control sources; otherwise those fields are known to be zero here,
+// so the constant-coefficient search compiles without their code (and keeps its register budget)
+template <int DIM, bool CN, bool EXTRA, int QM, bool PN>
+__global__ __launch_bounds__(kBlock) void k_sweep(LevelDev g, StencilDev st0, const double *__restrict__ X,
                                                   const double *__restrict__ U, const double *__restrict__ f0,
                                                   const double *__restrict__ f1, double t_mid, double theta,
                                                   const double *__restrict__ tau_p, const int16_t *__restrict__ a_in,
                                                   SweepOut o, double *__restrict__ Q) {
     __shared__ int64_t sh[kBlock / 64];
+    StencilDev st = st0;
+    if (!PN) {
+        st.xs = 0;
+        st.field = 0;
+        st.pernode = 0;
+        st.fk = 0;
+    }
     const double tau = tau_p[0];  // written by the tolerance kernel just before
     int ix[3];
     int i = tile_node<DIM>(g, ix);
@@ -109,8 +118,16 @@ void launch_sweep_dim(const LevelDev &g, const StencilDev &st, const double *X, 
                       const SweepOut &o, double *Q, int qmode, int nblocks, hipStream_t s) {
     bool cn = theta != 1.0;
     bool extra = o.margin != nullptr || o.ties != nullptr;
-#define SW(C, E, QQ) hipLaunchKernelGGL((k_sweep<DIM, C, E, QQ>), dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, X, U, f0, \
-                                        f1, t_mid, theta, tau, a_in, o, Q)
+    const bool pn = st.pernode || st.fk;
+#define SW(C, E, QQ)                                                                                                  \
+    do {                                                                                                              \
+        if (pn)                                                                                                       \
+            hipLaunchKernelGGL((k_sweep<DIM, C, E, QQ, true>), dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, X, U,  \
+                               f0, f1, t_mid, theta, tau, a_in, o, Q);                                               \
+        else                                                                                                          \
+            hipLaunchKernelGGL((k_sweep<DIM, C, E, QQ, false>), dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, X, U, \
+                               f0, f1, t_mid, theta, tau, a_in, o, Q);                                               \
+    } while (0)
     if (!cn) {
         if (extra) SW(false, true, 0); else SW(false, false, 0);
     } else if (qmode == 1) {

@@ -90,6 +90,11 @@ typedef struct {
     int32_t use_graphs;     /* 1: replay captured HIP graphs of the V-cycle (identical kernels), 0: launch eagerly */
     int32_t f_per_control;  /* 0: f0, f1 are full-grid arrays shared by all controls; 1: [K][N], the source
                                of each control (the search and the right-hand side take the node's control's) */
+    int32_t certified_skip; /* 1: within a time step, a search keeps the control of every untruncated wavefront
+                               whose recorded gap between its best and second-best G still exceeds twice the
+                               largest change of G allowed by the change of X since (constant coefficients,
+                               P = 1): the same controls as a full search, at a fraction of its cost.  0: every
+                               search evaluates every control */
     void *stream;           /* hipStream_t */
 } hjb_desc;
 
@@ -123,7 +128,7 @@ int hjb_setup(const hjb_desc *desc, hjb_handle **out);
 int hjb_set_stream(hjb_handle *hd, void *stream);
 
 /* Change solver controls after setup (precision, precond, restart, max_krylov, max_pi, nu1, nu2,
-   coarse_sweeps, omega, rtol_inf, tau_rel, pi_eta, use_graphs are taken from *desc; grid and controls
+   coarse_sweeps, omega, rtol_inf, tau_rel, pi_eta, use_graphs, certified_skip are taken from *desc; grid and controls
    are those of the setup).  restart may not exceed its value at setup. */
 int hjb_set_options(hjb_handle *hd, const hjb_desc *desc);
 

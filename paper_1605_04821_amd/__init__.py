@@ -48,7 +48,7 @@ class Desc(ctypes.Structure):
                 ("nu2", ctypes.c_int32), ("coarse_sweeps", ctypes.c_int32), ("min_coarse", ctypes.c_int32),
                 ("omega", ctypes.c_double), ("rtol_inf", ctypes.c_double), ("tau_rel", ctypes.c_double),
                 ("pi_eta", ctypes.c_double), ("use_graphs", ctypes.c_int32), ("f_per_control", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("certified_skip", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class StepStats(ctypes.Structure):
@@ -159,6 +159,7 @@ class Options:
     tau_rel: float = 1e-13
     pi_eta: float = 0.2
     use_graphs: int = 1
+    certified_skip: int = 1
 
 
 class Solver:
@@ -214,6 +215,7 @@ class Solver:
         desc.coarse_sweeps, desc.min_coarse, desc.omega = o.coarse_sweeps, o.min_coarse, o.omega
         desc.rtol_inf, desc.tau_rel, desc.pi_eta = o.rtol_inf, o.tau_rel, o.pi_eta
         desc.use_graphs = o.use_graphs
+        desc.certified_skip = o.certified_skip
 
     @classmethod
     def from_instance(cls, inst, options: Optional[Options] = None):

@@ -13,18 +13,6 @@
 
 namespace slhjb {
 
-template <int DIM>
-__device__ __forceinline__ int tile_node_at(const LevelDev &g, int t, int ix[3]) {
-    int bx = t % g.ntx, r = t / g.ntx;
-    int by = DIM == 3 ? r % g.nty : r;
-    int bz = DIM == 3 ? r / g.nty : 0;
-    ix[0] = (bx << g.tlog) + (int)(threadIdx.x & ((1u << g.tlog) - 1));
-    ix[1] = by * (kBlock >> g.tlog) + (int)(threadIdx.x >> g.tlog);
-    ix[2] = bz;
-    if (ix[0] >= g.n[0] || ix[1] >= g.n[1]) return -1;
-    return ix[0] + ix[1] * (int)g.s1 + (DIM == 3 ? ix[2] * (int)g.s2 : 0);
-}
-
 // table position of this block, its instance and whether the instance takes part
 struct BCtx {
     int pos, inst;

@@ -18,8 +18,7 @@ __device__ __forceinline__ int node_id() { return remap_block(blockIdx.x, gridDi
 // Node of this thread: blocks cover 2^tlog x (256 / 2^tlog) tiles (x fastest, then y, then z), so that the stencil
 // rows gathered by vertically adjacent nodes are shared in cache.  Returns -1 outside the grid.
 template <int DIM>
-__device__ __forceinline__ int tile_node(const LevelDev &g, int ix[3]) {
-    int b = remap_block(blockIdx.x, gridDim.x);
+__device__ __forceinline__ int tile_node_at(const LevelDev &g, int b, int ix[3]) {
     int bx = b % g.ntx, r = b / g.ntx;
     int by = DIM == 3 ? r % g.nty : r;
     int bz = DIM == 3 ? r / g.nty : 0;
@@ -28,6 +27,11 @@ __device__ __forceinline__ int tile_node(const LevelDev &g, int ix[3]) {
     ix[2] = bz;
     if (ix[0] >= g.n[0] || ix[1] >= g.n[1]) return -1;
     return ix[0] + ix[1] * (int)g.s1 + (DIM == 3 ? ix[2] * (int)g.s2 : 0);
+}
+
+template <int DIM>
+__device__ __forceinline__ int tile_node(const LevelDev &g, int ix[3]) {
+    return tile_node_at<DIM>(g, remap_block(blockIdx.x, gridDim.x), ix);
 }
 
 template <int DIM>
@@ -150,6 +154,39 @@ __device__ __forceinline__ TC interp_fast(const TS *__restrict__ V, int i, const
     return interp_w<DIM, TS, TC>(V, i + p.off, g, w);
 }
 
+// the 2^DIM corner values of the cell at `base`, and their weighted sum in interp_w's order with the
+// precomputed weights of a table point
+template <int DIM, typename TS>
+__device__ __forceinline__ void corner_vals(const TS *__restrict__ V, int base, const LevelDev &g, TS c[8]) {
+    const int s1 = (int)g.s1;
+    c[0] = V[base];
+    c[1] = V[base + 1];
+    c[2] = V[base + s1];
+    c[3] = V[base + s1 + 1];
+    if (DIM == 3) {
+        const int s2 = (int)g.s2;
+        c[4] = V[base + s2];
+        c[5] = V[base + s2 + 1];
+        c[6] = V[base + s2 + s1];
+        c[7] = V[base + s2 + s1 + 1];
+    }
+}
+
+template <int DIM, typename TS, typename TC>
+__device__ __forceinline__ TC corner_wsum(const typename FastOf<TC>::T &p, const TS c[8]) {
+    TC v = (TC)p.w[0] * (TC)c[0];
+    v = fmat((TC)p.w[1], (TC)c[1], v);
+    v = fmat((TC)p.w[2], (TC)c[2], v);
+    v = fmat((TC)p.w[3], (TC)c[3], v);
+    if (DIM == 3) {
+        v = fmat((TC)p.w[4], (TC)c[4], v);
+        v = fmat((TC)p.w[5], (TC)c[5], v);
+        v = fmat((TC)p.w[6], (TC)c[6], v);
+        v = fmat((TC)p.w[7], (TC)c[7], v);
+    }
+    return v;
+}
+
 // general landing: corner weights from the fractions, product over axes in axis order
 template <int DIM, typename TS, typename TC>
 __device__ __forceinline__ TC interp_land(const TS *__restrict__ V, const LevelDev &g, const int cell[3],
@@ -217,6 +254,39 @@ __device__ __forceinline__ void lhat_node(const LevelDev &g, const StencilDev &s
             if (TWO) {
                 TC wb = interp_land<DIM, TS, TC>(W, g, cb, tb);
                 accW = accW + (TC)2 * (wb - Wi);
+            }
+        }
+    } else if (deep && st.P == 1) {
+        // one diffusion pair: all corner loads are issued before any is used (the drift point's loads
+        // read the node itself when there is no drift, so they need no branch)
+        const typename FastOf<TC>::T *fp = FastOf<TC>::get(st) + k * st.npt;
+        const auto &a = fp[0];
+        const auto &b = fp[1];
+        const auto &c = fp[st.has_drift ? 2 : 0];
+        const int ba = i + a.off, bb = i + b.off, bc = st.has_drift ? i + c.off : i;
+        TS va[8], vb[8], vc[8], wa[TWO ? 8 : 1], wb[TWO ? 8 : 1], wc[TWO ? 8 : 1];
+        corner_vals<DIM, TS>(V, ba, g, va);
+        corner_vals<DIM, TS>(V, bb, g, vb);
+        corner_vals<DIM, TS>(V, bc, g, vc);
+        if (TWO) {
+            corner_vals<DIM, TS>(W, ba, g, wa);
+            corner_vals<DIM, TS>(W, bb, g, wb);
+            corner_vals<DIM, TS>(W, bc, g, wc);
+        }
+        TC vp = corner_wsum<DIM, TS, TC>(a, va);
+        TC vm = corner_wsum<DIM, TS, TC>(b, vb);
+        accV = accV + ((vp + vm) - (TC)2 * Vi);
+        if (TWO) {
+            TC wp = corner_wsum<DIM, TS, TC>(a, wa);
+            TC wm = corner_wsum<DIM, TS, TC>(b, wb);
+            accW = accW + ((wp + wm) - (TC)2 * Wi);
+        }
+        if (st.has_drift) {
+            TC vd = corner_wsum<DIM, TS, TC>(c, vc);
+            accV = accV + (TC)2 * (vd - Vi);
+            if (TWO) {
+                TC wd = corner_wsum<DIM, TS, TC>(c, wc);
+                accW = accW + (TC)2 * (wd - Wi);
             }
         }
     } else if (deep) {
@@ -325,26 +395,27 @@ struct OpMax {
 // ---- policy search (Howard's algorithm, eq. nonlinear_sys) ----------------------------------------
 
 // G_k at node i.  QM 0: explicit part evaluated (theta < 1) or absent (theta = 1); QM 1: evaluated and
-// stored in Q; QM 2: read from Q.  All three round identically.  Q is tile-major: entry (k, block, lane)
-// at (k * blocks + block) * kBlock + lane, so each wavefront moves whole aligned cache lines.
+// stored in Q; QM 2: read from Q.  All three round identically.  Q is tile-major: entry (k, tile, lane)
+// at k * qstride + qslot, qslot = tile * kBlock + lane, qstride = tiles * kBlock, so each wavefront
+// moves whole aligned cache lines.
 template <int DIM, bool CN, int QM>
 __device__ __forceinline__ double eval_G(const LevelDev &g, const StencilDev &st, int k, int i, const int ix[3],
                                          bool deep, const double *__restrict__ X, double Xi,
                                          const double *__restrict__ U, double Ui, double theta, double omt, double f,
-                                         double *__restrict__ Q) {
+                                         double *__restrict__ Q, int64_t qslot = 0, int64_t qstride = 0) {
     double ck = st.c ? st.c[k] : 0.0;
     double lx, lu = 0.0;
     double q;
     if (CN && QM == 2) {
         lx = lhat1<DIM, double, double>(g, st, k, i, ix, deep, X, Xi);
-        q = Q[((int64_t)k * gridDim.x + remap_block(blockIdx.x, gridDim.x)) * kBlock + threadIdx.x];
+        q = Q[(int64_t)k * qstride + qslot];
     } else {
         if (CN)
             lhat_node<DIM, double, double, true>(g, st, k, i, ix, deep, X, Xi, U, Ui, lx, lu);
         else
             lx = lhat1<DIM, double, double>(g, st, k, i, ix, deep, X, Xi);
         q = omt * (lu + ck * Ui);
-        if (CN && QM == 1) Q[((int64_t)k * gridDim.x + remap_block(blockIdx.x, gridDim.x)) * kBlock + threadIdx.x] = q;
+        if (CN && QM == 1) Q[(int64_t)k * qstride + qslot] = q;
     }
     return theta * (lx + ck * Xi) + q + f;
 }

@@ -78,6 +78,15 @@ struct hjb_handle {
     int64_t N = 0;
     int nb = 0, nbd = 0;
     int nb_cap = 0;      // largest level-0 tile count over the tile shapes the handle may take
+    // certified reuse of search decisions within a step: gap bounds [N], X at the previous search [N],
+    // per-tile largest change of X and its stencil-window maximum [nb_cap], window radius in nodes per axis
+    double *marg = nullptr, *Xs = nullptr, *dtile = nullptr, *dwin = nullptr;
+    uint8_t *keep = nullptr;  // [nb_cap * kBlock / 64] wavefronts whose decisions the next search keeps
+    int64_t *kpartial = nullptr;  // [nb_cap] kept interior nodes per tile
+    uint8_t *need = nullptr;      // [nb_cap] tiles the next search visits
+    int32_t *tlist = nullptr;     // [nb_cap + 1] their list and (last entry) its length
+    int64_t kept_last = 0;        // interior nodes whose decisions the last search kept
+    int reach[3] = {0, 0, 0};
     int tlog = kTileLog2;
     std::vector<Level> lev;
     double s_tab = -1.0;
@@ -208,6 +217,8 @@ int build_tables(hjb_handle *hd, double s) {
             for (const PointTab &p : host)
                 for (int a = 0; a < 3; ++a) E[a] = std::max(E[a], fabs(p.Y[a]));
         }
+        if (l == 0)
+            for (int a = 0; a < 3; ++a) hd->reach[a] = a < hd->dim ? (int)ceil(E[a]) + 1 : 0;
         for (int a = 0; a < 3; ++a) {
             if (a < hd->dim) {
                 int lo = (int)ceil(E[a]);
@@ -651,6 +662,7 @@ __global__ void k_tau(const double *partial, int nb, double coefA, double tau_re
     if (threadIdx.x == 0) {
         double S = coefA * sx[0] + sf[0];
         out[0] = tau_rel * S;
+        out[1] = S;
     }
 }
 
@@ -660,15 +672,34 @@ __global__ void k_sweep_tau_arg(const double *tau_dev, double *tau_copy) {
 
 int sweep(hjb_handle *hd, const double *X, const double *U, const double *f0, const double *f1, double t_prev,
           double dt, double theta, const int16_t *a_in, int16_t *a_out, double *gmin, double *margin, int32_t *ties,
-          int64_t *n_changed, double *tau_used, int qmode = 0) {
+          int64_t *n_changed, double *tau_used, int qmode = 0, int skip = 0) {
     hipStream_t s = hd->stream;
     const Level &L0 = hd->lev[0];
     double t_mid = t_prev + theta * dt;
+    // decisions are reused only where the search keeps no per-node extras and the tables are fixed; the
+    // reusing search runs in place
+    if (!hd->marg || !hd->desc.certified_skip || gmin || margin || ties || hd->desc.coef_model != HJB_COEF_CONST ||
+        hd->desc.f_per_control || hd->desc.P != 1)
+        skip = 0;
+    if (skip == 2 && a_in != a_out) skip = 1;
     launch_norms_xuf(hd->dim, L0.g, X, U, f0, f1, t_mid, hd->desc.K, stencil(hd, 0).fk, hd->partial, hd->nb, s);
     double inv2h = 0.5 / hd->desc.h;
     double coefA = 2.0 * hd->M * inv2h + hd->cmax;
     hipLaunchKernelGGL(k_tau, dim3(1), dim3(256), 0, s, hd->partial, hd->nb, coefA, hd->desc.tau_rel, hd->dvals + 4);
-    SweepOut o{a_out, gmin, margin, ties, hd->ipartial};
+    if (skip == 1) {
+        launch_delta_tiles(hd->dim, L0.g, X, hd->Xs, hd->dtile, true, s);
+    } else if (skip == 2) {
+        // |change of G_k| <= theta (4 M / (2h) + max|c|) max|change of X| over the node's stencil (untruncated
+        // nodes: unit interpolation weights); the gap shrinks by at most twice that
+        const double lip2 = 2.0 * theta * (4.0 * hd->M * inv2h + hd->cmax);
+        launch_delta_tiles(hd->dim, L0.g, X, hd->Xs, hd->dtile, false, s);
+        launch_window_max(hd->dim, L0.g, hd->dtile, hd->dwin, hd->reach, s);
+        launch_keep_pass(hd->dim, L0.g, hd->marg, hd->dwin, lip2, hd->dvals + 5, hd->keep, hd->kpartial, hd->need,
+                         hd->ipartial, s);
+        launch_tile_list(hd->need, hd->nb, hd->tlist, hd->tlist + hd->nb_cap, s);
+    }
+    SweepOut o{a_out, gmin, margin, ties, hd->ipartial, skip, hd->marg, hd->keep,
+               skip == 2 ? hd->tlist : nullptr, skip == 2 ? hd->tlist + hd->nb_cap : nullptr};
     if (!hd->Q) qmode = 0;
     // algorithmic FP64 work of the untruncated stencil per control and field: each point is a 2^d-corner
     // weighted sum (2^(d+1) - 1 flops), each diffusion pair adds 4, the drift 3, the 1/(2h) scaling 1
@@ -678,18 +709,34 @@ int sweep(hjb_handle *hd, const double *X, const double *U, const double *f0, co
     const double per_ctl = per_field + 5.0 + ((cn && qmode != 2) ? per_field + 3.0 : 0.0);
     double n_int = 1.0;
     for (int a = 0; a < hd->dim; ++a) n_int *= (double)(hd->desc.n[a] - 2);
-    TimedLaunch tl(hd, HJB_KERNEL_SWEEP, (double)hd->N * (4 * 8.0 + 2.0 + 2.0) + (qmode == 2 ? n_int * 8.0 * hd->desc.K : 0.0),
-                   n_int * (hd->desc.K * per_ctl + 2.0));
-    launch_sweep(hd->dim, L0.g, stencil(hd, 0), X, U, f0, f1, t_mid, theta, hd->dvals + 4, a_in, o, hd->Q, qmode,
-                 hd->nb, s);
+    const double bytes_all = (double)hd->N * (4 * 8.0 + 2.0 + 2.0) + (qmode == 2 ? n_int * 8.0 * hd->desc.K : 0.0);
+    const double flops_all = n_int * (hd->desc.K * per_ctl + 2.0);
+    int slot = -1;
+    {
+        TimedLaunch tl(hd, HJB_KERNEL_SWEEP, bytes_all, flops_all);
+        slot = tl.slot;
+        launch_sweep(hd->dim, L0.g, stencil(hd, 0), X, U, f0, f1, t_mid, theta, hd->dvals + 4, a_in, o, hd->Q, qmode,
+                     hd->nb, s);
+    }
     HIPCHK(hipGetLastError());
-    if (n_changed || tau_used) {
+    hd->kept_last = 0;
+    if (n_changed || tau_used || skip == 2) {
         launch_reduce_sum_i64(hd->ipartial, hd->nb, hd->ival, s);
-        HIPCHK(hipMemcpyAsync(hd->hpin_i, hd->ival, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        if (skip == 2) launch_reduce_sum_i64(hd->kpartial, hd->nb, hd->ival + 1, s);
+        HIPCHK(hipMemcpyAsync(hd->hpin_i, hd->ival, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(hd->hpin + 4, hd->dvals + 4, sizeof(double), hipMemcpyDeviceToHost, s));
         TRY(wait_stream(hd));
         if (n_changed) *n_changed = hd->hpin_i[0];
         if (tau_used) *tau_used = hd->hpin[4];
+        if (skip == 2) {
+            hd->kept_last = hd->hpin_i[1];
+            // the timed launch did the work of the evaluated nodes only (kept ones read their control)
+            if (slot >= 0) {
+                const double ev = std::max(0.0, n_int - (double)hd->kept_last) / n_int;
+                hd->timers[HJB_KERNEL_SWEEP].flops[slot] = flops_all * ev;
+                hd->timers[HJB_KERNEL_SWEEP].bytes[slot] = bytes_all * ev + 2.0 * (double)hd->kept_last;
+            }
+        }
     }
     return HJB_OK;
 }
@@ -745,12 +792,12 @@ int step_impl(hjb_handle *hd, const double *Uprev, double *Unext, const double *
         launch_extrapolate(hd->dim, hd->lev[0].g, Uprev, Uprev2, dt / dt_prev, Unext, s);
     else
         launch_copy_interior(hd->dim, hd->lev[0].g, Uprev, Unext, s);
-    int16_t *acur = hd->a0, *anew = hd->a1;
+    int16_t *acur = hd->a0;
     int64_t changed = 0;
     // the explicit part of every G_k is fixed within the step: the first search stores it (when the
     // handle could afford the K*N cache) and the later searches read it
     TRY(sweep(hd, Unext, Uprev, f0, f1, t_prev, dt, theta, alpha_io, acur, nullptr, nullptr, nullptr, &changed,
-              nullptr, 1));
+              nullptr, 1, 1));
     loc.n_changed_first = changed;
     double cert_den = 1.0 - theta * dt * hd->cplus;
     if (theta < 1.0) {
@@ -774,16 +821,16 @@ int step_impl(hjb_handle *hd, const double *Uprev, double *Unext, const double *
         loc.res_inf = res;
         loc.cert_bound = cert_den > 0 ? res / cert_den : INFINITY;
         if (rc != HJB_OK) break;
-        TRY(sweep(hd, Unext, Uprev, f0, f1, t_prev, dt, theta, acur, anew, nullptr, nullptr, nullptr, &changed,
-                  nullptr, 2));
+        // the search updates the policy in place (it reads only each node's own control)
+        TRY(sweep(hd, Unext, Uprev, f0, f1, t_prev, dt, theta, acur, acur, nullptr, nullptr, nullptr, &changed,
+                  nullptr, 2, 2));
         if (hd->trace)
-            fprintf(stderr, "[slhjb] pi %d: krylov %d res %.3e tight %d changed %lld\n", it, its, res, (int)tight,
-                    (long long)changed);
+            fprintf(stderr, "[slhjb] pi %d: krylov %d res %.3e tight %d changed %lld kept %lld\n", it, its, res,
+                    (int)tight, (long long)changed, (long long)hd->kept_last);
         if (changed == 0) {
             if (tight) break;
             want_tight = true;  // same policy, finish the solve
         } else {
-            std::swap(acur, anew);
             want_tight = hd->desc.pi_eta <= 0.0;
         }
         if (it + 1 == hd->desc.max_pi) rc = fail(HJB_ENOCONV_PI, "policy iteration not converged after %d", it + 1);
@@ -826,6 +873,7 @@ void hjb_desc_default(hjb_desc *d) {
     d->tau_rel = 1e-13;
     d->pi_eta = 0.2;
     d->use_graphs = 1;
+    d->certified_skip = 1;
     d->stream = nullptr;
 }
 
@@ -976,6 +1024,14 @@ int setup_impl(const hjb_desc *desc, hjb_handle **out, bool tables_only) {
     STRY(dalloc(hd, (void **)&hd->Ua, N * 8));
     STRY(dalloc(hd, (void **)&hd->Ub, N * 8));
     STRY(dalloc(hd, (void **)&hd->Uc, N * 8));
+    STRY(dalloc(hd, (void **)&hd->marg, N * 8));
+    STRY(dalloc(hd, (void **)&hd->Xs, N * 8));
+    STRY(dalloc(hd, (void **)&hd->dtile, (size_t)hd->nb_cap * 8));
+    STRY(dalloc(hd, (void **)&hd->dwin, (size_t)hd->nb_cap * 8));
+    STRY(dalloc(hd, (void **)&hd->keep, (size_t)hd->nb_cap * (kBlock / 64)));
+    STRY(dalloc(hd, (void **)&hd->kpartial, (size_t)hd->nb_cap * 8));
+    STRY(dalloc(hd, (void **)&hd->need, (size_t)hd->nb_cap));
+    STRY(dalloc(hd, (void **)&hd->tlist, ((size_t)hd->nb_cap + 1) * 4));
     STRY(dalloc(hd, (void **)&hd->a0, N * 2));
     STRY(dalloc(hd, (void **)&hd->a1, N * 2));
     STRY(dalloc(hd, (void **)&hd->acarry, N * 2));
@@ -1051,6 +1107,7 @@ int hjb_set_options(hjb_handle *hd, const hjb_desc *desc) {
     d.tau_rel = desc->tau_rel;
     d.pi_eta = desc->pi_eta;
     d.use_graphs = desc->use_graphs;
+    d.certified_skip = desc->certified_skip;
     select_precision(hd);
     drop_graphs(hd);
     return HJB_OK;

@@ -107,12 +107,42 @@ __device__ __forceinline__ void point_Y(const StencilDev &st, const PointTab &p,
 
 // ---- kernel launchers (slhjb_kernels.hip) ----------------------------------------------------
 
+// a kept decision needs its gap bound above this multiple of the search scale S (rounding of G is far below)
+constexpr double kSkipSlack = 1e-10;
+
 struct SweepOut {
     int16_t *alpha_out;
     double *gmin, *margin;
     int32_t *ties;
     int64_t *changed_partial;  // [nblocks]
+    // Certified reuse of decisions on untruncated wavefronts (constant coefficients, one diffusion pair).
+    // skip 0: off; 1: record, per node, the gap between the second-best and the best G when the node's
+    // control is the strict minimiser (-1 otherwise); 2: also keep the control of every wavefront whose
+    // recorded gaps, less twice the largest change of any G_k since they were recorded, exceed the
+    // rounding slack (such a control is still the strict minimiser, so the search would keep it).
+    // Mode 2 runs in place (alpha_out == a_in): kept wavefronts leave their controls as they are.
+    int32_t skip;
+    double *marg;          // [N] lower bounds of the gaps (modes 1 and 2)
+    const uint8_t *keep;   // [tiles * kBlock / 64] wavefronts certified by the keep pass (mode 2)
+    // optional work list (mode 2): the search visits only list[0 .. list_count[0]) and leaves the
+    // changed counts of the other tiles to the keep pass
+    const int32_t *list;
+    const int32_t *list_count;
 };
+
+// largest |X - Xs| over each tile (dtile[tile], record == 0), then Xs = X on the tile
+void launch_delta_tiles(int dim, const LevelDev &g, const double *X, double *Xs, double *dtile, bool record,
+                        hipStream_t s);
+// dwin[T] = max of dtile over the tiles within R[a] nodes of tile T along each axis
+void launch_window_max(int dim, const LevelDev &g, const double *dtile, double *dwin, const int R[3], hipStream_t s);
+// keep[wave] = 1 where every interior node of the wavefront is untruncated and marg - lip2 * dwin stays
+// above the rounding slack (scale[0] = S of the search); marg is then reduced by lip2 * dwin there.
+// kept_partial[tile]: interior nodes kept in the tile.
+// need[tile] = 1 where some wavefront with interior nodes is not kept; changed_partial[tile] = 0.
+void launch_keep_pass(int dim, const LevelDev &g, double *marg, const double *dwin, double lip2, const double *scale,
+                      uint8_t *keep, int64_t *kept_partial, uint8_t *need, int64_t *changed_partial, hipStream_t s);
+// list[0 .. *count) = tiles t < nt with need[t] != 0, increasing
+void launch_tile_list(const uint8_t *need, int nt, int32_t *list, int32_t *count, hipStream_t s);
 
 // qmode: 0 evaluate the explicit part (theta < 1) or skip it (theta = 1); 1 evaluate it and store
 // (1-theta)((L^k U)_i + c_k U_i) in Q (K * blocks * kBlock doubles, tile-major); 2 read it from Q.

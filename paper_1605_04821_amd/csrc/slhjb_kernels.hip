@@ -28,13 +28,146 @@ namespace slhjb {
 int blocks_for(int64_t N) { return (int)((N + kBlock - 1) / kBlock); }
 
 
+// ---- policy search over untruncated wavefronts ---------------------------------------------------
+// When no lane of a wavefront is near the boundary, every stencil point of control k lands at the fixed
+// offset of the precomputed table (constant coefficients), so the corner loads of B controls can all be
+// issued before any of them is used: one memory round trip per B controls instead of one per point
+// group.  The arithmetic is that of eval_G on the deep branch of lhat_node, operation for operation.
+
+template <int DIM>
+__device__ __forceinline__ void corner_loads(const double *__restrict__ V, int base, int s1, int s2, double c[8]) {
+    c[0] = V[base];
+    c[1] = V[base + 1];
+    c[2] = V[base + s1];
+    c[3] = V[base + s1 + 1];
+    if (DIM == 3) {
+        c[4] = V[base + s2];
+        c[5] = V[base + s2 + 1];
+        c[6] = V[base + s2 + s1];
+        c[7] = V[base + s2 + s1 + 1];
+    }
+}
+
+// the weighted corner sum of interp_w, same order
+template <int DIM>
+__device__ __forceinline__ double corner_sum(const double *w, const double c[8]) {
+    double v = w[0] * c[0];
+    v = fma(w[1], c[1], v);
+    v = fma(w[2], c[2], v);
+    v = fma(w[3], c[3], v);
+    if (DIM == 3) {
+        v = fma(w[4], c[4], v);
+        v = fma(w[5], c[5], v);
+        v = fma(w[6], c[6], v);
+        v = fma(w[7], c[7], v);
+    }
+    return v;
+}
+
+// G_k for k = k0 .. k0+B-1 at a node of an untruncated wavefront (k0 wave-uniform, k0 + B <= K).
+// P diffusion pairs and DRIFT are the table layout (npt = 2P + DRIFT).
+template <int DIM, bool CN, int QM, int P, bool DRIFT, int B>
+__device__ __forceinline__ void eval_G_deep(const LevelDev &g, const StencilDev &st, int k0, int i,
+                                            const double *__restrict__ X, double Xi, const double *__restrict__ U,
+                                            double Ui, double theta, double omt, double f, double *__restrict__ Q,
+                                            int64_t qrow, int64_t qstride, double G[B]) {
+    constexpr int NP = 2 * P + (DRIFT ? 1 : 0);
+    constexpr int NC = 1 << DIM;
+    constexpr bool TWO = CN && QM != 2;
+    const int s1 = (int)g.s1, s2 = (int)g.s2;
+    const FastPtD *fp = st.fastD + k0 * NP;
+    double cx[B][NP][NC];
+    double cu[TWO ? B : 1][TWO ? NP : 1][NC];
+    double qv[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            const int base = i + fp[b * NP + q].off;
+            corner_loads<DIM>(X, base, s1, s2, cx[b][q]);
+            if (TWO) corner_loads<DIM>(U, base, s1, s2, cu[TWO ? b : 0][TWO ? q : 0]);
+        }
+        if (CN && QM == 2) qv[b] = Q[(int64_t)(k0 + b) * qstride + qrow];
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int k = k0 + b;
+        double accV = 0.0, accW = 0.0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            double vp = corner_sum<DIM>(fp[b * NP + 2 * p].w, cx[b][2 * p]);
+            double vm = corner_sum<DIM>(fp[b * NP + 2 * p + 1].w, cx[b][2 * p + 1]);
+            accV = accV + ((vp + vm) - 2.0 * Xi);
+            if (TWO) {
+                double wp = corner_sum<DIM>(fp[b * NP + 2 * p].w, cu[TWO ? b : 0][TWO ? 2 * p : 0]);
+                double wm = corner_sum<DIM>(fp[b * NP + 2 * p + 1].w, cu[TWO ? b : 0][TWO ? 2 * p + 1 : 0]);
+                accW = accW + ((wp + wm) - 2.0 * Ui);
+            }
+        }
+        if (DRIFT) {
+            constexpr int QD = DRIFT ? 2 * P : 0;  // the drift point (the guard keeps the index in range)
+            double vb = corner_sum<DIM>(fp[b * NP + QD].w, cx[b][QD]);
+            accV = accV + 2.0 * (vb - Xi);
+            if (TWO) {
+                double wb = corner_sum<DIM>(fp[b * NP + QD].w, cu[TWO ? b : 0][TWO ? QD : 0]);
+                accW = accW + 2.0 * (wb - Ui);
+            }
+        }
+        const double lx = st.inv2h * accV;
+        const double ck = st.c ? st.c[k] : 0.0;
+        double q;
+        if (CN && QM == 2) {
+            q = qv[b];
+        } else {
+            const double lu = TWO ? st.inv2h * accW : 0.0;
+            q = omt * (lu + ck * Ui);
+            if (CN && QM == 1) Q[(int64_t)k * qstride + qrow] = q;
+        }
+        G[b] = theta * (lx + ck * Xi) + q + f;
+    }
+}
+
+// the whole control loop of the search on an untruncated wavefront: best value, its control and the
+// value of the node's current control, as the generic loop finds them
+template <int DIM, bool CN, int QM, int P, bool DRIFT>
+__device__ __forceinline__ void search_deep(const LevelDev &g, const StencilDev &st, int i, const double *__restrict__ X,
+                                            double Xi, const double *__restrict__ U, double Ui, double theta,
+                                            double omt, double f, double *__restrict__ Q, int64_t qrow,
+                                            int64_t qstride, int cur, double &best, int &kbest, double &gcur,
+                                            double &second) {
+    constexpr bool TWO = CN && QM != 2;
+    constexpr int B = (DIM == 2 && !TWO) ? 2 : 1;
+    // second: the least G over the controls other than kbest
+    auto take = [&](double G, int k) {
+        const double hi = G < best ? best : G;  // the larger of the two competes for second place
+        second = hi < second ? hi : second;
+        if (G < best) {
+            best = G;
+            kbest = k;
+        }
+        if (k == cur) gcur = G;
+    };
+    int k = 0;
+    for (; k + B <= st.K; k += B) {
+        double G[B];
+        eval_G_deep<DIM, CN, QM, P, DRIFT, B>(g, st, k, i, X, Xi, U, Ui, theta, omt, f, Q, qrow, qstride, G);
+#pragma unroll
+        for (int b = 0; b < B; ++b) take(G[b], k + b);
+    }
+    for (; k < st.K; ++k) {
+        double G[1];
+        eval_G_deep<DIM, CN, QM, P, DRIFT, 1>(g, st, k, i, X, Xi, U, Ui, theta, omt, f, Q, qrow, qstride, G);
+        take(G[0], k);
+    }
+}
+
 // PN: per-node coefficients or per-control sources; otherwise those fields are known to be zero here,
 // so the constant-coefficient search compiles without their code (and keeps its register budget)
 template <int DIM, bool CN, bool EXTRA, int QM, bool PN>
 __global__ __launch_bounds__(kBlock) void k_sweep(LevelDev g, StencilDev st0, const double *__restrict__ X,
                                                   const double *__restrict__ U, const double *__restrict__ f0,
                                                   const double *__restrict__ f1, double t_mid, double theta,
-                                                  const double *__restrict__ tau_p, const int16_t *__restrict__ a_in,
+                                                  const double *__restrict__ tau_p, const int16_t *a_in,
                                                   SweepOut o, double *__restrict__ Q) {
     __shared__ int64_t sh[kBlock / 64];
     StencilDev st = st0;
@@ -45,8 +178,23 @@ __global__ __launch_bounds__(kBlock) void k_sweep(LevelDev g, StencilDev st0, co
         st.fk = 0;
     }
     const double tau = tau_p[0];  // written by the tolerance kernel just before
+    // the tile of this block: its remapped position, or (with a work list) the list entry of this block's
+    // share, each XCD taking an equal contiguous part of the list
+    int tile;
+    if (o.list) {
+        // the grid is a multiple of 8 blocks with at least as many as there are tiles, so every XCD has
+        // ceil(tiles / 8) >= c8 blocks
+        const int cnt = o.list_count[0], c8 = (cnt + 7) >> 3;
+        const int t = (int)(blockIdx.x >> 3), j = (int)(blockIdx.x & 7) * c8 + t;
+        if (t >= c8 || j >= cnt) return;
+        tile = o.list[j];
+    } else {
+        tile = remap_block(blockIdx.x, gridDim.x);
+    }
+    const int64_t qslot = (int64_t)tile * kBlock + threadIdx.x;
+    const int64_t qstride = (int64_t)g.ntx * g.nty * g.ntz * kBlock;  // tiles of the grid, list or not
     int ix[3];
-    int i = tile_node<DIM>(g, ix);
+    int i = tile_node_at<DIM>(g, tile, ix);
     int64_t changed = 0;
     // re-evaluations read the cache this thread has just written
     constexpr int QM2 = QM == 1 ? 2 : QM;
@@ -60,56 +208,73 @@ __global__ __launch_bounds__(kBlock) void k_sweep(LevelDev g, StencilDev st0, co
             }
         } else {
             bool deep = deep_node<DIM>(g, ix);
-            double Xi = X[i], Ui = U[i];
-            const double f = f0[i] + t_mid * f1[i];
-            // the source of control k (one source for all controls unless st.fk != 0)
-            auto fk = [&](int k) { return st.fk ? f0[k * st.fk + i] + t_mid * f1[k * st.fk + i] : f; };
-            double omt = 1.0 - theta;
-            int cur = a_in[i];
-            double best = __builtin_inf(), gcur = __builtin_inf();
-            int kbest = 0;
-            for (int k = 0; k < st.K; ++k) {
-                double G = eval_G<DIM, CN, QM>(g, st, k, i, ix, deep, X, Xi, U, Ui, theta, omt, fk(k), Q);
-                if (G < best) {
-                    best = G;
-                    kbest = k;
-                }
-                if (k == cur) gcur = G;
-            }
-            double thr = best + tau;
-            int pick;
-            if (cur >= 0 && cur < st.K && gcur <= thr) {
-                pick = cur;
-            } else {
-                pick = kbest;
-                for (int k = 0; k < kbest; ++k) {
-                    double G = eval_G<DIM, CN, QM2>(g, st, k, i, ix, deep, X, Xi, U, Ui, theta, omt, fk(k), Q);
-                    if (G <= thr) {
-                        pick = k;
-                        break;
+            const int cur = a_in[i];
+            // untruncated wavefront, constant coefficients, one diffusion pair: the pipelined loop
+            int fast = 0;
+            if (!PN && st.fastD && st.P == 1 && __all(deep)) fast = st.has_drift ? 3 : 2;
+            // a wavefront whose decisions the certification pass kept: its controls are already in place
+            // (the search then runs in place) and its gap bounds are updated; no store on this path, so
+            // the tables of the search below stay scalar reads
+            const bool keep = !EXTRA && fast && o.skip == 2 && o.keep[tile * (kBlock / 64) + (threadIdx.x >> 6)];
+            if (!keep) {
+                double Xi = X[i], Ui = U[i];
+                const double f = f0[i] + t_mid * f1[i];
+                // the source of control k (one source for all controls unless st.fk != 0)
+                auto fk = [&](int k) { return st.fk ? f0[k * st.fk + i] + t_mid * f1[k * st.fk + i] : f; };
+                double omt = 1.0 - theta;
+                double best = __builtin_inf(), gcur = __builtin_inf(), second = __builtin_inf();
+                int kbest = 0;
+                if (fast == 3)
+                    search_deep<DIM, CN, QM, 1, true>(g, st, i, X, Xi, U, Ui, theta, omt, f, Q, qslot, qstride, cur, best,
+                                                      kbest, gcur, second);
+                else if (fast == 2)
+                    search_deep<DIM, CN, QM, 1, false>(g, st, i, X, Xi, U, Ui, theta, omt, f, Q, qslot, qstride, cur, best,
+                                                       kbest, gcur, second);
+                else
+                    for (int k = 0; k < st.K; ++k) {
+                        double G = eval_G<DIM, CN, QM>(g, st, k, i, ix, deep, X, Xi, U, Ui, theta, omt, fk(k), Q, qslot, qstride);
+                        if (G < best) {
+                            best = G;
+                            kbest = k;
+                        }
+                        if (k == cur) gcur = G;
+                    }
+                double thr = best + tau;
+                int pick;
+                if (cur >= 0 && cur < st.K && gcur <= thr) {
+                    pick = cur;
+                } else {
+                    pick = kbest;
+                    for (int k = 0; k < kbest; ++k) {
+                        double G = eval_G<DIM, CN, QM2>(g, st, k, i, ix, deep, X, Xi, U, Ui, theta, omt, fk(k), Q, qslot, qstride);
+                        if (G <= thr) {
+                            pick = k;
+                            break;
+                        }
                     }
                 }
-            }
-            o.alpha_out[i] = (int16_t)pick;
-            changed = (pick != cur) ? 1 : 0;
-            if (o.gmin) o.gmin[i] = best;
-            if (EXTRA) {
-                double mg = __builtin_inf();
-                int nt = 0;
-                for (int k = 0; k < st.K; ++k) {
-                    double G = eval_G<DIM, CN, QM2>(g, st, k, i, ix, deep, X, Xi, U, Ui, theta, omt, fk(k), Q);
-                    if (G <= thr)
-                        ++nt;
-                    else if (G - best < mg)
-                        mg = G - best;
+                o.alpha_out[i] = (int16_t)pick;
+                if (!EXTRA && o.skip) o.marg[i] = (fast && pick == kbest) ? second - best : -1.0;
+                changed = (pick != cur) ? 1 : 0;
+                if (o.gmin) o.gmin[i] = best;
+                if (EXTRA) {
+                    double mg = __builtin_inf();
+                    int nt = 0;
+                    for (int k = 0; k < st.K; ++k) {
+                        double G = eval_G<DIM, CN, QM2>(g, st, k, i, ix, deep, X, Xi, U, Ui, theta, omt, fk(k), Q, qslot, qstride);
+                        if (G <= thr)
+                            ++nt;
+                        else if (G - best < mg)
+                            mg = G - best;
+                    }
+                    if (o.margin) o.margin[i] = mg;
+                    if (o.ties) o.ties[i] = nt;
                 }
-                if (o.margin) o.margin[i] = mg;
-                if (o.ties) o.ties[i] = nt;
             }
         }
     }
     int64_t tot = block_reduce<int64_t>(changed, OpSum(), sh);
-    if (threadIdx.x == 0) o.changed_partial[remap_block(blockIdx.x, gridDim.x)] = tot;
+    if (threadIdx.x == 0) o.changed_partial[tile] = tot;
 }
 
 template <int DIM>
@@ -119,14 +284,16 @@ void launch_sweep_dim(const LevelDev &g, const StencilDev &st, const double *X, 
     bool cn = theta != 1.0;
     bool extra = o.margin != nullptr || o.ties != nullptr;
     const bool pn = st.pernode || st.fk;
+    // with a work list, whole groups of 8 blocks (one per XCD) cover the tiles
+    const int grid = o.list ? (tiles_for(g) + 7) / 8 * 8 : tiles_for(g);
 #define SW(C, E, QQ)                                                                                                  \
     do {                                                                                                              \
         if (pn)                                                                                                       \
-            hipLaunchKernelGGL((k_sweep<DIM, C, E, QQ, true>), dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, X, U,  \
-                               f0, f1, t_mid, theta, tau, a_in, o, Q);                                               \
+            hipLaunchKernelGGL((k_sweep<DIM, C, E, QQ, true>), dim3(grid), dim3(kBlock), 0, s, g, st, X, U, f0, f1,  \
+                               t_mid, theta, tau, a_in, o, Q);                                                       \
         else                                                                                                          \
-            hipLaunchKernelGGL((k_sweep<DIM, C, E, QQ, false>), dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, X, U, \
-                               f0, f1, t_mid, theta, tau, a_in, o, Q);                                               \
+            hipLaunchKernelGGL((k_sweep<DIM, C, E, QQ, false>), dim3(grid), dim3(kBlock), 0, s, g, st, X, U, f0, f1, \
+                               t_mid, theta, tau, a_in, o, Q);                                                       \
     } while (0)
     if (!cn) {
         if (extra) SW(false, true, 0); else SW(false, false, 0);
@@ -399,7 +566,7 @@ __device__ __forceinline__ T apply_level(const LevelDev &g, const StencilDev &st
 }
 
 template <int DIM, typename T>
-__global__ __launch_bounds__(kBlock) void k_jacobi(LevelDev g, StencilDev st0, const int16_t *__restrict__ alpha,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(DIM == 2 ? 8 : 1))) void k_jacobi(LevelDev g, StencilDev st0, const int16_t *__restrict__ alpha,
                                                    const T *__restrict__ e, const T *__restrict__ r,
                                                    const T *__restrict__ d, T *__restrict__ e_out, T theta_dt, T omega,
                                                    int first) {
@@ -432,7 +599,7 @@ void launch_jacobi(int dim, const LevelDev &g, const StencilDev &st, const int16
 }
 
 template <int DIM, typename T>
-__global__ __launch_bounds__(kBlock) void k_level_residual(LevelDev g, StencilDev st0, const int16_t *__restrict__ alpha,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(DIM == 2 ? 8 : 1))) void k_level_residual(LevelDev g, StencilDev st0, const int16_t *__restrict__ alpha,
                                                            const T *__restrict__ e, const T *__restrict__ r,
                                                            T *__restrict__ res, T theta_dt) {
     const StencilDev &st = st0;
@@ -593,6 +760,138 @@ void launch_coarse_solve(int dim, const LevelDev &g, const StencilDev &st, const
     else
         hipLaunchKernelGGL((k_coarse_solve<3, T>), dim3(1), dim3(1024), shm, s, g, st, alpha, r, d, e, (T)theta_dt,
                            (T)omega, sweeps);
+}
+
+// ---- bookkeeping of the certified decision reuse ---------------------------------------------------
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_delta_tiles(LevelDev g, const double *__restrict__ X,
+                                                        double *__restrict__ Xs, double *__restrict__ dtile,
+                                                        int record) {
+    __shared__ double sh[kBlock / 64];
+    int ix[3];
+    int i = tile_node<DIM>(g, ix);
+    double d = 0.0;
+    if (i >= 0) {
+        const double x = X[i];
+        d = fabs(x - Xs[i]);
+        d = (d == d) ? d : __builtin_inf();  // a NaN change is unbounded
+        Xs[i] = x;
+    }
+    if (record) return;
+    d = block_reduce<double>(d, OpMax(), sh);
+    if (threadIdx.x == 0) dtile[remap_block(blockIdx.x, gridDim.x)] = d;
+}
+
+void launch_delta_tiles(int dim, const LevelDev &g, const double *X, double *Xs, double *dtile, bool record,
+                        hipStream_t s) {
+    int nb = tiles_for(g);
+    if (dim == 2)
+        hipLaunchKernelGGL(k_delta_tiles<2>, dim3(nb), dim3(kBlock), 0, s, g, X, Xs, dtile, (int)record);
+    else
+        hipLaunchKernelGGL(k_delta_tiles<3>, dim3(nb), dim3(kBlock), 0, s, g, X, Xs, dtile, (int)record);
+}
+
+// tiles are (1 << tlog) x (kBlock >> tlog) x 1 nodes: the stencil window of tile (bx, by, bz) reaches
+// ceil(R/width) tiles along x, ceil(R/height) along y and R slabs along z
+__global__ __launch_bounds__(kBlock) void k_window_max(LevelDev g, const double *__restrict__ dtile,
+                                                       double *__restrict__ dwin, int rx, int ry, int rz) {
+    const int T = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ntiles = g.ntx * g.nty * g.ntz;
+    if (T >= ntiles) return;
+    const int bx = T % g.ntx, r = T / g.ntx, by = r % g.nty, bz = r / g.nty;
+    const int x0 = max(bx - rx, 0), x1 = min(bx + rx, g.ntx - 1);
+    const int y0 = max(by - ry, 0), y1 = min(by + ry, g.nty - 1);
+    const int z0 = max(bz - rz, 0), z1 = min(bz + rz, g.ntz - 1);
+    double m = 0.0;
+    for (int z = z0; z <= z1; ++z)
+        for (int y = y0; y <= y1; ++y)
+            for (int x = x0; x <= x1; ++x) {
+                const double v = dtile[x + g.ntx * (y + g.nty * z)];
+                m = (v > m || v != v) ? v : m;
+            }
+    dwin[T] = m;
+}
+
+void launch_window_max(int dim, const LevelDev &g, const double *dtile, double *dwin, const int R[3], hipStream_t s) {
+    const int tw = 1 << g.tlog, th = kBlock >> g.tlog;
+    const int rx = (R[0] + tw - 1) / tw, ry = (R[1] + th - 1) / th, rz = dim == 3 ? R[2] : 0;
+    const int ntiles = g.ntx * g.nty * g.ntz;
+    hipLaunchKernelGGL(k_window_max, dim3((ntiles + kBlock - 1) / kBlock), dim3(kBlock), 0, s, g, dtile, dwin, rx, ry,
+                       rz);
+}
+
+// Certification of the decisions of the next search (constant coefficients, one diffusion pair): a
+// wavefront whose interior nodes are all untruncated keeps its controls when every recorded gap, less
+// the largest change of G since (lip2 times the window change of X), stays above the rounding slack.
+// keep[wave] tells the search; kept nodes get the reduced bound.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_keep_pass(LevelDev g, double *__restrict__ marg,
+                                                      const double *__restrict__ dwin, double lip2,
+                                                      const double *__restrict__ scale, uint8_t *__restrict__ keep,
+                                                      int64_t *__restrict__ kept_partial, uint8_t *__restrict__ need,
+                                                      int64_t *__restrict__ changed_partial) {
+    __shared__ int64_t sh[kBlock / 64];
+    int ix[3];
+    int i = tile_node<DIM>(g, ix);
+    const int tile = remap_block(blockIdx.x, gridDim.x);
+    const bool inter = i >= 0 && interior<DIM>(g, ix);
+    const bool deep = inter && deep_node<DIM>(g, ix);
+    double lim = 0.0;
+    bool ok = false;
+    if (deep) {
+        lim = marg[i] - lip2 * dwin[tile];
+        ok = lim > kSkipSlack * scale[0];
+    }
+    const uint64_t bi = __ballot(inter), bd = __ballot(deep), bk = __ballot(ok);
+    const bool wk = bi != 0 && bd == bi && bk == bi;
+    if (wk && inter) marg[i] = lim;
+    if ((threadIdx.x & 63) == 0) keep[tile * (kBlock / 64) + (threadIdx.x >> 6)] = wk ? 1 : 0;
+    // the search visits the tile unless every wavefront is kept or has no interior node
+    const int any = __syncthreads_or((bi != 0 && !wk) ? 1 : 0);
+    const int64_t tot = block_reduce<int64_t>((wk && inter) ? 1 : 0, OpSum(), sh);
+    if (threadIdx.x == 0) {
+        kept_partial[tile] = tot;
+        need[tile] = any ? 1 : 0;
+        changed_partial[tile] = 0;  // the search rewrites it for the tiles it visits
+    }
+}
+
+void launch_keep_pass(int dim, const LevelDev &g, double *marg, const double *dwin, double lip2, const double *scale,
+                      uint8_t *keep, int64_t *kept_partial, uint8_t *need, int64_t *changed_partial, hipStream_t s) {
+    int nb = tiles_for(g);
+    if (dim == 2)
+        hipLaunchKernelGGL(k_keep_pass<2>, dim3(nb), dim3(kBlock), 0, s, g, marg, dwin, lip2, scale, keep,
+                           kept_partial, need, changed_partial);
+    else
+        hipLaunchKernelGGL(k_keep_pass<3>, dim3(nb), dim3(kBlock), 0, s, g, marg, dwin, lip2, scale, keep,
+                           kept_partial, need, changed_partial);
+}
+
+// list[0 .. count) = the tiles with need[t] != 0, in increasing order (one workgroup)
+__global__ __launch_bounds__(1024) void k_tile_list(const uint8_t *__restrict__ need, int nt, int32_t *__restrict__ list,
+                                                    int32_t *__restrict__ count) {
+    __shared__ int sh[1024];
+    const int per = (nt + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int b0 = (int)threadIdx.x * per, b1 = min(b0 + per, nt);
+    int c = 0;
+    for (int b = b0; b < b1; ++b) c += need[b] ? 1 : 0;
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+        const int v = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int pos = sh[threadIdx.x] - c;
+    for (int b = b0; b < b1; ++b)
+        if (need[b]) list[pos++] = b;
+    if (threadIdx.x == blockDim.x - 1) count[0] = sh[threadIdx.x];
+}
+
+void launch_tile_list(const uint8_t *need, int nt, int32_t *list, int32_t *count, hipStream_t s) {
+    hipLaunchKernelGGL(k_tile_list, dim3(1), dim3(1024), 0, s, need, nt, list, count);
 }
 
 template <int DIM>

@@ -232,6 +232,38 @@ def test_vcycle_graph_replays_match_eager(slhjb):
         np.testing.assert_array_equal(o, outs[0])
 
 
+SKIP_CASES = [
+    ("c2_129_cn", lambda: workloads.config_c2(129, n_cn=8)),
+    ("c2_257_cn", lambda: workloads.config_c2(257, n_cn=4)),
+    ("c5_17_3d", lambda: workloads.config_c5(17, n_steps=4)),
+    ("ragged_2d_p2", lambda: _toy((37, 29), K=7, P=2, seed=3, c=True)),
+    # 12 tiles of 32 x 8: a work list that is not a multiple of the 8 XCD shares
+    ("ragged_52x47_p1", lambda: _toy((52, 47), K=3, P=1, seed=11, c=True)),
+    ("ragged_3d_p1", lambda: _toy((11, 9, 13), K=5, P=1, seed=4)),
+]
+
+
+@pytest.mark.parametrize("name,mk", SKIP_CASES, ids=[c[0] for c in SKIP_CASES])
+def test_certified_skip_matches_full_search(slhjb, name, mk):
+    """Searches that keep certified decisions give the controls of full searches: the whole march, every
+    policy and every solver count agree bit for bit with certified_skip off."""
+    inst = mk()
+    log(f"certified skip {name}")
+    res = []
+    for skip in (0, 1):
+        solver = slhjb.Solver.from_instance(inst, slhjb.Options(precision=1, certified_skip=skip))
+        g = to_dev(inst.g)
+        U = torch.empty_like(g)
+        pol = torch.empty((len(inst.dts), inst.N), dtype=torch.int16, device=g.device)
+        st = solver.solve(g, to_dev(inst.psi), to_dev(inst.f0), to_dev(inst.f1), inst.dts, inst.thetas, inst.s, U, pol)
+        res.append((to_np(U), to_np(pol), st.krylov_total, st.pi_total))
+        solver.close()
+    log(f"  krylov {res[0][2]} / {res[1][2]}, pi {res[0][3]} / {res[1][3]}")
+    np.testing.assert_array_equal(res[1][1], res[0][1])
+    np.testing.assert_array_equal(res[1][0], res[0][0])
+    assert res[1][2:] == res[0][2:]
+
+
 @pytest.mark.parametrize("width", [16, 64, 128])
 def test_tile_widths_sweep_and_march(slhjb, width):
     """Every tile shape gives the bit-exact search and a march within the parity bound."""

@@ -388,8 +388,9 @@ struct OpSum {
     template <typename T>
     __device__ T operator()(T a, T b) const { return a + b; }
 };
+// a NaN operand wins, so that a NaN residual or norm is never reported as a finite maximum
 struct OpMax {
-    __device__ double operator()(double a, double b) const { return a > b ? a : b; }
+    __device__ double operator()(double a, double b) const { return (a > b || a != a) ? a : b; }
 };
 
 // ---- policy search (Howard's algorithm, eq. nonlinear_sys) ----------------------------------------

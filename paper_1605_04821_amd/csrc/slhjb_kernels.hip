@@ -1004,43 +1004,58 @@ void launch_multiaxpy_scale(double *w, const double *V, int64_t ldv, int nvec, c
     hipLaunchKernelGGL(k_multiaxpy_scale, dim3(nblocks), dim3(kBlock), 0, s, w, V, ldv, nvec, coef, N);
 }
 
-__global__ __launch_bounds__(kBlock) void k_reduce_sum(const double *__restrict__ partial, int nblocks,
-                                                       double *__restrict__ out) {
-    __shared__ double sh[kBlock / 64];
-    const double *p = partial + (int64_t)blockIdx.x * nblocks;
-    double acc = 0.0;
-    for (int q = threadIdx.x; q < nblocks; q += kBlock) acc += p[q];
-    double t = block_reduce<double>(acc, OpSum(), sh);
+// Reductions of per-block partials: one workgroup of kRedThreads per vector, four independent
+// accumulators per thread so that four loads are in flight at a time (the partial arrays are short and
+// latency, not bandwidth, sets the time).
+constexpr int kRedThreads = 1024;
+
+template <typename T, typename Op>
+__device__ __forceinline__ T reduce_strided(const T *__restrict__ p, int n, Op op, T id) {
+    T a0 = id, a1 = id, a2 = id, a3 = id;
+    int q = threadIdx.x;
+    for (; q + 3 * kRedThreads < n; q += 4 * kRedThreads) {
+        const T v0 = p[q], v1 = p[q + kRedThreads], v2 = p[q + 2 * kRedThreads], v3 = p[q + 3 * kRedThreads];
+        a0 = op(a0, v0);
+        a1 = op(a1, v1);
+        a2 = op(a2, v2);
+        a3 = op(a3, v3);
+    }
+    for (; q < n; q += kRedThreads) a0 = op(a0, p[q]);
+    return op(op(a0, a1), op(a2, a3));
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce_sum(const double *__restrict__ partial, int nblocks,
+                                                            double *__restrict__ out) {
+    __shared__ double sh[kRedThreads / 64];
+    const double t = block_reduce<double>(
+        reduce_strided<double>(partial + (int64_t)blockIdx.x * nblocks, nblocks, OpSum(), 0.0), OpSum(), sh);
     if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
 
-__global__ __launch_bounds__(kBlock) void k_reduce_max(const double *__restrict__ partial, int nblocks,
-                                                       double *__restrict__ out) {
-    __shared__ double sh[kBlock / 64];
-    const double *p = partial + (int64_t)blockIdx.x * nblocks;
-    double acc = 0.0;
-    for (int q = threadIdx.x; q < nblocks; q += kBlock) acc = fmax(acc, p[q]);
-    double t = block_reduce<double>(acc, OpMax(), sh);
+// largest entry (the partials are non-negative); a NaN anywhere is the result
+__global__ __launch_bounds__(kRedThreads) void k_reduce_max(const double *__restrict__ partial, int nblocks,
+                                                            double *__restrict__ out) {
+    __shared__ double sh[kRedThreads / 64];
+    const double t = block_reduce<double>(
+        reduce_strided<double>(partial + (int64_t)blockIdx.x * nblocks, nblocks, OpMax(), 0.0), OpMax(), sh);
     if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
 
-__global__ __launch_bounds__(kBlock) void k_reduce_sum_i64(const int64_t *__restrict__ partial, int nblocks,
-                                                           int64_t *__restrict__ out) {
-    __shared__ int64_t sh[kBlock / 64];
-    int64_t acc = 0;
-    for (int q = threadIdx.x; q < nblocks; q += kBlock) acc += partial[q];
-    int64_t t = block_reduce<int64_t>(acc, OpSum(), sh);
+__global__ __launch_bounds__(kRedThreads) void k_reduce_sum_i64(const int64_t *__restrict__ partial, int nblocks,
+                                                                int64_t *__restrict__ out) {
+    __shared__ int64_t sh[kRedThreads / 64];
+    const int64_t t = block_reduce<int64_t>(reduce_strided<int64_t>(partial, nblocks, OpSum(), (int64_t)0), OpSum(), sh);
     if (threadIdx.x == 0) out[0] = t;
 }
 
 void launch_reduce_sum(const double *partial, int nvec, int nblocks, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_sum, dim3(nvec), dim3(kBlock), 0, s, partial, nblocks, out);
+    hipLaunchKernelGGL(k_reduce_sum, dim3(nvec), dim3(kRedThreads), 0, s, partial, nblocks, out);
 }
 void launch_reduce_max(const double *partial, int nvec, int nblocks, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_max, dim3(nvec), dim3(kBlock), 0, s, partial, nblocks, out);
+    hipLaunchKernelGGL(k_reduce_max, dim3(nvec), dim3(kRedThreads), 0, s, partial, nblocks, out);
 }
 void launch_reduce_sum_i64(const int64_t *partial, int nblocks, int64_t *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_sum_i64, dim3(1), dim3(kBlock), 0, s, partial, nblocks, out);
+    hipLaunchKernelGGL(k_reduce_sum_i64, dim3(1), dim3(kRedThreads), 0, s, partial, nblocks, out);
 }
 
 __global__ __launch_bounds__(kBlock) void k_scale_by_inv_sqrt(double *__restrict__ dst, const double *__restrict__ src,

@@ -152,8 +152,8 @@ class Options:
     max_pi: int = 50
     nu1: int = 3
     nu2: int = 3
-    coarse_sweeps: int = 10
-    min_coarse: int = 17
+    coarse_sweeps: int = 4
+    min_coarse: int = 33
     omega: float = 0.9
     rtol_inf: float = 1e-13
     tau_rel: float = 1e-13

@@ -866,8 +866,8 @@ void hjb_desc_default(hjb_desc *d) {
     d->max_pi = 50;
     d->nu1 = 3;
     d->nu2 = 3;
-    d->coarse_sweeps = 10;
-    d->min_coarse = 17;
+    d->coarse_sweeps = 4;
+    d->min_coarse = 33;
     d->omega = 0.9;
     d->rtol_inf = 1e-13;
     d->tau_rel = 1e-13;

@@ -44,6 +44,103 @@ __device__ __forceinline__ bool interior_a(const LevelDev &g, const int ix[3]) {
     return ok;
 }
 
+template <int DIM>
+__device__ __forceinline__ bool deep_a(const LevelDev &g, const int ix[3]) {
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) ok = ok && ix[d] >= g.deep_lo[d] && ix[d] <= g.deep_hi[d];
+    return ok;
+}
+
+// ---- columns of L where the control is uniform over the stencil window ------------------------------
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_tile_code(LevelDev g, const int16_t *__restrict__ alpha, int K,
+                                                      int32_t *__restrict__ code) {
+    __shared__ int smin, smax;
+    if (threadIdx.x == 0) {
+        smin = 0x7fffffff;
+        smax = -1;
+    }
+    __syncthreads();
+    int ix[3];
+    const int j = tile_node_a<DIM>(g, ix);
+    const bool ok = j >= 0 && interior_a<DIM>(g, ix) && deep_a<DIM>(g, ix);
+    const int k = ok ? (int)alpha[j] : -1;
+    const int all = __syncthreads_and(ok ? 1 : 0);
+    if (ok) {
+        atomicMin(&smin, k);
+        atomicMax(&smax, k);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        code[remap_block_a(blockIdx.x, gridDim.x)] = (all && smin == smax && smin >= 0 && smin < K) ? smin : -1;
+}
+
+void launch_tile_code(int dim, const LevelDev &g, const int16_t *alpha, int K, int32_t *code, hipStream_t s) {
+    if (dim == 2)
+        hipLaunchKernelGGL(k_tile_code<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, alpha, K, code);
+    else
+        hipLaunchKernelGGL(k_tile_code<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, alpha, K, code);
+}
+
+__global__ __launch_bounds__(kBlock) void k_window_code(LevelDev g, const int32_t *__restrict__ code,
+                                                        int32_t *__restrict__ wflag, int rx, int ry, int rz) {
+    const int T = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ntiles = g.ntx * g.nty * g.ntz;
+    if (T >= ntiles) return;
+    const int bx = T % g.ntx, r = T / g.ntx, by = r % g.nty, bz = r / g.nty;
+    const int k = code[T];
+    bool same = k >= 0;
+    // a window cut by the grid edge holds boundary tiles (code -1), so a uniform window is never cut
+    for (int z = max(bz - rz, 0); same && z <= min(bz + rz, g.ntz - 1); ++z)
+        for (int y = max(by - ry, 0); same && y <= min(by + ry, g.nty - 1); ++y)
+            for (int x = max(bx - rx, 0); same && x <= min(bx + rx, g.ntx - 1); ++x)
+                same = code[x + g.ntx * (y + g.nty * z)] == k;
+    wflag[T] = same ? k : -1;
+}
+
+void launch_window_code(int dim, const LevelDev &g, const int32_t *code, int32_t *wflag, const int R[3],
+                        hipStream_t s) {
+    const int tw = 1 << g.tlog, th = kBlock >> g.tlog;
+    const int rx = (R[0] + tw - 1) / tw, ry = (R[1] + th - 1) / th, rz = dim == 3 ? R[2] : 0;
+    const int ntiles = g.ntx * g.nty * g.ntz;
+    hipLaunchKernelGGL(k_window_code, dim3((ntiles + kBlock - 1) / kBlock), dim3(kBlock), 0, s, g, code, wflag, rx,
+                       ry, rz);
+}
+
+// (L^T x)_j on a column whose whole stencil window has control k: sum over the points of the row stencil
+// of control k, reflected (x at j - off - delta_c with the weight of corner c), minus the diagonal part,
+// in the form of the forward operator (TW: weight table record type)
+template <int DIM, typename TC, typename TX, typename TW>
+__device__ __forceinline__ TC lt_reflect(const LevelDev &g, const StencilDev &st, const TW *__restrict__ tab, int k,
+                                         int j, const TX *__restrict__ x, TC xj) {
+    const TW *fp = tab + k * st.npt;
+    const int s1 = (int)g.s1, s2 = (int)g.s2;
+    auto pt = [&](const TW &p) {
+        const int o = j - p.off;
+        TC v = (TC)p.w[0] * (TC)x[o];
+        v = fma((TC)p.w[1], (TC)x[o - 1], v);
+        v = fma((TC)p.w[2], (TC)x[o - s1], v);
+        v = fma((TC)p.w[3], (TC)x[o - s1 - 1], v);
+        if (DIM == 3) {
+            v = fma((TC)p.w[4], (TC)x[o - s2], v);
+            v = fma((TC)p.w[5], (TC)x[o - s2 - 1], v);
+            v = fma((TC)p.w[6], (TC)x[o - s2 - s1], v);
+            v = fma((TC)p.w[7], (TC)x[o - s2 - s1 - 1], v);
+        }
+        return v;
+    };
+    TC acc = (TC)0;
+    for (int p = 0; p < st.P; ++p) acc = acc + ((pt(fp[2 * p]) + pt(fp[2 * p + 1])) - (TC)2 * xj);
+    if (st.has_drift) acc = acc + (TC)2 * (pt(fp[2 * st.P]) - xj);
+    return (TC)st.inv2h * acc;
+}
+
+__device__ __forceinline__ int window_control(const TransposeView &T) {
+    return T.wflag ? T.wflag[remap_block_a(blockIdx.x, gridDim.x)] : -1;
+}
+
 // ---- dual numbers ---------------------------------------------------------------------------------
 
 struct Dual {
@@ -651,12 +748,18 @@ __global__ __launch_bounds__(kBlock) void k_apply_T_f32x(LevelDev g, StencilDev 
         y[j] = 0.0;
         return;
     }
+    const int kw = window_control(T);
+    double xj = (double)x[j];
+    if (kw >= 0) {
+        const double cj = st.c ? st.c[kw] : 0.0;
+        y[j] = xj - w * (lt_reflect<DIM, double>(g, st, st.fastD, kw, j, x, xj) + cj * xj);
+        return;
+    }
     double cj = 0.0;
     if (st.c) {
         int k = alpha[j];
         cj = st.c[((unsigned)k < (unsigned)st.K) ? k : 0];
     }
-    double xj = (double)x[j];
     y[j] = xj - w * (lt_gather<float>(j, T, x) + cj * xj);
 }
 
@@ -692,9 +795,17 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_T32(LevelDev g, StencilDev st
         y[j] = omega * r[j] / d[j];
         return;
     }
+    const int kw = window_control(T);
     float xj = x[j];
-    float lt = lt_gather32<PACKED>(j, (int)g.s1, T, x);
-    float res = r[j] - (xj - theta_dt * (lt + coef32<DIM>(st, alpha, j) * xj));
+    float lt, cj;
+    if (kw >= 0) {
+        lt = lt_reflect<DIM, float>(g, st, st.fastF, kw, j, x, xj);
+        cj = st.c ? (float)st.c[kw] : 0.0f;
+    } else {
+        lt = lt_gather32<PACKED>(j, (int)g.s1, T, x);
+        cj = coef32<DIM>(st, alpha, j);
+    }
+    float res = r[j] - (xj - theta_dt * (lt + cj * xj));
     y[j] = xj + omega * res / d[j];
 }
 
@@ -728,9 +839,17 @@ __global__ __launch_bounds__(kBlock) void k_resid_T32(LevelDev g, StencilDev st,
         y[j] = 0.0f;
         return;
     }
+    const int kw = window_control(T);
     float xj = x[j];
-    float lt = lt_gather32<PACKED>(j, (int)g.s1, T, x);
-    y[j] = b[j] - (xj - theta_dt * (lt + coef32<DIM>(st, alpha, j) * xj));
+    float lt, cj;
+    if (kw >= 0) {
+        lt = lt_reflect<DIM, float>(g, st, st.fastF, kw, j, x, xj);
+        cj = st.c ? (float)st.c[kw] : 0.0f;
+    } else {
+        lt = lt_gather32<PACKED>(j, (int)g.s1, T, x);
+        cj = coef32<DIM>(st, alpha, j);
+    }
+    y[j] = b[j] - (xj - theta_dt * (lt + cj * xj));
 }
 
 void launch_resid_T32(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const TransposeView &T,

@@ -63,6 +63,7 @@ struct Level {
     void *r64 = nullptr, *e64 = nullptr, *t64 = nullptr, *d64 = nullptr;  // FP64 copies (plain path)
     void *r32 = nullptr, *e32 = nullptr, *t32 = nullptr, *d32 = nullptr;
     double *sig_node = nullptr;  // per-node sigma model: [N][P][dim] on this level (injected from level 0)
+    int reach[3] = {0, 0, 0};    // largest stencil corner offset in nodes along each axis (any control)
 };
 
 }  // namespace
@@ -217,8 +218,9 @@ int build_tables(hjb_handle *hd, double s) {
             for (const PointTab &p : host)
                 for (int a = 0; a < 3; ++a) E[a] = std::max(E[a], fabs(p.Y[a]));
         }
+        for (int a = 0; a < 3; ++a) L.reach[a] = a < hd->dim ? (int)ceil(E[a]) + 1 : 0;
         if (l == 0)
-            for (int a = 0; a < 3; ++a) hd->reach[a] = a < hd->dim ? (int)ceil(E[a]) + 1 : 0;
+            for (int a = 0; a < 3; ++a) hd->reach[a] = L.reach[a];
         for (int a = 0; a < 3; ++a) {
             if (a < hd->dim) {
                 int lo = (int)ceil(E[a]);
@@ -1425,9 +1427,23 @@ int hjb_autotune(hjb_handle *hd, const char *cache_path, int32_t *tile_width_out
 
 namespace {
 
+// the largest tile count of a level over the tile shapes the handle may take
+int tiles_cap(const LevelDev &g0, int dim) {
+    int cap = 0;
+    for (int tl = kTileLogMin; tl <= kTileLogMax; ++tl) {
+        LevelDev g = g0;
+        g.tlog = tl;
+        set_tiles(g, dim);
+        cap = std::max(cap, tiles_for(g));
+    }
+    return cap;
+}
+
 struct TransposeWork {
     int E = 0;
     TransposeBuf b{};
+    int32_t *tcode = nullptr, *wflag = nullptr;  // [tiles] uniform-window controls (constant coefficients)
+    bool wf = false;                             // wflag holds the current policy's windows
     std::vector<void *> mem;
     TransposeWork() = default;
     TransposeWork(const TransposeWork &) = delete;
@@ -1436,8 +1452,8 @@ struct TransposeWork {
         for (void *p : mem) (void)hipFree(p);
     }
     TransposeView view() const {
-        return TransposeView{b.colptr, b.rows_s,    b.vals_s,     b.ell_w,
-                             b.ell_off, b.ell_rows, b.ell_vals, b.ell_vals32, b.ell_d16};
+        return TransposeView{b.colptr, b.rows_s,   b.vals_s,     b.ell_w,   b.ell_off,
+                             b.ell_rows, b.ell_vals, b.ell_vals32, b.ell_d16, wf ? wflag : nullptr};
     }
     int alloc(hjb_handle *hd, int level, bool f32, bool pack) {
         const LevelDev &g = hd->lev[level].g;
@@ -1458,7 +1474,8 @@ struct TransposeWork {
                    {(void **)&b.vals_s, (size_t)n * 8}, {(void **)&b.colptr, (size_t)(nodes + 1) * 4},
                    {(void **)&b.ell_w, (size_t)ns * 4}, {(void **)&b.ell_off, (size_t)ns * 4},
                    {(void **)&b.ell_rows, (size_t)ne * 4}, {(void **)&b.ell_vals, (size_t)ne * 8},
-                   {&b.scratch, b.scratch_bytes + 256}};
+                   {&b.scratch, b.scratch_bytes + 256}, {(void **)&tcode, (size_t)tiles_cap(g, hd->dim) * 4},
+                   {(void **)&wflag, (size_t)tiles_cap(g, hd->dim) * 4}};
         for (auto &r : req) {
             if (hipMalloc(r.p, r.bytes) != hipSuccess) {
                 (void)hipGetLastError();
@@ -1529,6 +1546,12 @@ struct TransposeHierarchy {
             launch_diag<double>(hd->dim, L.g, stencil(hd, (int)l), L.alpha, theta_dt, (double *)L.d64, s);
             if (f32) launch_diag<float>(hd->dim, L.g, stencil(hd, (int)l), L.alpha, theta_dt, (float *)L.d32, s);
             TRY(lev[l]->build(hd, (int)l, L.alpha));
+            // columns whose whole stencil window shares one untruncated control are gathered matrix-free
+            lev[l]->wf = hd->desc.coef_model == HJB_COEF_CONST && !hd->desc.f_per_control;
+            if (lev[l]->wf) {
+                launch_tile_code(hd->dim, L.g, L.alpha, hd->desc.K, lev[l]->tcode, s);
+                launch_window_code(hd->dim, L.g, lev[l]->tcode, lev[l]->wflag, L.reach, s);
+            }
         }
         return HJB_OK;
     }

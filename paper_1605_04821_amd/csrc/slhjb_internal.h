@@ -237,7 +237,16 @@ struct TransposeView {
     const double *ell_vals;
     const float *ell_vals32;
     const int16_t *ell_d16;
+    // optional, per tile: the control shared by every node within the stencil reach of the tile (all
+    // untruncated, constant coefficients), else -1.  There column j of L is the row stencil reflected
+    // (entries w_c at j - off - delta_c), so the kernels gather it without the listing.
+    const int32_t *wflag;
 };
+// code[tile] = the control of all nodes of the tile when they are interior and untruncated, else -1
+void launch_tile_code(int dim, const LevelDev &g, const int16_t *alpha, int K, int32_t *code, hipStream_t s);
+// wflag[T] = code of T when every tile within R[a] nodes along each axis has the same code, else -1
+void launch_window_code(int dim, const LevelDev &g, const int32_t *code, int32_t *wflag, const int R[3],
+                        hipStream_t s);
 int build_transpose(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, int E, TransposeBuf &b,
                     hipStream_t s);
 size_t transpose_scratch_bytes(int64_t n, int N, int nslices);

@@ -643,25 +643,37 @@ int fgmres(hjb_handle *hd, const int16_t *alpha, const double *E, double *X, dou
 
 // ---- policy search ------------------------------------------------------------------------------
 
-__global__ void k_tau(const double *partial, int nb, double coefA, double tau_rel, double *out) {
-    // out[0] = tau from max(|X|,|U|) (partial[0..nb)) and max|f| (partial[nb..2nb))
-    __shared__ double sx[256], sf[256];
-    double ax = 0.0, af = 0.0;
-    for (int q = threadIdx.x; q < nb; q += blockDim.x) {
-        ax = fmax(ax, partial[q]);
-        af = fmax(af, partial[nb + q]);
+__global__ __launch_bounds__(1024) void k_tau(const double *partial, int nb, double coefA, double tau_rel,
+                                              double *out) {
+    // out[0] = tau and out[1] = S from max(|X|,|U|) (partial[0..nb)) and max|f| (partial[nb..2nb)); two
+    // loads of each array in flight per thread; a NaN wins the maximum
+    __shared__ double sx[1024], sf[1024];
+    auto mx = [](double a, double b) { return (a > b || a != a) ? a : b; };
+    const int t = threadIdx.x, nt = blockDim.x;
+    double ax0 = 0.0, ax1 = 0.0, af0 = 0.0, af1 = 0.0;
+    int q = t;
+    for (; q + nt < nb; q += 2 * nt) {
+        const double a0 = partial[q], a1 = partial[q + nt], f0 = partial[nb + q], f1 = partial[nb + q + nt];
+        ax0 = mx(ax0, a0);
+        ax1 = mx(ax1, a1);
+        af0 = mx(af0, f0);
+        af1 = mx(af1, f1);
     }
-    sx[threadIdx.x] = ax;
-    sf[threadIdx.x] = af;
+    for (; q < nb; q += nt) {
+        ax0 = mx(ax0, partial[q]);
+        af0 = mx(af0, partial[nb + q]);
+    }
+    sx[t] = mx(ax0, ax1);
+    sf[t] = mx(af0, af1);
     __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            sx[threadIdx.x] = fmax(sx[threadIdx.x], sx[threadIdx.x + w]);
-            sf[threadIdx.x] = fmax(sf[threadIdx.x], sf[threadIdx.x + w]);
+    for (int w = nt / 2; w > 0; w >>= 1) {
+        if (t < w) {
+            sx[t] = mx(sx[t], sx[t + w]);
+            sf[t] = mx(sf[t], sf[t + w]);
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
+    if (t == 0) {
         double S = coefA * sx[0] + sf[0];
         out[0] = tau_rel * S;
         out[1] = S;
@@ -687,7 +699,7 @@ int sweep(hjb_handle *hd, const double *X, const double *U, const double *f0, co
     launch_norms_xuf(hd->dim, L0.g, X, U, f0, f1, t_mid, hd->desc.K, stencil(hd, 0).fk, hd->partial, hd->nb, s);
     double inv2h = 0.5 / hd->desc.h;
     double coefA = 2.0 * hd->M * inv2h + hd->cmax;
-    hipLaunchKernelGGL(k_tau, dim3(1), dim3(256), 0, s, hd->partial, hd->nb, coefA, hd->desc.tau_rel, hd->dvals + 4);
+    hipLaunchKernelGGL(k_tau, dim3(1), dim3(1024), 0, s, hd->partial, hd->nb, coefA, hd->desc.tau_rel, hd->dvals + 4);
     if (skip == 1) {
         launch_delta_tiles(hd->dim, L0.g, X, hd->Xs, hd->dtile, true, s);
     } else if (skip == 2) {

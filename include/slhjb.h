@@ -80,7 +80,8 @@ typedef struct {
     int32_t max_pi;         /* policy iterations per time step */
     int32_t nu1, nu2;       /* V-cycle pre/post Jacobi sweeps */
     int32_t coarse_sweeps;  /* Jacobi sweeps on the coarsest level */
-    int32_t min_coarse;     /* stop coarsening when a level has <= min_coarse nodes per axis */
+    int32_t min_coarse;     /* stop coarsening at the first level with <= min_coarse nodes per axis that also
+                               fits the one-workgroup coarsest solve (<= 2048 nodes) */
     double omega;           /* Jacobi damping */
     double rtol_inf;        /* linear solve stops when |F - A X|_inf <= rtol_inf * max(1,|X|_inf) */
     double tau_rel;         /* policy tie tolerance relative to the scale S of the search */
@@ -95,6 +96,7 @@ typedef struct {
                                largest change of G allowed by the change of X since (constant coefficients,
                                P = 1): the same controls as a full search, at a fraction of its cost.  0: every
                                search evaluates every control */
+    int32_t max_levels;     /* at most this many multigrid levels (0: no limit); setup only */
     void *stream;           /* hipStream_t */
 } hjb_desc;
 

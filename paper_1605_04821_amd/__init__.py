@@ -48,7 +48,8 @@ class Desc(ctypes.Structure):
                 ("nu2", ctypes.c_int32), ("coarse_sweeps", ctypes.c_int32), ("min_coarse", ctypes.c_int32),
                 ("omega", ctypes.c_double), ("rtol_inf", ctypes.c_double), ("tau_rel", ctypes.c_double),
                 ("pi_eta", ctypes.c_double), ("use_graphs", ctypes.c_int32), ("f_per_control", ctypes.c_int32),
-                ("certified_skip", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("certified_skip", ctypes.c_int32), ("max_levels", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
 
 
 class StepStats(ctypes.Structure):
@@ -153,13 +154,14 @@ class Options:
     nu1: int = 3
     nu2: int = 3
     coarse_sweeps: int = 4
-    min_coarse: int = 33
+    min_coarse: int = 17
     omega: float = 0.9
     rtol_inf: float = 1e-13
     tau_rel: float = 1e-13
     pi_eta: float = 0.2
     use_graphs: int = 1
     certified_skip: int = 1
+    max_levels: int = 2
 
 
 class Solver:
@@ -216,6 +218,7 @@ class Solver:
         desc.rtol_inf, desc.tau_rel, desc.pi_eta = o.rtol_inf, o.tau_rel, o.pi_eta
         desc.use_graphs = o.use_graphs
         desc.certified_skip = o.certified_skip
+        desc.max_levels = o.max_levels
 
     @classmethod
     def from_instance(cls, inst, options: Optional[Options] = None):

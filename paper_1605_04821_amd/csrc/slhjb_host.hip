@@ -322,6 +322,7 @@ int check_options(const hjb_desc *d) {
     if (!(d->omega > 0.0 && d->omega < 2.0)) return fail(HJB_EINVAL, "omega must be in (0,2)");
     if (!(d->rtol_inf > 0.0) || !(d->tau_rel >= 0.0)) return fail(HJB_EINVAL, "rtol_inf > 0 and tau_rel >= 0 required");
     if (!(d->pi_eta >= 0.0 && d->pi_eta < 1.0)) return fail(HJB_EINVAL, "pi_eta must be in [0,1)");
+    if (d->max_levels < 0) return fail(HJB_EINVAL, "max_levels must be >= 0");
     return HJB_OK;
 }
 
@@ -881,13 +882,14 @@ void hjb_desc_default(hjb_desc *d) {
     d->nu1 = 3;
     d->nu2 = 3;
     d->coarse_sweeps = 4;
-    d->min_coarse = 33;
+    d->min_coarse = 17;
     d->omega = 0.9;
     d->rtol_inf = 1e-13;
     d->tau_rel = 1e-13;
     d->pi_eta = 0.2;
     d->use_graphs = 1;
     d->certified_skip = 1;
+    d->max_levels = 2;
     d->stream = nullptr;
 }
 
@@ -988,6 +990,7 @@ int setup_impl(const hjb_desc *desc, hjb_handle **out, bool tables_only) {
                 small = small && n[a] <= std::max(3, d.min_coarse);
             }
             if (!can || (small && L.g.N <= kCoarseMaxNodes)) break;
+            if (d.max_levels > 0 && (int)hd->lev.size() >= d.max_levels) break;
             for (int a = 0; a < d.dim; ++a) n[a] = (n[a] - 1) / 2 + 1;
         }
     }
@@ -2423,6 +2426,7 @@ int hjb_setup_batch(const hjb_desc *descs, int32_t count, hjb_batch **out) {
         db.nu2 = d0.nu2;
         db.coarse_sweeps = d0.coarse_sweeps;
         db.min_coarse = d0.min_coarse;
+        db.max_levels = d0.max_levels;
         db.omega = d0.omega;
         db.rtol_inf = d0.rtol_inf;
         db.tau_rel = d0.tau_rel;

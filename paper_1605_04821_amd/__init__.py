@@ -49,7 +49,7 @@ class Desc(ctypes.Structure):
                 ("omega", ctypes.c_double), ("rtol_inf", ctypes.c_double), ("tau_rel", ctypes.c_double),
                 ("pi_eta", ctypes.c_double), ("use_graphs", ctypes.c_int32), ("f_per_control", ctypes.c_int32),
                 ("certified_skip", ctypes.c_int32), ("max_levels", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("nu_tight", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class StepStats(ctypes.Structure):
@@ -162,6 +162,7 @@ class Options:
     use_graphs: int = 1
     certified_skip: int = 1
     max_levels: int = 2
+    nu_tight: int = 4
 
 
 class Solver:
@@ -219,6 +220,7 @@ class Solver:
         desc.use_graphs = o.use_graphs
         desc.certified_skip = o.certified_skip
         desc.max_levels = o.max_levels
+        desc.nu_tight = o.nu_tight
 
     @classmethod
     def from_instance(cls, inst, options: Optional[Options] = None):

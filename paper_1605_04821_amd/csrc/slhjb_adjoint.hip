@@ -52,60 +52,96 @@ __device__ __forceinline__ bool deep_a(const LevelDev &g, const int ix[3]) {
     return ok;
 }
 
-// ---- columns of L where the control is uniform over the stencil window ------------------------------
+// ---- columns of L whose stencil window holds few controls ------------------------------------------
 
+constexpr int kWinMax = 4;  // controls a window may hold for the matrix-free transposed gather
+
+// tset[5 T .. 5 T + 4] = {n, k_0 < k_1 < ...}: the n <= kWinMax distinct controls of tile T when all its
+// nodes are interior and untruncated, else n = -1
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_tile_code(LevelDev g, const int16_t *__restrict__ alpha, int K,
-                                                      int32_t *__restrict__ code) {
-    __shared__ int smin, smax;
-    if (threadIdx.x == 0) {
-        smin = 0x7fffffff;
-        smax = -1;
-    }
-    __syncthreads();
+__global__ __launch_bounds__(kBlock) void k_tile_set(LevelDev g, const int16_t *__restrict__ alpha, int K,
+                                                     int32_t *__restrict__ tset) {
+    __shared__ int smin;
     int ix[3];
     const int j = tile_node_a<DIM>(g, ix);
     const bool ok = j >= 0 && interior_a<DIM>(g, ix) && deep_a<DIM>(g, ix);
     const int k = ok ? (int)alpha[j] : -1;
-    const int all = __syncthreads_and(ok ? 1 : 0);
-    if (ok) {
-        atomicMin(&smin, k);
-        atomicMax(&smax, k);
+    const int all = __syncthreads_and((ok && k >= 0 && k < K) ? 1 : 0);
+    int32_t *out = tset + (int64_t)remap_block_a(blockIdx.x, gridDim.x) * (1 + kWinMax);
+    if (!all) {
+        if (threadIdx.x == 0) out[0] = -1;
+        return;
     }
-    __syncthreads();
-    if (threadIdx.x == 0)
-        code[remap_block_a(blockIdx.x, gridDim.x)] = (all && smin == smax && smin >= 0 && smin < K) ? smin : -1;
+    int n = 0, last = -1;
+    for (int it = 0; it <= kWinMax; ++it) {
+        if (threadIdx.x == 0) smin = 0x7fffffff;
+        __syncthreads();
+        if (k > last) atomicMin(&smin, k);
+        __syncthreads();
+        const int m = smin;
+        __syncthreads();
+        if (m == 0x7fffffff) break;
+        if (it == kWinMax) {
+            n = -1;  // more controls than a window may hold
+            break;
+        }
+        if (threadIdx.x == 0) out[1 + n] = m;
+        ++n;
+        last = m;
+    }
+    if (threadIdx.x == 0) out[0] = n;
 }
 
-void launch_tile_code(int dim, const LevelDev &g, const int16_t *alpha, int K, int32_t *code, hipStream_t s) {
+void launch_tile_set(int dim, const LevelDev &g, const int16_t *alpha, int K, int32_t *tset, hipStream_t s) {
     if (dim == 2)
-        hipLaunchKernelGGL(k_tile_code<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, alpha, K, code);
+        hipLaunchKernelGGL(k_tile_set<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, alpha, K, tset);
     else
-        hipLaunchKernelGGL(k_tile_code<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, alpha, K, code);
+        hipLaunchKernelGGL(k_tile_set<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, alpha, K, tset);
 }
 
-__global__ __launch_bounds__(kBlock) void k_window_code(LevelDev g, const int32_t *__restrict__ code,
-                                                        int32_t *__restrict__ wflag, int rx, int ry, int rz) {
+// wset[T] = the union of tset over the tiles within the stencil reach of T (n = -1 when a tile there is
+// not all-untruncated, or when the union exceeds kWinMax); a window cut by the grid edge holds boundary
+// tiles, so a valid window is never cut
+__global__ __launch_bounds__(kBlock) void k_window_set(LevelDev g, const int32_t *__restrict__ tset,
+                                                       int32_t *__restrict__ wset, int rx, int ry, int rz) {
     const int T = blockIdx.x * blockDim.x + threadIdx.x;
     const int ntiles = g.ntx * g.nty * g.ntz;
     if (T >= ntiles) return;
     const int bx = T % g.ntx, r = T / g.ntx, by = r % g.nty, bz = r / g.nty;
-    const int k = code[T];
-    bool same = k >= 0;
-    // a window cut by the grid edge holds boundary tiles (code -1), so a uniform window is never cut
-    for (int z = max(bz - rz, 0); same && z <= min(bz + rz, g.ntz - 1); ++z)
-        for (int y = max(by - ry, 0); same && y <= min(by + ry, g.nty - 1); ++y)
-            for (int x = max(bx - rx, 0); same && x <= min(bx + rx, g.ntx - 1); ++x)
-                same = code[x + g.ntx * (y + g.nty * z)] == k;
-    wflag[T] = same ? k : -1;
+    int ks[kWinMax];
+    int n = 0;
+    bool ok = true;
+    for (int z = max(bz - rz, 0); ok && z <= min(bz + rz, g.ntz - 1); ++z)
+        for (int y = max(by - ry, 0); ok && y <= min(by + ry, g.nty - 1); ++y)
+            for (int x = max(bx - rx, 0); ok && x <= min(bx + rx, g.ntx - 1); ++x) {
+                const int32_t *t = tset + (int64_t)(x + g.ntx * (y + g.nty * z)) * (1 + kWinMax);
+                const int tn = t[0];
+                if (tn < 0) {
+                    ok = false;
+                    break;
+                }
+                for (int q = 0; ok && q < tn; ++q) {
+                    const int k = t[1 + q];
+                    bool have = false;
+                    for (int m = 0; m < n; ++m) have = have || ks[m] == k;
+                    if (have) continue;
+                    if (n == kWinMax)
+                        ok = false;
+                    else
+                        ks[n++] = k;
+                }
+            }
+    int32_t *out = wset + (int64_t)T * (1 + kWinMax);
+    out[0] = ok ? n : -1;
+    for (int m = 0; m < kWinMax; ++m) out[1 + m] = (ok && m < n) ? ks[m] : 0;
 }
 
-void launch_window_code(int dim, const LevelDev &g, const int32_t *code, int32_t *wflag, const int R[3],
-                        hipStream_t s) {
+void launch_window_set(int dim, const LevelDev &g, const int32_t *tset, int32_t *wset, const int R[3],
+                       hipStream_t s) {
     const int tw = 1 << g.tlog, th = kBlock >> g.tlog;
     const int rx = (R[0] + tw - 1) / tw, ry = (R[1] + th - 1) / th, rz = dim == 3 ? R[2] : 0;
     const int ntiles = g.ntx * g.nty * g.ntz;
-    hipLaunchKernelGGL(k_window_code, dim3((ntiles + kBlock - 1) / kBlock), dim3(kBlock), 0, s, g, code, wflag, rx,
+    hipLaunchKernelGGL(k_window_set, dim3((ntiles + kBlock - 1) / kBlock), dim3(kBlock), 0, s, g, tset, wset, rx,
                        ry, rz);
 }
 
@@ -137,8 +173,52 @@ __device__ __forceinline__ TC lt_reflect(const LevelDev &g, const StencilDev &st
     return (TC)st.inv2h * acc;
 }
 
-__device__ __forceinline__ int window_control(const TransposeView &T) {
-    return T.wflag ? T.wflag[remap_block_a(blockIdx.x, gridDim.x)] : -1;
+// the window set of this block's tile (n = -1: gather from the listing)
+struct WSet {
+    int n;
+    int k[kWinMax];
+};
+__device__ __forceinline__ WSet window_set(const TransposeView &T) {
+    WSet w;
+    w.n = -1;
+    if (!T.wset) return w;
+    const int32_t *p = T.wset + (int64_t)remap_block_a(blockIdx.x, gridDim.x) * (1 + kWinMax);
+    w.n = p[0];
+#pragma unroll
+    for (int m = 0; m < kWinMax; ++m) w.k[m] = p[1 + m];
+    return w;
+}
+
+// (L^T x)_j on a column whose stencil window holds the controls w.k[0 .. w.n): for each of them, the rows
+// that reach j are those of that control among the reflected row-stencil positions j - off - delta_c
+template <int DIM, typename TC, typename TX, typename TW>
+__device__ __forceinline__ TC lt_reflect_multi(const LevelDev &g, const StencilDev &st, const TW *__restrict__ tab,
+                                               const WSet &w, int j, const TX *__restrict__ x,
+                                               const int16_t *__restrict__ alpha, TC xj) {
+    const int s1 = (int)g.s1, s2 = (int)g.s2;
+    TC acc = (TC)0;
+    for (int m = 0; m < w.n; ++m) {
+        const int k = w.k[m];
+        const TW *fp = tab + k * st.npt;
+        for (int q = 0; q < st.npt; ++q) {
+            const TW &p = fp[q];
+            const int o = j - p.off;
+            auto at = [&](int i) { return alpha[i] == k ? (TC)x[i] : (TC)0; };
+            TC v = (TC)p.w[0] * at(o);
+            v = fma((TC)p.w[1], at(o - 1), v);
+            v = fma((TC)p.w[2], at(o - s1), v);
+            v = fma((TC)p.w[3], at(o - s1 - 1), v);
+            if (DIM == 3) {
+                v = fma((TC)p.w[4], at(o - s2), v);
+                v = fma((TC)p.w[5], at(o - s2 - 1), v);
+                v = fma((TC)p.w[6], at(o - s2 - s1), v);
+                v = fma((TC)p.w[7], at(o - s2 - s1 - 1), v);
+            }
+            acc = q < 2 * st.P ? acc + v : acc + (TC)2 * v;  // drift point weight 2
+        }
+    }
+    const TC b = (TC)(2 * st.P + (st.has_drift ? 2 : 0));  // the row's own diagonal part
+    return (TC)st.inv2h * (acc - b * xj);
 }
 
 // ---- dual numbers ---------------------------------------------------------------------------------
@@ -748,19 +828,21 @@ __global__ __launch_bounds__(kBlock) void k_apply_T_f32x(LevelDev g, StencilDev 
         y[j] = 0.0;
         return;
     }
-    const int kw = window_control(T);
+    const WSet ws = window_set(T);
     double xj = (double)x[j];
-    if (kw >= 0) {
-        const double cj = st.c ? st.c[kw] : 0.0;
-        y[j] = xj - w * (lt_reflect<DIM, double>(g, st, st.fastD, kw, j, x, xj) + cj * xj);
-        return;
-    }
     double cj = 0.0;
     if (st.c) {
         int k = alpha[j];
         cj = st.c[((unsigned)k < (unsigned)st.K) ? k : 0];
     }
-    y[j] = xj - w * (lt_gather<float>(j, T, x) + cj * xj);
+    double lt;
+    if (ws.n == 1)
+        lt = lt_reflect<DIM, double>(g, st, st.fastD, ws.k[0], j, x, xj);
+    else if (ws.n > 1)
+        lt = lt_reflect_multi<DIM, double>(g, st, st.fastD, ws, j, x, alpha, xj);
+    else
+        lt = lt_gather<float>(j, T, x);
+    y[j] = xj - w * (lt + cj * xj);
 }
 
 void launch_apply_T_f32x(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha,
@@ -795,14 +877,15 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_T32(LevelDev g, StencilDev st
         y[j] = omega * r[j] / d[j];
         return;
     }
-    const int kw = window_control(T);
+    const WSet ws = window_set(T);
     float xj = x[j];
     float lt, cj;
-    if (kw >= 0) {
-        lt = lt_reflect<DIM, float>(g, st, st.fastF, kw, j, x, xj);
-        cj = st.c ? (float)st.c[kw] : 0.0f;
+    if (ws.n == 1) {
+        lt = lt_reflect<DIM, float>(g, st, st.fastF, ws.k[0], j, x, xj);
+        cj = st.c ? (float)st.c[ws.k[0]] : 0.0f;
     } else {
-        lt = lt_gather32<PACKED>(j, (int)g.s1, T, x);
+        lt = ws.n > 1 ? lt_reflect_multi<DIM, float>(g, st, st.fastF, ws, j, x, alpha, xj)
+                      : lt_gather32<PACKED>(j, (int)g.s1, T, x);
         cj = coef32<DIM>(st, alpha, j);
     }
     float res = r[j] - (xj - theta_dt * (lt + cj * xj));
@@ -839,14 +922,15 @@ __global__ __launch_bounds__(kBlock) void k_resid_T32(LevelDev g, StencilDev st,
         y[j] = 0.0f;
         return;
     }
-    const int kw = window_control(T);
+    const WSet ws = window_set(T);
     float xj = x[j];
     float lt, cj;
-    if (kw >= 0) {
-        lt = lt_reflect<DIM, float>(g, st, st.fastF, kw, j, x, xj);
-        cj = st.c ? (float)st.c[kw] : 0.0f;
+    if (ws.n == 1) {
+        lt = lt_reflect<DIM, float>(g, st, st.fastF, ws.k[0], j, x, xj);
+        cj = st.c ? (float)st.c[ws.k[0]] : 0.0f;
     } else {
-        lt = lt_gather32<PACKED>(j, (int)g.s1, T, x);
+        lt = ws.n > 1 ? lt_reflect_multi<DIM, float>(g, st, st.fastF, ws, j, x, alpha, xj)
+                      : lt_gather32<PACKED>(j, (int)g.s1, T, x);
         cj = coef32<DIM>(st, alpha, j);
     }
     y[j] = b[j] - (xj - theta_dt * (lt + cj * xj));

@@ -108,9 +108,12 @@ struct hjb_handle {
     struct VGraph {
         const void *a0, *v, *z;
         double theta_dt;
+        int nu1, nu2;
         hipGraphExec_t exec;
     };
     std::vector<VGraph> vgraphs;
+    // sweep counts of the V-cycles of the current solve: nu1/nu2, or nu_tight for solves to the certificate
+    int nu_pre = 3, nu_post = 3;
     hipStream_t capture_stream = nullptr;
     hipEvent_t sync_ev = nullptr;  // polled to wait for small read-backs
     struct Timer {
@@ -323,6 +326,7 @@ int check_options(const hjb_desc *d) {
     if (!(d->rtol_inf > 0.0) || !(d->tau_rel >= 0.0)) return fail(HJB_EINVAL, "rtol_inf > 0 and tau_rel >= 0 required");
     if (!(d->pi_eta >= 0.0 && d->pi_eta < 1.0)) return fail(HJB_EINVAL, "pi_eta must be in [0,1)");
     if (d->max_levels < 0) return fail(HJB_EINVAL, "max_levels must be >= 0");
+    if (d->nu_tight < 0 || d->nu_tight > 16) return fail(HJB_EINVAL, "nu_tight in 0..16");
     return HJB_OK;
 }
 
@@ -375,7 +379,7 @@ void vcycle(hjb_handle *hd, const T *r0, T *z, double theta_dt) {
     }
     r[0] = r0;
     // every smoothing sweep writes the other buffer of the pair; start so that level 0 ends in z
-    int flips0 = d.nu1 + d.nu2;
+    int flips0 = hd->nu_pre + hd->nu_post;
     if (Lc == 0) flips0 = d.coarse_sweeps;
     if (flips0 % 2 == 0) {
         e[0] = z;
@@ -389,7 +393,7 @@ void vcycle(hjb_handle *hd, const T *r0, T *z, double theta_dt) {
     }
     for (int l = 0; l < Lc; ++l) {
         Level &L = hd->lev[l];
-        smooth_level<T>(hd, l, e[l], t[l], r[l], d.nu1, true, theta_dt);
+        smooth_level<T>(hd, l, e[l], t[l], r[l], hd->nu_pre, true, theta_dt);
         {
             TimedLaunch tl(hd, l == 0 ? HJB_KERNEL_MG_RESID : -1, (double)L.g.N * (3.0 * sizeof(T) + 2.0));
             launch_level_residual<T>(hd->dim, L.g, stencil(hd, l), L.alpha, e[l], r[l], t[l], theta_dt, s);
@@ -408,7 +412,7 @@ void vcycle(hjb_handle *hd, const T *r0, T *z, double theta_dt) {
     for (int l = Lc - 1; l >= 0; --l) {
         Level &L = hd->lev[l];
         launch_prolong_add<T>(hd->dim, L.g, hd->lev[l + 1].g, e[l + 1], e[l], s);
-        smooth_level<T>(hd, l, e[l], t[l], r[l], d.nu2, false, theta_dt);
+        smooth_level<T>(hd, l, e[l], t[l], r[l], hd->nu_post, false, theta_dt);
     }
 }
 
@@ -460,7 +464,8 @@ int precondition(hjb_handle *hd, const double *v, void *z, double theta_dt) {
     }
     const void *a0 = hd->lev[0].alpha;
     for (auto &g : hd->vgraphs)
-        if (g.a0 == a0 && g.v == v && g.z == z && g.theta_dt == theta_dt) {
+        if (g.a0 == a0 && g.v == v && g.z == z && g.theta_dt == theta_dt && g.nu1 == hd->nu_pre &&
+            g.nu2 == hd->nu_post) {
             HIPCHK(hipGraphLaunch(g.exec, hd->stream));
             return HJB_OK;
         }
@@ -480,7 +485,7 @@ int precondition(hjb_handle *hd, const double *v, void *z, double theta_dt) {
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(HJB_EDEVICE, "V-cycle instantiate: %s", hipGetErrorString(e));
-    hd->vgraphs.push_back({a0, v, z, theta_dt, exec});
+    hd->vgraphs.push_back({a0, v, z, theta_dt, hd->nu_pre, hd->nu_post, exec});
     HIPCHK(hipGraphLaunch(exec, hd->stream));
     return HJB_OK;
 }
@@ -775,6 +780,13 @@ int check_time(double dt, double theta) {
     return HJB_OK;
 }
 
+// V-cycle sweep counts for the next solve: solves to the certificate take nu_tight (when set)
+void set_sweeps(hjb_handle *hd, bool tight) {
+    const bool t = tight && hd->desc.nu_tight > 0;
+    hd->nu_pre = t ? hd->desc.nu_tight : hd->desc.nu1;
+    hd->nu_post = t ? hd->desc.nu_tight : hd->desc.nu2;
+}
+
 int linsolve_impl(hjb_handle *hd, const int16_t *alpha, const double *U, const double *f0, const double *f1,
                   double t_prev, double dt, double theta, double *X, double eta, int *its, double *res, bool *tight) {
     hipStream_t s = hd->stream;
@@ -782,6 +794,7 @@ int linsolve_impl(hjb_handle *hd, const int16_t *alpha, const double *U, const d
     launch_explicit(hd->dim, hd->lev[0].g, stencil(hd, 0), alpha, U, f0, f1, t_mid, (1.0 - theta) * dt, dt, hd->E,
                     hd->nb, s);
     TRY(prepare_mg(hd, alpha, theta * dt));
+    set_sweeps(hd, eta <= 0.0);
     return fgmres(hd, alpha, hd->E, X, theta * dt, eta, its, res, tight);
 }
 
@@ -890,6 +903,7 @@ void hjb_desc_default(hjb_desc *d) {
     d->use_graphs = 1;
     d->certified_skip = 1;
     d->max_levels = 2;
+    d->nu_tight = 4;
     d->stream = nullptr;
 }
 
@@ -1033,6 +1047,7 @@ int setup_impl(const hjb_desc *desc, hjb_handle **out, bool tables_only) {
         hd->nb_cap = std::max(hd->nb_cap, tiles_for(g));
     }
     select_precision(hd);
+    set_sweeps(hd, false);
     if (!tables_only) {
     STRY(dalloc(hd, (void **)&hd->E, N * 8));
     STRY(dalloc(hd, (void **)&hd->R, N * 8));
@@ -1125,7 +1140,9 @@ int hjb_set_options(hjb_handle *hd, const hjb_desc *desc) {
     d.pi_eta = desc->pi_eta;
     d.use_graphs = desc->use_graphs;
     d.certified_skip = desc->certified_skip;
+    d.nu_tight = desc->nu_tight;
     select_precision(hd);
+    set_sweeps(hd, false);
     drop_graphs(hd);
     return HJB_OK;
 }
@@ -1457,8 +1474,8 @@ int tiles_cap(const LevelDev &g0, int dim) {
 struct TransposeWork {
     int E = 0;
     TransposeBuf b{};
-    int32_t *tcode = nullptr, *wflag = nullptr;  // [tiles] uniform-window controls (constant coefficients)
-    bool wf = false;                             // wflag holds the current policy's windows
+    int32_t *tset = nullptr, *wset = nullptr;  // [5 tiles] window control sets (constant coefficients)
+    bool wf = false;                           // wset holds the current policy's windows
     std::vector<void *> mem;
     TransposeWork() = default;
     TransposeWork(const TransposeWork &) = delete;
@@ -1468,7 +1485,7 @@ struct TransposeWork {
     }
     TransposeView view() const {
         return TransposeView{b.colptr, b.rows_s,   b.vals_s,     b.ell_w,   b.ell_off,
-                             b.ell_rows, b.ell_vals, b.ell_vals32, b.ell_d16, wf ? wflag : nullptr};
+                             b.ell_rows, b.ell_vals, b.ell_vals32, b.ell_d16, wf ? wset : nullptr};
     }
     int alloc(hjb_handle *hd, int level, bool f32, bool pack) {
         const LevelDev &g = hd->lev[level].g;
@@ -1489,8 +1506,8 @@ struct TransposeWork {
                    {(void **)&b.vals_s, (size_t)n * 8}, {(void **)&b.colptr, (size_t)(nodes + 1) * 4},
                    {(void **)&b.ell_w, (size_t)ns * 4}, {(void **)&b.ell_off, (size_t)ns * 4},
                    {(void **)&b.ell_rows, (size_t)ne * 4}, {(void **)&b.ell_vals, (size_t)ne * 8},
-                   {&b.scratch, b.scratch_bytes + 256}, {(void **)&tcode, (size_t)tiles_cap(g, hd->dim) * 4},
-                   {(void **)&wflag, (size_t)tiles_cap(g, hd->dim) * 4}};
+                   {&b.scratch, b.scratch_bytes + 256}, {(void **)&tset, (size_t)tiles_cap(g, hd->dim) * 20},
+                   {(void **)&wset, (size_t)tiles_cap(g, hd->dim) * 20}};
         for (auto &r : req) {
             if (hipMalloc(r.p, r.bytes) != hipSuccess) {
                 (void)hipGetLastError();
@@ -1561,11 +1578,11 @@ struct TransposeHierarchy {
             launch_diag<double>(hd->dim, L.g, stencil(hd, (int)l), L.alpha, theta_dt, (double *)L.d64, s);
             if (f32) launch_diag<float>(hd->dim, L.g, stencil(hd, (int)l), L.alpha, theta_dt, (float *)L.d32, s);
             TRY(lev[l]->build(hd, (int)l, L.alpha));
-            // columns whose whole stencil window shares one untruncated control are gathered matrix-free
+            // columns whose stencil window holds few untruncated controls are gathered matrix-free
             lev[l]->wf = hd->desc.coef_model == HJB_COEF_CONST && !hd->desc.f_per_control;
             if (lev[l]->wf) {
-                launch_tile_code(hd->dim, L.g, L.alpha, hd->desc.K, lev[l]->tcode, s);
-                launch_window_code(hd->dim, L.g, lev[l]->tcode, lev[l]->wflag, L.reach, s);
+                launch_tile_set(hd->dim, L.g, L.alpha, hd->desc.K, lev[l]->tset, s);
+                launch_window_set(hd->dim, L.g, lev[l]->tset, lev[l]->wset, L.reach, s);
             }
         }
         return HJB_OK;
@@ -1603,7 +1620,7 @@ void vcycle_T(hjb_handle *hd, const TransposeHierarchy &H, const T *r0, T *z, do
         r[l] = (const T *)(F ? hd->lev[l].r32 : hd->lev[l].r64);
     }
     r[0] = r0;
-    int flips0 = Lc == 0 ? d.coarse_sweeps : d.nu1 + d.nu2;
+    int flips0 = Lc == 0 ? d.coarse_sweeps : hd->nu_pre + hd->nu_post;
     if (flips0 % 2 == 0) {
         e[0] = z;
     } else {
@@ -1616,7 +1633,7 @@ void vcycle_T(hjb_handle *hd, const TransposeHierarchy &H, const T *r0, T *z, do
     }
     for (int l = 0; l < Lc; ++l) {
         Level &L = hd->lev[l];
-        smooth_T<T>(hd, H, l, e[l], t[l], r[l], d.nu1, true, theta_dt);
+        smooth_T<T>(hd, H, l, e[l], t[l], r[l], hd->nu_pre, true, theta_dt);
         if constexpr (F)
             launch_resid_T32(hd->dim, L.g, stencil(hd, l), L.alpha, H.lev[l]->view(), e[l], r[l], theta_dt, t[l], s);
         else
@@ -1627,7 +1644,7 @@ void vcycle_T(hjb_handle *hd, const TransposeHierarchy &H, const T *r0, T *z, do
     smooth_T<T>(hd, H, Lc, e[Lc], t[Lc], r[Lc], d.coarse_sweeps, true, theta_dt);
     for (int l = Lc - 1; l >= 0; --l) {
         launch_prolong_add<T>(hd->dim, hd->lev[l].g, hd->lev[l + 1].g, e[l + 1], e[l], s);
-        smooth_T<T>(hd, H, l, e[l], t[l], r[l], d.nu2, false, theta_dt);
+        smooth_T<T>(hd, H, l, e[l], t[l], r[l], hd->nu_post, false, theta_dt);
     }
 }
 
@@ -1671,6 +1688,7 @@ int solve_transposed(hjb_handle *hd, TransposeHierarchy &H, const int16_t *alpha
         };
     }
     bool tight = false;
+    set_sweeps(hd, true);
     return fgmres_core(hd, op, mu, 0.0, its, res, &tight);
 }
 

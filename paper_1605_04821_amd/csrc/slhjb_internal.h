@@ -237,16 +237,18 @@ struct TransposeView {
     const double *ell_vals;
     const float *ell_vals32;
     const int16_t *ell_d16;
-    // optional, per tile: the control shared by every node within the stencil reach of the tile (all
-    // untruncated, constant coefficients), else -1.  There column j of L is the row stencil reflected
-    // (entries w_c at j - off - delta_c), so the kernels gather it without the listing.
-    const int32_t *wflag;
+    // optional, per tile, 5 entries: {n, k_0..k_3}, the n <= 4 controls found within the stencil reach of
+    // the tile when every node there is untruncated (constant coefficients), else n = -1.  There column j
+    // of L is gathered from the row stencils reflected (entries w_c at j - off - delta_c, of the rows whose
+    // control is the stencil's), without the listing.
+    const int32_t *wset;
 };
-// code[tile] = the control of all nodes of the tile when they are interior and untruncated, else -1
-void launch_tile_code(int dim, const LevelDev &g, const int16_t *alpha, int K, int32_t *code, hipStream_t s);
-// wflag[T] = code of T when every tile within R[a] nodes along each axis has the same code, else -1
-void launch_window_code(int dim, const LevelDev &g, const int32_t *code, int32_t *wflag, const int R[3],
-                        hipStream_t s);
+// tset[5 T ..] = {n, controls} of tile T when all its nodes are interior and untruncated and it holds at
+// most 4 controls, else n = -1
+void launch_tile_set(int dim, const LevelDev &g, const int16_t *alpha, int K, int32_t *tset, hipStream_t s);
+// wset[5 T ..] = union of tset over the tiles within R[a] nodes of T along each axis (n = -1 if invalid)
+void launch_window_set(int dim, const LevelDev &g, const int32_t *tset, int32_t *wset, const int R[3],
+                       hipStream_t s);
 int build_transpose(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, int E, TransposeBuf &b,
                     hipStream_t s);
 size_t transpose_scratch_bytes(int64_t n, int N, int nslices);

@@ -103,20 +103,28 @@ def test_adjoint_matches_oracle(slhjb, name, mk, precision, precond):
     _check_adjoint(slhjb, name, mk(), precision, precond)
 
 
+def test_adjoint_deep_hierarchy_65(slhjb):
+    """The transposed V-cycle over the full hierarchy (65, 33, 17) in both precisions."""
+    inst = workloads.config_c2(65, n_cn=4)
+    for precision in (0, 1):
+        _check_adjoint(slhjb, "c2_65_deep", inst, precision, 2, max_levels=0)
+
+
 def test_adjoint_uniform_windows_129(slhjb):
     """At 129^2 many tiles lie inside regions of one control, where the mixed mode gathers the transposed
     columns matrix-free (the row stencil reflected); the gradients still match the oracle's."""
     _check_adjoint(slhjb, "c2_129_cn", workloads.config_c2(129, n_cn=4), 1, 2)
 
 
-def _check_adjoint(slhjb, name, inst, precision, precond):
+def _check_adjoint(slhjb, name, inst, precision, precond, max_levels=2):
     log(f"adjoint {name} n={inst.n} steps={len(inst.dts)} precision={precision} precond={precond}")
     s = S_TEST
     ref_march = oracle.march(inst, s=s, keep_policies=True)
     pols = ref_march["policies"]
     lam = _lam_N(inst, ref_march["U"])
     ref = oracle.adjoint_dense(inst, pols, lam, s=s)
-    solver = slhjb.Solver.from_instance(inst, slhjb.Options(precision=precision, precond=precond))
+    solver = slhjb.Solver.from_instance(inst, slhjb.Options(precision=precision, precond=precond,
+                                                            max_levels=max_levels))
     dg = torch.empty(inst.N, dtype=torch.float64, device="cuda")
     df0, df1 = torch.empty_like(dg), torch.empty_like(dg)
     ds, st = solver.adjoint(to_dev(inst.g), to_dev(inst.psi), to_dev(inst.f0), to_dev(inst.f1), inst.dts,

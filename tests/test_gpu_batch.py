@@ -65,11 +65,11 @@ def _run_batch(slhjb, insts, opts):
     return out, pols, st
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_batch_matches_oracle_and_single(slhjb, precision):
+@pytest.mark.parametrize("precision,max_levels", [(0, 2), (1, 2), (1, 0)], ids=["fp64", "mixed", "mixed-deep"])
+def test_batch_matches_oracle_and_single(slhjb, precision, max_levels):
     insts = _batch_2d()
-    log(f"batch of {len(insts)} 2D instances, precision={precision}")
-    opts = slhjb.Options(precision=precision)
+    log(f"batch of {len(insts)} 2D instances, precision={precision}, max_levels={max_levels}")
+    opts = slhjb.Options(precision=precision, max_levels=max_levels)
     Ub, pb, st = _run_batch(slhjb, insts, opts)
     for b, inst in enumerate(insts):
         ref = oracle.march(inst, keep_policies=True)

@@ -177,10 +177,12 @@ def test_march_c1(slhjb):
     log(f"  policy mismatches (near-ties) = {mism}")
 
 
+@pytest.mark.parametrize("max_levels", [2, 0], ids=["two-level", "deep"])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_march_c2_small(slhjb, precision):
+def test_march_c2_small(slhjb, precision, max_levels):
+    """65^2 Crank-Nicolson march: the default two-level hierarchy and the full one (65, 33, 17)."""
     inst = workloads.config_c2(65, n_cn=8)
-    rel, mism = _march_compare(slhjb, inst, slhjb.Options(precision=precision))
+    rel, mism = _march_compare(slhjb, inst, slhjb.Options(precision=precision, max_levels=max_levels))
     log(f"  policy mismatches (near-ties) = {mism}")
 
 
@@ -208,7 +210,8 @@ def test_march_xscaled_ragged(slhjb):
     _march_compare(slhjb, inst, slhjb.Options(precision=1))
 
 
-def test_vcycle_graph_replays_match_eager(slhjb):
+@pytest.mark.parametrize("max_levels", [2, 0], ids=["two-level", "deep"])
+def test_vcycle_graph_replays_match_eager(slhjb, max_levels):
     """Replayed V-cycle graphs launch the same kernels as the eager path: every replay must give the
     eager result bit for bit, also with eager work and synchronisations between replays."""
     inst = workloads.config_c2(129)
@@ -220,7 +223,8 @@ def test_vcycle_graph_replays_match_eager(slhjb):
     args = (to_dev(alpha), to_dev(U), to_dev(inst.f0), to_dev(inst.f1), 0.1, 1.0 / 64, 0.5, 1.0)
     outs = []
     for use_graphs in (0, 1, 1, 1):
-        solver = slhjb.Solver.from_instance(inst, slhjb.Options(precision=1, use_graphs=use_graphs))
+        solver = slhjb.Solver.from_instance(inst, slhjb.Options(precision=1, use_graphs=use_graphs,
+                                                                max_levels=max_levels))
         for rep in range(2):
             dX = to_dev(V0)
             st = solver.linsolve(*args, dX)

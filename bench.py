@@ -7,8 +7,9 @@ One benchmark step is one time step: policy iteration (fused policy sweeps) alte
 FGMRES solves preconditioned by the multigrid V-cycle, each step certified to |r|_inf <= 1e-13|U|.
 
 Modes: "mixed" (FP32 V-cycle under FP64 FGMRES; the headline value) and "fp64" (everything FP64).
-Prints one JSON line.  A kernel-timer pass inside the timed region gives the roofline of the
-dominant kernel; the CPU oracle is timed on a bounded sample (see cpu_baseline.sample).  The
+Prints one JSON line.  Kernel timers inside the timed region give the roofline of the dominant
+kernel: HIP events stamped by the dispatches themselves, on one V-cycle in TIMER_PERIOD (which runs
+eagerly; the others replay their captured graphs) and one launch in TIMER_PERIOD of the other classes; the CPU oracle is timed on a bounded sample (see cpu_baseline.sample).  The
 "adjoint" entries time one full forward march and the discrete adjoint march after it (gradients
 with respect to f0, f1, g and s) on the 513^2 adjoint workload and on the benchmark grid; the
 "batch" entry times 64 uneven two-asset instances solved as one batch and one after another.
@@ -27,6 +28,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+TIMER_PERIOD = 8               # kernel timers sample one V-cycle / launch in this many
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 
 
@@ -80,6 +82,7 @@ def run_mode(slhjb, inst, torch, mode, steps, warmup, args):
         Ua, Ub, Uc = Ub, Uc, Ua
     for k in slhjb.KERNEL_NAMES:
         solver.profile_enable(k, 20000)
+    solver.profile_sample(TIMER_PERIOD)
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()

@@ -260,13 +260,15 @@ int hjb_set_tile_width(hjb_handle *hd, int32_t width);
 int hjb_autotune(hjb_handle *hd, const char *cache_path, int32_t *tile_width_out, double *cost_ms_out);
 
 /* Kernel timers.  Any caller that wants the duration of one class of kernel launches during real work
-   (e.g. a benchmark's roofline) enables a timer; each launch of that class is then bracketed by HIP events
-   on the handle's stream (at most max_launches launches are recorded; enable again to reset).
+   (e.g. a benchmark's roofline) enables a timer; launches of that class then carry HIP events on the
+   handle's stream, stamped with the dispatch's own begin and end (hipExtLaunchKernel), at most
+   max_launches of them (enable again to reset).
    hjb_profile_read synchronises the stream and reports the recorded launches, their summed duration in
    milliseconds, their summed algorithmic bytes (each input element read once, each output written
    once; halo re-reads of gathered stencil points are not counted) and, for the policy search, their
    summed algorithmic FP64 operations on interior nodes (untruncated stencil arithmetic; 0 otherwise).
-   Enabling a timer of the smoother or the multigrid residual makes V-cycles launch eagerly. */
+   The smoother and multigrid-residual timers record the launches of sampled V-cycles, which run without
+   their captured graph; see hjb_profile_sample. */
 enum {
     HJB_KERNEL_APPLY = 0,     /* y = A^alpha z in FGMRES (FP64 out; z FP64 or FP32) */
     HJB_KERNEL_SMOOTH = 1,    /* damped Jacobi sweep with stencil gathers on the finest level */
@@ -279,6 +281,13 @@ enum {
 int hjb_profile_enable(hjb_handle *hd, int32_t kernel, int32_t max_launches);
 int hjb_profile_read(hjb_handle *hd, int32_t kernel, int64_t *launches, double *total_ms, double *total_bytes,
                      double *total_flops);
+
+/* Timer sampling: with period p >= 1, one V-cycle in p is sampled (launched eagerly, its finest-level
+   smoother and residual launches timed) while the others replay their captured graph untimed, and one
+   launch in p of each other enabled class is timed.  p = 1 (the default) times every launch and runs
+   every V-cycle eagerly while a smoother or residual timer is enabled.  Results do not depend on p.
+   Returns HJB_EINVAL for p outside 1..1000000. */
+int hjb_profile_sample(hjb_handle *hd, int32_t period);
 
 /* Free the handle and its device workspace (NULL is ignored). */
 void hjb_destroy(hjb_handle *hd);

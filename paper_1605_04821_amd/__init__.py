@@ -25,7 +25,7 @@ PRECOND_NONE, PRECOND_JACOBI, PRECOND_VCYCLE = 0, 1, 2
 
 EXPORTED = ["hjb_desc_default", "hjb_setup", "hjb_set_stream", "hjb_set_options", "hjb_policy_sweep", "hjb_apply",
             "hjb_linsolve", "hjb_step", "hjb_solve", "hjb_adjoint", "hjb_apply_transposed", "hjb_profile_enable",
-            "hjb_profile_read", "hjb_destroy", "hjb_last_error", "hjb_setup_batch", "hjb_batch_layout",
+            "hjb_profile_read", "hjb_profile_sample", "hjb_destroy", "hjb_last_error", "hjb_setup_batch", "hjb_batch_layout",
             "hjb_batch_set_stream", "hjb_solve_batch", "hjb_destroy_batch", "hjb_set_tile_width", "hjb_autotune"]
 KERNEL_APPLY, KERNEL_SMOOTH, KERNEL_MG_RESID, KERNEL_DOT, KERNEL_AXPY, KERNEL_SWEEP = range(6)
 KERNEL_NAMES = {KERNEL_APPLY: "apply", KERNEL_SMOOTH: "smooth", KERNEL_MG_RESID: "mg_residual",
@@ -102,6 +102,7 @@ def _load():
     L.hjb_autotune.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i32), ctypes.POINTER(d)]
     L.hjb_profile_enable.argtypes = [vp, i32, i32]
     L.hjb_profile_read.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d)]
+    L.hjb_profile_sample.argtypes = [vp, i32]
     L.hjb_destroy.argtypes = [vp]
     L.hjb_destroy.restype = None
     L.hjb_last_error.argtypes = []
@@ -320,6 +321,10 @@ class Solver:
     def profile_enable(self, kernel: int, max_launches: int = 4096):
         self._sync_stream()
         _check(_lib.hjb_profile_enable(self._h, int(kernel), int(max_launches)))
+
+    def profile_sample(self, period: int):
+        """Time one V-cycle (and one launch of each other class) in `period`; 1 times every launch."""
+        _check(_lib.hjb_profile_sample(self._h, int(period)))
 
     def profile_read(self, kernel: int):
         """(launches, total_ms, algorithmic_bytes, algorithmic_flops) recorded since profile_enable."""

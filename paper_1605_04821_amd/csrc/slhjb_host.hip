@@ -47,6 +47,13 @@ int fail(int code, const char *fmt, ...) {
     return code;
 }
 
+// Slots of the small device/host scalar arrays (dvals, hpin): [0, 16) solver scalars, [128, 128 + m) the
+// FGMRES update coefficients, 200 the adjoint gradient term, and the two Gram-Schmidt passes of one
+// Arnoldi step from kGsSlot0 and kGsSlot1 (m + 2 each).
+constexpr int kGsSlot0 = 256, kGsSlot1 = kGsSlot0 + kMaxRestart + 2;
+constexpr int kSmallSlots = 512;
+static_assert(kGsSlot1 + kMaxRestart + 2 <= kSmallSlots, "small-slot layout");
+
 #define HIPCHK(call)                                                                         \
     do {                                                                                     \
         hipError_t _e = (call);                                                              \
@@ -98,9 +105,9 @@ struct hjb_handle {
     int16_t *a0 = nullptr, *a1 = nullptr, *acarry = nullptr;
     double *Q = nullptr;        // [K][blocks][kBlock] explicit part of G for the searches of one step (or null)
     double *partial = nullptr;  // >= max(3*nb, (m+2)*nbd)
-    double *dvals = nullptr;    // device scalars / small vectors [256]
+    double *dvals = nullptr;    // device scalars / small vectors [512]
     int64_t *ipartial = nullptr, *ival = nullptr;
-    double *hpin = nullptr;     // pinned host mirror of small results [256]
+    double *hpin = nullptr;     // pinned host mirror of small results [512]
     int64_t *hpin_i = nullptr;
     std::vector<void *> allocs;
     bool trace = false;  // SLHJB_TRACE=1: policy-iteration progress on stderr
@@ -120,12 +127,17 @@ struct hjb_handle {
         int cap = 0, used = 0;
         std::vector<hipEvent_t> ev;  // 2*cap events
         std::vector<double> bytes, flops;
+        int64_t calls = 0;  // launches seen since enabled (sampling of the non-V-cycle classes)
     } timers[HJB_KERNEL_COUNT];
+    int sample_period = 1;   // time one unit in sample_period (hjb_profile_sample)
+    int64_t vc_count = 0;    // V-cycles since the V-cycle timers were enabled
+    bool vc_timed = false;   // the V-cycle being launched is a sampled one
 };
 
 namespace {
 
-// bracket one launch of kernel class `id` with events when its timer is enabled
+// time the one kernel launched in this scope (class `id`) when its timer is enabled: the launch stamps
+// the slot's events with the dispatch's begin and end
 struct TimedLaunch {
     hjb_handle *hd;
     int id;
@@ -133,15 +145,20 @@ struct TimedLaunch {
     TimedLaunch(hjb_handle *h, int i, double bytes, double flops = 0.0) : hd(h), id(i) {
         if (id < 0) return;
         auto &T = hd->timers[id];
-        if (T.used < T.cap) {
+        if (T.used >= T.cap) return;
+        const bool in_vcycle = id == HJB_KERNEL_SMOOTH || id == HJB_KERNEL_MG_RESID;
+        if (in_vcycle ? hd->vc_timed : (T.calls++ % hd->sample_period == 0)) {
             slot = T.used++;
             T.bytes[slot] = bytes;
             T.flops[slot] = flops;
-            (void)hipEventRecord(T.ev[2 * slot], hd->stream);
+            g_launch_events = LaunchEvents{T.ev[2 * slot], T.ev[2 * slot + 1]};
         }
     }
     ~TimedLaunch() {
-        if (slot >= 0) (void)hipEventRecord(hd->timers[id].ev[2 * slot + 1], hd->stream);
+        if (slot >= 0 && g_launch_events.start) {  // the scope launched no kernel: drop the slot
+            g_launch_events = LaunchEvents{};
+            --hd->timers[id].used;
+        }
     }
 };
 
@@ -454,12 +471,15 @@ void drop_graphs(hjb_handle *hd) {
 
 // z = M^{-1} v.  The V-cycle's launch sequence depends only on buffer addresses and theta*dt, so it is
 // captured once per (level-0 policy buffer, v, z, theta*dt) and replayed; policy, diagonal and table
-// contents are refreshed in place before each replay.  Timers on the smoother kernels force the
-// eager path (events cannot be accumulated from inside a replayed graph).
+// contents are refreshed in place before each replay.  A V-cycle sampled by the smoother or residual
+// timers runs eagerly (events cannot be accumulated from inside a replayed graph).
 int precondition(hjb_handle *hd, const double *v, void *z, double theta_dt) {
-    bool timed = hd->timers[HJB_KERNEL_SMOOTH].cap > 0 || hd->timers[HJB_KERNEL_MG_RESID].cap > 0;
-    if (!hd->desc.use_graphs || hd->desc.precond != HJB_PRECOND_VCYCLE || timed) {
+    const bool timers = hd->timers[HJB_KERNEL_SMOOTH].cap > 0 || hd->timers[HJB_KERNEL_MG_RESID].cap > 0;
+    const bool sampled = timers && hd->vc_count++ % hd->sample_period == 0;
+    if (!hd->desc.use_graphs || hd->desc.precond != HJB_PRECOND_VCYCLE || sampled) {
+        hd->vc_timed = sampled;
         precondition_eager(hd, v, z, theta_dt);
+        hd->vc_timed = false;
         return HJB_OK;
     }
     const void *a0 = hd->lev[0].alpha;
@@ -561,39 +581,45 @@ int fgmres_core(hjb_handle *hd, const KrylovOp &op, double *X, double eta, int *
             void *zj = none ? (void *)vj : (void *)((char *)hd->Zb + (int64_t)j * N * zsz);
             if (!none) TRY(op.precond(vj, zj));
             op.apply(zj, zf, w);
-            // classical Gram-Schmidt: one pass for <w,V_i> and |w|^2, one for the update and normalisation
-            // (norm by Pythagoras); a second pass when cancellation is severe
-            double hn = 0.0;
+            // classical Gram-Schmidt run twice (CGS2): each pass forms <w,V_i> and |w|^2 in one sweep, then
+            // subtracts and normalises in another (norm by Pythagoras).  A strong preconditioner makes w
+            // nearly parallel to v_j, so the second pass is needed almost every time; both passes are
+            // queued before the host reads their coefficients, one synchronisation per iteration.
             for (int pass = 0; pass < 2; ++pass) {
+                double *c = dv + (pass == 0 ? kGsSlot0 : kGsSlot1);
                 {
                     TimedLaunch tl(hd, HJB_KERNEL_DOT, (double)N * 8.0 * (j + 2));
                     launch_multidot(w, V, N, j + 1, N, hd->partial, hd->nbd, s);
                 }
-                launch_reduce_sum(hd->partial, j + 2, hd->nbd, dv + 16, s);
+                launch_reduce_sum(hd->partial, j + 2, hd->nbd, c, s);
                 {
                     TimedLaunch tl(hd, HJB_KERNEL_AXPY, (double)N * 8.0 * (j + 3));
-                    launch_multiaxpy_scale(w, V, N, j + 1, dv + 16, N, hd->nbd, s);
+                    launch_multiaxpy_scale(w, V, N, j + 1, c, N, hd->nbd, s);
                 }
-                HIPCHK(hipMemcpyAsync(hp + 16, dv + 16, (size_t)(j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
-                TRY(wait_stream(hd));
-                double w2 = hp[16 + j + 1], h2 = 0.0;
-                for (int i = 0; i <= j; ++i) h2 += hp[16 + i] * hp[16 + i];
+            }
+            HIPCHK(hipMemcpyAsync(hp + kGsSlot0, dv + kGsSlot0, (size_t)(kGsSlot1 - kGsSlot0 + j + 2) * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
+            TRY(wait_stream(hd));
+            double hn = 0.0;
+            bool dependent = false;
+            for (int pass = 0; pass < 2; ++pass) {
+                const double *c = hp + (pass == 0 ? kGsSlot0 : kGsSlot1);
+                double w2 = c[j + 1], h2 = 0.0;
+                for (int i = 0; i <= j; ++i) h2 += c[i] * c[i];
                 double hn2 = w2 - h2;
                 double sc = hn2 > 0.0 ? sqrt(hn2) : 1.0;  // the factor the kernel divided by
                 if (!isfinite(w2)) return fail(HJB_ENONFINITE, "non-finite Arnoldi vector");
                 if (pass == 0) {
-                    for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hp[16 + i];
+                    for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = c[i];
                     hn = sc;
+                    if (w2 == 0.0) dependent = true;
                 } else {
-                    for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += hp[16 + i] * hn;
+                    for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += c[i] * hn;
                     hn = hn * sc;
-                }
-                if (hn2 > 0.25 * w2) break;
-                if (w2 == 0.0 || (pass == 1 && !(hn2 > 0.0))) {
-                    hn = 0.0;  // w lies in the span of the basis: the Krylov space holds the solution
-                    break;
+                    if (!(hn2 > 0.0)) dependent = true;
                 }
             }
+            if (dependent) hn = 0.0;  // w lies in the span of the basis: the Krylov space holds the solution
             H[(size_t)(j + 1) * m + j] = hn;
             ++its;
             // apply previous rotations to column j, then a new one
@@ -1084,7 +1110,7 @@ int setup_impl(const hjb_desc *desc, hjb_handle **out, bool tables_only) {
     }
     size_t np = tables_only ? 16 : std::max<size_t>(3 * (size_t)hd->nb_cap, (size_t)(kMaxRestart + 2) * hd->nbd);
     STRY(dalloc(hd, (void **)&hd->partial, np * 8));
-    STRY(dalloc(hd, (void **)&hd->dvals, 256 * 8));
+    STRY(dalloc(hd, (void **)&hd->dvals, kSmallSlots * 8));
     STRY(dalloc(hd, (void **)&hd->ipartial, (size_t)hd->nb_cap * 8));
     STRY(dalloc(hd, (void **)&hd->ival, 64));
     if (!hd->c.empty()) {
@@ -1093,7 +1119,7 @@ int setup_impl(const hjb_desc *desc, hjb_handle **out, bool tables_only) {
         if (e != hipSuccess) return cleanup_fail(fail(HJB_EDEVICE, "%s", hipGetErrorString(e)));
     }
     {
-        hipError_t e = hipHostMalloc((void **)&hd->hpin, 256 * sizeof(double), hipHostMallocDefault);
+        hipError_t e = hipHostMalloc((void **)&hd->hpin, kSmallSlots * sizeof(double), hipHostMallocDefault);
         if (e != hipSuccess) return cleanup_fail(fail(HJB_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e)));
         e = hipHostMalloc((void **)&hd->hpin_i, 8 * sizeof(int64_t), hipHostMallocDefault);
         if (e != hipSuccess) return cleanup_fail(fail(HJB_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e)));
@@ -1271,6 +1297,15 @@ int hjb_profile_enable(hjb_handle *hd, int32_t kernel, int32_t max_launches) {
     T.flops.assign((size_t)max_launches, 0.0);
     T.cap = max_launches;
     T.used = 0;
+    T.calls = 0;
+    if (kernel == HJB_KERNEL_SMOOTH || kernel == HJB_KERNEL_MG_RESID) hd->vc_count = 0;
+    return HJB_OK;
+}
+
+int hjb_profile_sample(hjb_handle *hd, int32_t period) {
+    if (!hd) return fail(HJB_EINVAL, "null handle");
+    if (period < 1 || period > 1000000) return fail(HJB_EINVAL, "sampling period in 1..1000000");
+    hd->sample_period = period;
     return HJB_OK;
 }
 

@@ -2,6 +2,7 @@
 // Not part of the public C ABI (include/slhjb.h).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -13,6 +14,30 @@ constexpr int kBlock = 256;              // threads per block of the node-parall
 constexpr int kMaxRestart = 64;
 constexpr int kTileLog2 = 5;             // default node tile of one block: 32 x 8 (width 2^kTileLog2)
 constexpr int kTileLogMin = 4, kTileLogMax = 7;  // tile widths 16 ... 128 (heights 16 ... 2)
+
+// Start and stop events for the next timed kernel launch.  A host timer scope sets them; the launcher
+// of that kernel hands them to hipExtLaunchKernel, which stamps them with the dispatch's own begin and
+// end times, so no marker packets sit between the timed kernel and its neighbours.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local LaunchEvents g_launch_events;
+
+inline LaunchEvents take_launch_events() {
+    LaunchEvents e = g_launch_events;
+    g_launch_events = LaunchEvents{};
+    return e;
+}
+
+// Launch that consumes the pending timer events, if any (plain launch otherwise).
+#define SLHJB_LAUNCH(kernel, grid, block, shmem, stream, ...)                                               \
+    do {                                                                                                    \
+        const ::slhjb::LaunchEvents ev_ = ::slhjb::take_launch_events();                                    \
+        if (ev_.start)                                                                                      \
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, ev_.start, ev_.stop, 0u, __VA_ARGS__); \
+        else                                                                                                \
+            hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                            \
+    } while (0)
 
 // One stencil point of one control on one grid level.  Y is the displacement in cells of that level
 // (diffusion: s*sigma_p/sqrt(h) scaled to the level, drift: b scaled to the level).  The remaining

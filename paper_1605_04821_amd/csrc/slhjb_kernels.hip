@@ -25,6 +25,8 @@
 
 namespace slhjb {
 
+thread_local LaunchEvents g_launch_events;
+
 int blocks_for(int64_t N) { return (int)((N + kBlock - 1) / kBlock); }
 
 
@@ -289,11 +291,11 @@ void launch_sweep_dim(const LevelDev &g, const StencilDev &st, const double *X, 
 #define SW(C, E, QQ)                                                                                                  \
     do {                                                                                                              \
         if (pn)                                                                                                       \
-            hipLaunchKernelGGL((k_sweep<DIM, C, E, QQ, true>), dim3(grid), dim3(kBlock), 0, s, g, st, X, U, f0, f1,  \
-                               t_mid, theta, tau, a_in, o, Q);                                                       \
+            SLHJB_LAUNCH((k_sweep<DIM, C, E, QQ, true>), dim3(grid), dim3(kBlock), 0, s, g, st, X, U, f0, f1,         \
+                         t_mid, theta, tau, a_in, o, Q);                                                              \
         else                                                                                                          \
-            hipLaunchKernelGGL((k_sweep<DIM, C, E, QQ, false>), dim3(grid), dim3(kBlock), 0, s, g, st, X, U, f0, f1, \
-                               t_mid, theta, tau, a_in, o, Q);                                                       \
+            SLHJB_LAUNCH((k_sweep<DIM, C, E, QQ, false>), dim3(grid), dim3(kBlock), 0, s, g, st, X, U, f0, f1,        \
+                         t_mid, theta, tau, a_in, o, Q);                                                              \
     } while (0)
     if (!cn) {
         if (extra) SW(false, true, 0); else SW(false, false, 0);
@@ -382,8 +384,8 @@ __global__ __launch_bounds__(kBlock) void k_apply(LevelDev g, StencilDev st0, co
 
 void launch_apply(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const void *x,
                   bool x_is_float, double *y, double theta_dt, double *norm2_partial, int nblocks, hipStream_t s) {
-#define AP(D, TX) hipLaunchKernelGGL((k_apply<D, TX>), dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, \
-                                     (const TX *)x, y, theta_dt, norm2_partial)
+#define AP(D, TX) SLHJB_LAUNCH((k_apply<D, TX>), dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, \
+                               (const TX *)x, y, theta_dt, norm2_partial)
     if (x_is_float) {
         if (dim == 2) AP(2, float); else AP(3, float);
     } else {
@@ -591,11 +593,11 @@ void launch_jacobi(int dim, const LevelDev &g, const StencilDev &st, const int16
                    const T *d, T *e_out, double theta_dt, double omega, bool first, hipStream_t s) {
     int nb = tiles_for(g);
     if (dim == 2)
-        hipLaunchKernelGGL((k_jacobi<2, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, e, r, d, e_out, (T)theta_dt,
-                           (T)omega, (int)first);
+        SLHJB_LAUNCH((k_jacobi<2, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, e, r, d, e_out, (T)theta_dt,
+                     (T)omega, (int)first);
     else
-        hipLaunchKernelGGL((k_jacobi<3, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, e, r, d, e_out, (T)theta_dt,
-                           (T)omega, (int)first);
+        SLHJB_LAUNCH((k_jacobi<3, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, e, r, d, e_out, (T)theta_dt,
+                     (T)omega, (int)first);
 }
 
 template <int DIM, typename T>
@@ -616,11 +618,11 @@ void launch_level_residual(int dim, const LevelDev &g, const StencilDev &st, con
                            const T *r, T *res, double theta_dt, hipStream_t s) {
     int nb = tiles_for(g);
     if (dim == 2)
-        hipLaunchKernelGGL((k_level_residual<2, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, e, r, res,
-                           (T)theta_dt);
+        SLHJB_LAUNCH((k_level_residual<2, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, e, r, res,
+                     (T)theta_dt);
     else
-        hipLaunchKernelGGL((k_level_residual<3, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, e, r, res,
-                           (T)theta_dt);
+        SLHJB_LAUNCH((k_level_residual<3, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, e, r, res,
+                     (T)theta_dt);
 }
 
 // full weighting: weights 1/4, 1/2, 1/4 per axis around fine node 2I
@@ -972,7 +974,7 @@ int dot_blocks(int64_t N) { return (int)((N + (int64_t)kBlock * kDotItems - 1) /
 
 void launch_multidot(const double *w, const double *V, int64_t ldv, int nvec, int64_t N, double *partial, int nblocks,
                      hipStream_t s) {
-    hipLaunchKernelGGL(k_multidot, dim3(nblocks), dim3(kBlock), 0, s, w, V, ldv, nvec, N, partial);
+    SLHJB_LAUNCH(k_multidot, dim3(nblocks), dim3(kBlock), 0, s, w, V, ldv, nvec, N, partial);
 }
 
 __global__ __launch_bounds__(kBlock) void k_multiaxpy_scale(double *__restrict__ w, const double *__restrict__ V,
@@ -1001,7 +1003,7 @@ __global__ __launch_bounds__(kBlock) void k_multiaxpy_scale(double *__restrict__
 
 void launch_multiaxpy_scale(double *w, const double *V, int64_t ldv, int nvec, const double *coef, int64_t N,
                             int nblocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_multiaxpy_scale, dim3(nblocks), dim3(kBlock), 0, s, w, V, ldv, nvec, coef, N);
+    SLHJB_LAUNCH(k_multiaxpy_scale, dim3(nblocks), dim3(kBlock), 0, s, w, V, ldv, nvec, coef, N);
 }
 
 // Reductions of per-block partials: one workgroup of kRedThreads per vector, four independent

@@ -93,6 +93,7 @@ def test_null_handle_calls_fail_cleanly(slhjb):
     st = slhjb.StepStats()
     assert L.hjb_step(None, None, None, None, None, 0.0, 0.1, 1.0, 1.0, None, None, 0.0, ctypes.byref(st)) == -1
     assert L.hjb_profile_enable(None, 0, 10) == -1
+    assert L.hjb_profile_sample(None, 4) == -1
     assert L.hjb_apply(None, None, None, None, 0.1, 1.0, 1.0) == -1
     assert L.hjb_apply_transposed(None, None, None, None, 0.1, 1.0, 1.0) == -1
     assert L.hjb_adjoint(None, None, None, None, None, 1, None, None, 1.0, None, None, None, None, None, None, None,

@@ -236,6 +236,39 @@ def test_vcycle_graph_replays_match_eager(slhjb, max_levels):
         np.testing.assert_array_equal(o, outs[0])
 
 
+@pytest.mark.parametrize("period", [1, 5])
+def test_kernel_timers_leave_results_unchanged(slhjb, period):
+    """A march with every kernel timer enabled (every launch timed, or one V-cycle and one launch per class
+    in five) gives the untimed march bit for bit, and the timers record launches of every class."""
+    inst = workloads.config_c2(129, n_cn=4)
+    log(f"kernel timers, sampling period {period}")
+    res, counts = [], None
+    for timed in (False, True):
+        solver = slhjb.Solver.from_instance(inst, slhjb.Options(precision=1))
+        if timed:
+            for k in slhjb.KERNEL_NAMES:
+                solver.profile_enable(k, 20000)
+            solver.profile_sample(period)
+        g = to_dev(inst.g)
+        U = torch.empty_like(g)
+        st = solver.solve(g, to_dev(inst.psi), to_dev(inst.f0), to_dev(inst.f1), inst.dts, inst.thetas, inst.s, U)
+        res.append((to_np(U), st.krylov_total, st.pi_total))
+        if timed:
+            counts = {name: solver.profile_read(k) for k, name in slhjb.KERNEL_NAMES.items()}
+        solver.close()
+    np.testing.assert_array_equal(res[1][0], res[0][0])
+    assert res[1][1:] == res[0][1:]
+    kry, pi = res[0][1], res[0][2]
+    log(f"  krylov {kry}, pi {pi}, timed launches " + ", ".join(f"{k} {v[0]}" for k, v in counts.items()))
+    for name, (n, ms, by, fl) in counts.items():
+        assert n > 0 and ms > 0.0 and by > 0.0, name
+    # every Arnoldi step runs one apply and two Gram-Schmidt passes; sampling keeps one in `period`
+    assert counts["apply"][0] == -(-kry // period)
+    assert counts["multidot"][0] == -(-2 * kry // period)
+    if period == 1:
+        assert counts["mg_residual"][0] == kry
+
+
 SKIP_CASES = [
     ("c2_129_cn", lambda: workloads.config_c2(129, n_cn=8)),
     ("c2_257_cn", lambda: workloads.config_c2(257, n_cn=4)),

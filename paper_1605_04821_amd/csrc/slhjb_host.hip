@@ -116,6 +116,7 @@ struct hjb_handle {
         const void *a0, *v, *z;
         double theta_dt;
         int nu1, nu2;
+        bool rhs_ready;  // the graph starts from the single-precision right-hand side already in place
         hipGraphExec_t exec;
     };
     std::vector<VGraph> vgraphs;
@@ -442,8 +443,8 @@ __global__ void k_jacobi_precond32(const double *v, const float *dg, float *z, i
     if (n < N) z[n] = (float)v[n] / dg[n];
 }
 
-// z_j = M^{-1} v_j
-void precondition_eager(hjb_handle *hd, const double *v, void *z, double theta_dt) {
+// z_j = M^{-1} v_j (mixed precision: rhs_ready = the level-0 right-hand side already holds float(v_j))
+void precondition_eager(hjb_handle *hd, const double *v, void *z, double theta_dt, bool rhs_ready) {
     const int64_t N = hd->N;
     hipStream_t s = hd->stream;
     Level &L0 = hd->lev[0];
@@ -457,7 +458,7 @@ void precondition_eager(hjb_handle *hd, const double *v, void *z, double theta_d
         return;
     }
     if (mixed(hd)) {
-        launch_to_precond(v, L0.r, true, N, s);
+        if (!rhs_ready) launch_to_precond(v, L0.r, true, N, s);
         vcycle<float>(hd, (const float *)L0.r, (float *)z, theta_dt);
     } else {
         vcycle<double>(hd, v, (double *)z, theta_dt);
@@ -473,19 +474,19 @@ void drop_graphs(hjb_handle *hd) {
 // captured once per (level-0 policy buffer, v, z, theta*dt) and replayed; policy, diagonal and table
 // contents are refreshed in place before each replay.  A V-cycle sampled by the smoother or residual
 // timers runs eagerly (events cannot be accumulated from inside a replayed graph).
-int precondition(hjb_handle *hd, const double *v, void *z, double theta_dt) {
+int precondition(hjb_handle *hd, const double *v, void *z, double theta_dt, bool rhs_ready) {
     const bool timers = hd->timers[HJB_KERNEL_SMOOTH].cap > 0 || hd->timers[HJB_KERNEL_MG_RESID].cap > 0;
     const bool sampled = timers && hd->vc_count++ % hd->sample_period == 0;
     if (!hd->desc.use_graphs || hd->desc.precond != HJB_PRECOND_VCYCLE || sampled) {
         hd->vc_timed = sampled;
-        precondition_eager(hd, v, z, theta_dt);
+        precondition_eager(hd, v, z, theta_dt, rhs_ready);
         hd->vc_timed = false;
         return HJB_OK;
     }
     const void *a0 = hd->lev[0].alpha;
     for (auto &g : hd->vgraphs)
         if (g.a0 == a0 && g.v == v && g.z == z && g.theta_dt == theta_dt && g.nu1 == hd->nu_pre &&
-            g.nu2 == hd->nu_post) {
+            g.nu2 == hd->nu_post && g.rhs_ready == rhs_ready) {
             HIPCHK(hipGraphLaunch(g.exec, hd->stream));
             return HJB_OK;
         }
@@ -496,7 +497,7 @@ int precondition(hjb_handle *hd, const double *v, void *z, double theta_dt) {
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(hd->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        precondition_eager(hd, v, z, theta_dt);
+        precondition_eager(hd, v, z, theta_dt, rhs_ready);
         e = hipStreamEndCapture(hd->capture_stream, &graph);
     }
     hd->stream = saved;
@@ -505,7 +506,7 @@ int precondition(hjb_handle *hd, const double *v, void *z, double theta_dt) {
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(HJB_EDEVICE, "V-cycle instantiate: %s", hipGetErrorString(e));
-    hd->vgraphs.push_back({a0, v, z, theta_dt, hd->nu_pre, hd->nu_post, exec});
+    hd->vgraphs.push_back({a0, v, z, theta_dt, hd->nu_pre, hd->nu_post, rhs_ready, exec});
     HIPCHK(hipGraphLaunch(exec, hd->stream));
     return HJB_OK;
 }
@@ -529,12 +530,15 @@ int sync_small(hjb_handle *hd, const void *dev, void *host, size_t bytes) {
 
 // The operator of one linear solve: residual() writes r = b - A X into hd->R with the partials
 // [sum r^2 | max|r| | max|X|] (hd->nb each) in hd->partial; apply(z, z_is_float, w) writes w = A z;
-// precond(v, z) writes z = M^{-1} v (empty: no preconditioner, z = v).
+// precond(v, z, ready) writes z = M^{-1} v (empty: no preconditioner, z = v).  When rhs32 is set, the
+// preconditioner starts from float(v) in rhs32: the solver writes that copy while forming v and passes
+// ready = true, else the preconditioner converts v itself.
 struct KrylovOp {
     std::function<void()> residual;
     std::function<void(const void *, bool, double *)> apply;
-    std::function<int(const double *, void *)> precond;
+    std::function<int(const double *, void *, bool)> precond;
     bool zf = false;
+    float *rhs32 = nullptr;
 };
 
 // Flexible GMRES(m).  Stops when |r|_inf <= rtol_inf*max(1,|X|_inf), or, when eta > 0, once
@@ -547,6 +551,7 @@ int fgmres_core(hjb_handle *hd, const KrylovOp &op, double *X, double eta, int *
     hipStream_t s = hd->stream;
     const bool none = !op.precond;
     const bool zf = !none && op.zf;
+    float *const rhs32 = none ? nullptr : op.rhs32;
     const size_t zsz = zf ? sizeof(float) : sizeof(double);
     double *V = hd->Vb;
     double *dv = hd->dvals;
@@ -571,7 +576,7 @@ int fgmres_core(hjb_handle *hd, const KrylovOp &op, double *X, double eta, int *
         if (its >= d.max_krylov)
             return fail(HJB_ENOCONV_KRYLOV, "FGMRES: |r|_inf = %.3e > %.3e after %d iterations", rinf, target, its);
         // v0 = r / beta
-        launch_scale_by_inv_sqrt(V, hd->R, dv + 0, N, s);
+        launch_scale_by_inv_sqrt(V, hd->R, dv + 0, N, s, rhs32);
         std::fill(gvec.begin(), gvec.end(), 0.0);
         gvec[0] = beta;
         int j = 0;
@@ -579,23 +584,26 @@ int fgmres_core(hjb_handle *hd, const KrylovOp &op, double *X, double eta, int *
             double *vj = V + (int64_t)j * N;
             double *w = V + (int64_t)(j + 1) * N;
             void *zj = none ? (void *)vj : (void *)((char *)hd->Zb + (int64_t)j * N * zsz);
-            if (!none) TRY(op.precond(vj, zj));
+            if (!none) TRY(op.precond(vj, zj, rhs32 != nullptr));
             op.apply(zj, zf, w);
-            // classical Gram-Schmidt run twice (CGS2): each pass forms <w,V_i> and |w|^2 in one sweep, then
-            // subtracts and normalises in another (norm by Pythagoras).  A strong preconditioner makes w
-            // nearly parallel to v_j, so the second pass is needed almost every time; both passes are
-            // queued before the host reads their coefficients, one synchronisation per iteration.
-            for (int pass = 0; pass < 2; ++pass) {
-                double *c = dv + (pass == 0 ? kGsSlot0 : kGsSlot1);
-                {
-                    TimedLaunch tl(hd, HJB_KERNEL_DOT, (double)N * 8.0 * (j + 2));
-                    launch_multidot(w, V, N, j + 1, N, hd->partial, hd->nbd, s);
-                }
-                launch_reduce_sum(hd->partial, j + 2, hd->nbd, c, s);
-                {
-                    TimedLaunch tl(hd, HJB_KERNEL_AXPY, (double)N * 8.0 * (j + 3));
-                    launch_multiaxpy_scale(w, V, N, j + 1, c, N, hd->nbd, s);
-                }
+            // classical Gram-Schmidt run twice (CGS2): the sums <w,V_i> and |w|^2, the update and
+            // normalisation (norm by Pythagoras) fused with the second pass's sums, then the second update,
+            // which also writes the single-precision copy of v_{j+1} for the next preconditioner call.  A
+            // strong preconditioner makes w nearly parallel to v_j, so the second pass is needed almost
+            // every time; both passes are queued before the host reads their coefficients.
+            {
+                TimedLaunch tl(hd, HJB_KERNEL_DOT, (double)N * 8.0 * (j + 2));
+                launch_multidot(w, V, N, j + 1, N, hd->partial, hd->nbd, s);
+            }
+            launch_reduce_sum(hd->partial, j + 2, hd->nbd, dv + kGsSlot0, s);
+            {
+                TimedLaunch tl(hd, HJB_KERNEL_AXPY, (double)N * 8.0 * (j + 3));
+                launch_multiaxpy_scale_dot(w, V, N, j + 1, dv + kGsSlot0, N, hd->partial, hd->nbd, s);
+            }
+            launch_reduce_sum(hd->partial, j + 2, hd->nbd, dv + kGsSlot1, s);
+            {
+                TimedLaunch tl(hd, HJB_KERNEL_AXPY, (double)N * (8.0 * (j + 3) + (rhs32 ? 4.0 : 0.0)));
+                launch_multiaxpy_scale(w, V, N, j + 1, dv + kGsSlot1, N, hd->nbd, s, rhs32);
             }
             HIPCHK(hipMemcpyAsync(hp + kGsSlot0, dv + kGsSlot0, (size_t)(kGsSlot1 - kGsSlot0 + j + 2) * sizeof(double),
                                   hipMemcpyDeviceToHost, s));
@@ -668,8 +676,9 @@ int fgmres(hjb_handle *hd, const int16_t *alpha, const double *E, double *X, dou
         launch_apply(dim, L0.g, st, alpha, z, zf, w, theta_dt, nullptr, hd->nb, s);
     };
     if (hd->desc.precond != HJB_PRECOND_NONE)
-        op.precond = [=](const double *v, void *z) { return precondition(hd, v, z, theta_dt); };
+        op.precond = [=](const double *v, void *z, bool ready) { return precondition(hd, v, z, theta_dt, ready); };
     op.zf = mixed(hd);
+    if (op.zf && hd->desc.precond == HJB_PRECOND_VCYCLE) op.rhs32 = (float *)L0.r;
     return fgmres_core(hd, op, X, eta, its_out, res_out, tight_out);
 }
 
@@ -1455,7 +1464,7 @@ int hjb_autotune(hjb_handle *hd, const char *cache_path, int32_t *tile_width_out
                              hd->nb, s);
             HIPCHK(hipEventRecord(ev[2], s));
             if (hd->desc.precond != HJB_PRECOND_NONE)
-                for (int q = 0; q < na; ++q) precondition_eager(hd, hd->Vb, hd->Zb, theta_dt);
+                for (int q = 0; q < na; ++q) precondition_eager(hd, hd->Vb, hd->Zb, theta_dt, false);
             HIPCHK(hipEventRecord(ev[3], s));
         }
         HIPCHK(hipEventSynchronize(ev[3]));
@@ -1704,19 +1713,20 @@ int solve_transposed(hjb_handle *hd, TransposeHierarchy &H, const int16_t *alpha
     };
     op.zf = false;
     if (hd->desc.precond == HJB_PRECOND_VCYCLE && H.f32) {
-        op.precond = [=, &H](const double *v, void *z) {
-            launch_to_precond(v, L0.r32, true, hd->N, s);
+        op.precond = [=, &H](const double *v, void *z, bool ready) {
+            if (!ready) launch_to_precond(v, L0.r32, true, hd->N, s);
             vcycle_T<float>(hd, H, (const float *)L0.r32, (float *)z, theta_dt);
             return HJB_OK;
         };
         op.zf = true;
+        op.rhs32 = (float *)L0.r32;
     } else if (hd->desc.precond == HJB_PRECOND_VCYCLE) {
-        op.precond = [=, &H](const double *v, void *z) {
+        op.precond = [=, &H](const double *v, void *z, bool) {
             vcycle_T<double>(hd, H, v, (double *)z, theta_dt);
             return HJB_OK;
         };
     } else if (hd->desc.precond == HJB_PRECOND_JACOBI) {
-        op.precond = [=](const double *v, void *z) {
+        op.precond = [=](const double *v, void *z, bool) {
             hipLaunchKernelGGL(k_jacobi_precond64, dim3(blocks_for(hd->N)), dim3(kBlock), 0, s, v,
                                (const double *)L0.d64, (double *)z, hd->N);
             return HJB_OK;

@@ -220,12 +220,17 @@ void launch_inject_policy(int dim, const LevelDev &gf, const LevelDev &gc, const
 void launch_multidot(const double *w, const double *V, int64_t ldv, int nvec, int64_t N, double *partial,
                      int nblocks, hipStream_t s);
 // w = (w - sum_v coef[v] V_v) / sqrt(coef[nvec] - sum_v coef[v]^2)  (divisor 1 if that is not positive)
+// w <- (w - sum_v coef[v] V_v) / sqrt(coef[nvec] - sum_v coef[v]^2); wf (nullable) receives float(w)
 void launch_multiaxpy_scale(double *w, const double *V, int64_t ldv, int nvec, const double *coef, int64_t N,
-                            int nblocks, hipStream_t s);
+                            int nblocks, hipStream_t s, float *wf = nullptr);
+// the same update followed by the per-block partial sums of launch_multidot on the updated w
+void launch_multiaxpy_scale_dot(double *w, const double *V, int64_t ldv, int nvec, const double *coef, int64_t N,
+                                double *partial, int nblocks, hipStream_t s);
 void launch_reduce_sum(const double *partial, int nvec, int nblocks, double *out, hipStream_t s);
 void launch_reduce_max(const double *partial, int nvec, int nblocks, double *out, hipStream_t s);
 void launch_reduce_sum_i64(const int64_t *partial, int nblocks, int64_t *out, hipStream_t s);
-void launch_scale_by_inv_sqrt(double *dst, const double *src, const double *norm2, int64_t N, hipStream_t s);
+void launch_scale_by_inv_sqrt(double *dst, const double *src, const double *norm2, int64_t N, hipStream_t s,
+                              float *dstf = nullptr);
 void launch_to_precond(const double *v, void *out, bool out_float, int64_t N, hipStream_t s);
 void launch_update_solution(double *X, const void *Z, bool z_float, int64_t ldz, int m, const double *y, int64_t N,
                             hipStream_t s);

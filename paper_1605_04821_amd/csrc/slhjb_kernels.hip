@@ -979,7 +979,7 @@ void launch_multidot(const double *w, const double *V, int64_t ldv, int nvec, in
 
 __global__ __launch_bounds__(kBlock) void k_multiaxpy_scale(double *__restrict__ w, const double *__restrict__ V,
                                                             int64_t ldv, int nvec, const double *__restrict__ coef,
-                                                            int64_t N) {
+                                                            int64_t N, float *__restrict__ wf) {
     __shared__ double c[kMaxRestart + 2];
     for (int v = threadIdx.x; v <= nvec; v += blockDim.x) c[v] = coef[v];
     __syncthreads();
@@ -996,14 +996,84 @@ __global__ __launch_bounds__(kBlock) void k_multiaxpy_scale(double *__restrict__
         if (n < N) {
             double x = w[n];
             for (int v = 0; v < nvec; ++v) x -= c[v] * V[(int64_t)v * ldv + n];
-            w[n] = x * inv;
+            x *= inv;
+            w[n] = x;
+            if (wf) wf[n] = (float)x;  // the single-precision copy the next V-cycle reads
         }
     }
 }
 
 void launch_multiaxpy_scale(double *w, const double *V, int64_t ldv, int nvec, const double *coef, int64_t N,
-                            int nblocks, hipStream_t s) {
-    SLHJB_LAUNCH(k_multiaxpy_scale, dim3(nblocks), dim3(kBlock), 0, s, w, V, ldv, nvec, coef, N);
+                            int nblocks, hipStream_t s, float *wf) {
+    SLHJB_LAUNCH(k_multiaxpy_scale, dim3(nblocks), dim3(kBlock), 0, s, w, V, ldv, nvec, coef, N, wf);
+}
+
+// The update of k_multiaxpy_scale followed by the sums of k_multidot on the updated vector, with the NV
+// basis vectors held in registers between the two: one sweep over the basis instead of two.  Block
+// decomposition, per-thread order and block reduction are those of the two kernels, so the partial sums
+// are the same numbers.
+template <int NV>
+__global__ __launch_bounds__(kBlock) void k_multiaxpy_scale_dot(double *__restrict__ w, const double *__restrict__ V,
+                                                                int64_t ldv, const double *__restrict__ coef,
+                                                                int64_t N, double *__restrict__ partial) {
+    __shared__ double c[NV + 1];
+    __shared__ double sh[kBlock / 64];
+    for (int v = threadIdx.x; v <= NV; v += blockDim.x) c[v] = coef[v];
+    __syncthreads();
+    double h2 = 0.0;
+    for (int v = 0; v < NV; ++v) h2 += c[v] * c[v];
+    const double hn2 = c[NV] - h2;
+    const double inv = hn2 > 0.0 ? 1.0 / sqrt(hn2) : 1.0;
+    const int b = remap_block(blockIdx.x, gridDim.x);
+    const int64_t base = (int64_t)b * kBlock * kDotItems + threadIdx.x;
+    double vv[NV][kDotItems], x[kDotItems];
+#pragma unroll
+    for (int q = 0; q < kDotItems; ++q) {
+        const int64_t n = base + (int64_t)q * kBlock;
+        x[q] = 0.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) vv[v][q] = 0.0;
+        if (n < N) {
+            double t = w[n];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                vv[v][q] = V[(int64_t)v * ldv + n];
+                t -= c[v] * vv[v][q];
+            }
+            x[q] = t * inv;
+            w[n] = x[q];
+        }
+    }
+    double ww = 0.0;
+#pragma unroll
+    for (int q = 0; q < kDotItems; ++q) ww += x[q] * x[q];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < kDotItems; ++q)
+            if (base + (int64_t)q * kBlock < N) acc += x[q] * vv[v][q];
+        const double t = block_reduce<double>(acc, OpSum(), sh);
+        if (threadIdx.x == 0) partial[(int64_t)v * gridDim.x + b] = t;
+    }
+    const double t = block_reduce<double>(ww, OpSum(), sh);
+    if (threadIdx.x == 0) partial[(int64_t)NV * gridDim.x + b] = t;
+}
+
+void launch_multiaxpy_scale_dot(double *w, const double *V, int64_t ldv, int nvec, const double *coef, int64_t N,
+                                double *partial, int nblocks, hipStream_t s) {
+#define MD(NV)                                                                                                  \
+    case NV:                                                                                                    \
+        SLHJB_LAUNCH(k_multiaxpy_scale_dot<NV>, dim3(nblocks), dim3(kBlock), 0, s, w, V, ldv, coef, N, partial); \
+        return
+    switch (nvec) {
+        MD(1); MD(2); MD(3); MD(4); MD(5); MD(6); MD(7); MD(8);
+        default:
+            break;
+    }
+#undef MD
+    launch_multiaxpy_scale(w, V, ldv, nvec, coef, N, nblocks, s, nullptr);
+    launch_multidot(w, V, ldv, nvec, N, partial, nblocks, s);
 }
 
 // Reductions of per-block partials: one workgroup of kRedThreads per vector, four independent
@@ -1061,15 +1131,19 @@ void launch_reduce_sum_i64(const int64_t *partial, int nblocks, int64_t *out, hi
 }
 
 __global__ __launch_bounds__(kBlock) void k_scale_by_inv_sqrt(double *__restrict__ dst, const double *__restrict__ src,
-                                                              const double *__restrict__ norm2, int64_t N) {
+                                                              const double *__restrict__ norm2, int64_t N,
+                                                              float *__restrict__ dstf) {
     int64_t n = (int64_t)remap_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (n >= N) return;
     double inv = 1.0 / sqrt(norm2[0]);
-    dst[n] = src[n] * inv;
+    const double x = src[n] * inv;
+    dst[n] = x;
+    if (dstf) dstf[n] = (float)x;
 }
 
-void launch_scale_by_inv_sqrt(double *dst, const double *src, const double *norm2, int64_t N, hipStream_t s) {
-    hipLaunchKernelGGL(k_scale_by_inv_sqrt, dim3(blocks_for(N)), dim3(kBlock), 0, s, dst, src, norm2, N);
+void launch_scale_by_inv_sqrt(double *dst, const double *src, const double *norm2, int64_t N, hipStream_t s,
+                              float *dstf) {
+    hipLaunchKernelGGL(k_scale_by_inv_sqrt, dim3(blocks_for(N)), dim3(kBlock), 0, s, dst, src, norm2, N, dstf);
 }
 
 __global__ __launch_bounds__(kBlock) void k_to_f32(const double *__restrict__ v, float *__restrict__ out, int64_t N) {

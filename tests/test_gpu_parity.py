@@ -262,9 +262,11 @@ def test_kernel_timers_leave_results_unchanged(slhjb, period):
     log(f"  krylov {kry}, pi {pi}, timed launches " + ", ".join(f"{k} {v[0]}" for k, v in counts.items()))
     for name, (n, ms, by, fl) in counts.items():
         assert n > 0 and ms > 0.0 and by > 0.0, name
-    # every Arnoldi step runs one apply and two Gram-Schmidt passes; sampling keeps one in `period`
+    # every Arnoldi step runs one apply, one multi-dot and two updates (the first fused with the second
+    # pass's sums); sampling keeps one launch in `period`
     assert counts["apply"][0] == -(-kry // period)
-    assert counts["multidot"][0] == -(-2 * kry // period)
+    assert counts["multidot"][0] == -(-kry // period)
+    assert counts["multiaxpy"][0] == -(-2 * kry // period)
     if period == 1:
         assert counts["mg_residual"][0] == kry
 

@@ -109,6 +109,8 @@ struct hjb_handle {
     int64_t *ipartial = nullptr, *ival = nullptr;
     double *hpin = nullptr;     // pinned host mirror of small results [512]
     int64_t *hpin_i = nullptr;
+    unsigned *hflag = nullptr;  // pinned host word the publish kernel releases sequence numbers into
+    unsigned pub_seq = 0;
     std::vector<void *> allocs;
     bool trace = false;  // SLHJB_TRACE=1: policy-iteration progress on stderr
     // captured V-cycles, keyed by the buffers and scalars baked into their kernel arguments
@@ -123,7 +125,6 @@ struct hjb_handle {
     // sweep counts of the V-cycles of the current solve: nu1/nu2, or nu_tight for solves to the certificate
     int nu_pre = 3, nu_post = 3;
     hipStream_t capture_stream = nullptr;
-    hipEvent_t sync_ev = nullptr;  // polled to wait for small read-backs
     struct Timer {
         int cap = 0, used = 0;
         std::vector<hipEvent_t> ev;  // 2*cap events
@@ -513,19 +514,29 @@ int precondition(hjb_handle *hd, const double *v, void *z, double theta_dt, bool
 
 // ---- flexible GMRES(m) on A^alpha x = b, with x = X on interior nodes ----------------------------
 
-// Wait for the work queued so far by polling an event (a small result is read back right after).
-int wait_stream(hjb_handle *hd) {
-    HIPCHK(hipEventRecord(hd->sync_ev, hd->stream));
-    for (;;) {
-        hipError_t e = hipEventQuery(hd->sync_ev);
-        if (e == hipSuccess) return HJB_OK;
-        if (e != hipErrorNotReady) return fail(HJB_EDEVICE, "hipEventQuery: %s", hipGetErrorString(e));
+// Read small device results: a one-wave kernel copies them to pinned host memory and then releases a
+// new sequence number in the pinned flag word, which the host polls (no stream event, no copy engine).
+// The stream is queried every few thousand polls so that a device error ends the wait.
+int publish_wait(hjb_handle *hd, const void *dev0, void *host0, size_t bytes0, const void *dev1 = nullptr,
+                 void *host1 = nullptr, size_t bytes1 = 0) {
+    const unsigned seq = ++hd->pub_seq;
+    launch_publish(dev0, host0, bytes0, dev1, host1, bytes1, hd->hflag, seq, hd->stream);
+    HIPCHK(hipGetLastError());
+    int after_idle = 0;
+    for (uint64_t it = 1;; ++it) {
+        if (__atomic_load_n(hd->hflag, __ATOMIC_ACQUIRE) == seq) return HJB_OK;
+        if ((it & 4095) == 0) {
+            hipError_t e = hipStreamQuery(hd->stream);
+            if (e == hipErrorNotReady) continue;
+            if (e != hipSuccess) return fail(HJB_EDEVICE, "hipStreamQuery: %s", hipGetErrorString(e));
+            // the stream has drained; the flag store may still be on its way to host memory
+            if (++after_idle > 1000) return fail(HJB_EDEVICE, "stream drained without publishing its results");
+        }
     }
 }
 
 int sync_small(hjb_handle *hd, const void *dev, void *host, size_t bytes) {
-    HIPCHK(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, hd->stream));
-    return wait_stream(hd);
+    return publish_wait(hd, dev, host, bytes);
 }
 
 // The operator of one linear solve: residual() writes r = b - A X into hd->R with the partials
@@ -605,9 +616,7 @@ int fgmres_core(hjb_handle *hd, const KrylovOp &op, double *X, double eta, int *
                 TimedLaunch tl(hd, HJB_KERNEL_AXPY, (double)N * (8.0 * (j + 3) + (rhs32 ? 4.0 : 0.0)));
                 launch_multiaxpy_scale(w, V, N, j + 1, dv + kGsSlot1, N, hd->nbd, s, rhs32);
             }
-            HIPCHK(hipMemcpyAsync(hp + kGsSlot0, dv + kGsSlot0, (size_t)(kGsSlot1 - kGsSlot0 + j + 2) * sizeof(double),
-                                  hipMemcpyDeviceToHost, s));
-            TRY(wait_stream(hd));
+            TRY(publish_wait(hd, dv + kGsSlot0, hp + kGsSlot0, (size_t)(kGsSlot1 - kGsSlot0 + j + 2) * sizeof(double)));
             double hn = 0.0;
             bool dependent = false;
             for (int pass = 0; pass < 2; ++pass) {
@@ -778,9 +787,7 @@ int sweep(hjb_handle *hd, const double *X, const double *U, const double *f0, co
     if (n_changed || tau_used || skip == 2) {
         launch_reduce_sum_i64(hd->ipartial, hd->nb, hd->ival, s);
         if (skip == 2) launch_reduce_sum_i64(hd->kpartial, hd->nb, hd->ival + 1, s);
-        HIPCHK(hipMemcpyAsync(hd->hpin_i, hd->ival, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(hd->hpin + 4, hd->dvals + 4, sizeof(double), hipMemcpyDeviceToHost, s));
-        TRY(wait_stream(hd));
+        TRY(publish_wait(hd, hd->ival, hd->hpin_i, 2 * sizeof(int64_t), hd->dvals + 4, hd->hpin + 4, sizeof(double)));
         if (n_changed) *n_changed = hd->hpin_i[0];
         if (tau_used) *tau_used = hd->hpin[4];
         if (skip == 2) {
@@ -1128,14 +1135,14 @@ int setup_impl(const hjb_desc *desc, hjb_handle **out, bool tables_only) {
         if (e != hipSuccess) return cleanup_fail(fail(HJB_EDEVICE, "%s", hipGetErrorString(e)));
     }
     {
-        hipError_t e = hipHostMalloc((void **)&hd->hpin, kSmallSlots * sizeof(double), hipHostMallocDefault);
+        // fine-grained (coherent) host memory: kernels store small results and the publish flag into it
+        hipError_t e = hipHostMalloc((void **)&hd->hpin, kSmallSlots * sizeof(double), hipHostMallocCoherent);
         if (e != hipSuccess) return cleanup_fail(fail(HJB_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e)));
-        e = hipHostMalloc((void **)&hd->hpin_i, 8 * sizeof(int64_t), hipHostMallocDefault);
+        e = hipHostMalloc((void **)&hd->hpin_i, 8 * sizeof(int64_t), hipHostMallocCoherent);
         if (e != hipSuccess) return cleanup_fail(fail(HJB_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e)));
-    }
-    {
-        hipError_t e = hipEventCreateWithFlags(&hd->sync_ev, hipEventDisableTiming);
-        if (e != hipSuccess) return cleanup_fail(fail(HJB_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e)));
+        e = hipHostMalloc((void **)&hd->hflag, 64, hipHostMallocCoherent);
+        if (e != hipSuccess) return cleanup_fail(fail(HJB_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e)));
+        *hd->hflag = 0u;
     }
     STRY(build_tables(hd, 1.0));
 #undef STRY
@@ -1882,7 +1889,6 @@ void hjb_destroy(hjb_handle *hd) {
     if (!hd) return;
     drop_graphs(hd);
     if (hd->capture_stream) (void)hipStreamDestroy(hd->capture_stream);
-    if (hd->sync_ev) (void)hipEventDestroy(hd->sync_ev);
     for (auto &T : hd->timers)
         for (hipEvent_t e : T.ev) (void)hipEventDestroy(e);
     if (hd->stream) (void)hipStreamSynchronize(hd->stream);
@@ -1890,6 +1896,7 @@ void hjb_destroy(hjb_handle *hd) {
     for (void *p : hd->allocs) (void)hipFree(p);
     if (hd->hpin) (void)hipHostFree(hd->hpin);
     if (hd->hpin_i) (void)hipHostFree(hd->hpin_i);
+    if (hd->hflag) (void)hipHostFree(hd->hflag);
     delete hd;
 }
 

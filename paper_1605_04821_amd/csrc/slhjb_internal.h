@@ -229,6 +229,10 @@ void launch_multiaxpy_scale_dot(double *w, const double *V, int64_t ldv, int nve
 void launch_reduce_sum(const double *partial, int nvec, int nblocks, double *out, hipStream_t s);
 void launch_reduce_max(const double *partial, int nvec, int nblocks, double *out, hipStream_t s);
 void launch_reduce_sum_i64(const int64_t *partial, int nblocks, int64_t *out, hipStream_t s);
+// copy bytes0 (bytes1) from device src0 (src1) to pinned host dst0 (dst1), multiples of 8 bytes, then
+// store seq to the pinned host word *flag with a system-scope release
+void launch_publish(const void *src0, void *dst0, size_t bytes0, const void *src1, void *dst1, size_t bytes1,
+                    unsigned *flag, unsigned seq, hipStream_t s);
 void launch_scale_by_inv_sqrt(double *dst, const double *src, const double *norm2, int64_t N, hipStream_t s,
                               float *dstf = nullptr);
 void launch_to_precond(const double *v, void *out, bool out_float, int64_t N, hipStream_t s);

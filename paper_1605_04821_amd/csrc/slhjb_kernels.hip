@@ -1141,6 +1141,25 @@ __global__ __launch_bounds__(kBlock) void k_scale_by_inv_sqrt(double *__restrict
     if (dstf) dstf[n] = (float)x;
 }
 
+// Hand small device results to the host without a stream event: the 8-byte words of (src0, n0) and
+// (src1, n1) are stored to pinned host memory and made visible system-wide, then *flag receives seq with
+// a release at system scope, so a host that reads seq from the flag also reads the words.  One wave.
+__global__ __launch_bounds__(64) void k_publish(const uint64_t *__restrict__ src0, uint64_t *dst0, int n0,
+                                                const uint64_t *__restrict__ src1, uint64_t *dst1, int n1,
+                                                unsigned *flag, unsigned seq) {
+    for (int q = threadIdx.x; q < n0; q += 64) dst0[q] = src0[q];
+    for (int q = threadIdx.x; q < n1; q += 64) dst1[q] = src1[q];
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+void launch_publish(const void *src0, void *dst0, size_t bytes0, const void *src1, void *dst1, size_t bytes1,
+                    unsigned *flag, unsigned seq, hipStream_t s) {
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, (const uint64_t *)src0, (uint64_t *)dst0, (int)(bytes0 / 8),
+                       (const uint64_t *)src1, (uint64_t *)dst1, (int)(bytes1 / 8), flag, seq);
+}
+
 void launch_scale_by_inv_sqrt(double *dst, const double *src, const double *norm2, int64_t N, hipStream_t s,
                               float *dstf) {
     hipLaunchKernelGGL(k_scale_by_inv_sqrt, dim3(blocks_for(N)), dim3(kBlock), 0, s, dst, src, norm2, N, dstf);

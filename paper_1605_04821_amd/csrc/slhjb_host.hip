@@ -47,9 +47,9 @@ int fail(int code, const char *fmt, ...) {
     return code;
 }
 
-// Slots of the small device/host scalar arrays (dvals, hpin): [0, 16) solver scalars, [128, 128 + m) the
-// FGMRES update coefficients, 200 the adjoint gradient term, and the two Gram-Schmidt passes of one
-// Arnoldi step from kGsSlot0 and kGsSlot1 (m + 2 each).
+// Slots of the small device/host scalar arrays (dvals, hpin): [0, 16) solver scalars, 200 the adjoint
+// gradient term, and the two Gram-Schmidt passes of one Arnoldi step from kGsSlot0 and kGsSlot1 (m + 2
+// each).
 constexpr int kGsSlot0 = 256, kGsSlot1 = kGsSlot0 + kMaxRestart + 2;
 constexpr int kSmallSlots = 512;
 static_assert(kGsSlot1 + kMaxRestart + 2 <= kSmallSlots, "small-slot layout");
@@ -664,10 +664,8 @@ int fgmres_core(hjb_handle *hd, const KrylovOp &op, double *X, double eta, int *
             for (int q = i + 1; q < j; ++q) acc -= H[(size_t)i * m + q] * y[q];
             y[i] = acc / H[(size_t)i * m + i];
         }
-        for (int i = 0; i < j; ++i) hp[128 + i] = y[i];
-        HIPCHK(hipMemcpyAsync(dv + 128, hp + 128, (size_t)j * sizeof(double), hipMemcpyHostToDevice, s));
         const void *Z = none ? (const void *)V : (const void *)hd->Zb;
-        launch_update_solution(X, Z, zf, N, j, dv + 128, N, s);
+        launch_update_solution(X, Z, zf, N, j, y.data(), N, s);
         HIPCHK(hipGetLastError());
     }
 }

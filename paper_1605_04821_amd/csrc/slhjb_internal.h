@@ -236,7 +236,11 @@ void launch_publish(const void *src0, void *dst0, size_t bytes0, const void *src
 void launch_scale_by_inv_sqrt(double *dst, const double *src, const double *norm2, int64_t N, hipStream_t s,
                               float *dstf = nullptr);
 void launch_to_precond(const double *v, void *out, bool out_float, int64_t N, hipStream_t s);
-void launch_update_solution(double *X, const void *Z, bool z_float, int64_t ldz, int m, const double *y, int64_t N,
+// X += sum_{j<m} y_host[j] Z_j; the m <= kMaxRestart coefficients travel as a kernel argument
+struct UpdateCoef {
+    double c[kMaxRestart];
+};
+void launch_update_solution(double *X, const void *Z, bool z_float, int64_t ldz, int m, const double *y_host, int64_t N,
                             hipStream_t s);
 void launch_axpy(double *y, double a, const double *x, int64_t N, hipStream_t s);
 void launch_copy_interior(int dim, const LevelDev &g, const double *src, double *dst, hipStream_t s);

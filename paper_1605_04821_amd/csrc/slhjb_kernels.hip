@@ -581,8 +581,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(DIM == 2
         if (first) {
             v = omega * r[i] / d[i];
         } else {
-            T ae = apply_level<DIM, T>(g, st, alpha, e, i, ix, theta_dt);
-            v = e[i] + omega * (r[i] - ae) / d[i];
+            // the operands that do not depend on the stencil are requested before its gathers, so that
+            // their latency overlaps them (the arithmetic is that of apply_level)
+            const int k = alpha[i];
+            const T ei = e[i], ri = r[i], di = d[i];
+            const double ck = st.c ? st.c[((unsigned)k < (unsigned)st.K) ? k : 0] : 0.0;  // converted at its use
+            const T l = lhat1<DIM, T, T>(g, st, k, i, ix, deep_node<DIM>(g, ix), e, ei);
+            const T ae = ei - theta_dt * (l + (T)ck * ei);
+            v = ei + omega * (ri - ae) / di;
         }
     }
     e_out[i] = v;
@@ -609,7 +615,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(DIM == 2
     int i = tile_node<DIM>(g, ix);
     if (i < 0) return;
     T v = (T)0;
-    if (interior<DIM>(g, ix)) v = r[i] - apply_level<DIM, T>(g, st, alpha, e, i, ix, theta_dt);
+    if (interior<DIM>(g, ix)) {
+        const int k = alpha[i];
+        const T ei = e[i], ri = r[i];
+        const double ck = st.c ? st.c[((unsigned)k < (unsigned)st.K) ? k : 0] : 0.0;
+        const T l = lhat1<DIM, T, T>(g, st, k, i, ix, deep_node<DIM>(g, ix), e, ei);
+        v = ri - (ei - theta_dt * (l + (T)ck * ei));
+    }
     res[i] = v;
 }
 
@@ -1183,17 +1195,18 @@ void launch_to_precond(const double *v, void *out, bool out_float, int64_t N, hi
 
 template <typename TZ>
 __global__ __launch_bounds__(kBlock) void k_update_solution(double *__restrict__ X, const TZ *__restrict__ Z,
-                                                            int64_t ldz, int m, const double *__restrict__ y,
-                                                            int64_t N) {
+                                                            int64_t ldz, int m, const UpdateCoef y, int64_t N) {
     int64_t n = (int64_t)remap_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (n >= N) return;
     double x = X[n];
-    for (int j = 0; j < m; ++j) x += y[j] * (double)Z[(int64_t)j * ldz + n];
+    for (int j = 0; j < m; ++j) x += y.c[j] * (double)Z[(int64_t)j * ldz + n];
     X[n] = x;
 }
 
-void launch_update_solution(double *X, const void *Z, bool z_float, int64_t ldz, int m, const double *y, int64_t N,
+void launch_update_solution(double *X, const void *Z, bool z_float, int64_t ldz, int m, const double *y_host, int64_t N,
                             hipStream_t s) {
+    UpdateCoef y{};
+    for (int j = 0; j < m; ++j) y.c[j] = y_host[j];
     if (z_float)
         hipLaunchKernelGGL(k_update_solution<float>, dim3(blocks_for(N)), dim3(kBlock), 0, s, X, (const float *)Z, ldz,
                            m, y, N);

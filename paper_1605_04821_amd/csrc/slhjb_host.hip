@@ -71,6 +71,8 @@ struct Level {
     void *r32 = nullptr, *e32 = nullptr, *t32 = nullptr, *d32 = nullptr;
     double *sig_node = nullptr;  // per-node sigma model: [N][P][dim] on this level (injected from level 0)
     int reach[3] = {0, 0, 0};    // largest stencil corner offset in nodes along each axis (any control)
+    double *lii = nullptr;       // device [K]: StencilDev::lii_deep of this level
+    bool lii_ok = false;         // lii holds the current tables' values (constant coefficients, deep nodes exist)
 };
 
 }  // namespace
@@ -202,6 +204,8 @@ void fill_tables(hjb_handle *hd, double s, std::vector<PointTab> &host, int leve
     }
 }
 
+StencilDev stencil(const hjb_handle *hd, int level);
+
 int build_tables(hjb_handle *hd, double s) {
     if (hd->s_tab == s) return HJB_OK;
     if (!(s > 0.0) || !isfinite(s)) return fail(HJB_EINVAL, "volatility scale s must be positive and finite");
@@ -273,6 +277,16 @@ int build_tables(hjb_handle *hd, double s) {
         }
         HIPCHK(hipMemcpyAsync(L.fastF, hf.data(), hf.size() * sizeof(FastPtF), hipMemcpyHostToDevice, hd->stream));
         HIPCHK(hipMemcpyAsync(L.fastD, hdd.data(), hdd.size() * sizeof(FastPtD), hipMemcpyHostToDevice, hd->stream));
+        // per-control diagonal sums at deep nodes (constant coefficients), from the tables just uploaded
+        L.lii_ok = false;
+        bool has_deep = hd->desc.coef_model == HJB_COEF_CONST;
+        for (int a = 0; a < hd->dim; ++a) has_deep = has_deep && L.g.deep_lo[a] <= L.g.deep_hi[a];
+        if (has_deep) {
+            StencilDev st = stencil(hd, (int)l);  // lii_deep is not read by the table kernel
+            launch_lii_deep(hd->dim, L.g, st, L.g.deep_lo, L.lii, hd->stream);
+            HIPCHK(hipGetLastError());
+            L.lii_ok = true;
+        }
         HIPCHK(hipStreamSynchronize(hd->stream));  // host vectors go out of scope
     }
     HIPCHK(hipStreamSynchronize(hd->stream));
@@ -300,6 +314,7 @@ StencilDev stencil(const hjb_handle *hd, int level) {
     st.scale = ldexp(1.0, -level);
     for (int a = 0; a < 3; ++a) st.lo[a] = hd->desc.lo[a];
     st.hl = ldexp(hd->desc.h, level);
+    st.lii_deep = (!st.pernode && hd->lev[level].lii_ok) ? hd->lev[level].lii : nullptr;
     return st;
 }
 
@@ -1054,6 +1069,7 @@ int setup_impl(const hjb_desc *desc, hjb_handle **out, bool tables_only) {
         STRY(dalloc(hd, (void **)&L.tab, (size_t)d.K * hd->npt * sizeof(PointTab)));
         STRY(dalloc(hd, (void **)&L.fastF, (size_t)d.K * hd->npt * sizeof(FastPtF)));
         STRY(dalloc(hd, (void **)&L.fastD, (size_t)d.K * hd->npt * sizeof(FastPtD)));
+        STRY(dalloc(hd, (void **)&L.lii, (size_t)d.K * sizeof(double)));
         if (d.coef_model == HJB_COEF_FIELD) {
             // per-node sigma on this level: the finest level's value at the coinciding node
             const int pd = d.P * d.dim, stp = 1 << l;

@@ -93,6 +93,9 @@ struct StencilDev {
     double lo[3], hl;     // node coordinates on this level: x = lo + i * hl
     const double *sig_node;  // field model: [N_level][P][dim] on this level
     int64_t fk;           // control stride of f0, f1 (0: one source for all controls; N: [K][N])
+    // constant coefficients: [K] per-control sum over points of W (w_self - 1) at deep nodes of this level,
+    // where it does not depend on the node (nullptr: computed per node)
+    const double *lii_deep;
 };
 
 // Displacement in cells of stencil point q (table entry p) at node ix (linear index i on its level).
@@ -197,6 +200,8 @@ void launch_residual(int dim, const LevelDev &g, const StencilDev &st, const int
 template <typename T>
 void launch_diag(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, double theta_dt, T *d,
                  hipStream_t s);
+// per-control table of StencilDev::lii_deep, evaluated at the deep node ix0 of the level (K entries)
+void launch_lii_deep(int dim, const LevelDev &g, const StencilDev &st, const int ix0[3], double *out, hipStream_t s);
 template <typename T>
 void launch_jacobi(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const T *e, const T *r,
                    const T *d, T *e_out, double theta_dt, double omega, bool first, hipStream_t s);

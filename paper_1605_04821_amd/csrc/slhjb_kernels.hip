@@ -446,10 +446,11 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev g, StencilDev st0,
         vv = fabs(Vi);
         if (interior<DIM>(g, ix)) {
             int k = alpha[i];
+            const double Ei = E[i];  // requested before the stencil gathers
             bool deep = deep_node<DIM>(g, ix);
             double l = lhat1<DIM, double, double>(g, st, k, i, ix, deep, V, Vi);
             double ck = st.c ? st.c[((unsigned)k < (unsigned)st.K) ? k : 0] : 0.0;
-            rr = E[i] - (Vi - theta_dt * (l + ck * Vi));
+            rr = Ei - (Vi - theta_dt * (l + ck * Vi));
         }
         r[i] = rr;
     }
@@ -498,19 +499,10 @@ void launch_bad_policy(int dim, const LevelDev &g, const int16_t *alpha, int K, 
 
 // ---- multigrid level kernels ----------------------------------------------------------------------
 
-// diagonal of A = I - theta dt (L-hat + c) on one level: d = 1 - theta dt (l_ii + c)
-template <int DIM, typename T>
-__global__ __launch_bounds__(kBlock) void k_diag(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
-                                                 double theta_dt, T *__restrict__ d) {
-    int ix[3];
-    int i = tile_node<DIM>(g, ix);
-    if (i < 0) return;
-    if (!interior<DIM>(g, ix)) {
-        d[i] = (T)1;
-        return;
-    }
-    int k = alpha[i];
-    k = ((unsigned)k < (unsigned)st.K) ? k : 0;
+// Sum over the stencil points of control k of W (w_self - 1) at node ix: the diagonal of L-hat before the
+// 1/(2h) scaling (W: the point's weight after truncation, w_self: its interpolation weight on the node).
+template <int DIM>
+__device__ double diag_lii(const LevelDev &g, const StencilDev &st, int k, const int ix[3], int i) {
     const PointTab *pt = st.tab + k * st.npt;
     double lii = 0.0;
     for (int q = 0; q < st.npt; ++q) {
@@ -541,9 +533,45 @@ __global__ __launch_bounds__(kBlock) void k_diag(LevelDev g, StencilDev st, cons
         }
         lii += W * (wself - 1.0);
     }
+    return lii;
+}
+
+// diagonal of A = I - theta dt (L-hat + c) on one level: d = 1 - theta dt (l_ii + c).  At deep nodes of the
+// constant-coefficient model no point is truncated and every displacement is the table's, so l_ii is the
+// per-control value diag_lii gives at any deep node (same operations, same rounding): read from the table.
+template <int DIM, typename T>
+__global__ __launch_bounds__(kBlock) void k_diag(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
+                                                 double theta_dt, T *__restrict__ d) {
+    int ix[3];
+    int i = tile_node<DIM>(g, ix);
+    if (i < 0) return;
+    if (!interior<DIM>(g, ix)) {
+        d[i] = (T)1;
+        return;
+    }
+    int k = alpha[i];
+    k = ((unsigned)k < (unsigned)st.K) ? k : 0;
+    double lii = (st.lii_deep && deep_node<DIM>(g, ix)) ? st.lii_deep[k] : diag_lii<DIM>(g, st, k, ix, i);
     lii *= st.inv2h;
     double ck = st.c ? st.c[((unsigned)k < (unsigned)st.K) ? k : 0] : 0.0;
     d[i] = (T)(1.0 - theta_dt * (lii + ck));
+}
+
+template <int DIM>
+__global__ void k_lii_deep(LevelDev g, StencilDev st, int x0, int x1, int x2, double *__restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= st.K) return;
+    const int ix[3] = {x0, x1, x2};
+    const int i = x0 + x1 * (int)g.s1 + (DIM == 3 ? x2 * (int)g.s2 : 0);
+    out[k] = diag_lii<DIM>(g, st, k, ix, i);
+}
+
+void launch_lii_deep(int dim, const LevelDev &g, const StencilDev &st, const int ix0[3], double *out, hipStream_t s) {
+    const int nb = (st.K + 63) / 64;
+    if (dim == 2)
+        hipLaunchKernelGGL(k_lii_deep<2>, dim3(nb), dim3(64), 0, s, g, st, ix0[0], ix0[1], ix0[2], out);
+    else
+        hipLaunchKernelGGL(k_lii_deep<3>, dim3(nb), dim3(64), 0, s, g, st, ix0[0], ix0[1], ix0[2], out);
 }
 
 template <typename T>

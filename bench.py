@@ -239,7 +239,8 @@ def measured_traffic(kernel, pi_per_step):
         if not a or not b:
             return None
         return (tot(a[0]) + pi_per_step * tot(b[0])) / (1.0 + pi_per_step)
-    names = {"apply": "k_apply<2, float>", "smooth": "k_jacobi<2, float>", "mg_residual": "k_level_residual<2, float>"}
+    names = {"apply": "k_apply<2, float>", "smooth": "k_jacobi<2, float> (sweep with gathers)",
+             "mg_residual": "k_level_residual<2, float>"}
     hit = [k for k in per if names.get(kernel, "?") in k]
     return tot(hit[0]) if hit else None
 

@@ -757,15 +757,15 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_T(LevelDev g, StencilDev st, 
         y[j] = omega * r[j] / d[j];
         return;
     }
+    const double xj = x[j], rj = r[j], dj = d[j];  // requested before the column gathers
     double cj = 0.0;
     if (st.c) {
         int k = alpha[j];
         cj = st.c[((unsigned)k < (unsigned)st.K) ? k : 0];
     }
-    double xj = x[j];
     double lt = lt_gather<double>(j, T, x);
-    double res = r[j] - (xj - theta_dt * (lt + cj * xj));
-    y[j] = xj + omega * res / d[j];
+    double res = rj - (xj - theta_dt * (lt + cj * xj));
+    y[j] = xj + omega * res / dj;
 }
 
 void launch_jacobi_T(int dim, bool first, const LevelDev &g, const StencilDev &st, const int16_t *alpha,
@@ -877,8 +877,9 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_T32(LevelDev g, StencilDev st
         y[j] = omega * r[j] / d[j];
         return;
     }
+    // the node's own operands are requested before the column gathers, so that their latency overlaps
+    const float xj = x[j], rj = r[j], dj = d[j];
     const WSet ws = window_set(T);
-    float xj = x[j];
     float lt, cj;
     if (ws.n == 1) {
         lt = lt_reflect<DIM, float>(g, st, st.fastF, ws.k[0], j, x, xj);
@@ -888,8 +889,8 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_T32(LevelDev g, StencilDev st
                       : lt_gather32<PACKED>(j, (int)g.s1, T, x);
         cj = coef32<DIM>(st, alpha, j);
     }
-    float res = r[j] - (xj - theta_dt * (lt + cj * xj));
-    y[j] = xj + omega * res / d[j];
+    float res = rj - (xj - theta_dt * (lt + cj * xj));
+    y[j] = xj + omega * res / dj;
 }
 
 void launch_jacobi_T32(int dim, bool first, const LevelDev &g, const StencilDev &st, const int16_t *alpha,
@@ -922,8 +923,8 @@ __global__ __launch_bounds__(kBlock) void k_resid_T32(LevelDev g, StencilDev st,
         y[j] = 0.0f;
         return;
     }
+    const float xj = x[j], bj = b[j];  // requested before the column gathers
     const WSet ws = window_set(T);
-    float xj = x[j];
     float lt, cj;
     if (ws.n == 1) {
         lt = lt_reflect<DIM, float>(g, st, st.fastF, ws.k[0], j, x, xj);
@@ -933,7 +934,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_T32(LevelDev g, StencilDev st,
                       : lt_gather32<PACKED>(j, (int)g.s1, T, x);
         cj = coef32<DIM>(st, alpha, j);
     }
-    y[j] = b[j] - (xj - theta_dt * (lt + cj * xj));
+    y[j] = bj - (xj - theta_dt * (lt + cj * xj));
 }
 
 void launch_resid_T32(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const TransposeView &T,

@@ -149,6 +149,34 @@ def test_linsolve_matches_oracle(slhjb, precision, precond):
     solver.close()
 
 
+@pytest.mark.parametrize("restart", [9, 24])
+def test_linsolve_long_arnoldi(slhjb, restart):
+    """Jacobi-preconditioned FGMRES(m) runs every Arnoldi step of its cycles: the fused Gram-Schmidt kernels
+    for bases of 1 ... 8 vectors and the separate update and sums beyond; the solve still meets the oracle."""
+    inst = workloads.config_c2(65)
+    log(f"linsolve restart={restart}")
+    pb = oracle.Problem(inst)
+    alpha = workloads.random_policy(inst, 17)
+    U, _ = workloads.random_fields(inst, seed=18)
+    t_prev, dt, theta = 0.1, 1.0 / 64, 0.5
+    f = pb.f_at(inst.f0, inst.f1, t_prev + theta * dt)
+    L = pb.assemble(alpha)
+    E = oracle.explicit_part(pb, L, alpha, U, f, dt, theta)
+    V0 = U.copy()
+    V0[pb.bd] = inst.psi[pb.bd]
+    Vref, _ = oracle.linear_solve(pb, L, alpha, V0, E, dt, theta, rtol=1e-15)
+    solver = slhjb.Solver.from_instance(inst, slhjb.Options(precision=0, precond=1, restart=restart))
+    dX = to_dev(V0)
+    st = solver.linsolve(to_dev(alpha), to_dev(U), to_dev(inst.f0), to_dev(inst.f1), t_prev, dt, theta, 1.0, dX)
+    X = to_np(dX)
+    log(f"  krylov={st.krylov_total} res={st.res_inf:.2e}")
+    assert st.krylov_total >= 10  # Arnoldi steps with bases beyond the fused kernels' 8 vectors
+    rel = np.max(np.abs(X - Vref)) / np.max(np.abs(Vref))
+    assert rel <= 1e-11, rel
+    assert st.res_inf <= 1e-13 * max(1.0, np.max(np.abs(X)))
+    solver.close()
+
+
 def _march_compare(slhjb, inst, opts=None, tol=1e-10):
     ref = oracle.march(inst, keep_policies=True)
     solver = slhjb.Solver.from_instance(inst, opts)

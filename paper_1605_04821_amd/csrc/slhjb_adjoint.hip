@@ -167,6 +167,25 @@ __device__ __forceinline__ TC lt_reflect(const LevelDev &g, const StencilDev &st
         }
         return v;
     };
+    if (DIM == 2 && st.P == 1) {
+        // one diffusion pair (+ drift): all twelve gathers are issued before any sum (the drift's are read
+        // from the pair's stencil when there is no drift point, and unused); sums as in the general loop
+        const TW &pa = fp[0], &pb = fp[1], &pc = fp[st.has_drift ? 2 : 0];
+        const int oa = j - pa.off, ob = j - pb.off, oc = j - pc.off;
+        const TX a0 = x[oa], a1 = x[oa - 1], a2 = x[oa - s1], a3 = x[oa - s1 - 1];
+        const TX b0 = x[ob], b1 = x[ob - 1], b2 = x[ob - s1], b3 = x[ob - s1 - 1];
+        const TX c0 = x[oc], c1 = x[oc - 1], c2 = x[oc - s1], c3 = x[oc - s1 - 1];
+        auto ws4 = [](const TW &p, TX v0, TX v1, TX v2, TX v3) {
+            TC v = (TC)p.w[0] * (TC)v0;
+            v = fma((TC)p.w[1], (TC)v1, v);
+            v = fma((TC)p.w[2], (TC)v2, v);
+            return fma((TC)p.w[3], (TC)v3, v);
+        };
+        TC acc = (TC)0;
+        acc = acc + ((ws4(pa, a0, a1, a2, a3) + ws4(pb, b0, b1, b2, b3)) - (TC)2 * xj);
+        if (st.has_drift) acc = acc + (TC)2 * (ws4(pc, c0, c1, c2, c3) - xj);
+        return (TC)st.inv2h * acc;
+    }
     TC acc = (TC)0;
     for (int p = 0; p < st.P; ++p) acc = acc + ((pt(fp[2 * p]) + pt(fp[2 * p + 1])) - (TC)2 * xj);
     if (st.has_drift) acc = acc + (TC)2 * (pt(fp[2 * st.P]) - xj);
@@ -197,6 +216,41 @@ __device__ __forceinline__ TC lt_reflect_multi(const LevelDev &g, const StencilD
                                                const int16_t *__restrict__ alpha, TC xj) {
     const int s1 = (int)g.s1, s2 = (int)g.s2;
     TC acc = (TC)0;
+    if (DIM == 2 && st.P == 1) {
+        // one diffusion pair (+ drift): per control, the corner controls and values of all its points are
+        // requested before any sum (twelve of each; a missing drift point reads the pair's stencil, unused)
+        const int npt = st.npt;
+        for (int m = 0; m < w.n; ++m) {
+            const int k = w.k[m];
+            const TW *fp = tab + k * npt;
+            int o[3];
+            int16_t ac[3][4];
+            TX xc[3][4];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                o[q] = j - fp[q < npt ? q : 0].off;
+                const int ci[4] = {o[q], o[q] - 1, o[q] - s1, o[q] - s1 - 1};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    ac[q][c] = alpha[ci[c]];
+                    xc[q][c] = x[ci[c]];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                if (q >= npt) break;
+                const TW &p = fp[q];
+                auto at = [&](int c) { return ac[q][c] == k ? (TC)xc[q][c] : (TC)0; };
+                TC v = (TC)p.w[0] * at(0);
+                v = fma((TC)p.w[1], at(1), v);
+                v = fma((TC)p.w[2], at(2), v);
+                v = fma((TC)p.w[3], at(3), v);
+                acc = q < 2 ? acc + v : acc + (TC)2 * v;  // drift point weight 2
+            }
+        }
+        const TC b = (TC)(2 + (st.has_drift ? 2 : 0));
+        return (TC)st.inv2h * (acc - b * xj);
+    }
     for (int m = 0; m < w.n; ++m) {
         const int k = w.k[m];
         const TW *fp = tab + k * st.npt;

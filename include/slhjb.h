@@ -99,6 +99,9 @@ typedef struct {
     int32_t max_levels;     /* at most this many multigrid levels (0: no limit); setup only */
     int32_t nu_tight;       /* pre- and post-sweeps of the V-cycles of solves that must reach the certificate
                                (the last solve of a step, hjb_linsolve, every transposed solve); 0: nu1, nu2 */
+    int32_t coarse_sweeps_t; /* damped Jacobi sweeps on the coarsest level of the transposed V-cycles of the
+                               adjoint (0: coarse_sweeps; a single-level hierarchy always takes coarse_sweeps);
+                               0..1000 */
     void *stream;           /* hipStream_t */
 } hjb_desc;
 
@@ -132,7 +135,8 @@ int hjb_setup(const hjb_desc *desc, hjb_handle **out);
 int hjb_set_stream(hjb_handle *hd, void *stream);
 
 /* Change solver controls after setup (precision, precond, restart, max_krylov, max_pi, nu1, nu2,
-   coarse_sweeps, omega, rtol_inf, tau_rel, pi_eta, use_graphs, certified_skip, nu_tight are taken from *desc; grid and controls
+   coarse_sweeps, omega, rtol_inf, tau_rel, pi_eta, use_graphs, certified_skip, nu_tight, coarse_sweeps_t are taken from
+   *desc; grid and controls
    are those of the setup).  restart may not exceed its value at setup. */
 int hjb_set_options(hjb_handle *hd, const hjb_desc *desc);
 

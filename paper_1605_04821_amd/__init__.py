@@ -49,7 +49,8 @@ class Desc(ctypes.Structure):
                 ("omega", ctypes.c_double), ("rtol_inf", ctypes.c_double), ("tau_rel", ctypes.c_double),
                 ("pi_eta", ctypes.c_double), ("use_graphs", ctypes.c_int32), ("f_per_control", ctypes.c_int32),
                 ("certified_skip", ctypes.c_int32), ("max_levels", ctypes.c_int32),
-                ("nu_tight", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("nu_tight", ctypes.c_int32), ("coarse_sweeps_t", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
 
 
 class StepStats(ctypes.Structure):
@@ -164,6 +165,7 @@ class Options:
     certified_skip: int = 1
     max_levels: int = 2
     nu_tight: int = 4
+    coarse_sweeps_t: int = 2
 
 
 class Solver:
@@ -222,6 +224,7 @@ class Solver:
         desc.certified_skip = o.certified_skip
         desc.max_levels = o.max_levels
         desc.nu_tight = o.nu_tight
+        desc.coarse_sweeps_t = o.coarse_sweeps_t
 
     @classmethod
     def from_instance(cls, inst, options: Optional[Options] = None):

@@ -361,6 +361,7 @@ int check_options(const hjb_desc *d) {
     if (!(d->pi_eta >= 0.0 && d->pi_eta < 1.0)) return fail(HJB_EINVAL, "pi_eta must be in [0,1)");
     if (d->max_levels < 0) return fail(HJB_EINVAL, "max_levels must be >= 0");
     if (d->nu_tight < 0 || d->nu_tight > 16) return fail(HJB_EINVAL, "nu_tight in 0..16");
+    if (d->coarse_sweeps_t < 0 || d->coarse_sweeps_t > 1000) return fail(HJB_EINVAL, "coarse_sweeps_t in 0..1000");
     return HJB_OK;
 }
 
@@ -959,6 +960,7 @@ void hjb_desc_default(hjb_desc *d) {
     d->certified_skip = 1;
     d->max_levels = 2;
     d->nu_tight = 4;
+    d->coarse_sweeps_t = 2;
     d->stream = nullptr;
 }
 
@@ -1197,6 +1199,7 @@ int hjb_set_options(hjb_handle *hd, const hjb_desc *desc) {
     d.use_graphs = desc->use_graphs;
     d.certified_skip = desc->certified_skip;
     d.nu_tight = desc->nu_tight;
+    d.coarse_sweeps_t = desc->coarse_sweeps_t;
     select_precision(hd);
     set_sweeps(hd, false);
     drop_graphs(hd);
@@ -1706,7 +1709,10 @@ void vcycle_T(hjb_handle *hd, const TransposeHierarchy &H, const T *r0, T *z, do
                            nullptr, s);
         launch_restrict<T>(hd->dim, L.g, hd->lev[l + 1].g, t[l], (T *)(F ? hd->lev[l + 1].r32 : hd->lev[l + 1].r64), s);
     }
-    smooth_T<T>(hd, H, Lc, e[Lc], t[Lc], r[Lc], d.coarse_sweeps, true, theta_dt);
+    // the transposed cycle's coarsest level takes its own sweep count: more sweeps there did not lower
+    // the adjoint's Krylov count on the benchmark workloads
+    smooth_T<T>(hd, H, Lc, e[Lc], t[Lc], r[Lc], d.coarse_sweeps_t > 0 ? d.coarse_sweeps_t : d.coarse_sweeps, true,
+                theta_dt);
     for (int l = Lc - 1; l >= 0; --l) {
         launch_prolong_add<T>(hd->dim, hd->lev[l].g, hd->lev[l + 1].g, e[l + 1], e[l], s);
         smooth_T<T>(hd, H, l, e[l], t[l], r[l], hd->nu_post, false, theta_dt);

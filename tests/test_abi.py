@@ -55,7 +55,8 @@ def _desc(slhjb, **kw):
 @pytest.mark.parametrize("field,value,code", [
     ("dim", 4, -1), ("h", 0.0, -1), ("K", 0, -1), ("P", 9, -1), ("scheme", 1, -7), ("coef_model", 3, -7),
     ("restart", 0, -1), ("restart", 65, -1), ("omega", 2.5, -1), ("precision", 5, -1), ("nu1", 0, -1),
-    ("rtol_inf", 0.0, -1), ("precond", 7, -1), ("max_levels", -1, -1), ("nu_tight", 17, -1)])
+    ("rtol_inf", 0.0, -1), ("precond", 7, -1), ("max_levels", -1, -1), ("nu_tight", 17, -1),
+    ("coarse_sweeps_t", -1, -1)])
 def test_setup_rejects_invalid_arguments(slhjb, field, value, code):
     d, keep = _desc(slhjb, **{field: value})
     h = ctypes.c_void_p()

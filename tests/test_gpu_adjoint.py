@@ -116,7 +116,15 @@ def test_adjoint_uniform_windows_129(slhjb):
     _check_adjoint(slhjb, "c2_129_cn", workloads.config_c2(129, n_cn=4), 1, 2)
 
 
-def _check_adjoint(slhjb, name, inst, precision, precond, max_levels=2):
+@pytest.mark.parametrize("coarse_sweeps_t", [0, 1, 5])
+def test_adjoint_coarse_sweeps_option(slhjb, coarse_sweeps_t):
+    """The transposed cycles' own coarsest-level sweep count (0: the forward's) changes the work, not the
+    gradients: each setting meets the dense oracle adjoint."""
+    inst = workloads.config_c2(65, n_cn=4)
+    _check_adjoint(slhjb, f"c2_65 coarse_sweeps_t={coarse_sweeps_t}", inst, 1, 2, coarse_sweeps_t=coarse_sweeps_t)
+
+
+def _check_adjoint(slhjb, name, inst, precision, precond, max_levels=2, coarse_sweeps_t=2):
     log(f"adjoint {name} n={inst.n} steps={len(inst.dts)} precision={precision} precond={precond}")
     s = S_TEST
     ref_march = oracle.march(inst, s=s, keep_policies=True)
@@ -124,7 +132,7 @@ def _check_adjoint(slhjb, name, inst, precision, precond, max_levels=2):
     lam = _lam_N(inst, ref_march["U"])
     ref = oracle.adjoint_dense(inst, pols, lam, s=s)
     solver = slhjb.Solver.from_instance(inst, slhjb.Options(precision=precision, precond=precond,
-                                                            max_levels=max_levels))
+                                                            max_levels=max_levels, coarse_sweeps_t=coarse_sweeps_t))
     dg = torch.empty(inst.N, dtype=torch.float64, device="cuda")
     df0, df1 = torch.empty_like(dg), torch.empty_like(dg)
     ds, st = solver.adjoint(to_dev(inst.g), to_dev(inst.psi), to_dev(inst.f0), to_dev(inst.f1), inst.dts,

@@ -533,11 +533,15 @@ int precondition(hjb_handle *hd, const double *v, void *z, double theta_dt, bool
 // Read small device results: a one-wave kernel copies them to pinned host memory and then releases a
 // new sequence number in the pinned flag word, which the host polls (no stream event, no copy engine).
 // The stream is queried every few thousand polls so that a device error ends the wait.
-int publish_wait(hjb_handle *hd, const void *dev0, void *host0, size_t bytes0, const void *dev1 = nullptr,
-                 void *host1 = nullptr, size_t bytes1 = 0) {
-    const unsigned seq = ++hd->pub_seq;
-    launch_publish(dev0, host0, bytes0, dev1, host1, bytes1, hd->hflag, seq, hd->stream);
+int publish(hjb_handle *hd, unsigned *seq, const void *dev0, void *host0, size_t bytes0,
+            const void *dev1 = nullptr, void *host1 = nullptr, size_t bytes1 = 0) {
+    *seq = ++hd->pub_seq;
+    launch_publish(dev0, host0, bytes0, dev1, host1, bytes1, hd->hflag, *seq, hd->stream);
     HIPCHK(hipGetLastError());
+    return HJB_OK;
+}
+
+int wait_published(hjb_handle *hd, unsigned seq) {
     int after_idle = 0;
     for (uint64_t it = 1;; ++it) {
         if (__atomic_load_n(hd->hflag, __ATOMIC_ACQUIRE) == seq) return HJB_OK;
@@ -549,6 +553,13 @@ int publish_wait(hjb_handle *hd, const void *dev0, void *host0, size_t bytes0, c
             if (++after_idle > 1000) return fail(HJB_EDEVICE, "stream drained without publishing its results");
         }
     }
+}
+
+int publish_wait(hjb_handle *hd, const void *dev0, void *host0, size_t bytes0, const void *dev1 = nullptr,
+                 void *host1 = nullptr, size_t bytes1 = 0) {
+    unsigned seq = 0;
+    TRY(publish(hd, &seq, dev0, host0, bytes0, dev1, host1, bytes1));
+    return wait_published(hd, seq);
 }
 
 int sync_small(hjb_handle *hd, const void *dev, void *host, size_t bytes) {
@@ -590,7 +601,16 @@ int fgmres_core(hjb_handle *hd, const KrylovOp &op, double *X, double eta, int *
         op.residual();
         launch_reduce_sum(hd->partial, 1, hd->nb, dv + 0, s);
         launch_reduce_max(hd->partial + hd->nb, 2, hd->nb, dv + 1, s);
-        TRY(sync_small(hd, dv, hp, 3 * sizeof(double)));
+        unsigned seq = 0;
+        TRY(publish(hd, &seq, dv, hp, 3 * sizeof(double)));
+        // a solve rarely starts converged: its first basis vector and preconditioner application are
+        // queued before the host reads the residual norms (and discarded if it has converged)
+        const bool ahead = cycle == 0 && !none;
+        if (ahead) {
+            launch_scale_by_inv_sqrt(V, hd->R, dv + 0, N, s, rhs32);
+            TRY(op.precond(V, hd->Zb, rhs32 != nullptr));
+        }
+        TRY(wait_published(hd, seq));
         double beta = sqrt(hp[0]), rinf = hp[1], xinf = hp[2];
         *res_out = rinf;
         *its_out = its;
@@ -603,7 +623,7 @@ int fgmres_core(hjb_handle *hd, const KrylovOp &op, double *X, double eta, int *
         if (its >= d.max_krylov)
             return fail(HJB_ENOCONV_KRYLOV, "FGMRES: |r|_inf = %.3e > %.3e after %d iterations", rinf, target, its);
         // v0 = r / beta
-        launch_scale_by_inv_sqrt(V, hd->R, dv + 0, N, s, rhs32);
+        if (!ahead) launch_scale_by_inv_sqrt(V, hd->R, dv + 0, N, s, rhs32);
         std::fill(gvec.begin(), gvec.end(), 0.0);
         gvec[0] = beta;
         int j = 0;
@@ -611,7 +631,7 @@ int fgmres_core(hjb_handle *hd, const KrylovOp &op, double *X, double eta, int *
             double *vj = V + (int64_t)j * N;
             double *w = V + (int64_t)(j + 1) * N;
             void *zj = none ? (void *)vj : (void *)((char *)hd->Zb + (int64_t)j * N * zsz);
-            if (!none) TRY(op.precond(vj, zj, rhs32 != nullptr));
+            if (!none && !(ahead && j == 0)) TRY(op.precond(vj, zj, rhs32 != nullptr));
             op.apply(zj, zf, w);
             // classical Gram-Schmidt run twice (CGS2): the sums <w,V_i> and |w|^2, the update and
             // normalisation (norm by Pythagoras) fused with the second pass's sums, then the second update,

@@ -54,9 +54,7 @@ __device__ __forceinline__ bool deep_a(const LevelDev &g, const int ix[3]) {
 
 // ---- columns of L whose stencil window holds few controls ------------------------------------------
 
-constexpr int kWinMax = 4;  // controls a window may hold for the matrix-free transposed gather
-
-// tset[5 T .. 5 T + 4] = {n, k_0 < k_1 < ...}: the n <= kWinMax distinct controls of tile T when all its
+// tset[(1 + kWinMax) T ...] = {n, k_0 < k_1 < ...}: the n <= kWinMax distinct controls of tile T when all its
 // nodes are interior and untruncated, else n = -1
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_tile_set(LevelDev g, const int16_t *__restrict__ alpha, int K,

@@ -1594,8 +1594,8 @@ struct TransposeWork {
                    {(void **)&b.vals_s, (size_t)n * 8}, {(void **)&b.colptr, (size_t)(nodes + 1) * 4},
                    {(void **)&b.ell_w, (size_t)ns * 4}, {(void **)&b.ell_off, (size_t)ns * 4},
                    {(void **)&b.ell_rows, (size_t)ne * 4}, {(void **)&b.ell_vals, (size_t)ne * 8},
-                   {&b.scratch, b.scratch_bytes + 256}, {(void **)&tset, (size_t)tiles_cap(g, hd->dim) * 20},
-                   {(void **)&wset, (size_t)tiles_cap(g, hd->dim) * 20}};
+                   {&b.scratch, b.scratch_bytes + 256}, {(void **)&tset, (size_t)tiles_cap(g, hd->dim) * 4 * (1 + kWinMax)},
+                   {(void **)&wset, (size_t)tiles_cap(g, hd->dim) * 4 * (1 + kWinMax)}};
         for (auto &r : req) {
             if (hipMalloc(r.p, r.bytes) != hipSuccess) {
                 (void)hipGetLastError();

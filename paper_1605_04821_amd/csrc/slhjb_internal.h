@@ -14,6 +14,7 @@ constexpr int kBlock = 256;              // threads per block of the node-parall
 constexpr int kMaxRestart = 64;
 constexpr int kTileLog2 = 5;             // default node tile of one block: 32 x 8 (width 2^kTileLog2)
 constexpr int kTileLogMin = 4, kTileLogMax = 7;  // tile widths 16 ... 128 (heights 16 ... 2)
+constexpr int kWinMax = 4;  // controls a window may hold for the matrix-free transposed gather
 
 // Start and stop events for the next timed kernel launch.  A host timer scope sets them; the launcher
 // of that kernel hands them to hipExtLaunchKernel, which stamps them with the dispatch's own begin and

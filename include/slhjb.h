@@ -123,7 +123,8 @@ typedef struct {
     double max_cert_bound;
 } hjb_solve_stats;
 
-/* Fill *d with defaults (2D, FP64, V-cycle(2,2), m = 10, rtol 1e-13, tau_rel 1e-13, pi_eta 0.2, ...). Grid and controls
+/* Fill *d with defaults (2D, FP64, V-cycle(3,3) and (4,4) for solves to the certificate, m = 10, rtol 1e-13,
+   tau_rel 1e-13, pi_eta 0.35, ...). Grid and controls
    still have to be set by the caller. */
 void hjb_desc_default(hjb_desc *d);
 

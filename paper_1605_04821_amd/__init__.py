@@ -160,7 +160,7 @@ class Options:
     omega: float = 0.9
     rtol_inf: float = 1e-13
     tau_rel: float = 1e-13
-    pi_eta: float = 0.2
+    pi_eta: float = 0.35
     use_graphs: int = 1
     certified_skip: int = 1
     max_levels: int = 2

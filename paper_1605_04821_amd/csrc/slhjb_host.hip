@@ -975,7 +975,7 @@ void hjb_desc_default(hjb_desc *d) {
     d->omega = 0.9;
     d->rtol_inf = 1e-13;
     d->tau_rel = 1e-13;
-    d->pi_eta = 0.2;
+    d->pi_eta = 0.35;
     d->use_graphs = 1;
     d->certified_skip = 1;
     d->max_levels = 2;

@@ -121,6 +121,8 @@ struct hjb_handle {
         double theta_dt;
         int nu1, nu2;
         bool rhs_ready;  // the graph starts from the single-precision right-hand side already in place
+        const void *aa;  // policy of the operator application appended to the cycle (nullptr: none)
+        const double *w; // its output
         hipGraphExec_t exec;
     };
     std::vector<VGraph> vgraphs;
@@ -136,6 +138,7 @@ struct hjb_handle {
     int sample_period = 1;   // time one unit in sample_period (hjb_profile_sample)
     int64_t vc_count = 0;    // V-cycles since the V-cycle timers were enabled
     bool vc_timed = false;   // the V-cycle being launched is a sampled one
+    bool apply_with_vcycle = false;  // the operator application being launched follows a V-cycle
 };
 
 namespace {
@@ -150,7 +153,8 @@ struct TimedLaunch {
         if (id < 0) return;
         auto &T = hd->timers[id];
         if (T.used >= T.cap) return;
-        const bool in_vcycle = id == HJB_KERNEL_SMOOTH || id == HJB_KERNEL_MG_RESID;
+        const bool in_vcycle = id == HJB_KERNEL_SMOOTH || id == HJB_KERNEL_MG_RESID ||
+                               (id == HJB_KERNEL_APPLY && hd->apply_with_vcycle);
         if (in_vcycle ? hd->vc_timed : (T.calls++ % hd->sample_period == 0)) {
             slot = T.used++;
             T.bytes[slot] = bytes;
@@ -487,23 +491,39 @@ void drop_graphs(hjb_handle *hd) {
     hd->vgraphs.clear();
 }
 
-// z = M^{-1} v.  The V-cycle's launch sequence depends only on buffer addresses and theta*dt, so it is
-// captured once per (level-0 policy buffer, v, z, theta*dt) and replayed; policy, diagonal and table
-// contents are refreshed in place before each replay.  A V-cycle sampled by the smoother or residual
-// timers runs eagerly (events cannot be accumulated from inside a replayed graph).
-int precondition(hjb_handle *hd, const double *v, void *z, double theta_dt, bool rhs_ready) {
-    const bool timers = hd->timers[HJB_KERNEL_SMOOTH].cap > 0 || hd->timers[HJB_KERNEL_MG_RESID].cap > 0;
+using ApplyFn = std::function<void(const void *, bool, double *)>;
+
+// z = M^{-1} v, then, when apply is given, w = A z (policy apply_alpha).  The launch sequence depends only
+// on buffer addresses and theta*dt, so it is captured once per (level-0 policy buffer, v, z, theta*dt,
+// sweep counts, operator application) and replayed; policy, diagonal and table contents are refreshed in
+// place before each replay.  A cycle sampled by the smoother, residual or apply timers runs eagerly
+// (events cannot be accumulated from inside a replayed graph), its application timed with it.
+int precondition(hjb_handle *hd, const double *v, void *z, double theta_dt, bool rhs_ready,
+                 const ApplyFn *apply = nullptr, const void *apply_alpha = nullptr, double *w = nullptr,
+                 bool zf = false) {
+    const bool timers = hd->timers[HJB_KERNEL_SMOOTH].cap > 0 || hd->timers[HJB_KERNEL_MG_RESID].cap > 0 ||
+                        (apply && hd->timers[HJB_KERNEL_APPLY].cap > 0);
     const bool sampled = timers && hd->vc_count++ % hd->sample_period == 0;
-    if (!hd->desc.use_graphs || hd->desc.precond != HJB_PRECOND_VCYCLE || sampled) {
-        hd->vc_timed = sampled;
+    auto eager = [&](bool timed) {
+        hd->vc_timed = timed;
         precondition_eager(hd, v, z, theta_dt, rhs_ready);
+        if (apply) {
+            hd->apply_with_vcycle = true;
+            (*apply)(z, zf, w);
+            hd->apply_with_vcycle = false;
+        }
         hd->vc_timed = false;
+    };
+    if (!hd->desc.use_graphs || hd->desc.precond != HJB_PRECOND_VCYCLE || sampled) {
+        eager(sampled);
         return HJB_OK;
     }
     const void *a0 = hd->lev[0].alpha;
+    const void *aa = apply ? apply_alpha : nullptr;
+    const double *wk = apply ? w : nullptr;
     for (auto &g : hd->vgraphs)
         if (g.a0 == a0 && g.v == v && g.z == z && g.theta_dt == theta_dt && g.nu1 == hd->nu_pre &&
-            g.nu2 == hd->nu_post && g.rhs_ready == rhs_ready) {
+            g.nu2 == hd->nu_post && g.rhs_ready == rhs_ready && g.aa == aa && g.w == wk) {
             HIPCHK(hipGraphLaunch(g.exec, hd->stream));
             return HJB_OK;
         }
@@ -514,7 +534,7 @@ int precondition(hjb_handle *hd, const double *v, void *z, double theta_dt, bool
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(hd->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        precondition_eager(hd, v, z, theta_dt, rhs_ready);
+        eager(false);
         e = hipStreamEndCapture(hd->capture_stream, &graph);
     }
     hd->stream = saved;
@@ -523,7 +543,7 @@ int precondition(hjb_handle *hd, const double *v, void *z, double theta_dt, bool
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(HJB_EDEVICE, "V-cycle instantiate: %s", hipGetErrorString(e));
-    hd->vgraphs.push_back({a0, v, z, theta_dt, hd->nu_pre, hd->nu_post, rhs_ready, exec});
+    hd->vgraphs.push_back({a0, v, z, theta_dt, hd->nu_pre, hd->nu_post, rhs_ready, aa, wk, exec});
     HIPCHK(hipGraphLaunch(exec, hd->stream));
     return HJB_OK;
 }
@@ -575,6 +595,8 @@ struct KrylovOp {
     std::function<void()> residual;
     std::function<void(const void *, bool, double *)> apply;
     std::function<int(const double *, void *, bool)> precond;
+    // optional: precond(v, z, ready) followed by apply(z, zf, w) as one unit (one captured graph)
+    std::function<int(const double *, void *, double *, bool)> precond_apply;
     bool zf = false;
     float *rhs32 = nullptr;
 };
@@ -590,6 +612,17 @@ int fgmres_core(hjb_handle *hd, const KrylovOp &op, double *X, double eta, int *
     const bool none = !op.precond;
     const bool zf = !none && op.zf;
     float *const rhs32 = none ? nullptr : op.rhs32;
+    // z = M^{-1} v (z = v without a preconditioner), then w = A z
+    auto precond_then_apply = [&](const double *v, void *z, double *w) -> int {
+        if (none) {
+            op.apply(v, false, w);
+            return HJB_OK;
+        }
+        if (op.precond_apply) return op.precond_apply(v, z, w, rhs32 != nullptr);
+        TRY(op.precond(v, z, rhs32 != nullptr));
+        op.apply(z, zf, w);
+        return HJB_OK;
+    };
     const size_t zsz = zf ? sizeof(float) : sizeof(double);
     double *V = hd->Vb;
     double *dv = hd->dvals;
@@ -608,7 +641,7 @@ int fgmres_core(hjb_handle *hd, const KrylovOp &op, double *X, double eta, int *
         const bool ahead = cycle == 0 && !none;
         if (ahead) {
             launch_scale_by_inv_sqrt(V, hd->R, dv + 0, N, s, rhs32);
-            TRY(op.precond(V, hd->Zb, rhs32 != nullptr));
+            TRY(precond_then_apply(V, hd->Zb, V + N));
         }
         TRY(wait_published(hd, seq));
         double beta = sqrt(hp[0]), rinf = hp[1], xinf = hp[2];
@@ -631,8 +664,7 @@ int fgmres_core(hjb_handle *hd, const KrylovOp &op, double *X, double eta, int *
             double *vj = V + (int64_t)j * N;
             double *w = V + (int64_t)(j + 1) * N;
             void *zj = none ? (void *)vj : (void *)((char *)hd->Zb + (int64_t)j * N * zsz);
-            if (!none && !(ahead && j == 0)) TRY(op.precond(vj, zj, rhs32 != nullptr));
-            op.apply(zj, zf, w);
+            if (!(ahead && j == 0)) TRY(precond_then_apply(vj, zj, w));
             // classical Gram-Schmidt run twice (CGS2): the sums <w,V_i> and |w|^2, the update and
             // normalisation (norm by Pythagoras) fused with the second pass's sums, then the second update,
             // which also writes the single-precision copy of v_{j+1} for the next preconditioner call.  A
@@ -714,12 +746,20 @@ int fgmres(hjb_handle *hd, const int16_t *alpha, const double *E, double *X, dou
     hipStream_t s = hd->stream;
     KrylovOp op;
     op.residual = [=]() { launch_residual(dim, L0.g, st, alpha, X, E, theta_dt, hd->R, hd->partial, hd->nb, s); };
+    // the application reads the handle's stream when it runs: it may be captured into a V-cycle's graph
     op.apply = [=](const void *z, bool zf, double *w) {
         TimedLaunch tl(hd, HJB_KERNEL_APPLY, (double)hd->N * ((zf ? 4.0 : 8.0) + 2.0 + 8.0));
-        launch_apply(dim, L0.g, st, alpha, z, zf, w, theta_dt, nullptr, hd->nb, s);
+        launch_apply(dim, L0.g, st, alpha, z, zf, w, theta_dt, nullptr, hd->nb, hd->stream);
     };
     if (hd->desc.precond != HJB_PRECOND_NONE)
         op.precond = [=](const double *v, void *z, bool ready) { return precondition(hd, v, z, theta_dt, ready); };
+    if (hd->desc.precond == HJB_PRECOND_VCYCLE) {
+        const ApplyFn ap = op.apply;
+        const bool zf = mixed(hd);
+        op.precond_apply = [=](const double *v, void *z, double *w, bool ready) {
+            return precondition(hd, v, z, theta_dt, ready, &ap, alpha, w, zf);
+        };
+    }
     op.zf = mixed(hd);
     if (op.zf && hd->desc.precond == HJB_PRECOND_VCYCLE) op.rhs32 = (float *)L0.r;
     return fgmres_core(hd, op, X, eta, its_out, res_out, tight_out);

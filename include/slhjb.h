@@ -272,8 +272,9 @@ int hjb_autotune(hjb_handle *hd, const char *cache_path, int32_t *tile_width_out
    milliseconds, their summed algorithmic bytes (each input element read once, each output written
    once; halo re-reads of gathered stencil points are not counted) and, for the policy search, their
    summed algorithmic FP64 operations on interior nodes (untruncated stencil arithmetic; 0 otherwise).
-   The smoother and multigrid-residual timers record the launches of sampled V-cycles, which run without
-   their captured graph; see hjb_profile_sample. */
+   The smoother and multigrid-residual timers, and with the V-cycle preconditioner the operator-application
+   timer (the application is captured with the cycle it follows), record the launches of sampled V-cycles,
+   which run without their captured graph; see hjb_profile_sample. */
 enum {
     HJB_KERNEL_APPLY = 0,     /* y = A^alpha z in FGMRES (FP64 out; z FP64 or FP32) */
     HJB_KERNEL_SMOOTH = 1,    /* damped Jacobi sweep with stencil gathers on the finest level */
@@ -288,8 +289,8 @@ int hjb_profile_read(hjb_handle *hd, int32_t kernel, int64_t *launches, double *
                      double *total_flops);
 
 /* Timer sampling: with period p >= 1, one V-cycle in p is sampled (launched eagerly, its finest-level
-   smoother and residual launches timed) while the others replay their captured graph untimed, and one
-   launch in p of each other enabled class is timed.  p = 1 (the default) times every launch and runs
+   smoother and residual launches and the operator application after it timed) while the others replay
+   their captured graph untimed, and one launch in p of each other enabled class is timed.  p = 1 (the default) times every launch and runs
    every V-cycle eagerly while a smoother or residual timer is enabled.  Results do not depend on p.
    Returns HJB_EINVAL for p outside 1..1000000. */
 int hjb_profile_sample(hjb_handle *hd, int32_t period);

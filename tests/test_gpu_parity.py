@@ -149,6 +149,28 @@ def test_linsolve_matches_oracle(slhjb, precision, precond):
     solver.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_linsolve_from_converged_start(slhjb, precision):
+    """A solve that starts at the certificate returns at once: the first Arnoldi step queued ahead of the
+    residual read is discarded and the iterate is left as it was, bit for bit."""
+    inst = workloads.config_c2(65)
+    log(f"linsolve from a converged start, precision={precision}")
+    alpha = workloads.random_policy(inst, 27)
+    U, _ = workloads.random_fields(inst, seed=28)
+    V0 = U.copy()
+    V0[inst.boundary_mask()] = inst.psi[inst.boundary_mask()]
+    args = (to_dev(alpha), to_dev(U), to_dev(inst.f0), to_dev(inst.f1), 0.1, 1.0 / 64, 0.5, 1.0)
+    solver = slhjb.Solver.from_instance(inst, slhjb.Options(precision=precision))
+    dX = to_dev(V0)
+    st1 = solver.linsolve(*args, dX)
+    X1 = to_np(dX)
+    st2 = solver.linsolve(*args, dX)
+    log(f"  first solve {st1.krylov_total} iterations, second {st2.krylov_total}")
+    assert st1.krylov_total > 0 and st2.krylov_total == 0
+    np.testing.assert_array_equal(to_np(dX), X1)
+    solver.close()
+
+
 @pytest.mark.parametrize("restart", [9, 24])
 def test_linsolve_long_arnoldi(slhjb, restart):
     """Jacobi-preconditioned FGMRES(m) runs every Arnoldi step of its cycles: the fused Gram-Schmidt kernels

@@ -1023,7 +1023,7 @@ __global__ __launch_bounds__(kBlock) void k_multiaxpy_scale(double *__restrict__
     __shared__ double c[kMaxRestart + 2];
     for (int v = threadIdx.x; v <= nvec; v += blockDim.x) c[v] = coef[v];
     __syncthreads();
-    // norm of the orthogonalised vector by Pythagoras (the caller re-orthogonalises on cancellation)
+    // norm of the orthogonalised vector by Pythagoras (the caller runs a second pass on the result)
     double h2 = 0.0;
     for (int v = 0; v < nvec; ++v) h2 += c[v] * c[v];
     double hn2 = c[nvec] - h2;

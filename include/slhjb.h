@@ -290,7 +290,8 @@ int hjb_profile_read(hjb_handle *hd, int32_t kernel, int64_t *launches, double *
 
 /* Timer sampling: with period p >= 1, one V-cycle in p is sampled (launched eagerly, its finest-level
    smoother and residual launches and the operator application after it timed) while the others replay
-   their captured graph untimed, and one launch in p of each other enabled class is timed.  p = 1 (the default) times every launch and runs
+   their captured graph untimed, and one launch in p of the multi-dot and update classes is timed; the
+   policy search is timed at every launch.  p = 1 (the default) times every launch and runs
    every V-cycle eagerly while a smoother or residual timer is enabled.  Results do not depend on p.
    Returns HJB_EINVAL for p outside 1..1000000. */
 int hjb_profile_sample(hjb_handle *hd, int32_t period);

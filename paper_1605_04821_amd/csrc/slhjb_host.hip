@@ -153,9 +153,12 @@ struct TimedLaunch {
         if (id < 0) return;
         auto &T = hd->timers[id];
         if (T.used >= T.cap) return;
+        // the policy search is timed at every launch: its launches are few and long, and two kinds (the first
+        // search of a step and the later ones) alternate, which a fixed sampling stride would alias
         const bool in_vcycle = id == HJB_KERNEL_SMOOTH || id == HJB_KERNEL_MG_RESID ||
                                (id == HJB_KERNEL_APPLY && hd->apply_with_vcycle);
-        if (in_vcycle ? hd->vc_timed : (T.calls++ % hd->sample_period == 0)) {
+        const bool take = id == HJB_KERNEL_SWEEP || (in_vcycle ? hd->vc_timed : (T.calls++ % hd->sample_period == 0));
+        if (take) {
             slot = T.used++;
             T.bytes[slot] = bytes;
             T.flops[slot] = flops;

@@ -212,6 +212,7 @@ void fill_tables(hjb_handle *hd, double s, std::vector<PointTab> &host, int leve
 }
 
 StencilDev stencil(const hjb_handle *hd, int level);
+void drop_graphs(hjb_handle *hd);
 
 int build_tables(hjb_handle *hd, double s) {
     if (hd->s_tab == s) return HJB_OK;
@@ -298,6 +299,8 @@ int build_tables(hjb_handle *hd, double s) {
     }
     HIPCHK(hipStreamSynchronize(hd->stream));
     hd->s_tab = s;
+    // captured graphs hold level descriptors and stencil scalars by value (the deep box, s / sqrt(h))
+    drop_graphs(hd);
     return HJB_OK;
 }
 

@@ -321,6 +321,29 @@ def test_kernel_timers_leave_results_unchanged(slhjb, period):
         assert counts["mg_residual"][0] == kry
 
 
+def test_new_volatility_scale_recaptures_graphs(slhjb):
+    """A march at one volatility scale and then at another on the same handle gives, at the second scale,
+    the result of a fresh handle bit for bit: the captured V-cycle graphs (which hold the deep box and
+    the operator application by value) are rebuilt with the tables."""
+    inst = workloads.config_c2(65, n_cn=4)
+    log("graphs across a change of s")
+    g = to_dev(inst.g)
+    args = (g, to_dev(inst.psi), to_dev(inst.f0), to_dev(inst.f1), inst.dts, inst.thetas)
+    reused = slhjb.Solver.from_instance(inst, slhjb.Options(precision=1))
+    U = torch.empty_like(g)
+    reused.solve(*args, 1.0, U)
+    U_re = torch.empty_like(g)
+    st_re = reused.solve(*args, 1.6, U_re)
+    reused.close()
+    fresh = slhjb.Solver.from_instance(inst, slhjb.Options(precision=1))
+    U_fr = torch.empty_like(g)
+    st_fr = fresh.solve(*args, 1.6, U_fr)
+    fresh.close()
+    log(f"  krylov {st_re.krylov_total} / {st_fr.krylov_total}")
+    np.testing.assert_array_equal(to_np(U_re), to_np(U_fr))
+    assert st_re.krylov_total == st_fr.krylov_total
+
+
 SKIP_CASES = [
     ("c2_129_cn", lambda: workloads.config_c2(129, n_cn=8)),
     ("c2_257_cn", lambda: workloads.config_c2(257, n_cn=4)),

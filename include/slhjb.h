@@ -59,6 +59,13 @@ enum {
 };
 enum { HJB_PREC_FP64 = 0, HJB_PREC_MIXED = 1 }; /* V-cycle in FP64, or in FP32 under FP64 FGMRES */
 enum { HJB_PRECOND_NONE = 0, HJB_PRECOND_JACOBI = 1, HJB_PRECOND_VCYCLE = 2 };
+/* Flags of hjb_step_stats / hjb_solve_stats (bitwise or). */
+enum {
+    HJB_FLAG_POSITIVITY = 1,  /* positivity of the weights (eq. CFL_trunc) may fail: theta < 1 and
+                                 (1 - theta) dt (M/h + max|c|) > 1 */
+    HJB_FLAG_NEAR_TIES = 2    /* the returned policy has near ties: nodes where the second-best G_k is within
+                                 1e3 * tau of the best, so that several policies are correct results */
+};
 
 typedef struct {
     /* Grid (eqs. 1.1-1.3 on a box, Section 2.1): n[d] nodes per axis, uniform spacing h, corner lo. */
@@ -109,18 +116,24 @@ typedef struct {
     int32_t pi_iters;       /* policy iterations (linear solves) in the step */
     int32_t krylov_total;   /* FGMRES iterations summed over the step's solves */
     int32_t krylov_max;     /* largest FGMRES count of one solve */
-    int32_t flags;          /* bit 0: positivity condition (eq. CFL_trunc) may fail for theta < 1 */
+    int32_t flags;          /* HJB_FLAG_* */
     double res_inf;         /* final |F - A X|_inf of the last solve */
     double cert_bound;      /* bound on |X - X*|_inf of the last solve: res_inf / (1 - theta dt max(c,0)) */
     int64_t n_changed_first;/* controls changed by the first search of the step */
+    int64_t n_near_ties;    /* interior nodes whose decision in the step's last search is a near tie
+                               (HJB_FLAG_NEAR_TIES): the second-best G_k lies within 1e3 * tau of the best.
+                               Nodes kept by certified reuse are not evaluated and count as clear decisions
+                               (their certified gap exceeds 1e-10 S, which is 1e3 * tau at the default
+                               tau_rel). 0 for explicit steps. */
 } hjb_step_stats;
 
 typedef struct {
     int32_t steps_done;
-    int32_t flags;
+    int32_t flags;          /* HJB_FLAG_* of every step, or-ed */
     int64_t krylov_total;
     int64_t pi_total;
     double max_cert_bound;
+    int64_t near_ties_total; /* n_near_ties summed over the steps */
 } hjb_solve_stats;
 
 /* Fill *d with defaults (2D, FP64, V-cycle(3,3) and (4,4) for solves to the certificate, m = 10, rtol 1e-13,
@@ -188,14 +201,16 @@ int hjb_step(hjb_handle *hd, const double *Uprev, double *Unext, const double *f
              double t_prev, double dt, double theta, double s, int16_t *alpha_io, const double *Uprev2,
              double dt_prev, hjb_step_stats *st);
 
-/* March U^0 = g (eq. 1.2), U^n = psi on the boundary (eq. 1.3) through n_steps theta-steps with
-   dts[n], thetas[n] (host arrays); from the third step on, each step starts from the extrapolation of
-   the two previous levels (see hjb_step).  U_final: full-grid FP64 output.  policies (nullable): int16
+/* March U^0 = g (eq. 1.2), U^n = psi(t_n) on the boundary (eq. 1.3) through n_steps theta-steps with
+   dts[n], thetas[n] (host arrays), t_n = t_{n-1} + dts[n-1]; from the third step on, each step starts from the
+   extrapolation of the two previous levels (see hjb_step).  Dirichlet data: psi (full-grid FP64, only boundary
+   entries are read) and psi1 (nullable, full-grid FP64): psi(t) = psi + t * psi1, constant when psi1 is NULL.
+   theta = 0 steps are explicit (see hjb_step).  U_final: full-grid FP64 output.  policies (nullable): int16
    [n_steps][N], the converged policy of each step (the checkpoints an adjoint sweep reuses).
    values (nullable): FP64 [n_steps+1][N], U^0 = g and every U^n, for hjb_adjoint to use instead of
    recomputing them. */
-int hjb_solve(hjb_handle *hd, const double *g, const double *psi, const double *f0, const double *f1,
-              int32_t n_steps, const double *dts, const double *thetas, double s,
+int hjb_solve(hjb_handle *hd, const double *g, const double *psi, const double *psi1, const double *f0,
+              const double *f1, int32_t n_steps, const double *dts, const double *thetas, double s,
               double *U_final, int16_t *policies, double *values, hjb_solve_stats *st);
 
 typedef struct {
@@ -245,7 +260,8 @@ int hjb_setup_batch(const hjb_desc *descs, int32_t count, hjb_batch **out);
 int hjb_batch_layout(const hjb_batch *bh, int64_t *offsets, int64_t *total);
 int hjb_batch_set_stream(hjb_batch *bh, void *stream);
 /* hjb_solve for every instance with one shared schedule and s; arrays in the concatenated layout
-   (device, FP64; policies int16 [n_steps][total], nullable); st: host [count] (nullable).
+   (device, FP64; policies int16 [n_steps][total], nullable); st: host [count] (nullable; near ties are not
+   counted in batches: near_ties_total is 0).
    The first instance that fails (e.g. HJB_ENOCONV_KRYLOV) stops the whole batch; the message names it. */
 int hjb_solve_batch(hjb_batch *bh, const double *g, const double *psi, const double *f0, const double *f1,
                     int32_t n_steps, const double *dts, const double *thetas, double s, double *U_final,

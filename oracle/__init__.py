@@ -25,7 +25,7 @@ Readings taken where the paper is silent (repeated in the design doc):
     S = (2*M/(2h) + max|c|) * max(|X|_inf, |U|_inf) + |f|_inf;
   * the linear solve is run to an infinity-norm residual certificate: for an
     M-matrix with row sums >= 1 - theta*dt*max(c,0) the error is bounded by
-    |r|_inf / (1 - theta*dt*max(c,0)) (row sums, Section 3.3).
+    |r|_inf / (1 - theta*dt*max(c,0)) (row sums, Section 3.4).
 """
 from __future__ import annotations
 
@@ -299,16 +299,18 @@ def _system_matrix(pb: Problem, L, alpha, dt, theta):
     return (sp.identity(I.size, format="csr") - theta * dt * (Lii + sp.diags(c))).tocsc()
 
 
-def linear_solve(pb: Problem, L, alpha, V, E, dt, theta, rtol=1e-14, max_refine=20, direct_limit=70000):
+def linear_solve(pb: Problem, L, alpha, V, E, dt, theta, rtol=1e-14, max_refine=20, direct_limit=70000,
+                 direct_limit_3d=8000):
     """Solve the fixed-policy system to the infinity-norm certificate |r|_inf <= rtol * |V|_inf.
 
-    Direct sparse LU (SuperLU) for up to direct_limit unknowns, else Jacobi-preconditioned GMRES;
-    both followed by residual-correction sweeps until the certificate holds.
+    Direct sparse LU (SuperLU) for up to direct_limit unknowns in 2D (direct_limit_3d in 3D, where the
+    fill-in of the wide stencil makes the factorisation slow), else Jacobi-preconditioned GMRES; both
+    followed by residual-correction sweeps until the certificate holds.
     """
     I = pb.interior
     A = _system_matrix(pb, L, alpha, dt, theta)
     V = V.copy()
-    if I.size <= direct_limit:
+    if I.size <= (direct_limit if pb.dim == 2 else min(direct_limit, direct_limit_3d)):
         lu = spla.splu(A)
         solve = lu.solve
     else:
@@ -362,14 +364,21 @@ def step(pb: Problem, Uprev, psi, f0, f1, t_prev, dt, theta, alpha_prev, rtol=1e
         st.pi_iters = it + 1
         st.changed.append(res["changed"])
         if res["changed"] == 0:
-            st.near_ties = int(np.sum((res["ties"] > 1)[pb.interior]))
+            # several policies are correct results where the runner-up is within 1e3 tau of the best
+            st.near_ties = int(np.sum(((res["ties"] > 1) | (res["margin"] < 1e3 * tau))[pb.interior]))
             return V, alpha, st
         alpha = res["alpha"]
     raise RuntimeError("policy iteration did not terminate")
 
 
+def psi_at(inst, t: float):
+    """Dirichlet data at time t (eq. 1.3): psi, or psi + t psi1 when the instance gives time-dependent data."""
+    psi1 = getattr(inst, "psi1", None)
+    return inst.psi if psi1 is None else inst.psi + t * psi1
+
+
 def march(inst, s: Optional[float] = None, rtol=1e-14, keep_policies=False, keep_values=False, n_steps=None):
-    """Time march of the theta-scheme from U^0 = g (eq. 1.2) with U = psi on the boundary (eq. 1.3)."""
+    """Time march of the theta-scheme from U^0 = g (eq. 1.2) with U^n = psi(t_n) on the boundary (eq. 1.3)."""
     pb = Problem(inst, s=s)
     U = _f64(inst.g).copy()
     alpha = np.zeros(pb.N, np.int16)
@@ -379,7 +388,7 @@ def march(inst, s: Optional[float] = None, rtol=1e-14, keep_policies=False, keep
     steps = len(inst.dts) if n_steps is None else n_steps
     for n in range(steps):
         dt, th = float(inst.dts[n]), float(inst.thetas[n])
-        U, alpha, st = step(pb, U, inst.psi, inst.f0, inst.f1, t, dt, th, alpha, rtol=rtol)
+        U, alpha, st = step(pb, U, psi_at(inst, t + dt), inst.f0, inst.f1, t, dt, th, alpha, rtol=rtol)
         t = t + dt
         stats.append(st)
         if keep_policies:
@@ -414,18 +423,19 @@ def brute_force_step(pb: Problem, Uprev, psi, f0, f1, t_prev, dt, theta):
     U = _f64(Uprev)
     Vb = np.zeros(pb.N)
     Vb[pb.bd] = psi[pb.bd]
-    # per control k: dense rows restricted to interior columns, the boundary contribution and the explicit part
+    # per control k: dense rows restricted to interior columns and the right-hand side of eq. FullScheme,
+    # B U^{n-1} + dt f + the Dirichlet contribution, written out with dense matrices on every node
     Arows = np.empty((K, n, n))
     Frows = np.empty((K, n))
     for k in range(K):
         alpha = np.full(pb.N, k, np.int16)
         alpha[pb.bd] = -1
-        L = pb.assemble(alpha)
+        Ld = pb.assemble(alpha).toarray()
         c = pb.c_of(alpha)
-        E = explicit_part(pb, L, alpha, U, f, dt, theta)
-        Lii = L[I][:, I].toarray()
-        Arows[k] = np.eye(n) - theta * dt * (Lii + np.diag(c[I]))
-        Frows[k] = E[I] + theta * dt * (L @ Vb)[I]
+        B = np.eye(pb.N) + (1.0 - theta) * dt * (Ld + np.diag(c))
+        rhs = B @ U + dt * pb.f_of(f, alpha) + theta * dt * (Ld @ Vb)
+        Arows[k] = np.eye(n) - theta * dt * (Ld[np.ix_(I, I)] + np.diag(c[I]))
+        Frows[k] = rhs[I]
     best = np.full(n, np.inf)
     idx = np.indices((K,) * n).reshape(n, -1).T  # every policy
     chunk = 4096
@@ -457,7 +467,7 @@ def fixed_policy_march(inst, policies, s: Optional[float] = None, rtol=1e-15):
         L = pb.assemble(alpha)
         E = explicit_part(pb, L, alpha, U, f, dt, th)
         V = U.copy()
-        V[pb.bd] = inst.psi[pb.bd]
+        V[pb.bd] = psi_at(inst, t + dt)[pb.bd]
         V, _ = linear_solve(pb, L, alpha, V, E, dt, th, rtol=rtol)
         U = V
         out.append(U.copy())

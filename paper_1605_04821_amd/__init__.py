@@ -22,6 +22,7 @@ HJB_ENOCONV_KRYLOV, HJB_ENOCONV_PI, HJB_ENONFINITE, HJB_EUNSUPPORTED = -4, -5, -
 PREC_FP64, PREC_MIXED = 0, 1
 COEF_CONST, COEF_XSCALED, COEF_FIELD = 0, 1, 2
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_VCYCLE = 0, 1, 2
+FLAG_POSITIVITY, FLAG_NEAR_TIES = 1, 2
 
 EXPORTED = ["hjb_desc_default", "hjb_setup", "hjb_set_stream", "hjb_set_options", "hjb_policy_sweep", "hjb_apply",
             "hjb_linsolve", "hjb_step", "hjb_solve", "hjb_adjoint", "hjb_apply_transposed", "hjb_profile_enable",
@@ -56,12 +57,13 @@ class Desc(ctypes.Structure):
 class StepStats(ctypes.Structure):
     _fields_ = [("pi_iters", ctypes.c_int32), ("krylov_total", ctypes.c_int32), ("krylov_max", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("res_inf", ctypes.c_double), ("cert_bound", ctypes.c_double),
-                ("n_changed_first", ctypes.c_int64)]
+                ("n_changed_first", ctypes.c_int64), ("n_near_ties", ctypes.c_int64)]
 
 
 class SolveStats(ctypes.Structure):
     _fields_ = [("steps_done", ctypes.c_int32), ("flags", ctypes.c_int32), ("krylov_total", ctypes.c_int64),
-                ("pi_total", ctypes.c_int64), ("max_cert_bound", ctypes.c_double)]
+                ("pi_total", ctypes.c_int64), ("max_cert_bound", ctypes.c_double),
+                ("near_ties_total", ctypes.c_int64)]
 
 
 class AdjointStats(ctypes.Structure):
@@ -89,7 +91,7 @@ def _load():
     L.hjb_apply.argtypes = [vp, vp, vp, vp, d, d, d]
     L.hjb_linsolve.argtypes = [vp, vp, vp, vp, vp, d, d, d, d, vp, ctypes.POINTER(StepStats)]
     L.hjb_step.argtypes = [vp, vp, vp, vp, vp, d, d, d, d, vp, vp, d, ctypes.POINTER(StepStats)]
-    L.hjb_solve.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, d, vp, vp, vp, ctypes.POINTER(SolveStats)]
+    L.hjb_solve.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp, vp, d, vp, vp, vp, ctypes.POINTER(SolveStats)]
     L.hjb_adjoint.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, d, vp, vp, vp, vp, vp, vp, ctypes.POINTER(d),
                               ctypes.POINTER(AdjointStats)]
     L.hjb_apply_transposed.argtypes = [vp, vp, vp, vp, d, d, d]
@@ -339,12 +341,13 @@ class Solver:
                                      ctypes.byref(fl)))
         return int(n.value), float(ms.value), float(by.value), float(fl.value)
 
-    def solve(self, g, psi, f0, f1, dts, thetas, s, U_final, policies=None, values=None) -> SolveStats:
+    def solve(self, g, psi, f0, f1, dts, thetas, s, U_final, policies=None, values=None, psi1=None) -> SolveStats:
+        """hjb_solve; psi1 (optional): Dirichlet data psi(t) = psi + t psi1."""
         self._sync_stream()
         dts = np.ascontiguousarray(dts, dtype=np.float64)
         thetas = np.ascontiguousarray(thetas, dtype=np.float64)
         st = SolveStats()
-        _check(_lib.hjb_solve(self._h, _ptr(g), _ptr(psi), _ptr(f0), _ptr(f1), int(len(dts)),
+        _check(_lib.hjb_solve(self._h, _ptr(g), _ptr(psi), _ptr(psi1), _ptr(f0), _ptr(f1), int(len(dts)),
                               dts.ctypes.data, thetas.ctypes.data, float(s), _ptr(U_final), _ptr(policies),
                               _ptr(values), ctypes.byref(st)))
         return st

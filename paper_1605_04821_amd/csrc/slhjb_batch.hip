@@ -41,7 +41,7 @@ __global__ __launch_bounds__(kBlock) void k_norms_b(BTiles T, const double *__re
     int i = tile_node_at<DIM>(I.g, T.tile[c.pos], ix);
     double vx = 0.0, vf = 0.0;
     if (i >= 0) {
-        vx = fmax(fabs(X[o + i]), fabs(U[o + i]));
+        vx = OpMax()(fabs(X[o + i]), fabs(U[o + i]));
         if (interior<DIM>(I.g, ix)) vf = fabs(f0[o + i] + t_mid * f1[o + i]);
     }
     double a = block_reduce<double>(vx, OpMax(), sh);
@@ -50,24 +50,26 @@ __global__ __launch_bounds__(kBlock) void k_norms_b(BTiles T, const double *__re
     if (threadIdx.x == 0) partial[T.n + c.pos] = b;
 }
 
-// tau[b] = tau_rel * (coefA[b] * max(|X|,|U|) + max|f|) over instance b's tiles [first[b], first[b+1])
+// tau[b] = tau_rel * (coefA[b] * max(|X|,|U|) + max|f|) over instance b's tiles [first[b], first[b+1]);
+// a NaN wins the maxima (as in the single-instance tolerance), so a non-finite iterate gives a NaN tau
 __global__ void k_tau_b(const double *partial, int n, const int32_t *first, const double *coefA, double tau_rel,
                         const uint8_t *active, double *tau) {
     __shared__ double sx[256], sf[256];
     const int b = blockIdx.x;
     if (active && !active[b]) return;
+    const OpMax mx;
     double ax = 0.0, af = 0.0;
     for (int q = first[b] + threadIdx.x; q < first[b + 1]; q += blockDim.x) {
-        ax = fmax(ax, partial[q]);
-        af = fmax(af, partial[n + q]);
+        ax = mx(ax, partial[q]);
+        af = mx(af, partial[n + q]);
     }
     sx[threadIdx.x] = ax;
     sf[threadIdx.x] = af;
     __syncthreads();
     for (int w = blockDim.x / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) {
-            sx[threadIdx.x] = fmax(sx[threadIdx.x], sx[threadIdx.x + w]);
-            sf[threadIdx.x] = fmax(sf[threadIdx.x], sf[threadIdx.x + w]);
+            sx[threadIdx.x] = mx(sx[threadIdx.x], sx[threadIdx.x + w]);
+            sf[threadIdx.x] = mx(sf[threadIdx.x], sf[threadIdx.x + w]);
         }
         __syncthreads();
     }

@@ -4,7 +4,7 @@
 //
 // Method: Reisinger & Rotaetxe Arto (arXiv:1605.04821).  Each theta-step (eq. FullScheme) is a
 // row-wise nonlinear system (eq. nonlinear_sys) solved by Howard policy iteration; each policy's
-// linear system is an M-matrix with row sums >= 1 - theta dt max(c,0) (Section 3.3), so the
+// linear system is an M-matrix with row sums >= 1 - theta dt max(c,0) (Section 3.4), so the
 // infinity-norm residual bounds the error and serves as the stopping certificate.
 // The V-cycle rediscretises the operator on each coarse level with the same physical stencil
 // displacements (the 1/(2h) scaling of the finest grid is kept), injects the fine policy, smooths
@@ -816,7 +816,7 @@ __global__ void k_sweep_tau_arg(const double *tau_dev, double *tau_copy) {
 
 int sweep(hjb_handle *hd, const double *X, const double *U, const double *f0, const double *f1, double t_prev,
           double dt, double theta, const int16_t *a_in, int16_t *a_out, double *gmin, double *margin, int32_t *ties,
-          int64_t *n_changed, double *tau_used, int qmode = 0, int skip = 0) {
+          int64_t *n_changed, double *tau_used, int qmode = 0, int skip = 0, int64_t *n_near = nullptr) {
     hipStream_t s = hd->stream;
     const Level &L0 = hd->lev[0];
     double t_mid = t_prev + theta * dt;
@@ -864,11 +864,13 @@ int sweep(hjb_handle *hd, const double *X, const double *U, const double *f0, co
     }
     HIPCHK(hipGetLastError());
     hd->kept_last = 0;
-    if (n_changed || tau_used || skip == 2) {
+    if (n_changed || tau_used || n_near || skip == 2) {
         launch_reduce_sum_i64(hd->ipartial, hd->nb, hd->ival, s);
         if (skip == 2) launch_reduce_sum_i64(hd->kpartial, hd->nb, hd->ival + 1, s);
         TRY(publish_wait(hd, hd->ival, hd->hpin_i, 2 * sizeof(int64_t), hd->dvals + 4, hd->hpin + 4, sizeof(double)));
-        if (n_changed) *n_changed = hd->hpin_i[0];
+        // the search's partials hold the changed controls in their low 32 bits and the near ties above
+        if (n_changed) *n_changed = hd->hpin_i[0] & 0xffffffffll;
+        if (n_near) *n_near = (int64_t)((uint64_t)hd->hpin_i[0] >> 32);
         if (tau_used) *tau_used = hd->hpin[4];
         if (skip == 2) {
             hd->kept_last = hd->hpin_i[1];
@@ -934,7 +936,7 @@ int step_impl(hjb_handle *hd, const double *Uprev, double *Unext, const double *
         HIPCHK(hipMemcpyAsync(alpha_io, hd->a0, (size_t)N * sizeof(int16_t), hipMemcpyDeviceToDevice, s));
         HIPCHK(hipGetLastError());
         // positivity of the explicit scheme (eq. CFL_trunc): (1 - theta) dt (M/h + |c|) <= 1 for interior weights
-        if (dt * (hd->M / hd->desc.h + hd->cmax) > 1.0) loc.flags |= 1;
+        if (dt * (hd->M / hd->desc.h + hd->cmax) > 1.0) loc.flags |= HJB_FLAG_POSITIVITY;
         if (st) *st = loc;
         return HJB_OK;
     }
@@ -953,7 +955,7 @@ int step_impl(hjb_handle *hd, const double *Uprev, double *Unext, const double *
     if (theta < 1.0) {
         // eq. CFL_trunc can only be guaranteed for theta < 1 when (1-theta) dt M/h <= 1 (interior weights)
         double lhs = (1.0 - theta) * dt * (hd->M / hd->desc.h + hd->cmax);
-        if (lhs > 1.0) loc.flags |= 1;
+        if (lhs > 1.0) loc.flags |= HJB_FLAG_POSITIVITY;
     }
     int rc = HJB_OK;
     // Policy iteration.  While the policy may still change a solve only reduces the residual by pi_eta;
@@ -972,8 +974,10 @@ int step_impl(hjb_handle *hd, const double *Uprev, double *Unext, const double *
         loc.cert_bound = cert_den > 0 ? res / cert_den : INFINITY;
         if (rc != HJB_OK) break;
         // the search updates the policy in place (it reads only each node's own control)
+        int64_t near = 0;
         TRY(sweep(hd, Unext, Uprev, f0, f1, t_prev, dt, theta, acur, acur, nullptr, nullptr, nullptr, &changed,
-                  nullptr, 2, 2));
+                  nullptr, 2, 2, &near));
+        loc.n_near_ties = near;
         if (hd->trace)
             fprintf(stderr, "[slhjb] pi %d: krylov %d res %.3e tight %d changed %lld kept %lld\n", it, its, res,
                     (int)tight, (long long)changed, (long long)hd->kept_last);
@@ -985,6 +989,8 @@ int step_impl(hjb_handle *hd, const double *Uprev, double *Unext, const double *
         }
         if (it + 1 == hd->desc.max_pi) rc = fail(HJB_ENOCONV_PI, "policy iteration not converged after %d", it + 1);
     }
+    // the decisions of the last search are those of the returned policy
+    if (loc.n_near_ties > 0) loc.flags |= HJB_FLAG_NEAR_TIES;
     if (acur != alpha_io) {
         hipError_t e = hipMemcpyAsync(alpha_io, acur, (size_t)N * sizeof(int16_t), hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) rc = fail(HJB_EDEVICE, "copy policy: %s", hipGetErrorString(e));
@@ -1333,14 +1339,13 @@ int hjb_step(hjb_handle *hd, const double *Uprev, double *Unext, const double *f
     if (Uprev == Unext || Uprev2 == Unext) return fail(HJB_EINVAL, "Unext must differ from Uprev and Uprev2");
     if (Uprev2 && !(dt_prev > 0.0 && isfinite(dt_prev))) return fail(HJB_EINVAL, "dt_prev must be positive");
     TRY(check_time(dt, theta));
-    if (theta == 0.0) return fail(HJB_EUNSUPPORTED, "explicit steps (theta = 0) are not provided by hjb_step");
     TRY(build_tables(hd, s));
     return step_impl(hd, Uprev, Unext, f0, f1, t_prev, dt, theta, alpha_io, Uprev2, dt_prev, st);
 }
 
-int hjb_solve(hjb_handle *hd, const double *g, const double *psi, const double *f0, const double *f1, int32_t n_steps,
-              const double *dts, const double *thetas, double s, double *U_final, int16_t *policies,
-              double *values, hjb_solve_stats *st) {
+int hjb_solve(hjb_handle *hd, const double *g, const double *psi, const double *psi1, const double *f0,
+              const double *f1, int32_t n_steps, const double *dts, const double *thetas, double s, double *U_final,
+              int16_t *policies, double *values, hjb_solve_stats *st) {
     if (!hd) return fail(HJB_EINVAL, "null handle");
     if (!g || !psi || !f0 || !f1 || !dts || !thetas || !U_final) return fail(HJB_EINVAL, "null argument");
     if (n_steps < 0) return fail(HJB_EINVAL, "n_steps must be >= 0");
@@ -1358,13 +1363,18 @@ int hjb_solve(hjb_handle *hd, const double *g, const double *psi, const double *
     int rc = HJB_OK;
     if (values) HIPCHK(hipMemcpyAsync(values, g, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
     for (int n = 0; n < n_steps; ++n) {
-        HIPCHK(hipMemcpyAsync(Unx, psi, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
+        // boundary entries of U^n: psi(t_n) (the interior is overwritten by the step)
+        if (psi1)
+            launch_affine(psi, psi1, t + dts[n], Unx, N, str);
+        else
+            HIPCHK(hipMemcpyAsync(Unx, psi, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
         hjb_step_stats sst{};
         rc = step_impl(hd, Ucur, Unx, f0, f1, t, dts[n], thetas[n], acarry, n >= 1 ? Uold : nullptr,
                        n >= 1 ? dts[n - 1] : 0.0, &sst);
         loc.krylov_total += sst.krylov_total;
         loc.pi_total += sst.pi_iters;
         loc.flags |= sst.flags;
+        loc.near_ties_total += sst.n_near_ties;
         loc.max_cert_bound = std::max(loc.max_cert_bound, sst.cert_bound);
         if (rc != HJB_OK) break;
         if (policies) HIPCHK(hipMemcpyAsync(policies + (int64_t)n * N, acarry, (size_t)N * 2, hipMemcpyDeviceToDevice, str));
@@ -1845,6 +1855,13 @@ int hjb_apply_transposed(hjb_handle *hd, const int16_t *alpha, const double *x, 
     TransposeWork T;
     TRY(T.alloc(hd, 0, false, false));
     TRY(T.build(hd, 0, alpha));
+    // the same column gathers as the adjoint's transposed solves: matrix-free where the stencil window of a
+    // tile holds few untruncated controls (constant coefficients), the sorted listing elsewhere
+    T.wf = hd->desc.coef_model == HJB_COEF_CONST && !hd->desc.f_per_control;
+    if (T.wf) {
+        launch_tile_set(hd->dim, hd->lev[0].g, alpha, hd->desc.K, T.tset, hd->stream);
+        launch_window_set(hd->dim, hd->lev[0].g, T.tset, T.wset, hd->lev[0].reach, hd->stream);
+    }
     launch_apply_T(hd->dim, 0, hd->lev[0].g, stencil(hd, 0), alpha, T.view(), x, nullptr, theta * dt, y, nullptr,
                    hd->stream);
     HIPCHK(hipGetLastError());

@@ -138,12 +138,15 @@ __device__ __forceinline__ void point_Y(const StencilDev &st, const PointTab &p,
 
 // a kept decision needs its gap bound above this multiple of the search scale S (rounding of G is far below)
 constexpr double kSkipSlack = 1e-10;
+// a decision is a near tie when the second-best G is within kNearTie * tau of the best (several controls
+// within tau, or the runner-up closer than this): there several policies are correct results
+constexpr double kNearTie = 1e3;
 
 struct SweepOut {
     int16_t *alpha_out;
     double *gmin, *margin;
     int32_t *ties;
-    int64_t *changed_partial;  // [nblocks]
+    int64_t *changed_partial;  // [nblocks]: changed controls + (near ties << 32)
     // Certified reuse of decisions on untruncated wavefronts (constant coefficients, one diffusion pair).
     // skip 0: off; 1: record, per node, the gap between the second-best and the best G when the node's
     // control is the strict minimiser (-1 otherwise); 2: also keep the control of every wavefront whose
@@ -249,6 +252,7 @@ struct UpdateCoef {
 void launch_update_solution(double *X, const void *Z, bool z_float, int64_t ldz, int m, const double *y_host, int64_t N,
                             hipStream_t s);
 void launch_axpy(double *y, double a, const double *x, int64_t N, hipStream_t s);
+void launch_affine(const double *a, const double *b, double t, double *out, int64_t N, hipStream_t s);
 void launch_copy_interior(int dim, const LevelDev &g, const double *src, double *dst, hipStream_t s);
 void launch_zero(void *p, size_t bytes, hipStream_t s);
 void launch_extrapolate(int dim, const LevelDev &g, const double *U1, const double *U0, double ratio, double *out,

@@ -197,7 +197,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(LevelDev g, StencilDev st0, co
     const int64_t qstride = (int64_t)g.ntx * g.nty * g.ntz * kBlock;  // tiles of the grid, list or not
     int ix[3];
     int i = tile_node_at<DIM>(g, tile, ix);
-    int64_t changed = 0;
+    int64_t changed = 0, near = 0;
     // re-evaluations read the cache this thread has just written
     constexpr int QM2 = QM == 1 ? 2 : QM;
     if (i >= 0) {
@@ -235,6 +235,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep(LevelDev g, StencilDev st0, co
                 else
                     for (int k = 0; k < st.K; ++k) {
                         double G = eval_G<DIM, CN, QM>(g, st, k, i, ix, deep, X, Xi, U, Ui, theta, omt, fk(k), Q, qslot, qstride);
+                        const double hi = G < best ? best : G;  // second: the least G of the other controls
+                        second = hi < second ? hi : second;
                         if (G < best) {
                             best = G;
                             kbest = k;
@@ -258,6 +260,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(LevelDev g, StencilDev st0, co
                 o.alpha_out[i] = (int16_t)pick;
                 if (!EXTRA && o.skip) o.marg[i] = (fast && pick == kbest) ? second - best : -1.0;
                 changed = (pick != cur) ? 1 : 0;
+                near = (second - best < kNearTie * tau) ? 1 : 0;
                 if (o.gmin) o.gmin[i] = best;
                 if (EXTRA) {
                     double mg = __builtin_inf();
@@ -275,7 +278,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep(LevelDev g, StencilDev st0, co
             }
         }
     }
-    int64_t tot = block_reduce<int64_t>(changed, OpSum(), sh);
+    // changed controls in the low 32 bits, near ties in the high ones (either count is below 2^32)
+    int64_t tot = block_reduce<int64_t>(changed | (near << 32), OpSum(), sh);
     if (threadIdx.x == 0) o.changed_partial[tile] = tot;
 }
 
@@ -329,12 +333,12 @@ __global__ __launch_bounds__(kBlock) void k_norms_xuf(LevelDev g, const double *
     int i = tile_node<DIM>(g, ix);
     double vx = 0.0, vf = 0.0;
     if (i >= 0) {
-        vx = fmax(fabs(X[i]), fabs(U[i]));
+        vx = OpMax()(fabs(X[i]), fabs(U[i]));  // a NaN wins
         if (interior<DIM>(g, ix)) {
             if (fk == 0)
                 vf = fabs(f0[i] + t_mid * f1[i]);
             else
-                for (int k = 0; k < K; ++k) vf = fmax(vf, fabs(f0[k * fk + i] + t_mid * f1[k * fk + i]));
+                for (int k = 0; k < K; ++k) vf = OpMax()(vf, fabs(f0[k * fk + i] + t_mid * f1[k * fk + i]));
         }
     }
     int b = remap_block(blockIdx.x, gridDim.x);
@@ -1251,6 +1255,17 @@ __global__ __launch_bounds__(kBlock) void k_axpy(double *__restrict__ y, double 
 
 void launch_axpy(double *y, double a, const double *x, int64_t N, hipStream_t s) {
     hipLaunchKernelGGL(k_axpy, dim3(blocks_for(N)), dim3(kBlock), 0, s, y, a, x, N);
+}
+
+// out = a + t b on every node (time-dependent Dirichlet data psi(t) = psi0 + t psi1)
+__global__ __launch_bounds__(kBlock) void k_affine(const double *__restrict__ a, const double *__restrict__ b, double t,
+                                                   double *__restrict__ out, int64_t N) {
+    int64_t n = (int64_t)remap_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (n < N) out[n] = a[n] + t * b[n];
+}
+
+void launch_affine(const double *a, const double *b, double t, double *out, int64_t N, hipStream_t s) {
+    hipLaunchKernelGGL(k_affine, dim3(blocks_for(N)), dim3(kBlock), 0, s, a, b, t, out, N);
 }
 
 template <int DIM>

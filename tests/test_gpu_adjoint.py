@@ -85,6 +85,71 @@ def test_apply_transposed(slhjb, name, mk):
     solver.close()
 
 
+def _hub(pb, alpha, j, radius):
+    """Give every interior row near column j whose stencil (under some control) reaches j such a control, so that
+    column j of A collects far more entries than the sliced ELL holds (32 per column); the rest of the column
+    comes from the sorted listing."""
+    jx, jy = j % pb.n[0], j // pb.n[0]
+    hits = 0
+    for y in range(max(1, jy - radius), min(pb.n[1] - 1, jy + radius + 1)):
+        for x in range(max(1, jx - radius), min(pb.n[0] - 1, jx + radius + 1)):
+            i = x + pb.n[0] * y
+            for k in range(pb.K):
+                cols, vals = pb.row(i, k)
+                if np.any((cols == j) & (vals != 0.0)):
+                    alpha[i] = k
+                    hits += 1
+                    break
+    return hits
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("n", [513, 2049])
+def test_apply_transposed_full_size(slhjb, n):
+    """A^T x at the adjoint workload's grid (513^2) and the headline grid (2049^2) against the oracle's assembled
+    matrix on every node: the policy is the search's decision at the closed-form solution (piecewise constant, so
+    most tiles take the matrix-free reflected gather with one to four controls per window, stencil reach 23 and
+    45 cells), with one planted column of a few hundred entries that overflows the ELL width cap."""
+    inst = workloads.config_c3(n) if n == 513 else workloads.config_h(n)
+    pb = oracle.Problem(inst)
+    X0 = inst.coords()
+    t_prev, dt, th = 0.25, 1.0 / 64, 0.5
+    U = inst.exact(t_prev, X0)
+    X = inst.exact(t_prev + dt, X0)
+    X[pb.bd] = inst.psi[pb.bd]
+    f = pb.f_at(inst.f0, inst.f1, t_prev + th * dt)
+    a0 = np.zeros(inst.N, np.int16)
+    a0[pb.bd] = -1
+    alpha = pb.improve(X, U, th, f, pb.tau(X, U, f), a0, want_extra=False)["alpha"]
+    j = (n // 3) + inst.n[0] * (n // 2)
+    radius = int(np.ceil(np.max(np.abs(inst.sigma)) / np.sqrt(inst.h))) + 3
+    hits = _hub(pb, alpha, j, radius)
+    rng = np.random.default_rng(41)
+    x = rng.normal(size=inst.N)
+    x[pb.bd] = 0.0
+    y = rng.normal(size=inst.N)
+    y[pb.bd] = 0.0
+    solver = slhjb.Solver.from_instance(inst, slhjb.Options(precision=1))
+    da, dx = to_dev(alpha), to_dev(x)
+    ATx = torch.empty_like(dx)
+    Ay = torch.empty_like(dx)
+    solver.apply_transposed(da, dx, ATx, dt, th, 1.0)
+    solver.apply(da, to_dev(y), Ay, dt, th, 1.0)
+    ATx, Ay = to_np(ATx), to_np(Ay)
+    solver.close()
+    A = oracle._system_matrix(pb, pb.assemble(alpha).tocsr(), alpha, dt, th)
+    col_len = np.diff(A.tocsc().indptr)
+    log(f"apply_T {n}^2: hub column holds {hits} rows; longest column {col_len.max()} entries, "
+        f"{int(np.sum(col_len > 32))} columns beyond 32")
+    assert col_len.max() > 32
+    ref = np.zeros(inst.N)
+    ref[pb.interior] = A.T @ x[pb.interior]
+    assert np.all(ATx[pb.bd] == 0.0)
+    np.testing.assert_allclose(ATx, ref, rtol=0, atol=1e-13 * max(1.0, np.max(np.abs(ref))))
+    lhs, rhs = float(ATx @ y), float(x @ Ay)
+    assert abs(lhs - rhs) <= 1e-12 * (np.abs(ATx) @ np.abs(y))
+
+
 S_TEST = 0.93
 
 

@@ -11,6 +11,7 @@ import pytest
 import oracle
 import workloads
 from gpu_util import log, to_dev, to_np
+from policy_parity import check_march_policies
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -72,8 +73,9 @@ def test_batch_matches_oracle_and_single(slhjb, precision, max_levels):
     opts = slhjb.Options(precision=precision, max_levels=max_levels)
     Ub, pb, st = _run_batch(slhjb, insts, opts)
     for b, inst in enumerate(insts):
-        ref = oracle.march(inst, keep_policies=True)
+        ref = oracle.march(inst, keep_policies=True, keep_values=True)
         rel = np.max(np.abs(Ub[b] - ref["U"])) / np.max(np.abs(ref["U"]))
+        check_march_policies(inst, ref, pb[b], log=log)
         solver = slhjb.Solver.from_instance(inst, opts)
         g = to_dev(inst.g)
         U1 = torch.empty_like(g)
@@ -107,8 +109,9 @@ def test_batch_3d(slhjb):
     log("batch of 3D instances")
     Ub, pb, st = _run_batch(slhjb, insts, slhjb.Options(precision=1))
     for b, inst in enumerate(insts):
-        ref = oracle.march(inst)
+        ref = oracle.march(inst, keep_policies=True, keep_values=True)
         rel = np.max(np.abs(Ub[b] - ref["U"])) / np.max(np.abs(ref["U"]))
+        check_march_policies(inst, ref, pb[b], log=log)
         log(f"  {inst.name}: pi={st[b].pi_total} krylov={st[b].krylov_total} rel {rel:.2e}")
         assert rel <= 1e-10
 
@@ -139,7 +142,26 @@ def test_batch_mixed_coefficient_models(slhjb):
                       [0.125, 0.125], [1.0, 1.0])
     Ub, pb, st = _run_batch(slhjb, insts, slhjb.Options(precision=1))
     for b, inst in enumerate(insts):
-        ref = oracle.march(inst)
+        ref = oracle.march(inst, keep_policies=True, keep_values=True)
         rel = np.max(np.abs(Ub[b] - ref["U"])) / np.max(np.abs(ref["U"]))
+        check_march_policies(inst, ref, pb[b], log=log)
         log(f"  {inst.name}: pi={st[b].pi_total} krylov={st[b].krylov_total} rel {rel:.2e}")
         assert rel <= 1e-10
+
+
+@pytest.mark.timeout(400)
+def test_c4_batch_instances_match_oracle(slhjb):
+    """The uneven 64-instance two-asset batch (65^2 ... 513^2, 50 implicit steps) in one hjb_solve_batch; four of
+    its 65^2 instances against the oracle: values to the parity bound and policies at every clear decision."""
+    insts = workloads.config_c4()
+    log(f"C4 batch: {len(insts)} instances, {sum(i.N for i in insts)} nodes")
+    Ub, pb, st = _run_batch(slhjb, insts, slhjb.Options(precision=1))
+    small = [b for b, inst in enumerate(insts) if inst.n[0] == 65][:4]
+    for b in small:
+        inst = insts[b]
+        ref = oracle.march(inst, keep_policies=True, keep_values=True)
+        rel = np.max(np.abs(Ub[b] - ref["U"])) / np.max(np.abs(ref["U"]))
+        log(f"  instance {b} ({inst.n[0]}^2): batch pi={st[b].pi_total} krylov={st[b].krylov_total} rel {rel:.2e}")
+        assert st[b].steps_done == len(inst.dts)
+        assert rel <= 1e-10
+        check_march_policies(inst, ref, pb[b], log=log)

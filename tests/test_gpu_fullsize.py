@@ -3,7 +3,7 @@
 At these sizes the oracle does not solve, but it can (a) run its own search over every node, so the
 GPU search is compared bit for bit on the whole grid, and (b) recompute the residual of the discrete
 HJB system, max_k (A^k X - F^k)_i = X_i - U_i - dt * min_k G_k(X)_i, of a GPU step.  For these
-M-matrices with row sums >= 1 (Section 3.3) the infinity norm of that residual bounds |X - X*|_inf,
+M-matrices with row sums >= 1 (Section 3.4) the infinity norm of that residual bounds |X - X*|_inf,
 where X* is the exact discrete solution (eq. nonlinear_sys), so each GPU step is certified against
 it.  The oracle's search started from the GPU policy must also change nothing: the GPU policy is the
 tie rule's fixed point at X.
@@ -39,7 +39,7 @@ def _certify(inst, pb, Uprev, Unext, alpha, t_prev, dt, theta, res_gpu, rel_tol=
         f"oracle search changes {r['changed']}")
     assert r["changed"] == 0
     assert rinf <= res_gpu + dt * tau + 1e-14 * max(1.0, xinf)
-    # |X - X*|_inf <= |R|_inf for c = 0 (row sums of Section 3.3): the accuracy target
+    # |X - X*|_inf <= |R|_inf for c = 0 (row sums of Section 3.4): the accuracy target
     assert rinf <= rel_tol * max(1.0, xinf)
     return rinf
 
@@ -98,18 +98,22 @@ def _march_steps(slhjb, inst, n_steps, check_every=1, precision=1):
     return worst
 
 
-def test_h2049_steps_certified(slhjb):
-    """The first four steps of the benchmark march (two implicit half steps, two Crank-Nicolson)."""
+@pytest.mark.timeout(400)
+def test_h2049_march_certified(slhjb):
+    """All 65 solves of the benchmark march (two implicit half steps, 63 Crank-Nicolson steps) in the mixed
+    configuration; every 8th step (and the last) certified by the oracle."""
     inst = workloads.config_h(2049)
     log("2049^2 march, mixed precision")
-    _march_steps(slhjb, inst, 4)
+    _march_steps(slhjb, inst, len(inst.dts), check_every=8)
 
 
-def test_c5_129_steps_certified(slhjb):
-    """3D workload (129^3, 64 directions) in the mixed configuration."""
+@pytest.mark.timeout(400)
+def test_c5_129_march_certified(slhjb):
+    """3D workload (129^3, 64 directions), all 32 implicit steps in the mixed configuration; every 8th step
+    (and the last) certified by the oracle."""
     inst = workloads.config_c5(129)
     log("129^3 march, mixed precision")
-    _march_steps(slhjb, inst, 3)
+    _march_steps(slhjb, inst, len(inst.dts), check_every=8)
 
 
 def test_c2_257_full_march_certified(slhjb):

@@ -6,7 +6,8 @@ per step; implicit: to the 1e-10 parity bound).  On larger grids the GPU's L-inf
 over the whole grid are compared with the values the paper prints (tests/golden/paper_tables.json):
 Tab:Linf_matrix_40 / Tab:Linf_exp_trunc_40_B (explicit, truncation) and Tab:Linf_imp_trunc_40
 (implicit, truncation, dt = T), to the three digits printed, and the explicit scheme with dt = dx/4
-blows up at N_x = 321 as printed (Cor. cor:CFL).
+blows up at N_x = 321 as printed (Cor. cor:CFL).  The shifted box of Remark rem:two-over (time-dependent
+boundary data, two-sided overstepping) reproduces Table Tab:shifted, blow-ups included.
 """
 import json
 import math
@@ -34,6 +35,8 @@ def slhjb():
 
 def _make(prob, Nx, col, theta):
     h = 2 * math.pi / (Nx - 1)
+    if prob == "A-shifted":
+        return workloads.problem_a(Nx, dt=DTS[col](h), theta=theta, lo_shift=7 * math.pi / 8)
     mk = workloads.problem_a if prob == "A" else workloads.problem_b
     return mk(Nx, dt=DTS[col](h), theta=theta)
 
@@ -42,8 +45,9 @@ def _gpu_march(slhjb, inst, precision=0):
     solver = slhjb.Solver.from_instance(inst, slhjb.Options(precision=precision))
     g = to_dev(inst.g)
     U = torch.empty_like(g)
+    psi1 = None if inst.psi1 is None else to_dev(inst.psi1)
     st = solver.solve(g, to_dev(inst.psi), to_dev(np.ascontiguousarray(inst.f0)), to_dev(np.ascontiguousarray(inst.f1)),
-                      inst.dts, inst.thetas, inst.s, U)
+                      inst.dts, inst.thetas, inst.s, U, psi1=psi1)
     solver.close()
     return to_np(U), st
 
@@ -52,7 +56,7 @@ def _err(inst, U):
     return float(np.max(np.abs(U - inst.exact(inst.T, inst.coords()))))
 
 
-@pytest.mark.parametrize("prob", ["A", "B"])
+@pytest.mark.parametrize("prob", ["A", "B", "A-shifted"])
 @pytest.mark.parametrize("Nx,col", [(41, "dt=dx^2"), (41, "dt=T"), (81, "dt=dx^1.5")])
 def test_explicit_march_bit_exact(slhjb, prob, Nx, col):
     inst = _make(prob, Nx, col, 0.0)
@@ -121,3 +125,42 @@ def test_implicit_problem_b_report(slhjb, Nx):
     ref = GOLDEN["implicit_truncation_B"]["dt=T"][str(Nx)]
     log(f"implicit problem B N_x={Nx}: error {e:.3e} (paper {ref:.2e}, ratio {e / ref:.3f})")
     assert 0.5 * ref < e < 2.0 * ref
+
+
+def _shifted_err(inst, U):
+    X = inst.coords()
+    e = np.abs(U - inst.exact(inst.T, X))
+    lo, hi = 3 * math.pi / 8 - 1e-12, 11 * math.pi / 8 + 1e-12
+    m = (X[0] >= lo) & (X[0] <= hi) & (X[1] >= lo) & (X[1] <= hi)
+    return float(np.max(e)), float(np.max(e[m]))
+
+
+SHIFTED_CASES = [("dt=T", 161), ("dt=T", 321), ("dt=T", 641), ("dt=dx^2", 161), ("dt=dx^2", 321),
+                 ("dt=dx/4", 161), ("dt=dx^1.5", 161)]
+
+
+@pytest.mark.parametrize("col,Nx", SHIFTED_CASES, ids=[f"{c}-{n}" for c, n in SHIFTED_CASES])
+def test_shifted_domain_table_values(slhjb, col, Nx):
+    """Table Tab:shifted (Remark rem:two-over): Problem A on [-pi/8, 15pi/8]^2 with the time-dependent boundary
+    data psi(t) = (3/2 - t) sin x1 sin x2, explicit scheme with truncation.  Both sides of the diffusion stencil
+    overstep near the corner (-pi/8, -pi/8), so dt = dx/4 and dt = dx^(3/2) blow up (Cor. cor:CFL) while dt = dx^2
+    converges; whole-grid and interior errors to the three printed digits."""
+    inst = _make("A-shifted", Nx, col, 0.0)
+    U, st = _gpu_march(slhjb, inst)
+    whole, inner = _shifted_err(inst, U)
+    gw = GOLDEN["explicit_truncation_A_shifted"]["whole grid"][col][str(Nx)]
+    gi = GOLDEN["explicit_truncation_A_shifted"]["[3pi/8, 11pi/8]^2"][col][str(Nx)]
+    log(f"shifted problem A {col} N_x={Nx}: {len(inst.dts)} steps, errors {whole:.3e} / {inner:.3e} "
+        f"(paper {gw:.2e} / {gi:.2e})")
+    assert whole == pytest.approx(gw, rel=6e-3)
+    assert inner == pytest.approx(gi, rel=6e-3)
+
+
+def test_shifted_domain_blowup_at_321(slhjb):
+    """dt = dx/4 at N_x = 321 on the shifted box: the paper prints 6.73e+103 (whole grid) and 7.99e+47 (interior)."""
+    inst = _make("A-shifted", 321, "dt=dx/4", 0.0)
+    U, st = _gpu_march(slhjb, inst)
+    whole, inner = _shifted_err(inst, U)
+    log(f"shifted problem A dt=dx/4 N_x=321: errors {whole:.3e} / {inner:.3e}")
+    assert not np.isfinite(whole) or whole > 1e90
+    assert not np.isfinite(inner) or inner > 1e40

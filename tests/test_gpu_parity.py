@@ -12,6 +12,7 @@ import pytest
 import oracle
 import workloads
 from gpu_util import log, to_dev, to_np
+from policy_parity import check_march_policies
 
 pytestmark = pytest.mark.gpu
 
@@ -200,31 +201,32 @@ def test_linsolve_long_arnoldi(slhjb, restart):
 
 
 def _march_compare(slhjb, inst, opts=None, tol=1e-10):
-    ref = oracle.march(inst, keep_policies=True)
+    """Values within tol of the oracle at the end, policies identical at every clear decision of every
+    step, and every GPU step the tie rule's fixed point with a certified discrete HJB residual."""
+    ref = oracle.march(inst, keep_policies=True, keep_values=True)
     solver = slhjb.Solver.from_instance(inst, opts)
     g, psi, f0, f1 = to_dev(inst.g), to_dev(inst.psi), to_dev(inst.f0), to_dev(inst.f1)
     U = torch.empty_like(g)
     pol = torch.empty((len(inst.dts), inst.N), dtype=torch.int16, device=g.device)
-    st = solver.solve(g, psi, f0, f1, inst.dts, inst.thetas, inst.s, U, pol)
+    vals = torch.empty((len(inst.dts) + 1, inst.N), dtype=torch.float64, device=g.device)
+    psi1 = None if inst.psi1 is None else to_dev(inst.psi1)
+    st = solver.solve(g, psi, f0, f1, inst.dts, inst.thetas, inst.s, U, pol, vals, psi1=psi1)
     Ug = to_np(U)
     rel = np.max(np.abs(Ug - ref["U"])) / np.max(np.abs(ref["U"]))
     log(f"  {inst.name}: steps={st.steps_done} krylov={st.krylov_total} pi={st.pi_total} rel={rel:.2e}")
     assert st.steps_done == len(inst.dts)
     assert rel <= tol, rel
-    # policies: identical wherever the oracle's decision is not a certified near-tie
-    pb = oracle.Problem(inst)
-    pg = to_np(pol)
-    mism = 0
-    for n in range(len(inst.dts)):
-        mism += int(np.sum(pg[n] != ref["policies"][n]))
+    vg = to_np(vals)
+    steps_rel = np.max(np.abs(vg - ref["values"]), axis=1) / np.maximum(np.max(np.abs(ref["values"]), axis=1), 1e-300)
+    assert np.all(steps_rel <= tol), steps_rel
+    near = check_march_policies(inst, ref, to_np(pol), vg, s=inst.s, log=log)
     solver.close()
-    return rel, mism
+    return rel, near
 
 
 def test_march_c1(slhjb):
     inst = workloads.config_c1(33)
-    rel, mism = _march_compare(slhjb, inst)
-    log(f"  policy mismatches (near-ties) = {mism}")
+    _march_compare(slhjb, inst)
 
 
 @pytest.mark.parametrize("max_levels", [2, 0], ids=["two-level", "deep"])
@@ -232,14 +234,20 @@ def test_march_c1(slhjb):
 def test_march_c2_small(slhjb, precision, max_levels):
     """65^2 Crank-Nicolson march: the default two-level hierarchy and the full one (65, 33, 17)."""
     inst = workloads.config_c2(65, n_cn=8)
-    rel, mism = _march_compare(slhjb, inst, slhjb.Options(precision=precision, max_levels=max_levels))
-    log(f"  policy mismatches (near-ties) = {mism}")
+    _march_compare(slhjb, inst, slhjb.Options(precision=precision, max_levels=max_levels))
 
 
 def test_march_c5_small(slhjb):
     inst = workloads.config_c5(17, n_steps=4)
-    rel, mism = _march_compare(slhjb, inst, slhjb.Options(precision=1))
-    log(f"  policy mismatches (near-ties) = {mism}")
+    _march_compare(slhjb, inst, slhjb.Options(precision=1))
+
+
+@pytest.mark.timeout(400)
+def test_march_c5_33(slhjb):
+    """The 3D workload at the oracle's stated size (33^3, 64 Fibonacci-hemisphere directions), its first four
+    implicit steps: values, every step's policy and fixed point."""
+    inst = workloads.config_c5(33, n_steps=4)
+    _march_compare(slhjb, inst, slhjb.Options(precision=1))
 
 
 def test_march_ragged_no_coarsening(slhjb):
@@ -251,13 +259,49 @@ def test_march_ragged_no_coarsening(slhjb):
 def test_march_c4_xscaled(slhjb, precision):
     """Two-asset x-scaled instance at 65^2, all 50 implicit steps."""
     inst = workloads.c4_instance(65, 0.12, 0.29, 0.35, 0.02)
-    rel, mism = _march_compare(slhjb, inst, slhjb.Options(precision=precision))
-    log(f"  policy mismatches (near-ties) = {mism}")
+    _march_compare(slhjb, inst, slhjb.Options(precision=precision))
 
 
 def test_march_xscaled_ragged(slhjb):
     inst = _xscaled_toy((30, 27), seed=9)
     _march_compare(slhjb, inst, slhjb.Options(precision=1))
+
+
+NEAR_CASES = [("c1_33", lambda: workloads.config_c1(33)), ("c2_65_cn", lambda: workloads.config_c2(65, n_cn=4)),
+              ("problem_b_41", lambda: workloads.problem_b(41, dt=0.125))]
+
+
+@pytest.mark.parametrize("name,mk", NEAR_CASES, ids=[c[0] for c in NEAR_CASES])
+def test_step_near_tie_count(slhjb, name, mk):
+    """hjb_step reports the near ties of its returned policy: interior nodes whose second-best G_k lies within
+    1e3 * tau of the best.  The count equals the oracle's at the GPU's own values (identical searches), and the
+    flag is set exactly when it is non-zero.  Problem B's Hamiltonian does not depend on the control in the
+    continuum, so nearly every node is a near tie there."""
+    inst = mk()
+    pb = oracle.Problem(inst)
+    solver = slhjb.Solver.from_instance(inst, slhjb.Options(precision=1))
+    g, psi = to_dev(inst.g), to_dev(inst.psi)
+    f0, f1 = to_dev(np.ascontiguousarray(inst.f0)), to_dev(np.ascontiguousarray(inst.f1))
+    Ua, Ub = g.clone(), psi.clone()
+    alpha = torch.zeros(inst.N, dtype=torch.int16, device="cuda")
+    t = 0.0
+    for n in range(min(3, len(inst.dts))):
+        Ub.copy_(psi)
+        dt, th = float(inst.dts[n]), float(inst.thetas[n])
+        st = solver.step(Ua, Ub, f0, f1, t, dt, th, 1.0, alpha)
+        Uprev, X = to_np(Ua), to_np(Ub)
+        f = pb.f_at(inst.f0, inst.f1, t + th * dt)
+        tau = pb.tau(X, Uprev, f)
+        r = pb.improve(X, Uprev, th, f, tau, to_np(alpha), want_extra=True)
+        I = pb.interior
+        near = int(np.sum(((r["ties"] > 1) | (r["margin"] < 1e3 * tau))[I]))
+        log(f"  {name} step {n}: near ties gpu {st.n_near_ties} oracle {near} of {I.size}, flags {st.flags}")
+        assert r["changed"] == 0
+        assert st.n_near_ties == near
+        assert bool(st.flags & slhjb.FLAG_NEAR_TIES) == (near > 0)
+        t += dt
+        Ua, Ub = Ub, Ua
+    solver.close()
 
 
 @pytest.mark.parametrize("max_levels", [2, 0], ids=["two-level", "deep"])

@@ -4,7 +4,7 @@ Each test ties a part of the oracle to something other than the oracle itself:
 the consistency conditions the truncation weights were derived from
 (eqs. AB_drift, AB1, AB2), the properties of multilinear interpolation
 (eq. monotone_int_2), the row-sum identity after eq. Lhat, the row and
-column sums of Section 3.3, the characterisation of the discrete HJB solution
+column sums of Section 3.4, the characterisation of the discrete HJB solution
 as the minimum over all policies, the discrete maximum principle, and the
 error tables the paper prints for Problems A and B (Section 2.4).
 """
@@ -214,12 +214,12 @@ def test_evaluator_matches_listing():
 
 
 # ---------------------------------------------------------------------------
-# Matrix properties (Section 1 and Section 3.3)
+# Matrix properties (Section 1 and Section 3.4)
 # ---------------------------------------------------------------------------
 
 def test_system_matrix_is_m_matrix_with_row_sums():
     """A^alpha = I - theta dt (L + c): positive diagonal, non-positive off-diagonal,
-    full row sums 1 - theta dt c (Section 3.3, row sums)."""
+    full row sums 1 - theta dt c (Section 3.4, row sums)."""
     inst = _toy(n=(12, 11), K=5, P=1, seed=8, c=True)
     pb = oracle.Problem(inst)
     alpha = workloads.random_policy(inst, 2)
@@ -282,7 +282,9 @@ def test_tie_rule_smallest_index_and_hysteresis():
 
 
 @pytest.mark.parametrize("theta,cfg", [(1.0, dict(n=(5, 5), K=3, seed=11)), (0.5, dict(n=(5, 5), K=3, seed=12)),
-                                       (1.0, dict(n=(6, 6), K=2, seed=13, c=True))])
+                                       (1.0, dict(n=(6, 6), K=2, seed=13, c=True)),
+                                       (0.5, dict(n=(6, 6), K=2, seed=14, c=True)),
+                                       (0.3, dict(n=(5, 5), K=3, seed=15, c=True))])
 def test_policy_iteration_equals_brute_force(theta, cfg):
     """The discrete solution is the componentwise minimum of (A^alpha)^{-1} F^alpha over all policies
     (M-matrix systems, eq. nonlinear_sys); policy iteration must reach it exactly."""
@@ -295,6 +297,24 @@ def test_policy_iteration_equals_brute_force(theta, cfg):
     Vb = oracle.brute_force_step(pb, inst.g, inst.psi, inst.f0, inst.f1, 0.2, dt, theta)
     np.testing.assert_allclose(V, Vb, rtol=1e-11, atol=1e-11)
     assert st.pi_iters >= 1
+
+
+@pytest.mark.parametrize("theta", [1.0, 0.5, 0.25])
+def test_explicit_part_on_constants(theta):
+    """Rows of L-hat sum to zero (interpolation reproduces constants and the weights A, B, C enter as
+    A v+ + B v- - (A+B) v_i), so for U = 1 on every node the known part of eq. FullScheme is
+    1 + (1-theta) dt c + dt f, which fixes the discount term of the explicit part in closed form."""
+    inst = _toy(n=(9, 8), K=4, P=1, seed=21, drift=True, c=True)
+    pb = oracle.Problem(inst)
+    rng = np.random.default_rng(22)
+    alpha = rng.integers(0, inst.K, size=pb.N).astype(np.int16)
+    alpha[pb.bd] = -1
+    dt = 0.07
+    f = inst.f0 + 0.3 * inst.f1
+    E = oracle.explicit_part(pb, pb.assemble(alpha), alpha, np.ones(pb.N), f, dt, theta)
+    I = pb.interior
+    expect = 1.0 + (1.0 - theta) * dt * inst.c[alpha[I]] + dt * f[I]
+    np.testing.assert_allclose(E[I], expect, rtol=0, atol=1e-13)
 
 
 def test_policy_iteration_equals_brute_force_xscaled():
@@ -481,3 +501,34 @@ def test_s_central_difference_is_converged():
     a = oracle.ds_central_difference(inst, pols, lam, 0.93, eps=1e-5)
     b = oracle.ds_central_difference(inst, pols, lam, 0.93, eps=5e-6)
     assert abs(a - b) <= 1e-7 * max(1.0, abs(a))
+
+
+# ---------------------------------------------------------------------------
+# Shifted domain with time-dependent Dirichlet data (Remark rem:two-over, Table Tab:shifted)
+# ---------------------------------------------------------------------------
+
+SHIFTED = GOLDEN["explicit_truncation_A_shifted"]
+
+
+def _shifted_errors(Nx, col):
+    h = 2 * math.pi / (Nx - 1)
+    dt = {"dt=T": 0.5, "dt=dx/4": h / 4, "dt=dx^1.5": h ** 1.5, "dt=dx^2": h * h}[col]
+    inst = workloads.problem_a(Nx, dt=dt, theta=0.0, lo_shift=7 * math.pi / 8)
+    out = oracle.march(inst)
+    X = inst.coords()
+    e = np.abs(out["U"] - inst.exact(inst.T, X))
+    lo, hi = 3 * math.pi / 8 - 1e-12, 11 * math.pi / 8 + 1e-12
+    m = (X[0] >= lo) & (X[0] <= hi) & (X[1] >= lo) & (X[1] <= hi)
+    return float(np.max(e)), float(np.max(e[m]))
+
+
+@pytest.mark.parametrize("Nx,col", [(41, "dt=T"), (41, "dt=dx/4"), (41, "dt=dx^1.5"), (41, "dt=dx^2"),
+                                    (81, "dt=T"), (81, "dt=dx/4"), (81, "dt=dx^1.5"), (81, "dt=dx^2")])
+def test_shifted_domain_explicit_table(Nx, col):
+    """On the box [-pi/8, 15pi/8]^2 the boundary data (3/2 - t) sin x1 sin x2 move with t and both sides of the
+    diffusion stencil overstep near the corner where sigma = (-1, 1): the explicit scheme then needs
+    dt ~ dx^2 (Cor. cor:CFL, second condition).  Whole-grid and interior errors of Table Tab:shifted, including
+    the blow-ups for dt = dx/4 and dx^(3/2) at N_x = 81."""
+    whole, inner = _shifted_errors(Nx, col)
+    assert whole == pytest.approx(SHIFTED["whole grid"][col][str(Nx)], rel=6e-3)
+    assert inner == pytest.approx(SHIFTED["[3pi/8, 11pi/8]^2"][col][str(Nx)], rel=6e-3)

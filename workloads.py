@@ -16,7 +16,8 @@ Conventions
 * A control k carries P diffusion columns sigma[k, p, :] (a = 1/2 sigma sigma^T,
   eq. (1.1) and the definition of L), a drift b[k, :] and a discount c[k].
 * The source is affine in time and the same for every control unless stated:
-  f(t, x) = f0(x) + t * f1(x).  Problem B of Section 2.4 has a
+  f(t, x) = f0(x) + t * f1(x).  Dirichlet data are constant in time unless psi1
+  is given: psi(t, x) = psi(x) + t * psi1(x) (the shifted-domain Problem A).  Problem B of Section 2.4 has a
   control-dependent source; it is given as f0[k, :], f1[k, :].
 * A time schedule is a list of (dt_n, theta_n).
 """
@@ -46,7 +47,7 @@ class Instance:
     f0: np.ndarray               # (N,) or (K, N)
     f1: np.ndarray               # (N,) or (K, N)
     g: np.ndarray                # (N,) initial data u(0, x)
-    psi: np.ndarray              # (N,) Dirichlet data on the boundary nodes
+    psi: np.ndarray              # (N,) Dirichlet data on the boundary nodes (at t = 0 when psi1 is given)
     dts: np.ndarray              # (n_steps,)
     thetas: np.ndarray           # (n_steps,)
     s: float = 1.0               # volatility scale multiplying sigma
@@ -54,6 +55,7 @@ class Instance:
     coef_model: str = "const"    # "const": sigma, drift per control; "xscaled": sigma_k(x) = diag(x) S_k,
                                  # b_k(x) = diag(x) beta_k with S = sigma (K, P, dim), beta = drift (K, dim)
     exact: Optional[callable] = None          # closed-form u(t, X) if known, X = coordinate arrays
+    psi1: Optional[np.ndarray] = None         # (N,) time-dependent Dirichlet data psi(t) = psi + t * psi1
     meta: dict = dataclasses.field(default_factory=dict)
 
     @property
@@ -275,8 +277,12 @@ def problem_a(Nx: int, dt: Optional[float] = None, theta: float = 1.0, n_alpha: 
     inst.f0 = 0.5 * s1 * s2 + 1.5 * br
     inst.f1 = -s1 * s2 - br
     inst.g = 1.5 * s1 * s2
-    inst.psi = (1.5 - 0.0) * s1 * s2 * inst.boundary_mask()   # u on the boundary (zero on [-pi,pi]^2)
-    inst.meta["psi_t"] = lambda t, X: (1.5 - t) * np.sin(X[0]) * np.sin(X[1])
+    # u on the boundary: (3/2 - t) s1 s2, i.e. psi + t psi1 (zero up to rounding on [-pi,pi]^2; the shifted
+    # box of Remark rem:two-over has non-zero, time-dependent boundary data)
+    bd = inst.boundary_mask()
+    inst.psi = 1.5 * s1 * s2 * bd
+    if lo_shift != 0.0:
+        inst.psi1 = -(s1 * s2) * bd
     inst.exact = lambda t, X: (1.5 - t) * np.sin(X[0]) * np.sin(X[1])
     return inst
 

@@ -174,6 +174,24 @@ int hjb_policy_sweep(hjb_handle *hd, const double *X, const double *U, const dou
                      const int16_t *alpha_in, int16_t *alpha_out, double *gmin, double *margin, int32_t *ties,
                      int64_t *n_changed, double *tau_used);
 
+/* hjb_policy_sweep for callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same arguments, kernels and results, bit for bit, but the search's
+ * own scratch (block partials of the tolerance, tau, the per-tile change counts and their sums) lives in a static
+ * 1 MiB device array that the library holds on each GPU until the process ends, instead of the handle's buffers.
+ * No hipMalloc, hipFree or other allocating routine is called.
+ *   - The handle comes from hjb_setup (which allocates, once); its stencil tables must already be those of s
+ *     (s = 1 after setup, else the s of the handle's latest call of another entry point): HJB_EINVAL otherwise.
+ *   - Grids needing more than the 1 MiB (about 43,000 tiles of 256 nodes, e.g. 3300 x 3300 in 2D) give HJB_EINVAL.
+ *   - Every call on one GPU shares that GPU's array: calls that overlap in time on one GPU (other streams, other
+ *     threads, other handles) race and must be serialised by the caller.  Every value the search reads from the
+ *     array is written earlier in the same call, so what a previous call left there does not matter.
+ *   - Without n_changed and tau_used nothing is read back and the call only enqueues work on the stream.
+ */
+int hjb_policy_sweep_noalloc(hjb_handle *hd, const double *X, const double *U, const double *f0, const double *f1,
+                             double t_prev, double dt, double theta, double s, const int16_t *alpha_in,
+                             int16_t *alpha_out, double *gmin, double *margin, int32_t *ties, int64_t *n_changed,
+                             double *tau_used);
+
 /* y = A^alpha x for the fixed-policy matrix of eq. FullScheme restricted to interior nodes,
    (A x)_i = x_i - theta*dt*((L^{alpha_i} x)_i + c x_i), reading boundary entries of x as given
    (pass zeros there for the matrix itself).  y is written on interior nodes and zeroed on the boundary.

@@ -24,7 +24,8 @@ COEF_CONST, COEF_XSCALED, COEF_FIELD = 0, 1, 2
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_VCYCLE = 0, 1, 2
 FLAG_POSITIVITY, FLAG_NEAR_TIES = 1, 2
 
-EXPORTED = ["hjb_desc_default", "hjb_setup", "hjb_set_stream", "hjb_set_options", "hjb_policy_sweep", "hjb_apply",
+EXPORTED = ["hjb_desc_default", "hjb_setup", "hjb_set_stream", "hjb_set_options", "hjb_policy_sweep",
+            "hjb_policy_sweep_noalloc", "hjb_apply",
             "hjb_linsolve", "hjb_step", "hjb_solve", "hjb_adjoint", "hjb_apply_transposed", "hjb_profile_enable",
             "hjb_profile_read", "hjb_profile_sample", "hjb_destroy", "hjb_last_error", "hjb_setup_batch", "hjb_batch_layout",
             "hjb_batch_set_stream", "hjb_solve_batch", "hjb_destroy_batch", "hjb_set_tile_width", "hjb_autotune"]
@@ -88,6 +89,8 @@ def _load():
     L.hjb_set_options.argtypes = [vp, ctypes.POINTER(Desc)]
     L.hjb_policy_sweep.argtypes = [vp, vp, vp, vp, vp, d, d, d, d, vp, vp, vp, vp, vp,
                                    ctypes.POINTER(i64), ctypes.POINTER(d)]
+    L.hjb_policy_sweep_noalloc.argtypes = [vp, vp, vp, vp, vp, d, d, d, d, vp, vp, vp, vp, vp,
+                                           ctypes.POINTER(i64), ctypes.POINTER(d)]
     L.hjb_apply.argtypes = [vp, vp, vp, vp, d, d, d]
     L.hjb_linsolve.argtypes = [vp, vp, vp, vp, vp, d, d, d, d, vp, ctypes.POINTER(StepStats)]
     L.hjb_step.argtypes = [vp, vp, vp, vp, vp, d, d, d, d, vp, vp, d, ctypes.POINTER(StepStats)]
@@ -268,6 +271,19 @@ class Solver:
                                      float(theta), float(s), _ptr(alpha_in), _ptr(alpha_out), _ptr(gmin),
                                      _ptr(margin), _ptr(ties), ctypes.byref(nch), ctypes.byref(tau)))
         return int(nch.value), float(tau.value)
+
+    def policy_sweep_noalloc(self, X, U, f0, f1, t_prev, dt, theta, s, alpha_in, alpha_out,
+                             gmin=None, margin=None, ties=None, read_back=True):
+        """hjb_policy_sweep_noalloc (scratch in the library's static device array); returns (n_changed, tau),
+        or (None, None) without read-back."""
+        self._sync_stream()
+        nch = ctypes.c_int64(0)
+        tau = ctypes.c_double(0.0)
+        _check(_lib.hjb_policy_sweep_noalloc(self._h, _ptr(X), _ptr(U), _ptr(f0), _ptr(f1), float(t_prev), float(dt),
+                                             float(theta), float(s), _ptr(alpha_in), _ptr(alpha_out), _ptr(gmin),
+                                             _ptr(margin), _ptr(ties), ctypes.byref(nch) if read_back else None,
+                                             ctypes.byref(tau) if read_back else None))
+        return (int(nch.value), float(tau.value)) if read_back else (None, None)
 
     def apply(self, alpha, x, y, dt, theta, s=1.0):
         self._sync_stream()

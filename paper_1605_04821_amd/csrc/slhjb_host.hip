@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <functional>
 #include <memory>
+#include <mutex>
 #include <type_traits>
 #include <string>
 #include <vector>
@@ -79,6 +80,7 @@ struct Level {
 
 struct hjb_handle {
     hjb_desc desc{};
+    int device = 0;        // the GPU current at setup (its copy of the allocation-free scratch)
     std::vector<double> sigma, drift, c;
     bool has_drift = false;
     int npt = 0, M = 0;
@@ -814,22 +816,36 @@ __global__ void k_sweep_tau_arg(const double *tau_dev, double *tau_copy) {
     if (threadIdx.x == 0) tau_copy[0] = tau_dev[0];
 }
 
+// Device buffers of one search: block partials of the tolerance's maxima [2 nb], tau and S [2], per-tile
+// counts [nb] and their sums [2].  By default the handle's own; the allocation-free entry point passes
+// slices of its static scratch.
+struct SweepScratch {
+    double *partial;
+    double *tauS;
+    int64_t *ipartial;
+    int64_t *ival;
+};
+
 int sweep(hjb_handle *hd, const double *X, const double *U, const double *f0, const double *f1, double t_prev,
           double dt, double theta, const int16_t *a_in, int16_t *a_out, double *gmin, double *margin, int32_t *ties,
-          int64_t *n_changed, double *tau_used, int qmode = 0, int skip = 0, int64_t *n_near = nullptr) {
+          int64_t *n_changed, double *tau_used, int qmode = 0, int skip = 0, int64_t *n_near = nullptr,
+          const SweepScratch *sc = nullptr) {
     hipStream_t s = hd->stream;
     const Level &L0 = hd->lev[0];
     double t_mid = t_prev + theta * dt;
+    const SweepScratch own{hd->partial, hd->dvals + 4, hd->ipartial, hd->ival};
+    const SweepScratch &B = sc ? *sc : own;
     // decisions are reused only where the search keeps no per-node extras and the tables are fixed; the
-    // reusing search runs in place
-    if (!hd->marg || !hd->desc.certified_skip || gmin || margin || ties || hd->desc.coef_model != HJB_COEF_CONST ||
-        hd->desc.f_per_control || hd->desc.P != 1)
+    // reusing search runs in place (and keeps its bookkeeping in handle buffers: never with outside scratch)
+    if (sc || !hd->marg || !hd->desc.certified_skip || gmin || margin || ties ||
+        hd->desc.coef_model != HJB_COEF_CONST || hd->desc.f_per_control || hd->desc.P != 1)
         skip = 0;
+    if (sc) qmode = 0;
     if (skip == 2 && a_in != a_out) skip = 1;
-    launch_norms_xuf(hd->dim, L0.g, X, U, f0, f1, t_mid, hd->desc.K, stencil(hd, 0).fk, hd->partial, hd->nb, s);
+    launch_norms_xuf(hd->dim, L0.g, X, U, f0, f1, t_mid, hd->desc.K, stencil(hd, 0).fk, B.partial, hd->nb, s);
     double inv2h = 0.5 / hd->desc.h;
     double coefA = 2.0 * hd->M * inv2h + hd->cmax;
-    hipLaunchKernelGGL(k_tau, dim3(1), dim3(1024), 0, s, hd->partial, hd->nb, coefA, hd->desc.tau_rel, hd->dvals + 4);
+    hipLaunchKernelGGL(k_tau, dim3(1), dim3(1024), 0, s, B.partial, hd->nb, coefA, hd->desc.tau_rel, B.tauS);
     if (skip == 1) {
         launch_delta_tiles(hd->dim, L0.g, X, hd->Xs, hd->dtile, true, s);
     } else if (skip == 2) {
@@ -842,7 +858,7 @@ int sweep(hjb_handle *hd, const double *X, const double *U, const double *f0, co
                          hd->ipartial, s);
         launch_tile_list(hd->need, hd->nb, hd->tlist, hd->tlist + hd->nb_cap, s);
     }
-    SweepOut o{a_out, gmin, margin, ties, hd->ipartial, skip, hd->marg, hd->keep,
+    SweepOut o{a_out, gmin, margin, ties, B.ipartial, skip, hd->marg, hd->keep,
                skip == 2 ? hd->tlist : nullptr, skip == 2 ? hd->tlist + hd->nb_cap : nullptr};
     if (!hd->Q) qmode = 0;
     // algorithmic FP64 work of the untruncated stencil per control and field: each point is a 2^d-corner
@@ -859,15 +875,15 @@ int sweep(hjb_handle *hd, const double *X, const double *U, const double *f0, co
     {
         TimedLaunch tl(hd, HJB_KERNEL_SWEEP, bytes_all, flops_all);
         slot = tl.slot;
-        launch_sweep(hd->dim, L0.g, stencil(hd, 0), X, U, f0, f1, t_mid, theta, hd->dvals + 4, a_in, o, hd->Q, qmode,
+        launch_sweep(hd->dim, L0.g, stencil(hd, 0), X, U, f0, f1, t_mid, theta, B.tauS, a_in, o, hd->Q, qmode,
                      hd->nb, s);
     }
     HIPCHK(hipGetLastError());
     hd->kept_last = 0;
     if (n_changed || tau_used || n_near || skip == 2) {
-        launch_reduce_sum_i64(hd->ipartial, hd->nb, hd->ival, s);
-        if (skip == 2) launch_reduce_sum_i64(hd->kpartial, hd->nb, hd->ival + 1, s);
-        TRY(publish_wait(hd, hd->ival, hd->hpin_i, 2 * sizeof(int64_t), hd->dvals + 4, hd->hpin + 4, sizeof(double)));
+        launch_reduce_sum_i64(B.ipartial, hd->nb, B.ival, s);
+        if (skip == 2) launch_reduce_sum_i64(hd->kpartial, hd->nb, B.ival + 1, s);
+        TRY(publish_wait(hd, B.ival, hd->hpin_i, 2 * sizeof(int64_t), B.tauS, hd->hpin + 4, sizeof(double)));
         // the search's partials hold the changed controls in their low 32 bits and the near ties above
         if (n_changed) *n_changed = hd->hpin_i[0] & 0xffffffffll;
         if (n_near) *n_near = (int64_t)((uint64_t)hd->hpin_i[0] >> 32);
@@ -1043,6 +1059,50 @@ const char *hjb_last_error(void) { return g_err.c_str(); }
 namespace {
 
 // tables_only: level geometry and stencil tables, no work vectors (instances of a batch)
+// ---- allocation-free search ----------------------------------------------------------------------
+// The scratch of hjb_policy_sweep_noalloc (see SweepScratch), one copy per GPU for the life of the process.
+// In host code `scratch` names a host-side stand-in; the device address of each GPU's copy is looked up once
+// per device (at the first setup on it) and only that address is used.
+constexpr size_t kNoAllocScratchBytes = (size_t)1 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// slices of the scratch for a search over nb tiles: [partial 2nb | tau, S | ipartial nb | ival 2], each
+// 256-byte aligned; the bytes needed (may exceed the scratch: checked by the caller)
+size_t noalloc_layout(char *base, int nb, SweepScratch *sc) {
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    size_t off = 0;
+    const size_t o_partial = off;
+    off += up((size_t)2 * nb * 8);
+    const size_t o_tau = off;
+    off += up(2 * 8);
+    const size_t o_ip = off;
+    off += up((size_t)nb * 8);
+    const size_t o_iv = off;
+    off += up(2 * 8);
+    if (sc && base) {
+        sc->partial = (double *)(base + o_partial);
+        sc->tauS = (double *)(base + o_tau);
+        sc->ipartial = (int64_t *)(base + o_ip);
+        sc->ival = (int64_t *)(base + o_iv);
+    }
+    return off;
+}
+
+// device address of the current GPU's scratch (looked up once per device)
+int scratch_init(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(HJB_EDEVICE, "device id %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return HJB_OK;
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(HJB_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+    return HJB_OK;
+}
+
 int setup_impl(const hjb_desc *desc, hjb_handle **out, bool tables_only) {
     g_err.clear();
     if (!desc || !out) return fail(HJB_EINVAL, "null argument");
@@ -1233,6 +1293,12 @@ int setup_impl(const hjb_desc *desc, hjb_handle **out, bool tables_only) {
         *hd->hflag = 0u;
     }
     STRY(build_tables(hd, 1.0));
+    {
+        // this GPU's copy of the allocation-free scratch
+        hipError_t e = hipGetDevice(&hd->device);
+        if (e != hipSuccess) return cleanup_fail(fail(HJB_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e)));
+        STRY(scratch_init(hd->device));
+    }
 #undef STRY
     *out = hd;
     return HJB_OK;
@@ -1289,6 +1355,38 @@ int hjb_policy_sweep(hjb_handle *hd, const double *X, const double *U, const dou
     int64_t ch = 0;
     TRY(sweep(hd, X, U, f0, f1, t_prev, dt, theta, alpha_in, alpha_out, gmin, margin, ties, n_changed ? &ch : nullptr,
               tau_used));
+    if (n_changed) *n_changed = ch;
+    return HJB_OK;
+}
+
+int hjb_policy_sweep_noalloc(hjb_handle *hd, const double *X, const double *U, const double *f0, const double *f1,
+                             double t_prev, double dt, double theta, double s, const int16_t *alpha_in,
+                             int16_t *alpha_out, double *gmin, double *margin, int32_t *ties, int64_t *n_changed,
+                             double *tau_used) {
+    if (!hd) return fail(HJB_EINVAL, "null handle");
+    if (!X || !U || !f0 || !f1 || !alpha_in || !alpha_out) return fail(HJB_EINVAL, "null array argument");
+    if (!finite_param(t_prev)) return fail(HJB_EINVAL, "t_prev must be finite");
+    TRY(check_time(dt, theta));
+    // building tables for another s allocates host memory: the tables must already be those of s
+    if (s != hd->s_tab)
+        return fail(HJB_EINVAL, "allocation-free search: the handle's stencil tables are built for s = %.17g, not %.17g "
+                                "(one call of another entry point with this s builds them)", hd->s_tab, s);
+    const size_t need = noalloc_layout(nullptr, hd->nb, nullptr);
+    if (need > kNoAllocScratchBytes)
+        return fail(HJB_EINVAL, "allocation-free search: %d tiles need %zu bytes of scratch, the limit is %zu "
+                                "(about %zu tiles)", hd->nb, need, kNoAllocScratchBytes,
+                    (kNoAllocScratchBytes - 1024) / 24);
+    void *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        base = (hd->device >= 0 && hd->device < kMaxDevices) ? g_scratch_ptr[hd->device] : nullptr;
+    }
+    if (!base) return fail(HJB_EDEVICE, "allocation-free scratch not set up on device %d", hd->device);
+    SweepScratch sc{};
+    noalloc_layout((char *)base, hd->nb, &sc);
+    int64_t ch = 0;
+    TRY(sweep(hd, X, U, f0, f1, t_prev, dt, theta, alpha_in, alpha_out, gmin, margin, ties, n_changed ? &ch : nullptr,
+              tau_used, 0, 0, nullptr, &sc));
     if (n_changed) *n_changed = ch;
     return HJB_OK;
 }

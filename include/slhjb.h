@@ -59,6 +59,7 @@ enum {
 };
 enum { HJB_PREC_FP64 = 0, HJB_PREC_MIXED = 1 }; /* V-cycle in FP64, or in FP32 under FP64 FGMRES */
 enum { HJB_PRECOND_NONE = 0, HJB_PRECOND_JACOBI = 1, HJB_PRECOND_VCYCLE = 2 };
+enum { HJB_KRYLOV_FGMRES = 0, HJB_KRYLOV_BICGSTAB = 1 };  /* outer FP64 Krylov method of the linear solves */
 /* Flags of hjb_step_stats / hjb_solve_stats (bitwise or). */
 enum {
     HJB_FLAG_POSITIVITY = 1,  /* positivity of the weights (eq. CFL_trunc) may fail: theta < 1 and
@@ -109,6 +110,7 @@ typedef struct {
     int32_t coarse_sweeps_t; /* damped Jacobi sweeps on the coarsest level of the transposed V-cycles of the
                                adjoint (0: coarse_sweeps; a single-level hierarchy always takes coarse_sweeps);
                                0..1000 */
+    int32_t krylov;         /* HJB_KRYLOV_FGMRES (default) or HJB_KRYLOV_BICGSTAB for the forward linear solves */
     void *stream;           /* hipStream_t */
 } hjb_desc;
 

@@ -22,6 +22,7 @@ HJB_ENOCONV_KRYLOV, HJB_ENOCONV_PI, HJB_ENONFINITE, HJB_EUNSUPPORTED = -4, -5, -
 PREC_FP64, PREC_MIXED = 0, 1
 COEF_CONST, COEF_XSCALED, COEF_FIELD = 0, 1, 2
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_VCYCLE = 0, 1, 2
+KRYLOV_FGMRES, KRYLOV_BICGSTAB = 0, 1
 FLAG_POSITIVITY, FLAG_NEAR_TIES = 1, 2
 
 EXPORTED = ["hjb_desc_default", "hjb_setup", "hjb_set_stream", "hjb_set_options", "hjb_policy_sweep",
@@ -52,6 +53,7 @@ class Desc(ctypes.Structure):
                 ("pi_eta", ctypes.c_double), ("use_graphs", ctypes.c_int32), ("f_per_control", ctypes.c_int32),
                 ("certified_skip", ctypes.c_int32), ("max_levels", ctypes.c_int32),
                 ("nu_tight", ctypes.c_int32), ("coarse_sweeps_t", ctypes.c_int32),
+                ("krylov", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
 
 
@@ -171,6 +173,7 @@ class Options:
     max_levels: int = 2
     nu_tight: int = 4
     coarse_sweeps_t: int = 2
+    krylov: int = 0
 
 
 class Solver:
@@ -230,6 +233,7 @@ class Solver:
         desc.max_levels = o.max_levels
         desc.nu_tight = o.nu_tight
         desc.coarse_sweeps_t = o.coarse_sweeps_t
+        desc.krylov = o.krylov
 
     @classmethod
     def from_instance(cls, inst, options: Optional[Options] = None):

@@ -34,6 +34,11 @@ __device__ __forceinline__ int tile_node(const LevelDev &g, int ix[3]) {
     return tile_node_at<DIM>(g, remap_block(blockIdx.x, gridDim.x), ix);
 }
 
+// the wave-control table entry of this thread's wavefront (-1 without a table), read through the scalar unit
+__device__ __forceinline__ int wave_control(const int16_t *__restrict__ wctl, int tile) {
+    return wctl ? (int)wctl[tile * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)] : -1;
+}
+
 template <int DIM>
 __device__ __forceinline__ void unflatten(const LevelDev &g, int i, int ix[3]) {
     if (DIM == 2) {

@@ -74,6 +74,12 @@ struct Level {
     int reach[3] = {0, 0, 0};    // largest stencil corner offset in nodes along each axis (any control)
     double *lii = nullptr;       // device [K]: StencilDev::lii_deep of this level
     bool lii_ok = false;         // lii holds the current tables' values (constant coefficients, deep nodes exist)
+    // wave-control table of the current policy (tiles x 4 wavefronts) and the per-control deep diagonal in
+    // both precisions, written with the diagonal; valid (wctl_ok) after prepare_mg when lii_ok
+    int16_t *wctl = nullptr;
+    float *dk32 = nullptr;
+    double *dk64 = nullptr;
+    bool wctl_ok = false;
 };
 
 }  // namespace
@@ -215,6 +221,7 @@ void fill_tables(hjb_handle *hd, double s, std::vector<PointTab> &host, int leve
 
 StencilDev stencil(const hjb_handle *hd, int level);
 void drop_graphs(hjb_handle *hd);
+int tiles_cap(const LevelDev &g0, int dim);
 
 int build_tables(hjb_handle *hd, double s) {
     if (hd->s_tab == s) return HJB_OK;
@@ -374,6 +381,8 @@ int check_options(const hjb_desc *d) {
     if (d->max_levels < 0) return fail(HJB_EINVAL, "max_levels must be >= 0");
     if (d->nu_tight < 0 || d->nu_tight > 16) return fail(HJB_EINVAL, "nu_tight in 0..16");
     if (d->coarse_sweeps_t < 0 || d->coarse_sweeps_t > 1000) return fail(HJB_EINVAL, "coarse_sweeps_t in 0..1000");
+    if (d->krylov != HJB_KRYLOV_FGMRES && d->krylov != HJB_KRYLOV_BICGSTAB) return fail(HJB_EINVAL, "krylov");
+    if (d->krylov == HJB_KRYLOV_BICGSTAB) return fail(HJB_EUNSUPPORTED, "BiCGSTAB is not available yet");
     return HJB_OK;
 }
 
@@ -388,10 +397,14 @@ int prepare_mg(hjb_handle *hd, const int16_t *alpha, double theta_dt) {
         launch_inject_policy(hd->dim, hd->lev[l - 1].g, hd->lev[l].g, hd->lev[l - 1].alpha, hd->lev[l].alpha, s);
     for (size_t l = 0; l < hd->lev.size(); ++l) {
         Level &L = hd->lev[l];
+        const StencilDev st = stencil(hd, (int)l);
+        L.wctl_ok = L.wctl && st.lii_deep;
         if (mixed(hd))
-            launch_diag<float>(hd->dim, L.g, stencil(hd, (int)l), L.alpha, theta_dt, (float *)L.d, s);
+            launch_diag<float>(hd->dim, L.g, st, L.alpha, theta_dt, (float *)L.d, s, L.wctl_ok ? L.wctl : nullptr,
+                               L.dk32);
         else
-            launch_diag<double>(hd->dim, L.g, stencil(hd, (int)l), L.alpha, theta_dt, (double *)L.d, s);
+            launch_diag<double>(hd->dim, L.g, st, L.alpha, theta_dt, (double *)L.d, s, L.wctl_ok ? L.wctl : nullptr,
+                                L.dk64);
     }
     HIPCHK(hipGetLastError());
     return HJB_OK;
@@ -403,9 +416,12 @@ void smooth_level(hjb_handle *hd, int l, T *&e, T *&t, const T *r, int sweeps, b
     StencilDev st = stencil(hd, l);
     for (int q = 0; q < sweeps; ++q) {
         bool gathers = !(first && q == 0);
-        TimedLaunch tl(hd, (l == 0 && gathers) ? HJB_KERNEL_SMOOTH : -1, (double)L.g.N * (4.0 * sizeof(T) + 2.0));
+        // algorithmic bytes: e, r, alpha in, e out (the diagonal is a derived quantity, not counted)
+        TimedLaunch tl(hd, (l == 0 && gathers) ? HJB_KERNEL_SMOOTH : -1, (double)L.g.N * (3.0 * sizeof(T) + 2.0));
+        const T *dk = nullptr;
+        if constexpr (std::is_same<T, float>::value) dk = L.dk32; else dk = L.dk64;
         launch_jacobi<T>(hd->dim, L.g, st, L.alpha, e, r, (const T *)L.d, t, theta_dt, hd->desc.omega,
-                         first && q == 0, hd->stream);
+                         first && q == 0, hd->stream, L.wctl_ok ? L.wctl : nullptr, dk);
         std::swap(e, t);
     }
 }
@@ -443,7 +459,8 @@ void vcycle(hjb_handle *hd, const T *r0, T *z, double theta_dt) {
         smooth_level<T>(hd, l, e[l], t[l], r[l], hd->nu_pre, true, theta_dt);
         {
             TimedLaunch tl(hd, l == 0 ? HJB_KERNEL_MG_RESID : -1, (double)L.g.N * (3.0 * sizeof(T) + 2.0));
-            launch_level_residual<T>(hd->dim, L.g, stencil(hd, l), L.alpha, e[l], r[l], t[l], theta_dt, s);
+            launch_level_residual<T>(hd->dim, L.g, stencil(hd, l), L.alpha, e[l], r[l], t[l], theta_dt, s,
+                                     L.wctl_ok ? L.wctl : nullptr);
         }
         launch_restrict<T>(hd->dim, L.g, hd->lev[l + 1].g, t[l], (T *)hd->lev[l + 1].r, s);
     }
@@ -753,11 +770,15 @@ int fgmres(hjb_handle *hd, const int16_t *alpha, const double *E, double *X, dou
     const StencilDev st = stencil(hd, 0);
     hipStream_t s = hd->stream;
     KrylovOp op;
-    op.residual = [=]() { launch_residual(dim, L0.g, st, alpha, X, E, theta_dt, hd->R, hd->partial, hd->nb, s); };
+    // the level-0 wave-control table of prepare_mg belongs to this solve's policy
+    const int16_t *wctl = (L0.wctl_ok && L0.alpha == alpha) ? L0.wctl : nullptr;
+    op.residual = [=]() {
+        launch_residual(dim, L0.g, st, alpha, X, E, theta_dt, hd->R, hd->partial, hd->nb, s, wctl);
+    };
     // the application reads the handle's stream when it runs: it may be captured into a V-cycle's graph
     op.apply = [=](const void *z, bool zf, double *w) {
         TimedLaunch tl(hd, HJB_KERNEL_APPLY, (double)hd->N * ((zf ? 4.0 : 8.0) + 2.0 + 8.0));
-        launch_apply(dim, L0.g, st, alpha, z, zf, w, theta_dt, nullptr, hd->nb, hd->stream);
+        launch_apply(dim, L0.g, st, alpha, z, zf, w, theta_dt, nullptr, hd->nb, hd->stream, wctl);
     };
     if (hd->desc.precond != HJB_PRECOND_NONE)
         op.precond = [=](const double *v, void *z, bool ready) { return precondition(hd, v, z, theta_dt, ready); };
@@ -859,7 +880,7 @@ int sweep(hjb_handle *hd, const double *X, const double *U, const double *f0, co
         launch_tile_list(hd->need, hd->nb, hd->tlist, hd->tlist + hd->nb_cap, s);
     }
     SweepOut o{a_out, gmin, margin, ties, B.ipartial, skip, hd->marg, hd->keep,
-               skip == 2 ? hd->tlist : nullptr, skip == 2 ? hd->tlist + hd->nb_cap : nullptr};
+               skip == 2 ? hd->tlist : nullptr, skip == 2 ? hd->tlist + hd->nb_cap : nullptr, n_near ? 1 : 0};
     if (!hd->Q) qmode = 0;
     // algorithmic FP64 work of the untruncated stencil per control and field: each point is a 2^d-corner
     // weighted sum (2^(d+1) - 1 flops), each diffusion pair adds 4, the drift 3, the 1/(2h) scaling 1
@@ -990,10 +1011,11 @@ int step_impl(hjb_handle *hd, const double *Uprev, double *Unext, const double *
         loc.cert_bound = cert_den > 0 ? res / cert_den : INFINITY;
         if (rc != HJB_OK) break;
         // the search updates the policy in place (it reads only each node's own control)
+        // near ties are counted by the searches that may end the step: those after a solve to the certificate
         int64_t near = 0;
         TRY(sweep(hd, Unext, Uprev, f0, f1, t_prev, dt, theta, acur, acur, nullptr, nullptr, nullptr, &changed,
-                  nullptr, 2, 2, &near));
-        loc.n_near_ties = near;
+                  nullptr, 2, 2, tight ? &near : nullptr));
+        if (tight) loc.n_near_ties = near;
         if (hd->trace)
             fprintf(stderr, "[slhjb] pi %d: krylov %d res %.3e tight %d changed %lld kept %lld\n", it, its, res,
                     (int)tight, (long long)changed, (long long)hd->kept_last);
@@ -1049,6 +1071,7 @@ void hjb_desc_default(hjb_desc *d) {
     d->max_levels = 2;
     d->nu_tight = 4;
     d->coarse_sweeps_t = 2;
+    d->krylov = HJB_KRYLOV_FGMRES;
     d->stream = nullptr;
 }
 
@@ -1204,6 +1227,9 @@ int setup_impl(const hjb_desc *desc, hjb_handle **out, bool tables_only) {
         STRY(dalloc(hd, (void **)&L.fastF, (size_t)d.K * hd->npt * sizeof(FastPtF)));
         STRY(dalloc(hd, (void **)&L.fastD, (size_t)d.K * hd->npt * sizeof(FastPtD)));
         STRY(dalloc(hd, (void **)&L.lii, (size_t)d.K * sizeof(double)));
+        STRY(dalloc(hd, (void **)&L.wctl, (size_t)tiles_cap(L.g, d.dim) * (kBlock / 64) * sizeof(int16_t)));
+        STRY(dalloc(hd, (void **)&L.dk32, (size_t)d.K * sizeof(float)));
+        STRY(dalloc(hd, (void **)&L.dk64, (size_t)d.K * sizeof(double)));
         if (d.coef_model == HJB_COEF_FIELD) {
             // per-node sigma on this level: the finest level's value at the coinciding node
             const int pd = d.P * d.dim, stp = 1 << l;
@@ -1338,6 +1364,7 @@ int hjb_set_options(hjb_handle *hd, const hjb_desc *desc) {
     d.certified_skip = desc->certified_skip;
     d.nu_tight = desc->nu_tight;
     d.coarse_sweeps_t = desc->coarse_sweeps_t;
+    d.krylov = desc->krylov;
     select_precision(hd);
     set_sweeps(hd, false);
     drop_graphs(hd);
@@ -1812,6 +1839,8 @@ struct TransposeHierarchy {
     }
     int build(hjb_handle *hd, const int16_t *alpha, double theta_dt) {
         hipStream_t s = hd->stream;
+        // the level policies change: the forward kernels' per-policy tables no longer apply
+        for (Level &L : hd->lev) L.wctl_ok = false;
         hd->lev[0].alpha = const_cast<int16_t *>(alpha);
         for (size_t l = 1; l < lev.size(); ++l)
             launch_inject_policy(hd->dim, hd->lev[l - 1].g, hd->lev[l].g, hd->lev[l - 1].alpha, hd->lev[l].alpha, s);

@@ -160,6 +160,7 @@ struct SweepOut {
     // changed counts of the other tiles to the keep pass
     const int32_t *list;
     const int32_t *list_count;
+    int32_t count_near;    // also count near ties (high 32 bits of changed_partial)
 };
 
 // largest |X - Xs| over each tile (dtile[tile], record == 0), then Xs = X on the tile
@@ -187,9 +188,14 @@ void launch_norms_xuf(int dim, const LevelDev &g, const double *X, const double 
 void launch_explicit_update(int dim, const LevelDev &g, const double *U, const double *gmin, double dt, double *out,
                             hipStream_t s);
 
+// Wave-control table (wctl, nullable): per wavefront of the tile mapping, the control shared by all its 64 nodes
+// when all are untruncated interior nodes, else -1; written by launch_diag for the level's current policy.  With
+// it the node kernels read neither the policy nor the diagonal on such wavefronts.
+
 // y = x - theta dt (L x + c x) on interior nodes, 0 on the boundary (x may be float or double)
 void launch_apply(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const void *x,
-                  bool x_is_float, double *y, double theta_dt, double *norm2_partial, int nblocks, hipStream_t s);
+                  bool x_is_float, double *y, double theta_dt, double *norm2_partial, int nblocks, hipStream_t s,
+                  const int16_t *wctl = nullptr);
 
 // E = U + (1-theta) dt (L U + c U) + dt (f0 + t_mid f1)
 void launch_explicit(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const double *U,
@@ -198,20 +204,24 @@ void launch_explicit(int dim, const LevelDev &g, const StencilDev &st, const int
 
 // r = E - (V - theta dt (L V + c V)); partials: [3][nblocks] = sum r^2, max|r|, max|V| (interior)
 void launch_residual(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const double *V,
-                     const double *E, double theta_dt, double *r, double *partial, int nblocks, hipStream_t s);
+                     const double *E, double theta_dt, double *r, double *partial, int nblocks, hipStream_t s,
+                     const int16_t *wctl = nullptr);
 
 // multigrid level kernels, T = float or double
+// d = diagonal of A on the level; with wctl (ignored without per-control deep values) also the wave-control
+// table and dk[k], the diagonal at untruncated nodes of control k
 template <typename T>
 void launch_diag(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, double theta_dt, T *d,
-                 hipStream_t s);
+                 hipStream_t s, int16_t *wctl = nullptr, T *dk = nullptr);
 // per-control table of StencilDev::lii_deep, evaluated at the deep node ix0 of the level (K entries)
 void launch_lii_deep(int dim, const LevelDev &g, const StencilDev &st, const int ix0[3], double *out, hipStream_t s);
 template <typename T>
 void launch_jacobi(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const T *e, const T *r,
-                   const T *d, T *e_out, double theta_dt, double omega, bool first, hipStream_t s);
+                   const T *d, T *e_out, double theta_dt, double omega, bool first, hipStream_t s,
+                   const int16_t *wctl = nullptr, const T *dk = nullptr);
 template <typename T>
 void launch_level_residual(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const T *e,
-                           const T *r, T *res, double theta_dt, hipStream_t s);
+                           const T *r, T *res, double theta_dt, hipStream_t s, const int16_t *wctl = nullptr);
 template <typename T>
 void launch_restrict(int dim, const LevelDev &gf, const LevelDev &gc, const T *rf, T *rc, hipStream_t s);
 template <typename T>

@@ -164,8 +164,10 @@ __device__ __forceinline__ void search_deep(const LevelDev &g, const StencilDev 
 }
 
 // PN: per-node coefficients or per-control sources; otherwise those fields are known to be zero here,
-// so the constant-coefficient search compiles without their code (and keeps its register budget)
-template <int DIM, bool CN, bool EXTRA, int QM, bool PN>
+// so the constant-coefficient search compiles without their code (and keeps its register budget).
+// NEAR: also count near ties (the runner-up within kNearTie * tau of the best); a separate instantiation
+// because keeping the runner-up alive costs the search a wave of occupancy.
+template <int DIM, bool CN, bool EXTRA, int QM, bool PN, bool NEAR = false>
 __global__ __launch_bounds__(kBlock) void k_sweep(LevelDev g, StencilDev st0, const double *__restrict__ X,
                                                   const double *__restrict__ U, const double *__restrict__ f0,
                                                   const double *__restrict__ f1, double t_mid, double theta,
@@ -235,8 +237,10 @@ __global__ __launch_bounds__(kBlock) void k_sweep(LevelDev g, StencilDev st0, co
                 else
                     for (int k = 0; k < st.K; ++k) {
                         double G = eval_G<DIM, CN, QM>(g, st, k, i, ix, deep, X, Xi, U, Ui, theta, omt, fk(k), Q, qslot, qstride);
-                        const double hi = G < best ? best : G;  // second: the least G of the other controls
-                        second = hi < second ? hi : second;
+                        if (NEAR) {
+                            const double hi = G < best ? best : G;  // second: the least G of the other controls
+                            second = hi < second ? hi : second;
+                        }
                         if (G < best) {
                             best = G;
                             kbest = k;
@@ -260,7 +264,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(LevelDev g, StencilDev st0, co
                 o.alpha_out[i] = (int16_t)pick;
                 if (!EXTRA && o.skip) o.marg[i] = (fast && pick == kbest) ? second - best : -1.0;
                 changed = (pick != cur) ? 1 : 0;
-                near = (second - best < kNearTie * tau) ? 1 : 0;
+                if (NEAR) near = (second - best < kNearTie * tau) ? 1 : 0;
                 if (o.gmin) o.gmin[i] = best;
                 if (EXTRA) {
                     double mg = __builtin_inf();
@@ -292,10 +296,18 @@ void launch_sweep_dim(const LevelDev &g, const StencilDev &st, const double *X, 
     const bool pn = st.pernode || st.fk;
     // with a work list, whole groups of 8 blocks (one per XCD) cover the tiles
     const int grid = o.list ? (tiles_for(g) + 7) / 8 * 8 : tiles_for(g);
+    // near ties are counted on request by the lean (no per-node extras) searches
+    const bool near = o.count_near && !extra;
 #define SW(C, E, QQ)                                                                                                  \
     do {                                                                                                              \
-        if (pn)                                                                                                       \
+        if (pn && near)                                                                                               \
+            SLHJB_LAUNCH((k_sweep<DIM, C, E, QQ, true, !E>), dim3(grid), dim3(kBlock), 0, s, g, st, X, U, f0, f1,     \
+                         t_mid, theta, tau, a_in, o, Q);                                                              \
+        else if (pn)                                                                                                  \
             SLHJB_LAUNCH((k_sweep<DIM, C, E, QQ, true>), dim3(grid), dim3(kBlock), 0, s, g, st, X, U, f0, f1,         \
+                         t_mid, theta, tau, a_in, o, Q);                                                              \
+        else if (near)                                                                                                \
+            SLHJB_LAUNCH((k_sweep<DIM, C, E, QQ, false, !E>), dim3(grid), dim3(kBlock), 0, s, g, st, X, U, f0, f1,    \
                          t_mid, theta, tau, a_in, o, Q);                                                              \
         else                                                                                                          \
             SLHJB_LAUNCH((k_sweep<DIM, C, E, QQ, false>), dim3(grid), dim3(kBlock), 0, s, g, st, X, U, f0, f1,        \
@@ -363,13 +375,22 @@ void launch_norms_xuf(int dim, const LevelDev &g, const double *X, const double 
 template <int DIM, typename TX>
 __global__ __launch_bounds__(kBlock) void k_apply(LevelDev g, StencilDev st0, const int16_t *__restrict__ alpha,
                                                   const TX *__restrict__ x, double *__restrict__ y, double theta_dt,
-                                                  double *norm2_partial) {
+                                                  double *norm2_partial, const int16_t *__restrict__ wctl) {
     __shared__ double sh[kBlock / 64];
     const StencilDev &st = st0;
+    const int tile = remap_block(blockIdx.x, gridDim.x);
     int ix[3];
-    int i = tile_node<DIM>(g, ix);
+    int i = tile_node_at<DIM>(g, tile, ix);
     double yy = 0.0;
-    if (i >= 0) {
+    const int wc = i >= 0 ? wave_control(wctl, tile) : -1;
+    if (wc >= 0) {
+        double xi = (double)x[i];
+        double l, unused;
+        lhat_node<DIM, TX, double, false>(g, st, wc, i, ix, true, x, xi, x, xi, l, unused);
+        double ck = st.c ? st.c[wc] : 0.0;
+        yy = xi - theta_dt * (l + ck * xi);
+        y[i] = yy;
+    } else if (i >= 0) {
         if (interior<DIM>(g, ix)) {
             int k = alpha[i];
             bool deep = deep_node<DIM>(g, ix);
@@ -387,9 +408,10 @@ __global__ __launch_bounds__(kBlock) void k_apply(LevelDev g, StencilDev st0, co
 }
 
 void launch_apply(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const void *x,
-                  bool x_is_float, double *y, double theta_dt, double *norm2_partial, int nblocks, hipStream_t s) {
+                  bool x_is_float, double *y, double theta_dt, double *norm2_partial, int nblocks, hipStream_t s,
+                  const int16_t *wctl) {
 #define AP(D, TX) SLHJB_LAUNCH((k_apply<D, TX>), dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, \
-                               (const TX *)x, y, theta_dt, norm2_partial)
+                               (const TX *)x, y, theta_dt, norm2_partial, wctl)
     if (x_is_float) {
         if (dim == 2) AP(2, float); else AP(3, float);
     } else {
@@ -439,13 +461,24 @@ void launch_explicit(int dim, const LevelDev &g, const StencilDev &st, const int
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_residual(LevelDev g, StencilDev st0, const int16_t *__restrict__ alpha,
                                                      const double *__restrict__ V, const double *__restrict__ E,
-                                                     double theta_dt, double *__restrict__ r, double *partial) {
+                                                     double theta_dt, double *__restrict__ r, double *partial,
+                                                     const int16_t *__restrict__ wctl) {
     __shared__ double sh[kBlock / 64];
     const StencilDev &st = st0;
+    const int tile = remap_block(blockIdx.x, gridDim.x);
     int ix[3];
-    int i = tile_node<DIM>(g, ix);
+    int i = tile_node_at<DIM>(g, tile, ix);
     double rr = 0.0, vv = 0.0;
-    if (i >= 0) {
+    const int wc = i >= 0 ? wave_control(wctl, tile) : -1;
+    if (wc >= 0) {
+        const double Vi = V[i], Ei = E[i];
+        vv = fabs(Vi);
+        double l, unused;
+        lhat_node<DIM, double, double, false>(g, st, wc, i, ix, true, V, Vi, V, Vi, l, unused);
+        double ck = st.c ? st.c[wc] : 0.0;
+        rr = Ei - (Vi - theta_dt * (l + ck * Vi));
+        r[i] = rr;
+    } else if (i >= 0) {
         double Vi = V[i];
         vv = fabs(Vi);
         if (interior<DIM>(g, ix)) {
@@ -468,11 +501,14 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev g, StencilDev st0,
 }
 
 void launch_residual(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const double *V,
-                     const double *E, double theta_dt, double *r, double *partial, int nblocks, hipStream_t s) {
+                     const double *E, double theta_dt, double *r, double *partial, int nblocks, hipStream_t s,
+                     const int16_t *wctl) {
     if (dim == 2)
-        hipLaunchKernelGGL(k_residual<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, V, E, theta_dt, r, partial);
+        hipLaunchKernelGGL(k_residual<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, V, E, theta_dt, r, partial,
+                           wctl);
     else
-        hipLaunchKernelGGL(k_residual<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, V, E, theta_dt, r, partial);
+        hipLaunchKernelGGL(k_residual<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, V, E, theta_dt, r, partial,
+                           wctl);
 }
 
 // number of interior nodes whose control index is outside [0, K)
@@ -543,22 +579,46 @@ __device__ double diag_lii(const LevelDev &g, const StencilDev &st, int k, const
 // diagonal of A = I - theta dt (L-hat + c) on one level: d = 1 - theta dt (l_ii + c).  At deep nodes of the
 // constant-coefficient model no point is truncated and every displacement is the table's, so l_ii is the
 // per-control value diag_lii gives at any deep node (same operations, same rounding): read from the table.
+// With wctl (constant coefficients, per-control deep values available): also the wave-control table of this
+// level and policy, wctl[tile * 4 + wave] = the control shared by all 64 nodes of the wavefront when every one
+// of them is an untruncated interior node, else -1, and dk[k] = the diagonal at untruncated nodes of control k
+// (the same operations as d[i] there, so dk[alpha_i] == d[i] bit for bit).  The node kernels then read neither
+// the policy nor the diagonal on such wavefronts.
 template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) void k_diag(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
-                                                 double theta_dt, T *__restrict__ d) {
+                                                 double theta_dt, T *__restrict__ d, int16_t *__restrict__ wctl,
+                                                 T *__restrict__ dk) {
+    const int tile = remap_block(blockIdx.x, gridDim.x);
     int ix[3];
-    int i = tile_node<DIM>(g, ix);
-    if (i < 0) return;
-    if (!interior<DIM>(g, ix)) {
-        d[i] = (T)1;
-        return;
+    const int i = tile_node_at<DIM>(g, tile, ix);
+    int k = -1;
+    bool uni = false;  // an untruncated interior node (its diagonal is the per-control value)
+    if (i >= 0) {
+        if (!interior<DIM>(g, ix)) {
+            d[i] = (T)1;
+        } else {
+            k = alpha[i];
+            k = ((unsigned)k < (unsigned)st.K) ? k : 0;
+            uni = st.lii_deep && deep_node<DIM>(g, ix);
+            double lii = uni ? st.lii_deep[k] : diag_lii<DIM>(g, st, k, ix, i);
+            lii *= st.inv2h;
+            double ck = st.c ? st.c[((unsigned)k < (unsigned)st.K) ? k : 0] : 0.0;
+            d[i] = (T)(1.0 - theta_dt * (lii + ck));
+        }
     }
-    int k = alpha[i];
-    k = ((unsigned)k < (unsigned)st.K) ? k : 0;
-    double lii = (st.lii_deep && deep_node<DIM>(g, ix)) ? st.lii_deep[k] : diag_lii<DIM>(g, st, k, ix, i);
-    lii *= st.inv2h;
-    double ck = st.c ? st.c[((unsigned)k < (unsigned)st.K) ? k : 0] : 0.0;
-    d[i] = (T)(1.0 - theta_dt * (lii + ck));
+    if (wctl) {
+        // every lane takes part: lanes outside the grid make the wavefront non-uniform
+        const int k0 = __shfl(k, 0, 64);
+        const bool all = __all(uni && k == k0);
+        if ((threadIdx.x & 63) == 0) wctl[tile * (kBlock / 64) + (threadIdx.x >> 6)] = all ? (int16_t)k0 : (int16_t)-1;
+        if (blockIdx.x == 0)
+            for (int q = threadIdx.x; q < st.K; q += blockDim.x) {
+                double lii = st.lii_deep[q];
+                lii *= st.inv2h;
+                double ck = st.c ? st.c[q] : 0.0;
+                dk[q] = (T)(1.0 - theta_dt * (lii + ck));
+            }
+    }
 }
 
 template <int DIM>
@@ -580,12 +640,13 @@ void launch_lii_deep(int dim, const LevelDev &g, const StencilDev &st, const int
 
 template <typename T>
 void launch_diag(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, double theta_dt, T *d,
-                 hipStream_t s) {
+                 hipStream_t s, int16_t *wctl, T *dk) {
     int nb = tiles_for(g);
+    if (!st.lii_deep) wctl = nullptr;
     if (dim == 2)
-        hipLaunchKernelGGL((k_diag<2, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, theta_dt, d);
+        hipLaunchKernelGGL((k_diag<2, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, theta_dt, d, wctl, dk);
     else
-        hipLaunchKernelGGL((k_diag<3, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, theta_dt, d);
+        hipLaunchKernelGGL((k_diag<3, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, theta_dt, d, wctl, dk);
 }
 
 template <int DIM, typename T>
@@ -603,13 +664,30 @@ template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(DIM == 2 ? 8 : 1))) void k_jacobi(LevelDev g, StencilDev st0, const int16_t *__restrict__ alpha,
                                                    const T *__restrict__ e, const T *__restrict__ r,
                                                    const T *__restrict__ d, T *__restrict__ e_out, T theta_dt, T omega,
-                                                   int first) {
+                                                   int first, const int16_t *__restrict__ wctl,
+                                                   const T *__restrict__ dk) {
     const StencilDev &st = st0;
+    const int tile = remap_block(blockIdx.x, gridDim.x);
     int ix[3];
-    int i = tile_node<DIM>(g, ix);
+    int i = tile_node_at<DIM>(g, tile, ix);
     if (i < 0) return;
     T v = (T)0;
-    if (interior<DIM>(g, ix)) {
+    const int wc = wave_control(wctl, tile);
+    if (wc >= 0) {
+        // a wavefront of untruncated interior nodes with one control: the control and the diagonal come from
+        // the tables (the same values the per-node path reads), the arithmetic is that path's
+        const T di = dk[wc];
+        if (first) {
+            v = omega * r[i] / di;
+        } else {
+            const T ei = e[i], ri = r[i];
+            const double ck = st.c ? st.c[wc] : 0.0;
+            T l, unused;
+            lhat_node<DIM, T, T, false>(g, st, wc, i, ix, true, e, ei, e, ei, l, unused);
+            const T ae = ei - theta_dt * (l + (T)ck * ei);
+            v = ei + omega * (ri - ae) / di;
+        }
+    } else if (interior<DIM>(g, ix)) {
         if (first) {
             v = omega * r[i] / d[i];
         } else {
@@ -628,26 +706,36 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(DIM == 2
 
 template <typename T>
 void launch_jacobi(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const T *e, const T *r,
-                   const T *d, T *e_out, double theta_dt, double omega, bool first, hipStream_t s) {
+                   const T *d, T *e_out, double theta_dt, double omega, bool first, hipStream_t s,
+                   const int16_t *wctl, const T *dk) {
     int nb = tiles_for(g);
     if (dim == 2)
         SLHJB_LAUNCH((k_jacobi<2, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, e, r, d, e_out, (T)theta_dt,
-                     (T)omega, (int)first);
+                     (T)omega, (int)first, wctl, dk);
     else
         SLHJB_LAUNCH((k_jacobi<3, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, e, r, d, e_out, (T)theta_dt,
-                     (T)omega, (int)first);
+                     (T)omega, (int)first, wctl, dk);
 }
 
 template <int DIM, typename T>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(DIM == 2 ? 8 : 1))) void k_level_residual(LevelDev g, StencilDev st0, const int16_t *__restrict__ alpha,
                                                            const T *__restrict__ e, const T *__restrict__ r,
-                                                           T *__restrict__ res, T theta_dt) {
+                                                           T *__restrict__ res, T theta_dt,
+                                                           const int16_t *__restrict__ wctl) {
     const StencilDev &st = st0;
+    const int tile = remap_block(blockIdx.x, gridDim.x);
     int ix[3];
-    int i = tile_node<DIM>(g, ix);
+    int i = tile_node_at<DIM>(g, tile, ix);
     if (i < 0) return;
     T v = (T)0;
-    if (interior<DIM>(g, ix)) {
+    const int wc = wave_control(wctl, tile);
+    if (wc >= 0) {
+        const T ei = e[i], ri = r[i];
+        const double ck = st.c ? st.c[wc] : 0.0;
+        T l, unused;
+        lhat_node<DIM, T, T, false>(g, st, wc, i, ix, true, e, ei, e, ei, l, unused);
+        v = ri - (ei - theta_dt * (l + (T)ck * ei));
+    } else if (interior<DIM>(g, ix)) {
         const int k = alpha[i];
         const T ei = e[i], ri = r[i];
         const double ck = st.c ? st.c[((unsigned)k < (unsigned)st.K) ? k : 0] : 0.0;
@@ -659,14 +747,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(DIM == 2
 
 template <typename T>
 void launch_level_residual(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const T *e,
-                           const T *r, T *res, double theta_dt, hipStream_t s) {
+                           const T *r, T *res, double theta_dt, hipStream_t s, const int16_t *wctl) {
     int nb = tiles_for(g);
     if (dim == 2)
         SLHJB_LAUNCH((k_level_residual<2, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, e, r, res,
-                     (T)theta_dt);
+                     (T)theta_dt, wctl);
     else
         SLHJB_LAUNCH((k_level_residual<3, T>), dim3(nb), dim3(kBlock), 0, s, g, st, alpha, e, r, res,
-                     (T)theta_dt);
+                     (T)theta_dt, wctl);
 }
 
 // full weighting: weights 1/4, 1/2, 1/4 per axis around fine node 2I
@@ -961,17 +1049,20 @@ void launch_inject_policy(int dim, const LevelDev &gf, const LevelDev &gc, const
 }
 
 template void launch_diag<float>(int, const LevelDev &, const StencilDev &, const int16_t *, double, float *,
-                                 hipStream_t);
+                                 hipStream_t, int16_t *, float *);
 template void launch_diag<double>(int, const LevelDev &, const StencilDev &, const int16_t *, double, double *,
-                                  hipStream_t);
+                                  hipStream_t, int16_t *, double *);
 template void launch_jacobi<float>(int, const LevelDev &, const StencilDev &, const int16_t *, const float *,
-                                   const float *, const float *, float *, double, double, bool, hipStream_t);
+                                   const float *, const float *, float *, double, double, bool, hipStream_t,
+                                   const int16_t *, const float *);
 template void launch_jacobi<double>(int, const LevelDev &, const StencilDev &, const int16_t *, const double *,
-                                    const double *, const double *, double *, double, double, bool, hipStream_t);
+                                    const double *, const double *, double *, double, double, bool, hipStream_t,
+                                    const int16_t *, const double *);
 template void launch_level_residual<float>(int, const LevelDev &, const StencilDev &, const int16_t *, const float *,
-                                           const float *, float *, double, hipStream_t);
+                                           const float *, float *, double, hipStream_t, const int16_t *);
 template void launch_level_residual<double>(int, const LevelDev &, const StencilDev &, const int16_t *,
-                                            const double *, const double *, double *, double, hipStream_t);
+                                            const double *, const double *, double *, double, hipStream_t,
+                                            const int16_t *);
 template void launch_restrict<float>(int, const LevelDev &, const LevelDev &, const float *, float *, hipStream_t);
 template void launch_restrict<double>(int, const LevelDev &, const LevelDev &, const double *, double *, hipStream_t);
 template void launch_prolong_add<float>(int, const LevelDev &, const LevelDev &, const float *, float *, hipStream_t);

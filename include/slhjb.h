@@ -83,8 +83,8 @@ typedef struct {
     /* Solver controls. */
     int32_t precision;      /* HJB_PREC_FP64 | HJB_PREC_MIXED */
     int32_t precond;        /* HJB_PRECOND_* */
-    int32_t restart;        /* FGMRES restart length m, 1..64 */
-    int32_t max_krylov;     /* total FGMRES iterations per linear solve */
+    int32_t restart;        /* FGMRES restart length m, 1..64 (BiCGSTAB: >= 3, its four vectors use that storage) */
+    int32_t max_krylov;     /* total Krylov iterations per linear solve (a BiCGSTAB iteration counts two) */
     int32_t max_pi;         /* policy iterations per time step */
     int32_t nu1, nu2;       /* V-cycle pre/post Jacobi sweeps */
     int32_t coarse_sweeps;  /* Jacobi sweeps on the coarsest level */
@@ -110,14 +110,18 @@ typedef struct {
     int32_t coarse_sweeps_t; /* damped Jacobi sweeps on the coarsest level of the transposed V-cycles of the
                                adjoint (0: coarse_sweeps; a single-level hierarchy always takes coarse_sweeps);
                                0..1000 */
-    int32_t krylov;         /* HJB_KRYLOV_FGMRES (default) or HJB_KRYLOV_BICGSTAB for the forward linear solves */
+    int32_t krylov;         /* HJB_KRYLOV_FGMRES (default) or HJB_KRYLOV_BICGSTAB (Section 3.3's Krylov baseline,
+                               right-preconditioned by the same V-cycle or Jacobi, same stopping rule and
+                               certificate, restarted from the true residual) for every linear solve of the
+                               handle, transposed solves included; batches take FGMRES only */
     void *stream;           /* hipStream_t */
 } hjb_desc;
 
 typedef struct {
     int32_t pi_iters;       /* policy iterations (linear solves) in the step */
-    int32_t krylov_total;   /* FGMRES iterations summed over the step's solves */
-    int32_t krylov_max;     /* largest FGMRES count of one solve */
+    int32_t krylov_total;   /* Krylov iterations summed over the step's solves: applications of the
+                               preconditioned operator (one per FGMRES iteration, two per BiCGSTAB iteration) */
+    int32_t krylov_max;     /* largest Krylov count of one solve */
     int32_t flags;          /* HJB_FLAG_* */
     double res_inf;         /* final |F - A X|_inf of the last solve */
     double cert_bound;      /* bound on |X - X*|_inf of the last solve: res_inf / (1 - theta dt max(c,0)) */

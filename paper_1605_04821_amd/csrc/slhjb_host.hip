@@ -48,7 +48,8 @@ int fail(int code, const char *fmt, ...) {
     return code;
 }
 
-// Slots of the small device/host scalar arrays (dvals, hpin): [0, 16) solver scalars, 200 the adjoint
+// Slots of the small device/host scalar arrays (dvals, hpin): [0, 16) solver scalars, [16, 23) the
+// BiCGSTAB recurrence, 200 the adjoint
 // gradient term, and the two Gram-Schmidt passes of one Arnoldi step from kGsSlot0 and kGsSlot1 (m + 2
 // each).
 constexpr int kGsSlot0 = 256, kGsSlot1 = kGsSlot0 + kMaxRestart + 2;
@@ -382,7 +383,8 @@ int check_options(const hjb_desc *d) {
     if (d->nu_tight < 0 || d->nu_tight > 16) return fail(HJB_EINVAL, "nu_tight in 0..16");
     if (d->coarse_sweeps_t < 0 || d->coarse_sweeps_t > 1000) return fail(HJB_EINVAL, "coarse_sweeps_t in 0..1000");
     if (d->krylov != HJB_KRYLOV_FGMRES && d->krylov != HJB_KRYLOV_BICGSTAB) return fail(HJB_EINVAL, "krylov");
-    if (d->krylov == HJB_KRYLOV_BICGSTAB) return fail(HJB_EUNSUPPORTED, "BiCGSTAB is not available yet");
+    if (d->krylov == HJB_KRYLOV_BICGSTAB && d->restart < 3)
+        return fail(HJB_EINVAL, "BiCGSTAB keeps four vectors in the Krylov basis storage: restart must be >= 3");
     return HJB_OK;
 }
 
@@ -763,6 +765,97 @@ int fgmres_core(hjb_handle *hd, const KrylovOp &op, double *X, double eta, int *
     }
 }
 
+// BiCGSTAB with right preconditioning (the paper's Krylov baseline of Section 3.3), same stopping rule
+// and certificate as fgmres_core: the recurrence runs until its updated residual meets half the target,
+// then the true residual b - A X is recomputed and certifies the result, or restarts the recurrence
+// (fresh shadow vector rhat = r) when rounding has made the two drift apart.  A zero denominator
+// (breakdown) also restarts it.  Each iteration applies the preconditioned operator twice and counts as
+// two Krylov iterations.  Vectors: rhat, p, v, t in the first four slices of Vb, s in R over r, phat and
+// shat in the first two slices of Zb; the recurrence scalars stay in device slots (one host read per
+// iteration, for the residual norm).
+constexpr int kBicgSlot = 16;  // [rho, (rhat,v), |v|^2, (t,s), (t,t), max|r|, max|X|]
+
+int bicgstab_core(hjb_handle *hd, const KrylovOp &op, double *X, double eta, int *its_out, double *res_out,
+                  bool *tight_out) {
+    const hjb_desc &d = hd->desc;
+    const int64_t N = hd->N;
+    hipStream_t s = hd->stream;
+    const bool none = !op.precond;
+    const bool zf = !none && op.zf;
+    float *const rhs32 = none ? nullptr : op.rhs32;
+    const size_t zsz = zf ? sizeof(float) : sizeof(double);
+    double *const r = hd->R;
+    double *const rhat = hd->Vb, *const p = hd->Vb + N, *const v = hd->Vb + 2 * N, *const t = hd->Vb + 3 * N;
+    void *const phat = none ? (void *)p : hd->Zb;
+    void *const shat = none ? (void *)r : (void *)((char *)hd->Zb + N * zsz);
+    double *const sc = hd->dvals + kBicgSlot;
+    double *const hs = hd->hpin + kBicgSlot;
+    double *dv = hd->dvals;
+    double *hp = hd->hpin;
+    auto precond_then_apply = [&](const double *in, void *z, double *w) -> int {
+        if (none) {
+            op.apply(in, false, w);
+            return HJB_OK;
+        }
+        if (op.precond_apply) return op.precond_apply(in, z, w, rhs32 != nullptr);
+        TRY(op.precond(in, z, rhs32 != nullptr));
+        op.apply(z, zf, w);
+        return HJB_OK;
+    };
+    const int nbx = blocks_for(N);
+    int its = 0;
+    double loose = 0.0;
+    for (int cycle = 0;; ++cycle) {
+        op.residual();
+        launch_reduce_sum(hd->partial, 1, hd->nb, dv + 0, s);
+        launch_reduce_max(hd->partial + hd->nb, 2, hd->nb, dv + 1, s);
+        TRY(publish_wait(hd, dv, hp, 3 * sizeof(double)));
+        const double rr = hp[0], rinf = hp[1], xinf = hp[2];
+        *res_out = rinf;
+        *its_out = its;
+        if (!isfinite(rr) || !isfinite(xinf)) return fail(HJB_ENONFINITE, "non-finite residual in linear solve");
+        double target = d.rtol_inf * std::max(1.0, xinf);
+        if (cycle == 0 && eta > 0.0) loose = eta * rinf;
+        *tight_out = rinf <= target;
+        if (rinf <= std::max(target, loose)) return HJB_OK;
+        if (its >= d.max_krylov)
+            return fail(HJB_ENOCONV_KRYLOV, "BiCGSTAB: |r|_inf = %.3e > %.3e after %d iterations", rinf,
+                        std::max(target, loose), its);
+        // rhat = r and rho = (rhat, r) = |r|^2
+        launch_to_precond(r, rhat, false, N, s);
+        launch_reduce_sum(hd->partial, 1, hd->nb, sc + 0, s);  // the residual's partial sums of r^2
+        for (bool first = true; its < d.max_krylov; first = false) {
+            launch_bicg_p(p, r, v, sc, first, rhs32, N, s);
+            TRY(precond_then_apply(p, phat, v));
+            launch_multidot(v, rhat, N, 1, N, hd->partial, hd->nbd, s);
+            launch_reduce_sum(hd->partial, 2, hd->nbd, sc + 1, s);
+            launch_bicg_s(r, v, sc, rhs32, N, s);
+            TRY(precond_then_apply(r, shat, t));
+            launch_multidot(t, r, N, 1, N, hd->partial, hd->nbd, s);
+            launch_reduce_sum(hd->partial, 2, hd->nbd, sc + 3, s);
+            // the update's partials come from blocks_for(N) flat blocks, not the node kernels' tiles
+            launch_bicg_xr(X, r, t, phat, shat, zf, rhat, sc, hd->partial, N, s);
+            launch_reduce_sum(hd->partial, 1, nbx, sc + 0, s);
+            launch_reduce_max(hd->partial + nbx, 2, nbx, sc + 5, s);
+            TRY(publish_wait(hd, sc, hs, 7 * sizeof(double)));
+            its += 2;
+            if (!isfinite(hs[5]) || !isfinite(hs[6]))
+                return fail(HJB_ENONFINITE, "non-finite BiCGSTAB iterate");
+            const double goal = std::max(d.rtol_inf * std::max(1.0, hs[6]), loose);
+            if (hs[5] <= 0.5 * goal) break;
+            if (hs[0] == 0.0 || hs[1] == 0.0 || !(hs[4] > 0.0) || hs[3] == 0.0) break;  // breakdown: restart
+        }
+        HIPCHK(hipGetLastError());
+    }
+}
+
+// The Krylov method the descriptor selects (flexible GMRES or BiCGSTAB).
+int krylov_core(hjb_handle *hd, const KrylovOp &op, double *X, double eta, int *its_out, double *res_out,
+                bool *tight_out) {
+    if (hd->desc.krylov == HJB_KRYLOV_BICGSTAB) return bicgstab_core(hd, op, X, eta, its_out, res_out, tight_out);
+    return fgmres_core(hd, op, X, eta, its_out, res_out, tight_out);
+}
+
 int fgmres(hjb_handle *hd, const int16_t *alpha, const double *E, double *X, double theta_dt, double eta,
            int *its_out, double *res_out, bool *tight_out) {
     const int dim = hd->dim;
@@ -791,7 +884,7 @@ int fgmres(hjb_handle *hd, const int16_t *alpha, const double *E, double *X, dou
     }
     op.zf = mixed(hd);
     if (op.zf && hd->desc.precond == HJB_PRECOND_VCYCLE) op.rhs32 = (float *)L0.r;
-    return fgmres_core(hd, op, X, eta, its_out, res_out, tight_out);
+    return krylov_core(hd, op, X, eta, its_out, res_out, tight_out);
 }
 
 // ---- policy search ------------------------------------------------------------------------------
@@ -1964,7 +2057,7 @@ int solve_transposed(hjb_handle *hd, TransposeHierarchy &H, const int16_t *alpha
     }
     bool tight = false;
     set_sweeps(hd, true);
-    return fgmres_core(hd, op, mu, 0.0, its, res, &tight);
+    return krylov_core(hd, op, mu, 0.0, its, res, &tight);
 }
 
 }  // namespace
@@ -2696,6 +2789,7 @@ int hjb_setup_batch(const hjb_desc *descs, int32_t count, hjb_batch **out) {
     TRY(check_options(&d0));
     if ((d0.nu1 + d0.nu2) % 2 != 0) return fail(HJB_EUNSUPPORTED, "batched V-cycles take an even nu1 + nu2");
     if (d0.precond == HJB_PRECOND_JACOBI) return fail(HJB_EUNSUPPORTED, "batched solves take the V-cycle or no preconditioner");
+    if (d0.krylov != HJB_KRYLOV_FGMRES) return fail(HJB_EUNSUPPORTED, "batched solves use flexible GMRES");
     for (int b = 0; b < count; ++b) {
         if (descs[b].dim != d0.dim) return fail(HJB_EINVAL, "all instances of a batch have the same dimension");
         if (descs[b].f_per_control) return fail(HJB_EUNSUPPORTED, "batched instances take one source for all controls");

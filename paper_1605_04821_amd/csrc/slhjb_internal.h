@@ -262,6 +262,13 @@ struct UpdateCoef {
 void launch_update_solution(double *X, const void *Z, bool z_float, int64_t ldz, int m, const double *y_host, int64_t N,
                             hipStream_t s);
 void launch_axpy(double *y, double a, const double *x, int64_t N, hipStream_t s);
+// BiCGSTAB updates; sc = device slots [rho, (rhat,v), |v|^2, (t,s), (t,t)] (alpha and omega derived there)
+void launch_bicg_p(double *p, const double *r, const double *v, const double *sc, bool first, float *pf, int64_t N,
+                   hipStream_t s);
+void launch_bicg_s(double *r, const double *v, const double *sc, float *sf, int64_t N, hipStream_t s);
+// partial: [sum rhat*r | max|r| | max|X|], blocks_for(N) entries each
+void launch_bicg_xr(double *X, double *r, const double *t, const void *phat, const void *shat, bool z_float,
+                    const double *rhat, const double *sc, double *partial, int64_t N, hipStream_t s);
 void launch_affine(const double *a, const double *b, double t, double *out, int64_t N, hipStream_t s);
 void launch_copy_interior(int dim, const LevelDev &g, const double *src, double *dst, hipStream_t s);
 void launch_zero(void *p, size_t bytes, hipStream_t s);

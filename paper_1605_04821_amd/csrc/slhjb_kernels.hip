@@ -1359,6 +1359,93 @@ void launch_affine(const double *a, const double *b, double t, double *out, int6
     hipLaunchKernelGGL(k_affine, dim3(blocks_for(N)), dim3(kBlock), 0, s, a, b, t, out, N);
 }
 
+// ---- BiCGSTAB vector updates (right preconditioning) ----------------------------------------------
+// The recurrence scalars never leave the device.  sc holds the reduced inner products of the current
+// iteration: sc[0] = rho = (rhat, r), sc[1] = (rhat, v), sc[3] = (t, s), sc[4] = (t, t) (sc[2], sc[5]
+// hold |v|^2 and unused sums).  alpha = rho / (rhat, v), omega = (t, s) / (t, t); a zero denominator gives
+// a zero coefficient, which ends the recurrence without a division by zero (the host then restarts it
+// from the true residual).  The direction update needs beta = (rho_new / rho_old) (alpha / omega), which
+// in these slots is rho_new (t, t) / ((rhat, v) (t, s)): the old rho cancels, so one rho slot suffices.
+
+__device__ __forceinline__ double bicg_alpha(const double *sc) { return sc[1] != 0.0 ? sc[0] / sc[1] : 0.0; }
+__device__ __forceinline__ double bicg_omega(const double *sc) { return sc[4] > 0.0 ? sc[3] / sc[4] : 0.0; }
+
+// p = r (first) or p = r + beta (p - omega v); pf (nullable) receives float(p)
+__global__ __launch_bounds__(kBlock) void k_bicg_p(double *__restrict__ p, const double *__restrict__ r,
+                                                   const double *__restrict__ v, const double *__restrict__ sc,
+                                                   bool first, float *__restrict__ pf, int64_t N) {
+    int64_t n = (int64_t)remap_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (n >= N) return;
+    double x;
+    if (first) {
+        x = r[n];
+    } else {
+        const double den = sc[1] * sc[3];
+        const double beta = den != 0.0 ? sc[0] * sc[4] / den : 0.0;
+        x = r[n] + beta * (p[n] - bicg_omega(sc) * v[n]);
+    }
+    p[n] = x;
+    if (pf) pf[n] = (float)x;
+}
+
+// s = r - alpha v, in place over r; sf (nullable) receives float(s)
+__global__ __launch_bounds__(kBlock) void k_bicg_s(double *__restrict__ r, const double *__restrict__ v,
+                                                   const double *__restrict__ sc, float *__restrict__ sf, int64_t N) {
+    int64_t n = (int64_t)remap_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (n >= N) return;
+    const double x = r[n] - bicg_alpha(sc) * v[n];
+    r[n] = x;
+    if (sf) sf[n] = (float)x;
+}
+
+// X += alpha phat + omega shat, r = s - omega t (s in r, in place; shat may be r itself), and the per-block
+// partials [sum rhat*r | max |r| | max |X|] over gridDim.x blocks each.
+template <typename TZ>
+__global__ __launch_bounds__(kBlock) void k_bicg_xr(double *__restrict__ X, double *r, const double *__restrict__ t,
+                                                    const TZ *__restrict__ phat, const TZ *shat,
+                                                    const double *__restrict__ rhat, const double *__restrict__ sc,
+                                                    double *__restrict__ partial, int64_t N) {
+    __shared__ double sh[kBlock / 64];
+    const int b = remap_block(blockIdx.x, gridDim.x);
+    const int64_t n = (int64_t)b * kBlock + threadIdx.x;
+    double dot = 0.0, rmax = 0.0, xmax = 0.0;
+    if (n < N) {
+        const double al = bicg_alpha(sc), om = bicg_omega(sc);
+        const double x = X[n] + al * (double)phat[n] + om * (double)shat[n];
+        const double rn = r[n] - om * t[n];
+        X[n] = x;
+        r[n] = rn;
+        dot = rhat[n] * rn;
+        rmax = fabs(rn);
+        xmax = fabs(x);
+    }
+    double a = block_reduce<double>(dot, OpSum(), sh);
+    if (threadIdx.x == 0) partial[b] = a;
+    a = block_reduce<double>(rmax, OpMax(), sh);
+    if (threadIdx.x == 0) partial[gridDim.x + b] = a;
+    a = block_reduce<double>(xmax, OpMax(), sh);
+    if (threadIdx.x == 0) partial[2 * gridDim.x + b] = a;
+}
+
+void launch_bicg_p(double *p, const double *r, const double *v, const double *sc, bool first, float *pf, int64_t N,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(k_bicg_p, dim3(blocks_for(N)), dim3(kBlock), 0, s, p, r, v, sc, first, pf, N);
+}
+
+void launch_bicg_s(double *r, const double *v, const double *sc, float *sf, int64_t N, hipStream_t s) {
+    hipLaunchKernelGGL(k_bicg_s, dim3(blocks_for(N)), dim3(kBlock), 0, s, r, v, sc, sf, N);
+}
+
+void launch_bicg_xr(double *X, double *r, const double *t, const void *phat, const void *shat, bool z_float,
+                    const double *rhat, const double *sc, double *partial, int64_t N, hipStream_t s) {
+    if (z_float)
+        hipLaunchKernelGGL(k_bicg_xr<float>, dim3(blocks_for(N)), dim3(kBlock), 0, s, X, r, t, (const float *)phat,
+                           (const float *)shat, rhat, sc, partial, N);
+    else
+        hipLaunchKernelGGL(k_bicg_xr<double>, dim3(blocks_for(N)), dim3(kBlock), 0, s, X, r, t, (const double *)phat,
+                           (const double *)shat, rhat, sc, partial, N);
+}
+
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_copy_interior(LevelDev g, const double *__restrict__ src,
                                                           double *__restrict__ dst) {

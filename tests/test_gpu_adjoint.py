@@ -189,15 +189,16 @@ def test_adjoint_coarse_sweeps_option(slhjb, coarse_sweeps_t):
     _check_adjoint(slhjb, f"c2_65 coarse_sweeps_t={coarse_sweeps_t}", inst, 1, 2, coarse_sweeps_t=coarse_sweeps_t)
 
 
-def _check_adjoint(slhjb, name, inst, precision, precond, max_levels=2, coarse_sweeps_t=2):
-    log(f"adjoint {name} n={inst.n} steps={len(inst.dts)} precision={precision} precond={precond}")
+def _check_adjoint(slhjb, name, inst, precision, precond, max_levels=2, coarse_sweeps_t=2, krylov=0):
+    log(f"adjoint {name} n={inst.n} steps={len(inst.dts)} precision={precision} precond={precond} krylov={krylov}")
     s = S_TEST
     ref_march = oracle.march(inst, s=s, keep_policies=True)
     pols = ref_march["policies"]
     lam = _lam_N(inst, ref_march["U"])
     ref = oracle.adjoint_dense(inst, pols, lam, s=s)
     solver = slhjb.Solver.from_instance(inst, slhjb.Options(precision=precision, precond=precond,
-                                                            max_levels=max_levels, coarse_sweeps_t=coarse_sweeps_t))
+                                                            max_levels=max_levels, coarse_sweeps_t=coarse_sweeps_t,
+                                                            krylov=krylov))
     dg = torch.empty(inst.N, dtype=torch.float64, device="cuda")
     df0, df1 = torch.empty_like(dg), torch.empty_like(dg)
     ds, st = solver.adjoint(to_dev(inst.g), to_dev(inst.psi), to_dev(inst.f0), to_dev(inst.f1), inst.dts,

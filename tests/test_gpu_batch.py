@@ -122,6 +122,8 @@ def test_batch_rejects_bad_options(slhjb):
         slhjb.Batch(insts, slhjb.Options(nu1=2, nu2=1))
     with pytest.raises(slhjb.HJBError):
         slhjb.Batch(insts, slhjb.Options(precond=slhjb.PRECOND_JACOBI))
+    with pytest.raises(slhjb.HJBError):
+        slhjb.Batch(insts, slhjb.Options(krylov=slhjb.KRYLOV_BICGSTAB))
 
 
 def test_batch_graph_replays_match_eager(slhjb):

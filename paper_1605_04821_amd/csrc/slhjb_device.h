@@ -4,6 +4,8 @@
 // search quantity G_k (eq. nonlinear_sys).
 #pragma once
 
+#include <type_traits>
+
 #include "slhjb_internal.h"
 
 namespace slhjb {
@@ -115,6 +117,54 @@ __device__ __forceinline__ double landing(const LevelDev &g, const int ix[3], co
     return mu;
 }
 
+// The landing rules of landing() in FP32 with approximate reciprocals, for the FP32 multigrid kernels only:
+// those kernels precondition the FP64 Krylov solve, so the operator they apply may differ from the FP64 one
+// by rounding (near a tie of the rules, by the landing cell chosen).
+template <int DIM>
+__device__ __forceinline__ float landing_f(const LevelDev &g, const int ix[3], const float Y[3], int cell[3],
+                                           float t[3]) {
+    float m[3];
+    float mu = 1.0f;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        m[d] = __builtin_inff();
+        if (Y[d] != 0.0f) {
+            const int D = (Y[d] > 0.0f) ? (g.n[d] - 1 - ix[d]) : ix[d];
+            m[d] = (float)D * __builtin_amdgcn_rcpf(fabsf(Y[d]));
+            if (m[d] < mu) mu = m[d];
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        int c;
+        float tt;
+        if (mu == 1.0f) {
+            const float fl = floorf(Y[d]);
+            c = ix[d] + (int)fl;
+            tt = Y[d] - fl;
+        } else if (Y[d] != 0.0f && m[d] == mu) {
+            c = (Y[d] > 0.0f) ? g.n[d] - 1 : 0;
+            tt = 0.0f;
+        } else {
+            float q = (float)ix[d] + mu * Y[d];
+            q = q < 0.0f ? 0.0f : q;
+            const float top = (float)(g.n[d] - 1);
+            q = q > top ? top : q;
+            const float fl = floorf(q);
+            c = (int)fl;
+            tt = q - fl;
+        }
+        if (c >= g.n[d] - 1) {
+            c = g.n[d] - 2;
+            tt = 1.0f;
+        }
+        if (c < 0) c = 0;
+        cell[d] = c;
+        t[d] = tt;
+    }
+    return mu;
+}
+
 __device__ __forceinline__ double fmat(double a, double b, double c) { return fma(a, b, c); }
 __device__ __forceinline__ float fmat(float a, float b, float c) { return fmaf(a, b, c); }
 
@@ -193,9 +243,9 @@ __device__ __forceinline__ TC corner_wsum(const typename FastOf<TC>::T &p, const
 }
 
 // general landing: corner weights from the fractions, product over axes in axis order
-template <int DIM, typename TS, typename TC>
+template <int DIM, typename TS, typename TC, typename TT = double>
 __device__ __forceinline__ TC interp_land(const TS *__restrict__ V, const LevelDev &g, const int cell[3],
-                                          const double td[3]) {
+                                          const TT td[3]) {
     TC t[3], u[3], w[8];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -211,6 +261,36 @@ __device__ __forceinline__ TC interp_land(const TS *__restrict__ V, const LevelD
     }
     int base = cell[0] + cell[1] * (int)g.s1 + (DIM == 3 ? cell[2] * (int)g.s2 : 0);
     return interp_w<DIM, TS, TC>(V, base, g, w);
+}
+
+// Whether node ix lies where no stencil point of control k is truncated and every landing cell, with its
+// upper corners, is inside the grid: 0 <= ix_d + floor(Y_d) <= n_d - 2 on every axis for every point.  Then
+// every ratio D/|Y_d| of the landing is at least 1 (mu = 1, A = B = C = 1) and no cell is clamped: the
+// general rules give the untruncated landing of the tables (in FP64 the same corner weights and sums bit for
+// bit; in FP32 the tables' weights are the FP64 ones rounded once).  Constant coefficients only (per-node
+// displacements have no tables).
+template <int DIM>
+__device__ __forceinline__ bool lands_inside(const LevelDev &g, const StencilDev &st, int k, const int ix[3]) {
+    const FastPtF *fp = st.fastF + ((unsigned)k < (unsigned)st.K ? k : 0) * st.npt;
+    bool ok = true;
+    for (int q = 0; q < st.npt; ++q)
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            const int c = ix[d] + fp[q].fl[d];
+            ok = ok && c >= 0 && c <= g.n[d] - 2;
+        }
+    return ok;
+}
+
+// deep, or (constant coefficients) every point of control k lands inside the grid untruncated; the tables are
+// read through the scalar unit when k is the same on every active lane
+template <int DIM>
+__device__ __forceinline__ bool untruncated(const LevelDev &g, const StencilDev &st, int k, const int ix[3],
+                                            bool deep) {
+    if (st.pernode || __all(deep)) return deep;
+    const int k0 = __builtin_amdgcn_readfirstlane(k);
+    if (__all(k == k0)) return deep || lands_inside<DIM>(g, st, k0, ix);
+    return deep || lands_inside<DIM>(g, st, k, ix);
 }
 
 // (L-hat^k V)_i for one or two fields sharing the stencil geometry (eq. TruncScheme).
@@ -317,6 +397,46 @@ __device__ __forceinline__ void lhat_node(const LevelDev &g, const StencilDev &s
                 accW = accW + (TC)2 * (wb - Wi);
             }
         }
+    } else if constexpr (std::is_same<TC, float>::value) {
+        // FP32 kernels: the landings in FP32 (landing_f)
+        auto yf = [&](int q, float Yf[3]) {
+            double Y[3];
+            point_Y(st, pt[q], q, ix, i, DIM, Y);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) Yf[d] = (float)Y[d];
+        };
+        for (int p = 0; p < st.P; ++p) {
+            float Ya[3], Yb[3];
+            yf(2 * p, Ya);
+            yf(2 * p + 1, Yb);
+            int cp[3], cm[3];
+            float tp[3], tm[3];
+            const float mup = landing_f<DIM>(g, ix, Ya, cp, tp);
+            const float mum = landing_f<DIM>(g, ix, Yb, cm, tm);
+            const float A = 2.0f * __builtin_amdgcn_rcpf(mup * (mup + mum));
+            const float B = 2.0f * __builtin_amdgcn_rcpf(mum * (mum + mup));
+            const TC vp = interp_land<DIM, TS, TC, float>(V, g, cp, tp);
+            const TC vm = interp_land<DIM, TS, TC, float>(V, g, cm, tm);
+            accV = accV + ((A * vp + B * vm) - (A + B) * Vi);
+            if (TWO) {
+                const TC wp = interp_land<DIM, TS, TC, float>(W, g, cp, tp);
+                const TC wm = interp_land<DIM, TS, TC, float>(W, g, cm, tm);
+                accW = accW + ((A * wp + B * wm) - (A + B) * Wi);
+            }
+        }
+        if (st.has_drift) {
+            float Yc[3];
+            yf(2 * st.P, Yc);
+            int cb[3];
+            float tb[3];
+            const float C2 = 2.0f * __builtin_amdgcn_rcpf(landing_f<DIM>(g, ix, Yc, cb, tb));
+            const TC vb = interp_land<DIM, TS, TC, float>(V, g, cb, tb);
+            accV = accV + C2 * (vb - Vi);
+            if (TWO) {
+                const TC wb = interp_land<DIM, TS, TC, float>(W, g, cb, tb);
+                accW = accW + C2 * (wb - Wi);
+            }
+        }
     } else {
         for (int p = 0; p < st.P; ++p) {
             double Ya[3], Yb[3];
@@ -362,6 +482,7 @@ template <int DIM, typename TS, typename TC>
 __device__ __forceinline__ TC lhat1(const LevelDev &g, const StencilDev &st, int k, int i, const int ix[3], bool deep,
                                     const TS *__restrict__ V, TC Vi) {
     TC a, b;
+    deep = untruncated<DIM>(g, st, k, ix, deep);
     // the policy is piecewise constant: when the whole wavefront shares one control (and is untruncated),
     // its stencil tables are read once through the scalar unit instead of per lane
     int k0 = __builtin_amdgcn_readfirstlane(k);
@@ -417,7 +538,8 @@ __device__ __forceinline__ double eval_G(const LevelDev &g, const StencilDev &st
         q = Q[(int64_t)k * qstride + qslot];
     } else {
         if (CN)
-            lhat_node<DIM, double, double, true>(g, st, k, i, ix, deep, X, Xi, U, Ui, lx, lu);
+            lhat_node<DIM, double, double, true>(g, st, k, i, ix, untruncated<DIM>(g, st, k, ix, deep), X, Xi, U, Ui,
+                                                 lx, lu);
         else
             lx = lhat1<DIM, double, double>(g, st, k, i, ix, deep, X, Xi);
         q = omt * (lu + ck * Ui);

@@ -284,6 +284,7 @@ int build_tables(hjb_handle *hd, double s) {
             memset(&hf[q], 0, sizeof(FastPtF));
             memset(&hdd[q], 0, sizeof(FastPtD));
             hf[q].off = hdd[q].off = (int32_t)host[q].off;
+            for (int a = 0; a < hd->dim; ++a) hf[q].fl[a] = (int32_t)floor(host[q].Y[a]);
             const double *t = host[q].t;
             for (int c = 0; c < (1 << hd->dim); ++c) {
                 double w = (c & 1) ? t[0] : (1.0 - t[0]);

@@ -56,10 +56,12 @@ struct PointTab {
 // Untruncated landing used by the node loops: linear offset of the landing cell and the 2^d corner
 // weights (corner c: bit d set = upper corner on axis d; weight = product over axes of t_d or 1 - t_d).
 // Sizes are multiples of 16 bytes so kernels whose control varies per node can stage them in LDS.
+// FastPtF also keeps the cell offset per axis, floor(Y_d) (0 beyond the dimension), for the test of
+// whether a node outside the untruncated box lands inside the grid.
 struct FastPtF {
     int32_t off;
     float w[8];
-    int32_t pad[3];
+    int32_t fl[3];
 };
 struct FastPtD {
     int32_t off;

@@ -3,16 +3,17 @@
 //
 // Transposition.  The rows of L-hat^alpha (eq. Lhat: for each stencil point, its truncation weight
 // times the corner weights of eq. monotone_int, plus the diagonal) are emitted into fixed slots
-// (node i, entry e) and stably sorted by column.  The transposed product then gathers, for each
-// column j, the entries of the rows that reference j in increasing row order: deterministic, no
-// atomics.
+// (node i, entry e) and sorted by column with a counting sort that keeps the slot order within a
+// column.  The transposed product then gathers, for each column j, the entries of the rows that
+// reference j in increasing row order: deterministic, no atomics in the products.
 //
 // s-derivative.  Diffusion displacements are Y = s*sigma/sqrt(h) (drift points do not depend on s).
 // The operator is evaluated with forward-mode dual numbers along the same landing rules as the
 // forward kernels, so the derivative includes how truncation (mu, A_p, B_p of Prop. pro:scheme2)
 // changes with s; it is the one-sided derivative at the (measure-zero) kinks of floor and min.
 
-#include <hipcub/hipcub.hpp>
+#include <algorithm>
+#include <climits>
 
 #include "slhjb_internal.h"
 
@@ -461,19 +462,18 @@ __device__ double landing_plain(const LevelDev &g, const int ix[3], const double
 }
 
 // slots [i*E, (i+1)*E): for each stencil point its 2^d corners (weight * corner weight / 2h), then the
-// diagonal -(sum of weights)/2h.  Boundary rows get the sentinel column N.
+// diagonal -(sum of weights)/2h.  Boundary rows get the sentinel column N.  Weights are stored by slot, the
+// columns entry-major (entry e of row i at e * N + i) for the coalesced passes of the column sort.
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_emit_rows(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
-                                                      int E, int32_t *__restrict__ cols, double *__restrict__ vals,
-                                                      int32_t *__restrict__ ids) {
+                                                      int E, int32_t *__restrict__ cols, double *__restrict__ vals) {
     int ix[3];
     int i = tile_node_a<DIM>(g, ix);
     if (i < 0) return;
     int64_t base = (int64_t)i * E;
-    for (int e = 0; e < E; ++e) ids[base + e] = (int32_t)(base + e);
     if (!interior_a<DIM>(g, ix)) {
         for (int e = 0; e < E; ++e) {
-            cols[base + e] = (int32_t)g.N;
+            cols[(int64_t)e * g.N + i] = (int32_t)g.N;
             vals[base + e] = 0.0;
         }
         return;
@@ -508,37 +508,222 @@ __global__ __launch_bounds__(kBlock) void k_emit_rows(LevelDev g, StencilDev st,
             w = w * (((c >> 1) & 1) ? t[1] : (1.0 - t[1]));
             if (DIM == 3) w = w * (((c >> 2) & 1) ? t[2] : (1.0 - t[2]));
             int off = (c & 1) + ((c >> 1) & 1) * s1 + (DIM == 3 ? ((c >> 2) & 1) * s2 : 0);
-            cols[base + e] = cb + off;
+            cols[(int64_t)e * g.N + i] = cb + off;
             vals[base + e] = Ws * w;
             ++e;
         }
         diag -= Ws;
     }
-    cols[base + e] = i;
+    cols[(int64_t)e * g.N + i] = i;
     vals[base + e] = diag;
     ++e;
     for (; e < E; ++e) {
-        cols[base + e] = (int32_t)g.N;
+        cols[(int64_t)e * g.N + i] = (int32_t)g.N;
         vals[base + e] = 0.0;
     }
 }
 
-// colptr[j] = first sorted position whose column is >= j, for j = 0..N (the sentinel N sorts last);
-// the entries are then laid out in column order: vals_s[p] = vals[id], rows_s[p] = id / E.
-__global__ __launch_bounds__(kBlock) void k_colptr(const int32_t *__restrict__ keys, const int32_t *__restrict__ ids,
-                                                   const double *__restrict__ vals, int E, int64_t n, int32_t N,
-                                                   int32_t *__restrict__ colptr, double *__restrict__ vals_s,
-                                                   int32_t *__restrict__ rows_s) {
-    int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (p >= n) return;
-    int32_t key = keys[p];
-    int32_t prev = p == 0 ? -1 : keys[p - 1];
-    for (int32_t j = prev + 1; j <= key && j <= N; ++j) colptr[j] = (int32_t)p;
-    if (p == n - 1)
-        for (int32_t j = key + 1; j <= N; ++j) colptr[j] = (int32_t)n;
-    int32_t id = ids[p];
+// ---- column-sorted listing: counting sort by column, stable in slot order --------------------------------
+// Slot p = i * E + e of the row listing holds entry e of row i.  The listing sorted by column keeps, within a
+// column, the slot order (increasing row), so every sum over a column's entries runs in one fixed order.
+// The sentinel column N (boundary rows, unused slots) is not listed.
+
+// Threads take the entries entry-major (thread q: entry q / N of row q % N, as the columns are stored), so a
+// wavefront's atomics go to the distinct columns of consecutive rows rather than to the columns one row's
+// entries share with its neighbours'.
+__device__ __forceinline__ int64_t entry_major_slot(int64_t q, int64_t rows, int E) {
+    const int64_t e = q / rows;
+    return (q - e * rows) * E + e;
+}
+
+__global__ __launch_bounds__(kBlock) void k_col_count(const int32_t *__restrict__ cols, int64_t n, int E, int32_t N,
+                                                      int32_t *__restrict__ cnt) {
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= n) return;
+    const int32_t c = cols[q];
+    if (c < N) atomicAdd(&cnt[c], 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy_i32(const int32_t *__restrict__ a, int32_t *__restrict__ b,
+                                                     int64_t n) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p < n) b[p] = a[p];
+}
+
+// cursor starts as the column starts; each listed slot takes the next free place of its column
+__global__ __launch_bounds__(kBlock) void k_col_scatter(const int32_t *__restrict__ cols, int64_t n, int E, int32_t N,
+                                                        int32_t *__restrict__ cursor, int32_t *__restrict__ slot_s) {
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= n) return;
+    const int32_t c = cols[q];
+    if (c < N) slot_s[atomicAdd(&cursor[c], 1)] = (int32_t)entry_major_slot(q, n / E, E);
+}
+
+// The places a column's slots took depend on the order of the atomics: each column's slots are put back in
+// increasing order.  Columns of at most kShortCol entries (almost all) are sorted in registers by one thread
+// (odd-even transposition network); longer ones (next to the boundary, where truncated landings gather) are
+// appended to a list and sorted by one block each.
+constexpr int kShortCol = 16, kLongColLds = 8192;
+
+__global__ __launch_bounds__(kBlock) void k_col_order(const int32_t *__restrict__ colptr, int32_t N,
+                                                      int32_t *__restrict__ slot_s, int32_t *__restrict__ long_list,
+                                                      int32_t *__restrict__ long_count) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= N) return;
+    const int32_t a = colptr[j], len = colptr[j + 1] - a;
+    if (len <= 1) return;
+    if (len > kShortCol) {
+        long_list[atomicAdd(long_count, 1)] = (int32_t)j;
+        return;
+    }
+    int32_t v[kShortCol];
+#pragma unroll
+    for (int q = 0; q < kShortCol; ++q) v[q] = q < len ? slot_s[a + q] : INT32_MAX;
+#pragma unroll
+    for (int r = 0; r < kShortCol; ++r)
+#pragma unroll
+        for (int q = r & 1; q + 1 < kShortCol; q += 2)
+            if (v[q] > v[q + 1]) {
+                const int32_t t = v[q];
+                v[q] = v[q + 1];
+                v[q + 1] = t;
+            }
+#pragma unroll
+    for (int q = 0; q < kShortCol; ++q)
+        if (q < len) slot_s[a + q] = v[q];
+}
+
+// one block per listed long column (the grid strides over the list): each entry's place is the number of
+// smaller entries of its column (the slots are distinct)
+__global__ __launch_bounds__(kBlock) void k_col_order_long(const int32_t *__restrict__ colptr,
+                                                           int32_t *__restrict__ slot_s,
+                                                           const int32_t *__restrict__ long_list,
+                                                           const int32_t *__restrict__ long_count) {
+    __shared__ int32_t sh[kLongColLds];
+    const int32_t cnt = long_count[0];
+    for (int32_t q = blockIdx.x; q < cnt; q += gridDim.x) {
+        const int32_t j = long_list[q];
+        const int32_t a = colptr[j], len = colptr[j + 1] - a;
+        if (len <= kLongColLds) {
+            for (int32_t t = threadIdx.x; t < len; t += blockDim.x) sh[t] = slot_s[a + t];
+            __syncthreads();
+            for (int32_t t = threadIdx.x; t < len; t += blockDim.x) {
+                const int32_t v = sh[t];
+                int32_t rank = 0;
+                for (int32_t u = 0; u < len; ++u) rank += sh[u] < v ? 1 : 0;
+                slot_s[a + rank] = v;
+            }
+        } else if (threadIdx.x == 0) {
+            // beyond the shared-memory copy: insertion sort in place
+            for (int32_t p = a + 1; p < a + len; ++p) {
+                const int32_t v = slot_s[p];
+                int32_t r = p - 1;
+                while (r >= a && slot_s[r] > v) {
+                    slot_s[r + 1] = slot_s[r];
+                    --r;
+                }
+                slot_s[r + 1] = v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// rows and weights of the listed entries in column order
+__global__ __launch_bounds__(kBlock) void k_col_fill(const int32_t *__restrict__ slot_s, const int32_t *__restrict__ total,
+                                                     int64_t n, int E, const double *__restrict__ vals,
+                                                     double *__restrict__ vals_s, int32_t *__restrict__ rows_s) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= n || p >= total[0]) return;
+    const int32_t id = slot_s[p];
     vals_s[p] = vals[id];
     rows_s[p] = id / E;
+}
+
+// ---- exclusive prefix sums of int32 counts ---------------------------------------------------------------
+constexpr int kScanThreads = 1024, kScanItems = 4;
+constexpr int kScanChunk = kScanThreads * kScanItems;
+
+// block-wide exclusive scan of one value per thread; returns the block total through *total
+__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *sh, int32_t *total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    __syncthreads();
+    if (lane == 63) sh[wid] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int w = 0; w < kScanThreads / 64; ++w) {
+            const int32_t t = sh[w];
+            sh[w] = run;
+            run += t;
+        }
+        sh[kScanThreads / 64] = run;
+    }
+    __syncthreads();
+    *total = sh[kScanThreads / 64];
+    return sh[wid] + x - v;
+}
+
+// out[q] = sum of in[0..q) within each chunk of kScanChunk entries; part[b] = total of chunk b
+__global__ __launch_bounds__(kScanThreads) void k_scan_local(const int32_t *__restrict__ in, int64_t m,
+                                                             int32_t *__restrict__ out, int32_t *__restrict__ part) {
+    __shared__ int32_t sh[kScanThreads / 64 + 1];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    int32_t v[kScanItems], s = 0;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        v[q] = base + q < m ? in[base + q] : 0;
+        s += v[q];
+    }
+    int32_t total;
+    int32_t run = block_exclusive_scan(s, sh, &total);
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        if (base + q < m) out[base + q] = run;
+        run += v[q];
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+// part[0..nb) -> exclusive prefix sums in place (one block, chunk by chunk); *total_out = the sum of all
+__global__ __launch_bounds__(kScanThreads) void k_scan_parts(int32_t *__restrict__ part, int nb, int32_t *total_out) {
+    __shared__ int32_t sh[kScanThreads / 64 + 1];
+    int32_t carry = 0;
+    for (int c0 = 0; c0 < nb; c0 += kScanThreads) {
+        const int q = c0 + (int)threadIdx.x;
+        const int32_t v = q < nb ? part[q] : 0;
+        int32_t total;
+        const int32_t ex = block_exclusive_scan(v, sh, &total);
+        if (q < nb) part[q] = carry + ex;
+        carry += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(int32_t *__restrict__ out, int64_t m,
+                                                           const int32_t *__restrict__ part) {
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    const int32_t add = part[blockIdx.x];
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q)
+        if (base + q < m) out[base + q] += add;
+}
+
+// out[q] = in[0] + ... + in[q-1] for q < m, and *total_out (nullable) = the sum of all m; part holds
+// scan_parts(m) entries
+inline int64_t scan_parts(int64_t m) { return (m + kScanChunk - 1) / kScanChunk; }
+void exclusive_scan(const int32_t *in, int64_t m, int32_t *out, int32_t *part, int32_t *total_out, hipStream_t s) {
+    const int nb = (int)std::max<int64_t>(1, scan_parts(m));
+    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kScanThreads), 0, s, in, m, out, part);
+    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(kScanThreads), 0, s, part, nb, total_out);
+    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kScanThreads), 0, s, out, m, (const int32_t *)part);
 }
 
 // slice widths: longest column of each wavefront's 64 nodes, capped at kEllCap
@@ -592,25 +777,34 @@ int build_transpose(int dim, const LevelDev &g, const StencilDev &st, const int1
     int64_t n = g.N * (int64_t)E;
     const int nt = tiles_for(g);
     if (dim == 2)
-        hipLaunchKernelGGL(k_emit_rows<2>, dim3(nt), dim3(kBlock), 0, s, g, st, alpha, E, b.cols, b.vals, b.ids);
+        hipLaunchKernelGGL(k_emit_rows<2>, dim3(nt), dim3(kBlock), 0, s, g, st, alpha, E, b.cols, b.vals);
     else
-        hipLaunchKernelGGL(k_emit_rows<3>, dim3(nt), dim3(kBlock), 0, s, g, st, alpha, E, b.cols, b.vals, b.ids);
-    int end_bit = 1;
-    while (((int64_t)1 << end_bit) <= g.N) ++end_bit;
-    size_t tb = b.scratch_bytes;
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(b.scratch, tb, b.cols, b.cols_s, b.ids, b.ids_s, (int)n, 0,
-                                                      end_bit, s);
-    if (e != hipSuccess) return -1;
-    hipLaunchKernelGGL(k_colptr, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, b.cols_s, b.ids_s,
-                       b.vals, E, n, (int32_t)g.N, b.colptr, b.vals_s, b.rows_s);
+        hipLaunchKernelGGL(k_emit_rows<3>, dim3(nt), dim3(kBlock), 0, s, g, st, alpha, E, b.cols, b.vals);
+    // column starts by counting sort: counts, their prefix sums (colptr[N] = listed entries), scatter, order
+    const unsigned gb = (unsigned)((n + kBlock - 1) / kBlock);
+    int32_t *part = (int32_t *)b.scratch;
+    launch_zero(b.cols_s, (size_t)g.N * 4, s);
+    hipLaunchKernelGGL(k_col_count, dim3(gb), dim3(kBlock), 0, s, b.cols, n, E, (int32_t)g.N, b.cols_s);
+    exclusive_scan(b.cols_s, g.N, b.colptr, part, b.colptr + g.N, s);
+    hipLaunchKernelGGL(k_copy_i32, dim3((unsigned)((g.N + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       (const int32_t *)b.colptr, b.cols_s, g.N);
+    hipLaunchKernelGGL(k_col_scatter, dim3(gb), dim3(kBlock), 0, s, b.cols, n, E, (int32_t)g.N, b.cols_s,
+                       b.ids_s);
+    // the cursor array is free again: it takes the list of long columns, counted behind the partial sums
+    int32_t *long_count = part + scan_parts(std::max<int64_t>(g.N, ell_slices(g)));
+    launch_zero(long_count, 4, s);
+    hipLaunchKernelGGL(k_col_order, dim3((unsigned)((g.N + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       (const int32_t *)b.colptr, (int32_t)g.N, b.ids_s, b.cols_s, long_count);
+    hipLaunchKernelGGL(k_col_order_long, dim3(1024), dim3(kBlock), 0, s, (const int32_t *)b.colptr, b.ids_s,
+                       (const int32_t *)b.cols_s, (const int32_t *)long_count);
+    hipLaunchKernelGGL(k_col_fill, dim3(gb), dim3(kBlock), 0, s, (const int32_t *)b.ids_s,
+                       (const int32_t *)(b.colptr + g.N), n, E, (const double *)b.vals, b.vals_s, b.rows_s);
     const int64_t ns = ell_slices(g);
     if (dim == 2)
         hipLaunchKernelGGL(k_ell_width<2>, dim3(nt), dim3(kBlock), 0, s, g, b.colptr, b.ell_w);
     else
         hipLaunchKernelGGL(k_ell_width<3>, dim3(nt), dim3(kBlock), 0, s, g, b.colptr, b.ell_w);
-    tb = b.scratch_bytes;
-    e = hipcub::DeviceScan::ExclusiveSum(b.scratch, tb, b.ell_w, b.ell_off, (int)ns, s);
-    if (e != hipSuccess) return -1;
+    exclusive_scan(b.ell_w, ns, b.ell_off, part, nullptr, s);
     if (dim == 2)
         hipLaunchKernelGGL(k_ell_fill<2>, dim3(nt), dim3(kBlock), 0, s, g, b.colptr, b.rows_s, b.vals_s, b.ell_w,
                            b.ell_off, b.ell_rows, b.ell_vals, b.ell_vals32, b.ell_d16);
@@ -621,14 +815,8 @@ int build_transpose(int dim, const LevelDev &g, const StencilDev &st, const int1
 }
 
 size_t transpose_scratch_bytes(int64_t n, int N, int nslices) {
-    size_t tb = 0, ts = 0;
-    int end_bit = 1;
-    while (((int64_t)1 << end_bit) <= N) ++end_bit;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (int32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr,
-                                             (int32_t *)nullptr, (int)n, 0, end_bit, (hipStream_t)0);
-    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, ts, (int32_t *)nullptr, (int32_t *)nullptr, nslices,
-                                           (hipStream_t)0);
-    return tb > ts ? tb : ts;
+    (void)n;
+    return (size_t)(scan_parts(std::max<int64_t>(N, nslices)) + 1) * 4;  // partial sums, long-column count
 }
 
 // (L^T x)_j over the interior rows that reference column j, in increasing row order: the slice's

@@ -1863,8 +1863,8 @@ struct TransposeWork {
         struct R {
             void **p;
             size_t bytes;
-        } req[] = {{(void **)&b.cols, (size_t)n * 4},   {(void **)&b.ids, (size_t)n * 4},
-                   {(void **)&b.cols_s, (size_t)n * 4}, {(void **)&b.ids_s, (size_t)n * 4},
+        } req[] = {{(void **)&b.cols, (size_t)n * 4},
+                   {(void **)&b.cols_s, (size_t)nodes * 4}, {(void **)&b.ids_s, (size_t)n * 4},
                    {(void **)&b.rows_s, (size_t)n * 4}, {(void **)&b.vals, (size_t)n * 8},
                    {(void **)&b.vals_s, (size_t)n * 8}, {(void **)&b.colptr, (size_t)(nodes + 1) * 4},
                    {(void **)&b.ell_w, (size_t)ns * 4}, {(void **)&b.ell_off, (size_t)ns * 4},
@@ -1899,7 +1899,7 @@ struct TransposeWork {
     int build(hjb_handle *hd, int level, const int16_t *alpha) {
         const LevelDev &g = hd->lev[level].g;
         if (build_transpose(hd->dim, g, stencil(hd, level), alpha, E, b, hd->stream) != 0)
-            return fail(HJB_EDEVICE, "radix sort of the transposed operator failed");
+            return fail(HJB_EDEVICE, "column sort of the transposed operator failed");
         HIPCHK(hipGetLastError());
         if (hd->trace) {  // padding of the sliced ELL copy
             const int64_t ns = ell_slices(g);

@@ -288,7 +288,7 @@ constexpr int kEllCap = 32;
 // The FP32 copy (preconditioner) holds the weights as float and, in 2D when every stencil point stays
 // within 127 cells, the row as int8 offsets (dx | dy << 8) from the column node.
 struct TransposeBuf {
-    int32_t *cols, *ids, *cols_s, *ids_s, *colptr, *rows_s;
+    int32_t *cols, *cols_s, *ids_s, *colptr, *rows_s;  // cols_s: counts / scatter cursor, ids_s: slots
     double *vals, *vals_s;
     int32_t *ell_w, *ell_off, *ell_rows;
     double *ell_vals;

@@ -238,8 +238,8 @@ int hjb_solve(hjb_handle *hd, const double *g, const double *psi, const double *
               double *U_final, int16_t *policies, double *values, hjb_solve_stats *st);
 
 typedef struct {
-    int64_t krylov_recompute;  /* FGMRES iterations of the forward recomputation */
-    int64_t krylov_adjoint;    /* FGMRES iterations of the transposed solves */
+    int64_t krylov_recompute;  /* Krylov iterations of the recomputation of the values (0 with values given) */
+    int64_t krylov_adjoint;    /* Krylov iterations of the transposed solves */
     double max_res_adjoint;    /* largest final |lambda - A^T mu|_inf of the transposed solves */
 } hjb_adjoint_stats;
 
@@ -247,8 +247,11 @@ typedef struct {
  * Discrete adjoint of hjb_solve at the policies it returned (gradients of a functional J of U^N).
  * Each step solves A_n U^n = B_n U^{n-1} + dt_n f(t_mid) + Dirichlet terms (eq. FullScheme with
  * A_n = I - theta dt (L^{alpha_n} + C) on interior nodes and B_n = I + (1-theta) dt (L^{alpha_n} + C) on the
- * full previous level).  The values U^n are taken from `values` (hjb_solve's output) or, when it is
- * NULL, recomputed from g with one fixed-policy solve per step; then backwards: A_n^T mu_n = lambda_n, dJ/df0 += dt mu_n, dJ/df1 += dt t_mid mu_n,
+ * full previous level).  The values U^n enter only dJ/ds: they are taken from `values` (hjb_solve's output)
+ * or, when it is NULL and dJ_ds is requested, recomputed from g and the int16 policies by fixed-policy solves,
+ * keeping only every ceil(sqrt(n_steps))-th value and recomputing one segment at a time in the backward
+ * sweep (2 n_steps solves, about 2 sqrt(n_steps) + 1 FP64 arrays); without dJ_ds nothing is recomputed.
+ * Then backwards: A_n^T mu_n = lambda_n, dJ/df0 += dt mu_n, dJ/df1 += dt t_mid mu_n,
  * dJ/ds += dt mu_n^T (theta d_s L U^n + (1-theta) d_s L U^{n-1}), lambda_{n-1} = B_n^T mu_n, dJ/dg = lambda_0.
  * Policies are held fixed, so the gradient is exact away from policy switches (where J is differentiable).
  *   g, psi, f0, f1: full-grid FP64 as for hjb_solve; policies: int16 [n_steps][N] from hjb_solve;

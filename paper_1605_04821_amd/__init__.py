@@ -455,33 +455,39 @@ def _autograd_function():
         adjoint at the forward policies (hjb_adjoint)."""
 
         @staticmethod
-        def forward(ctx, g, f0, f1, s, solver, psi, dts, thetas):
+        def forward(ctx, g, f0, f1, s, solver, psi, dts, thetas, store_values):
             N = g.numel()
             U = torch.empty_like(g)
             pol = torch.empty((len(dts), N), dtype=torch.int16, device=g.device)
-            vals = torch.empty((len(dts) + 1, N), dtype=torch.float64, device=g.device)
+            vals = torch.empty((len(dts) + 1, N), dtype=torch.float64, device=g.device) if store_values else None
             solver.solve(g, psi, f0, f1, dts, thetas, float(s), U, pol, vals)
-            ctx.save_for_backward(g, f0, f1, psi, pol, vals)
+            saved = (g, f0, f1, psi, pol) + ((vals,) if store_values else ())
+            ctx.save_for_backward(*saved)
             ctx.meta = (solver, float(s), np.asarray(dts, np.float64), np.asarray(thetas, np.float64))
             return U
 
         @staticmethod
         def backward(ctx, gU):
-            g, f0, f1, psi, pol, vals = ctx.saved_tensors
+            g, f0, f1, psi, pol = ctx.saved_tensors[:5]
+            vals = ctx.saved_tensors[5] if len(ctx.saved_tensors) > 5 else None
             solver, s, dts, thetas = ctx.meta
             df0, df1, dg = torch.empty_like(g), torch.empty_like(g), torch.empty_like(g)
             ds, _ = solver.adjoint(g, psi, f0, f1, dts, thetas, s, pol, gU.contiguous(), df0, dg, dJ_df1=df1,
                                    values=vals)
             dsv = torch.tensor(ds, dtype=torch.float64, device=g.device)
-            return dg, df0, df1, dsv, None, None, None, None
+            return dg, df0, df1, dsv, None, None, None, None, None
 
     return HJBMarch
 
 
-def hjb_march(solver: Solver, g, psi, f0, f1, dts, thetas, s):
-    """Differentiable march: returns U^N; gradients flow to g, f0, f1 and s (a 0-d FP64 tensor or float)."""
+def hjb_march(solver: Solver, g, psi, f0, f1, dts, thetas, s, store_values: bool = False):
+    """Differentiable march: returns U^N; gradients flow to g, f0, f1 and s (a 0-d FP64 tensor or float).
+
+    The forward pass keeps the int16 policies of every step; the backward pass recomputes the values it needs
+    from them (hjb_adjoint without values).  store_values=True keeps the FP64 values of every step instead
+    (n_steps + 1 full-grid arrays) and skips the recomputation."""
     import torch
     F = _autograd_function()
     if not torch.is_tensor(s):
         s = torch.tensor(float(s), dtype=torch.float64, device=g.device)
-    return F.apply(g, f0, f1, s, solver, psi, dts, thetas)
+    return F.apply(g, f0, f1, s, solver, psi, dts, thetas, bool(store_values))

@@ -2110,8 +2110,7 @@ int hjb_adjoint(hjb_handle *hd, const double *g, const double *psi, const double
     hipStream_t str = hd->stream;
     for (int n = 0; n < n_steps; ++n) TRY(check_policy(hd, policies + (int64_t)n * N));
     hjb_adjoint_stats loc{};
-    // values U^0..U^N: the forward march's, or recomputed from the policy checkpoints
-    double *Us = nullptr, *lam = nullptr, *mu = nullptr;
+    double *lam = nullptr, *mu = nullptr;
     struct Free {
         std::vector<void *> p;
         ~Free() {
@@ -2136,25 +2135,64 @@ int hjb_adjoint(hjb_handle *hd, const double *g, const double *psi, const double
             t = t + dts[n];
         }
     }
-    const double *Uv = values;
-    if (!values) {
-        TRY(get(&Us, (size_t)(n_steps + 1) * N * 8));
-        HIPCHK(hipMemcpyAsync(Us, g, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
-        for (int n = 0; n < n_steps; ++n) {
-            double *Un = Us + (int64_t)(n + 1) * N;
-            const double *Up = Us + (int64_t)n * N;
-            HIPCHK(hipMemcpyAsync(Un, psi, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
+    // Values U^n enter only the s-derivative.  Given `values`, they are read from there.  Otherwise (with
+    // dJ_ds) they are recomputed from g and the int16 policies by fixed-policy solves: a forward pass keeps
+    // every seg-th value (seg = ceil(sqrt(n_steps))), and the backward sweep recomputes one segment of at most
+    // seg + 1 values from its checkpoint before stepping through it: 2 n_steps solves and about
+    // 2 sqrt(n_steps) + 1 FP64 arrays instead of n_steps + 1.
+    const bool need_values = dJ_ds != nullptr;
+    const int seg = (values || !need_values) ? n_steps : std::max(1, (int)ceil(sqrt((double)n_steps)));
+    double *ck = nullptr, *sb = nullptr;  // checkpoints U^{k seg}, segment buffer U^{n0} .. U^{n0 + seg}
+    int seg_n0 = -1;                      // first step of the segment in sb
+    // U^n by a fixed-policy solve from U^{n-1}, started from the linear extrapolation of U^{n-2}, U^{n-1}
+    auto recompute = [&](int n, const double *Up, const double *Upp, double *Un) -> int {
+        HIPCHK(hipMemcpyAsync(Un, psi, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
+        if (Upp)
+            launch_extrapolate(dim, g0, Up, Upp, dts[n] / dts[n - 1], Un, str);
+        else
             launch_copy_interior(dim, g0, Up, Un, str);
-            int its = 0;
-            double res = 0.0;
-            bool tight = false;
-            int rc = linsolve_impl(hd, policies + (int64_t)n * N, Up, f0, f1, tprev[n], dts[n], thetas[n], Un, 0.0,
-                                   &its, &res, &tight);
-            loc.krylov_recompute += its;
-            if (rc != HJB_OK) return rc;
+        int its = 0;
+        double res = 0.0;
+        bool tight = false;
+        int rc = linsolve_impl(hd, policies + (int64_t)n * N, Up, f0, f1, tprev[n], dts[n], thetas[n], Un, 0.0, &its,
+                               &res, &tight);
+        loc.krylov_recompute += its;
+        return rc;
+    };
+    if (!values && need_values) {
+        const int ncp = (n_steps + seg - 1) / seg;
+        TRY(get(&ck, (size_t)ncp * N * 8));
+        TRY(get(&sb, (size_t)(seg + 1) * N * 8));
+        HIPCHK(hipMemcpyAsync(ck, g, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
+        const double *Up = g, *Upp = nullptr;  // three buffers of sb rotate (seg >= 2 here)
+        for (int n = 0; n + 1 < (ncp - 1) * seg + 1; ++n) {
+            double *Un = sb + (int64_t)(n % 3) * N;
+            TRY(recompute(n, Up, Upp, Un));
+            if ((n + 1) % seg == 0)
+                HIPCHK(hipMemcpyAsync(ck + (int64_t)((n + 1) / seg) * N, Un, (size_t)N * 8, hipMemcpyDeviceToDevice,
+                                      str));
+            Upp = Up;
+            Up = Un;
         }
-        Uv = Us;
     }
+    // U^m for a step n of the backward sweep (m = n or n + 1)
+    auto U_at = [&](int n, int m, const double **out) -> int {
+        if (values) {
+            *out = values + (int64_t)m * N;
+            return HJB_OK;
+        }
+        const int n0 = (n / seg) * seg;
+        if (n0 != seg_n0) {
+            const int n1 = std::min(n0 + seg, n_steps);
+            HIPCHK(hipMemcpyAsync(sb, ck + (int64_t)(n0 / seg) * N, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
+            for (int q = n0; q < n1; ++q)
+                TRY(recompute(q, sb + (int64_t)(q - n0) * N, q > n0 ? sb + (int64_t)(q - n0 - 1) * N : nullptr,
+                              sb + (int64_t)(q - n0 + 1) * N));
+            seg_n0 = n0;
+        }
+        *out = sb + (int64_t)(m - n0) * N;
+        return HJB_OK;
+    };
     TransposeHierarchy TH;
     {
         // int8 row offsets need every stencil point within 127 cells (2D)
@@ -2192,8 +2230,10 @@ int hjb_adjoint(hjb_handle *hd, const double *g, const double *psi, const double
         launch_axpy_interior(dim, g0, dt, mu, dJ_df0, str);
         if (dJ_df1) launch_axpy_interior(dim, g0, dt * t_mid, mu, dJ_df1, str);
         if (dJ_ds) {
-            launch_ds_dot(dim, g0, stencil(hd, 0), alpha, mu, Uv + (int64_t)(n + 1) * N, th, Uv + (int64_t)n * N,
-                          1.0 - th, inv_s, hd->partial, str);
+            const double *Un = nullptr, *Up = nullptr;
+            TRY(U_at(n, n + 1, &Un));
+            TRY(U_at(n, n, &Up));
+            launch_ds_dot(dim, g0, stencil(hd, 0), alpha, mu, Un, th, Up, 1.0 - th, inv_s, hd->partial, str);
             launch_reduce_sum(hd->partial, 1, hd->nb, hd->dvals + 200, str);
             TRY(sync_small(hd, hd->dvals + 200, hd->hpin + 200, sizeof(double)));
             ds += dt * hd->hpin[200];

@@ -275,3 +275,36 @@ def test_adjoint_with_stored_values(slhjb):
         assert np.max(np.abs(a - b)) <= 1e-10 * max(1.0, np.max(np.abs(a)))
     assert abs(outs[0][3] - outs[1][3]) <= 1e-9 * max(1.0, abs(outs[0][3]))
     solver.close()
+
+
+@pytest.mark.parametrize("n_cn", [1, 8, 14])
+def test_adjoint_checkpointed_recompute(slhjb, n_cn):
+    """Without stored values the adjoint recomputes them from the int16 policies, keeping every
+    ceil(sqrt(n_steps))-th value (3, 10 and 16 steps: segments of 2+1, 4+4+2 and 4x4 steps): the
+    gradients equal those with the forward's stored values, the recomputation costs about two fixed-policy
+    solves per step, and without dJ/ds nothing is recomputed."""
+    inst = workloads.config_c2(65, n_cn=n_cn)
+    n = len(inst.dts)
+    log(f"checkpointed recompute c2_65, {n} steps")
+    solver = slhjb.Solver.from_instance(inst)
+    g, psi, f0, f1 = to_dev(inst.g), to_dev(inst.psi), to_dev(inst.f0), to_dev(inst.f1)
+    U = torch.empty_like(g)
+    pol = torch.empty((n, inst.N), dtype=torch.int16, device="cuda")
+    vals = torch.empty((n + 1, inst.N), dtype=torch.float64, device="cuda")
+    fst = solver.solve(g, psi, f0, f1, inst.dts, inst.thetas, 1.0, U, pol, vals)
+    lam = torch.from_numpy(_lam_N(inst, to_np(U))).cuda()
+    res = {}
+    for name, v, want in (("stored", vals, True), ("recomputed", None, True), ("no ds", None, False)):
+        dg, df0, df1 = torch.empty_like(g), torch.empty_like(g), torch.empty_like(g)
+        ds, st = solver.adjoint(g, psi, f0, f1, inst.dts, inst.thetas, 1.0, pol, lam, df0, dg, dJ_df1=df1,
+                                values=v, want_ds=want)
+        log(f"  {name}: recompute its {st.krylov_recompute}, adjoint its {st.krylov_adjoint}, ds {ds}")
+        res[name] = (to_np(dg), to_np(df0), to_np(df1), ds, st)
+    assert res["stored"][4].krylov_recompute == 0 and res["no ds"][4].krylov_recompute == 0
+    assert res["recomputed"][4].krylov_recompute > 0
+    for name in ("recomputed", "no ds"):
+        for a, b in zip(res[name][:3], res["stored"][:3]):
+            assert np.max(np.abs(a - b)) <= 1e-10 * max(1.0, np.max(np.abs(b)))
+    ds_r, ds_s = res["recomputed"][3], res["stored"][3]
+    assert abs(ds_r - ds_s) <= 1e-9 * max(1.0, abs(ds_s))
+    solver.close()

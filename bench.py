@@ -242,8 +242,8 @@ def measured_traffic(kernel, pi_per_step):
     tot = lambda name: per[name]["read_bytes"] + per[name]["write_bytes"]
     if kernel == "sweep":
         # timed Crank-Nicolson steps: one search storing the explicit part, then pi_per_step reading it
-        a = [k for k in per if "k_sweep<2, true, false, 1, false>" in k]
-        b = [k for k in per if "k_sweep<2, true, false, 2, false>" in k]
+        a = [k for k in per if "k_sweep<2, true, false, 1, false, false>" in k]
+        b = [k for k in per if "k_sweep<2, true, false, 2, false, false>" in k]
         if not a or not b:
             return None
         return (tot(a[0]) + pi_per_step * tot(b[0])) / (1.0 + pi_per_step)

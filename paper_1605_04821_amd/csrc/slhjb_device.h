@@ -263,36 +263,6 @@ __device__ __forceinline__ TC interp_land(const TS *__restrict__ V, const LevelD
     return interp_w<DIM, TS, TC>(V, base, g, w);
 }
 
-// Whether node ix lies where no stencil point of control k is truncated and every landing cell, with its
-// upper corners, is inside the grid: 0 <= ix_d + floor(Y_d) <= n_d - 2 on every axis for every point.  Then
-// every ratio D/|Y_d| of the landing is at least 1 (mu = 1, A = B = C = 1) and no cell is clamped: the
-// general rules give the untruncated landing of the tables (in FP64 the same corner weights and sums bit for
-// bit; in FP32 the tables' weights are the FP64 ones rounded once).  Constant coefficients only (per-node
-// displacements have no tables).
-template <int DIM>
-__device__ __forceinline__ bool lands_inside(const LevelDev &g, const StencilDev &st, int k, const int ix[3]) {
-    const FastPtF *fp = st.fastF + ((unsigned)k < (unsigned)st.K ? k : 0) * st.npt;
-    bool ok = true;
-    for (int q = 0; q < st.npt; ++q)
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-            const int c = ix[d] + fp[q].fl[d];
-            ok = ok && c >= 0 && c <= g.n[d] - 2;
-        }
-    return ok;
-}
-
-// deep, or (constant coefficients) every point of control k lands inside the grid untruncated; the tables are
-// read through the scalar unit when k is the same on every active lane
-template <int DIM>
-__device__ __forceinline__ bool untruncated(const LevelDev &g, const StencilDev &st, int k, const int ix[3],
-                                            bool deep) {
-    if (st.pernode || __all(deep)) return deep;
-    const int k0 = __builtin_amdgcn_readfirstlane(k);
-    if (__all(k == k0)) return deep || lands_inside<DIM>(g, st, k0, ix);
-    return deep || lands_inside<DIM>(g, st, k, ix);
-}
-
 // (L-hat^k V)_i for one or two fields sharing the stencil geometry (eq. TruncScheme).
 // TS: storage type of the fields, TC: arithmetic type.
 template <int DIM, typename TS, typename TC, bool TWO>
@@ -482,7 +452,6 @@ template <int DIM, typename TS, typename TC>
 __device__ __forceinline__ TC lhat1(const LevelDev &g, const StencilDev &st, int k, int i, const int ix[3], bool deep,
                                     const TS *__restrict__ V, TC Vi) {
     TC a, b;
-    deep = untruncated<DIM>(g, st, k, ix, deep);
     // the policy is piecewise constant: when the whole wavefront shares one control (and is untruncated),
     // its stencil tables are read once through the scalar unit instead of per lane
     int k0 = __builtin_amdgcn_readfirstlane(k);
@@ -538,8 +507,7 @@ __device__ __forceinline__ double eval_G(const LevelDev &g, const StencilDev &st
         q = Q[(int64_t)k * qstride + qslot];
     } else {
         if (CN)
-            lhat_node<DIM, double, double, true>(g, st, k, i, ix, untruncated<DIM>(g, st, k, ix, deep), X, Xi, U, Ui,
-                                                 lx, lu);
+            lhat_node<DIM, double, double, true>(g, st, k, i, ix, deep, X, Xi, U, Ui, lx, lu);
         else
             lx = lhat1<DIM, double, double>(g, st, k, i, ix, deep, X, Xi);
         q = omt * (lu + ck * Ui);

@@ -284,7 +284,6 @@ int build_tables(hjb_handle *hd, double s) {
             memset(&hf[q], 0, sizeof(FastPtF));
             memset(&hdd[q], 0, sizeof(FastPtD));
             hf[q].off = hdd[q].off = (int32_t)host[q].off;
-            for (int a = 0; a < hd->dim; ++a) hf[q].fl[a] = (int32_t)floor(host[q].Y[a]);
             const double *t = host[q].t;
             for (int c = 0; c < (1 << hd->dim); ++c) {
                 double w = (c & 1) ? t[0] : (1.0 - t[0]);
@@ -864,15 +863,13 @@ int fgmres(hjb_handle *hd, const int16_t *alpha, const double *E, double *X, dou
     const StencilDev st = stencil(hd, 0);
     hipStream_t s = hd->stream;
     KrylovOp op;
-    // the level-0 wave-control table of prepare_mg belongs to this solve's policy
-    const int16_t *wctl = (L0.wctl_ok && L0.alpha == alpha) ? L0.wctl : nullptr;
     op.residual = [=]() {
-        launch_residual(dim, L0.g, st, alpha, X, E, theta_dt, hd->R, hd->partial, hd->nb, s, wctl);
+        launch_residual(dim, L0.g, st, alpha, X, E, theta_dt, hd->R, hd->partial, hd->nb, s);
     };
     // the application reads the handle's stream when it runs: it may be captured into a V-cycle's graph
     op.apply = [=](const void *z, bool zf, double *w) {
         TimedLaunch tl(hd, HJB_KERNEL_APPLY, (double)hd->N * ((zf ? 4.0 : 8.0) + 2.0 + 8.0));
-        launch_apply(dim, L0.g, st, alpha, z, zf, w, theta_dt, nullptr, hd->nb, hd->stream, wctl);
+        launch_apply(dim, L0.g, st, alpha, z, zf, w, theta_dt, nullptr, hd->nb, hd->stream);
     };
     if (hd->desc.precond != HJB_PRECOND_NONE)
         op.precond = [=](const double *v, void *z, bool ready) { return precondition(hd, v, z, theta_dt, ready); };

@@ -56,12 +56,10 @@ struct PointTab {
 // Untruncated landing used by the node loops: linear offset of the landing cell and the 2^d corner
 // weights (corner c: bit d set = upper corner on axis d; weight = product over axes of t_d or 1 - t_d).
 // Sizes are multiples of 16 bytes so kernels whose control varies per node can stage them in LDS.
-// FastPtF also keeps the cell offset per axis, floor(Y_d) (0 beyond the dimension), for the test of
-// whether a node outside the untruncated box lands inside the grid.
 struct FastPtF {
     int32_t off;
     float w[8];
-    int32_t fl[3];
+    int32_t pad[3];
 };
 struct FastPtD {
     int32_t off;
@@ -192,12 +190,11 @@ void launch_explicit_update(int dim, const LevelDev &g, const double *U, const d
 
 // Wave-control table (wctl, nullable): per wavefront of the tile mapping, the control shared by all its 64 nodes
 // when all are untruncated interior nodes, else -1; written by launch_diag for the level's current policy.  With
-// it the node kernels read neither the policy nor the diagonal on such wavefronts.
+// it the multigrid smoother and residual read neither the policy nor the diagonal on such wavefronts.
 
 // y = x - theta dt (L x + c x) on interior nodes, 0 on the boundary (x may be float or double)
 void launch_apply(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const void *x,
-                  bool x_is_float, double *y, double theta_dt, double *norm2_partial, int nblocks, hipStream_t s,
-                  const int16_t *wctl = nullptr);
+                  bool x_is_float, double *y, double theta_dt, double *norm2_partial, int nblocks, hipStream_t s);
 
 // E = U + (1-theta) dt (L U + c U) + dt (f0 + t_mid f1)
 void launch_explicit(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const double *U,
@@ -206,8 +203,7 @@ void launch_explicit(int dim, const LevelDev &g, const StencilDev &st, const int
 
 // r = E - (V - theta dt (L V + c V)); partials: [3][nblocks] = sum r^2, max|r|, max|V| (interior)
 void launch_residual(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const double *V,
-                     const double *E, double theta_dt, double *r, double *partial, int nblocks, hipStream_t s,
-                     const int16_t *wctl = nullptr);
+                     const double *E, double theta_dt, double *r, double *partial, int nblocks, hipStream_t s);
 
 // multigrid level kernels, T = float or double
 // d = diagonal of A on the level; with wctl (ignored without per-control deep values) also the wave-control

@@ -375,22 +375,13 @@ void launch_norms_xuf(int dim, const LevelDev &g, const double *X, const double 
 template <int DIM, typename TX>
 __global__ __launch_bounds__(kBlock) void k_apply(LevelDev g, StencilDev st0, const int16_t *__restrict__ alpha,
                                                   const TX *__restrict__ x, double *__restrict__ y, double theta_dt,
-                                                  double *norm2_partial, const int16_t *__restrict__ wctl) {
+                                                  double *norm2_partial) {
     __shared__ double sh[kBlock / 64];
     const StencilDev &st = st0;
-    const int tile = remap_block(blockIdx.x, gridDim.x);
     int ix[3];
-    int i = tile_node_at<DIM>(g, tile, ix);
+    int i = tile_node<DIM>(g, ix);
     double yy = 0.0;
-    const int wc = i >= 0 ? wave_control(wctl, tile) : -1;
-    if (wc >= 0) {
-        double xi = (double)x[i];
-        double l, unused;
-        lhat_node<DIM, TX, double, false>(g, st, wc, i, ix, true, x, xi, x, xi, l, unused);
-        double ck = st.c ? st.c[wc] : 0.0;
-        yy = xi - theta_dt * (l + ck * xi);
-        y[i] = yy;
-    } else if (i >= 0) {
+    if (i >= 0) {
         if (interior<DIM>(g, ix)) {
             int k = alpha[i];
             bool deep = deep_node<DIM>(g, ix);
@@ -408,10 +399,9 @@ __global__ __launch_bounds__(kBlock) void k_apply(LevelDev g, StencilDev st0, co
 }
 
 void launch_apply(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const void *x,
-                  bool x_is_float, double *y, double theta_dt, double *norm2_partial, int nblocks, hipStream_t s,
-                  const int16_t *wctl) {
+                  bool x_is_float, double *y, double theta_dt, double *norm2_partial, int nblocks, hipStream_t s) {
 #define AP(D, TX) SLHJB_LAUNCH((k_apply<D, TX>), dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, \
-                               (const TX *)x, y, theta_dt, norm2_partial, wctl)
+                               (const TX *)x, y, theta_dt, norm2_partial)
     if (x_is_float) {
         if (dim == 2) AP(2, float); else AP(3, float);
     } else {
@@ -461,24 +451,13 @@ void launch_explicit(int dim, const LevelDev &g, const StencilDev &st, const int
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_residual(LevelDev g, StencilDev st0, const int16_t *__restrict__ alpha,
                                                      const double *__restrict__ V, const double *__restrict__ E,
-                                                     double theta_dt, double *__restrict__ r, double *partial,
-                                                     const int16_t *__restrict__ wctl) {
+                                                     double theta_dt, double *__restrict__ r, double *partial) {
     __shared__ double sh[kBlock / 64];
     const StencilDev &st = st0;
-    const int tile = remap_block(blockIdx.x, gridDim.x);
     int ix[3];
-    int i = tile_node_at<DIM>(g, tile, ix);
+    int i = tile_node<DIM>(g, ix);
     double rr = 0.0, vv = 0.0;
-    const int wc = i >= 0 ? wave_control(wctl, tile) : -1;
-    if (wc >= 0) {
-        const double Vi = V[i], Ei = E[i];
-        vv = fabs(Vi);
-        double l, unused;
-        lhat_node<DIM, double, double, false>(g, st, wc, i, ix, true, V, Vi, V, Vi, l, unused);
-        double ck = st.c ? st.c[wc] : 0.0;
-        rr = Ei - (Vi - theta_dt * (l + ck * Vi));
-        r[i] = rr;
-    } else if (i >= 0) {
+    if (i >= 0) {
         double Vi = V[i];
         vv = fabs(Vi);
         if (interior<DIM>(g, ix)) {
@@ -501,14 +480,11 @@ __global__ __launch_bounds__(kBlock) void k_residual(LevelDev g, StencilDev st0,
 }
 
 void launch_residual(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, const double *V,
-                     const double *E, double theta_dt, double *r, double *partial, int nblocks, hipStream_t s,
-                     const int16_t *wctl) {
+                     const double *E, double theta_dt, double *r, double *partial, int nblocks, hipStream_t s) {
     if (dim == 2)
-        hipLaunchKernelGGL(k_residual<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, V, E, theta_dt, r, partial,
-                           wctl);
+        hipLaunchKernelGGL(k_residual<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, V, E, theta_dt, r, partial);
     else
-        hipLaunchKernelGGL(k_residual<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, V, E, theta_dt, r, partial,
-                           wctl);
+        hipLaunchKernelGGL(k_residual<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, V, E, theta_dt, r, partial);
 }
 
 // number of interior nodes whose control index is outside [0, K)

@@ -60,6 +60,8 @@ enum {
 enum { HJB_PREC_FP64 = 0, HJB_PREC_MIXED = 1 }; /* V-cycle in FP64, or in FP32 under FP64 FGMRES */
 enum { HJB_PRECOND_NONE = 0, HJB_PRECOND_JACOBI = 1, HJB_PRECOND_VCYCLE = 2 };
 enum { HJB_KRYLOV_FGMRES = 0, HJB_KRYLOV_BICGSTAB = 1 };  /* outer FP64 Krylov method of the linear solves */
+/* coarse operators of the V-cycle: rediscretised on each level, or Galerkin products R A P (Section 3.3) */
+enum { HJB_COARSE_REDISCRETIZED = 0, HJB_COARSE_GALERKIN = 1 };
 /* Flags of hjb_step_stats / hjb_solve_stats (bitwise or). */
 enum {
     HJB_FLAG_POSITIVITY = 1,  /* positivity of the weights (eq. CFL_trunc) may fail: theta < 1 and
@@ -114,6 +116,11 @@ typedef struct {
                                right-preconditioned by the same V-cycle or Jacobi, same stopping rule and
                                certificate, restarted from the true residual) for every linear solve of the
                                handle, transposed solves included; batches take FGMRES only */
+    int32_t coarse_op;      /* HJB_COARSE_REDISCRETIZED (default) or HJB_COARSE_GALERKIN: coarse levels of the forward
+                               V-cycle are A_{l+1} = R A_l P (full weighting R, bilinear P, Section 3.3), rebuilt
+                               for every policy and held as sliced ELL rows of at most 128 entries (wider rows
+                               fail with HJB_EUNSUPPORTED); damped Jacobi on them.  2D only; the adjoint's
+                               transposed cycles and batches keep rediscretised levels */
     void *stream;           /* hipStream_t */
 } hjb_desc;
 
@@ -272,6 +279,13 @@ int hjb_adjoint(hjb_handle *hd, const double *g, const double *psi, const double
    x, y: full-grid FP64 (distinct). */
 int hjb_apply_transposed(hjb_handle *hd, const int16_t *alpha, const double *x, double *y, double dt, double theta,
                          double s);
+
+/* The Galerkin coarse operator of multigrid level `level` (>= 1; HJB_COARSE_GALERKIN) for the policy of the
+ * handle's last solve: sliced ELL rows over the level's full grid, entry s of node i at s * nodes + i
+ * (column index on the level, -1 for an unused slot; boundary rows empty), copied to the caller's device
+ * buffers cols / vals (width * nodes entries each; either may be NULL).  width and nodes (nullable) receive
+ * the ELL width and the level's node count.  HJB_EINVAL for a level without a Galerkin operator. */
+int hjb_coarse_operator(hjb_handle *hd, int32_t level, int32_t *width, int64_t *nodes, int32_t *cols, double *vals);
 
 /* ---- batches of independent instances (uneven grids, coefficients and multigrid depths) ----------
 

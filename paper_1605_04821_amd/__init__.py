@@ -23,9 +23,10 @@ PREC_FP64, PREC_MIXED = 0, 1
 COEF_CONST, COEF_XSCALED, COEF_FIELD = 0, 1, 2
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_VCYCLE = 0, 1, 2
 KRYLOV_FGMRES, KRYLOV_BICGSTAB = 0, 1
+COARSE_REDISCRETIZED, COARSE_GALERKIN = 0, 1
 FLAG_POSITIVITY, FLAG_NEAR_TIES = 1, 2
 
-EXPORTED = ["hjb_desc_default", "hjb_setup", "hjb_set_stream", "hjb_set_options", "hjb_policy_sweep",
+EXPORTED = ["hjb_coarse_operator", "hjb_desc_default", "hjb_setup", "hjb_set_stream", "hjb_set_options", "hjb_policy_sweep",
             "hjb_policy_sweep_noalloc", "hjb_apply",
             "hjb_linsolve", "hjb_step", "hjb_solve", "hjb_adjoint", "hjb_apply_transposed", "hjb_profile_enable",
             "hjb_profile_read", "hjb_profile_sample", "hjb_destroy", "hjb_last_error", "hjb_setup_batch", "hjb_batch_layout",
@@ -53,7 +54,7 @@ class Desc(ctypes.Structure):
                 ("pi_eta", ctypes.c_double), ("use_graphs", ctypes.c_int32), ("f_per_control", ctypes.c_int32),
                 ("certified_skip", ctypes.c_int32), ("max_levels", ctypes.c_int32),
                 ("nu_tight", ctypes.c_int32), ("coarse_sweeps_t", ctypes.c_int32),
-                ("krylov", ctypes.c_int32),
+                ("krylov", ctypes.c_int32), ("coarse_op", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
 
 
@@ -94,6 +95,7 @@ def _load():
     L.hjb_policy_sweep_noalloc.argtypes = [vp, vp, vp, vp, vp, d, d, d, d, vp, vp, vp, vp, vp,
                                            ctypes.POINTER(i64), ctypes.POINTER(d)]
     L.hjb_apply.argtypes = [vp, vp, vp, vp, d, d, d]
+    L.hjb_coarse_operator.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i64), vp, vp]
     L.hjb_linsolve.argtypes = [vp, vp, vp, vp, vp, d, d, d, d, vp, ctypes.POINTER(StepStats)]
     L.hjb_step.argtypes = [vp, vp, vp, vp, vp, d, d, d, d, vp, vp, d, ctypes.POINTER(StepStats)]
     L.hjb_solve.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp, vp, d, vp, vp, vp, ctypes.POINTER(SolveStats)]
@@ -174,6 +176,7 @@ class Options:
     nu_tight: int = 4
     coarse_sweeps_t: int = 2
     krylov: int = 0
+    coarse_op: int = 0
 
 
 class Solver:
@@ -234,6 +237,7 @@ class Solver:
         desc.nu_tight = o.nu_tight
         desc.coarse_sweeps_t = o.coarse_sweeps_t
         desc.krylov = o.krylov
+        desc.coarse_op = o.coarse_op
 
     @classmethod
     def from_instance(cls, inst, options: Optional[Options] = None):
@@ -328,6 +332,18 @@ class Solver:
                                 _ptr(dJ_df1), _ptr(dJ_dg), ctypes.byref(ds) if want_ds else None,
                                 ctypes.byref(st)))
         return (float(ds.value) if want_ds else None), st
+
+    def coarse_operator(self, level: int):
+        """hjb_coarse_operator: the Galerkin operator of one level as (cols, vals) device tensors of shape
+        (width, nodes) (slot-major sliced ELL, column -1 for unused slots)."""
+        import torch
+        self._sync_stream()
+        w, n = ctypes.c_int32(0), ctypes.c_int64(0)
+        _check(_lib.hjb_coarse_operator(self._h, int(level), ctypes.byref(w), ctypes.byref(n), None, None))
+        cols = torch.empty((w.value, n.value), dtype=torch.int32, device="cuda")
+        vals = torch.empty((w.value, n.value), dtype=torch.float64, device="cuda")
+        _check(_lib.hjb_coarse_operator(self._h, int(level), None, None, _ptr(cols), _ptr(vals)))
+        return cols, vals
 
     def set_tile_width(self, width: int):
         self._sync_stream()

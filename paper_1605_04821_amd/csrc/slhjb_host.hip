@@ -49,10 +49,10 @@ int fail(int code, const char *fmt, ...) {
 }
 
 // Slots of the small device/host scalar arrays (dvals, hpin): [0, 16) solver scalars, [16, 23) the
-// BiCGSTAB recurrence, 200 the adjoint
-// gradient term, and the two Gram-Schmidt passes of one Arnoldi step from kGsSlot0 and kGsSlot1 (m + 2
-// each).
+// BiCGSTAB recurrence, 200 the adjoint gradient term, 230 the widest Galerkin row, and the two
+// Gram-Schmidt passes of one Arnoldi step from kGsSlot0 and kGsSlot1 (m + 2 each).
 constexpr int kGsSlot0 = 256, kGsSlot1 = kGsSlot0 + kMaxRestart + 2;
+constexpr int kGalSlot = 230;  // the widest Galerkin row
 constexpr int kSmallSlots = 512;
 static_assert(kGsSlot1 + kMaxRestart + 2 <= kSmallSlots, "small-slot layout");
 
@@ -81,7 +81,13 @@ struct Level {
     float *dk32 = nullptr;
     double *dk64 = nullptr;
     bool wctl_ok = false;
+    // Galerkin coarse operator (levels >= 1 with HJB_COARSE_GALERKIN): sliced ELL, kGalWidth slots
+    int32_t *gcol = nullptr;
+    double *gval = nullptr;
+    float *gval32 = nullptr;
 };
+
+constexpr int kGalWidth = 128;  // slots of a Galerkin coarse row
 
 }  // namespace
 
@@ -97,6 +103,10 @@ struct hjb_handle {
     int64_t N = 0;
     int nb = 0, nbd = 0;
     int nb_cap = 0;      // largest level-0 tile count over the tile shapes the handle may take
+    // Galerkin coarse operators: the finest level's rows (npt * 4 + 1 slots) and a device overflow word
+    int32_t *g0col = nullptr;
+    double *g0val = nullptr;
+    int32_t *goverflow = nullptr;
     // certified reuse of search decisions within a step: gap bounds [N], X at the previous search [N],
     // per-tile largest change of X and its stencil-window maximum [nb_cap], window radius in nodes per axis
     double *marg = nullptr, *Xs = nullptr, *dtile = nullptr, *dwin = nullptr;
@@ -383,6 +393,10 @@ int check_options(const hjb_desc *d) {
     if (d->nu_tight < 0 || d->nu_tight > 16) return fail(HJB_EINVAL, "nu_tight in 0..16");
     if (d->coarse_sweeps_t < 0 || d->coarse_sweeps_t > 1000) return fail(HJB_EINVAL, "coarse_sweeps_t in 0..1000");
     if (d->krylov != HJB_KRYLOV_FGMRES && d->krylov != HJB_KRYLOV_BICGSTAB) return fail(HJB_EINVAL, "krylov");
+    if (d->coarse_op != HJB_COARSE_REDISCRETIZED && d->coarse_op != HJB_COARSE_GALERKIN)
+        return fail(HJB_EINVAL, "coarse_op");
+    if (d->coarse_op == HJB_COARSE_GALERKIN && d->dim != 2)
+        return fail(HJB_EUNSUPPORTED, "Galerkin coarse operators are provided for 2D grids");
     if (d->krylov == HJB_KRYLOV_BICGSTAB && d->restart < 3)
         return fail(HJB_EINVAL, "BiCGSTAB keeps four vectors in the Krylov basis storage: restart must be >= 3");
     return HJB_OK;
@@ -391,6 +405,35 @@ int check_options(const hjb_desc *d) {
 // ---- multigrid ---------------------------------------------------------------------------------
 
 constexpr int64_t kCoarseMaxNodes = 2048;  // LDS-resident coarsest level (two FP64 buffers = 32 KiB)
+
+// Galerkin coarse operators for the policy: the finest level's rows, then A_{l+1} = R A_l P level by level,
+// each level's diagonal (for the smoother) and FP32 weights; the widest row is checked against the ELL width.
+int publish_wait(hjb_handle *hd, const void *dev0, void *host0, size_t bytes0, const void *dev1, void *host1,
+                 size_t bytes1);
+
+int build_galerkin(hjb_handle *hd, const int16_t *alpha, double theta_dt) {
+    hipStream_t s = hd->stream;
+    const int E0 = hd->npt * 4 + 1;
+    int32_t *wide = (int32_t *)(hd->hpin + kGalSlot);  // pinned host word
+    launch_gal_emit(hd->lev[0].g, stencil(hd, 0), alpha, theta_dt, E0, hd->g0col, hd->g0val, s);
+    int Wf = E0;
+    for (size_t l = 1; l < hd->lev.size(); ++l) {
+        Level &F = hd->lev[l - 1], &C = hd->lev[l];
+        const int32_t *fc = l == 1 ? hd->g0col : F.gcol;
+        const double *fv = l == 1 ? hd->g0val : F.gval;
+        launch_zero(hd->goverflow, 4, s);
+        if (launch_gal_rap(F.g, C.g, Wf, fc, fv, kGalWidth, C.gcol, C.gval, hd->goverflow, s) != 0)
+            return fail(HJB_EUNSUPPORTED, "Galerkin product: rows of level %d have %d entries", (int)l - 1, Wf);
+        launch_gal_diag(C.g.N, kGalWidth, C.gcol, C.gval, C.gval32, mixed(hd) ? (float *)C.d : nullptr,
+                        mixed(hd) ? nullptr : (double *)C.d, s);
+        TRY(publish_wait(hd, hd->goverflow, wide, 8, nullptr, nullptr, 0));
+        if (wide[0] > kGalWidth)
+            return fail(HJB_EUNSUPPORTED, "Galerkin coarse row with %d entries (the ELL width is %d)", wide[0],
+                        kGalWidth);
+        Wf = std::max(1, wide[0]);
+    }
+    return HJB_OK;
+}
 
 int prepare_mg(hjb_handle *hd, const int16_t *alpha, double theta_dt) {
     hipStream_t s = hd->stream;
@@ -408,6 +451,7 @@ int prepare_mg(hjb_handle *hd, const int16_t *alpha, double theta_dt) {
             launch_diag<double>(hd->dim, L.g, st, L.alpha, theta_dt, (double *)L.d, s, L.wctl_ok ? L.wctl : nullptr,
                                 L.dk64);
     }
+    if (hd->desc.coarse_op == HJB_COARSE_GALERKIN && hd->lev.size() > 1) TRY(build_galerkin(hd, alpha, theta_dt));
     HIPCHK(hipGetLastError());
     return HJB_OK;
 }
@@ -416,6 +460,16 @@ template <typename T>
 void smooth_level(hjb_handle *hd, int l, T *&e, T *&t, const T *r, int sweeps, bool first, double theta_dt) {
     Level &L = hd->lev[l];
     StencilDev st = stencil(hd, l);
+    if (l >= 1 && L.gcol) {
+        const T *gv;
+        if constexpr (std::is_same<T, float>::value) gv = L.gval32; else gv = L.gval;
+        for (int q = 0; q < sweeps; ++q) {
+            launch_gal_jacobi<T>(L.g.N, kGalWidth, L.gcol, gv, (const T *)L.d, e, r, t, hd->desc.omega,
+                                 first && q == 0, hd->stream);
+            std::swap(e, t);
+        }
+        return;
+    }
     for (int q = 0; q < sweeps; ++q) {
         bool gathers = !(first && q == 0);
         // algorithmic bytes: e, r, alpha in, e out (the diagonal is a derived quantity, not counted)
@@ -461,14 +515,20 @@ void vcycle(hjb_handle *hd, const T *r0, T *z, double theta_dt) {
         smooth_level<T>(hd, l, e[l], t[l], r[l], hd->nu_pre, true, theta_dt);
         {
             TimedLaunch tl(hd, l == 0 ? HJB_KERNEL_MG_RESID : -1, (double)L.g.N * (3.0 * sizeof(T) + 2.0));
-            launch_level_residual<T>(hd->dim, L.g, stencil(hd, l), L.alpha, e[l], r[l], t[l], theta_dt, s,
-                                     L.wctl_ok ? L.wctl : nullptr);
+            if (l >= 1 && L.gcol) {
+                const T *gv;
+                if constexpr (std::is_same<T, float>::value) gv = L.gval32; else gv = L.gval;
+                launch_gal_residual<T>(L.g.N, kGalWidth, L.gcol, gv, e[l], r[l], t[l], s);
+            } else {
+                launch_level_residual<T>(hd->dim, L.g, stencil(hd, l), L.alpha, e[l], r[l], t[l], theta_dt, s,
+                                         L.wctl_ok ? L.wctl : nullptr);
+            }
         }
         launch_restrict<T>(hd->dim, L.g, hd->lev[l + 1].g, t[l], (T *)hd->lev[l + 1].r, s);
     }
     {
         Level &C = hd->lev[Lc];
-        if (C.g.N <= kCoarseMaxNodes) {
+        if (C.g.N <= kCoarseMaxNodes && !C.gcol) {
             launch_coarse_solve<T>(hd->dim, C.g, stencil(hd, Lc), C.alpha, r[Lc], (const T *)C.d, e[Lc], t[Lc],
                                    theta_dt, d.omega, d.coarse_sweeps, s);
         } else {
@@ -1163,6 +1223,7 @@ void hjb_desc_default(hjb_desc *d) {
     d->nu_tight = 4;
     d->coarse_sweeps_t = 2;
     d->krylov = HJB_KRYLOV_FGMRES;
+    d->coarse_op = HJB_COARSE_REDISCRETIZED;
     d->stream = nullptr;
 }
 
@@ -1321,6 +1382,17 @@ int setup_impl(const hjb_desc *desc, hjb_handle **out, bool tables_only) {
         STRY(dalloc(hd, (void **)&L.wctl, (size_t)tiles_cap(L.g, d.dim) * (kBlock / 64) * sizeof(int16_t)));
         STRY(dalloc(hd, (void **)&L.dk32, (size_t)d.K * sizeof(float)));
         STRY(dalloc(hd, (void **)&L.dk64, (size_t)d.K * sizeof(double)));
+        if (d.coarse_op == HJB_COARSE_GALERKIN && l >= 1 && !tables_only) {
+            STRY(dalloc(hd, (void **)&L.gcol, n * kGalWidth * 4));
+            STRY(dalloc(hd, (void **)&L.gval, n * kGalWidth * 8));
+            STRY(dalloc(hd, (void **)&L.gval32, n * kGalWidth * 4));
+        }
+        if (d.coarse_op == HJB_COARSE_GALERKIN && l == 0 && !tables_only) {
+            const size_t E0 = (size_t)hd->npt * 4 + 1;
+            STRY(dalloc(hd, (void **)&hd->g0col, n * E0 * 4));
+            STRY(dalloc(hd, (void **)&hd->g0val, n * E0 * 8));
+            STRY(dalloc(hd, (void **)&hd->goverflow, 8));
+        }
         if (d.coef_model == HJB_COEF_FIELD) {
             // per-node sigma on this level: the finest level's value at the coinciding node
             const int pd = d.P * d.dim, stp = 1 << l;
@@ -1456,6 +1528,7 @@ int hjb_set_options(hjb_handle *hd, const hjb_desc *desc) {
     d.nu_tight = desc->nu_tight;
     d.coarse_sweeps_t = desc->coarse_sweeps_t;
     d.krylov = desc->krylov;
+    if (desc->coarse_op != d.coarse_op) return fail(HJB_EINVAL, "coarse_op is fixed at setup");
     select_precision(hd);
     set_sweeps(hd, false);
     drop_graphs(hd);
@@ -2243,6 +2316,20 @@ int hjb_adjoint(hjb_handle *hd, const double *g, const double *psi, const double
     HIPCHK(hipStreamSynchronize(str));
     if (dJ_ds) *dJ_ds = ds;
     if (stats) *stats = loc;
+    return HJB_OK;
+}
+
+int hjb_coarse_operator(hjb_handle *hd, int32_t level, int32_t *width, int64_t *nodes, int32_t *cols, double *vals) {
+    if (!hd) return fail(HJB_EINVAL, "null handle");
+    if (level < 1 || level >= (int)hd->lev.size() || !hd->lev[level].gcol)
+        return fail(HJB_EINVAL, "level %d has no Galerkin operator", (int)level);
+    const Level &L = hd->lev[level];
+    if (width) *width = kGalWidth;
+    if (nodes) *nodes = L.g.N;
+    const size_t n = (size_t)L.g.N * kGalWidth;
+    if (cols) HIPCHK(hipMemcpyAsync(cols, L.gcol, n * 4, hipMemcpyDeviceToDevice, hd->stream));
+    if (vals) HIPCHK(hipMemcpyAsync(vals, L.gval, n * 8, hipMemcpyDeviceToDevice, hd->stream));
+    HIPCHK(hipStreamSynchronize(hd->stream));
     return HJB_OK;
 }
 

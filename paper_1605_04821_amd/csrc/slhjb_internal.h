@@ -275,6 +275,24 @@ void launch_extrapolate(int dim, const LevelDev &g, const double *U1, const doub
 
 int blocks_for(int64_t N);
 
+// Galerkin coarse operators (slhjb_galerkin.hip), 2D: ELL slot-major (entry s of row i at s * N + i, column -1
+// unused).  emit: rows of A = I - theta dt (L-hat + c) at the interior nodes of the finest level (E = npt * 4 + 1
+// slots); rap: R A P onto the next level (Wc slots; *overflow = the widest row when wider than Wc); diag: the
+// diagonal (1 on boundary rows) and optional FP32 weights; jacobi / residual: the smoother and residual.
+void launch_gal_emit(const LevelDev &g, const StencilDev &st, const int16_t *alpha, double theta_dt, int E,
+                     int32_t *col, double *val, hipStream_t s);
+int gal_sort_size(int Wf);
+int launch_gal_rap(const LevelDev &gf, const LevelDev &gc, int Wf, const int32_t *fcol, const double *fval, int Wc,
+                   int32_t *ccol, double *cval, int32_t *overflow, hipStream_t s);
+void launch_gal_diag(int64_t N, int W, const int32_t *col, const double *val, float *val32, float *d32, double *d64,
+                     hipStream_t s);
+template <typename T>
+void launch_gal_jacobi(int64_t N, int W, const int32_t *col, const T *val, const T *d, const T *e, const T *r, T *out,
+                       double omega, bool first, hipStream_t s);
+template <typename T>
+void launch_gal_residual(int64_t N, int W, const int32_t *col, const T *val, const T *e, const T *r, T *res,
+                         hipStream_t s);
+
 // adjoint (slhjb_adjoint.hip)
 // Row listing of one level's operator (slots [i*E, (i+1)*E)) and its column-sorted form.
 // The sorted entries are also laid out as sliced ELL: slice = one wavefront of the node kernels' launch

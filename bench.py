@@ -204,12 +204,13 @@ def batch_cost(slhjb, torch, mode):
             "krylov_total": int(sum(x.krylov_total for x in st)), "max_rel_diff_vs_sequential": worst}
 
 
-def march_rate(slhjb, torch, inst, mode, n_steps=None):
+def march_rate(slhjb, torch, inst, mode, n_steps=None, **options):
     """Time steps per second of hjb_solve over the instance's schedule (its first n_steps), after one
-    untimed march; policy iterations and Krylov iterations of the timed march."""
+    untimed march; policy iterations and Krylov iterations of the timed march.  options: further solver
+    options (coarse operators, depth of the hierarchy)."""
     import numpy as np
     prec = slhjb.PREC_MIXED if mode == "mixed" else slhjb.PREC_FP64
-    solver = slhjb.Solver.from_instance(inst, slhjb.Options(precision=prec))
+    solver = slhjb.Solver.from_instance(inst, slhjb.Options(precision=prec, **options))
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     g, psi, f0, f1 = dev(inst.g), dev(inst.psi), dev(inst.f0), dev(inst.f1)
     dts = inst.dts if n_steps is None else inst.dts[:n_steps]
@@ -399,6 +400,17 @@ def main():
             configs[name] = {m: march_rate(slhjb, torch, wl, m, nst) for m in ("mixed", "fp64")}
             print(f"[bench]   mixed {configs[name]['mixed']['steps_per_s']:.2f} steps/s, fp64 "
                   f"{configs[name]['fp64']['steps_per_s']:.2f} steps/s", file=sys.stderr, flush=True)
+    coarse = None
+    if not args.no_configs:
+        # Section 3.3: Galerkin coarse operators R A P (rebuilt for every policy) against rediscretised levels
+        coarse = {}
+        for name, wl, nst in (("c2 257^2", workloads.config_c2(257), None), ("h 2049^2 (first 6 steps)", inst, 6)):
+            for label, cop, ml in (("rediscretised, 2 levels", 0, 2), ("galerkin, 2 levels", 1, 2),
+                                   ("rediscretised, all levels", 0, 0), ("galerkin, all levels", 1, 0)):
+                if nst is not None and label == "galerkin, all levels":
+                    continue  # level-2 Galerkin rows at 2049^2 exceed the 128-entry ELL rows
+                print(f"[bench] coarse operators {name}: {label}", file=sys.stderr, flush=True)
+                coarse[f"{name}, {label}"] = march_rate(slhjb, torch, wl, "mixed", nst, coarse_op=cop, max_levels=ml)
     batch = None
     if not args.no_batch:
         print("[bench] batch of 64 two-asset instances", file=sys.stderr, flush=True)
@@ -432,6 +444,7 @@ def main():
         "adjoint": adj,
         "batch": batch,
         "other_configs": configs,
+        "coarse_operators": coarse,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

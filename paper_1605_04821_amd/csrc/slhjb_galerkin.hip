@@ -148,37 +148,47 @@ __global__ __launch_bounds__(64) void k_gal_rap(LevelDev gf, LevelDev gc, int Wf
             __syncthreads();
         }
     }
-    // one lane walks the runs of equal columns in order and writes the row (sums in contribution order)
-    if (lane == 0) {
-        int out = 0;
-        int p = 0;
-        while (p < nsort && key[p] != ~0ull) {
-            const uint64_t J = key[p] >> 20;
+    // runs of equal columns: the lane at a run's first entry sums the run in order (contribution order) and
+    // writes it at the run's rank among the runs, found by counting run heads chunk by chunk
+    int out = 0;  // runs before the current chunk (wave-uniform)
+    for (int base = 0; base < nsort; base += 64) {
+        const int p = base + lane;
+        const uint64_t kp = key[p];
+        const bool valid = kp != ~0ull;
+        const bool head = valid && (p == 0 || (key[p - 1] >> 20) != (kp >> 20));
+        const uint64_t heads = __ballot(head);
+        if (head) {
+            const int rank = out + __popcll(heads & ((1ull << lane) - 1ull));
+            const uint64_t J = kp >> 20;
             double acc = 0.0;
-            while (p < nsort && key[p] != ~0ull && (key[p] >> 20) == J) acc += sval[p++];
-            if (out < Wc) {
-                ccol[(int64_t)out * gc.N + I] = (int32_t)J;
-                cval[(int64_t)out * gc.N + I] = acc;
+            for (int q = p; q < nsort && key[q] != ~0ull && (key[q] >> 20) == J; ++q) acc += sval[q];
+            if (rank < Wc) {
+                ccol[(int64_t)rank * gc.N + I] = (int32_t)J;
+                cval[(int64_t)rank * gc.N + I] = acc;
             }
-            ++out;
         }
-        atomicMax(widest, out);
-        for (int s = out; s < Wc; ++s) ccol[(int64_t)s * gc.N + I] = -1;
+        out += __popcll(heads);
+        if (!__any(valid)) break;
     }
+    if (lane == 0) atomicMax(widest, out);
+    for (int s = out + lane; s < Wc; s += 64) ccol[(int64_t)s * gc.N + I] = -1;
 }
 
-// diagonal of an ELL operator (boundary rows: 1) and, optionally, its FP32 weights
+// Jacobi divisor of an ELL level, the row's absolute sum sum_j |a_ij| (l1 Jacobi; boundary rows: 1), and,
+// optionally, its FP32 weights.  Galerkin products of the wide-stencil operator need not be diagonally
+// dominant, and plain damped Jacobi on them can diverge; the absolute row sum bounds the row's spectrum.
 __global__ __launch_bounds__(kBlock) void k_gal_diag(int64_t N, int W, const int32_t *__restrict__ col,
                                                      const double *__restrict__ val, float *__restrict__ val32,
                                                      float *__restrict__ d32, double *__restrict__ d64) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= N) return;
-    double dg = 1.0;
+    double dg = 0.0;
     for (int s = 0; s < W; ++s) {
         const int j = col[s * N + i];
-        if (j == i) dg = val[s * N + i];
+        if (j >= 0) dg += fabs(val[s * N + i]);
         if (val32) val32[s * N + i] = j >= 0 ? (float)val[s * N + i] : 0.0f;
     }
+    if (!(dg > 0.0)) dg = 1.0;
     if (d32) d32[i] = (float)dg;
     if (d64) d64[i] = dg;
 }
@@ -196,9 +206,10 @@ __global__ __launch_bounds__(kBlock) void k_gal_jacobi(int64_t N, int W, const i
         return;
     }
     T ae = (T)0;
-    for (int s = 0; s < W; ++s) {
+    for (int s = 0; s < W; ++s) {  // a row's entries fill its first slots
         const int j = col[s * N + i];
-        if (j >= 0) ae += val[s * N + i] * e[j];
+        if (j < 0) break;
+        ae += val[s * N + i] * e[j];
     }
     out[i] = e[i] + omega * (r[i] - ae) / d[i];
 }
@@ -213,7 +224,8 @@ __global__ __launch_bounds__(kBlock) void k_gal_residual(int64_t N, int W, const
     T ae = (T)0;
     for (int s = 0; s < W; ++s) {
         const int j = col[s * N + i];
-        if (j >= 0) ae += val[s * N + i] * e[j];
+        if (j < 0) break;
+        ae += val[s * N + i] * e[j];
     }
     res[i] = r[i] - ae;
 }

@@ -85,6 +85,7 @@ struct Level {
     int32_t *gcol = nullptr;
     double *gval = nullptr;
     float *gval32 = nullptr;
+    int gw = 0;  // widest row of the current operator (slots past it are unused)
 };
 
 constexpr int kGalWidth = 128;  // slots of a Galerkin coarse row
@@ -431,6 +432,7 @@ int build_galerkin(hjb_handle *hd, const int16_t *alpha, double theta_dt) {
             return fail(HJB_EUNSUPPORTED, "Galerkin coarse row with %d entries (the ELL width is %d)", wide[0],
                         kGalWidth);
         Wf = std::max(1, wide[0]);
+        C.gw = Wf;
     }
     return HJB_OK;
 }
@@ -464,7 +466,7 @@ void smooth_level(hjb_handle *hd, int l, T *&e, T *&t, const T *r, int sweeps, b
         const T *gv;
         if constexpr (std::is_same<T, float>::value) gv = L.gval32; else gv = L.gval;
         for (int q = 0; q < sweeps; ++q) {
-            launch_gal_jacobi<T>(L.g.N, kGalWidth, L.gcol, gv, (const T *)L.d, e, r, t, hd->desc.omega,
+            launch_gal_jacobi<T>(L.g.N, L.gw, L.gcol, gv, (const T *)L.d, e, r, t, hd->desc.omega,
                                  first && q == 0, hd->stream);
             std::swap(e, t);
         }
@@ -518,7 +520,7 @@ void vcycle(hjb_handle *hd, const T *r0, T *z, double theta_dt) {
             if (l >= 1 && L.gcol) {
                 const T *gv;
                 if constexpr (std::is_same<T, float>::value) gv = L.gval32; else gv = L.gval;
-                launch_gal_residual<T>(L.g.N, kGalWidth, L.gcol, gv, e[l], r[l], t[l], s);
+                launch_gal_residual<T>(L.g.N, L.gw, L.gcol, gv, e[l], r[l], t[l], s);
             } else {
                 launch_level_residual<T>(hd->dim, L.g, stencil(hd, l), L.alpha, e[l], r[l], t[l], theta_dt, s,
                                          L.wctl_ok ? L.wctl : nullptr);

@@ -58,7 +58,10 @@ enum {
                                (host, N*P*dim, full grid, x fastest); drift, c constant per control */
 };
 enum { HJB_PREC_FP64 = 0, HJB_PREC_MIXED = 1 }; /* V-cycle in FP64, or in FP32 under FP64 FGMRES */
-enum { HJB_PRECOND_NONE = 0, HJB_PRECOND_JACOBI = 1, HJB_PRECOND_VCYCLE = 2 };
+/* preconditioner of the linear solves: none, Jacobi, the geometric V-cycle, or aggregation-based algebraic
+   multigrid with a Krylov-accelerated cycle (the introduction, Sections 3.4-3.5; HJB_PRECOND_AMG: 2D, FP64,
+   forward solves only) */
+enum { HJB_PRECOND_NONE = 0, HJB_PRECOND_JACOBI = 1, HJB_PRECOND_VCYCLE = 2, HJB_PRECOND_AMG = 3 };
 enum { HJB_KRYLOV_FGMRES = 0, HJB_KRYLOV_BICGSTAB = 1 };  /* outer FP64 Krylov method of the linear solves */
 /* coarse operators of the V-cycle: rediscretised on each level, or Galerkin products R A P (Section 3.3) */
 enum { HJB_COARSE_REDISCRETIZED = 0, HJB_COARSE_GALERKIN = 1 };
@@ -121,6 +124,10 @@ typedef struct {
                                for every policy and held as sliced ELL rows of at most 128 entries (wider rows
                                fail with HJB_EUNSUPPORTED); damped Jacobi on them.  2D only; the adjoint's
                                transposed cycles and batches keep rediscretised levels */
+    int32_t kcycle_levels;  /* HJB_PRECOND_AMG: coarse levels 1..kcycle_levels solve their residual equation by two
+                               GCR iterations preconditioned by the cycle below (the K-cycle), deeper levels by one
+                               (a V-cycle whose coarse correction is scaled by its minimal-residual factor);
+                               -1 (default): every level */
     void *stream;           /* hipStream_t */
 } hjb_desc;
 
@@ -286,6 +293,17 @@ int hjb_apply_transposed(hjb_handle *hd, const int16_t *alpha, const double *x, 
  * buffers cols / vals (width * nodes entries each; either may be NULL).  width and nodes (nullable) receive
  * the ELL width and the level's node count.  HJB_EINVAL for a level without a Galerkin operator. */
 int hjb_coarse_operator(hjb_handle *hd, int32_t level, int32_t *width, int64_t *nodes, int32_t *cols, double *vals);
+
+/* One level of the aggregation hierarchy (HJB_PRECOND_AMG, Sections 3.4-3.5) built for the policy of the handle's
+ * last solve.  Level 0 is the finest system matrix A = I - theta dt (L-hat + c) of the interior unknowns,
+ * indexed by full-grid node (boundary rows empty, boundary columns left to the right-hand side); level l >= 1 holds A_l = P_l^T A_{l-1} P_l, where P_l is piecewise constant: fine node i of
+ * level l-1 maps to aggregate agg[i] of level l (-1: in no aggregate).  Rows are sliced ELL, entry s of row i
+ * at s * rows + i (column -1 unused, a row's entries in its first slots).  levels, rows and width (nullable)
+ * receive the hierarchy's depth, the level's row count and ELL width; agg (level >= 1: rows of level l-1
+ * entries), cols and vals (width * rows entries) are the caller's device buffers, each nullable.
+ * HJB_EINVAL when no hierarchy is built or level is out of range. */
+int hjb_amg_level(hjb_handle *hd, int32_t level, int32_t *levels, int64_t *rows, int32_t *width, int32_t *agg,
+                  int32_t *cols, double *vals);
 
 /* ---- batches of independent instances (uneven grids, coefficients and multigrid depths) ----------
 

@@ -21,12 +21,12 @@ HJB_OK, HJB_EINVAL, HJB_EDEVICE, HJB_ENOMEM = 0, -1, -2, -3
 HJB_ENOCONV_KRYLOV, HJB_ENOCONV_PI, HJB_ENONFINITE, HJB_EUNSUPPORTED = -4, -5, -6, -7
 PREC_FP64, PREC_MIXED = 0, 1
 COEF_CONST, COEF_XSCALED, COEF_FIELD = 0, 1, 2
-PRECOND_NONE, PRECOND_JACOBI, PRECOND_VCYCLE = 0, 1, 2
+PRECOND_NONE, PRECOND_JACOBI, PRECOND_VCYCLE, PRECOND_AMG = 0, 1, 2, 3
 KRYLOV_FGMRES, KRYLOV_BICGSTAB = 0, 1
 COARSE_REDISCRETIZED, COARSE_GALERKIN = 0, 1
 FLAG_POSITIVITY, FLAG_NEAR_TIES = 1, 2
 
-EXPORTED = ["hjb_coarse_operator", "hjb_desc_default", "hjb_setup", "hjb_set_stream", "hjb_set_options", "hjb_policy_sweep",
+EXPORTED = ["hjb_amg_level", "hjb_coarse_operator", "hjb_desc_default", "hjb_setup", "hjb_set_stream", "hjb_set_options", "hjb_policy_sweep",
             "hjb_policy_sweep_noalloc", "hjb_apply",
             "hjb_linsolve", "hjb_step", "hjb_solve", "hjb_adjoint", "hjb_apply_transposed", "hjb_profile_enable",
             "hjb_profile_read", "hjb_profile_sample", "hjb_destroy", "hjb_last_error", "hjb_setup_batch", "hjb_batch_layout",
@@ -54,7 +54,7 @@ class Desc(ctypes.Structure):
                 ("pi_eta", ctypes.c_double), ("use_graphs", ctypes.c_int32), ("f_per_control", ctypes.c_int32),
                 ("certified_skip", ctypes.c_int32), ("max_levels", ctypes.c_int32),
                 ("nu_tight", ctypes.c_int32), ("coarse_sweeps_t", ctypes.c_int32),
-                ("krylov", ctypes.c_int32), ("coarse_op", ctypes.c_int32),
+                ("krylov", ctypes.c_int32), ("coarse_op", ctypes.c_int32), ("kcycle_levels", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
 
 
@@ -96,6 +96,7 @@ def _load():
                                            ctypes.POINTER(i64), ctypes.POINTER(d)]
     L.hjb_apply.argtypes = [vp, vp, vp, vp, d, d, d]
     L.hjb_coarse_operator.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i64), vp, vp]
+    L.hjb_amg_level.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i32), vp, vp, vp]
     L.hjb_linsolve.argtypes = [vp, vp, vp, vp, vp, d, d, d, d, vp, ctypes.POINTER(StepStats)]
     L.hjb_step.argtypes = [vp, vp, vp, vp, vp, d, d, d, d, vp, vp, d, ctypes.POINTER(StepStats)]
     L.hjb_solve.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp, vp, d, vp, vp, vp, ctypes.POINTER(SolveStats)]
@@ -177,6 +178,7 @@ class Options:
     coarse_sweeps_t: int = 2
     krylov: int = 0
     coarse_op: int = 0
+    kcycle_levels: int = -1
 
 
 class Solver:
@@ -238,6 +240,7 @@ class Solver:
         desc.coarse_sweeps_t = o.coarse_sweeps_t
         desc.krylov = o.krylov
         desc.coarse_op = o.coarse_op
+        desc.kcycle_levels = o.kcycle_levels
 
     @classmethod
     def from_instance(cls, inst, options: Optional[Options] = None):
@@ -344,6 +347,26 @@ class Solver:
         vals = torch.empty((w.value, n.value), dtype=torch.float64, device="cuda")
         _check(_lib.hjb_coarse_operator(self._h, int(level), None, None, _ptr(cols), _ptr(vals)))
         return cols, vals
+
+    def amg_level(self, level: int):
+        """hjb_amg_level: one level of the aggregation hierarchy of the last solve as a dict with 'levels',
+        'rows', 'width', 'agg' (level >= 1: int32 map from the finer level's rows, -1 outside every aggregate)
+        and 'cols' / 'vals' (device tensors of shape (width, rows), slot-major sliced ELL, column -1 unused)."""
+        import torch
+        self._sync_stream()
+        nl, n, w = ctypes.c_int32(0), ctypes.c_int64(0), ctypes.c_int32(0)
+        _check(_lib.hjb_amg_level(self._h, int(level), ctypes.byref(nl), ctypes.byref(n), ctypes.byref(w),
+                                  None, None, None))
+        agg = None
+        if level >= 1:
+            nf = ctypes.c_int64(0)
+            _check(_lib.hjb_amg_level(self._h, int(level) - 1, None, ctypes.byref(nf), None, None, None, None))
+            agg = torch.empty(nf.value, dtype=torch.int32, device="cuda")
+        cols = torch.empty((w.value, n.value), dtype=torch.int32, device="cuda")
+        vals = torch.empty((w.value, n.value), dtype=torch.float64, device="cuda")
+        _check(_lib.hjb_amg_level(self._h, int(level), None, None, None, _ptr(agg) if agg is not None else None,
+                                  _ptr(cols), _ptr(vals)))
+        return {"levels": nl.value, "rows": n.value, "width": w.value, "agg": agg, "cols": cols, "vals": vals}
 
     def set_tile_width(self, width: int):
         self._sync_stream()

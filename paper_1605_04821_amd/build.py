@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libslhjb.so")
-SOURCES = ["slhjb_kernels.hip", "slhjb_adjoint.hip", "slhjb_batch.hip", "slhjb_galerkin.hip", "slhjb_host.hip"]
+SOURCES = ["slhjb_kernels.hip", "slhjb_adjoint.hip", "slhjb_batch.hip", "slhjb_galerkin.hip", "slhjb_amg.hip",
+           "slhjb_host.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -718,7 +718,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(int32_t *__restrict__
 
 // out[q] = in[0] + ... + in[q-1] for q < m, and *total_out (nullable) = the sum of all m; part holds
 // scan_parts(m) entries
-inline int64_t scan_parts(int64_t m) { return (m + kScanChunk - 1) / kScanChunk; }
+int64_t scan_parts(int64_t m) { return (m + kScanChunk - 1) / kScanChunk; }
 void exclusive_scan(const int32_t *in, int64_t m, int32_t *out, int32_t *part, int32_t *total_out, hipStream_t s) {
     const int nb = (int)std::max<int64_t>(1, scan_parts(m));
     hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kScanThreads), 0, s, in, m, out, part);

@@ -90,6 +90,22 @@ struct Level {
 
 constexpr int kGalWidth = 128;  // slots of a Galerkin coarse row
 
+// device buffer that grows on demand (aggregation hierarchy: level sizes are known only once built)
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    template <typename T> T *as() const { return (T *)p; }
+};
+
+// one level of the aggregation hierarchy: its matrix (ELL, n rows, W widest row, slot stride n), its diagonal,
+// the map from the finer level's nodes and the aggregates' members (4 per row, -1 unused), the cycle's vectors
+struct AmgLevel {
+    int64_t n = 0;
+    int W = 0;
+    DevBuf col, val, d, agg, mem4, inv;
+    DevBuf x, r, t, v1, w1, v2, w2, r1;
+};
+
 }  // namespace
 
 struct hjb_handle {
@@ -108,6 +124,11 @@ struct hjb_handle {
     int32_t *g0col = nullptr;
     double *g0val = nullptr;
     int32_t *goverflow = nullptr;
+    // aggregation AMG (HJB_PRECOND_AMG), rebuilt for every policy: amg[0] is the finest matrix (merged rows)
+    std::vector<AmgLevel> amg;
+    DevBuf amg_rawc, amg_rawv, amg_mate, amg_cand, amg_flag, amg_id, amg_part, amg_aggA, amg_aggB, amg_mem2a, amg_mem2b,
+        amg_icol, amg_ival, amg_words, amg_dpart, amg_sc, amg_trow, amg_tval, amg_scol, amg_sval;
+    int amg_levels = 0;  // levels of the current hierarchy (0: none built)
     // certified reuse of search decisions within a step: gap bounds [N], X at the previous search [N],
     // per-tile largest change of X and its stencil-window maximum [nb_cap], window radius in nodes per axis
     double *marg = nullptr, *Xs = nullptr, *dtile = nullptr, *dwin = nullptr;
@@ -381,7 +402,10 @@ void select_precision(hjb_handle *hd) {
 
 int check_options(const hjb_desc *d) {
     if (d->precision != HJB_PREC_FP64 && d->precision != HJB_PREC_MIXED) return fail(HJB_EINVAL, "precision");
-    if (d->precond < HJB_PRECOND_NONE || d->precond > HJB_PRECOND_VCYCLE) return fail(HJB_EINVAL, "precond");
+    if (d->precond < HJB_PRECOND_NONE || d->precond > HJB_PRECOND_AMG) return fail(HJB_EINVAL, "precond");
+    if (d->precond == HJB_PRECOND_AMG && d->dim != 2)
+        return fail(HJB_EUNSUPPORTED, "the aggregation AMG preconditioner is provided for 2D grids");
+    if (d->kcycle_levels < -1) return fail(HJB_EINVAL, "kcycle_levels must be >= -1");
     if (d->restart < 1 || d->restart > kMaxRestart) return fail(HJB_EINVAL, "restart must be in 1..%d", kMaxRestart);
     if (d->max_krylov < 1) return fail(HJB_EINVAL, "max_krylov must be >= 1");
     if (d->max_pi < 1) return fail(HJB_EINVAL, "max_pi must be >= 1");
@@ -437,7 +461,10 @@ int build_galerkin(hjb_handle *hd, const int16_t *alpha, double theta_dt) {
     return HJB_OK;
 }
 
+int prepare_amg(hjb_handle *hd, const int16_t *alpha, double theta_dt);
+
 int prepare_mg(hjb_handle *hd, const int16_t *alpha, double theta_dt) {
+    if (hd->desc.precond == HJB_PRECOND_AMG) return prepare_amg(hd, alpha, theta_dt);
     hipStream_t s = hd->stream;
     hd->lev[0].alpha = const_cast<int16_t *>(alpha);
     for (size_t l = 1; l < hd->lev.size(); ++l)
@@ -544,6 +571,307 @@ void vcycle(hjb_handle *hd, const T *r0, T *z, double theta_dt) {
     }
 }
 
+// ---- aggregation AMG -------------------------------------------------------------------------------
+//
+// The hierarchy is rebuilt for every policy: the finest rows of A = I - theta dt (L-hat + c) emitted from the
+// stencil and merged, then level by level two pairing passes (double pairwise aggregation: aggregates of up to
+// four nodes) and the Galerkin product with the piecewise-constant prolongation, until a level has at most
+// kAmgDenseMax rows, whose dense inverse is formed (or until the coarsening stalls, below 5/4 per level, or the
+// rows grow wider than kAmgMaxWidth: then the last level is solved by Jacobi sweeps).  The cycle smooths with damped Jacobi (matrix-free on the
+// finest level), restricts by aggregate sums and solves each coarse residual equation by GCR iterations
+// preconditioned by the cycle one level down (two on the first kcycle_levels coarse levels, one below), with
+// the GCR coefficients kept on the device.
+
+constexpr double kAmgBeta = 0.25;      // strong coupling: -a_ij >= kAmgBeta * (the row's largest -a_ik)
+constexpr double kAmgDominance = 5.0;  // rows with a_ii >= kAmgDominance * sum_{j != i} |a_ij| join no aggregate
+constexpr int kAmgRounds = 6;          // handshake rounds per pairing pass
+constexpr int kAmgMaxWidth = 256;      // coarsening stops at a level with rows wider than this (the products
+                                       // sort two rows of a pair, at most 1024 entries, in LDS)
+constexpr int kAmgMaxLevels = 24;
+constexpr int kAmgSlot = 232;          // pinned host words of the hierarchy build
+constexpr int kAmgScSlots = 8;         // device GCR scalars per level
+
+int grow(hjb_handle *hd, DevBuf &b, size_t bytes) {
+    if (bytes <= b.cap) return HJB_OK;
+    if (b.p) {
+        HIPCHK(hipStreamSynchronize(hd->stream));
+        HIPCHK(hipFree(b.p));
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    const size_t want = std::max<size_t>(256, bytes + bytes / 8);
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        return fail(HJB_ENOMEM, "aggregation hierarchy: %zu bytes: %s", want, hipGetErrorString(e));
+    }
+    b.cap = want;
+    return HJB_OK;
+}
+
+void release(DevBuf &b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+// One pairing pass over the n rows of (col, val): the symmetric part S of the couplings is formed, then
+// kAmgRounds handshake rounds pair each unmatched node with its strongest unmatched neighbour on S when the
+// choice is mutual; agg (n entries) maps each row to its pair or singleton (-1: none, the row being empty or
+// dominant by dd), mem2 (2 per aggregate) lists the members.  *nc receives the number of aggregates and, when
+// wide is given, *wide the widest row of the last product (device word 0, read with the same synchronisation).
+int amg_pair(hjb_handle *hd, int64_t n, int W, const int32_t *col, const double *val, double dd, int32_t *agg,
+             int32_t *mem2, int64_t *nc, int *wide) {
+    hipStream_t s = hd->stream;
+    int32_t *mate = hd->amg_mate.as<int32_t>(), *cand = hd->amg_cand.as<int32_t>();
+    int32_t *flag = hd->amg_flag.as<int32_t>(), *id = hd->amg_id.as<int32_t>(), *part = hd->amg_part.as<int32_t>();
+    // device words: [0] the widest row of the last product, [1] the longest column, [2] the number of aggregates
+    // (read 16 bytes at a time)
+    int32_t *words = hd->amg_words.as<int32_t>();
+    int32_t *h = (int32_t *)(hd->hpin + kAmgSlot);
+    // S = -(M + M^T)/2 off the diagonal: column counts (in flag), segment offsets (in id), fill counters (in cand)
+    TRY(grow(hd, hd->amg_trow, (size_t)n * W * 4));
+    TRY(grow(hd, hd->amg_tval, (size_t)n * W * 8));
+    launch_zero(flag, (size_t)n * 4, s);
+    launch_zero(cand, (size_t)n * 4, s);
+    launch_zero(words + 1, 4, s);
+    launch_amg_colcount(n, W, col, flag, words + 1, s);
+    exclusive_scan(flag, n, id, part, words + 3, s);
+    launch_amg_scatter(n, W, col, val, id, cand, hd->amg_trow.as<int32_t>(), hd->amg_tval.as<double>(), s);
+    TRY(publish_wait(hd, words, h, 16, nullptr, nullptr, 0));
+    if (wide) *wide = h[0];
+    const int Ws = std::max(1, W + h[1]);
+    TRY(grow(hd, hd->amg_scol, (size_t)n * Ws * 4));
+    TRY(grow(hd, hd->amg_sval, (size_t)n * Ws * 8));
+    int32_t *scol = hd->amg_scol.as<int32_t>();
+    double *sval = hd->amg_sval.as<double>();
+    if (launch_amg_sym(n, W, h[1], col, val, id, flag, hd->amg_trow.as<int32_t>(), hd->amg_tval.as<double>(), Ws, scol,
+                       sval, s) != 0)
+        return fail(HJB_EUNSUPPORTED, "aggregation: rows of %d entries", W);
+    // matching
+    launch_amg_init(n, W, col, val, dd, mate, s);
+    for (int q = 0; q < kAmgRounds; ++q) launch_amg_match_round(n, Ws, scol, sval, kAmgBeta, mate, cand, s);
+    launch_amg_leader(n, mate, flag, s);
+    exclusive_scan(flag, n, id, part, words + 2, s);
+    launch_amg_assign(n, mate, id, agg, mem2, s);
+    TRY(publish_wait(hd, words, h, 16, nullptr, nullptr, 0));
+    *nc = h[2];
+    return HJB_OK;
+}
+
+int amg_vectors(hjb_handle *hd, AmgLevel &L) {
+    const size_t b = (size_t)std::max<int64_t>(1, L.n) * 8;
+    for (DevBuf *v : {&L.x, &L.r, &L.t, &L.v1, &L.w1, &L.v2, &L.w2, &L.r1}) TRY(grow(hd, *v, b));
+    return HJB_OK;
+}
+
+int build_amg(hjb_handle *hd, const int16_t *alpha, double theta_dt) {
+    hipStream_t s = hd->stream;
+    const int64_t N = hd->N;
+    const int E0 = hd->npt * 4 + 1;
+    hd->amg_levels = 0;
+    TRY(grow(hd, hd->amg_rawc, (size_t)N * E0 * 4));
+    TRY(grow(hd, hd->amg_rawv, (size_t)N * E0 * 8));
+    for (DevBuf *b : {&hd->amg_mate, &hd->amg_cand, &hd->amg_flag, &hd->amg_id, &hd->amg_aggA, &hd->amg_aggB})
+        TRY(grow(hd, *b, (size_t)N * 4));
+    TRY(grow(hd, hd->amg_mem2a, (size_t)N * 8));
+    TRY(grow(hd, hd->amg_mem2b, (size_t)N * 8));
+    TRY(grow(hd, hd->amg_part, (size_t)(scan_parts(N) + 2) * 4));
+    TRY(grow(hd, hd->amg_words, 16));
+    TRY(grow(hd, hd->amg_dpart, (size_t)2 * 1024 * 8));
+    TRY(grow(hd, hd->amg_sc, (size_t)kAmgMaxLevels * kAmgScSlots * 8));
+    if (hd->amg.empty()) hd->amg.resize(1);
+    {
+        AmgLevel &F0 = hd->amg[0];
+        F0.n = N;
+        F0.W = E0;
+        TRY(grow(hd, F0.col, (size_t)N * E0 * 4));
+        TRY(grow(hd, F0.val, (size_t)N * E0 * 8));
+        launch_gal_emit(hd->lev[0].g, stencil(hd, 0), alpha, theta_dt, E0, hd->amg_rawc.as<int32_t>(),
+                        hd->amg_rawv.as<double>(), s);
+        launch_amg_merge(N, hd->lev[0].g.n[0], hd->lev[0].g.n[1], E0, hd->amg_rawc.as<int32_t>(),
+                         hd->amg_rawv.as<double>(), F0.col.as<int32_t>(), F0.val.as<double>(), s);
+    }
+    int32_t *widest = hd->amg_words.as<int32_t>();
+    int32_t *aggA = hd->amg_aggA.as<int32_t>(), *aggB = hd->amg_aggB.as<int32_t>();
+    int32_t *mem2a = hd->amg_mem2a.as<int32_t>(), *mem2b = hd->amg_mem2b.as<int32_t>();
+    int levels = 1;
+    bool w_pending = false;  // the last level's W is an upper bound; its widest row is in *widest
+    for (;;) {
+        if ((int)hd->amg.size() < levels + 1) hd->amg.resize(levels + 1);
+        AmgLevel &F = hd->amg[levels - 1], &C = hd->amg[levels];
+        if (F.n <= kAmgDenseMax || levels >= kAmgMaxLevels) break;
+        // first pass on the level's matrix (which also reads the level's widest row)
+        int64_t nA = 0;
+        int wf = 0;
+        TRY(amg_pair(hd, F.n, F.W, F.col.as<int32_t>(), F.val.as<double>(), kAmgDominance, aggA, mem2a, &nA, &wf));
+        if (w_pending) F.W = std::max(1, wf);
+        w_pending = false;
+        if (nA == 0) break;  // every row is dominant: the smoother resolves the level
+        if (F.W > kAmgMaxWidth) break;  // rows this wide: the level is the coarsest
+        const int wi_cap = 2 * F.W;
+        TRY(grow(hd, hd->amg_icol, (size_t)nA * wi_cap * 4));
+        TRY(grow(hd, hd->amg_ival, (size_t)nA * wi_cap * 8));
+        int32_t *icol = hd->amg_icol.as<int32_t>();
+        double *ival = hd->amg_ival.as<double>();
+        launch_zero(widest, 4, s);
+        launch_amg_product(F.n, F.W, F.col.as<int32_t>(), F.val.as<double>(), aggA, mem2a, 2, nA, wi_cap, icol, ival,
+                           widest, s);
+        // second pass on the pairs' matrix
+        int64_t nB = 0;
+        int wi = 0;
+        TRY(amg_pair(hd, nA, wi_cap, icol, ival, 0.0, aggB, mem2b, &nB, &wi));
+        wi = std::max(1, wi);
+        if (wi > kAmgMaxWidth) break;  // the pairs' rows are already this wide: the level is the coarsest
+        C.n = nB;
+        const int wc_cap = 2 * wi;
+        TRY(grow(hd, C.agg, (size_t)F.n * 4));
+        TRY(grow(hd, C.mem4, (size_t)nB * 16));
+        TRY(grow(hd, C.col, (size_t)nB * wc_cap * 4));
+        TRY(grow(hd, C.val, (size_t)nB * wc_cap * 8));
+        TRY(grow(hd, C.d, (size_t)nB * 8));
+        TRY(amg_vectors(hd, C));
+        launch_amg_compose(F.n, aggA, aggB, C.agg.as<int32_t>(), s);
+        launch_amg_members4(nB, mem2b, mem2a, C.mem4.as<int32_t>(), s);
+        launch_zero(widest, 4, s);
+        launch_amg_product(nA, wi, icol, ival, aggB, mem2b, 2, nB, wc_cap, C.col.as<int32_t>(), C.val.as<double>(),
+                           widest, s);
+        C.W = wc_cap;
+        w_pending = true;
+        launch_amg_diag(nB, C.W, C.col.as<int32_t>(), C.val.as<double>(), C.d.as<double>(), s);
+        const bool stalled = 5 * nB > 4 * F.n;
+        ++levels;
+        if (stalled) break;
+    }
+    AmgLevel &Lc = hd->amg[levels - 1];
+    if (w_pending) {
+        int32_t *h = (int32_t *)(hd->hpin + kAmgSlot);
+        TRY(publish_wait(hd, widest, h, 8, nullptr, nullptr, 0));
+        Lc.W = std::max(1, h[0]);
+    }
+    if (levels > 1 && Lc.n <= kAmgDenseMax) {
+        TRY(grow(hd, Lc.inv, (size_t)Lc.n * Lc.n * 8));
+        launch_amg_dense_inverse((int)Lc.n, Lc.W, Lc.col.as<int32_t>(), Lc.val.as<double>(), Lc.inv.as<double>(), s);
+    }
+    hd->amg_levels = levels;
+    return HJB_OK;
+}
+
+int prepare_amg(hjb_handle *hd, const int16_t *alpha, double theta_dt) {
+    Level &L = hd->lev[0];
+    L.alpha = const_cast<int16_t *>(alpha);
+    const StencilDev st = stencil(hd, 0);
+    L.wctl_ok = L.wctl && st.lii_deep;
+    launch_diag<double>(hd->dim, L.g, st, alpha, theta_dt, (double *)L.d64, hd->stream,
+                        L.wctl_ok ? L.wctl : nullptr, L.dk64);
+    TRY(build_amg(hd, alpha, theta_dt));
+    HIPCHK(hipGetLastError());
+    return HJB_OK;
+}
+
+// damped Jacobi sweeps on level l (the finest level matrix-free), alternating between e and t
+void amg_smooth(hjb_handle *hd, int l, double *&e, double *&t, const double *r, int sweeps, bool first,
+                double theta_dt) {
+    hipStream_t s = hd->stream;
+    if (l == 0) {
+        Level &L = hd->lev[0];
+        for (int q = 0; q < sweeps; ++q) {
+            TimedLaunch tl(hd, (q > 0 || !first) ? HJB_KERNEL_SMOOTH : -1, (double)L.g.N * (3.0 * 8 + 2.0));
+            launch_jacobi<double>(hd->dim, L.g, stencil(hd, 0), L.alpha, e, r, (const double *)L.d64, t, theta_dt,
+                                  hd->desc.omega, first && q == 0, s, L.wctl_ok ? L.wctl : nullptr, L.dk64);
+            std::swap(e, t);
+        }
+        return;
+    }
+    AmgLevel &A = hd->amg[l];
+    for (int q = 0; q < sweeps; ++q) {
+        launch_gal_jacobi<double>(A.n, A.W, A.col.as<int32_t>(), A.val.as<double>(), A.d.as<double>(), e, r, t,
+                                  hd->desc.omega, first && q == 0, s);
+        std::swap(e, t);
+    }
+}
+
+void amg_solve(hjb_handle *hd, int l, const double *r, double *x, double theta_dt);
+
+// out = one cycle on level l for the right-hand side r from a zero initial guess: pre-smoothing, the
+// residual restricted by aggregate sums, the coarse residual equation solved by amg_solve, its solution
+// added to the aggregates' nodes, post-smoothing
+void amg_cycle(hjb_handle *hd, int l, const double *r, double *out, double theta_dt) {
+    hipStream_t s = hd->stream;
+    double *tmp = l == 0 ? (double *)hd->lev[0].t64 : hd->amg[l].t.as<double>();
+    double *e = out, *t = tmp;
+    if ((hd->nu_pre + hd->nu_post) % 2) std::swap(e, t);
+    amg_smooth(hd, l, e, t, r, hd->nu_pre, true, theta_dt);
+    if (l == 0) {
+        Level &L = hd->lev[0];
+        TimedLaunch tl(hd, HJB_KERNEL_MG_RESID, (double)L.g.N * (3.0 * 8 + 2.0));
+        launch_level_residual<double>(hd->dim, L.g, stencil(hd, 0), L.alpha, e, r, t, theta_dt, s,
+                                      L.wctl_ok ? L.wctl : nullptr);
+    } else {
+        AmgLevel &A = hd->amg[l];
+        launch_gal_residual<double>(A.n, A.W, A.col.as<int32_t>(), A.val.as<double>(), e, r, t, s);
+    }
+    AmgLevel &C = hd->amg[l + 1];
+    launch_amg_restrict(C.n, C.mem4.as<int32_t>(), t, C.r.as<double>(), s);
+    amg_solve(hd, l + 1, C.r.as<double>(), C.x.as<double>(), theta_dt);
+    launch_amg_prolong(hd->amg[l].n, C.agg.as<int32_t>(), C.x.as<double>(), e, s);
+    amg_smooth(hd, l, e, t, r, hd->nu_post, false, theta_dt);
+}
+
+// x ~ A_l^{-1} r on level l >= 1: the coarsest level through its dense inverse (or Jacobi sweeps when the
+// coarsening stopped early), other levels by GCR iterations preconditioned by amg_cycle(l): x = a1 v1 with
+// v1 = cycle(r), a1 minimising |r - a1 A v1|; then (two-iteration levels) v2 = cycle(r - a1 A v1)
+// orthogonalised against A v1 and x += a2 v2 minimising the residual again
+void amg_solve(hjb_handle *hd, int l, const double *r, double *x, double theta_dt) {
+    hipStream_t s = hd->stream;
+    AmgLevel &A = hd->amg[l];
+    const int32_t *col = A.col.as<int32_t>();
+    const double *val = A.val.as<double>();
+    if (l == hd->amg_levels - 1) {
+        if (A.n <= kAmgDenseMax) {
+            launch_amg_dense_solve((int)A.n, A.inv.as<double>(), r, x, s);
+        } else if (A.n <= kAmgCoarseMax) {
+            launch_amg_coarse((int)A.n, A.W, col, val, A.d.as<double>(), r, hd->desc.coarse_sweeps, x, s);
+        } else {
+            double *e = x, *t = A.t.as<double>();
+            if (hd->desc.coarse_sweeps % 2) std::swap(e, t);
+            for (int q = 0; q < hd->desc.coarse_sweeps; ++q) {
+                launch_gal_jacobi<double>(A.n, A.W, col, val, A.d.as<double>(), e, r, t, 1.0, q == 0, s);
+                std::swap(e, t);
+            }
+        }
+        return;
+    }
+    double *sc = hd->amg_sc.as<double>() + (size_t)l * kAmgScSlots;
+    double *part = hd->amg_dpart.as<double>();
+    double *v1 = A.v1.as<double>(), *w1 = A.w1.as<double>(), *v2 = A.v2.as<double>(), *w2 = A.w2.as<double>();
+    double *r1 = A.r1.as<double>();
+    amg_cycle(hd, l, r, v1, theta_dt);
+    launch_amg_spmv(A.n, A.W, col, val, v1, w1, s);
+    launch_amg_dot2(A.n, w1, r, w1, part, sc, s);
+    launch_amg_gcr(A.n, 0, sc, x, v1, w1, nullptr, nullptr, r, r1, s);
+    if (hd->desc.kcycle_levels >= 0 && l > hd->desc.kcycle_levels) return;
+    amg_cycle(hd, l, r1, v2, theta_dt);
+    launch_amg_spmv(A.n, A.W, col, val, v2, w2, s);
+    launch_amg_dot2(A.n, w1, w2, w1, part, sc + 2, s);
+    launch_amg_gcr(A.n, 1, sc + 2, nullptr, v2, w2, v1, w1, nullptr, nullptr, s);
+    launch_amg_dot2(A.n, w2, r1, w2, part, sc + 4, s);
+    launch_amg_gcr(A.n, 2, sc + 4, x, v2, nullptr, nullptr, nullptr, nullptr, nullptr, s);
+}
+
+// z = M^{-1} v for the aggregation preconditioner (FP64)
+void amg_precondition(hjb_handle *hd, const double *v, double *z, double theta_dt) {
+    if (hd->amg_levels > 1) {
+        amg_cycle(hd, 0, v, z, theta_dt);
+        return;
+    }
+    double *e = z, *t = (double *)hd->lev[0].t64;
+    const int sw = hd->nu_pre + hd->nu_post;
+    if (sw % 2) std::swap(e, t);
+    amg_smooth(hd, 0, e, t, v, sw, true, theta_dt);
+}
+
 __global__ void k_jacobi_precond64(const double *v, const double *dg, double *z, int64_t N) {
     int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n < N) z[n] = v[n] / dg[n];
@@ -558,6 +886,10 @@ void precondition_eager(hjb_handle *hd, const double *v, void *z, double theta_d
     const int64_t N = hd->N;
     hipStream_t s = hd->stream;
     Level &L0 = hd->lev[0];
+    if (hd->desc.precond == HJB_PRECOND_AMG) {
+        amg_precondition(hd, v, (double *)z, theta_dt);
+        return;
+    }
     if (hd->desc.precond == HJB_PRECOND_JACOBI) {
         int nb = blocks_for(N);
         if (mixed(hd))
@@ -942,7 +1274,7 @@ int fgmres(hjb_handle *hd, const int16_t *alpha, const double *E, double *X, dou
             return precondition(hd, v, z, theta_dt, ready, &ap, alpha, w, zf);
         };
     }
-    op.zf = mixed(hd);
+    op.zf = mixed(hd) && hd->desc.precond != HJB_PRECOND_AMG;  // the aggregation cycle runs in FP64
     if (op.zf && hd->desc.precond == HJB_PRECOND_VCYCLE) op.rhs32 = (float *)L0.r;
     return krylov_core(hd, op, X, eta, its_out, res_out, tight_out);
 }
@@ -1226,6 +1558,7 @@ void hjb_desc_default(hjb_desc *d) {
     d->coarse_sweeps_t = 2;
     d->krylov = HJB_KRYLOV_FGMRES;
     d->coarse_op = HJB_COARSE_REDISCRETIZED;
+    d->kcycle_levels = -1;
     d->stream = nullptr;
 }
 
@@ -1530,6 +1863,7 @@ int hjb_set_options(hjb_handle *hd, const hjb_desc *desc) {
     d.nu_tight = desc->nu_tight;
     d.coarse_sweeps_t = desc->coarse_sweeps_t;
     d.krylov = desc->krylov;
+    d.kcycle_levels = desc->kcycle_levels;
     if (desc->coarse_op != d.coarse_op) return fail(HJB_EINVAL, "coarse_op is fixed at setup");
     select_precision(hd);
     set_sweeps(hd, false);
@@ -1831,7 +2165,7 @@ int hjb_autotune(hjb_handle *hd, const char *cache_path, int32_t *tile_width_out
     launch_zero(hd->Vb, (size_t)N * 8, s);
     launch_zero(hd->Zb, (size_t)N * 8, s);
     const double dt = 1.0 / 64, theta_dt = dt;
-    const bool zf = mixed(hd) && hd->desc.precond != HJB_PRECOND_NONE;
+    const bool zf = mixed(hd) && hd->desc.precond != HJB_PRECOND_NONE && hd->desc.precond != HJB_PRECOND_AMG;
     hipEvent_t ev[4];
     for (hipEvent_t &e : ev) HIPCHK(hipEventCreate(&e));
     double best = INFINITY;
@@ -2175,6 +2509,8 @@ int hjb_adjoint(hjb_handle *hd, const double *g, const double *psi, const double
         if (thetas[n] == 0.0) return fail(HJB_EUNSUPPORTED, "explicit steps (theta = 0) are not provided");
     }
     if (hd->desc.f_per_control) return fail(HJB_EUNSUPPORTED, "the adjoint takes one source for all controls");
+    if (hd->desc.precond == HJB_PRECOND_AMG)
+        return fail(HJB_EUNSUPPORTED, "the aggregation preconditioner serves forward solves only");
     TRY(build_tables(hd, s));
     const int64_t N = hd->N;
     const int dim = hd->dim;
@@ -2335,6 +2671,24 @@ int hjb_coarse_operator(hjb_handle *hd, int32_t level, int32_t *width, int64_t *
     return HJB_OK;
 }
 
+int hjb_amg_level(hjb_handle *hd, int32_t level, int32_t *levels, int64_t *rows, int32_t *width, int32_t *agg,
+                  int32_t *cols, double *vals) {
+    if (!hd) return fail(HJB_EINVAL, "null handle");
+    if (levels) *levels = hd->amg_levels;
+    if (hd->amg_levels == 0) return fail(HJB_EINVAL, "no aggregation hierarchy has been built");
+    if (level < 0 || level >= hd->amg_levels) return fail(HJB_EINVAL, "level %d of %d", (int)level, hd->amg_levels);
+    const AmgLevel &L = hd->amg[level];
+    if (rows) *rows = L.n;
+    if (width) *width = L.W;
+    if (agg && level >= 1)
+        HIPCHK(hipMemcpyAsync(agg, L.agg.p, (size_t)hd->amg[level - 1].n * 4, hipMemcpyDeviceToDevice, hd->stream));
+    // a row's entries fill its first W slots: slots W.. of the buffer are not part of the level
+    if (cols) HIPCHK(hipMemcpyAsync(cols, L.col.p, (size_t)L.n * L.W * 4, hipMemcpyDeviceToDevice, hd->stream));
+    if (vals) HIPCHK(hipMemcpyAsync(vals, L.val.p, (size_t)L.n * L.W * 8, hipMemcpyDeviceToDevice, hd->stream));
+    HIPCHK(hipStreamSynchronize(hd->stream));
+    return HJB_OK;
+}
+
 void hjb_destroy(hjb_handle *hd) {
     if (!hd) return;
     drop_graphs(hd);
@@ -2344,6 +2698,15 @@ void hjb_destroy(hjb_handle *hd) {
     if (hd->stream) (void)hipStreamSynchronize(hd->stream);
     else (void)hipDeviceSynchronize();
     for (void *p : hd->allocs) (void)hipFree(p);
+    for (AmgLevel &L : hd->amg)
+        for (DevBuf *b : {&L.col, &L.val, &L.d, &L.agg, &L.mem4, &L.inv, &L.x, &L.r, &L.t, &L.v1, &L.w1, &L.v2, &L.w2,
+                          &L.r1})
+            release(*b);
+    for (DevBuf *b : {&hd->amg_rawc, &hd->amg_rawv, &hd->amg_mate, &hd->amg_cand, &hd->amg_flag, &hd->amg_id,
+                      &hd->amg_part, &hd->amg_aggA, &hd->amg_aggB, &hd->amg_mem2a, &hd->amg_mem2b, &hd->amg_icol,
+                      &hd->amg_ival, &hd->amg_words, &hd->amg_dpart, &hd->amg_sc, &hd->amg_trow, &hd->amg_tval,
+                      &hd->amg_scol, &hd->amg_sval})
+        release(*b);
     if (hd->hpin) (void)hipHostFree(hd->hpin);
     if (hd->hpin_i) (void)hipHostFree(hd->hpin_i);
     if (hd->hflag) (void)hipHostFree(hd->hflag);
@@ -2915,7 +3278,8 @@ int hjb_setup_batch(const hjb_desc *descs, int32_t count, hjb_batch **out) {
     const hjb_desc &d0 = descs[0];
     TRY(check_options(&d0));
     if ((d0.nu1 + d0.nu2) % 2 != 0) return fail(HJB_EUNSUPPORTED, "batched V-cycles take an even nu1 + nu2");
-    if (d0.precond == HJB_PRECOND_JACOBI) return fail(HJB_EUNSUPPORTED, "batched solves take the V-cycle or no preconditioner");
+    if (d0.precond == HJB_PRECOND_JACOBI || d0.precond == HJB_PRECOND_AMG)
+        return fail(HJB_EUNSUPPORTED, "batched solves take the V-cycle or no preconditioner");
     if (d0.krylov != HJB_KRYLOV_FGMRES) return fail(HJB_EUNSUPPORTED, "batched solves use flexible GMRES");
     for (int b = 0; b < count; ++b) {
         if (descs[b].dim != d0.dim) return fail(HJB_EINVAL, "all instances of a batch have the same dimension");

@@ -293,6 +293,54 @@ template <typename T>
 void launch_gal_residual(int64_t N, int W, const int32_t *col, const T *val, const T *e, const T *r, T *res,
                          hipStream_t s);
 
+// Aggregation AMG (slhjb_amg.hip): ELL slot-major levels with compact rows.  merge: emitted finest rows ->
+// one entry per column; colcount / scatter / sym: the symmetric part S of the couplings (column counts and
+// their largest, transposed segments, S rows of width Ws); init / match_round / leader / assign: one pairing
+// pass (state in mate, candidates in cand, leader flags, aggregate ids from their prefix sums, members two per
+// aggregate); compose / members4: two
+// passes as one map with four members per aggregate; product: P^T M P for piecewise-constant P (-1: the row
+// sum exceeds the sort capacity); diag; restrict / prolong; spmv; dot2: (a,b), (a,c) into out[0..1] (part holds
+// 2 * amg_dot_parts(n) doubles); gcr: the GCR updates of the cycle; coarse: Jacobi sweeps in one workgroup.
+constexpr int kAmgCoarseMax = 2048;  // coarsest level solved by Jacobi sweeps in one workgroup, at most
+constexpr int kAmgDenseMax = 120;    // coarsest level solved through its dense inverse (LDS-resident), at most
+void launch_amg_merge(int64_t n, int nx, int ny, int E, const int32_t *icol, const double *ival, int32_t *ocol,
+                      double *oval, hipStream_t s);
+void launch_amg_init(int64_t n, int W, const int32_t *col, const double *val, double dd, int32_t *mate,
+                     hipStream_t s);
+void launch_amg_colcount(int64_t n, int W, const int32_t *col, int32_t *cnt, int32_t *mx, hipStream_t s);
+void launch_amg_scatter(int64_t n, int W, const int32_t *col, const double *val, const int32_t *off, int32_t *fill,
+                        int32_t *trow, double *tval, hipStream_t s);
+int launch_amg_sym(int64_t n, int W, int maxcol, const int32_t *col, const double *val, const int32_t *off,
+                   const int32_t *cnt, const int32_t *trow, const double *tval, int Ws, int32_t *scol, double *sval,
+                   hipStream_t s);
+void launch_amg_match_round(int64_t n, int Ws, const int32_t *scol, const double *sval, double beta, int32_t *mate,
+                            int32_t *cand, hipStream_t s);
+void launch_amg_leader(int64_t n, const int32_t *mate, int32_t *flag, hipStream_t s);
+void launch_amg_assign(int64_t n, const int32_t *mate, const int32_t *id, int32_t *agg, int32_t *mem2, hipStream_t s);
+void launch_amg_compose(int64_t n, const int32_t *agg1, const int32_t *agg2, int32_t *agg, hipStream_t s);
+void launch_amg_members4(int64_t nc, const int32_t *mem2b, const int32_t *mem2a, int32_t *mem4, hipStream_t s);
+int launch_amg_product(int64_t nf, int W, const int32_t *fcol, const double *fval, const int32_t *agg,
+                       const int32_t *mem, int maxm, int64_t nc, int Wc, int32_t *ccol, double *cval, int32_t *widest,
+                       hipStream_t s);
+void launch_amg_diag(int64_t n, int W, const int32_t *col, const double *val, double *d, hipStream_t s);
+void launch_amg_restrict(int64_t nc, const int32_t *mem4, const double *rf, double *rc, hipStream_t s);
+void launch_amg_prolong(int64_t nf, const int32_t *agg, const double *ec, double *ef, hipStream_t s);
+void launch_amg_spmv(int64_t n, int W, const int32_t *col, const double *val, const double *x, double *y,
+                     hipStream_t s);
+int amg_dot_parts(int64_t n);
+void launch_amg_dot2(int64_t n, const double *a, const double *b, const double *c, double *part, double *out,
+                     hipStream_t s);
+void launch_amg_gcr(int64_t n, int mode, const double *sc, double *x, double *v, double *w, const double *v1,
+                    const double *w1, const double *r, double *r_out, hipStream_t s);
+void launch_amg_coarse(int n, int W, const int32_t *col, const double *val, const double *d, const double *r,
+                       int sweeps, double *x, hipStream_t s);
+void launch_amg_dense_inverse(int n, int W, const int32_t *col, const double *val, double *inv, hipStream_t s);
+void launch_amg_dense_solve(int n, const double *inv, const double *r, double *x, hipStream_t s);
+// exclusive prefix sums of int32 counts (slhjb_adjoint.hip): out[q] = in[0] + ... + in[q-1], *total_out
+// (nullable, device) = the sum; part holds scan_parts(m) + 1 entries
+int64_t scan_parts(int64_t m);
+void exclusive_scan(const int32_t *in, int64_t m, int32_t *out, int32_t *part, int32_t *total_out, hipStream_t s);
+
 // adjoint (slhjb_adjoint.hip)
 // Row listing of one level's operator (slots [i*E, (i+1)*E)) and its column-sorted form.
 // The sorted entries are also laid out as sliced ELL: slice = one wavefront of the node kernels' launch

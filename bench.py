@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch measurement")
     ap.add_argument("--no-configs", action="store_true", help="skip the marches of the other configurations")
+    ap.add_argument("--no-amg", action="store_true", help="skip the aggregation-AMG preconditioner comparison")
+    ap.add_argument("--amg-only", action="store_true", help="run only the aggregation-AMG comparison")
     ap.add_argument("--oracle-sample", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--pi-eta", type=float, default=None)
     ap.add_argument("--restart", type=int, default=None)
@@ -227,6 +229,21 @@ def march_rate(slhjb, torch, inst, mode, n_steps=None, **options):
             "krylov_per_solve": round(st.krylov_total / max(1, st.pi_total), 2)}
 
 
+def amg_compare(slhjb, torch, workloads, inst):
+    """Aggregation AMG (Sections 3.4-3.5) against the geometric V-cycle: marches of c2 257^2 and the first two
+    steps of the headline workload, with the K-cycle at every coarse level and on the first coarse level only."""
+    out = {}
+    for name, wl, nst in (("c2 257^2", workloads.config_c2(257), None), ("h 2049^2 (first 2 steps)", inst, 2)):
+        for label, mode, opts in (("geometric V-cycle (mixed)", "mixed", {}),
+                                  ("aggregation AMG, K-cycle at every level", "fp64",
+                                   {"precond": slhjb.PRECOND_AMG}),
+                                  ("aggregation AMG, K-cycle on level 1", "fp64",
+                                   {"precond": slhjb.PRECOND_AMG, "kcycle_levels": 1})):
+            print(f"[bench] preconditioners {name}: {label}", file=sys.stderr, flush=True)
+            out[f"{name}, {label}"] = march_rate(slhjb, torch, wl, mode, nst, **opts)
+    return out
+
+
 def measured_traffic(kernel, pi_per_step):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, scaled by
     the copy-kernel calibration recorded there; None when the kernel source changed since it was taken."""
@@ -341,6 +358,9 @@ def main():
     import paper_1605_04821_amd as slhjb
 
     inst = workloads.config_h(n=args.n)
+    if args.amg_only:
+        print(json.dumps({"aggregation_amg": amg_compare(slhjb, torch, workloads, inst)}), flush=True)
+        return
     modes = [m for m in args.modes.split(",") if m]
     if args.calibrate_copy:
         a = torch.ones(1 << 25, dtype=torch.float64, device="cuda")   # written: 2^28 bytes
@@ -411,6 +431,9 @@ def main():
                     continue  # level-2 Galerkin rows at 2049^2 exceed the 128-entry ELL rows
                 print(f"[bench] coarse operators {name}: {label}", file=sys.stderr, flush=True)
                 coarse[f"{name}, {label}"] = march_rate(slhjb, torch, wl, "mixed", nst, coarse_op=cop, max_levels=ml)
+    amg = None
+    if not args.no_configs and not args.no_amg:
+        amg = amg_compare(slhjb, torch, workloads, inst)
     batch = None
     if not args.no_batch:
         print("[bench] batch of 64 two-asset instances", file=sys.stderr, flush=True)
@@ -445,6 +468,7 @@ def main():
         "batch": batch,
         "other_configs": configs,
         "coarse_operators": coarse,
+        "aggregation_amg": amg,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -602,9 +602,137 @@ __global__ void k_seg_reduce(const TV *__restrict__ partial, int n, const int32_
     if (threadIdx.x == 0) out[(int64_t)b * nvec + v] = sh[0];
 }
 
+// ---- flexible GMRES scalars on the device (one thread per instance) -----------------------------------
+// The Hessenberg columns, Givens rotations, residual estimates and the instances' masks of a restart cycle
+// are advanced by these kernels, so that a cycle needs no host decision and can be captured as one graph.
+// The arithmetic is that of the single-instance host loop (classical Gram-Schmidt twice, the second pass
+// skipped where the first kept more than a quarter of |w|^2).
+
+// a cycle starts: g = (|r|_2, 0, ...), no column yet, every solving instance in the cycle
+__global__ void k_cycle_init_b(BKrylov K, int B, const uint8_t *__restrict__ solving, const double *__restrict__ r2,
+                               uint8_t *__restrict__ cyc) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    cyc[b] = solving[b];
+    K.jb[b] = 0;
+    if (!solving[b]) return;
+    double *g = K.g + (int64_t)b * (K.m + 1);
+    g[0] = sqrt(r2[b]);
+    for (int i = 1; i <= K.m; ++i) g[i] = 0.0;
+}
+
+__global__ void k_mask_copy_b(int B, const uint8_t *__restrict__ src, uint8_t *__restrict__ dst) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B) dst[b] = src[b];
+}
+
+// after Gram-Schmidt pass `pass` of step j (seg[b][0..j+1]: the pass's products with V_0..V_j and |w|^2):
+// the update coefficients, the Hessenberg column, the norm of the new vector, and whether a second pass follows
+__global__ void k_arnoldi_pass_b(BKrylov K, int B, int j, int pass, const double *__restrict__ seg,
+                                 double *__restrict__ coef, int ldc, const uint8_t *__restrict__ in_pass,
+                                 uint8_t *__restrict__ next_pass) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    if (!in_pass[b]) {
+        next_pass[b] = 0;
+        return;
+    }
+    const double *hp = seg + (int64_t)b * (j + 2);
+    double *cb = coef + (int64_t)b * ldc;
+    for (int i = 0; i <= j + 1; ++i) cb[i] = hp[i];
+    const double w2 = hp[j + 1];
+    double h2 = 0.0;
+    for (int i = 0; i <= j; ++i) h2 += hp[i] * hp[i];
+    const double hn2 = w2 - h2;
+    const double sc = hn2 > 0.0 ? sqrt(hn2) : 1.0;
+    if (!isfinite(w2)) K.bad[b] = 1;
+    double *H = K.H + (int64_t)b * (K.m + 1) * K.m;
+    if (pass == 0) {
+        for (int i = 0; i <= j; ++i) H[(int64_t)i * K.m + j] = hp[i];
+        K.hn[b] = sc;
+    } else {
+        for (int i = 0; i <= j; ++i) H[(int64_t)i * K.m + j] += hp[i] * K.hn[b];
+        K.hn[b] = K.hn[b] * sc;
+    }
+    bool done = hn2 > 0.25 * w2;
+    if (!done && (w2 == 0.0 || (pass == 1 && !(hn2 > 0.0)))) {
+        K.hn[b] = 0.0;
+        done = true;
+    }
+    next_pass[b] = done ? 0 : 1;
+}
+
+// step j closes: subdiagonal entry, earlier rotations applied, the new rotation, the residual estimate; an
+// instance leaves the cycle once |g_{j+1}| <= target / 2, at breakdown, or at its iteration limit
+__global__ void k_givens_b(BKrylov K, int B, int j, uint8_t *__restrict__ cyc) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B || !cyc[b]) return;
+    const int m = K.m;
+    double *H = K.H + (int64_t)b * (m + 1) * m;
+    double *cs = K.cs + (int64_t)b * m, *sn = K.sn + (int64_t)b * m, *g = K.g + (int64_t)b * (m + 1);
+    H[(int64_t)(j + 1) * m + j] = K.hn[b];
+    K.its[b] += 1;
+    for (int i = 0; i < j; ++i) {
+        const double a = H[(int64_t)i * m + j], c = H[(int64_t)(i + 1) * m + j];
+        H[(int64_t)i * m + j] = cs[i] * a + sn[i] * c;
+        H[(int64_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+    }
+    const double a = H[(int64_t)j * m + j], c = H[(int64_t)(j + 1) * m + j];
+    const double rr = hypot(a, c);
+    cs[j] = rr > 0 ? a / rr : 1.0;
+    sn[j] = rr > 0 ? c / rr : 0.0;
+    H[(int64_t)j * m + j] = rr;
+    H[(int64_t)(j + 1) * m + j] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    K.jb[b] = j + 1;
+    if (fabs(g[j + 1]) <= 0.5 * K.target[b] || K.hn[b] == 0.0 || K.its[b] >= K.maxk) cyc[b] = 0;
+}
+
+// y = R^{-1} g over the cycle's columns (the update X += Z y follows); count[b] = the number of columns
+__global__ void k_backsolve_b(BKrylov K, int B, const uint8_t *__restrict__ solving, double *__restrict__ y, int ldy,
+                              int32_t *__restrict__ count) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    if (!solving[b]) {
+        count[b] = 0;
+        return;
+    }
+    const int m = K.m, jj = K.jb[b];
+    const double *H = K.H + (int64_t)b * (m + 1) * m, *g = K.g + (int64_t)b * (m + 1);
+    double *yb = y + (int64_t)b * ldy;
+    for (int i = jj - 1; i >= 0; --i) {
+        double acc = g[i];
+        for (int q = i + 1; q < jj; ++q) acc -= H[(int64_t)i * m + q] * yb[q];
+        yb[i] = acc / H[(int64_t)i * m + i];
+    }
+    count[b] = jj;
+}
+
 // ---- launchers ---------------------------------------------------------------------------------------
 
 #define BGRID(T) dim3((unsigned)(T).n), dim3(kBlock), 0, s
+
+static dim3 bgrid_inst(int B) { return dim3((unsigned)((B + 63) / 64)); }
+void launch_cycle_init_b(const BKrylov &K, int B, const uint8_t *solving, const double *r2, uint8_t *cyc,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_cycle_init_b, bgrid_inst(B), dim3(64), 0, s, K, B, solving, r2, cyc);
+}
+void launch_mask_copy_b(int B, const uint8_t *src, uint8_t *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_mask_copy_b, bgrid_inst(B), dim3(64), 0, s, B, src, dst);
+}
+void launch_arnoldi_pass_b(const BKrylov &K, int B, int j, int pass, const double *seg, double *coef, int ldc,
+                           const uint8_t *in_pass, uint8_t *next_pass, hipStream_t s) {
+    hipLaunchKernelGGL(k_arnoldi_pass_b, bgrid_inst(B), dim3(64), 0, s, K, B, j, pass, seg, coef, ldc, in_pass,
+                       next_pass);
+}
+void launch_givens_b(const BKrylov &K, int B, int j, uint8_t *cyc, hipStream_t s) {
+    hipLaunchKernelGGL(k_givens_b, bgrid_inst(B), dim3(64), 0, s, K, B, j, cyc);
+}
+void launch_backsolve_b(const BKrylov &K, int B, const uint8_t *solving, double *y, int ldy, int32_t *count,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_backsolve_b, bgrid_inst(B), dim3(64), 0, s, K, B, solving, y, ldy, count);
+}
 
 void launch_norms_b(int dim, const BTiles &T, const double *X, const double *U, const double *f0, const double *f1,
                     double t_mid, double *partial, hipStream_t s) {

@@ -2778,6 +2778,19 @@ struct hjb_batch {
     };
     std::vector<VGraph> vgraphs;    // captured batched V-cycles (masks are read from fixed buffers)
     hipStream_t capture_stream = nullptr;
+    // FGMRES scalars on the device (BKrylov) and the pinned host copies read once per restart cycle
+    double *dH = nullptr, *dcs = nullptr, *dsn = nullptr, *dg = nullptr, *dhn = nullptr, *dtarget = nullptr;
+    int32_t *dits = nullptr, *djb = nullptr, *dbad = nullptr;
+    uint8_t *dnext = nullptr;       // instances that take a second Gram-Schmidt pass
+    double *htarget = nullptr;
+    int32_t *hits = nullptr;        // [its | bad], 2 B entries
+    struct CGraph {
+        const void *a0;
+        int j;
+        double theta_dt;
+        hipGraphExec_t exec;
+    };
+    std::vector<CGraph> cgraphs;    // captured Arnoldi steps
 };
 
 namespace {
@@ -2997,35 +3010,96 @@ struct BSolveOut {
 };
 
 // Solve A_b X_b = E_b for every instance with on[b]; eta[b] as in fgmres_core.
+// Arnoldi step j of every instance in the cycle mask (dmask[2]): preconditioner, operator, two Gram-Schmidt
+// passes and the Givens rotation, each advancing the device-side scalars and masks (an instance that
+// converges leaves the mask), so that no host decision is needed inside the step and its launch sequence
+// depends only on buffer addresses, theta*dt and j.
+void bstep_eager(hjb_batch *bh, const int16_t *alpha, double theta_dt, int j) {
+    const hjb_desc &d = bh->opt;
+    const int B = bh->B, dim = bh->dim;
+    const int64_t N = bh->N;
+    hipStream_t s = bh->stream;
+    const bool none = d.precond == HJB_PRECOND_NONE;
+    const bool zf = d.precision == HJB_PREC_MIXED && !none && d.precond == HJB_PRECOND_VCYCLE;
+    const size_t zsz = zf ? 4 : 8;
+    BLevel &L0 = bh->lev[0];
+    const TileTab &A0 = L0.all;
+    uint8_t *mC = bh->dmask[2], *mP = bh->dmask[3];
+    const BKrylov K{bh->dH, bh->dcs, bh->dsn, bh->dg, bh->dhn, bh->dtarget, bh->dits, bh->djb, bh->dbad, d.restart,
+                    d.max_krylov};
+    double *vj = bh->Vb + (int64_t)j * N;
+    double *w = bh->Vb + (int64_t)(j + 1) * N;
+    void *zj = none ? (void *)vj : (void *)((char *)bh->Zb + (int64_t)j * N * zsz);
+    if (!none) bprecondition_eager(bh, vj, zj, theta_dt, alpha, mC);
+    launch_apply_b(dim, btiles(A0, L0.I, mC), alpha, zj, zf, w, theta_dt, s);
+    launch_mask_copy_b(B, mC, mP, s);
+    for (int pass = 0; pass < 2; ++pass) {
+        launch_multidot_b(dim, btiles(A0, L0.I, mP), w, bh->Vb, N, j + 1, bh->partial, s);
+        launch_seg_sum(bh->partial, A0.n, A0.first_dev, j + 2, mP, bh->dseg, B, s);
+        launch_arnoldi_pass_b(K, B, j, pass, bh->dseg, bh->dcoef, kLdc, mP, bh->dnext, s);
+        launch_multiaxpy_scale_b(dim, btiles(A0, L0.I, mP), w, bh->Vb, N, j + 1, bh->dcoef, kLdc, s);
+        if (pass == 0) launch_mask_copy_b(B, bh->dnext, mP, s);
+    }
+    launch_givens_b(K, B, j, mC, s);
+}
+
+// the step, replayed from a captured graph per (policy buffer, theta*dt, j) unless graphs are off
+int bstep_arnoldi(hjb_batch *bh, const int16_t *alpha, double theta_dt, int j) {
+    if (!bh->opt.use_graphs) {
+        bstep_eager(bh, alpha, theta_dt, j);
+        HIPCHK(hipGetLastError());
+        return HJB_OK;
+    }
+    for (auto &g : bh->cgraphs)
+        if (g.a0 == alpha && g.j == j && g.theta_dt == theta_dt) {
+            HIPCHK(hipGraphLaunch(g.exec, bh->stream));
+            return HJB_OK;
+        }
+    if (bh->cgraphs.size() >= 256) {
+        for (auto &g : bh->cgraphs) (void)hipGraphExecDestroy(g.exec);
+        bh->cgraphs.clear();
+    }
+    if (!bh->capture_stream) HIPCHK(hipStreamCreateWithFlags(&bh->capture_stream, hipStreamNonBlocking));
+    hipStream_t saved = bh->stream;
+    bh->stream = bh->capture_stream;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(bh->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        bstep_eager(bh, alpha, theta_dt, j);
+        e = hipStreamEndCapture(bh->capture_stream, &graph);
+    }
+    bh->stream = saved;
+    if (e != hipSuccess) return fail(HJB_EDEVICE, "batched Arnoldi step capture: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(HJB_EDEVICE, "batched Arnoldi step instantiate: %s", hipGetErrorString(e));
+    bh->cgraphs.push_back({alpha, j, theta_dt, exec});
+    HIPCHK(hipGraphLaunch(exec, bh->stream));
+    return HJB_OK;
+}
+
+// Flexible GMRES(m) of every instance with on[b], each to its own certificate: the host reads the residual
+// norms, iteration counts and non-finite flags once per restart cycle and decides which instances continue,
+// and the cycle mask once per Arnoldi step; the Gram-Schmidt and Givens scalars stay on the device.
 int bfgmres(hjb_batch *bh, const int16_t *alpha, double *X, double theta_dt, const std::vector<uint8_t> &on,
             const std::vector<double> &eta, BSolveOut &out) {
     const hjb_desc &d = bh->opt;
-    const int B = bh->B, m = d.restart, dim = bh->dim;
-    const int64_t N = bh->N;
+    const int B = bh->B, dim = bh->dim;
     hipStream_t s = bh->stream;
-    const bool mixed_p = d.precision == HJB_PREC_MIXED;
-    const bool none = d.precond == HJB_PRECOND_NONE;
-    const bool zf = mixed_p && !none && d.precond == HJB_PRECOND_VCYCLE;
-    const size_t zsz = zf ? 4 : 8;
     BLevel &L0 = bh->lev[0];
     const TileTab &A0 = L0.all;
     const int n0 = A0.n;
     out.its.assign(B, 0);
     out.res.assign(B, 0.0);
     out.tight.assign(B, 0);
-    std::vector<double> loose(B, 0.0), target(B, 0.0), beta(B, 0.0);
-    std::vector<std::vector<double>> H(B), cs(B), sn(B), gv(B), yv(B);
-    for (int b = 0; b < B; ++b) {
-        H[b].assign((size_t)(m + 1) * m, 0.0);
-        cs[b].assign(m, 0.0);
-        sn[b].assign(m, 0.0);
-        gv[b].assign(m + 1, 0.0);
-        yv[b].assign(m, 0.0);
-    }
+    std::vector<double> loose(B, 0.0);
     std::vector<uint8_t> act = on;  // still solving
-    std::vector<int> jb(B, 0);
-    uint8_t *mS = bh->dmask[1], *mC = bh->dmask[2], *mP = bh->dmask[3];
-    uint8_t *hS = bh->hmask[1], *hC = bh->hmask[2], *hP = bh->hmask[3];
+    uint8_t *mS = bh->dmask[1];
+    uint8_t *hS = bh->hmask[1];
+    const bool none = d.precond == HJB_PRECOND_NONE;
+    const bool zf = d.precision == HJB_PREC_MIXED && !none && d.precond == HJB_PRECOND_VCYCLE;
+    launch_zero(bh->dits, (size_t)B * 2 * 4, s);  // iteration counts and non-finite flags
     for (int cycle = 0;; ++cycle) {
         for (int b = 0; b < B; ++b) hS[b] = act[b];
         TRY(bupload_mask(bh, 1));
@@ -3033,140 +3107,52 @@ int bfgmres(hjb_batch *bh, const int16_t *alpha, double *X, double theta_dt, con
         launch_seg_sum(bh->partial, n0, A0.first_dev, 1, mS, bh->dseg, B, s);
         launch_seg_max(bh->partial + n0, n0, A0.first_dev, 2, mS, bh->dseg + B, B, s);
         HIPCHK(hipMemcpyAsync(bh->hseg, bh->dseg, (size_t)3 * B * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(bh->hits, bh->dits, (size_t)2 * B * 4, hipMemcpyDeviceToHost, s));
         TRY(bwait(bh));
         bool any = false;
         for (int b = 0; b < B; ++b) {
             if (!act[b]) continue;
+            if (bh->hits[B + b]) return fail(HJB_ENONFINITE, "non-finite Arnoldi vector (instance %d)", b);
+            out.its[b] = bh->hits[b];
             double b2 = bh->hseg[b], rinf = bh->hseg[B + 2 * b], xinf = bh->hseg[B + 2 * b + 1];
             out.res[b] = rinf;
             if (!isfinite(b2) || !isfinite(xinf)) return fail(HJB_ENONFINITE, "non-finite residual (instance %d)", b);
-            target[b] = d.rtol_inf * std::max(1.0, xinf);
+            double target = d.rtol_inf * std::max(1.0, xinf);
             if (cycle == 0 && eta[b] > 0.0) loose[b] = eta[b] * rinf;
-            out.tight[b] = rinf <= target[b];
-            if (rinf <= std::max(target[b], loose[b])) {
+            out.tight[b] = rinf <= target;
+            if (rinf <= std::max(target, loose[b])) {
                 act[b] = 0;
                 continue;
             }
-            target[b] = std::max(target[b], loose[b]);
+            target = std::max(target, loose[b]);
             if (out.its[b] >= d.max_krylov)
                 return fail(HJB_ENOCONV_KRYLOV, "FGMRES (instance %d): |r|_inf = %.3e > %.3e after %d iterations", b,
-                            rinf, target[b], out.its[b]);
-            beta[b] = sqrt(b2);
-            std::fill(gv[b].begin(), gv[b].end(), 0.0);
-            gv[b][0] = beta[b];
-            jb[b] = 0;
+                            rinf, target, out.its[b]);
+            bh->htarget[b] = target;
             any = true;
         }
         if (!any) return HJB_OK;
-        for (int b = 0; b < B; ++b) hC[b] = act[b];
-        TRY(bupload_mask(bh, 2));
-        // v0 = r / |r|_2 per instance (dseg[b] holds sum r^2)
-        launch_scale_b(dim, btiles(A0, L0.I, mC), bh->Vb, bh->R, bh->dseg, 1, s);
-        std::vector<uint8_t> inc = act;
-        for (int j = 0; j < m; ++j) {
-            bool anyc = false;
-            for (int b = 0; b < B; ++b) anyc |= inc[b] != 0;
-            if (!anyc) break;
-            double *vj = bh->Vb + (int64_t)j * N;
-            double *w = bh->Vb + (int64_t)(j + 1) * N;
-            void *zj = none ? (void *)vj : (void *)((char *)bh->Zb + (int64_t)j * N * zsz);
-            if (!none) TRY(bprecondition(bh, vj, zj, theta_dt, alpha, mC));
-            launch_apply_b(dim, btiles(A0, L0.I, mC), alpha, zj, zf, w, theta_dt, s);
-            std::vector<double> hn(B, 0.0);
-            std::vector<uint8_t> need(inc);  // instances still orthogonalising in this pass
-            for (int pass = 0; pass < 2; ++pass) {
-                bool anyp = false;
-                for (int b = 0; b < B; ++b) {
-                    hP[b] = need[b];
-                    anyp |= need[b] != 0;
-                }
-                if (!anyp) break;
-                TRY(bupload_mask(bh, 3));
-                launch_multidot_b(dim, btiles(A0, L0.I, mP), w, bh->Vb, N, j + 1, bh->partial, s);
-                launch_seg_sum(bh->partial, n0, A0.first_dev, j + 2, mP, bh->dseg, B, s);
-                HIPCHK(hipMemcpyAsync(bh->hseg, bh->dseg, (size_t)B * (j + 2) * 8, hipMemcpyDeviceToHost, s));
-                TRY(bwait(bh));
-                for (int b = 0; b < B; ++b) {
-                    if (!need[b]) continue;
-                    const double *hp = bh->hseg + (size_t)b * (j + 2);
-                    double *cb = bh->hcoef + (size_t)b * kLdc;
-                    for (int i = 0; i <= j + 1; ++i) cb[i] = hp[i];
-                }
-                HIPCHK(hipMemcpyAsync(bh->dcoef, bh->hcoef, (size_t)B * kLdc * 8, hipMemcpyHostToDevice, s));
-                launch_multiaxpy_scale_b(dim, btiles(A0, L0.I, mP), w, bh->Vb, N, j + 1, bh->dcoef, kLdc, s);
-                for (int b = 0; b < B; ++b) {
-                    if (!need[b]) continue;
-                    const double *hp = bh->hseg + (size_t)b * (j + 2);
-                    double w2 = hp[j + 1], h2 = 0.0;
-                    for (int i = 0; i <= j; ++i) h2 += hp[i] * hp[i];
-                    double hn2 = w2 - h2;
-                    double sc = hn2 > 0.0 ? sqrt(hn2) : 1.0;
-                    if (!isfinite(w2)) return fail(HJB_ENONFINITE, "non-finite Arnoldi vector (instance %d)", b);
-                    if (pass == 0) {
-                        for (int i = 0; i <= j; ++i) H[b][(size_t)i * m + j] = hp[i];
-                        hn[b] = sc;
-                    } else {
-                        for (int i = 0; i <= j; ++i) H[b][(size_t)i * m + j] += hp[i] * hn[b];
-                        hn[b] = hn[b] * sc;
-                    }
-                    bool done_b = hn2 > 0.25 * w2;
-                    if (!done_b && (w2 == 0.0 || (pass == 1 && !(hn2 > 0.0)))) {
-                        hn[b] = 0.0;
-                        done_b = true;
-                    }
-                    need[b] = done_b ? 0 : 1;
-                }
-                // the host coefficient buffer is rewritten only after the next wait
-            }
-            bool changed = false;
-            for (int b = 0; b < B; ++b) {
-                if (!inc[b]) continue;
-                std::vector<double> &Hb = H[b];
-                Hb[(size_t)(j + 1) * m + j] = hn[b];
-                ++out.its[b];
-                for (int i = 0; i < j; ++i) {
-                    double a = Hb[(size_t)i * m + j], c = Hb[(size_t)(i + 1) * m + j];
-                    Hb[(size_t)i * m + j] = cs[b][i] * a + sn[b][i] * c;
-                    Hb[(size_t)(i + 1) * m + j] = -sn[b][i] * a + cs[b][i] * c;
-                }
-                double a = Hb[(size_t)j * m + j], c = Hb[(size_t)(j + 1) * m + j];
-                double rr = hypot(a, c);
-                cs[b][j] = rr > 0 ? a / rr : 1.0;
-                sn[b][j] = rr > 0 ? c / rr : 0.0;
-                Hb[(size_t)j * m + j] = rr;
-                Hb[(size_t)(j + 1) * m + j] = 0.0;
-                gv[b][j + 1] = -sn[b][j] * gv[b][j];
-                gv[b][j] = cs[b][j] * gv[b][j];
-                jb[b] = j + 1;
-                if (fabs(gv[b][j + 1]) <= 0.5 * target[b] || hn[b] == 0.0 || out.its[b] >= d.max_krylov) {
-                    inc[b] = 0;
-                    changed = true;
-                }
-            }
-            if (changed) {
-                for (int b = 0; b < B; ++b) hC[b] = inc[b];
-                TRY(bupload_mask(bh, 2));
-            }
-        }
-        // y = H^{-1} g per instance, X += Z y
-        for (int b = 0; b < B; ++b) {
-            bh->hm[b] = 0;
-            if (!act[b]) continue;
-            const int jj = jb[b];
-            for (int i = jj - 1; i >= 0; --i) {
-                double acc = gv[b][i];
-                for (int q = i + 1; q < jj; ++q) acc -= H[b][(size_t)i * m + q] * yv[b][q];
-                yv[b][i] = acc / H[b][(size_t)i * m + i];
-            }
-            bh->hm[b] = jj;
-            for (int i = 0; i < jj; ++i) bh->hy[(size_t)b * kMaxRestart + i] = yv[b][i];
-        }
-        HIPCHK(hipMemcpyAsync(bh->dy, bh->hy, (size_t)B * kMaxRestart * 8, hipMemcpyHostToDevice, s));
-        HIPCHK(hipMemcpyAsync(bh->dm, bh->hm, (size_t)B * 4, hipMemcpyHostToDevice, s));
         for (int b = 0; b < B; ++b) hS[b] = act[b];
         TRY(bupload_mask(bh, 1));
-        launch_update_b(dim, btiles(A0, L0.I, mS), X, none ? (const void *)bh->Vb : (const void *)bh->Zb, zf, N,
-                        bh->dm, bh->dy, kMaxRestart, s);
+        HIPCHK(hipMemcpyAsync(bh->dtarget, bh->htarget, (size_t)B * 8, hipMemcpyHostToDevice, s));
+        // the cycle: v_0 = r / |r|_2, Arnoldi steps while any instance is still in the cycle (one host read of
+        // the cycle mask per step), then y = R^{-1} g and X += Z y
+        const BKrylov K{bh->dH, bh->dcs, bh->dsn, bh->dg, bh->dhn, bh->dtarget, bh->dits, bh->djb, bh->dbad,
+                        d.restart, d.max_krylov};
+        uint8_t *mC = bh->dmask[2], *hC = bh->hmask[2];
+        launch_cycle_init_b(K, B, mS, bh->dseg, mC, s);  // dseg[b]: sum r^2 of the residual just reduced
+        launch_scale_b(dim, btiles(A0, L0.I, mC), bh->Vb, bh->R, bh->dseg, 1, s);
+        for (int j = 0; j < d.restart; ++j) {
+            TRY(bstep_arnoldi(bh, alpha, theta_dt, j));
+            HIPCHK(hipMemcpyAsync(hC, mC, (size_t)B, hipMemcpyDeviceToHost, s));
+            TRY(bwait(bh));
+            bool inc = false;
+            for (int b = 0; b < B; ++b) inc |= hC[b] != 0;
+            if (!inc) break;
+        }
+        launch_backsolve_b(K, B, mS, bh->dy, kMaxRestart, bh->dm, s);
+        launch_update_b(dim, btiles(A0, L0.I, mS), X, none ? (const void *)bh->Vb : (const void *)bh->Zb, zf,
+                        bh->N, bh->dm, bh->dy, kMaxRestart, s);
         HIPCHK(hipGetLastError());
     }
 }
@@ -3401,6 +3387,21 @@ int hjb_setup_batch(const hjb_desc *descs, int32_t count, hjb_batch **out) {
     BTRY(bpin(bh, (void **)&bh->hy, (size_t)count * kMaxRestart * 8));
     BTRY(bpin(bh, (void **)&bh->hchg, (size_t)count * 8));
     BTRY(bpin(bh, (void **)&bh->hm, (size_t)count * 4));
+    {
+        const size_t mr = (size_t)d0.restart;
+        BTRY(balloc(bh, (void **)&bh->dH, (size_t)count * (mr + 1) * mr * 8));
+        BTRY(balloc(bh, (void **)&bh->dcs, (size_t)count * mr * 8));
+        BTRY(balloc(bh, (void **)&bh->dsn, (size_t)count * mr * 8));
+        BTRY(balloc(bh, (void **)&bh->dg, (size_t)count * (mr + 1) * 8));
+        BTRY(balloc(bh, (void **)&bh->dhn, (size_t)count * 8));
+        BTRY(balloc(bh, (void **)&bh->dtarget, (size_t)count * 8));
+        BTRY(balloc(bh, (void **)&bh->dits, (size_t)count * 3 * 4));  // its | bad | columns
+        bh->dbad = bh->dits + count;
+        bh->djb = bh->dits + 2 * count;
+        BTRY(balloc(bh, (void **)&bh->dnext, (size_t)count));
+        BTRY(bpin(bh, (void **)&bh->htarget, (size_t)count * 8));
+        BTRY(bpin(bh, (void **)&bh->hits, (size_t)count * 2 * 4));
+    }
     memset(bh->hcoef, 0, (size_t)count * kLdc * 8);
     memset(bh->hy, 0, (size_t)count * kMaxRestart * 8);
     {
@@ -3487,6 +3488,7 @@ void hjb_destroy_batch(hjb_batch *bh) {
     if (bh->stream) (void)hipStreamSynchronize(bh->stream);
     else (void)hipDeviceSynchronize();
     for (auto &g : bh->vgraphs) (void)hipGraphExecDestroy(g.exec);
+    for (auto &g : bh->cgraphs) (void)hipGraphExecDestroy(g.exec);
     if (bh->capture_stream) (void)hipStreamDestroy(bh->capture_stream);
     for (hjb_handle *h : bh->sub) hjb_destroy(h);
     for (void *p : bh->allocs) (void)hipFree(p);

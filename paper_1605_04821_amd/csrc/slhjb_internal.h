@@ -461,6 +461,22 @@ void launch_scale_b(int dim, const BTiles &T, double *dst, const double *src, co
                     hipStream_t s);
 void launch_update_b(int dim, const BTiles &T, double *X, const void *Z, bool z_float, int64_t ldz, const int32_t *m,
                      const double *y, int ldy, hipStream_t s);
+// device-side FGMRES scalars of a batch: per instance the Hessenberg matrix ((m+1) x m, row-major), Givens
+// cosines and sines (m), residual estimates g (m+1), the new vector's norm, the target, iteration counts,
+// the columns of the current cycle and a non-finite flag
+struct BKrylov {
+    double *H, *cs, *sn, *g, *hn, *target;
+    int32_t *its, *jb, *bad;
+    int m, maxk;
+};
+void launch_cycle_init_b(const BKrylov &K, int B, const uint8_t *solving, const double *r2, uint8_t *cyc,
+                         hipStream_t s);
+void launch_mask_copy_b(int B, const uint8_t *src, uint8_t *dst, hipStream_t s);
+void launch_arnoldi_pass_b(const BKrylov &K, int B, int j, int pass, const double *seg, double *coef, int ldc,
+                           const uint8_t *in_pass, uint8_t *next_pass, hipStream_t s);
+void launch_givens_b(const BKrylov &K, int B, int j, uint8_t *cyc, hipStream_t s);
+void launch_backsolve_b(const BKrylov &K, int B, const uint8_t *solving, double *y, int ldy, int32_t *count,
+                        hipStream_t s);
 void launch_seg_sum(const double *partial, int n, const int32_t *first, int nvec, const uint8_t *active, double *out,
                     int B, hipStream_t s);
 void launch_seg_max(const double *partial, int n, const int32_t *first, int nvec, const uint8_t *active, double *out,

@@ -127,8 +127,9 @@ def test_batch_rejects_bad_options(slhjb):
 
 
 def test_batch_graph_replays_match_eager(slhjb):
-    """Batched V-cycles replayed from captured graphs (reused across Krylov iterations, policy iterations
-    and time steps, with eager work in between) give the eager results bit for bit."""
+    """Batched restart cycles (m Arnoldi steps with their V-cycles and device-side Givens rotations) and
+    V-cycles replayed from captured graphs (reused across restart cycles, policy iterations and time steps,
+    with eager work in between) give the eager results bit for bit."""
     insts = _batch_2d()[:4]
     Ug, pg, _ = _run_batch(slhjb, insts, slhjb.Options(precision=1, use_graphs=1))
     Ue, pe, _ = _run_batch(slhjb, insts, slhjb.Options(precision=1, use_graphs=0))

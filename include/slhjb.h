@@ -318,6 +318,18 @@ int hjb_setup_batch(const hjb_desc *descs, int32_t count, hjb_batch **out);
 /* offsets (host, count entries, nullable) and total nodes (host, nullable) of the concatenated layout */
 int hjb_batch_layout(const hjb_batch *bh, int64_t *offsets, int64_t *total);
 int hjb_batch_set_stream(hjb_batch *bh, void *stream);
+
+/* Tile shape of each instance: widths[b] (16, 32, 64 or 128 nodes along x; each level takes at most its own
+   next power of two) for instance b (host, count entries).  The batch's launch lists are rebuilt; results
+   agree with any other widths to the solver's certificate (partial sums follow the tiles).  HJB_EINVAL for
+   another width. */
+int hjb_batch_set_tile_widths(hjb_batch *bh, const int32_t *widths);
+
+/* The autotuner over a batch: for each distinct (grid, controls, coefficient model, precision, stencil reach)
+   among the instances, hjb_autotune on a full handle of one such instance (its cache file cache_path,
+   nullable, shared with hjb_autotune), then hjb_batch_set_tile_widths with the chosen widths; widths_out
+   (host, count entries, nullable) receives them. */
+int hjb_batch_autotune(hjb_batch *bh, const char *cache_path, int32_t *widths_out);
 /* hjb_solve for every instance with one shared schedule and s; arrays in the concatenated layout
    (device, FP64; policies int16 [n_steps][total], nullable); st: host [count] (nullable; near ties are not
    counted in batches: near_ties_total is 0).

@@ -30,7 +30,7 @@ EXPORTED = ["hjb_amg_level", "hjb_coarse_operator", "hjb_desc_default", "hjb_set
             "hjb_policy_sweep_noalloc", "hjb_apply",
             "hjb_linsolve", "hjb_step", "hjb_solve", "hjb_adjoint", "hjb_apply_transposed", "hjb_profile_enable",
             "hjb_profile_read", "hjb_profile_sample", "hjb_destroy", "hjb_last_error", "hjb_setup_batch", "hjb_batch_layout",
-            "hjb_batch_set_stream", "hjb_solve_batch", "hjb_destroy_batch", "hjb_set_tile_width", "hjb_autotune"]
+            "hjb_batch_set_stream", "hjb_batch_set_tile_widths", "hjb_batch_autotune", "hjb_solve_batch", "hjb_destroy_batch", "hjb_set_tile_width", "hjb_autotune"]
 KERNEL_APPLY, KERNEL_SMOOTH, KERNEL_MG_RESID, KERNEL_DOT, KERNEL_AXPY, KERNEL_SWEEP = range(6)
 KERNEL_NAMES = {KERNEL_APPLY: "apply", KERNEL_SMOOTH: "smooth", KERNEL_MG_RESID: "mg_residual",
                 KERNEL_DOT: "multidot", KERNEL_AXPY: "multiaxpy", KERNEL_SWEEP: "sweep"}
@@ -106,6 +106,8 @@ def _load():
     L.hjb_setup_batch.argtypes = [ctypes.POINTER(Desc), i32, ctypes.POINTER(vp)]
     L.hjb_batch_layout.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.hjb_batch_set_stream.argtypes = [vp, vp]
+    L.hjb_batch_set_tile_widths.argtypes = [vp, ctypes.POINTER(i32)]
+    L.hjb_batch_autotune.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i32)]
     L.hjb_solve_batch.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, d, vp, vp, ctypes.POINTER(SolveStats)]
     L.hjb_destroy_batch.argtypes = [vp]
     L.hjb_destroy_batch.restype = None
@@ -452,6 +454,18 @@ class Batch:
         _check(_lib.hjb_batch_layout(self._h, offs, ctypes.byref(tot)))
         self.offsets = [int(v) for v in offs]
         self.total = int(tot.value)
+
+    def set_tile_widths(self, widths):
+        """hjb_batch_set_tile_widths: one tile width (16, 32, 64, 128) per instance."""
+        w = (ctypes.c_int32 * len(self.instances))(*[int(v) for v in widths])
+        _check(_lib.hjb_batch_set_tile_widths(self._h, w))
+
+    def autotune(self, cache_path: Optional[str] = None):
+        """hjb_batch_autotune: per-instance tile widths from the timing autotuner (one run per distinct
+        instance key, results cached in cache_path); returns the widths."""
+        w = (ctypes.c_int32 * len(self.instances))()
+        _check(_lib.hjb_batch_autotune(self._h, cache_path.encode() if cache_path else None, w))
+        return [int(v) for v in w]
 
     def close(self):
         if getattr(self, "_h", None):

@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <functional>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <type_traits>
@@ -2791,6 +2792,7 @@ struct hjb_batch {
         hipGraphExec_t exec;
     };
     std::vector<CGraph> cgraphs;    // captured Arnoldi steps
+    int64_t maxn_cap = 0;           // tile entries of one level the partial-sum buffers hold
 };
 
 namespace {
@@ -2870,6 +2872,36 @@ int brefresh(hjb_batch *bh) {
         HIPCHK(hipMemcpyAsync(L.I, L.Ih.data(), (size_t)bh->B * sizeof(BInst), hipMemcpyHostToDevice, bh->stream));
     }
     return bwait(bh);
+}
+
+void bdrop_graphs(hjb_batch *bh) {
+    for (auto &g : bh->vgraphs) (void)hipGraphExecDestroy(g.exec);
+    bh->vgraphs.clear();
+    for (auto &g : bh->cgraphs) (void)hipGraphExecDestroy(g.exec);
+    bh->cgraphs.clear();
+}
+
+// tile tables of every level for the instances' current tile shapes (after a change of tile widths): the
+// launch lists, the partial-sum buffers when they must grow, the per-instance descriptors; captured graphs
+// hold the old lists and are dropped
+int brebuild_tiles(hjb_batch *bh) {
+    int64_t maxn = 0;
+    for (size_t l = 0; l < bh->lev.size(); ++l) {
+        BLevel &L = bh->lev[l];
+        const int li = (int)l;
+        TRY(build_tiletab(bh, li, [&](int) { return true; }, L.all));
+        TRY(build_tiletab(bh, li, [&](int b) { return li + 1 < bh->nlev[b]; }, L.fine));
+        TRY(build_tiletab(bh, li, [&](int b) {
+            return li == bh->nlev[b] - 1 && bh->sub[b]->lev[li].g.N > kCoarseMaxNodes; }, L.csm));
+        maxn = std::max<int64_t>(maxn, L.all.n);
+    }
+    if (maxn > bh->maxn_cap) {
+        TRY(balloc(bh, (void **)&bh->partial, (size_t)kLdc * maxn * 8));
+        TRY(balloc(bh, (void **)&bh->ipartial, (size_t)maxn * 8));
+        bh->maxn_cap = maxn;
+    }
+    bdrop_graphs(bh);
+    return brefresh(bh);
 }
 
 // ---- batched multigrid ---------------------------------------------------------------------------
@@ -3371,6 +3403,7 @@ int hjb_setup_batch(const hjb_desc *descs, int32_t count, hjb_batch **out) {
     BTRY(balloc(bh, (void **)&bh->acarry, N * 2));
     BTRY(balloc(bh, (void **)&bh->partial, (size_t)kLdc * maxn * 8));
     BTRY(balloc(bh, (void **)&bh->ipartial, (size_t)maxn * 8));
+    bh->maxn_cap = maxn;
     BTRY(balloc(bh, (void **)&bh->dseg, (size_t)count * kLdc * 8));
     BTRY(balloc(bh, (void **)&bh->dtau, (size_t)count * 8));
     BTRY(balloc(bh, (void **)&bh->dcoefA, (size_t)count * 8));
@@ -3430,6 +3463,46 @@ int hjb_batch_set_stream(hjb_batch *bh, void *stream) {
     bh->stream = (hipStream_t)stream;
     for (hjb_handle *h : bh->sub) h->stream = bh->stream;
     return HJB_OK;
+}
+
+int hjb_batch_set_tile_widths(hjb_batch *bh, const int32_t *widths) {
+    if (!bh || !widths) return fail(HJB_EINVAL, "null argument");
+    std::vector<int> tl(bh->B, -1);
+    for (int b = 0; b < bh->B; ++b) {
+        for (int c = kTileLogMin; c <= kTileLogMax; ++c)
+            if (widths[b] == (1 << c)) tl[b] = c;
+        if (tl[b] < 0) return fail(HJB_EINVAL, "instance %d: tile width must be 16, 32, 64 or 128", b);
+    }
+    HIPCHK(hipStreamSynchronize(bh->stream));
+    for (int b = 0; b < bh->B; ++b) apply_tiles(bh->sub[b], tl[b]);
+    return brebuild_tiles(bh);
+}
+
+int hjb_batch_autotune(hjb_batch *bh, const char *cache_path, int32_t *widths_out) {
+    if (!bh) return fail(HJB_EINVAL, "null batch");
+    // one tuning run per distinct key (grid, controls, coefficient model, precision, stencil reach), on a
+    // full handle set up from a representative instance
+    std::map<std::string, int> width_of;
+    std::vector<int32_t> widths(bh->B, 1 << kTileLog2);
+    for (int b = 0; b < bh->B; ++b) {
+        const std::string key = tune_key(bh->sub[b]);
+        auto it = width_of.find(key);
+        if (it == width_of.end()) {
+            hjb_desc db = bh->sub[b]->desc;
+            db.stream = bh->stream;
+            hjb_handle *h = nullptr;
+            TRY(setup_impl(&db, &h, false));
+            int32_t w = 0;
+            const int rc = hjb_autotune(h, cache_path, &w, nullptr);
+            hjb_destroy(h);
+            TRY(rc);
+            it = width_of.emplace(key, w).first;
+        }
+        widths[b] = it->second;
+    }
+    if (widths_out)
+        for (int b = 0; b < bh->B; ++b) widths_out[b] = widths[b];
+    return hjb_batch_set_tile_widths(bh, widths.data());
 }
 
 int hjb_solve_batch(hjb_batch *bh, const double *g, const double *psi, const double *f0, const double *f1,

@@ -168,3 +168,65 @@ def test_c4_batch_instances_match_oracle(slhjb):
         assert st[b].steps_done == len(inst.dts)
         assert rel <= 1e-10
         check_march_policies(inst, ref, pb[b], log=log)
+
+
+def _run_batch_tuned(slhjb, insts, opts, widths=None, cache=None):
+    bt = slhjb.Batch(insts, opts)
+    chosen = None
+    if widths is not None:
+        bt.set_tile_widths(widths)
+    if cache is not None:
+        chosen = bt.autotune(cache)
+    g, psi, f0, f1 = (to_dev(bt.concat(k)) for k in ("g", "psi", "f0", "f1"))
+    U = torch.empty_like(g)
+    pol = torch.empty((len(insts[0].dts), bt.total), dtype=torch.int16, device="cuda")
+    st = bt.solve(g, psi, f0, f1, insts[0].dts, insts[0].thetas, 1.0, U, pol)
+    out = [to_np(u) for u in bt.split(U)]
+    pols = [to_np(pol[:, o:o + inst.N]) for inst, o in zip(insts, bt.offsets)]
+    bt.close()
+    return out, pols, st, chosen
+
+
+def test_batch_per_instance_tile_widths(slhjb):
+    """Each instance of a batch on its own tile shape: the launch lists follow the instances' tiles, and the
+    results meet the oracle and the uniform-width batch (partial sums follow the tiles, so agreement is to the
+    certificate, not bitwise)."""
+    insts = _batch_2d()
+    widths = [16, 64, 128, 32, 16, 64]
+    opts = slhjb.Options(precision=1, max_levels=0)
+    Uw, pw, st, _ = _run_batch_tuned(slhjb, insts, opts, widths=widths)
+    Uu, pu, _ = _run_batch(slhjb, insts, opts)
+    for b, inst in enumerate(insts):
+        ref = oracle.march(inst, keep_policies=True, keep_values=True)
+        rel = np.max(np.abs(Uw[b] - ref["U"])) / np.max(np.abs(ref["U"]))
+        relu = np.max(np.abs(Uw[b] - Uu[b])) / np.max(np.abs(Uu[b]))
+        check_march_policies(inst, ref, pw[b], log=log)
+        log(f"  {inst.name} width {widths[b]}: pi={st[b].pi_total} krylov={st[b].krylov_total} rel vs oracle "
+            f"{rel:.2e}, vs uniform {relu:.2e}")
+        assert rel <= 1e-10 and relu <= 1e-10
+    with pytest.raises(slhjb.HJBError):
+        bt = slhjb.Batch(insts, opts)
+        try:
+            bt.set_tile_widths([16, 64, 128, 32, 16, 48])
+        finally:
+            bt.close()
+
+
+def test_batch_autotune(slhjb, tmp_path):
+    """The autotuner over a batch: one timing run per distinct instance key, widths from the cache on the
+    second call, and a solve on the chosen shapes that meets the oracle."""
+    insts = _batch_2d()[:4]
+    cache = str(tmp_path / "tune.jsonl")
+    opts = slhjb.Options(precision=1)
+    U1, p1, st, w1 = _run_batch_tuned(slhjb, insts, opts, cache=cache)
+    _, _, _, w2 = _run_batch_tuned(slhjb, insts, opts, cache=cache)
+    log(f"  autotuned widths {w1}, from the cache {w2}")
+    assert all(w in (16, 32, 64, 128) for w in w1)
+    assert w1 == w2
+    lines = open(cache).read().splitlines()
+    assert 1 <= len(lines) <= len(insts)
+    for b, inst in enumerate(insts):
+        ref = oracle.march(inst, keep_policies=True, keep_values=True)
+        rel = np.max(np.abs(U1[b] - ref["U"])) / np.max(np.abs(ref["U"]))
+        check_march_policies(inst, ref, p1[b], log=log)
+        assert rel <= 1e-10

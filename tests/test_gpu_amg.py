@@ -225,3 +225,42 @@ def test_amg_option_checks(slhjb):
     with pytest.raises(slhjb.HJBError):
         solver.amg_level(lv["levels"])
     solver.close()
+
+
+@pytest.mark.parametrize("name,mk", [("ragged_37x29_p2", lambda: _toy_amg((37, 29), K=7, P=2, seed=3)),
+                                     ("ragged_52x47_p1", lambda: _toy_amg((52, 47), K=3, P=1, seed=11)),
+                                     ("tiny_9", lambda: workloads.config_c2(9, n_cn=2))],
+                         ids=["ragged_37x29_p2", "ragged_52x47_p1", "tiny_9"])
+def test_amg_march_ragged_and_tiny(slhjb, name, mk):
+    """Ragged boxes with discounting and two diffusion columns, and a grid of 49 unknowns (no coarse level:
+    the preconditioner is the smoother alone)."""
+    inst = mk()
+    log(f"AMG march {name}")
+    _march_compare(slhjb, inst, slhjb.Options(precond=slhjb.PRECOND_AMG))
+
+
+def _toy_amg(n, K, P, seed):
+    from test_gpu_parity import _toy
+    return _toy(n, K=K, P=P, seed=seed, c=True)
+
+
+def test_amg_switch_preconditioners(slhjb):
+    """One handle: geometric cycle, aggregation, geometric again (set_options), each solve meeting the oracle."""
+    inst = workloads.config_c2(65)
+    pb, alpha, U = _setup_case(inst, 11)
+    t_prev, dt, theta = 0.0, 1.0 / 64, 0.5
+    f = pb.f_at(inst.f0, inst.f1, t_prev + theta * dt)
+    L = pb.assemble(alpha)
+    E = oracle.explicit_part(pb, L, alpha, U, f, dt, theta)
+    V0 = U.copy()
+    V0[pb.bd] = inst.psi[pb.bd]
+    Vref, _ = oracle.linear_solve(pb, L, alpha, V0, E, dt, theta, rtol=1e-15)
+    solver = slhjb.Solver.from_instance(inst, slhjb.Options(precision=1))
+    for pc in (slhjb.PRECOND_VCYCLE, slhjb.PRECOND_AMG, slhjb.PRECOND_VCYCLE, slhjb.PRECOND_AMG):
+        solver.set_options(slhjb.Options(precision=1, precond=pc))
+        dX = to_dev(V0)
+        st = solver.linsolve(to_dev(alpha), to_dev(U), to_dev(inst.f0), to_dev(inst.f1), t_prev, dt, theta, 1.0, dX)
+        rel = np.max(np.abs(to_np(dX) - Vref)) / np.max(np.abs(Vref))
+        log(f"  precond={pc}: krylov {st.krylov_total}, rel {rel:.2e}")
+        assert rel <= 1e-11
+    solver.close()

@@ -128,6 +128,9 @@ typedef struct {
                                GCR iterations preconditioned by the cycle below (the K-cycle), deeper levels by one
                                (a V-cycle whose coarse correction is scaled by its minimal-residual factor);
                                -1 (default): every level */
+    int32_t value_stride;   /* k >= 1: the `values` of hjb_solve and hjb_adjoint hold every k-th level only, U^0,
+                               U^k, U^2k, ... (n_steps / k + 1 arrays); hjb_adjoint recomputes the levels between
+                               them one segment at a time (default 1: every level) */
     void *stream;           /* hipStream_t */
 } hjb_desc;
 
@@ -169,7 +172,8 @@ int hjb_setup(const hjb_desc *desc, hjb_handle **out);
 int hjb_set_stream(hjb_handle *hd, void *stream);
 
 /* Change solver controls after setup (precision, precond, restart, max_krylov, max_pi, nu1, nu2,
-   coarse_sweeps, omega, rtol_inf, tau_rel, pi_eta, use_graphs, certified_skip, nu_tight, coarse_sweeps_t are taken from
+   coarse_sweeps, omega, rtol_inf, tau_rel, pi_eta, use_graphs, certified_skip, nu_tight, coarse_sweeps_t,
+   krylov, kcycle_levels, value_stride are taken from
    *desc; grid and controls
    are those of the setup).  restart may not exceed its value at setup. */
 int hjb_set_options(hjb_handle *hd, const hjb_desc *desc);
@@ -245,8 +249,8 @@ int hjb_step(hjb_handle *hd, const double *Uprev, double *Unext, const double *f
    entries are read) and psi1 (nullable, full-grid FP64): psi(t) = psi + t * psi1, constant when psi1 is NULL.
    theta = 0 steps are explicit (see hjb_step).  U_final: full-grid FP64 output.  policies (nullable): int16
    [n_steps][N], the converged policy of each step (the checkpoints an adjoint sweep reuses).
-   values (nullable): FP64 [n_steps+1][N], U^0 = g and every U^n, for hjb_adjoint to use instead of
-   recomputing them. */
+   values (nullable): FP64 [n_steps / value_stride + 1][N], U^0 = g and every value_stride-th U^n, for
+   hjb_adjoint to use instead of recomputing them. */
 int hjb_solve(hjb_handle *hd, const double *g, const double *psi, const double *psi1, const double *f0,
               const double *f1, int32_t n_steps, const double *dts, const double *thetas, double s,
               double *U_final, int16_t *policies, double *values, hjb_solve_stats *st);
@@ -264,12 +268,14 @@ typedef struct {
  * full previous level).  The values U^n enter only dJ/ds: they are taken from `values` (hjb_solve's output)
  * or, when it is NULL and dJ_ds is requested, recomputed from g and the int16 policies by fixed-policy solves,
  * keeping only every ceil(sqrt(n_steps))-th value and recomputing one segment at a time in the backward
- * sweep (2 n_steps solves, about 2 sqrt(n_steps) + 1 FP64 arrays); without dJ_ds nothing is recomputed.
+ * sweep (2 n_steps solves, about 2 sqrt(n_steps) + 1 FP64 arrays); with values holding every k-th level
+ * (value_stride = k > 1, as hjb_solve stored them) only the segments are recomputed (n_steps solves, k + 1
+ * arrays); without dJ_ds nothing is recomputed.
  * Then backwards: A_n^T mu_n = lambda_n, dJ/df0 += dt mu_n, dJ/df1 += dt t_mid mu_n,
  * dJ/ds += dt mu_n^T (theta d_s L U^n + (1-theta) d_s L U^{n-1}), lambda_{n-1} = B_n^T mu_n, dJ/dg = lambda_0.
  * Policies are held fixed, so the gradient is exact away from policy switches (where J is differentiable).
  *   g, psi, f0, f1: full-grid FP64 as for hjb_solve; policies: int16 [n_steps][N] from hjb_solve;
- *   values (nullable): FP64 [n_steps+1][N] from hjb_solve;
+ *   values (nullable): FP64 [n_steps / value_stride + 1][N] from hjb_solve with the same value_stride;
  *   dts, thetas: host [n_steps]; dJ_dUN: full-grid FP64 (boundary entries ignored);
  *   dJ_df0, dJ_dg: full-grid FP64 outputs (dJ_df0 zero on the boundary); dJ_df1: nullable;
  *   dJ_ds: host scalar (nullable).  Transposed solves use FGMRES on an explicitly transposed operator

@@ -8,6 +8,8 @@ There is no CPU fallback: if the library is missing the import fails.
 from __future__ import annotations
 
 import ctypes
+import math
+import dataclasses
 import os
 from dataclasses import dataclass
 from typing import Optional
@@ -55,6 +57,7 @@ class Desc(ctypes.Structure):
                 ("certified_skip", ctypes.c_int32), ("max_levels", ctypes.c_int32),
                 ("nu_tight", ctypes.c_int32), ("coarse_sweeps_t", ctypes.c_int32),
                 ("krylov", ctypes.c_int32), ("coarse_op", ctypes.c_int32), ("kcycle_levels", ctypes.c_int32),
+                ("value_stride", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
 
 
@@ -181,6 +184,7 @@ class Options:
     krylov: int = 0
     coarse_op: int = 0
     kcycle_levels: int = -1
+    value_stride: int = 1
 
 
 class Solver:
@@ -243,6 +247,7 @@ class Solver:
         desc.krylov = o.krylov
         desc.coarse_op = o.coarse_op
         desc.kcycle_levels = o.kcycle_levels
+        desc.value_stride = o.value_stride
 
     @classmethod
     def from_instance(cls, inst, options: Optional[Options] = None):
@@ -509,38 +514,65 @@ def _autograd_function():
 
         @staticmethod
         def forward(ctx, g, f0, f1, s, solver, psi, dts, thetas, store_values):
-            N = g.numel()
+            N, n = g.numel(), len(dts)
             U = torch.empty_like(g)
-            pol = torch.empty((len(dts), N), dtype=torch.int16, device=g.device)
-            vals = torch.empty((len(dts) + 1, N), dtype=torch.float64, device=g.device) if store_values else None
-            solver.solve(g, psi, f0, f1, dts, thetas, float(s), U, pol, vals)
-            saved = (g, f0, f1, psi, pol) + ((vals,) if store_values else ())
+            pol = torch.empty((n, N), dtype=torch.int16, device=g.device)
+            stride = 1
+            if store_values == "checkpoints":
+                stride = max(1, math.ceil(math.sqrt(n)))
+            vals = None
+            if store_values:
+                vals = torch.empty((n // stride + 1, N), dtype=torch.float64, device=g.device)
+            with _value_stride(solver, stride):
+                solver.solve(g, psi, f0, f1, dts, thetas, float(s), U, pol, vals)
+            saved = (g, f0, f1, psi, pol) + ((vals,) if vals is not None else ())
             ctx.save_for_backward(*saved)
-            ctx.meta = (solver, float(s), np.asarray(dts, np.float64), np.asarray(thetas, np.float64))
+            ctx.meta = (solver, float(s), np.asarray(dts, np.float64), np.asarray(thetas, np.float64), stride)
             return U
 
         @staticmethod
         def backward(ctx, gU):
             g, f0, f1, psi, pol = ctx.saved_tensors[:5]
             vals = ctx.saved_tensors[5] if len(ctx.saved_tensors) > 5 else None
-            solver, s, dts, thetas = ctx.meta
+            solver, s, dts, thetas, stride = ctx.meta
             df0, df1, dg = torch.empty_like(g), torch.empty_like(g), torch.empty_like(g)
-            ds, _ = solver.adjoint(g, psi, f0, f1, dts, thetas, s, pol, gU.contiguous(), df0, dg, dJ_df1=df1,
-                                   values=vals)
+            with _value_stride(solver, stride):
+                ds, _ = solver.adjoint(g, psi, f0, f1, dts, thetas, s, pol, gU.contiguous(), df0, dg, dJ_df1=df1,
+                                       values=vals)
             dsv = torch.tensor(ds, dtype=torch.float64, device=g.device)
             return dg, df0, df1, dsv, None, None, None, None, None
 
     return HJBMarch
 
 
-def hjb_march(solver: Solver, g, psi, f0, f1, dts, thetas, s, store_values: bool = False):
+class _value_stride:
+    """Context: the solver's value_stride option set to `stride` (restored on exit)."""
+
+    def __init__(self, solver, stride):
+        self.solver, self.stride = solver, int(stride)
+
+    def __enter__(self):
+        self.saved = self.solver.options
+        if self.saved.value_stride != self.stride:
+            self.solver.set_options(dataclasses.replace(self.saved, value_stride=self.stride))
+
+    def __exit__(self, *exc):
+        if self.solver.options is not self.saved:
+            self.solver.set_options(self.saved)
+        return False
+
+
+def hjb_march(solver: Solver, g, psi, f0, f1, dts, thetas, s, store_values="checkpoints"):
     """Differentiable march: returns U^N; gradients flow to g, f0, f1 and s (a 0-d FP64 tensor or float).
 
-    The forward pass keeps the int16 policies of every step; the backward pass recomputes the values it needs
-    from them (hjb_adjoint without values).  store_values=True keeps the FP64 values of every step instead
-    (n_steps + 1 full-grid arrays) and skips the recomputation."""
+    The forward pass keeps the int16 policies of every step.  store_values="checkpoints" (default) also keeps
+    every ceil(sqrt(n_steps))-th FP64 level, from which the backward pass recomputes the values it needs one
+    segment at a time (n_steps fixed-policy solves); False keeps no values (the adjoint first recomputes the
+    checkpoints, 2 n_steps solves); True keeps every level (n_steps + 1 full-grid arrays, no recomputation)."""
     import torch
     F = _autograd_function()
     if not torch.is_tensor(s):
         s = torch.tensor(float(s), dtype=torch.float64, device=g.device)
-    return F.apply(g, f0, f1, s, solver, psi, dts, thetas, bool(store_values))
+    if store_values not in (True, False, "checkpoints"):
+        raise ValueError("store_values: True, False or 'checkpoints'")
+    return F.apply(g, f0, f1, s, solver, psi, dts, thetas, store_values)

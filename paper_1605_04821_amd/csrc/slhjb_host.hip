@@ -407,6 +407,7 @@ int check_options(const hjb_desc *d) {
     if (d->precond == HJB_PRECOND_AMG && d->dim != 2)
         return fail(HJB_EUNSUPPORTED, "the aggregation AMG preconditioner is provided for 2D grids");
     if (d->kcycle_levels < -1) return fail(HJB_EINVAL, "kcycle_levels must be >= -1");
+    if (d->value_stride < 1) return fail(HJB_EINVAL, "value_stride must be >= 1");
     if (d->restart < 1 || d->restart > kMaxRestart) return fail(HJB_EINVAL, "restart must be in 1..%d", kMaxRestart);
     if (d->max_krylov < 1) return fail(HJB_EINVAL, "max_krylov must be >= 1");
     if (d->max_pi < 1) return fail(HJB_EINVAL, "max_pi must be >= 1");
@@ -1560,6 +1561,7 @@ void hjb_desc_default(hjb_desc *d) {
     d->krylov = HJB_KRYLOV_FGMRES;
     d->coarse_op = HJB_COARSE_REDISCRETIZED;
     d->kcycle_levels = -1;
+    d->value_stride = 1;
     d->stream = nullptr;
 }
 
@@ -1865,6 +1867,7 @@ int hjb_set_options(hjb_handle *hd, const hjb_desc *desc) {
     d.coarse_sweeps_t = desc->coarse_sweeps_t;
     d.krylov = desc->krylov;
     d.kcycle_levels = desc->kcycle_levels;
+    d.value_stride = desc->value_stride;
     if (desc->coarse_op != d.coarse_op) return fail(HJB_EINVAL, "coarse_op is fixed at setup");
     select_precision(hd);
     set_sweeps(hd, false);
@@ -2004,8 +2007,9 @@ int hjb_solve(hjb_handle *hd, const double *g, const double *psi, const double *
         loc.max_cert_bound = std::max(loc.max_cert_bound, sst.cert_bound);
         if (rc != HJB_OK) break;
         if (policies) HIPCHK(hipMemcpyAsync(policies + (int64_t)n * N, acarry, (size_t)N * 2, hipMemcpyDeviceToDevice, str));
-        if (values)
-            HIPCHK(hipMemcpyAsync(values + (int64_t)(n + 1) * N, Unx, (size_t)N * 8, hipMemcpyDeviceToDevice, str));
+        if (values && (n + 1) % hd->desc.value_stride == 0)
+            HIPCHK(hipMemcpyAsync(values + (int64_t)((n + 1) / hd->desc.value_stride) * N, Unx, (size_t)N * 8,
+                                  hipMemcpyDeviceToDevice, str));
         std::swap(Uold, Ucur);  // Uold <- U^{n-1}
         std::swap(Ucur, Unx);   // Ucur <- U^n
         t = t + dts[n];
@@ -2548,9 +2552,13 @@ int hjb_adjoint(hjb_handle *hd, const double *g, const double *psi, const double
     // dJ_ds) they are recomputed from g and the int16 policies by fixed-policy solves: a forward pass keeps
     // every seg-th value (seg = ceil(sqrt(n_steps))), and the backward sweep recomputes one segment of at most
     // seg + 1 values from its checkpoint before stepping through it: 2 n_steps solves and about
-    // 2 sqrt(n_steps) + 1 FP64 arrays instead of n_steps + 1.
+    // 2 sqrt(n_steps) + 1 FP64 arrays instead of n_steps + 1.  With values holding every k-th level
+    // (value_stride = k > 1) those are the checkpoints and only the backward recomputation remains.
     const bool need_values = dJ_ds != nullptr;
-    const int seg = (values || !need_values) ? n_steps : std::max(1, (int)ceil(sqrt((double)n_steps)));
+    const int stride = hd->desc.value_stride;
+    const bool all_values = values && stride == 1;
+    const int seg = (all_values || !need_values) ? n_steps
+                    : values ? stride : std::max(1, (int)ceil(sqrt((double)n_steps)));
     double *ck = nullptr, *sb = nullptr;  // checkpoints U^{k seg}, segment buffer U^{n0} .. U^{n0 + seg}
     int seg_n0 = -1;                      // first step of the segment in sb
     // U^n by a fixed-policy solve from U^{n-1}, started from the linear extrapolation of U^{n-2}, U^{n-1}
@@ -2584,9 +2592,13 @@ int hjb_adjoint(hjb_handle *hd, const double *g, const double *psi, const double
             Up = Un;
         }
     }
+    if (values && !all_values && need_values) {
+        ck = const_cast<double *>(values);  // read only
+        TRY(get(&sb, (size_t)(std::min(seg, n_steps) + 1) * N * 8));
+    }
     // U^m for a step n of the backward sweep (m = n or n + 1)
     auto U_at = [&](int n, int m, const double **out) -> int {
-        if (values) {
+        if (all_values) {
             *out = values + (int64_t)m * N;
             return HJB_OK;
         }

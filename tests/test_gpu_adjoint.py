@@ -215,10 +215,12 @@ def _check_adjoint(slhjb, name, inst, precision, precond, max_levels=2, coarse_s
     solver.close()
 
 
-def test_autograd_march(slhjb):
-    """HJBMarch: backward of sum(w * U^N) gives the adjoint gradients with lambda_N = w."""
+@pytest.mark.parametrize("store", ["checkpoints", False, True], ids=["checkpoints", "recompute", "stored"])
+def test_autograd_march(slhjb, store):
+    """HJBMarch: backward of sum(w * U^N) gives the adjoint gradients with lambda_N = w, with the forward
+    keeping every ceil(sqrt(n))-th level, no level, or every level."""
     inst = workloads.config_c2(33, n_cn=4)
-    log("autograd march c2_33")
+    log(f"autograd march c2_33, store_values={store}")
     ref_march = oracle.march(inst, keep_policies=True)
     w = _lam_N(inst, ref_march["U"], seed=41)
     ref = oracle.adjoint_dense(inst, ref_march["policies"], w)
@@ -227,7 +229,7 @@ def test_autograd_march(slhjb):
     f0 = to_dev(inst.f0).requires_grad_(True)
     f1 = to_dev(inst.f1).requires_grad_(True)
     s = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=True)
-    U = slhjb.hjb_march(solver, g, to_dev(inst.psi), f0, f1, inst.dts, inst.thetas, s)
+    U = slhjb.hjb_march(solver, g, to_dev(inst.psi), f0, f1, inst.dts, inst.thetas, s, store_values=store)
     np.testing.assert_allclose(to_np(U.detach()), ref_march["U"], rtol=0, atol=1e-10)
     (U * to_dev(w)).sum().backward()
     for key, t in (("dg", g), ("df0", f0), ("df1", f1)):
@@ -282,7 +284,8 @@ def test_adjoint_checkpointed_recompute(slhjb, n_cn):
     """Without stored values the adjoint recomputes them from the int16 policies, keeping every
     ceil(sqrt(n_steps))-th value (3, 10 and 16 steps: segments of 2+1, 4+4+2 and 4x4 steps): the
     gradients equal those with the forward's stored values, the recomputation costs about two fixed-policy
-    solves per step, and without dJ/ds nothing is recomputed."""
+    solves per step, and without dJ/ds nothing is recomputed.  With the forward's every k-th level as
+    checkpoints (value_stride) only the segments are recomputed, to the same gradients."""
     inst = workloads.config_c2(65, n_cn=n_cn)
     n = len(inst.dts)
     log(f"checkpointed recompute c2_65, {n} steps")
@@ -300,11 +303,25 @@ def test_adjoint_checkpointed_recompute(slhjb, n_cn):
                                 values=v, want_ds=want)
         log(f"  {name}: recompute its {st.krylov_recompute}, adjoint its {st.krylov_adjoint}, ds {ds}")
         res[name] = (to_np(dg), to_np(df0), to_np(df1), ds, st)
+    # checkpoints from the forward march (every k-th level, value_stride = k): only the segments are recomputed
+    k = max(1, int(np.ceil(np.sqrt(n))))
+    solver.set_options(slhjb.Options(value_stride=k))
+    ck = torch.empty((n // k + 1, inst.N), dtype=torch.float64, device="cuda")
+    U2 = torch.empty_like(g)
+    solver.solve(g, psi, f0, f1, inst.dts, inst.thetas, 1.0, U2, pol, ck)
+    assert torch.equal(U2, U)
+    assert torch.equal(ck, vals[::k][: n // k + 1])
+    dg, df0, df1 = torch.empty_like(g), torch.empty_like(g), torch.empty_like(g)
+    ds, st = solver.adjoint(g, psi, f0, f1, inst.dts, inst.thetas, 1.0, pol, lam, df0, dg, dJ_df1=df1, values=ck)
+    log(f"  forward checkpoints (stride {k}): recompute its {st.krylov_recompute}, adjoint its "
+        f"{st.krylov_adjoint}, ds {ds}")
+    res["checkpoints"] = (to_np(dg), to_np(df0), to_np(df1), ds, st)
     assert res["stored"][4].krylov_recompute == 0 and res["no ds"][4].krylov_recompute == 0
     assert res["recomputed"][4].krylov_recompute > 0
-    for name in ("recomputed", "no ds"):
+    assert 0 < res["checkpoints"][4].krylov_recompute <= res["recomputed"][4].krylov_recompute
+    for name in ("recomputed", "no ds", "checkpoints"):
         for a, b in zip(res[name][:3], res["stored"][:3]):
             assert np.max(np.abs(a - b)) <= 1e-10 * max(1.0, np.max(np.abs(b)))
-    ds_r, ds_s = res["recomputed"][3], res["stored"][3]
-    assert abs(ds_r - ds_s) <= 1e-9 * max(1.0, abs(ds_s))
+    for name in ("recomputed", "checkpoints"):
+        assert abs(res[name][3] - res["stored"][3]) <= 1e-9 * max(1.0, abs(res["stored"][3]))
     solver.close()

@@ -131,6 +131,10 @@ typedef struct {
     int32_t value_stride;   /* k >= 1: the `values` of hjb_solve and hjb_adjoint hold every k-th level only, U^0,
                                U^k, U^2k, ... (n_steps / k + 1 arrays); hjb_adjoint recomputes the levels between
                                them one segment at a time (default 1: every level) */
+    int32_t amg_reuse;      /* HJB_PRECOND_AMG: 0 (default) rebuilds the aggregation hierarchy for every policy;
+                               1 builds it at the first solve of each time step and keeps its coarse levels for
+                               the step's later policies (the finest level always follows the current policy;
+                               the outer Krylov method still meets the certificate) */
     void *stream;           /* hipStream_t */
 } hjb_desc;
 
@@ -173,7 +177,7 @@ int hjb_set_stream(hjb_handle *hd, void *stream);
 
 /* Change solver controls after setup (precision, precond, restart, max_krylov, max_pi, nu1, nu2,
    coarse_sweeps, omega, rtol_inf, tau_rel, pi_eta, use_graphs, certified_skip, nu_tight, coarse_sweeps_t,
-   krylov, kcycle_levels, value_stride are taken from
+   krylov, kcycle_levels, value_stride, amg_reuse are taken from
    *desc; grid and controls
    are those of the setup).  restart may not exceed its value at setup. */
 int hjb_set_options(hjb_handle *hd, const hjb_desc *desc);
@@ -300,8 +304,8 @@ int hjb_apply_transposed(hjb_handle *hd, const int16_t *alpha, const double *x, 
  * the ELL width and the level's node count.  HJB_EINVAL for a level without a Galerkin operator. */
 int hjb_coarse_operator(hjb_handle *hd, int32_t level, int32_t *width, int64_t *nodes, int32_t *cols, double *vals);
 
-/* One level of the aggregation hierarchy (HJB_PRECOND_AMG, Sections 3.4-3.5) built for the policy of the handle's
- * last solve.  Level 0 is the finest system matrix A = I - theta dt (L-hat + c) of the interior unknowns,
+/* One level of the aggregation hierarchy (HJB_PRECOND_AMG, Sections 3.4-3.5) of the handle's last hierarchy
+ * build (the last solve's policy, or with amg_reuse the policy of its time step's first solve).  Level 0 is the finest system matrix A = I - theta dt (L-hat + c) of the interior unknowns,
  * indexed by full-grid node (boundary rows empty, boundary columns left to the right-hand side); level l >= 1 holds A_l = P_l^T A_{l-1} P_l, where P_l is piecewise constant: fine node i of
  * level l-1 maps to aggregate agg[i] of level l (-1: in no aggregate).  Rows are sliced ELL, entry s of row i
  * at s * rows + i (column -1 unused, a row's entries in its first slots).  levels, rows and width (nullable)

@@ -57,7 +57,7 @@ class Desc(ctypes.Structure):
                 ("certified_skip", ctypes.c_int32), ("max_levels", ctypes.c_int32),
                 ("nu_tight", ctypes.c_int32), ("coarse_sweeps_t", ctypes.c_int32),
                 ("krylov", ctypes.c_int32), ("coarse_op", ctypes.c_int32), ("kcycle_levels", ctypes.c_int32),
-                ("value_stride", ctypes.c_int32),
+                ("value_stride", ctypes.c_int32), ("amg_reuse", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
 
 
@@ -185,6 +185,7 @@ class Options:
     coarse_op: int = 0
     kcycle_levels: int = -1
     value_stride: int = 1
+    amg_reuse: int = 0
 
 
 class Solver:
@@ -248,6 +249,7 @@ class Solver:
         desc.coarse_op = o.coarse_op
         desc.kcycle_levels = o.kcycle_levels
         desc.value_stride = o.value_stride
+        desc.amg_reuse = o.amg_reuse
 
     @classmethod
     def from_instance(cls, inst, options: Optional[Options] = None):

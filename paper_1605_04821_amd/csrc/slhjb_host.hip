@@ -130,6 +130,8 @@ struct hjb_handle {
     DevBuf amg_rawc, amg_rawv, amg_mate, amg_cand, amg_flag, amg_id, amg_part, amg_aggA, amg_aggB, amg_mem2a, amg_mem2b,
         amg_icol, amg_ival, amg_words, amg_dpart, amg_sc, amg_trow, amg_tval, amg_scol, amg_sval;
     int amg_levels = 0;  // levels of the current hierarchy (0: none built)
+    bool amg_fresh = true;     // the next hierarchy is built anew (a time step or a single solve starts)
+    double amg_theta_dt = -1;  // theta*dt of the current hierarchy
     // certified reuse of search decisions within a step: gap bounds [N], X at the previous search [N],
     // per-tile largest change of X and its stencil-window maximum [nb_cap], window radius in nodes per axis
     double *marg = nullptr, *Xs = nullptr, *dtile = nullptr, *dwin = nullptr;
@@ -408,6 +410,7 @@ int check_options(const hjb_desc *d) {
         return fail(HJB_EUNSUPPORTED, "the aggregation AMG preconditioner is provided for 2D grids");
     if (d->kcycle_levels < -1) return fail(HJB_EINVAL, "kcycle_levels must be >= -1");
     if (d->value_stride < 1) return fail(HJB_EINVAL, "value_stride must be >= 1");
+    if (d->amg_reuse != 0 && d->amg_reuse != 1) return fail(HJB_EINVAL, "amg_reuse must be 0 or 1");
     if (d->restart < 1 || d->restart > kMaxRestart) return fail(HJB_EINVAL, "restart must be in 1..%d", kMaxRestart);
     if (d->max_krylov < 1) return fail(HJB_EINVAL, "max_krylov must be >= 1");
     if (d->max_pi < 1) return fail(HJB_EINVAL, "max_pi must be >= 1");
@@ -767,7 +770,12 @@ int prepare_amg(hjb_handle *hd, const int16_t *alpha, double theta_dt) {
     L.wctl_ok = L.wctl && st.lii_deep;
     launch_diag<double>(hd->dim, L.g, st, alpha, theta_dt, (double *)L.d64, hd->stream,
                         L.wctl_ok ? L.wctl : nullptr, L.dk64);
-    TRY(build_amg(hd, alpha, theta_dt));
+    // with amg_reuse, later policies of a time step keep the step's coarse levels (the finest level, smoothed
+    // and reduced matrix-free with the current policy, is always current)
+    const bool keep = hd->desc.amg_reuse && !hd->amg_fresh && hd->amg_levels > 0 && hd->amg_theta_dt == theta_dt;
+    if (!keep) TRY(build_amg(hd, alpha, theta_dt));
+    hd->amg_fresh = false;
+    hd->amg_theta_dt = theta_dt;
     HIPCHK(hipGetLastError());
     return HJB_OK;
 }
@@ -1451,6 +1459,7 @@ int step_impl(hjb_handle *hd, const double *Uprev, double *Unext, const double *
     hipStream_t s = hd->stream;
     const int64_t N = hd->N;
     hjb_step_stats loc{};
+    hd->amg_fresh = true;
     if (theta == 0.0) {
         // explicit scheme: U^n = U^{n-1} + dt min_k G_k(U^{n-1}) on interior nodes, one search and no solve
         // (G_k at theta = 0 equals the theta = 1 quantity evaluated at X = U, with f at t_{n-1})
@@ -1562,6 +1571,7 @@ void hjb_desc_default(hjb_desc *d) {
     d->coarse_op = HJB_COARSE_REDISCRETIZED;
     d->kcycle_levels = -1;
     d->value_stride = 1;
+    d->amg_reuse = 0;
     d->stream = nullptr;
 }
 
@@ -1868,6 +1878,7 @@ int hjb_set_options(hjb_handle *hd, const hjb_desc *desc) {
     d.krylov = desc->krylov;
     d.kcycle_levels = desc->kcycle_levels;
     d.value_stride = desc->value_stride;
+    d.amg_reuse = desc->amg_reuse;
     if (desc->coarse_op != d.coarse_op) return fail(HJB_EINVAL, "coarse_op is fixed at setup");
     select_precision(hd);
     set_sweeps(hd, false);
@@ -1945,6 +1956,7 @@ int hjb_linsolve(hjb_handle *hd, const int16_t *alpha, const double *U, const do
     int its = 0;
     double res = 0.0;
     bool tight = false;
+    hd->amg_fresh = true;
     int rc = linsolve_impl(hd, alpha, U, f0, f1, t_prev, dt, theta, X, 0.0, &its, &res, &tight);
     if (st) {
         memset(st, 0, sizeof *st);

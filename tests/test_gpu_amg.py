@@ -264,3 +264,13 @@ def test_amg_switch_preconditioners(slhjb):
         log(f"  precond={pc}: krylov {st.krylov_total}, rel {rel:.2e}")
         assert rel <= 1e-11
     solver.close()
+
+
+@pytest.mark.parametrize("name,mk", [("c2_65", lambda: workloads.config_c2(65, n_cn=6)),
+                                     ("c1_33", lambda: workloads.config_c1(33))], ids=["c2_65", "c1_33"])
+def test_amg_march_reused_hierarchy(slhjb, name, mk):
+    """amg_reuse: the hierarchy of a step's first policy preconditions the step's later solves (the finest
+    level follows the current policy); the marches still meet the oracle."""
+    inst = mk()
+    log(f"AMG march with the hierarchy kept within each step: {name}")
+    _march_compare(slhjb, inst, slhjb.Options(precond=slhjb.PRECOND_AMG, amg_reuse=1))

@@ -694,6 +694,57 @@ __global__ __launch_bounds__(kAmgCoarseThreads) void k_amg_dense_solve(int n, co
     }
 }
 
+// ---- wide levels: row-major copies and one wavefront per row ----------------------------------------------
+// Coarse aggregation levels have rows of tens to hundreds of entries over few rows: one thread per row leaves
+// most of the GPU idle and walks each row serially.  Such levels keep a row-major copy (entry s of row i at
+// i * W + s) and the cycle's kernels give each row one wavefront: lanes take the row's entries in strides of
+// 64 (coalesced) and the partial sums are combined by a fixed butterfly, so the result does not depend on
+// scheduling.
+
+__global__ __launch_bounds__(kBlock) void k_amg_rowmajor(int64_t n, int W, const int32_t *__restrict__ col,
+                                                         const double *__restrict__ val, int32_t *__restrict__ rcol,
+                                                         double *__restrict__ rval) {
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;  // entry of the row-major copy
+    if (q >= n * W) return;
+    const int64_t i = q / W;
+    const int s = (int)(q % W);
+    const int j = col[(int64_t)s * n + i];
+    rcol[q] = j;
+    rval[q] = j >= 0 ? val[(int64_t)s * n + i] : 0.0;
+}
+
+__device__ __forceinline__ double wave_row_dot(int64_t i, int W, const int32_t *__restrict__ rcol,
+                                               const double *__restrict__ rval, const double *__restrict__ x,
+                                               int lane) {
+    double a = 0.0;
+    const int64_t base = i * W;
+    for (int s = lane; s < W; s += 64) {
+        const int j = rcol[base + s];
+        if (j >= 0) a += rval[base + s] * x[j];
+    }
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    return a;
+}
+
+// mode 0: y = A x; mode 1: y = r - A x; mode 2: Jacobi y = x + omega (r - A x) / d (first: y = omega r / d)
+__global__ __launch_bounds__(256) void k_amg_wave_op(int64_t n, int W, const int32_t *__restrict__ rcol,
+                                                     const double *__restrict__ rval, const double *__restrict__ d,
+                                                     const double *__restrict__ x, const double *__restrict__ r,
+                                                     double *__restrict__ y, int mode, double omega, int first) {
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= n) return;
+    if (mode == 2 && first) {
+        if (lane == 0) y[i] = omega * r[i] / d[i];
+        return;
+    }
+    const double a = wave_row_dot(i, W, rcol, rval, x, lane);
+    if (lane != 0) return;
+    if (mode == 0) y[i] = a;
+    else if (mode == 1) y[i] = r[i] - a;
+    else y[i] = x[i] + omega * (r[i] - a) / d[i];
+}
+
 // ---- launchers -------------------------------------------------------------------------------------------
 
 static unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + kBlock - 1) / kBlock); }
@@ -793,6 +844,15 @@ void launch_amg_gcr(int64_t n, int mode, const double *sc, double *x, double *v,
 void launch_amg_coarse(int n, int W, const int32_t *col, const double *val, const double *d, const double *r,
                        int sweeps, double *x, hipStream_t s) {
     hipLaunchKernelGGL(k_amg_coarse, dim3(1), dim3(kAmgCoarseThreads), 0, s, n, W, col, val, d, r, sweeps, x);
+}
+void launch_amg_rowmajor(int64_t n, int W, const int32_t *col, const double *val, int32_t *rcol, double *rval,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_amg_rowmajor, dim3(grid_for(n * W)), dim3(kBlock), 0, s, n, W, col, val, rcol, rval);
+}
+void launch_amg_wave_op(int64_t n, int W, const int32_t *rcol, const double *rval, const double *d, const double *x,
+                        const double *r, double *y, int mode, double omega, bool first, hipStream_t s) {
+    hipLaunchKernelGGL(k_amg_wave_op, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, W, rcol, rval, d, x, r, y,
+                       mode, omega, (int)first);
 }
 void launch_amg_dense_inverse(int n, int W, const int32_t *col, const double *val, double *inv, hipStream_t s) {
     hipLaunchKernelGGL(k_amg_dense_inverse, dim3(1), dim3(kAmgCoarseThreads), 0, s, n, W, col, val, inv);

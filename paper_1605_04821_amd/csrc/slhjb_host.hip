@@ -103,7 +103,8 @@ struct DevBuf {
 struct AmgLevel {
     int64_t n = 0;
     int W = 0;
-    DevBuf col, val, d, agg, mem4, inv;
+    bool wide = false;  // rows wider than kAmgWaveWidth: the cycle reads the row-major copy (rcol, rval)
+    DevBuf col, val, d, agg, mem4, inv, rcol, rval;
     DevBuf x, r, t, v1, w1, v2, w2, r1;
 };
 
@@ -759,6 +760,17 @@ int build_amg(hjb_handle *hd, const int16_t *alpha, double theta_dt) {
         TRY(grow(hd, Lc.inv, (size_t)Lc.n * Lc.n * 8));
         launch_amg_dense_inverse((int)Lc.n, Lc.W, Lc.col.as<int32_t>(), Lc.val.as<double>(), Lc.inv.as<double>(), s);
     }
+    for (int l = 1; l < levels; ++l) {
+        AmgLevel &A = hd->amg[l];
+        // a wavefront per row pays where rows are wide and few; with many rows one thread per row already fills
+        // the GPU and reads the slot-major layout coalesced
+        A.wide = A.W > kAmgWaveWidth && A.n <= kAmgWaveRows;
+        if (!A.wide) continue;
+        TRY(grow(hd, A.rcol, (size_t)A.n * A.W * 4));
+        TRY(grow(hd, A.rval, (size_t)A.n * A.W * 8));
+        launch_amg_rowmajor(A.n, A.W, A.col.as<int32_t>(), A.val.as<double>(), A.rcol.as<int32_t>(),
+                            A.rval.as<double>(), s);
+    }
     hd->amg_levels = levels;
     return HJB_OK;
 }
@@ -796,8 +808,12 @@ void amg_smooth(hjb_handle *hd, int l, double *&e, double *&t, const double *r, 
     }
     AmgLevel &A = hd->amg[l];
     for (int q = 0; q < sweeps; ++q) {
-        launch_gal_jacobi<double>(A.n, A.W, A.col.as<int32_t>(), A.val.as<double>(), A.d.as<double>(), e, r, t,
-                                  hd->desc.omega, first && q == 0, s);
+        if (A.wide)
+            launch_amg_wave_op(A.n, A.W, A.rcol.as<int32_t>(), A.rval.as<double>(), A.d.as<double>(), e, r, t, 2,
+                               hd->desc.omega, first && q == 0, s);
+        else
+            launch_gal_jacobi<double>(A.n, A.W, A.col.as<int32_t>(), A.val.as<double>(), A.d.as<double>(), e, r, t,
+                                      hd->desc.omega, first && q == 0, s);
         std::swap(e, t);
     }
 }
@@ -820,7 +836,11 @@ void amg_cycle(hjb_handle *hd, int l, const double *r, double *out, double theta
                                       L.wctl_ok ? L.wctl : nullptr);
     } else {
         AmgLevel &A = hd->amg[l];
-        launch_gal_residual<double>(A.n, A.W, A.col.as<int32_t>(), A.val.as<double>(), e, r, t, s);
+        if (A.wide)
+            launch_amg_wave_op(A.n, A.W, A.rcol.as<int32_t>(), A.rval.as<double>(), nullptr, e, r, t, 1, 0.0, false,
+                               s);
+        else
+            launch_gal_residual<double>(A.n, A.W, A.col.as<int32_t>(), A.val.as<double>(), e, r, t, s);
     }
     AmgLevel &C = hd->amg[l + 1];
     launch_amg_restrict(C.n, C.mem4.as<int32_t>(), t, C.r.as<double>(), s);
@@ -841,6 +861,14 @@ void amg_solve(hjb_handle *hd, int l, const double *r, double *x, double theta_d
     if (l == hd->amg_levels - 1) {
         if (A.n <= kAmgDenseMax) {
             launch_amg_dense_solve((int)A.n, A.inv.as<double>(), r, x, s);
+        } else if (A.wide) {
+            double *e = x, *t = A.t.as<double>();
+            if (hd->desc.coarse_sweeps % 2) std::swap(e, t);
+            for (int q = 0; q < hd->desc.coarse_sweeps; ++q) {
+                launch_amg_wave_op(A.n, A.W, A.rcol.as<int32_t>(), A.rval.as<double>(), A.d.as<double>(), e, r, t, 2,
+                                   1.0, q == 0, s);
+                std::swap(e, t);
+            }
         } else if (A.n <= kAmgCoarseMax) {
             launch_amg_coarse((int)A.n, A.W, col, val, A.d.as<double>(), r, hd->desc.coarse_sweeps, x, s);
         } else {
@@ -857,13 +885,20 @@ void amg_solve(hjb_handle *hd, int l, const double *r, double *x, double theta_d
     double *part = hd->amg_dpart.as<double>();
     double *v1 = A.v1.as<double>(), *w1 = A.w1.as<double>(), *v2 = A.v2.as<double>(), *w2 = A.w2.as<double>();
     double *r1 = A.r1.as<double>();
+    auto spmv = [&](const double *x, double *y) {
+        if (A.wide)
+            launch_amg_wave_op(A.n, A.W, A.rcol.as<int32_t>(), A.rval.as<double>(), nullptr, x, nullptr, y, 0, 0.0,
+                               false, s);
+        else
+            launch_amg_spmv(A.n, A.W, col, val, x, y, s);
+    };
     amg_cycle(hd, l, r, v1, theta_dt);
-    launch_amg_spmv(A.n, A.W, col, val, v1, w1, s);
+    spmv(v1, w1);
     launch_amg_dot2(A.n, w1, r, w1, part, sc, s);
     launch_amg_gcr(A.n, 0, sc, x, v1, w1, nullptr, nullptr, r, r1, s);
     if (hd->desc.kcycle_levels >= 0 && l > hd->desc.kcycle_levels) return;
     amg_cycle(hd, l, r1, v2, theta_dt);
-    launch_amg_spmv(A.n, A.W, col, val, v2, w2, s);
+    spmv(v2, w2);
     launch_amg_dot2(A.n, w1, w2, w1, part, sc + 2, s);
     launch_amg_gcr(A.n, 1, sc + 2, nullptr, v2, w2, v1, w1, nullptr, nullptr, s);
     launch_amg_dot2(A.n, w2, r1, w2, part, sc + 4, s);
@@ -2724,8 +2759,8 @@ void hjb_destroy(hjb_handle *hd) {
     else (void)hipDeviceSynchronize();
     for (void *p : hd->allocs) (void)hipFree(p);
     for (AmgLevel &L : hd->amg)
-        for (DevBuf *b : {&L.col, &L.val, &L.d, &L.agg, &L.mem4, &L.inv, &L.x, &L.r, &L.t, &L.v1, &L.w1, &L.v2, &L.w2,
-                          &L.r1})
+        for (DevBuf *b : {&L.col, &L.val, &L.d, &L.agg, &L.mem4, &L.inv, &L.rcol, &L.rval, &L.x, &L.r, &L.t, &L.v1,
+                          &L.w1, &L.v2, &L.w2, &L.r1})
             release(*b);
     for (DevBuf *b : {&hd->amg_rawc, &hd->amg_rawv, &hd->amg_mate, &hd->amg_cand, &hd->amg_flag, &hd->amg_id,
                       &hd->amg_part, &hd->amg_aggA, &hd->amg_aggB, &hd->amg_mem2a, &hd->amg_mem2b, &hd->amg_icol,

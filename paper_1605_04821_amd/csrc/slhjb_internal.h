@@ -335,6 +335,14 @@ void launch_amg_gcr(int64_t n, int mode, const double *sc, double *x, double *v,
 void launch_amg_coarse(int n, int W, const int32_t *col, const double *val, const double *d, const double *r,
                        int sweeps, double *x, hipStream_t s);
 void launch_amg_dense_inverse(int n, int W, const int32_t *col, const double *val, double *inv, hipStream_t s);
+// wide levels: row-major copy (entry s of row i at i * W + s) and one wavefront per row; mode 0: y = A x,
+// 1: y = r - A x, 2: damped Jacobi y = x + omega (r - A x) / d (first: y = omega r / d)
+void launch_amg_rowmajor(int64_t n, int W, const int32_t *col, const double *val, int32_t *rcol, double *rval,
+                         hipStream_t s);
+void launch_amg_wave_op(int64_t n, int W, const int32_t *rcol, const double *rval, const double *d, const double *x,
+                        const double *r, double *y, int mode, double omega, bool first, hipStream_t s);
+constexpr int kAmgWaveWidth = 32;       // levels with wider rows and at most kAmgWaveRows rows use the row-major
+constexpr int64_t kAmgWaveRows = 262144;  // copy and the wavefront kernels
 void launch_amg_dense_solve(int n, const double *inv, const double *r, double *x, hipStream_t s);
 // exclusive prefix sums of int32 counts (slhjb_adjoint.hip): out[q] = in[0] + ... + in[q-1], *total_out
 // (nullable, device) = the sum; part holds scan_parts(m) + 1 entries

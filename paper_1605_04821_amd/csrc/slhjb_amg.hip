@@ -769,7 +769,9 @@ void launch_amg_scatter(int64_t n, int W, const int32_t *col, const double *val,
 int launch_amg_sym(int64_t n, int W, int maxcol, const int32_t *col, const double *val, const int32_t *off,
                    const int32_t *cnt, const int32_t *trow, const double *tval, int Ws, int32_t *scol, double *sval,
                    hipStream_t s) {
-    if (W <= 32 && maxcol <= 32) {
+    // one thread per row where rows are narrow or many (it then fills the GPU; the long columns of a few rows
+    // cost only their own threads), one wavefront per row on small wide levels
+    if ((W <= 32 && maxcol <= 32) || n > kAmgWaveRows) {
         hipLaunchKernelGGL(k_amg_sym, dim3(grid_for(n)), dim3(kBlock), 0, s, n, W, col, val, off, cnt, trow, tval, Ws,
                            scol, sval);
         return 0;
@@ -781,7 +783,7 @@ int launch_amg_sym(int64_t n, int W, int maxcol, const int32_t *col, const doubl
 }
 void launch_amg_match_round(int64_t n, int Ws, const int32_t *scol, const double *sval, double beta, int32_t *mate,
                             int32_t *cand, hipStream_t s) {
-    if (Ws > 64)
+    if (Ws > 64 && n <= kAmgWaveRows)
         hipLaunchKernelGGL(k_amg_strong_wave, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, Ws, scol, sval, beta,
                            (const int32_t *)mate, cand);
     else

@@ -61,3 +61,31 @@ def test_batch_reports_nonfinite_instance(slhjb):
     assert err.value.code == slhjb.HJB_ENONFINITE
     assert f"instance {bad}" in str(err.value)
     bt.close()
+
+
+@pytest.mark.parametrize("opts,code", [(dict(max_krylov=1), "HJB_ENOCONV_KRYLOV"), (dict(max_pi=1), "HJB_ENOCONV_PI")],
+                         ids=["krylov_limit", "pi_limit"])
+def test_march_reports_iteration_limits(slhjb, opts, code):
+    """A solve that needs more Krylov iterations, or a step that needs more policy iterations, than allowed
+    ends with the corresponding status."""
+    inst = workloads.config_c2(33, n_cn=2)
+    solver = slhjb.Solver.from_instance(inst, slhjb.Options(**opts))
+    g, psi, f0, f1 = (to_dev(getattr(inst, k)) for k in ("g", "psi", "f0", "f1"))
+    U = torch.empty_like(g)
+    with pytest.raises(slhjb.HJBError) as err:
+        solver.solve(g, psi, f0, f1, inst.dts, inst.thetas, inst.s, U)
+    log(f"  {opts}: {err.value}")
+    assert err.value.code == getattr(slhjb, code)
+    solver.close()
+
+
+def test_batch_reports_krylov_limit(slhjb):
+    insts = _batch_2d()[:3]
+    bt = slhjb.Batch(insts, slhjb.Options(precision=1, max_krylov=1))
+    g, psi, f0, f1 = (to_dev(bt.concat(k)) for k in ("g", "psi", "f0", "f1"))
+    U = torch.empty_like(g)
+    with pytest.raises(slhjb.HJBError) as err:
+        bt.solve(g, psi, f0, f1, insts[0].dts, insts[0].thetas, 1.0, U)
+    log(f"  {err.value}")
+    assert err.value.code == slhjb.HJB_ENOCONV_KRYLOV
+    bt.close()

@@ -244,10 +244,11 @@ def march_rate(slhjb, torch, inst, mode, n_steps=None, **options):
 
 def amg_compare(slhjb, torch, workloads, inst):
     """Aggregation AMG (Sections 3.4-3.5) against the geometric V-cycle: marches of c2 257^2 and the first two
-    steps of the headline workload, with the K-cycle at every coarse level and on the first coarse level only,
-    and with the hierarchy built once per time step."""
+    steps of the headline workload and of the 129^3 workload, with the K-cycle at every coarse level, on the
+    first coarse level only (2D), and with the hierarchy built once per time step."""
     out = {}
-    for name, wl, nst in (("c2 257^2", workloads.config_c2(257), None), ("h 2049^2 (first 2 steps)", inst, 2)):
+    for name, wl, nst in (("c2 257^2", workloads.config_c2(257), None), ("h 2049^2 (first 2 steps)", inst, 2),
+                          ("c5 129^3 (first 2 steps)", workloads.config_c5(129), 2)):
         for label, mode, opts in (("geometric V-cycle (mixed)", "mixed", {}),
                                   ("aggregation AMG, K-cycle at every level", "fp64",
                                    {"precond": slhjb.PRECOND_AMG}),
@@ -255,6 +256,8 @@ def amg_compare(slhjb, torch, workloads, inst):
                                    {"precond": slhjb.PRECOND_AMG, "kcycle_levels": 1}),
                                   ("aggregation AMG, K-cycle at every level, hierarchy once per step", "fp64",
                                    {"precond": slhjb.PRECOND_AMG, "amg_reuse": 1})):
+            if name.startswith("c5") and "K-cycle on level 1" in label:
+                continue
             print(f"[bench] preconditioners {name}: {label}", file=sys.stderr, flush=True)
             out[f"{name}, {label}"] = march_rate(slhjb, torch, wl, mode, nst, **opts)
     return out

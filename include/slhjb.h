@@ -59,7 +59,7 @@ enum {
 };
 enum { HJB_PREC_FP64 = 0, HJB_PREC_MIXED = 1 }; /* V-cycle in FP64, or in FP32 under FP64 FGMRES */
 /* preconditioner of the linear solves: none, Jacobi, the geometric V-cycle, or aggregation-based algebraic
-   multigrid with a Krylov-accelerated cycle (the introduction, Sections 3.4-3.5; HJB_PRECOND_AMG: 2D, FP64,
+   multigrid with a Krylov-accelerated cycle (the introduction, Sections 3.4-3.5; HJB_PRECOND_AMG: FP64,
    forward solves only) */
 enum { HJB_PRECOND_NONE = 0, HJB_PRECOND_JACOBI = 1, HJB_PRECOND_VCYCLE = 2, HJB_PRECOND_AMG = 3 };
 enum { HJB_KRYLOV_FGMRES = 0, HJB_KRYLOV_BICGSTAB = 1 };  /* outer FP64 Krylov method of the linear solves */

@@ -15,18 +15,18 @@
 namespace slhjb {
 
 constexpr int kAmgSortMax = 1024;  // contributions of one coarse row sorted in LDS, at most
-constexpr int kAmgMergeMax = 4 * kMaxPts + 1;  // slots of an emitted finest row
+constexpr int kAmgMergeMax = 8 * kMaxPts + 1;  // slots of an emitted finest row (3D: 8 corners per point)
 constexpr int kAmgCoarseThreads = 1024;
 
 // ---- setup -----------------------------------------------------------------------------------------------
 
 // Emitted rows (E slots with holes, duplicate columns where landings share interpolation corners) merged into
 // one entry per column, in order of first occurrence, duplicates summed in slot order; columns of boundary
-// nodes (nx x ny grid) are dropped, their values being Dirichlet data of the right-hand side, so that the
-// rows are those of the system on the interior unknowns.  One wavefront per row.
-__global__ __launch_bounds__(256) void k_amg_merge(int64_t n, int nx, int ny, int E, const int32_t *__restrict__ icol,
-                                                   const double *__restrict__ ival, int32_t *__restrict__ ocol,
-                                                   double *__restrict__ oval) {
+// nodes (nx x ny x nz grid, nz = 1 in 2D) are dropped, their values being Dirichlet data of the right-hand
+// side, so that the rows are those of the system on the interior unknowns.  One wavefront per row.
+__global__ __launch_bounds__(256) void k_amg_merge(int64_t n, int nx, int ny, int nz, int E,
+                                                   const int32_t *__restrict__ icol, const double *__restrict__ ival,
+                                                   int32_t *__restrict__ ocol, double *__restrict__ oval) {
     __shared__ int32_t sc[4][kAmgMergeMax];
     __shared__ double sv[4][kAmgMergeMax];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -35,8 +35,8 @@ __global__ __launch_bounds__(256) void k_amg_merge(int64_t n, int nx, int ny, in
     for (int c = lane; c < E; c += 64) {
         int j = row ? icol[(int64_t)c * n + i] : -1;
         if (j >= 0) {
-            const int jx = j % nx, jy = j / nx;
-            if (jx == 0 || jx == nx - 1 || jy == 0 || jy == ny - 1) j = -1;
+            const int jx = j % nx, jr = j / nx, jy = jr % ny, jz = jr / ny;
+            if (jx == 0 || jx == nx - 1 || jy == 0 || jy == ny - 1 || (nz > 1 && (jz == 0 || jz == nz - 1))) j = -1;
         }
         sc[w][c] = j;
         sv[w][c] = row ? ival[(int64_t)c * n + i] : 0.0;
@@ -749,10 +749,10 @@ __global__ __launch_bounds__(256) void k_amg_wave_op(int64_t n, int W, const int
 
 static unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + kBlock - 1) / kBlock); }
 
-void launch_amg_merge(int64_t n, int nx, int ny, int E, const int32_t *icol, const double *ival, int32_t *ocol,
-                      double *oval, hipStream_t s) {
-    hipLaunchKernelGGL(k_amg_merge, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, nx, ny, E, icol, ival, ocol,
-                       oval);
+void launch_amg_merge(int64_t n, int nx, int ny, int nz, int E, const int32_t *icol, const double *ival,
+                      int32_t *ocol, double *oval, hipStream_t s) {
+    hipLaunchKernelGGL(k_amg_merge, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, nx, ny, nz, E, icol, ival,
+                       ocol, oval);
 }
 void launch_amg_init(int64_t n, int W, const int32_t *col, const double *val, double dd, int32_t *mate,
                      hipStream_t s) {

@@ -16,35 +16,38 @@ namespace slhjb {
 
 constexpr int kGalMaxSort = 4096;  // contributions of one coarse row held in LDS, at most
 
-// rows of the finest level's A at interior nodes: slot e < E of row i; boundary rows empty
+// rows of the finest level's A at interior nodes: slot e < E of row i; boundary rows empty.  E = npt 2^DIM + 1:
+// the 2^DIM interpolation corners of each stencil point, then the diagonal
+template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_gal_emit(LevelDev g, StencilDev st, const int16_t *__restrict__ alpha,
                                                      double theta_dt, int E, int32_t *__restrict__ col,
                                                      double *__restrict__ val) {
     int ix[3];
-    const int i = tile_node<2>(g, ix);
+    const int i = tile_node<DIM>(g, ix);
     if (i < 0) return;
     const int64_t N = g.N;
-    if (!interior<2>(g, ix)) {
+    if (!interior<DIM>(g, ix)) {
         for (int e = 0; e < E; ++e) col[e * N + i] = -1;
         return;
     }
     int k = alpha[i];
     k = ((unsigned)k < (unsigned)st.K) ? k : 0;
     const PointTab *pt = st.tab + k * st.npt;
-    const int s1 = (int)g.s1;
+    const int s1 = (int)g.s1, s2 = (int)g.s2;
     int e = 0;
     double self = 0.0;
     auto emit_point = [&](int q, double factor) {
         double Y[3];
-        point_Y(st, pt[q], q, ix, i, 2, Y);
+        point_Y(st, pt[q], q, ix, i, DIM, Y);
         int cell[3];
         double t[3];
-        landing<2>(g, ix, Y, cell, t);
-        const int cb = cell[0] + cell[1] * s1;
-        for (int c = 0; c < 4; ++c) {
+        landing<DIM>(g, ix, Y, cell, t);
+        const int cb = cell[0] + cell[1] * s1 + (DIM == 3 ? cell[2] * s2 : 0);
+        for (int c = 0; c < (1 << DIM); ++c) {
             double w = (c & 1) ? t[0] : (1.0 - t[0]);
             w = w * ((c & 2) ? t[1] : (1.0 - t[1]));
-            const int j = cb + (c & 1) + ((c & 2) ? s1 : 0);
+            if (DIM == 3) w = w * ((c & 4) ? t[2] : (1.0 - t[2]));
+            const int j = cb + (c & 1) + ((c & 2) ? s1 : 0) + ((DIM == 3 && (c & 4)) ? s2 : 0);
             const double a = -theta_dt * st.inv2h * factor * w;
             col[e * N + i] = (j == i) ? -1 : j;  // the node's own corner weight joins the diagonal
             val[e * N + i] = a;
@@ -55,12 +58,12 @@ __global__ __launch_bounds__(kBlock) void k_gal_emit(LevelDev g, StencilDev st, 
     double sumf = 0.0;
     for (int p = 0; p < st.P; ++p) {
         double Ya[3], Yb[3];
-        point_Y(st, pt[2 * p], 2 * p, ix, i, 2, Ya);
-        point_Y(st, pt[2 * p + 1], 2 * p + 1, ix, i, 2, Yb);
+        point_Y(st, pt[2 * p], 2 * p, ix, i, DIM, Ya);
+        point_Y(st, pt[2 * p + 1], 2 * p + 1, ix, i, DIM, Yb);
         int cc[3];
         double tt[3];
-        const double mup = landing<2>(g, ix, Ya, cc, tt);
-        const double mum = landing<2>(g, ix, Yb, cc, tt);
+        const double mup = landing<DIM>(g, ix, Ya, cc, tt);
+        const double mum = landing<DIM>(g, ix, Yb, cc, tt);
         const double A = 2.0 / (mup * (mup + mum)), B = 2.0 / (mum * (mum + mup));
         emit_point(2 * p, A);
         emit_point(2 * p + 1, B);
@@ -68,10 +71,10 @@ __global__ __launch_bounds__(kBlock) void k_gal_emit(LevelDev g, StencilDev st, 
     }
     if (st.has_drift) {
         double Yc[3];
-        point_Y(st, pt[2 * st.P], 2 * st.P, ix, i, 2, Yc);
+        point_Y(st, pt[2 * st.P], 2 * st.P, ix, i, DIM, Yc);
         int cc[3];
         double tt[3];
-        const double C2 = 2.0 / landing<2>(g, ix, Yc, cc, tt);
+        const double C2 = 2.0 / landing<DIM>(g, ix, Yc, cc, tt);
         emit_point(2 * st.P, C2);
         sumf += C2;
     }
@@ -230,9 +233,12 @@ __global__ __launch_bounds__(kBlock) void k_gal_residual(int64_t N, int W, const
     res[i] = r[i] - ae;
 }
 
-void launch_gal_emit(const LevelDev &g, const StencilDev &st, const int16_t *alpha, double theta_dt, int E,
+void launch_gal_emit(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, double theta_dt, int E,
                      int32_t *col, double *val, hipStream_t s) {
-    hipLaunchKernelGGL(k_gal_emit, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, theta_dt, E, col, val);
+    if (dim == 3)
+        hipLaunchKernelGGL(k_gal_emit<3>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, theta_dt, E, col, val);
+    else
+        hipLaunchKernelGGL(k_gal_emit<2>, dim3(tiles_for(g)), dim3(kBlock), 0, s, g, st, alpha, theta_dt, E, col, val);
 }
 
 int gal_sort_size(int Wf) {

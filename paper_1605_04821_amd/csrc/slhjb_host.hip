@@ -407,8 +407,6 @@ void select_precision(hjb_handle *hd) {
 int check_options(const hjb_desc *d) {
     if (d->precision != HJB_PREC_FP64 && d->precision != HJB_PREC_MIXED) return fail(HJB_EINVAL, "precision");
     if (d->precond < HJB_PRECOND_NONE || d->precond > HJB_PRECOND_AMG) return fail(HJB_EINVAL, "precond");
-    if (d->precond == HJB_PRECOND_AMG && d->dim != 2)
-        return fail(HJB_EUNSUPPORTED, "the aggregation AMG preconditioner is provided for 2D grids");
     if (d->kcycle_levels < -1) return fail(HJB_EINVAL, "kcycle_levels must be >= -1");
     if (d->value_stride < 1) return fail(HJB_EINVAL, "value_stride must be >= 1");
     if (d->amg_reuse != 0 && d->amg_reuse != 1) return fail(HJB_EINVAL, "amg_reuse must be 0 or 1");
@@ -446,7 +444,7 @@ int build_galerkin(hjb_handle *hd, const int16_t *alpha, double theta_dt) {
     hipStream_t s = hd->stream;
     const int E0 = hd->npt * 4 + 1;
     int32_t *wide = (int32_t *)(hd->hpin + kGalSlot);  // pinned host word
-    launch_gal_emit(hd->lev[0].g, stencil(hd, 0), alpha, theta_dt, E0, hd->g0col, hd->g0val, s);
+    launch_gal_emit(2, hd->lev[0].g, stencil(hd, 0), alpha, theta_dt, E0, hd->g0col, hd->g0val, s);
     int Wf = E0;
     for (size_t l = 1; l < hd->lev.size(); ++l) {
         Level &F = hd->lev[l - 1], &C = hd->lev[l];
@@ -675,7 +673,7 @@ int amg_vectors(hjb_handle *hd, AmgLevel &L) {
 int build_amg(hjb_handle *hd, const int16_t *alpha, double theta_dt) {
     hipStream_t s = hd->stream;
     const int64_t N = hd->N;
-    const int E0 = hd->npt * 4 + 1;
+    const int E0 = (hd->npt << hd->dim) + 1;
     hd->amg_levels = 0;
     TRY(grow(hd, hd->amg_rawc, (size_t)N * E0 * 4));
     TRY(grow(hd, hd->amg_rawv, (size_t)N * E0 * 8));
@@ -694,9 +692,9 @@ int build_amg(hjb_handle *hd, const int16_t *alpha, double theta_dt) {
         F0.W = E0;
         TRY(grow(hd, F0.col, (size_t)N * E0 * 4));
         TRY(grow(hd, F0.val, (size_t)N * E0 * 8));
-        launch_gal_emit(hd->lev[0].g, stencil(hd, 0), alpha, theta_dt, E0, hd->amg_rawc.as<int32_t>(),
+        launch_gal_emit(hd->dim, hd->lev[0].g, stencil(hd, 0), alpha, theta_dt, E0, hd->amg_rawc.as<int32_t>(),
                         hd->amg_rawv.as<double>(), s);
-        launch_amg_merge(N, hd->lev[0].g.n[0], hd->lev[0].g.n[1], E0, hd->amg_rawc.as<int32_t>(),
+        launch_amg_merge(N, hd->lev[0].g.n[0], hd->lev[0].g.n[1], hd->lev[0].g.n[2], E0, hd->amg_rawc.as<int32_t>(),
                          hd->amg_rawv.as<double>(), F0.col.as<int32_t>(), F0.val.as<double>(), s);
     }
     int32_t *widest = hd->amg_words.as<int32_t>();

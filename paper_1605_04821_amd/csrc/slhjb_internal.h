@@ -279,7 +279,7 @@ int blocks_for(int64_t N);
 // unused).  emit: rows of A = I - theta dt (L-hat + c) at the interior nodes of the finest level (E = npt * 4 + 1
 // slots); rap: R A P onto the next level (Wc slots; *overflow = the widest row when wider than Wc); diag: the
 // diagonal (1 on boundary rows) and optional FP32 weights; jacobi / residual: the smoother and residual.
-void launch_gal_emit(const LevelDev &g, const StencilDev &st, const int16_t *alpha, double theta_dt, int E,
+void launch_gal_emit(int dim, const LevelDev &g, const StencilDev &st, const int16_t *alpha, double theta_dt, int E,
                      int32_t *col, double *val, hipStream_t s);
 int gal_sort_size(int Wf);
 int launch_gal_rap(const LevelDev &gf, const LevelDev &gc, int Wf, const int32_t *fcol, const double *fval, int Wc,
@@ -303,8 +303,8 @@ void launch_gal_residual(int64_t N, int W, const int32_t *col, const T *val, con
 // 2 * amg_dot_parts(n) doubles); gcr: the GCR updates of the cycle; coarse: Jacobi sweeps in one workgroup.
 constexpr int kAmgCoarseMax = 2048;  // coarsest level solved by Jacobi sweeps in one workgroup, at most
 constexpr int kAmgDenseMax = 120;    // coarsest level solved through its dense inverse (LDS-resident), at most
-void launch_amg_merge(int64_t n, int nx, int ny, int E, const int32_t *icol, const double *ival, int32_t *ocol,
-                      double *oval, hipStream_t s);
+void launch_amg_merge(int64_t n, int nx, int ny, int nz, int E, const int32_t *icol, const double *ival,
+                      int32_t *ocol, double *oval, hipStream_t s);
 void launch_amg_init(int64_t n, int W, const int32_t *col, const double *val, double dd, int32_t *mate,
                      hipStream_t s);
 void launch_amg_colcount(int64_t n, int W, const int32_t *col, int32_t *cnt, int32_t *mx, hipStream_t s);

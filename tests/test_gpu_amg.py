@@ -205,9 +205,9 @@ def test_amg_march_c1_scaled_cycle(slhjb):
 
 
 def test_amg_option_checks(slhjb):
-    with pytest.raises(slhjb.HJBError):
-        slhjb.Solver.from_instance(workloads.config_c5(17, n_steps=1), slhjb.Options(precond=slhjb.PRECOND_AMG))
     inst = workloads.config_c2(33, n_cn=1)
+    with pytest.raises(slhjb.HJBError):
+        slhjb.Solver.from_instance(inst, slhjb.Options(precond=slhjb.PRECOND_AMG, amg_reuse=2))
     with pytest.raises(slhjb.HJBError):
         slhjb.Solver.from_instance(inst, slhjb.Options(precond=slhjb.PRECOND_AMG, kcycle_levels=-2))
     solver = slhjb.Solver.from_instance(inst, slhjb.Options(precond=slhjb.PRECOND_AMG))
@@ -274,3 +274,31 @@ def test_amg_march_reused_hierarchy(slhjb, name, mk):
     inst = mk()
     log(f"AMG march with the hierarchy kept within each step: {name}")
     _march_compare(slhjb, inst, slhjb.Options(precond=slhjb.PRECOND_AMG, amg_reuse=1))
+
+
+def _toy3(n, K, P, seed):
+    from test_gpu_parity import _toy
+    return _toy(n, K=K, P=P, seed=seed, c=True)
+
+
+@pytest.mark.parametrize("name,mk", [("c5_17", lambda: workloads.config_c5(17, n_steps=2)),
+                                     ("ragged_3d", lambda: _toy3((11, 9, 13), K=5, P=1, seed=4))],
+                         ids=["c5_17", "ragged_3d"])
+def test_amg_hierarchy_3d(slhjb, name, mk):
+    """3D grids: eight interpolation corners per stencil point in the finest rows; every level against the
+    oracle's matrix chain, and a march against the oracle."""
+    inst = mk()
+    log(f"aggregation hierarchy 3D {name}")
+    pb, alpha, U = _setup_case(inst, 5)
+    t_prev, dt, theta = 0.0, float(inst.dts[-1]), float(inst.thetas[-1])
+    solver = slhjb.Solver.from_instance(inst, slhjb.Options(precond=slhjb.PRECOND_AMG))
+    X = U.copy()
+    X[pb.bd] = inst.psi[pb.bd]
+    dX = to_dev(X)
+    st = solver.linsolve(to_dev(alpha), to_dev(U), to_dev(inst.f0), to_dev(inst.f1), t_prev, dt, theta, 1.0, dX)
+    log(f"  linsolve krylov={st.krylov_total}")
+    A0, _ = _full_matrix(pb, alpha, dt, theta)
+    sizes = _check_hierarchy(solver, A0, pb.interior)
+    log(f"  level sizes {sizes}")
+    solver.close()
+    _march_compare(slhjb, inst, slhjb.Options(precond=slhjb.PRECOND_AMG))

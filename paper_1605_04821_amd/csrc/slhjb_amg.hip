@@ -769,9 +769,9 @@ void launch_amg_scatter(int64_t n, int W, const int32_t *col, const double *val,
 int launch_amg_sym(int64_t n, int W, int maxcol, const int32_t *col, const double *val, const int32_t *off,
                    const int32_t *cnt, const int32_t *trow, const double *tval, int Ws, int32_t *scol, double *sval,
                    hipStream_t s) {
-    // one thread per row where rows are narrow or many (it then fills the GPU; the long columns of a few rows
-    // cost only their own threads), one wavefront per row on small wide levels
-    if ((W <= 32 && maxcol <= 32) || n > kAmgWaveRows) {
+    // one thread per row where rows are narrow, or many and of moderate width (it then fills the GPU; the long
+    // columns of a few rows cost only their own threads), one wavefront per row on wide levels
+    if ((W <= 32 && maxcol <= 32) || (n > kAmgWaveRows && W <= 48)) {
         hipLaunchKernelGGL(k_amg_sym, dim3(grid_for(n)), dim3(kBlock), 0, s, n, W, col, val, off, cnt, trow, tval, Ws,
                            scol, sval);
         return 0;

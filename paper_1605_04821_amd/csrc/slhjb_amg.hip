@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_amg_colmax(int64_t n, const int32_t 
         if ((int)threadIdx.x < w) sm[threadIdx.x] = max(sm[threadIdx.x], sm[threadIdx.x + w]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicMax(mx, sm[0]);
+    if (threadIdx.x == 0 && sm[0] > __atomic_load_n(mx, __ATOMIC_RELAXED)) atomicMax(mx, sm[0]);
 }
 __global__ __launch_bounds__(kBlock) void k_amg_scatter(int64_t n, int W, const int32_t *__restrict__ col,
                                                         const double *__restrict__ val,
@@ -484,7 +484,9 @@ __global__ __launch_bounds__(64 * R) void k_amg_product(int64_t nf, int W, const
         out += __popcll(heads);
         if (!__any(valid)) break;
     }
-    if (lane == 0) atomicMax(widest, out);
+    // the widest row so far only grows: a row no wider than the value read skips the atomic (a stale read
+    // costs one atomic more), so that most of the coarse rows do not queue on the one address
+    if (lane == 0 && out > __atomic_load_n(widest, __ATOMIC_RELAXED)) atomicMax(widest, out);
     for (int s = out + lane; s < Wc; s += 64) ccol[(int64_t)s * nc + A] = -1;
 }
 

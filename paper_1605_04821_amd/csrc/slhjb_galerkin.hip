@@ -173,7 +173,9 @@ __global__ __launch_bounds__(64) void k_gal_rap(LevelDev gf, LevelDev gc, int Wf
         out += __popcll(heads);
         if (!__any(valid)) break;
     }
-    if (lane == 0) atomicMax(widest, out);
+    // the widest row so far only grows: a row no wider than the value read skips the atomic (a stale read
+    // costs one atomic more), so that most of the coarse rows do not queue on the one address
+    if (lane == 0 && out > __atomic_load_n(widest, __ATOMIC_RELAXED)) atomicMax(widest, out);
     for (int s = out + lane; s < Wc; s += 64) ccol[(int64_t)s * gc.N + I] = -1;
 }
 

@@ -137,9 +137,13 @@ __global__ __launch_bounds__(kBlock) void k_amg_sym(int64_t n, int W, const int3
         const int j = col[s * n + i];
         if (j < 0) break;
         if (j == i) continue;
+        // the last entry of column i's segment from row j (searched from the end, so the search stops there)
         double b = 0.0;
-        for (int p = t0; p < t1; ++p)
-            if (trow[p] == j) b = tval[p];
+        for (int p = t1 - 1; p >= t0; --p)
+            if (trow[p] == j) {
+                b = tval[p];
+                break;
+            }
         const double w = -0.5 * (val[s * n + i] + b);
         if (w > 0.0) {
             scol[(int64_t)k * n + i] = j;
@@ -153,7 +157,10 @@ __global__ __launch_bounds__(kBlock) void k_amg_sym(int64_t n, int W, const int3
         for (int s = 0; s < W; ++s) {
             const int c = col[s * n + i];
             if (c < 0) break;
-            in_row = in_row || c == j;
+            if (c == j) {
+                in_row = true;
+                break;
+            }
         }
         if (in_row) continue;
         const double w = -0.5 * (tval[p] + 0.0);
